@@ -1,0 +1,381 @@
+"""ctypes view of the CPU oracle (oracle/ora.c) -- test infrastructure only.
+
+Only tests/, the smoke check and bench.py's cpu_baseline leg use this module.
+The product library never imports it.
+"""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ora.c")
+_LIB = os.path.join(_HERE, "libora.so")
+
+u64p = C.POINTER(C.c_uint64)
+i64p = C.POINTER(C.c_int64)
+dblp = C.POINTER(C.c_double)
+u32p = C.POINTER(C.c_uint32)
+intp = C.POINTER(C.c_int)
+
+STATUS = {0: "ok", -1: "invalid", -2: "range", -3: "depth"}
+
+
+def build(force=False):
+    """Compile ora.c with gcc (plain C, OpenMP over limbs, binary128 encoder)."""
+    if os.path.exists(_LIB) and not force:
+        return _LIB
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-Wall", "-Wno-unused-function", "-o", tmp, _SRC, "-lquadmath", "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        vp = C.c_void_p
+        sig = {
+            "ora_params_new": (vp, [C.c_int] * 7),
+            "ora_params_free": (None, [vp]),
+            "ora_params_info": (None, [vp, u64p, dblp, u64p, intp]),
+            "ora_set_threads": (None, [C.c_int]),
+            "ora_negacyclic_mul": (None, [C.c_uint64, C.c_uint64, C.c_uint64, u64p, u64p, u64p]),
+            "ora_ntt_forward": (None, [C.c_uint64, C.c_uint64, C.c_uint64, u64p]),
+            "ora_chacha20_block": (None, [C.c_char_p, C.c_uint32, C.c_char_p, u32p]),
+            "ora_sample": (None, [C.c_char_p, C.c_uint32, C.c_uint64, C.c_int, C.c_uint64, C.c_uint64, i64p]),
+            "ora_encode": (C.c_int, [vp, dblp, C.c_uint32, C.c_double, i64p]),
+            "ora_decode": (None, [vp, i64p, C.c_double, C.c_uint32, dblp]),
+            "ora_automorphism": (None, [C.c_uint64, C.c_uint64, C.c_uint64, u64p, u64p]),
+            "ora_bconv": (None, [u64p, u64p, C.c_int, C.c_uint64, C.c_uint64, u64p]),
+            "ora_moddown": (None, [vp, C.c_int, u64p, u64p]),
+            "ora_rescale_poly": (None, [vp, u64p, C.c_int, u64p]),
+            "ora_keygen": (vp, [vp, C.c_char_p, C.c_int, u32p, C.c_int]),
+            "ora_keys_free": (None, [vp]),
+            "ora_keys_secret": (None, [vp, i64p]),
+            "ora_encrypt": (vp, [vp, dblp, C.c_uint32, C.c_int, C.c_char_p, intp]),
+            "ora_decrypt": (None, [vp, vp, dblp, C.c_uint32]),
+            "ora_decrypt_coeffs": (None, [vp, vp, i64p]),
+            "ora_ct_free": (None, [vp]),
+            "ora_ct_level": (C.c_int, [vp]),
+            "ora_ct_scale": (C.c_double, [vp]),
+            "ora_ct_export": (None, [vp, u64p]),
+            "ora_ct_import": (vp, [vp, C.c_int, u64p]),
+            "ora_rescale": (vp, [vp]),
+            "ora_drop": (vp, [vp, C.c_int]),
+            "ora_add": (vp, [vp, vp]),
+            "ora_sub": (vp, [vp, vp]),
+            "ora_add_const": (vp, [vp, C.c_double]),
+            "ora_cmul_to": (vp, [vp, C.c_double, C.c_int, intp]),
+            "ora_mul_plain": (vp, [vp, dblp, C.c_uint32, intp]),
+            "ora_add_plain": (vp, [vp, dblp, C.c_uint32, intp]),
+            "ora_mul": (vp, [vp, vp, vp, intp]),
+            "ora_apply_galois": (vp, [vp, vp, C.c_uint32, intp]),
+            "ora_rotate": (vp, [vp, vp, C.c_int64, intp]),
+            "ora_trans_r": (vp, [vp, vp, C.c_uint32, intp]),
+            "ora_trans_c": (vp, [vp, vp, C.c_uint32, intp]),
+            "ora_sum_r": (vp, [vp, vp, C.c_uint32, intp]),
+            "ora_sum_c": (vp, [vp, vp, C.c_uint32, intp]),
+            "ora_repl_r": (vp, [vp, vp, C.c_uint32, intp]),
+            "ora_repl_c": (vp, [vp, vp, C.c_uint32, intp]),
+            "ora_poly7": (vp, [vp, vp, dblp, intp]),
+            "ora_cmp_sign": (vp, [vp, vp, C.c_int, C.c_int, intp]),
+            "ora_cmp_matrix": (vp, [vp, vp, C.c_uint32, C.c_int, C.c_int, intp]),
+            "ora_rank": (vp, [vp, vp, C.c_uint32, C.c_int, C.c_int, intp]),
+            "ora_rank_depth": (C.c_int, [C.c_int, C.c_int]),
+            "ora_rank_galois": (C.c_int, [vp, C.c_uint32, u32p]),
+            "ora_galois_left": (C.c_uint32, [vp, C.c_uint64]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+def set_threads(t):
+    lib().ora_set_threads(int(t))
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(ptr, st, what):
+    if not ptr:
+        raise OracleError(f"{what}: status {STATUS.get(st.value, st.value)}")
+    return ptr
+
+
+class Params:
+    """Oracle parameter set: prime chain, special primes, per-level scales."""
+
+    def __init__(self, logn, L, q0_bits, log_scale, K, p_bits, dnum):
+        self.ptr = lib().ora_params_new(logn, L, q0_bits, log_scale, K, p_bits, dnum)
+        if not self.ptr:
+            raise OracleError("bad parameters")
+        self.logn, self.L, self.K, self.dnum = logn, L, K, dnum
+        self.n = 1 << logn
+        nm = L + 1 + K
+        self.mods = np.zeros(nm, np.uint64)
+        self.psi = np.zeros(nm, np.uint64)
+        self.scales = np.zeros(L + 1, np.float64)
+        dims = np.zeros(5, np.int32)
+        lib().ora_params_info(self.ptr, _p(self.mods, u64p), _p(self.scales, dblp), _p(self.psi, u64p),
+                              _p(dims, intp))
+        self.alpha = int(dims[4])
+        self.q = [int(x) for x in self.mods[:L + 1]]
+        self.p = [int(x) for x in self.mods[L + 1:]]
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            lib().ora_params_free(self.ptr)
+            self.ptr = None
+
+    def galois_left(self, k):
+        return int(lib().ora_galois_left(self.ptr, k))
+
+    def rank_galois(self, N):
+        out = np.zeros(256, np.uint32)
+        c = lib().ora_rank_galois(self.ptr, N, _p(out, u32p))
+        return [int(x) for x in out[:c]]
+
+
+class Keys:
+    def __init__(self, params, seed, lmax, galois):
+        self.params = params
+        gal = np.array(list(galois), np.uint32)
+        self.ptr = lib().ora_keygen(params.ptr, bytes(seed), lmax, _p(gal, u32p), len(gal))
+        if not self.ptr:
+            raise OracleError("keygen failed")
+        self.lmax = lmax
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            lib().ora_keys_free(self.ptr)
+            self.ptr = None
+
+    def secret(self):
+        s = np.zeros(self.params.n, np.int64)
+        lib().ora_keys_secret(self.ptr, _p(s, i64p))
+        return s
+
+
+class Ct:
+    def __init__(self, ptr, params):
+        self.ptr = ptr
+        self.params = params
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            lib().ora_ct_free(self.ptr)
+            self.ptr = None
+
+    @property
+    def level(self):
+        return lib().ora_ct_level(self.ptr)
+
+    @property
+    def scale(self):
+        return lib().ora_ct_scale(self.ptr)
+
+    def export(self):
+        out = np.zeros((2, self.level + 1, self.params.n), np.uint64)
+        lib().ora_ct_export(self.ptr, _p(out, u64p))
+        return out
+
+    @staticmethod
+    def from_array(params, arr):
+        arr = np.ascontiguousarray(arr, np.uint64)
+        level = arr.shape[1] - 1
+        return Ct(lib().ora_ct_import(params.ptr, level, _p(arr, u64p)), params)
+
+
+def _ct(fn, params, *args, what="op"):
+    st = C.c_int(0)
+    ptr = fn(*args, C.byref(st))
+    return Ct(_check(ptr, st, what), params)
+
+
+def encrypt(keys, z, level, seed):
+    z = np.ascontiguousarray(z, np.float64)
+    return _ct(lib().ora_encrypt, keys.params, keys.ptr, _p(z, dblp), len(z), level, bytes(seed), what="encrypt")
+
+
+def decrypt(keys, ct, count):
+    out = np.zeros(count, np.float64)
+    lib().ora_decrypt(keys.ptr, ct.ptr, _p(out, dblp), count)
+    return out
+
+
+def decrypt_coeffs(keys, ct):
+    out = np.zeros(keys.params.n, np.int64)
+    lib().ora_decrypt_coeffs(keys.ptr, ct.ptr, _p(out, i64p))
+    return out
+
+
+def encode(params, z, scale):
+    z = np.ascontiguousarray(z, np.float64)
+    m = np.zeros(params.n, np.int64)
+    st = lib().ora_encode(params.ptr, _p(z, dblp), len(z), scale, _p(m, i64p))
+    if st != 0:
+        raise OracleError(f"encode: {STATUS.get(st, st)}")
+    return m
+
+
+def decode(params, m, scale, count):
+    m = np.ascontiguousarray(m, np.int64)
+    z = np.zeros(count, np.float64)
+    lib().ora_decode(params.ptr, _p(m, i64p), scale, count, _p(z, dblp))
+    return z
+
+
+def rescale(ct):
+    return Ct(lib().ora_rescale(ct.ptr), ct.params)
+
+
+def drop(ct, level):
+    return Ct(lib().ora_drop(ct.ptr, level), ct.params)
+
+
+def add(a, b):
+    return Ct(lib().ora_add(a.ptr, b.ptr), a.params)
+
+
+def sub(a, b):
+    return Ct(lib().ora_sub(a.ptr, b.ptr), a.params)
+
+
+def add_const(a, c):
+    return Ct(lib().ora_add_const(a.ptr, float(c)), a.params)
+
+
+def cmul_to(a, c, target):
+    return _ct(lib().ora_cmul_to, a.params, a.ptr, float(c), target, what="cmul_to")
+
+
+def mul_plain(a, z):
+    z = np.ascontiguousarray(z, np.float64)
+    return _ct(lib().ora_mul_plain, a.params, a.ptr, _p(z, dblp), len(z), what="mul_plain")
+
+
+def add_plain(a, z):
+    z = np.ascontiguousarray(z, np.float64)
+    return _ct(lib().ora_add_plain, a.params, a.ptr, _p(z, dblp), len(z), what="add_plain")
+
+
+def mul(keys, a, b):
+    return _ct(lib().ora_mul, a.params, keys.ptr, a.ptr, b.ptr, what="mul")
+
+
+def apply_galois(keys, a, g):
+    return _ct(lib().ora_apply_galois, a.params, keys.ptr, a.ptr, g, what="galois")
+
+
+def rotate(keys, a, k):
+    return _ct(lib().ora_rotate, a.params, keys.ptr, a.ptr, int(k), what="rotate")
+
+
+def _mat(fn, keys, a, N):
+    return _ct(fn, a.params, keys.ptr, a.ptr, N, what=fn.__name__)
+
+
+def trans_r(keys, a, N): return _mat(lib().ora_trans_r, keys, a, N)
+def trans_c(keys, a, N): return _mat(lib().ora_trans_c, keys, a, N)
+def sum_r(keys, a, N): return _mat(lib().ora_sum_r, keys, a, N)
+def sum_c(keys, a, N): return _mat(lib().ora_sum_c, keys, a, N)
+def repl_r(keys, a, N): return _mat(lib().ora_repl_r, keys, a, N)
+def repl_c(keys, a, N): return _mat(lib().ora_repl_c, keys, a, N)
+
+
+def poly7(keys, a, coeffs):
+    c = np.ascontiguousarray(coeffs, np.float64)
+    return _ct(lib().ora_poly7, a.params, keys.ptr, a.ptr, _p(c, dblp), what="poly7")
+
+
+def cmp_sign(keys, a, dg, df):
+    return _ct(lib().ora_cmp_sign, a.params, keys.ptr, a.ptr, dg, df, what="cmp_sign")
+
+
+def cmp_matrix(keys, a, N, dg, df):
+    return _ct(lib().ora_cmp_matrix, a.params, keys.ptr, a.ptr, N, dg, df, what="cmp_matrix")
+
+
+def rank(keys, a, N, dg, df):
+    return _ct(lib().ora_rank, a.params, keys.ptr, a.ptr, N, dg, df, what="rank")
+
+
+def rank_depth(dg, df):
+    return lib().ora_rank_depth(dg, df)
+
+
+# ---- primitive pins -------------------------------------------------------
+
+def negacyclic_mul(n, q, psi, a, b):
+    a = np.ascontiguousarray(a, np.uint64)
+    b = np.ascontiguousarray(b, np.uint64)
+    c = np.zeros(n, np.uint64)
+    lib().ora_negacyclic_mul(n, q, psi, _p(a, u64p), _p(b, u64p), _p(c, u64p))
+    return c
+
+
+def ntt_forward(n, q, psi, a):
+    a = np.array(a, np.uint64)
+    lib().ora_ntt_forward(n, q, psi, _p(a, u64p))
+    return a
+
+
+def chacha20_block(key, counter, nonce):
+    out = np.zeros(16, np.uint32)
+    lib().ora_chacha20_block(bytes(key), counter, bytes(nonce), _p(out, u32p))
+    return out
+
+
+def sample(key, purpose, oid, kind, q, count):
+    out = np.zeros(count, np.int64)
+    lib().ora_sample(bytes(key), purpose, oid, kind, q, count, _p(out, i64p))
+    return out
+
+
+def automorphism(n, q, g, a):
+    a = np.ascontiguousarray(a, np.uint64)
+    b = np.zeros(n, np.uint64)
+    lib().ora_automorphism(n, q, g, _p(a, u64p), _p(b, u64p))
+    return b
+
+
+def bconv(x, src, t):
+    x = np.ascontiguousarray(x, np.uint64)
+    src = np.ascontiguousarray(src, np.uint64)
+    n = x.shape[1]
+    out = np.zeros(n, np.uint64)
+    lib().ora_bconv(_p(x, u64p), _p(src, u64p), len(src), t, n, _p(out, u64p))
+    return out
+
+
+def moddown(params, level, x):
+    x = np.ascontiguousarray(x, np.uint64)
+    out = np.zeros((level + 1, params.n), np.uint64)
+    lib().ora_moddown(params.ptr, level, _p(x, u64p), _p(out, u64p))
+    return out
+
+
+def rescale_poly(params, x, level):
+    x = np.ascontiguousarray(x, np.uint64)
+    out = np.zeros((level, params.n), np.uint64)
+    lib().ora_rescale_poly(params.ptr, _p(x, u64p), level, _p(out, u64p))
+    return out

@@ -1,0 +1,168 @@
+"""Slot-level shadow of the paper's circuits -- test infrastructure only.
+
+Plain float64 vectors stand in for ciphertext slots: no encryption, no
+noise, no levels.  Every function follows the paper's matrix operations and
+algorithms step by step:
+  * section 2.3 (row-by-row matrix encoding, MaskR/MaskC),
+  * Algorithm TransR / TransC (section 2.3),
+  * Appendix A (SumR, SumC, ReplR, ReplC),
+  * Algorithm Rank (section 3.1), Order Statistic (section 3.2),
+    Sorting (section 3.3), Tie-Correction Offset (section 4).
+Rotations are cyclic over `slots` positions: x << k means new[j] = x[j+k].
+
+The comparator is either the ideal function of Eq. (1) applied to the pair
+(x, y), or the f/g composite of section 2.2 applied to x - y.
+"""
+import numpy as np
+
+F_COEF = (35 / 16, -35 / 16, 21 / 16, -5 / 16)
+G_COEF = (4589 / 1024, -16577 / 1024, 25614 / 1024, -12860 / 1024)
+
+
+def rot_left(x, k):
+    return np.roll(x, -int(k))
+
+
+def rot_right(x, k):
+    return np.roll(x, int(k))
+
+
+def log2i(N):
+    return int(N).bit_length() - 1
+
+
+def mask_row(x, N, r):
+    m = np.zeros_like(x)
+    m[r * N:(r + 1) * N] = 1.0
+    return x * m
+
+
+def mask_col(x, N, c):
+    m = np.zeros_like(x)
+    m[c:N * N:N] = 1.0
+    return x * m
+
+
+def trans_r(x, N, trace=None):
+    for i in range(1, log2i(N) + 1):
+        x = x + rot_right(x, N * (N - 1) >> i)
+        if trace is not None:
+            trace.append(x.copy())
+    return mask_col(x, N, 0)
+
+
+def trans_c(x, N, trace=None):
+    for i in range(1, log2i(N) + 1):
+        x = x + rot_left(x, N * (N - 1) >> i)
+        if trace is not None:
+            trace.append(x.copy())
+    return mask_row(x, N, 0)
+
+
+def sum_r(x, N):
+    for i in range(log2i(N)):
+        x = x + rot_left(x, N << i)
+    return mask_row(x, N, 0)
+
+
+def sum_c(x, N):
+    for i in range(log2i(N)):
+        x = x + rot_left(x, 1 << i)
+    return mask_col(x, N, 0)
+
+
+def repl_r(x, N):
+    for i in range(log2i(N)):
+        x = x + rot_right(x, N << i)
+    return x
+
+
+def repl_c(x, N):
+    for i in range(log2i(N)):
+        x = x + rot_right(x, 1 << i)
+    return x
+
+
+def cmp_ideal(x, y):
+    """Eq. (1): 1 if x > y, 0.5 if x == y, 0 if x < y."""
+    return np.where(x > y, 1.0, np.where(x == y, 0.5, 0.0))
+
+
+def poly7(x, a):
+    return a[0] * x + a[1] * x ** 3 + a[2] * x ** 5 + a[3] * x ** 7
+
+
+def cmp_composite(d, dg, df):
+    """(f^{d_f}(g^{d_g}(d)) + 1) / 2 on the difference d = x - y (section 2.2)."""
+    for _ in range(dg):
+        d = poly7(d, G_COEF)
+    for _ in range(df):
+        d = poly7(d, F_COEF)
+    return (d + 1.0) / 2.0
+
+
+def comparator(cmp):
+    if cmp == "ideal":
+        return lambda x, y: cmp_ideal(x, y)
+    dg, df = cmp
+    return lambda x, y: cmp_composite(x - y, dg, df)
+
+
+def embed(v, slots):
+    x = np.zeros(slots)
+    x[:len(v)] = v
+    return x
+
+
+def rank(v, N, slots, cmp="ideal"):
+    """Algorithm Rank; returns the slot vector and the named intermediates."""
+    x = embed(v, slots)
+    VR = repl_r(x, N)
+    VC = repl_c(trans_r(x, N), N)
+    Cm = comparator(cmp)(VR, VC)
+    S = sum_r(Cm, N)
+    half = embed(np.full(N, 0.5), slots)
+    R = S + half
+    return R, dict(VR=VR, VC=VC, C=Cm, S=S)
+
+
+def tie_offset(C, N, slots):
+    """Algorithm Tie-Correction Offset from the comparison matrix C."""
+    E = 4.0 * C * (1.0 - C)
+    delta = np.zeros(slots)
+    for i in range(N):
+        for j in range(i, N):
+            delta[i * N + j] = 1.0          # delta_{j >= i}: row i, column j
+    U = sum_r(E * delta, N)
+    T = sum_r(E, N)
+    F = U - 0.5 * T - embed(np.full(N, 0.5), slots)
+    return F, dict(E=E, delta=delta, U=U, T=T)
+
+
+def sort(v, N, slots, cmp="ideal", ind=None):
+    """Algorithm Sorting (distinct inputs).  `ind` maps a slot vector x to
+    Ind_0(x); the ideal indicator is used when None."""
+    x = embed(v, slots)
+    R, _ = rank(v, N, slots, cmp)
+    RR = repl_r(R, N)
+    steps = np.zeros(slots)
+    for k in range(N):
+        steps[k * N:(k + 1) * N] = k + 1   # (1^N || 2^N || ... || N^N)
+    D = RR - steps
+    M = (np.abs(D) < 0.5).astype(float) if ind is None else ind(D)
+    VR = repl_r(x, N)
+    P = M * VR
+    SC = sum_c(P, N)
+    S = trans_c(SC, N)
+    return S, dict(R=R, RR=RR, D=D, M=M, P=P, SC=SC)
+
+
+def min_onehot(v, N, slots, cmp="ideal"):
+    """Tie-corrected argmin: k = Rank + offset, one-hot where k = 1, value = SumC(O * V)."""
+    x = embed(v, slots)
+    R, inter = rank(v, N, slots, cmp)
+    F, _ = tie_offset(inter["C"], N, slots)
+    k = R + F
+    O = np.where(np.abs(k - 1.0) < 0.5, 1.0, 0.0) * embed(np.ones(N), slots)
+    val = sum_c(O * x, N)
+    return O, val, k

@@ -1,0 +1,62 @@
+"""Seeded synthetic inputs and parameter-set descriptions.
+
+This module holds no arithmetic of the method: it only draws input vectors,
+seeds and names the parameter sets (ring size, prime sizes, digit count).
+Both the HIP path and the CPU oracle are fed from here.
+
+Input recipe (the paper draws values uniformly at random in a bounded
+interval, section 6.1 "Experimental Setup"):
+  * min_gap_uniform: N values in [0, 1) whose pairwise gap is at least `gap`,
+    drawn exactly uniformly on that constrained set by sort-and-spread
+    (u ~ U[0, 1 - (N-1) gap)^N, sort, add i*gap to the i-th smallest,
+    shuffle).
+  * tied_pool: `pool` distinct values (min_gap_uniform) plus N - pool draws
+    with replacement from the pool, shuffled (25 % duplicates at N=128).
+  * seeds: 32-byte key / encryption seeds from numpy's default_rng.
+"""
+import numpy as np
+
+# Parameter sets.  logn: ring degree 2^logn; L: top level (q_0..q_L);
+# q0_bits: size class of q_0; log_scale: log2 of the top-level scale (the
+# rescale primes are picked near the running scale); K special primes of
+# p_bits; dnum key-switching digits.
+PSETS = {
+    # toy ring for the N=8 rank (not secure)
+    "P12": dict(logn=12, L=11, q0_bits=44, log_scale=36, K=4, p_bits=40, dnum=3),
+    # rank on N <= 128 at n = 2^16 (log QP ~ 1320 bits)
+    "P16": dict(logn=16, L=23, q0_bits=50, log_scale=40, K=7, p_bits=50, dnum=3),
+    # small rings used by the unit and parity tests
+    "T10": dict(logn=10, L=7, q0_bits=44, log_scale=36, K=3, p_bits=46, dnum=3),
+    "T13": dict(logn=13, L=11, q0_bits=44, log_scale=36, K=4, p_bits=40, dnum=3),
+}
+
+# Comparator compositions (d_g, d_f) per workload: g applied d_g times, then f d_f times.
+RANK_CMP = {8: (2, 1), 16: (3, 1), 32: (3, 1), 64: (4, 1), 128: (4, 1)}
+
+
+def min_gap_uniform(N, gap, rng):
+    if (N - 1) * gap >= 1.0:
+        raise ValueError("gap too large for N values in [0,1)")
+    u = np.sort(rng.uniform(0.0, 1.0 - (N - 1) * gap, N))
+    v = u + gap * np.arange(N)
+    rng.shuffle(v)
+    return v
+
+
+def tied_pool(N, pool, gap, rng):
+    base = min_gap_uniform(pool, gap, rng)
+    extra = rng.choice(base, size=N - pool, replace=True)
+    v = np.concatenate([base, extra])
+    rng.shuffle(v)
+    return v
+
+
+def seed_bytes(rng):
+    return bytes(rng.integers(0, 256, 32, dtype=np.uint8).tolist())
+
+
+def rank_workload(N, gap, seed):
+    """(values, key seed, encryption seed) of one seeded rank query."""
+    rng = np.random.default_rng(seed)
+    v = min_gap_uniform(N, gap, rng)
+    return v, seed_bytes(rng), seed_bytes(rng)

@@ -1,0 +1,175 @@
+"""Circuit-level pins: the paper's worked examples and closed forms.
+
+The slot-level shadow (oracle/shadow.py) is checked against Figures 1-4 and
+the proofs' closed forms; the oracle's decrypted CKKS outputs are then
+checked against the shadow (same circuit, composite comparator) and against
+exact plaintext ranks.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import shadow as S
+from paper_2412_15126_amd import workloads as W
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_examples.json")))
+
+
+def _mat(x, N):
+    return np.asarray(x[:N * N]).reshape(N, N)
+
+
+def test_fig1_transc_steps():
+    g = GOLD["fig1_transc_n8"]
+    N = g["N"]
+    x = np.zeros(N * N)
+    x[0:N * N:N] = np.arange(1, N + 1)       # column vector v_1..v_8
+    trace = []
+    out = S.trans_c(x, N, trace)
+    assert np.array_equal(_mat(x, N), np.array(g["steps"][0]))
+    for t, want in zip(trace, g["steps"][1:4]):
+        assert np.array_equal(_mat(t, N), np.array(want))
+    assert np.array_equal(_mat(out, N), np.array(g["steps"][4]))
+    assert [N * (N - 1) >> i for i in (1, 2, 3)] == g["shifts"]
+
+
+@pytest.mark.parametrize("slots", [64, 2048])
+def test_transr_transc_roundtrip_and_row0(slots):
+    N = 8
+    v = np.arange(1, N + 1, dtype=float)
+    col = S.trans_r(S.embed(v, slots), N)
+    assert np.array_equal(col[0:N * N:N], v) and np.count_nonzero(col) == N
+    row = S.trans_c(col, N)
+    assert np.array_equal(row[:N], v) and np.count_nonzero(row) == N
+
+
+def test_fig2_rank_intermediates():
+    g = GOLD["fig2_rank"]
+    N = 4
+    R, it = S.rank(np.array(g["v"], float), N, 64)
+    assert np.array_equal(_mat(it["VR"], N), np.array(g["VR"]))
+    assert np.array_equal(_mat(it["VC"], N), np.array(g["VC"]))
+    assert np.array_equal(_mat(it["C"], N), np.array(g["C"]))
+    assert np.array_equal(it["S"][:N], np.array(g["sumR"]))
+    assert np.array_equal(R[:N], np.array(g["rank"], float))
+
+
+def test_fractional_rank_example_with_padding():
+    g = GOLD["fractional_rank"]
+    v = np.array(g["v"], float)
+    # pad to the next power of two with values above every input
+    padded = np.concatenate([v, [1e9, 2e9, 3e9]])
+    R, _ = S.rank(padded, 8, 128)
+    assert np.array_equal(R[:5], np.array(g["rank"]))
+
+
+def test_fig3_sort_intermediates():
+    g = GOLD["fig3_sort"]
+    N = 4
+    out, it = S.sort(np.array(g["v"], float), N, 64)
+    assert np.array_equal(it["R"][:N], np.array(g["rank"], float))
+    assert np.array_equal(_mat(it["D"], N), np.array(g["D"]))
+    assert np.array_equal(_mat(it["M"], N), np.array(g["M"]))
+    assert np.array_equal(_mat(it["P"], N), np.array(g["P"]))
+    assert np.array_equal(it["SC"][0:N * N:N], np.array(g["sumC"], float))
+    assert np.array_equal(out[:N], np.array(g["sorted"], float))
+
+
+def test_fig4_tie_offset():
+    g = GOLD["fig4_ties"]
+    N = 4
+    v = np.array(g["v"], float)
+    R, it = S.rank(v, N, 64)
+    assert np.array_equal(R[:N], np.array(g["rank"]))
+    F, t = S.tie_offset(it["C"], N, 64)
+    assert np.array_equal(_mat(t["E"], N), np.array(g["E"]))
+    assert np.array_equal(_mat(t["delta"], N), np.array(g["delta"]))
+    assert np.array_equal(_mat(t["E"] * t["delta"], N), np.array(g["Edelta"]))
+    assert np.array_equal(t["T"][:N], np.array(g["T"], float))
+    assert np.array_equal(t["U"][:N], np.array(g["U"], float))
+    assert np.array_equal(F[:N], np.array(g["F"]))
+    assert np.array_equal((R + F)[:N], np.array(g["k"], float))
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_rank_closed_form_and_tie_permutation(seed):
+    """r_j = |L_j| + (|E_j| + 1)/2 (section 3.1 proof); R + F is a permutation with
+    v_j the k_j-th order statistic (section 4 proof)."""
+    rng = np.random.default_rng(seed)
+    N = 16
+    v = rng.integers(0, 6, N).astype(float)           # many ties
+    R, it = S.rank(v, N, 512)
+    L = np.array([(v < x).sum() for x in v])
+    E = np.array([(v == x).sum() for x in v])
+    assert np.array_equal(R[:N], L + 0.5 * (E + 1))
+    F, _ = S.tie_offset(it["C"], N, 512)
+    k = (R + F)[:N]
+    assert sorted(k.tolist()) == list(range(1, N + 1))
+    assert np.array_equal(np.sort(v)[k.astype(int) - 1], v)
+    # merged form used by the circuits: k = SumR(C + E*(delta - 1/2)) (linearity of SumR)
+    Em = 4 * it["C"] * (1 - it["C"])
+    delta = np.zeros(512)
+    for i in range(N):
+        delta[i * N + i:(i + 1) * N] = 1
+    merged = S.sum_r(it["C"] + Em * (delta - 0.5), N)
+    assert np.array_equal(merged[:N], k)
+
+
+@pytest.mark.parametrize("N,seeds", [(8, range(100)), (128, range(20))])
+def test_composite_comparator_ranks_round_exactly(N, seeds):
+    dg, df = W.RANK_CMP[N]
+    gap = 0.01 if N == 8 else 2.0 ** -10
+    worst = 0.0
+    for s in seeds:
+        v, _, _ = W.rank_workload(N, gap, s)
+        R, _ = S.rank(v, N, 2 * N * N, (dg, df))
+        exact = np.argsort(np.argsort(v)) + 1
+        worst = max(worst, np.max(np.abs(R[:N] - exact)))
+    assert worst < 0.45
+
+
+@pytest.fixture(scope="module")
+def p12(ora):
+    P = ora.Params(**W.PSETS["P12"])
+    return P
+
+
+def test_oracle_rank8_matches_shadow_and_exact(ora, p12):
+    N = 8
+    dg, df = W.RANK_CMP[N]
+    errs = []
+    for seed in range(3):
+        v, kseed, eseed = W.rank_workload(N, 0.01, seed)
+        keys = ora.Keys(p12, kseed, p12.L, p12.rank_galois(N))
+        ct = ora.encrypt(keys, v, p12.L, eseed)
+        R = ora.rank(keys, ct, N, dg, df)
+        assert R.level == 0
+        got = ora.decrypt(keys, R, N)
+        sh, _ = S.rank(v, N, p12.n // 2, (dg, df))
+        errs.append(np.max(np.abs(got - sh[:N])))
+        assert np.array_equal(np.round(got), np.argsort(np.argsort(v)) + 1)
+    assert max(errs) < 1e-3
+
+
+def test_oracle_matrix_ops_match_shadow(ora, p12):
+    N = 8
+    h = p12.n // 2
+    v = np.linspace(0.05, 0.9, N)
+    gal = sorted(set(p12.rank_galois(N)) | {p12.galois_left(N * (N - 1) >> i) for i in (1, 2, 3)}
+                 | {p12.galois_left(1 << i) for i in range(3)})
+    keys = ora.Keys(p12, bytes(range(32)), p12.L, gal)
+    ct = ora.encrypt(keys, v, p12.L, bytes([5] * 32))
+    x = S.embed(v, h)
+    for name, fn, sfn in [("trans_r", ora.trans_r, S.trans_r), ("repl_r", ora.repl_r, S.repl_r),
+                          ("sum_r", ora.sum_r, S.sum_r)]:
+        got = ora.decrypt(keys, fn(keys, ct, N), 2 * N * N)
+        want = sfn(x, N)[:2 * N * N]
+        assert np.max(np.abs(got - want)) < 1e-4, name
+    col = ora.trans_r(keys, ct, N)
+    for name, fn, sfn in [("repl_c", ora.repl_c, S.repl_c), ("sum_c", ora.sum_c, S.sum_c),
+                          ("trans_c", ora.trans_c, S.trans_c)]:
+        got = ora.decrypt(keys, fn(keys, col, N), 2 * N * N)
+        want = sfn(S.trans_r(x, N), N)[:2 * N * N]
+        assert np.max(np.abs(got - want)) < 1e-4, name

@@ -1,0 +1,295 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Every check here is independent of the oracle's own code: big-integer CRT
+arithmetic in Python, naive O(n^2) negacyclic convolution, the RFC 8439
+test vector, number-theoretic invariants, and decryption identities.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2412_15126_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _probable_prime(n):
+    if n < 2:
+        return False
+    for p in (2, 3, 5, 7, 11, 13):
+        if n % p == 0:
+            return n == p
+    return all(pow(b, n - 1, n) == 1 for b in (2, 3, 5, 7, 11, 13, 17, 19, 23))
+
+
+@pytest.fixture(scope="module")
+def t10(ora):
+    return ora.Params(**W.PSETS["T10"])
+
+
+# ---------------------------------------------------------------- primes
+@pytest.mark.parametrize("name", ["T10", "P12", "P16"])
+def test_prime_chain_properties(ora, name):
+    ps = W.PSETS[name]
+    P = ora.Params(**ps)
+    m = 2 * P.n
+    mods = [int(x) for x in P.mods]
+    assert len(set(mods)) == len(mods)
+    for x in mods:
+        assert x % m == 1 and _probable_prime(x) and x < 2 ** 50
+    # special primes: the K largest primes = 1 mod 2n below 2^p_bits
+    c = ((1 << ps["p_bits"]) - 1) // m * m + 1
+    expect = []
+    while len(expect) < ps["K"]:
+        if _probable_prime(c):
+            expect.append(c)
+        c -= m
+    assert P.p == expect
+    # q_0: largest unused prime below 2^q0_bits
+    c = ((1 << ps["q0_bits"]) - 1) // m * m + 1
+    while not (_probable_prime(c) and c not in expect):
+        c -= m
+    assert P.q[0] == c
+    # scale table starts at 2^log_scale and stays within 1e-3 of it
+    assert P.scales[P.L] == 2.0 ** ps["log_scale"]
+    assert np.all(np.abs(P.scales / 2.0 ** ps["log_scale"] - 1) < 1e-3)
+    # each rescale prime is the nearest unused candidate to its level's scale
+    used = set(expect) | {P.q[0]}
+    for lvl in range(P.L, 0, -1):
+        q, D = P.q[lvl], P.scales[lvl]
+        for cand in (q - m, q + m):
+            if abs(cand - D) < abs(q - D):
+                assert not _probable_prime(cand) or cand in used
+        used.add(q)
+    # psi: primitive 2n-th roots
+    for x, w in zip(mods, P.psi):
+        w = int(w)
+        assert pow(w, P.n, x) == x - 1 and pow(w, 2 * P.n, x) == 1
+
+
+# ---------------------------------------------------------------- NTT
+@pytest.mark.parametrize("n", [8, 32, 256])
+def test_ntt_product_equals_naive_negacyclic_convolution(ora, t10, n):
+    q = t10.q[1]
+    # primitive 2n-th root for this small n from the ring's psi
+    psi = pow(int(t10.psi[1]), t10.n // n, q)
+    rng = np.random.default_rng(n)
+    a = [int(x) for x in rng.integers(0, q, n, dtype=np.uint64)]
+    b = [int(x) for x in rng.integers(0, q, n, dtype=np.uint64)]
+    c = [0] * n
+    for i in range(n):
+        for j in range(n):
+            k = i + j
+            if k < n:
+                c[k] += a[i] * b[j]
+            else:
+                c[k - n] -= a[i] * b[j]
+    c = [x % q for x in c]
+    got = ora.negacyclic_mul(n, q, psi, np.array(a, np.uint64), np.array(b, np.uint64))
+    assert [int(x) for x in got] == c
+
+
+def test_ntt_forward_is_evaluation_at_odd_powers(ora, t10):
+    n, q = 64, t10.q[2]
+    psi = pow(int(t10.psi[2]), t10.n // n, q)
+    rng = np.random.default_rng(5)
+    a = [int(x) for x in rng.integers(0, q, n, dtype=np.uint64)]
+    got = ora.ntt_forward(n, q, psi, np.array(a, np.uint64))
+    for k in range(n):
+        x = pow(psi, 2 * k + 1, q)
+        assert int(got[k]) == sum(a[j] * pow(x, j, q) for j in range(n)) % q
+
+
+# ---------------------------------------------------------------- ChaCha20
+def test_chacha20_rfc8439_block(ora):
+    g = json.load(open(os.path.join(GOLD, "rfc8439_chacha20.json")))["block"]
+    out = ora.chacha20_block(bytes.fromhex(g["key"]), g["counter"], bytes.fromhex(g["nonce"]))
+    assert [f"{int(x):08x}" for x in out] == g["state_out"]
+
+
+def test_samplers_distributions(ora):
+    key = bytes(range(32))
+    t = ora.sample(key, 1, 0, 0, 0, 30000)
+    assert set(np.unique(t)) <= {-1, 0, 1}
+    assert np.all(np.abs(np.bincount(t + 1) / 30000 - 1 / 3) < 0.02)
+    e = ora.sample(key, 3, 0, 1, 0, 30000)
+    assert e.min() >= -21 and e.max() <= 21
+    assert abs(e.var() - 10.5) < 0.5 and abs(e.mean()) < 0.1
+    q = (1 << 40) + 12345
+    u = ora.sample(key, 2, 7, 2, q, 30000)
+    assert u.min() >= 0 and u.max() < q and abs(u.mean() / q - 0.5) < 0.01
+    # different stream ids give different streams
+    assert not np.array_equal(ora.sample(key, 2, 8, 2, q, 100), u[:100])
+
+
+# ---------------------------------------------------------------- automorphism
+def test_automorphism_group_law_and_ring_homomorphism(ora, t10):
+    n, q = t10.n, t10.q[1]
+    rng = np.random.default_rng(3)
+    a = rng.integers(0, q, n, dtype=np.uint64)
+    b = rng.integers(0, q, n, dtype=np.uint64)
+    g, h = 5, pow(5, 7, 2 * n)
+    lhs = ora.automorphism(n, q, g, ora.automorphism(n, q, h, a))
+    rhs = ora.automorphism(n, q, (g * h) % (2 * n), a)
+    assert np.array_equal(lhs, rhs)
+    psi = int(t10.psi[1])
+    ab = ora.negacyclic_mul(n, q, psi, a, b)
+    lhs = ora.automorphism(n, q, g, ab)
+    rhs = ora.negacyclic_mul(n, q, psi, ora.automorphism(n, q, g, a), ora.automorphism(n, q, g, b))
+    assert np.array_equal(lhs, rhs)
+    # sigma_{2n-1} is x -> x^{-1}: coefficient j goes to -x^{n-j}
+    inv = ora.automorphism(n, q, 2 * n - 1, a)
+    assert int(inv[0]) == int(a[0])
+    assert all(int(inv[n - j]) == (q - int(a[j])) % q for j in range(1, n))
+
+
+# ---------------------------------------------------------------- base conversion
+def _crt(res, mods):
+    M = 1
+    for m in mods:
+        M *= m
+    x = 0
+    for r, m in zip(res, mods):
+        Mi = M // m
+        x += int(r) * Mi * pow(Mi, -1, m)
+    return x % M, M
+
+
+def test_bconv_is_exact_up_to_multiple_of_source_product(ora, t10):
+    src = t10.q[:4]
+    t = t10.p[0]
+    rng = np.random.default_rng(11)
+    n = 64
+    x = np.stack([rng.integers(0, s, n, dtype=np.uint64) for s in src])
+    got = ora.bconv(x, np.array(src, np.uint64), t)
+    for c in range(n):
+        X, D = _crt([x[i, c] for i in range(4)], src)
+        ok = [u for u in range(len(src)) if (X + u * D) % t == int(got[c])]
+        assert ok, c
+
+
+def test_rescale_poly_is_floor_division(ora, t10):
+    level = 4
+    mods = t10.q[:level + 1]
+    rng = np.random.default_rng(12)
+    x = np.stack([rng.integers(0, m, t10.n, dtype=np.uint64) for m in mods])
+    got = ora.rescale_poly(t10, x, level)
+    for c in range(0, t10.n, 7):
+        X, _ = _crt(x[:, c], mods)
+        y = X // mods[level]
+        assert [int(got[i, c]) for i in range(level)] == [y % m for m in mods[:level]]
+
+
+def test_moddown_is_floor_division_by_P_minus_small(ora, t10):
+    level = 3
+    qs = t10.q[:level + 1]
+    mods = qs + t10.p
+    rng = np.random.default_rng(13)
+    x = np.stack([rng.integers(0, m, t10.n, dtype=np.uint64) for m in mods])
+    got = ora.moddown(t10, level, x)
+    Pp = 1
+    for p in t10.p:
+        Pp *= p
+    for c in range(0, t10.n, 5):
+        X, _ = _crt(x[:, c], mods)
+        base = X // Pp
+        found = [u for u in range(len(t10.p)) if all(int(got[i, c]) == (base - u) % qs[i] for i in range(level + 1))]
+        assert found, c
+
+
+# ---------------------------------------------------------------- encoding
+def test_encode_matches_direct_canonical_embedding(ora, t10):
+    n = t10.n
+    rng = np.random.default_rng(21)
+    z = rng.uniform(-1, 1, n // 2)
+    scale = 2.0 ** 30
+    m = ora.encode(t10, z, scale)
+    j = np.arange(n)
+    g = np.array([pow(5, k, 2 * n) for k in range(n // 2)])
+    ang = np.pi * np.outer(j, g) / n
+    direct = (2 * scale / n) * (np.cos(ang) @ z)
+    assert np.max(np.abs(m - direct)) <= 1.0
+    back = ora.decode(t10, m, scale, n // 2)
+    assert np.max(np.abs(back - z)) < 1e-7
+
+
+def test_slot_order_rotation_and_product(ora, t10):
+    """sigma_{5^k} rotates slots left by k; the ring product multiplies slots."""
+    n, q, psi = t10.n, t10.q[0], int(t10.psi[0])
+    rng = np.random.default_rng(22)
+    z1 = rng.uniform(-1, 1, n // 2)
+    z2 = rng.uniform(-1, 1, n // 2)
+    m0 = ora.encode(t10, z1, 2.0 ** 34)
+    r = ora.automorphism(n, q, pow(5, 3, 2 * n), np.array([x % q for x in m0.tolist()], np.uint64))
+    rc = np.array([int(x) if int(x) < q // 2 else int(x) - q for x in r], np.int64)
+    assert np.max(np.abs(ora.decode(t10, rc, 2.0 ** 34, n // 2) - np.roll(z1, -3))) < 1e-7
+    s = 2.0 ** 20
+    m1 = ora.encode(t10, z1, s)
+    m2 = ora.encode(t10, z2, s)
+    pr = ora.negacyclic_mul(n, q, psi, np.array([x % q for x in m1.tolist()], np.uint64),
+                            np.array([x % q for x in m2.tolist()], np.uint64))
+    pc = np.array([int(x) if int(x) < q // 2 else int(x) - q for x in pr], np.int64)
+    assert np.max(np.abs(ora.decode(t10, pc, s * s, n // 2) - z1 * z2)) < 1e-3
+
+
+# ---------------------------------------------------------------- scheme
+@pytest.fixture(scope="module")
+def t10keys(ora, t10):
+    gal = [t10.galois_left(k) for k in (1, 3, 4, 7, t10.n // 2 - 1)]
+    return ora.Keys(t10, bytes(range(32)), t10.L, gal)
+
+
+def test_encrypt_decrypt_roundtrip(ora, t10, t10keys):
+    z = np.random.default_rng(1).uniform(0, 1, 64)
+    ct = ora.encrypt(t10keys, z, t10.L, bytes([9] * 32))
+    assert ct.level == t10.L
+    assert np.max(np.abs(ora.decrypt(t10keys, ct, 64) - z)) < 1e-6
+    # decryption error is c0 + c1 s - m: small, centred noise
+    m = ora.encode(t10, np.pad(z, (0, 0)), t10.scales[t10.L])
+    err = ora.decrypt_coeffs(t10keys, ct) - m
+    assert np.max(np.abs(err)) < 2 ** 14
+
+
+def test_rotation_and_composition(ora, t10, t10keys):
+    h = t10.n // 2
+    z = np.random.default_rng(2).uniform(0, 1, h)
+    ct = ora.encrypt(t10keys, z, 5, bytes([4] * 32))
+    r3 = ora.rotate(t10keys, ct, 3)
+    assert np.max(np.abs(ora.decrypt(t10keys, r3, h) - np.roll(z, -3))) < 1e-5
+    r34 = ora.rotate(t10keys, r3, 4)
+    assert np.max(np.abs(ora.decrypt(t10keys, r34, h) - np.roll(z, -7))) < 1e-5
+    r7 = ora.rotate(t10keys, ct, 7)
+    assert np.max(np.abs(ora.decrypt(t10keys, r34, h) - ora.decrypt(t10keys, r7, h))) < 1e-5
+    rr = ora.rotate(t10keys, ct, -1)
+    assert np.max(np.abs(ora.decrypt(t10keys, rr, h) - np.roll(z, 1))) < 1e-5
+
+
+def test_mul_rescale_and_const_ops(ora, t10, t10keys):
+    z1 = np.random.default_rng(3).uniform(-1, 1, 256)
+    z2 = np.random.default_rng(4).uniform(-1, 1, 256)
+    a = ora.encrypt(t10keys, z1, 6, bytes([1] * 32))
+    b = ora.encrypt(t10keys, z2, 6, bytes([2] * 32))
+    p = ora.mul(t10keys, a, b)
+    assert p.level == 5
+    assert np.max(np.abs(ora.decrypt(t10keys, p, 256) - z1 * z2)) < 1e-5
+    c = ora.cmul_to(a, -2.75, 3)
+    assert c.level == 3 and np.max(np.abs(ora.decrypt(t10keys, c, 256) + 2.75 * z1)) < 1e-5
+    d = ora.add_const(a, 0.25)
+    assert np.max(np.abs(ora.decrypt(t10keys, d, 256) - z1 - 0.25)) < 1e-6
+    mk = np.zeros(256)
+    mk[::3] = 1.0
+    e = ora.mul_plain(a, mk)
+    assert e.level == 5 and np.max(np.abs(ora.decrypt(t10keys, e, 256) - z1 * mk)) < 1e-5
+    s = ora.sub(a, b)
+    assert np.max(np.abs(ora.decrypt(t10keys, s, 256) - (z1 - z2))) < 1e-6
+
+
+def test_poly7_matches_polynomial(ora, t10, t10keys):
+    from oracle import shadow
+    z = np.random.default_rng(5).uniform(-1, 1, 128)
+    a = ora.encrypt(t10keys, z, 7, bytes([3] * 32))
+    p = ora.poly7(t10keys, a, shadow.G_COEF)
+    assert p.level == 4
+    assert np.max(np.abs(ora.decrypt(t10keys, p, 128) - shadow.poly7(z, shadow.G_COEF))) < 1e-4
