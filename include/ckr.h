@@ -1,0 +1,202 @@
+/*
+ * ckr.h -- C ABI of the MI355X (gfx950) library for encrypted ranking,
+ * order statistics and sorting under RNS-CKKS (arXiv 2412.15126).
+ *
+ * The paper's problem statement fixes the user-level calls: an encrypted
+ * vector v of N reals goes in; out come its fractional ranking (Algorithm
+ * Rank, section 3.1), a one-hot mask of its minimum with the minimum's value
+ * (Algorithm Order Statistic, section 3.2, with the Tie-Correction Offset of
+ * section 4), or its sorted form (Algorithm Sorting, section 3.3).  The
+ * comparison function is the f/g composite of section 2.2,
+ *   Cmp(x, y) = (f^{d_f}(g^{d_g}(x - y)) + 1) / 2.
+ *
+ * Conventions for every call:
+ *  - Handles returned to the caller are caller-owned; release each with the
+ *    matching *_free.  Host arrays are borrowed for the duration of the call.
+ *  - Device memory belongs to the context.  It comes from hipMalloc unless the
+ *    caller installs an allocator (ckr_context_set_allocator).
+ *  - No exception or abort crosses this boundary.  Every call returns a
+ *    ckr_status; the message of the last failure on the calling thread is
+ *    available from ckr_last_error().
+ *  - Work is issued on the context's stream (the null stream unless set).
+ *    Calls that return host data (decrypt, export) synchronise that stream.
+ *  - Results are deterministic: equal seeds give equal ciphertexts, bit for
+ *    bit, whether a query runs alone or inside a batch.
+ *  - A ciphertext at level l holds 2 polynomials x (l+1) RNS limbs x n
+ *    coefficients.  Exported form: uint64 words [poly][limb][coeff], each a
+ *    canonical residue in [0, q_limb), in the coefficient domain.
+ */
+#ifndef CKR_H
+#define CKR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CKR_OK = 0,
+    CKR_E_INVALID = -1, /* bad argument, null handle, residue >= q on import   */
+    CKR_E_RANGE = -2,   /* N not a power of two in [2, 2^15], or N^2 > n/2      */
+    CKR_E_DEPTH = -3,   /* ciphertext has too few levels for the circuit       */
+    CKR_E_NOMEM = -4,   /* device allocation failed or HBM budget exceeded     */
+    CKR_E_DEVICE = -5,  /* HIP runtime error                                   */
+    CKR_E_BUSY = -6     /* ticket not finished within the timeout              */
+} ckr_status;
+
+typedef struct ckr_context ckr_context;
+typedef struct ckr_keys ckr_keys;
+typedef struct ckr_ct ckr_ct;
+
+/* Parameter set.  Ring degree n = 2^log_n (10..17).  The ciphertext modulus
+ * chain is q_0..q_{n_q-1}: q_0 is the largest prime below 2^q0_bits, the
+ * others are rescaling primes chosen level by level, from the top, as the
+ * unused prime nearest to the running scale (top scale 2^log_scale).  n_p
+ * special primes (largest primes below 2^p_bits) serve hybrid key switching
+ * with dnum digits.  Every prime is 1 mod 2n and below 2^50. */
+typedef struct {
+    uint32_t log_n;
+    uint32_t n_q;
+    uint32_t q0_bits;
+    uint32_t log_scale;
+    uint32_t n_p;
+    uint32_t p_bits;
+    uint32_t dnum;
+} ckr_params;
+
+/* Comparator composition: g applied d_g times, then f applied d_f times
+ * (section 2.2).  Each application consumes 3 levels. */
+typedef struct {
+    uint8_t d_g;
+    uint8_t d_f;
+} ckr_sign;
+
+/* Create a context on HIP device `hip_device`.  hbm_budget bounds the bytes
+ * the context may hold on the device (0 = no bound); beyond it allocations
+ * fail with CKR_E_NOMEM.  Derives the prime chain and uploads the transform
+ * tables. */
+ckr_status ckr_context_create(const ckr_params *params, int hip_device, size_t hbm_budget, ckr_context **out);
+void ckr_context_free(ckr_context *ctx);
+
+/* Issue all work on `hip_stream` (a hipStream_t, e.g. torch's current stream). */
+ckr_status ckr_context_set_stream(ckr_context *ctx, void *hip_stream);
+
+/* Route device allocations through alloc/free (e.g. PyTorch's caching
+ * allocator).  Must be called before any key or ciphertext exists. */
+ckr_status ckr_context_set_allocator(ckr_context *ctx, void *(*alloc)(size_t bytes, void *user),
+                                     void (*free_fn)(void *ptr, void *user), void *user);
+
+/* Moduli (n_q + n_p values: q chain then special primes) and per-level scales
+ * (n_q values).  Either pointer may be NULL. */
+ckr_status ckr_context_info(const ckr_context *ctx, uint64_t *moduli, double *scales);
+
+/* Host-only: derive the modulus chain of `params` without a device.  moduli
+ * receives n_q + n_p values, scales n_q values (either may be NULL). */
+ckr_status ckr_params_derive(const ckr_params *params, uint64_t *moduli, double *scales);
+
+/* Host-only: encode real slot values z[0..count) (other slots 0) at `scale`
+ * into the n = 2^log_n signed coefficients m_j = round((2 scale / n) *
+ * Re sum_k z_k zeta^{-j 5^k}), zeta = exp(i pi / n), rounding half away from
+ * zero.  CKR_E_RANGE if a coefficient exceeds 2^62. */
+ckr_status ckr_encode(uint32_t log_n, const double *z, uint32_t count, double scale, int64_t *m);
+
+/* Host-only: `count` samples of the ChaCha20 stream keyed by `seed` with
+ * nonce (purpose, id): kind 0 ternary, 1 centred binomial (eta = 21),
+ * 2 uniform in [0, q). */
+ckr_status ckr_sample(const uint8_t seed[32], uint32_t purpose, uint64_t id, int kind, uint64_t q, size_t count,
+                      int64_t *out);
+
+/* Device bytes currently held by the context and its high-water mark. */
+ckr_status ckr_context_memory(const ckr_context *ctx, size_t *in_use, size_t *high_water);
+
+/* Key generation from a 32-byte seed (ChaCha20 streams, RFC 8439).  Makes the
+ * secret key (kept in host memory), the public key, the relinearisation key
+ * and the rotation keys the circuits need for every N in Ns[0..nN).  Keys
+ * cover limbs q_0..q_max_level plus the special primes and stay resident on
+ * the device.  `what` selects circuits: bit 0 rank, bit 1 argmin, bit 2 sort
+ * (their rotation sets differ). */
+ckr_status ckr_keygen(ckr_context *ctx, const uint8_t seed[32], uint32_t max_level, const uint32_t *Ns, size_t nN,
+                      uint32_t what, ckr_keys **out);
+void ckr_keys_free(ckr_keys *keys);
+
+/* Rotation keys for explicit slot shifts (k > 0: left rotation new[j] = old[j+k];
+ * k < 0: right rotation), added to `keys`. */
+ckr_status ckr_keys_add_rotations(ckr_context *ctx, ckr_keys *keys, const int64_t *shifts, size_t count);
+
+/* Encrypt v[0..N) into slots [0, N) (others 0) at `level` with the public key;
+ * randomness from a 32-byte seed. */
+ckr_status ckr_encrypt(ckr_context *ctx, const ckr_keys *keys, const double *v, uint32_t N, uint32_t level,
+                       const uint8_t seed[32], ckr_ct **out);
+
+/* Decrypt and decode slots [0, count) (real parts) into out. */
+ckr_status ckr_decrypt(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *ct, double *out, uint32_t count);
+
+/* Fractional ranking (Algorithm Rank): out slots [0,N) hold rank(v_j).
+ * tie_correct != 0 adds the tie-correction offset (section 4), so the output
+ * is a permutation of 1..N.  The output sits at level(v) - depth. */
+ckr_status ckr_rank(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, ckr_sign cmp, int tie_correct,
+                    ckr_ct **out);
+
+/* Levels consumed by ckr_rank / ckr_argmin / ckr_sort for the given comparators. */
+uint32_t ckr_rank_depth(ckr_sign cmp, int tie_correct);
+uint32_t ckr_argmin_depth(ckr_sign cmp, ckr_sign ind);
+uint32_t ckr_sort_depth(ckr_sign cmp, ckr_sign ind);
+
+/* Minimum with tie-correction (Algorithm Order Statistic with k = 1):
+ * onehot slots [0,N) hold 1 at the lowest index among the minima, 0
+ * elsewhere; value slot 0 holds the minimum.  `ind` is the composition of the
+ * one-sided indicator Cmp(1.5, k). */
+ckr_status ckr_argmin(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, ckr_sign cmp, ckr_sign ind,
+                      ckr_ct **onehot, ckr_ct **value);
+
+/* Sorting (Algorithm Sorting), distinct inputs: out slots [0,N) hold v in
+ * increasing order. */
+ckr_status ckr_sort(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, ckr_sign cmp, ckr_sign ind,
+                    ckr_ct **out);
+
+/* Rank on `count` ciphertexts of equal N and level, run as one batched pass:
+ * every kernel launch covers all of them.  Outputs equal count single calls,
+ * bit for bit. */
+ckr_status ckr_rank_batch(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *const *v, size_t count, uint32_t N,
+                          ckr_sign cmp, ckr_ct **out);
+
+/* Ciphertext access.  export: words = 2*(level+1)*n uint64 (layout above). */
+uint32_t ckr_ct_level(const ckr_ct *ct);
+double ckr_ct_scale(const ckr_ct *ct);
+ckr_status ckr_ct_export(ckr_context *ctx, const ckr_ct *ct, uint64_t *coeff_limbs, size_t words);
+/* import: rejects any residue >= its modulus (CKR_E_INVALID). */
+ckr_status ckr_ct_import(ckr_context *ctx, const uint64_t *coeff_limbs, size_t words, uint32_t level, ckr_ct **out);
+void ckr_ct_free(ckr_ct *ct);
+
+/* Homomorphic operations on single ciphertexts (the building blocks the
+ * circuits use; exposed for testing and custom circuits). */
+ckr_status ckr_op_rotate(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, int64_t k, ckr_ct **out);
+ckr_status ckr_op_mul(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, const ckr_ct *b, ckr_ct **out);
+ckr_status ckr_op_add(ckr_context *ctx, const ckr_ct *a, const ckr_ct *b, ckr_ct **out);
+ckr_status ckr_op_sub(ckr_context *ctx, const ckr_ct *a, const ckr_ct *b, ckr_ct **out);
+ckr_status ckr_op_rescale(ckr_context *ctx, const ckr_ct *a, ckr_ct **out);
+/* c * a brought to level `target` (drop to target+1 limbs, multiply by
+ * round(c * D_target * q_{target+1} / D_level), rescale). */
+ckr_status ckr_op_cmul_to(ckr_context *ctx, const ckr_ct *a, double c, uint32_t target, ckr_ct **out);
+ckr_status ckr_op_add_const(ckr_context *ctx, const ckr_ct *a, double c, ckr_ct **out);
+/* slot-wise product with the plaintext z[0..count) (others 0), then rescale */
+ckr_status ckr_op_mul_plain(ckr_context *ctx, const ckr_ct *a, const double *z, uint32_t count, ckr_ct **out);
+
+/* Raw negacyclic NTT on device buffers: `limbs` limbs of n words at `data`
+ * (device pointer), limb t reduced modulo modulus index first_mod + t.
+ * inverse != 0 runs the inverse transform.  Forward output order is the
+ * library's internal evaluation order; inverse(forward(x)) == x. */
+ckr_status ckr_ntt_device(ckr_context *ctx, uint64_t *data, uint32_t limbs, uint32_t first_mod, int inverse);
+
+/* Per-kernel timing of the last circuit call (rank/argmin/sort/batch), read
+ * from HIP events recorded on the context stream when profiling is enabled. */
+ckr_status ckr_set_profiling(ckr_context *ctx, int enable);
+
+const char *ckr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,276 @@
+"""Python binding of libckr.so (include/ckr.h): argument marshalling only.
+
+Every homomorphic step runs in the library's HIP kernels.  Importing this
+module loads the built library and raises if it is missing; there is no
+fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libckr.so")
+
+STATUS = {0: "ok", -1: "invalid", -2: "range", -3: "depth", -4: "nomem", -5: "device", -6: "busy"}
+
+
+class CkrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("log_n", C.c_uint32), ("n_q", C.c_uint32), ("q0_bits", C.c_uint32), ("log_scale", C.c_uint32),
+                ("n_p", C.c_uint32), ("p_bits", C.c_uint32), ("dnum", C.c_uint32)]
+
+    @staticmethod
+    def of(pset):
+        return Params(pset["logn"], pset["L"] + 1, pset["q0_bits"], pset["log_scale"], pset["K"], pset["p_bits"],
+                      pset["dnum"])
+
+
+class Sign(C.Structure):
+    _fields_ = [("d_g", C.c_uint8), ("d_f", C.c_uint8)]
+
+
+vp = C.c_void_p
+u64p = C.POINTER(C.c_uint64)
+i64p = C.POINTER(C.c_int64)
+dblp = C.POINTER(C.c_double)
+u32p = C.POINTER(C.c_uint32)
+
+_SIGS = {
+    "ckr_last_error": (C.c_char_p, []),
+    "ckr_context_create": (C.c_int, [C.POINTER(Params), C.c_int, C.c_size_t, C.POINTER(vp)]),
+    "ckr_context_free": (None, [vp]),
+    "ckr_context_set_stream": (C.c_int, [vp, vp]),
+    "ckr_context_set_allocator": (C.c_int, [vp, vp, vp, vp]),
+    "ckr_context_info": (C.c_int, [vp, u64p, dblp]),
+    "ckr_params_derive": (C.c_int, [C.POINTER(Params), u64p, dblp]),
+    "ckr_encode": (C.c_int, [C.c_uint32, dblp, C.c_uint32, C.c_double, i64p]),
+    "ckr_sample": (C.c_int, [C.c_char_p, C.c_uint32, C.c_uint64, C.c_int, C.c_uint64, C.c_size_t, i64p]),
+    "ckr_context_memory": (C.c_int, [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "ckr_keygen": (C.c_int, [vp, C.c_char_p, C.c_uint32, u32p, C.c_size_t, C.c_uint32, C.POINTER(vp)]),
+    "ckr_keys_free": (None, [vp]),
+    "ckr_keys_add_rotations": (C.c_int, [vp, vp, i64p, C.c_size_t]),
+    "ckr_encrypt": (C.c_int, [vp, vp, dblp, C.c_uint32, C.c_uint32, C.c_char_p, C.POINTER(vp)]),
+    "ckr_decrypt": (C.c_int, [vp, vp, vp, dblp, C.c_uint32]),
+    "ckr_rank": (C.c_int, [vp, vp, vp, C.c_uint32, Sign, C.c_int, C.POINTER(vp)]),
+    "ckr_rank_depth": (C.c_uint32, [Sign, C.c_int]),
+    "ckr_argmin_depth": (C.c_uint32, [Sign, Sign]),
+    "ckr_sort_depth": (C.c_uint32, [Sign, Sign]),
+    "ckr_argmin": (C.c_int, [vp, vp, vp, C.c_uint32, Sign, Sign, C.POINTER(vp), C.POINTER(vp)]),
+    "ckr_sort": (C.c_int, [vp, vp, vp, C.c_uint32, Sign, Sign, C.POINTER(vp)]),
+    "ckr_rank_batch": (C.c_int, [vp, vp, C.POINTER(vp), C.c_size_t, C.c_uint32, Sign, C.POINTER(vp)]),
+    "ckr_ct_level": (C.c_uint32, [vp]),
+    "ckr_ct_scale": (C.c_double, [vp]),
+    "ckr_ct_export": (C.c_int, [vp, vp, u64p, C.c_size_t]),
+    "ckr_ct_import": (C.c_int, [vp, u64p, C.c_size_t, C.c_uint32, C.POINTER(vp)]),
+    "ckr_ct_free": (None, [vp]),
+    "ckr_op_rotate": (C.c_int, [vp, vp, vp, C.c_int64, C.POINTER(vp)]),
+    "ckr_op_mul": (C.c_int, [vp, vp, vp, vp, C.POINTER(vp)]),
+    "ckr_op_add": (C.c_int, [vp, vp, vp, C.POINTER(vp)]),
+    "ckr_op_sub": (C.c_int, [vp, vp, vp, C.POINTER(vp)]),
+    "ckr_op_rescale": (C.c_int, [vp, vp, C.POINTER(vp)]),
+    "ckr_op_cmul_to": (C.c_int, [vp, vp, C.c_double, C.c_uint32, C.POINTER(vp)]),
+    "ckr_op_add_const": (C.c_int, [vp, vp, C.c_double, C.POINTER(vp)]),
+    "ckr_op_mul_plain": (C.c_int, [vp, vp, dblp, C.c_uint32, C.POINTER(vp)]),
+    "ckr_ntt_device": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32, C.c_int]),
+    "ckr_set_profiling": (C.c_int, [vp, C.c_int]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libckr.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run paper_2412_15126_amd/build.py (or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ok(st):
+    if st != 0:
+        raise CkrError(st, lib().ckr_last_error().decode())
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+def sign(cmp):
+    return Sign(int(cmp[0]), int(cmp[1]))
+
+
+# ---- host-only helpers ------------------------------------------------------
+def derive_params(pset):
+    nq, K = pset["L"] + 1, pset["K"]
+    mods = np.zeros(nq + K, np.uint64)
+    scales = np.zeros(nq, np.float64)
+    _ok(lib().ckr_params_derive(C.byref(Params.of(pset)), _p(mods, u64p), _p(scales, dblp)))
+    return mods, scales
+
+
+def encode(log_n, z, scale):
+    z = np.ascontiguousarray(z, np.float64)
+    m = np.zeros(1 << log_n, np.int64)
+    _ok(lib().ckr_encode(log_n, _p(z, dblp), len(z), scale, _p(m, i64p)))
+    return m
+
+
+def sample(seed, purpose, oid, kind, q, count):
+    out = np.zeros(count, np.int64)
+    _ok(lib().ckr_sample(bytes(seed), purpose, oid, kind, q, count, _p(out, i64p)))
+    return out
+
+
+def rank_depth(cmp):
+    return int(lib().ckr_rank_depth(sign(cmp), 0))
+
+
+# ---- device objects -----------------------------------------------------------
+class Context:
+    def __init__(self, pset, device=0, hbm_budget=0):
+        self.pset = dict(pset)
+        self.n = 1 << pset["logn"]
+        self.L = pset["L"]
+        h = vp()
+        _ok(lib().ckr_context_create(C.byref(Params.of(pset)), device, hbm_budget, C.byref(h)))
+        self.h = h
+        nq, K = pset["L"] + 1, pset["K"]
+        self.moduli = np.zeros(nq + K, np.uint64)
+        self.scales = np.zeros(nq, np.float64)
+        _ok(lib().ckr_context_info(self.h, _p(self.moduli, u64p), _p(self.scales, dblp)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ckr_context_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_stream(self, stream_ptr):
+        _ok(lib().ckr_context_set_stream(self.h, vp(stream_ptr)))
+
+    def memory(self):
+        a, b = C.c_size_t(), C.c_size_t()
+        _ok(lib().ckr_context_memory(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    # -- keys and ciphertexts
+    def keygen(self, seed, max_level, Ns=(), what=1):
+        Ns = np.array(list(Ns), np.uint32)
+        h = vp()
+        _ok(lib().ckr_keygen(self.h, bytes(seed), max_level, _p(Ns, u32p), len(Ns), what, C.byref(h)))
+        return Keys(self, h)
+
+    def encrypt(self, keys, v, level, seed):
+        v = np.ascontiguousarray(v, np.float64)
+        h = vp()
+        _ok(lib().ckr_encrypt(self.h, keys.h, _p(v, dblp), len(v), level, bytes(seed), C.byref(h)))
+        return Ct(self, h)
+
+    def decrypt(self, keys, ct, count):
+        out = np.zeros(count, np.float64)
+        _ok(lib().ckr_decrypt(self.h, keys.h, ct.h, _p(out, dblp), count))
+        return out
+
+    def import_ct(self, arr):
+        arr = np.ascontiguousarray(arr, np.uint64)
+        h = vp()
+        _ok(lib().ckr_ct_import(self.h, _p(arr, u64p), arr.size, arr.shape[1] - 1, C.byref(h)))
+        return Ct(self, h)
+
+    # -- circuits
+    def rank(self, keys, ct, N, cmp):
+        h = vp()
+        _ok(lib().ckr_rank(self.h, keys.h, ct.h, N, sign(cmp), 0, C.byref(h)))
+        return Ct(self, h)
+
+    def rank_batch(self, keys, cts, N, cmp):
+        arr = (vp * len(cts))(*[c.h for c in cts])
+        out = (vp * len(cts))()
+        _ok(lib().ckr_rank_batch(self.h, keys.h, arr, len(cts), N, sign(cmp), out))
+        return [Ct(self, vp(o)) for o in out]
+
+    # -- single operations
+    def _unary(self, fn, *args):
+        h = vp()
+        _ok(fn(self.h, *args, C.byref(h)))
+        return Ct(self, h)
+
+    def rotate(self, keys, a, k):
+        return self._unary(lib().ckr_op_rotate, keys.h, a.h, int(k))
+
+    def mul(self, keys, a, b):
+        return self._unary(lib().ckr_op_mul, keys.h, a.h, b.h)
+
+    def add(self, a, b):
+        return self._unary(lib().ckr_op_add, a.h, b.h)
+
+    def sub(self, a, b):
+        return self._unary(lib().ckr_op_sub, a.h, b.h)
+
+    def rescale(self, a):
+        return self._unary(lib().ckr_op_rescale, a.h)
+
+    def cmul_to(self, a, c, target):
+        return self._unary(lib().ckr_op_cmul_to, a.h, float(c), int(target))
+
+    def add_const(self, a, c):
+        return self._unary(lib().ckr_op_add_const, a.h, float(c))
+
+    def mul_plain(self, a, z):
+        z = np.ascontiguousarray(z, np.float64)
+        return self._unary(lib().ckr_op_mul_plain, a.h, _p(z, dblp), len(z))
+
+    def ntt_device(self, ptr, limbs, first_mod, inverse):
+        _ok(lib().ckr_ntt_device(self.h, vp(ptr), limbs, first_mod, int(inverse)))
+
+
+class Keys:
+    def __init__(self, ctx, h):
+        self.ctx, self.h = ctx, h
+
+    def add_rotations(self, shifts):
+        s = np.array(list(shifts), np.int64)
+        _ok(lib().ckr_keys_add_rotations(self.ctx.h, self.h, _p(s, i64p), len(s)))
+
+    def __del__(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            lib().ckr_keys_free(self.h)
+            self.h = None
+
+
+class Ct:
+    def __init__(self, ctx, h):
+        self.ctx, self.h = ctx, h
+
+    @property
+    def level(self):
+        return int(lib().ckr_ct_level(self.h))
+
+    @property
+    def scale(self):
+        return float(lib().ckr_ct_scale(self.h))
+
+    def export(self):
+        out = np.zeros((2, self.level + 1, self.ctx.n), np.uint64)
+        _ok(lib().ckr_ct_export(self.ctx.h, self.h, _p(out, u64p), out.size))
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            lib().ckr_ct_free(self.h)
+            self.h = None

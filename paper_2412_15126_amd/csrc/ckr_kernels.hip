@@ -1,0 +1,505 @@
+// ckr_kernels.hip -- gfx950 kernels of the RNS-CKKS path.
+//
+// Residues live in HBM as canonical uint64 in [0, q), q < 2^50, limb-major
+// (each limb = n contiguous words).  Inside a kernel they are carried as
+// doubles: every value below 2^52 is an exact double, so a modular product
+// is computed exactly with FP64 FMAs (error-free product split plus a
+// rounded quotient estimate), which runs at the full FP64 vector rate on
+// CDNA4 -- faster than 64-bit integer multiplies.  No MFMA: the work is
+// exact modular integer arithmetic.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace ckr {
+
+#define C52 4503599627370496.0  // 2^52
+
+// ------------------------------------------------------------------------
+// exact modular arithmetic in FP64
+// ------------------------------------------------------------------------
+// uint64 x < 2^52  ->  double (exact)
+__device__ __forceinline__ double u2d(u64 x) {
+    return __hiloint2double(0x43300000 | (int)(x >> 32), (int)(u32)x) - C52;
+}
+// integer-valued double in [0, 2^52)  ->  uint64
+__device__ __forceinline__ u64 d2u(double d) {
+    return (u64)__double_as_longlong(d + C52) & 0xFFFFFFFFFFFFFull;
+}
+
+// x * w mod q for a constant w with wq = w/q; x in [0, 2^52).
+// The product is split exactly (hi + lo), the quotient estimate round(x*wq)
+// is within 1 of x*w/q, so the result lands in (0, 2q).
+__device__ __forceinline__ double mm_lazy(double x, double w, double wq, double q) {
+    double hi = x * w;
+    double lo = __fma_rn(x, w, -hi);
+    double k = __fma_rn(x, wq, C52) - (C52 + 1.0);
+    return __fma_rn(-k, q, hi) + lo;
+}
+// x * y mod q for canonical x, y < q < 2^50: result in (-0.75q, 0.75q)
+__device__ __forceinline__ double mm_signed(double x, double y, double q, double qinv) {
+    double hi = x * y;
+    double lo = __fma_rn(x, y, -hi);
+    double k = __fma_rn(hi, qinv, C52) - C52;
+    return __fma_rn(-k, q, hi) + lo;
+}
+__device__ __forceinline__ double red1(double x, double q) { return x >= q ? x - q : x; }  // [0,2q) -> [0,q)
+__device__ __forceinline__ double pos1(double x, double q) { return x < 0 ? x + q : x; }   // (-q,q) -> [0,q)
+// x in [0, 2^53) -> x mod q
+__device__ __forceinline__ double red_any(double x, double q, double qinv) {
+    double k = floor(x * qinv);
+    double r = __fma_rn(-k, q, x);
+    r = r < 0 ? r + q : r;
+    return r >= q ? r - q : r;
+}
+
+// ------------------------------------------------------------------------
+// negacyclic NTT: one pass of a two-pass decomposition n = n1 * n2
+// ------------------------------------------------------------------------
+// Forward transform (Cooley-Tukey, merged psi twiddles): stage g pairs indices
+// j, j + n/2^{g+1} with twiddle tw[2^g + (j >> (logn - g))].  The first logn1
+// stages act on columns {c + n2 r}, the rest on contiguous rows of n2.  The
+// inverse runs the Gentleman-Sande butterflies in the opposite stage order,
+// rows first, and folds n^{-1} into its final stage.
+//
+// A workgroup owns C columns (or rows) of S = 2^LOGS elements.  Each thread
+// holds E = 2^LOGE elements in registers and runs up to LOGE stages between
+// LDS exchanges; a round's LOGE-bit window of the local index selects which
+// elements a thread holds.  Values stay lazily reduced: [0, 4q) in the
+// forward direction, [0, 2q) in the inverse, canonical at the end.
+template <int LOGS, int LOGE, int C, bool COLPASS, bool INV>
+__global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
+    ntt_pass(u64 *__restrict__ base, size_t poly_stride, int limbs, LimbMap map, int logn,
+             const double2 *__restrict__ mq, const double2 *__restrict__ twtab, const double2 *__restrict__ twlast) {
+    constexpr int S = 1 << LOGS, E = 1 << LOGE, TPC = S / E, NT = C * TPC;
+    constexpr int NR = (LOGS + LOGE - 1) / LOGE;
+    constexpr int SP = S + (S >> 4) + 1;
+    constexpr bool FINAL = (INV == COLPASS);
+    __shared__ double lds[C * SP];
+
+    const int job = blockIdx.y;
+    const int p = job / limbs, t = job - p * limbs;
+    const int mod = map(t);
+    const size_t n = (size_t)1 << logn;
+    u64 *data = base + (size_t)p * poly_stride + (size_t)t * n;
+    const double q = mq[mod].x, two_q = 2.0 * q;
+    const double2 *tw = twtab + (size_t)mod * n;
+
+    const int ncol = (int)(n >> LOGS);
+    const int c0 = blockIdx.x * C;
+    const int tid = threadIdx.x;
+    const int cl = COLPASS ? (tid % C) : (tid / TPC);
+    const int tau = COLPASS ? (tid / C) : (tid % TPC);
+    const int c = c0 + cl;
+    const int g0 = COLPASS ? 0 : (logn - LOGS);
+    const int cpart = COLPASS ? 0 : c;
+    auto gaddr = [&](int r) -> size_t { return COLPASS ? (size_t)r * ncol + c : (size_t)c * S + r; };
+    auto lidx = [&](int cc, int r) -> int { return cc * SP + r + (r >> 4); };
+
+    double x[E];
+
+#pragma unroll
+    for (int rho = 0; rho < NR; rho++) {
+        const int w = INV ? min(rho * LOGE, LOGS - LOGE) : max(LOGS - (rho + 1) * LOGE, 0);
+        const int lo = tau & ((1 << w) - 1), hi = tau >> w;
+        const int rbase = (hi << (w + LOGE)) | lo;
+        const bool direct = COLPASS || w >= 3;
+        // ---- load
+        if (rho == 0) {
+            if (direct) {
+#pragma unroll
+                for (int k = 0; k < E; k++) x[k] = u2d(data[gaddr(rbase | (k << w))]);
+            } else {
+                // rows are contiguous: the tile is C*S consecutive words
+                const u64 *src = data + (size_t)c0 * S;
+                for (int i = tid; i < C * S; i += NT) lds[lidx(i / S, i % S)] = u2d(src[i]);
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < E; k++) x[k] = lds[lidx(cl, rbase | (k << w))];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < E; k++) x[k] = lds[lidx(cl, rbase | (k << w))];
+        }
+        // ---- butterflies
+        if (!INV) {
+            const int s_begin = rho * LOGE, s_end = min((rho + 1) * LOGE, LOGS);
+#pragma unroll
+            for (int s = s_begin; s < s_end; s++) {
+                const int kb = (LOGS - 1 - s) - w;
+                const int g = g0 + s;
+#pragma unroll
+                for (int k = 0; k < E; k++) {
+                    if (k & (1 << kb)) continue;
+                    const int k2 = k | (1 << kb);
+                    const int r = rbase | (k << w);
+                    const double2 W = tw[(1 << g) + (cpart << s) + (r >> (LOGS - s))];
+                    double u = x[k];
+                    u = u >= two_q ? u - two_q : u;
+                    const double v = mm_lazy(x[k2], W.x, W.y, q);
+                    x[k] = u + v;
+                    x[k2] = u - v + two_q;
+                }
+            }
+        } else {
+            const int b_begin = rho * LOGE, b_end = min((rho + 1) * LOGE, LOGS);
+#pragma unroll
+            for (int b = b_begin; b < b_end; b++) {
+                const int s = LOGS - 1 - b;
+                const int kb = b - w;
+                const int g = g0 + s;
+#pragma unroll
+                for (int k = 0; k < E; k++) {
+                    if (k & (1 << kb)) continue;
+                    const int k2 = k | (1 << kb);
+                    const double sm = x[k] + x[k2];
+                    const double d = x[k] - x[k2] + two_q;
+                    if (FINAL && g == 0) {
+                        const double2 N0 = twlast[2 * mod], N1 = twlast[2 * mod + 1];
+                        x[k] = mm_lazy(sm, N0.x, N0.y, q);
+                        x[k2] = mm_lazy(d, N1.x, N1.y, q);
+                    } else {
+                        const int r = rbase | (k << w);
+                        const double2 W = tw[(1 << g) + (cpart << s) + (r >> (LOGS - s))];
+                        x[k] = sm >= two_q ? sm - two_q : sm;
+                        x[k2] = mm_lazy(d, W.x, W.y, q);
+                    }
+                }
+            }
+        }
+        // ---- store
+        if (rho == NR - 1) {
+            if (FINAL) {
+#pragma unroll
+                for (int k = 0; k < E; k++) {
+                    double v = x[k];
+                    if (!INV) v = v >= two_q ? v - two_q : v;
+                    x[k] = v >= q ? v - q : v;
+                }
+            }
+            if (direct) {
+#pragma unroll
+                for (int k = 0; k < E; k++) data[gaddr(rbase | (k << w))] = d2u(x[k]);
+            } else {
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < E; k++) lds[lidx(cl, rbase | (k << w))] = x[k];
+                __syncthreads();
+                u64 *dst = data + (size_t)c0 * S;
+                for (int i = tid; i < C * S; i += NT) dst[i] = d2u(lds[lidx(i / S, i % S)]);
+            }
+        } else {
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < E; k++) lds[lidx(cl, rbase | (k << w))] = x[k];
+            __syncthreads();
+        }
+    }
+}
+
+template <int LOGS, int LOGE, int C, bool COLPASS, bool INV>
+static void launch_pass(const DevTables &T, const LimbBatch &b, hipStream_t s) {
+    const int logn = T.logn;
+    const int blocks = (1 << (logn - LOGS)) / C;
+    dim3 grid(blocks, b.limbs * b.polys);
+    dim3 block(C * (1 << (LOGS - LOGE)));
+    hipLaunchKernelGGL((ntt_pass<LOGS, LOGE, C, COLPASS, INV>), grid, block, 0, s, b.base, b.poly_stride, b.limbs,
+                       b.map, logn, T.mq, INV ? T.tw_inv : T.tw_fwd, T.tw_last);
+}
+
+template <int L1, int E1, int C1, int L2, int E2, int C2>
+static void ntt_two_pass(const DevTables &T, const LimbBatch &b, bool inverse, hipStream_t s) {
+    if (!inverse) {
+        launch_pass<L1, E1, C1, true, false>(T, b, s);
+        launch_pass<L2, E2, C2, false, false>(T, b, s);
+    } else {
+        launch_pass<L2, E2, C2, false, true>(T, b, s);
+        launch_pass<L1, E1, C1, true, true>(T, b, s);
+    }
+}
+
+void k_ntt(const DevTables &T, const LimbBatch &b, bool inverse, hipStream_t s) {
+    if (b.limbs * b.polys == 0) return;
+    switch (T.logn) {
+    case 10: ntt_two_pass<5, 4, 16, 5, 4, 32>(T, b, inverse, s); break;
+    case 11: ntt_two_pass<6, 3, 16, 5, 4, 32>(T, b, inverse, s); break;
+    case 12: ntt_two_pass<6, 3, 16, 6, 3, 16>(T, b, inverse, s); break;
+    case 13: ntt_two_pass<7, 4, 16, 6, 3, 16>(T, b, inverse, s); break;
+    case 14: ntt_two_pass<7, 4, 16, 7, 4, 16>(T, b, inverse, s); break;
+    case 15: ntt_two_pass<8, 4, 16, 7, 4, 16>(T, b, inverse, s); break;
+    case 16: ntt_two_pass<8, 4, 16, 8, 4, 16>(T, b, inverse, s); break;
+    case 17: ntt_two_pass<9, 4, 16, 8, 4, 16>(T, b, inverse, s); break;
+    default: break;
+    }
+}
+
+// ------------------------------------------------------------------------
+// elementwise kernels: grid.x covers n/2 pairs of coefficients, grid.y the limbs
+// ------------------------------------------------------------------------
+#define EW_PROLOGUE                                                       \
+    const int job = blockIdx.y;                                           \
+    const int p = job / limbs, t = job - p * limbs;                       \
+    const size_t n = (size_t)1 << logn;                                   \
+    const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 2; \
+    if (i >= n) return;
+
+__global__ void ew_add(u64 *out, const u64 *a, const u64 *b, int limbs, size_t so, size_t sa, size_t sb, LimbMap map,
+                       int logn, const u64 *qi, int sub) {
+    EW_PROLOGUE
+    const u64 q = qi[map(t)];
+    const ulonglong2 va = *(const ulonglong2 *)(a + p * sa + t * n + i);
+    const ulonglong2 vb = *(const ulonglong2 *)(b + p * sb + t * n + i);
+    ulonglong2 r;
+    if (sub) {
+        r.x = va.x >= vb.x ? va.x - vb.x : va.x + (q - vb.x);
+        r.y = va.y >= vb.y ? va.y - vb.y : va.y + (q - vb.y);
+    } else {
+        r.x = va.x + vb.x; r.x = r.x >= q ? r.x - q : r.x;
+        r.y = va.y + vb.y; r.y = r.y >= q ? r.y - q : r.y;
+    }
+    *(ulonglong2 *)(out + p * so + t * n + i) = r;
+}
+
+__global__ void ew_add_scalar(u64 *data, int limbs, size_t stride, LimbMap map, int logn, const u64 *qi,
+                              LimbScalars c) {
+    EW_PROLOGUE
+    const u64 q = qi[map(t)];
+    const u64 k = (u64)c.v[t];
+    u64 *ptr = data + p * stride + t * n + i;
+    ulonglong2 v = *(ulonglong2 *)ptr;
+    v.x += k; v.x = v.x >= q ? v.x - q : v.x;
+    v.y += k; v.y = v.y >= q ? v.y - q : v.y;
+    *(ulonglong2 *)ptr = v;
+}
+
+__global__ void ew_mul_scalar(u64 *out, const u64 *a, int limbs, size_t so, size_t sa, LimbMap map, int logn,
+                              const double2 *mq, LimbScalars c) {
+    EW_PROLOGUE
+    const double q = mq[map(t)].x;
+    const double w = c.v[t], wq = c.vq[t];
+    const ulonglong2 v = *(const ulonglong2 *)(a + p * sa + t * n + i);
+    ulonglong2 r;
+    r.x = d2u(red1(mm_lazy(u2d(v.x), w, wq, q), q));
+    r.y = d2u(red1(mm_lazy(u2d(v.y), w, wq, q), q));
+    *(ulonglong2 *)(out + p * so + t * n + i) = r;
+}
+
+__global__ void ew_mul_pt(u64 *out, const u64 *a, const u64 *pt, int limbs, size_t so, size_t sa, LimbMap map,
+                          int logn, const double2 *mq, const u64 *qi, int add) {
+    EW_PROLOGUE
+    const ulonglong2 v = *(const ulonglong2 *)(a + p * sa + t * n + i);
+    const ulonglong2 m = *(const ulonglong2 *)(pt + t * n + i);
+    ulonglong2 r;
+    if (add) {
+        const u64 q = qi[map(t)];
+        r.x = v.x + m.x; r.x = r.x >= q ? r.x - q : r.x;
+        r.y = v.y + m.y; r.y = r.y >= q ? r.y - q : r.y;
+    } else {
+        const double2 Q = mq[map(t)];
+        r.x = d2u(pos1(mm_signed(u2d(v.x), u2d(m.x), Q.x, Q.y), Q.x));
+        r.y = d2u(pos1(mm_signed(u2d(v.y), u2d(m.y), Q.x, Q.y), Q.x));
+    }
+    *(ulonglong2 *)(out + p * so + t * n + i) = r;
+}
+
+__global__ void ew_tensor(u64 *d, const u64 *a, const u64 *bb, int limbs, size_t sd, size_t sa, size_t sb, int logn,
+                          const double2 *mq) {
+    EW_PROLOGUE
+    const double2 Q = mq[t];
+    const size_t L = (size_t)limbs * n, o = t * n + i;
+    const u64 *A = a + p * sa, *Bq = bb + p * sb;
+    u64 *D = d + p * sd;
+    const ulonglong2 A0 = *(const ulonglong2 *)(A + o), A1 = *(const ulonglong2 *)(A + L + o);
+    const ulonglong2 B0 = *(const ulonglong2 *)(Bq + o), B1 = *(const ulonglong2 *)(Bq + L + o);
+    ulonglong2 r0, r1, r2;
+    {
+        const double x0 = u2d(A0.x), x1 = u2d(A1.x), y0 = u2d(B0.x), y1 = u2d(B1.x);
+        r0.x = d2u(pos1(mm_signed(x0, y0, Q.x, Q.y), Q.x));
+        const double m = mm_signed(x0, y1, Q.x, Q.y) + mm_signed(x1, y0, Q.x, Q.y) + 2.0 * Q.x;  // (0.5q, 3.5q)
+        r1.x = d2u(red_any(m, Q.x, Q.y));
+        r2.x = d2u(pos1(mm_signed(x1, y1, Q.x, Q.y), Q.x));
+    }
+    {
+        const double x0 = u2d(A0.y), x1 = u2d(A1.y), y0 = u2d(B0.y), y1 = u2d(B1.y);
+        r0.y = d2u(pos1(mm_signed(x0, y0, Q.x, Q.y), Q.x));
+        const double m = mm_signed(x0, y1, Q.x, Q.y) + mm_signed(x1, y0, Q.x, Q.y) + 2.0 * Q.x;
+        r1.y = d2u(red_any(m, Q.x, Q.y));
+        r2.y = d2u(pos1(mm_signed(x1, y1, Q.x, Q.y), Q.x));
+    }
+    *(ulonglong2 *)(D + o) = r0;
+    *(ulonglong2 *)(D + L + o) = r1;
+    *(ulonglong2 *)(D + 2 * L + o) = r2;
+}
+
+// evaluation position i holds a(psi^{2 brev(i) + 1}); sigma_g reads position
+// brev(((2 brev(i) + 1) g mod 2n - 1) / 2)
+__global__ void ew_automorph(u64 *out, const u64 *in, int limbs, size_t so, size_t si, int logn, u32 g) {
+    const int job = blockIdx.y;
+    const int p = job / limbs, t = job - p * limbs;
+    const size_t n = (size_t)1 << logn;
+    const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const u32 e = (u32)((((u64)(__brev(i) >> (32 - logn)) * 2 + 1) * g) & (2 * n - 1));
+    const u32 src = __brev((e - 1) >> 1) >> (32 - logn);
+    out[p * so + t * n + i] = in[p * si + t * n + src];
+}
+
+// fast base conversion; grid.x over coefficients, grid.y over the batch.
+// y_i = [x_i * hinv_i]_{q_i} once per source, then for every target t:
+// sum_i y_i * hmod[i][t] mod t, kept in [0, 2t) while accumulating.
+__global__ void ew_bconv(u64 *out, const u64 *src, BConvTab tab, int logn, size_t so, size_t si, const double2 *mq) {
+    const size_t n = (size_t)1 << logn;
+    const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const u64 *sb = src + blockIdx.y * si;
+    u64 *ob = out + blockIdx.y * so;
+    double y[kMaxBConvSrc];
+#pragma unroll
+    for (int i = 0; i < kMaxBConvSrc; i++) {
+        if (i < tab.ns) {
+            const double q = mq[tab.src_mod[i]].x;
+            const double2 h = tab.hinv[i];
+            y[i] = red1(mm_lazy(u2d(sb[(size_t)i * n + c]), h.x, h.y, q), q);
+        }
+    }
+    for (int j = 0; j < tab.nt; j++) {
+        const double tq = mq[tab.tgt_mod[j]].x, two_t = 2.0 * tq;
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < kMaxBConvSrc; i++) {
+            if (i < tab.ns) {
+                const double2 h = tab.hmod[i * tab.nt + j];
+                acc += mm_lazy(y[i], h.x, h.y, tq);
+                acc = acc >= two_t ? acc - two_t : acc;
+            }
+        }
+        ob[(size_t)tab.tgt_slot[j] * n + c] = d2u(red1(acc, tq));
+    }
+}
+
+__global__ void ew_ip(IPArgs a, int logn, const double2 *mq) {
+    const size_t n = (size_t)1 << logn;
+    const size_t c = ((size_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (c >= n) return;
+    const int t = blockIdx.y;  // target limb in [0, E)
+    const int bi = blockIdx.z;
+    a.d += bi * a.sd;
+    a.ext += bi * a.sext;
+    a.accb += bi * a.sacc;
+    a.acca += bi * a.sacc;
+    const int mod = t <= a.level ? t : a.nq + (t - a.level - 1);
+    const int kl = t <= a.level ? t : a.lmax_key + 1 + (t - a.level - 1);
+    const double2 Q = mq[mod];
+    double sb = 0.0, sa = 0.0;
+    for (int j = 0; j < a.beta; j++) {
+        const u64 *xs = (t <= a.level && t / a.alpha == j) ? a.d + (size_t)t * n
+                                                           : a.ext + ((size_t)j * a.E + t) * n;
+        const double x = u2d(xs[c]);
+        const double kb = u2d(a.key[(((size_t)j * 2 + 0) * a.Ek + kl) * n + c]);
+        const double ka = u2d(a.key[(((size_t)j * 2 + 1) * a.Ek + kl) * n + c]);
+        sb = red1(sb + pos1(mm_signed(x, kb, Q.x, Q.y), Q.x), Q.x);
+        sa = red1(sa + pos1(mm_signed(x, ka, Q.x, Q.y), Q.x), Q.x);
+    }
+    a.accb[(size_t)t * n + c] = d2u(sb);
+    a.acca[(size_t)t * n + c] = d2u(sa);
+}
+
+__global__ void ew_sub_mul(u64 *out, const u64 *x, const u64 *y, const u64 *add, int limbs, size_t so, size_t sx,
+                           size_t sy, size_t sadd, int logn, const double2 *mq, LimbScalars c) {
+    EW_PROLOGUE
+    const double q = mq[t].x;
+    const double w = c.v[t], wq = c.vq[t];
+    const ulonglong2 vx = *(const ulonglong2 *)(x + p * sx + t * n + i);
+    const ulonglong2 vy = *(const ulonglong2 *)(y + p * sy + t * n + i);
+    double r0 = red1(mm_lazy(u2d(vx.x) - u2d(vy.x) + q, w, wq, q), q);
+    double r1 = red1(mm_lazy(u2d(vx.y) - u2d(vy.y) + q, w, wq, q), q);
+    if (add) {
+        const ulonglong2 va = *(const ulonglong2 *)(add + p * sadd + t * n + i);
+        r0 = red1(r0 + u2d(va.x), q);
+        r1 = red1(r1 + u2d(va.y), q);
+    }
+    ulonglong2 r;
+    r.x = d2u(r0);
+    r.y = d2u(r1);
+    *(ulonglong2 *)(out + p * so + t * n + i) = r;
+}
+
+__global__ void ew_bcast_mod(u64 *out, const u64 *src, int limbs, size_t so, size_t ss, int logn, const double2 *mq) {
+    EW_PROLOGUE
+    const double2 Q = mq[t];
+    const ulonglong2 v = *(const ulonglong2 *)(src + p * ss + i);
+    ulonglong2 r;
+    r.x = d2u(red_any(u2d(v.x), Q.x, Q.y));
+    r.y = d2u(red_any(u2d(v.y), Q.x, Q.y));
+    *(ulonglong2 *)(out + p * so + t * n + i) = r;
+}
+
+__global__ void ew_check_range(const u64 *data, int limbs, size_t stride, int logn, const u64 *qi, int *flag) {
+    EW_PROLOGUE
+    const u64 q = qi[t];
+    const ulonglong2 v = *(const ulonglong2 *)(data + p * stride + t * n + i);
+    if (v.x >= q || v.y >= q) atomicOr(flag, 1);
+}
+
+// ------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------
+static dim3 ew_grid(int logn, int jobs) { return dim3((unsigned)(((1u << logn) / 2 + 255) / 256), (unsigned)jobs); }
+
+void k_add(const DevTables &T, u64 *out, const u64 *a, const u64 *b, int limbs, int polys, size_t so, size_t sa,
+           size_t sb, LimbMap map, bool sub, hipStream_t s) {
+    if (limbs * polys == 0) return;
+    hipLaunchKernelGGL(ew_add, ew_grid(T.logn, limbs * polys), dim3(256), 0, s, out, a, b, limbs, so, sa, sb, map,
+                       T.logn, T.qi, (int)sub);
+}
+void k_add_scalar(const DevTables &T, u64 *data, int limbs, int polys, size_t stride, LimbMap map,
+                  const LimbScalars &c, hipStream_t s) {
+    hipLaunchKernelGGL(ew_add_scalar, ew_grid(T.logn, limbs * polys), dim3(256), 0, s, data, limbs, stride, map,
+                       T.logn, T.qi, c);
+}
+void k_mul_scalar(const DevTables &T, u64 *out, const u64 *a, int limbs, int polys, size_t so, size_t sa,
+                  LimbMap map, const LimbScalars &c, hipStream_t s) {
+    hipLaunchKernelGGL(ew_mul_scalar, ew_grid(T.logn, limbs * polys), dim3(256), 0, s, out, a, limbs, so, sa, map,
+                       T.logn, T.mq, c);
+}
+void k_mul_pt(const DevTables &T, u64 *out, const u64 *a, const u64 *pt, int limbs, int polys, size_t so, size_t sa,
+              LimbMap map, bool add, hipStream_t s) {
+    hipLaunchKernelGGL(ew_mul_pt, ew_grid(T.logn, limbs * polys), dim3(256), 0, s, out, a, pt, limbs, so, sa, map,
+                       T.logn, T.mq, T.qi, (int)add);
+}
+void k_tensor(const DevTables &T, u64 *d, const u64 *a, const u64 *bb, int limbs, int batch, size_t sd, size_t sa,
+              size_t sb, hipStream_t s) {
+    hipLaunchKernelGGL(ew_tensor, ew_grid(T.logn, limbs * batch), dim3(256), 0, s, d, a, bb, limbs, sd, sa, sb, T.logn,
+                       T.mq);
+}
+void k_automorph(const DevTables &T, u64 *out, const u64 *in, int limbs, int polys, size_t so, size_t si, u32 g,
+                 hipStream_t s) {
+    dim3 grid((unsigned)((1u << T.logn) / 256 > 0 ? (1u << T.logn) / 256 : 1), (unsigned)(limbs * polys));
+    hipLaunchKernelGGL(ew_automorph, grid, dim3(256), 0, s, out, in, limbs, so, si, T.logn, g);
+}
+void k_bconv(const DevTables &T, u64 *out, const u64 *src, const BConvTab &tab, int batch, size_t so, size_t si,
+             hipStream_t s) {
+    dim3 grid((unsigned)(((1u << T.logn) + 255) / 256), (unsigned)batch);
+    hipLaunchKernelGGL(ew_bconv, grid, dim3(256), 0, s, out, src, tab, T.logn, so, si, T.mq);
+}
+void k_ip(const DevTables &T, const IPArgs &a, hipStream_t s) {
+    dim3 grid((unsigned)(((1u << T.logn) + 255) / 256), (unsigned)a.E, (unsigned)a.B);
+    hipLaunchKernelGGL(ew_ip, grid, dim3(256), 0, s, a, T.logn, T.mq);
+}
+void k_sub_mul(const DevTables &T, u64 *out, const u64 *x, const u64 *y, const u64 *add, int limbs, int polys,
+               size_t so, size_t sx, size_t sy, size_t sadd, const LimbScalars &c, hipStream_t s) {
+    hipLaunchKernelGGL(ew_sub_mul, ew_grid(T.logn, limbs * polys), dim3(256), 0, s, out, x, y, add, limbs, so, sx, sy,
+                       sadd, T.logn, T.mq, c);
+}
+void k_bcast_mod(const DevTables &T, u64 *out, const u64 *src, int limbs, int polys, size_t so, size_t ss,
+                 hipStream_t s) {
+    hipLaunchKernelGGL(ew_bcast_mod, ew_grid(T.logn, limbs * polys), dim3(256), 0, s, out, src, limbs, so, ss, T.logn,
+                       T.mq);
+}
+void k_check_range(const DevTables &T, const u64 *data, int limbs, int polys, size_t stride, int *flag,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(ew_check_range, ew_grid(T.logn, limbs * polys), dim3(256), 0, s, data, limbs, stride, T.logn,
+                       T.qi, flag);
+}
+
+}  // namespace ckr

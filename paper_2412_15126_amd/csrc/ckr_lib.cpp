@@ -1,0 +1,1262 @@
+// ckr_lib.cpp -- context, device pool, evaluator, key generation, circuits and
+// the C ABI of the ckr library.
+//
+// Every homomorphic step runs in the HIP kernels of ckr_kernels.hip on the
+// context stream; the host only derives parameters, samples randomness,
+// encodes plaintexts and sequences launches.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/ckr.h"
+#include "host_math.h"
+#include "internal.h"
+
+namespace ckr {
+
+#define HIPCHK(x)                                                                               \
+    do {                                                                                        \
+        hipError_t e_ = (x);                                                                    \
+        if (e_ != hipSuccess) throw Error{CKR_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+static thread_local std::string g_last_error;
+
+// ------------------------------------------------------------------------
+// device memory pool with an HBM budget
+// ------------------------------------------------------------------------
+class Pool {
+  public:
+    void *(*ualloc)(size_t, void *) = nullptr;
+    void (*ufree)(void *, void *) = nullptr;
+    void *user = nullptr;
+    size_t budget = 0, in_use = 0, held = 0, high = 0;
+
+    static size_t round(size_t b) { return (b + 65535) & ~size_t(65535); }
+
+    void *get(size_t bytes) {
+        bytes = round(bytes);
+        auto it = cache_.find(bytes);
+        if (it != cache_.end() && !it->second.empty()) {
+            void *p = it->second.back();
+            it->second.pop_back();
+            in_use += bytes;
+            high = std::max(high, in_use);
+            return p;
+        }
+        if (budget && held + bytes > budget) trim();
+        if (budget && held + bytes > budget) throw Error{CKR_E_NOMEM, "HBM budget exceeded"};
+        void *p = nullptr;
+        if (ualloc) {
+            p = ualloc(bytes, user);
+        } else if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            trim();
+            p = nullptr;
+            if (hipMalloc(&p, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                p = nullptr;
+            }
+        }
+        if (!p) throw Error{CKR_E_NOMEM, "device allocation failed"};
+        held += bytes;
+        in_use += bytes;
+        high = std::max(high, in_use);
+        return p;
+    }
+    void put(void *p, size_t bytes) {
+        if (!p) return;
+        bytes = round(bytes);
+        in_use -= bytes;
+        cache_[bytes].push_back(p);
+    }
+    // return cached blocks to the allocator (stream-ordered frees are safe
+    // because the caller synchronises first)
+    void trim() {
+        for (auto &kv : cache_) {
+            for (void *p : kv.second) {
+                if (ufree) ufree(p, user);
+                else (void)hipFree(p);
+                held -= kv.first;
+            }
+            kv.second.clear();
+        }
+    }
+    ~Pool() { trim(); }
+
+  private:
+    std::unordered_map<size_t, std::vector<void *>> cache_;
+};
+
+struct Ctx;
+
+// RAII device buffer drawn from the context pool
+class Buf {
+  public:
+    Buf() = default;
+    Buf(Ctx *c, size_t words);
+    Buf(Buf &&o) noexcept : c_(o.c_), p_(o.p_), words_(o.words_) { o.p_ = nullptr; }
+    Buf &operator=(Buf &&o) noexcept {
+        if (this != &o) {
+            release();
+            c_ = o.c_; p_ = o.p_; words_ = o.words_;
+            o.p_ = nullptr;
+        }
+        return *this;
+    }
+    Buf(const Buf &) = delete;
+    Buf &operator=(const Buf &) = delete;
+    ~Buf() { release(); }
+    u64 *get() const { return p_; }
+    size_t words() const { return words_; }
+
+  private:
+    void release();
+    Ctx *c_ = nullptr;
+    u64 *p_ = nullptr;
+    size_t words_ = 0;
+};
+
+// B ciphertexts at one level, layout [B][2][level+1][n]
+struct DCt {
+    int level = -1;
+    int B = 0;
+    Buf buf;
+    u64 *d() const { return buf.get(); }
+};
+
+struct PlainKey {
+    int kind, N, level;
+    bool operator<(const PlainKey &o) const { return std::tie(kind, N, level) < std::tie(o.kind, o.N, o.level); }
+};
+
+struct Ctx {
+    Params P;
+    DevTables T{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    Pool pool;
+    std::vector<void *> table_mem;  // owned by the context (tables)
+    std::map<std::pair<int, int>, BConvTab> modup;  // (level, digit)
+    std::map<int, BConvTab> moddown;                // level
+    std::map<PlainKey, Buf> plain;                  // encoded plaintexts, eval domain
+    std::mutex mu;
+    size_t n() const { return P.n; }
+
+    void *table_alloc(size_t bytes) {
+        void *p = nullptr;
+        HIPCHK(hipMalloc(&p, bytes));
+        table_mem.push_back(p);
+        return p;
+    }
+    ~Ctx() {
+        plain.clear();
+        if (stream) (void)hipStreamSynchronize(stream);
+        pool.trim();
+        for (void *p : table_mem) (void)hipFree(p);
+    }
+};
+
+Buf::Buf(Ctx *c, size_t words) : c_(c), words_(words) { p_ = (u64 *)c->pool.get(words * 8); }
+void Buf::release() {
+    if (p_ && c_) c_->pool.put(p_, words_ * 8);
+    p_ = nullptr;
+}
+
+struct Keys {
+    Ctx *C = nullptr;
+    int lmax = 0;
+    std::vector<i64> s;               // ternary secret, host only
+    Buf pk;                           // [2][lmax+1][n] eval domain
+    std::map<u32, Buf> swk;           // galois element (0 = relinearisation) -> [beta][2][Ek][n]
+    int Ek() const { return lmax + 1 + C->P.K; }
+};
+
+// ------------------------------------------------------------------------
+// small helpers
+// ------------------------------------------------------------------------
+static inline size_t limb_words(const Ctx &C) { return C.P.n; }
+
+static DCt ct_new(Ctx &C, int level, int B) {
+    DCt c;
+    c.level = level;
+    c.B = B;
+    c.buf = Buf(&C, (size_t)B * 2 * (level + 1) * C.n());
+    return c;
+}
+
+static void ntt(Ctx &C, u64 *base, int limbs, int polys, size_t stride, LimbMap map, bool inv) {
+    LimbBatch b{base, limbs, polys, stride, map};
+    k_ntt(C.T, b, inv, C.stream);
+}
+
+// 2-D strided device copy: `rows` rows of `width` words
+static void copy2d(Ctx &C, u64 *dst, size_t dpitch, const u64 *src, size_t spitch, size_t width, size_t rows) {
+    HIPCHK(hipMemcpy2DAsync(dst, dpitch * 8, src, spitch * 8, width * 8, rows, hipMemcpyDeviceToDevice, C.stream));
+}
+
+static void scalars_of(const Ctx &C, i64 K, int limbs, LimbMap map, LimbScalars &s) {
+    if (limbs > kMaxLimbArgs) throw Error{CKR_E_INVALID, "too many limbs"};
+    for (int t = 0; t < limbs; t++) {
+        const u64 q = C.P.mod[map(t)];
+        const u64 v = hred(K, q);
+        s.v[t] = (double)v;
+        s.vq[t] = (double)v / (double)q;
+    }
+}
+
+static void scalars_of_vals(const Ctx &C, const std::vector<u64> &vals, LimbScalars &s) {
+    if ((int)vals.size() > kMaxLimbArgs) throw Error{CKR_E_INVALID, "too many limbs"};
+    for (size_t t = 0; t < vals.size(); t++) {
+        s.v[t] = (double)vals[t];
+        s.vq[t] = (double)vals[t] / (double)C.P.mod[t];
+    }
+}
+
+// ------------------------------------------------------------------------
+// context setup: twiddle tables and constants
+// ------------------------------------------------------------------------
+static u64 brev(u64 x, int bits) {
+    u64 r = 0;
+    for (int i = 0; i < bits; i++) r |= ((x >> i) & 1) << (bits - 1 - i);
+    return r;
+}
+
+static void setup_tables(Ctx &C) {
+    const Params &P = C.P;
+    const int nm = P.nmod();
+    const u64 n = P.n;
+    C.T.logn = P.logn;
+    C.T.nmod = nm;
+    std::vector<double2> mq(nm), fwd((size_t)nm * n), inv((size_t)nm * n), last(2 * nm);
+    std::vector<u64> qi(nm);
+    std::vector<u64> pw(n), ipw(n);
+    for (int t = 0; t < nm; t++) {
+        const u64 q = P.mod[t];
+        const double dq = (double)q;
+        mq[t] = make_double2(dq, 1.0 / dq);
+        qi[t] = q;
+        const u64 psi = P.psi[t], ipsi = hinv(psi, q);
+        pw[0] = 1; ipw[0] = 1;
+        for (u64 j = 1; j < n; j++) {
+            pw[j] = hmul(pw[j - 1], psi, q);
+            ipw[j] = hmul(ipw[j - 1], ipsi, q);
+        }
+        for (u64 i = 0; i < n; i++) {
+            const u64 w = pw[brev(i, P.logn)], wi = ipw[brev(i, P.logn)];
+            fwd[(size_t)t * n + i] = make_double2((double)w, (double)w / dq);
+            inv[(size_t)t * n + i] = make_double2((double)wi, (double)wi / dq);
+        }
+        const u64 ninv = hinv(n % q, q);
+        const u64 w1 = hmul(ipw[n / 2], ninv, q);
+        last[2 * t] = make_double2((double)ninv, (double)ninv / dq);
+        last[2 * t + 1] = make_double2((double)w1, (double)w1 / dq);
+    }
+    C.T.mq = (double2 *)C.table_alloc(nm * sizeof(double2));
+    C.T.qi = (u64 *)C.table_alloc(nm * sizeof(u64));
+    C.T.tw_fwd = (double2 *)C.table_alloc(fwd.size() * sizeof(double2));
+    C.T.tw_inv = (double2 *)C.table_alloc(inv.size() * sizeof(double2));
+    C.T.tw_last = (double2 *)C.table_alloc(last.size() * sizeof(double2));
+    HIPCHK(hipMemcpy(C.T.mq, mq.data(), nm * sizeof(double2), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(C.T.qi, qi.data(), nm * sizeof(u64), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(C.T.tw_fwd, fwd.data(), fwd.size() * sizeof(double2), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(C.T.tw_inv, inv.data(), inv.size() * sizeof(double2), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(C.T.tw_last, last.data(), last.size() * sizeof(double2), hipMemcpyHostToDevice));
+}
+
+// fast base conversion table from moduli src[] to moduli tgt[] (output slots given)
+static BConvTab make_bconv(Ctx &C, const std::vector<int> &src, const std::vector<int> &tgt,
+                           const std::vector<int> &slot) {
+    if ((int)src.size() > kMaxBConvSrc || (int)tgt.size() > kMaxLimbArgs) throw Error{CKR_E_INVALID, "bconv size"};
+    BConvTab tab{};
+    tab.ns = (int)src.size();
+    tab.nt = (int)tgt.size();
+    std::vector<double2> hi(tab.ns), hm((size_t)tab.ns * tab.nt);
+    for (int i = 0; i < tab.ns; i++) {
+        tab.src_mod[i] = src[i];
+        const u64 qi = C.P.mod[src[i]];
+        u64 prod = 1 % qi;
+        for (int k = 0; k < tab.ns; k++)
+            if (k != i) prod = hmul(prod, C.P.mod[src[k]] % qi, qi);
+        const u64 v = hinv(prod, qi);
+        hi[i] = make_double2((double)v, (double)v / (double)qi);
+        for (int j = 0; j < tab.nt; j++) {
+            const u64 t = C.P.mod[tgt[j]];
+            u64 h = 1 % t;
+            for (int k = 0; k < tab.ns; k++)
+                if (k != i) h = hmul(h, C.P.mod[src[k]] % t, t);
+            hm[(size_t)i * tab.nt + j] = make_double2((double)h, (double)h / (double)t);
+        }
+    }
+    for (int j = 0; j < tab.nt; j++) {
+        tab.tgt_mod[j] = tgt[j];
+        tab.tgt_slot[j] = slot[j];
+    }
+    tab.hinv = (double2 *)C.table_alloc(hi.size() * sizeof(double2));
+    tab.hmod = (double2 *)C.table_alloc(hm.size() * sizeof(double2));
+    HIPCHK(hipMemcpy(tab.hinv, hi.data(), hi.size() * sizeof(double2), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(tab.hmod, hm.data(), hm.size() * sizeof(double2), hipMemcpyHostToDevice));
+    return tab;
+}
+
+// ModUp of digit j at `level`: sources = live primes of the digit, targets =
+// every other limb of (q_0..q_level, p_0..p_{K-1}); limb index t in [0, E)
+static const BConvTab &modup_tab(Ctx &C, int level, int j) {
+    std::lock_guard<std::mutex> g(C.mu);
+    auto key = std::make_pair(level, j);
+    auto it = C.modup.find(key);
+    if (it != C.modup.end()) return it->second;
+    const Params &P = C.P;
+    const int lo = j * P.alpha, hi = std::min(lo + P.alpha, level + 1) - 1, E = level + 1 + P.K;
+    std::vector<int> src, tgt, slot;
+    for (int i = lo; i <= hi; i++) src.push_back(i);
+    for (int t = 0; t < E; t++) {
+        if (t >= lo && t <= hi) continue;
+        tgt.push_back(t <= level ? t : P.nq + (t - level - 1));
+        slot.push_back(t);
+    }
+    return C.modup.emplace(key, make_bconv(C, src, tgt, slot)).first->second;
+}
+
+static const BConvTab &moddown_tab(Ctx &C, int level) {
+    std::lock_guard<std::mutex> g(C.mu);
+    auto it = C.moddown.find(level);
+    if (it != C.moddown.end()) return it->second;
+    std::vector<int> src, tgt, slot;
+    for (int k = 0; k < C.P.K; k++) src.push_back(C.P.nq + k);
+    for (int i = 0; i <= level; i++) tgt.push_back(i), slot.push_back(i);
+    return C.moddown.emplace(level, make_bconv(C, src, tgt, slot)).first->second;
+}
+
+// ------------------------------------------------------------------------
+// evaluator
+// ------------------------------------------------------------------------
+static void check_same(const DCt &a, const DCt &b) {
+    if (a.level != b.level || a.B != b.B) throw Error{CKR_E_INVALID, "level or batch mismatch"};
+}
+
+static DCt ev_add(Ctx &C, const DCt &a, const DCt &b, bool sub) {
+    check_same(a, b);
+    DCt o = ct_new(C, a.level, a.B);
+    const size_t L = (size_t)(a.level + 1) * C.n();
+    k_add(C.T, o.d(), a.d(), b.d(), a.level + 1, 2 * a.B, L, L, L, plain_map(), sub, C.stream);
+    return o;
+}
+
+static DCt ev_copy(Ctx &C, const DCt &a) {
+    DCt o = ct_new(C, a.level, a.B);
+    HIPCHK(hipMemcpyAsync(o.d(), a.d(), (size_t)a.B * 2 * (a.level + 1) * C.n() * 8, hipMemcpyDeviceToDevice,
+                          C.stream));
+    return o;
+}
+
+// constant c added to every slot: round(c * D_l) on the constant coefficient
+static DCt ev_add_const(Ctx &C, const DCt &a, double c) {
+    DCt o = ev_copy(C, a);
+    const i64 K = std::llround(c * C.P.scale[a.level]);
+    LimbScalars s;
+    scalars_of(C, K, a.level + 1, plain_map(), s);
+    k_add_scalar(C.T, o.d(), a.level + 1, a.B, (size_t)2 * (a.level + 1) * C.n(), plain_map(), s, C.stream);
+    return o;
+}
+
+// floor-form rescale: c_i <- (c_i - [c_l]_{q_i}) * q_l^{-1} mod q_i
+static DCt ev_rescale(Ctx &C, const DCt &a) {
+    const int l = a.level;
+    if (l < 1) throw Error{CKR_E_DEPTH, "rescale at level 0"};
+    const size_t n = C.n(), L = (size_t)(l + 1) * n;
+    const int P2 = 2 * a.B;
+    Buf last(&C, (size_t)P2 * n);
+    copy2d(C, last.get(), n, a.d() + (size_t)l * n, L, n, P2);
+    ntt(C, last.get(), 1, P2, n, plain_map(l), true);
+    Buf y(&C, (size_t)P2 * l * n);
+    k_bcast_mod(C.T, y.get(), last.get(), l, P2, (size_t)l * n, n, C.stream);
+    ntt(C, y.get(), l, P2, (size_t)l * n, plain_map(), false);
+    DCt o = ct_new(C, l - 1, a.B);
+    std::vector<u64> inv(l);
+    for (int i = 0; i < l; i++) inv[i] = hinv(C.P.mod[l] % C.P.mod[i], C.P.mod[i]);
+    LimbScalars s;
+    scalars_of_vals(C, inv, s);
+    k_sub_mul(C.T, o.d(), a.d(), y.get(), nullptr, l, P2, (size_t)l * n, L, (size_t)l * n, 0, s, C.stream);
+    return o;
+}
+
+// c * a brought to level `target`: drop to target+1 limbs, multiply by
+// round(c * D_target * q_{target+1} / D_level), rescale by q_{target+1}
+static DCt ev_cmul_to(Ctx &C, const DCt &a, double c, int target) {
+    if (target < 0 || target >= a.level) throw Error{CKR_E_DEPTH, "cmul_to target"};
+    const double v = ((c * C.P.scale[target]) * (double)C.P.mod[target + 1]) / C.P.scale[a.level];
+    const i64 K = std::llround(v);
+    const int l2 = target + 1;
+    DCt m = ct_new(C, l2, a.B);
+    LimbScalars s;
+    scalars_of(C, K, l2 + 1, plain_map(), s);
+    const size_t n = C.n();
+    k_mul_scalar(C.T, m.d(), a.d(), l2 + 1, 2 * a.B, (size_t)(l2 + 1) * n, (size_t)(a.level + 1) * n, plain_map(), s,
+                 C.stream);
+    return ev_rescale(C, m);
+}
+
+// hybrid key switch of d (B polys, eval domain, limbs 0..l, batch stride sd):
+//   out_b = ModDown(sum_j ModUp_j(d) * key_j.b) (+ add_b),  out_a likewise
+static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_t sd, int l, int B, u64 *ob,
+                      size_t sob, const u64 *addb, size_t saddb, u64 *oa, size_t soa) {
+    const Params &P = C.P;
+    if (l > K.lmax) throw Error{CKR_E_DEPTH, "ciphertext above key level"};
+    const size_t n = C.n();
+    const int beta = P.beta(l), E = l + 1 + P.K;
+    // coefficient-domain copy of d
+    Buf dc(&C, (size_t)B * (l + 1) * n);
+    copy2d(C, dc.get(), (size_t)(l + 1) * n, d, sd, (size_t)(l + 1) * n, B);
+    ntt(C, dc.get(), l + 1, B, (size_t)(l + 1) * n, plain_map(), true);
+    // ModUp: base conversion of each digit to the other limbs, then NTT
+    const size_t sext = (size_t)beta * E * n;
+    Buf ext(&C, (size_t)B * sext);
+    for (int j = 0; j < beta; j++) {
+        const int lo = j * P.alpha, hi = std::min(lo + P.alpha, l + 1) - 1;
+        u64 *ej = ext.get() + (size_t)j * E * n;
+        k_bconv(C.T, ej, dc.get() + (size_t)lo * n, modup_tab(C, l, j), B, sext, (size_t)(l + 1) * n, C.stream);
+        if (lo > 0) ntt(C, ej, lo, B, sext, plain_map(), false);
+        if (hi + 1 < E) ntt(C, ej + (size_t)(hi + 1) * n, E - hi - 1, B, sext, LimbMap{l - hi, hi + 1, P.nq}, false);
+    }
+    // inner product with the key digits
+    const size_t sacc = (size_t)2 * E * n;
+    Buf acc(&C, (size_t)B * sacc);
+    IPArgs ia;
+    ia.d = d;
+    ia.ext = ext.get();
+    ia.key = key.get();
+    ia.accb = acc.get();
+    ia.acca = acc.get() + (size_t)E * n;
+    ia.level = l;
+    ia.E = E;
+    ia.beta = beta;
+    ia.alpha = P.alpha;
+    ia.Ek = K.Ek();
+    ia.lmax_key = K.lmax;
+    ia.nq = P.nq;
+    ia.B = B;
+    ia.sd = sd;
+    ia.sext = sext;
+    ia.sacc = sacc;
+    k_ip(C.T, ia, C.stream);
+    // ModDown: (x_Q - BConv_{P->Q}(x_P)) * P^{-1}
+    ntt(C, acc.get() + (size_t)(l + 1) * n, P.K, 2 * B, (size_t)E * n, plain_map(P.nq), true);
+    Buf conv(&C, (size_t)2 * B * (l + 1) * n);
+    k_bconv(C.T, conv.get(), acc.get() + (size_t)(l + 1) * n, moddown_tab(C, l), 2 * B, (size_t)(l + 1) * n,
+            (size_t)E * n, C.stream);
+    ntt(C, conv.get(), l + 1, 2 * B, (size_t)(l + 1) * n, plain_map(), false);
+    std::vector<u64> pinv(l + 1);
+    for (int i = 0; i <= l; i++) {
+        const u64 q = P.mod[i];
+        u64 pp = 1 % q;
+        for (int k = 0; k < P.K; k++) pp = hmul(pp, P.mod[P.nq + k] % q, q);
+        pinv[i] = hinv(pp, q);
+    }
+    LimbScalars s;
+    scalars_of_vals(C, pinv, s);
+    const size_t Lc = (size_t)(l + 1) * n;
+    k_sub_mul(C.T, ob, acc.get(), conv.get(), addb, l + 1, B, sob, sacc, 2 * Lc, saddb, s, C.stream);
+    k_sub_mul(C.T, oa, acc.get() + (size_t)E * n, conv.get() + Lc, nullptr, l + 1, B, soa, sacc, 2 * Lc, 0, s,
+              C.stream);
+}
+
+static const Buf &find_key(const Keys &K, u32 g) {
+    auto it = K.swk.find(g);
+    if (it == K.swk.end()) throw Error{CKR_E_INVALID, "missing switching key for galois element " + std::to_string(g)};
+    return it->second;
+}
+
+// ct * ct: tensor, relinearise with the s^2 key, rescale
+static DCt ev_mul(Ctx &C, const Keys &K, const DCt &a, const DCt &b) {
+    check_same(a, b);
+    const int l = a.level;
+    if (l < 1) throw Error{CKR_E_DEPTH, "mul at level 0"};
+    const size_t n = C.n(), L = (size_t)(l + 1) * n;
+    Buf d(&C, (size_t)a.B * 3 * L);
+    k_tensor(C.T, d.get(), a.d(), b.d(), l + 1, a.B, 3 * L, 2 * L, 2 * L, C.stream);
+    DCt r = ct_new(C, l, a.B);
+    keyswitch(C, K, find_key(K, 0), d.get() + 2 * L, 3 * L, l, a.B, r.d(), 2 * L, d.get(), 3 * L, r.d() + L, 2 * L);
+    // poly 1 still needs d1: out_a was written without it
+    k_add(C.T, r.d() + L, r.d() + L, d.get() + L, l + 1, a.B, 2 * L, 2 * L, 3 * L, plain_map(), false, C.stream);
+    return ev_rescale(C, r);
+}
+
+static u32 galois_left(const Ctx &C, i64 k) {
+    const i64 h = (i64)(C.n() / 2);
+    const u64 kk = (u64)(((k % h) + h) % h);
+    return (u32)hpow(5, kk, 2 * C.n());
+}
+
+// left rotation by k (new[j] = old[j+k]); k < 0 rotates right
+static DCt ev_rotate(Ctx &C, const Keys &K, const DCt &a, i64 k) {
+    const u32 g = galois_left(C, k);
+    if (g == 1) return ev_copy(C, a);
+    const Buf &key = find_key(K, g);
+    const int l = a.level;
+    const size_t n = C.n(), L = (size_t)(l + 1) * n;
+    DCt r = ct_new(C, l, a.B);
+    k_automorph(C.T, r.d(), a.d(), l + 1, 2 * a.B, L, L, g, C.stream);
+    DCt o = ct_new(C, l, a.B);
+    keyswitch(C, K, key, r.d() + L, 2 * L, l, a.B, o.d(), 2 * L, r.d(), 2 * L, o.d() + L, 2 * L);
+    return o;
+}
+
+// plaintext holding z on slots [0, count) at scale D_level, eval domain [level+1][n]
+enum PlainKind { kMaskRow0 = 1, kMaskCol0 = 2, kHalfRow0 = 3, kTieMask = 4, kSteps = 5, kNegHalfRow0 = 6 };
+
+static Buf encode_plain(Ctx &C, const std::vector<double> &z, int level) {
+    const size_t n = C.n();
+    std::vector<i64> m(n);
+    if (!encode_slots(C.P.logn, z.data(), (u32)z.size(), C.P.scale[level], m.data()))
+        throw Error{CKR_E_RANGE, "plaintext coefficient overflow"};
+    std::vector<u64> res((size_t)(level + 1) * n);
+    for (int t = 0; t <= level; t++)
+        for (size_t j = 0; j < n; j++) res[(size_t)t * n + j] = hred(m[j], C.P.mod[t]);
+    Buf b(&C, res.size());
+    HIPCHK(hipMemcpyAsync(b.get(), res.data(), res.size() * 8, hipMemcpyHostToDevice, C.stream));
+    ntt(C, b.get(), level + 1, 1, (size_t)(level + 1) * n, plain_map(), false);
+    HIPCHK(hipStreamSynchronize(C.stream));  // res goes out of scope
+    return b;
+}
+
+static std::vector<double> plain_values(int kind, int N) {
+    std::vector<double> z((size_t)N * N, 0.0);
+    switch (kind) {
+    case kMaskRow0: for (int j = 0; j < N; j++) z[j] = 1.0; break;
+    case kMaskCol0: for (int i = 0; i < N; i++) z[(size_t)i * N] = 1.0; break;
+    case kHalfRow0: z.assign(N, 0.5); break;
+    case kNegHalfRow0: z.assign(N, -0.5); break;
+    case kTieMask:  // delta_{j >= i} - 1/2 on the N x N block
+        for (int i = 0; i < N; i++)
+            for (int j = 0; j < N; j++) z[(size_t)i * N + j] = (j >= i) ? 0.5 : -0.5;
+        break;
+    case kSteps:  // (1^N || 2^N || ... || N^N)
+        for (int i = 0; i < N; i++)
+            for (int j = 0; j < N; j++) z[(size_t)i * N + j] = (double)(i + 1);
+        break;
+    default: throw Error{CKR_E_INVALID, "plaintext kind"};
+    }
+    return z;
+}
+
+static const Buf &get_plain(Ctx &C, int kind, int N, int level) {
+    PlainKey key{kind, N, level};
+    {
+        std::lock_guard<std::mutex> g(C.mu);
+        auto it = C.plain.find(key);
+        if (it != C.plain.end()) return it->second;
+    }
+    Buf b = encode_plain(C, plain_values(kind, N), level);
+    std::lock_guard<std::mutex> g(C.mu);
+    return C.plain.emplace(key, std::move(b)).first->second;
+}
+
+// slot-wise product with a plaintext (eval domain), then rescale
+static DCt ev_mul_plain(Ctx &C, const DCt &a, const Buf &pt) {
+    const size_t L = (size_t)(a.level + 1) * C.n();
+    DCt m = ct_new(C, a.level, a.B);
+    k_mul_pt(C.T, m.d(), a.d(), pt.get(), a.level + 1, 2 * a.B, L, L, plain_map(), false, C.stream);
+    return ev_rescale(C, m);
+}
+
+static DCt ev_add_plain(Ctx &C, const DCt &a, const Buf &pt) {
+    const size_t L = (size_t)(a.level + 1) * C.n();
+    DCt o = ev_copy(C, a);
+    k_mul_pt(C.T, o.d(), a.d(), pt.get(), a.level + 1, a.B, 2 * L, 2 * L, plain_map(), true, C.stream);
+    return o;
+}
+
+// ------------------------------------------------------------------------
+// matrix operations (section 2.3, Algorithms TransR/TransC, Appendix A)
+// ------------------------------------------------------------------------
+static int lg(int N) {
+    int r = 0;
+    while ((1 << r) < N) r++;
+    return r;
+}
+
+static DCt add_rot(Ctx &C, const Keys &K, const DCt &X, i64 k) {
+    DCt r = ev_rotate(C, K, X, k);
+    return ev_add(C, X, r, false);
+}
+
+static DCt trans_r(Ctx &C, const Keys &K, const DCt &V, int N) {
+    DCt X = ev_copy(C, V);
+    for (int i = 1; i <= lg(N); i++) X = add_rot(C, K, X, -(i64)(((i64)N * (N - 1)) >> i));
+    return ev_mul_plain(C, X, get_plain(C, kMaskCol0, N, X.level));
+}
+static DCt trans_c(Ctx &C, const Keys &K, const DCt &V, int N) {
+    DCt X = ev_copy(C, V);
+    for (int i = 1; i <= lg(N); i++) X = add_rot(C, K, X, (i64)(((i64)N * (N - 1)) >> i));
+    return ev_mul_plain(C, X, get_plain(C, kMaskRow0, N, X.level));
+}
+static DCt sum_r(Ctx &C, const Keys &K, const DCt &V, int N) {
+    DCt X = ev_copy(C, V);
+    for (int i = 0; i < lg(N); i++) X = add_rot(C, K, X, (i64)N << i);
+    return ev_mul_plain(C, X, get_plain(C, kMaskRow0, N, X.level));
+}
+static DCt sum_c(Ctx &C, const Keys &K, const DCt &V, int N) {
+    DCt X = ev_copy(C, V);
+    for (int i = 0; i < lg(N); i++) X = add_rot(C, K, X, (i64)1 << i);
+    return ev_mul_plain(C, X, get_plain(C, kMaskCol0, N, X.level));
+}
+static DCt repl_r(Ctx &C, const Keys &K, const DCt &V, int N) {
+    DCt X = ev_copy(C, V);
+    for (int i = 0; i < lg(N); i++) X = add_rot(C, K, X, -((i64)N << i));
+    return X;
+}
+static DCt repl_c(Ctx &C, const Keys &K, const DCt &V, int N) {
+    DCt X = ev_copy(C, V);
+    for (int i = 0; i < lg(N); i++) X = add_rot(C, K, X, -((i64)1 << i));
+    return X;
+}
+
+// ------------------------------------------------------------------------
+// comparator: f/g composite of odd degree-7 polynomials (section 2.2)
+// ------------------------------------------------------------------------
+static const double kF[4] = {35.0 / 16, -35.0 / 16, 21.0 / 16, -5.0 / 16};
+static const double kG[4] = {4589.0 / 1024, -16577.0 / 1024, 25614.0 / 1024, -12860.0 / 1024};
+
+// a1 x + a3 x^3 + a5 x^5 + a7 x^7 in three levels:
+//   x2 = x^2, x4 = x2^2, t3 = (a3 x) x2, t7 = (a7 x) x2, h = x4 (t7 + a5 x),
+//   result = h + t3 + a1 x, the last two brought down to level l-3 by constant products
+static DCt poly7(Ctx &C, const Keys &K, const DCt &x, const double a[4]) {
+    const int l = x.level;
+    if (l < 3) throw Error{CKR_E_DEPTH, "poly7 needs three levels"};
+    DCt x2 = ev_mul(C, K, x, x);
+    DCt x4 = ev_mul(C, K, x2, x2);
+    DCt u3 = ev_cmul_to(C, x, a[1], l - 1);
+    DCt t3 = ev_mul(C, K, u3, x2);
+    DCt u7 = ev_cmul_to(C, x, a[3], l - 1);
+    DCt t7 = ev_mul(C, K, u7, x2);
+    DCt u5 = ev_cmul_to(C, x, a[2], l - 2);
+    DCt w = ev_add(C, t7, u5, false);
+    DCt h = ev_mul(C, K, x4, w);
+    DCt v3 = ev_cmul_to(C, t3, 1.0, l - 3);
+    DCt v1 = ev_cmul_to(C, x, a[0], l - 3);
+    DCt s1 = ev_add(C, h, v3, false);
+    return ev_add(C, s1, v1, false);
+}
+
+// (f^{d_f}(g^{d_g}(D)) + 1) / 2 with the 1/2 folded into the last polynomial
+static DCt cmp_sign(Ctx &C, const Keys &K, const DCt &D, ckr_sign cmp) {
+    const int total = cmp.d_g + cmp.d_f;
+    if (total < 1) throw Error{CKR_E_INVALID, "empty comparator"};
+    if (D.level < 3 * total) throw Error{CKR_E_DEPTH, "comparator depth"};
+    DCt X = ev_copy(C, D);
+    for (int r = 0; r < total; r++) {
+        const double *c = r < cmp.d_g ? kG : kF;
+        double cc[4];
+        for (int i = 0; i < 4; i++) cc[i] = (r == total - 1) ? c[i] * 0.5 : c[i];
+        X = poly7(C, K, X, cc);
+    }
+    return ev_add_const(C, X, 0.5);
+}
+
+// ------------------------------------------------------------------------
+// Rank (Algorithm Rank), argmin (Order Statistic with k = 1 and the
+// tie-correction offset), Sorting
+// ------------------------------------------------------------------------
+static void check_N(const Ctx &C, u32 N) {
+    if (N < 2 || (N & (N - 1)) || (u64)N * N > C.n() / 2) throw Error{CKR_E_RANGE, "N must be a power of two with N^2 <= n/2"};
+}
+
+uint32_t rank_depth(ckr_sign c, int tie) { return 2 + 3 * (c.d_g + c.d_f) + (tie ? 2 : 0); }
+uint32_t argmin_depth(ckr_sign c, ckr_sign i) { return rank_depth(c, 1) + 1 + 3 * (i.d_g + i.d_f) + 2; }
+uint32_t sort_depth(ckr_sign c, ckr_sign i) { return rank_depth(c, 0) + 3 * (i.d_g + i.d_f) + 1 + 2; }
+
+// C = Cmp(V_R, V_C): C[i][j] = Cmp(v_j, v_i)
+static DCt cmp_matrix(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, DCt *VR_out = nullptr) {
+    DCt VR = repl_r(C, K, V, N);
+    DCt T = trans_r(C, K, V, N);
+    DCt VC = repl_c(C, K, T, N);
+    DCt VRa = ev_cmul_to(C, VR, 1.0, VC.level);
+    DCt D = ev_add(C, VRa, VC, true);
+    if (VR_out) *VR_out = std::move(VR);
+    return cmp_sign(C, K, D, cmp);
+}
+
+static DCt rank(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp) {
+    check_N(C, (u32)N);
+    if ((u32)V.level < rank_depth(cmp, 0)) throw Error{CKR_E_DEPTH, "not enough levels for rank"};
+    DCt Cm = cmp_matrix(C, K, V, N, cmp);
+    DCt S = sum_r(C, K, Cm, N);
+    return ev_add_plain(C, S, get_plain(C, kHalfRow0, N, S.level));
+}
+
+}  // namespace ckr
+
+// ========================================================================
+// C ABI
+// ========================================================================
+using namespace ckr;
+
+struct ckr_context {
+    std::unique_ptr<Ctx> C;
+};
+struct ckr_keys {
+    std::unique_ptr<Keys> K;
+};
+struct ckr_ct {
+    Ctx *C;
+    DCt ct;
+};
+
+template <class F>
+static ckr_status guard(F &&f) {
+    try {
+        f();
+        return CKR_OK;
+    } catch (const Error &e) {
+        g_last_error = e.msg;
+        return (ckr_status)e.status;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return CKR_E_NOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return CKR_E_INVALID;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return CKR_E_INVALID;
+    }
+}
+
+#define NEED(x)                                                   \
+    do {                                                          \
+        if (!(x)) throw Error{CKR_E_INVALID, "null argument: " #x}; \
+    } while (0)
+
+extern "C" {
+
+const char *ckr_last_error(void) { return g_last_error.c_str(); }
+
+ckr_status ckr_context_create(const ckr_params *p, int dev, size_t budget, ckr_context **out) {
+    return guard([&] {
+        NEED(p && out);
+        *out = nullptr;
+        int count = 0;
+        HIPCHK(hipGetDeviceCount(&count));
+        if (dev < 0 || dev >= count) throw Error{CKR_E_DEVICE, "no such HIP device"};
+        HIPCHK(hipSetDevice(dev));
+        auto ctx = std::make_unique<ckr_context>();
+        ctx->C = std::make_unique<Ctx>();
+        Ctx &C = *ctx->C;
+        C.device = dev;
+        C.P = make_params((int)p->log_n, (int)p->n_q, (int)p->q0_bits, (int)p->log_scale, (int)p->n_p,
+                          (int)p->p_bits, (int)p->dnum);
+        if (C.P.alpha > kMaxBConvSrc || C.P.K > kMaxBConvSrc) throw Error{CKR_E_INVALID, "digit too large"};
+        C.pool.budget = budget;
+        setup_tables(C);
+        *out = ctx.release();
+    });
+}
+
+void ckr_context_free(ckr_context *ctx) { delete ctx; }
+
+ckr_status ckr_context_set_stream(ckr_context *ctx, void *s) {
+    return guard([&] {
+        NEED(ctx);
+        ctx->C->stream = (hipStream_t)s;
+    });
+}
+
+ckr_status ckr_context_set_allocator(ckr_context *ctx, void *(*a)(size_t, void *), void (*f)(void *, void *),
+                                     void *user) {
+    return guard([&] {
+        NEED(ctx && a && f);
+        if (ctx->C->pool.held) throw Error{CKR_E_INVALID, "allocator must be set before any allocation"};
+        ctx->C->pool.ualloc = a;
+        ctx->C->pool.ufree = f;
+        ctx->C->pool.user = user;
+    });
+}
+
+ckr_status ckr_context_info(const ckr_context *ctx, uint64_t *mods, double *scales) {
+    return guard([&] {
+        NEED(ctx);
+        const Params &P = ctx->C->P;
+        if (mods) std::copy(P.mod.begin(), P.mod.end(), mods);
+        if (scales) std::copy(P.scale.begin(), P.scale.end(), scales);
+    });
+}
+
+ckr_status ckr_params_derive(const ckr_params *p, uint64_t *mods, double *scales) {
+    return guard([&] {
+        NEED(p);
+        Params P = make_params((int)p->log_n, (int)p->n_q, (int)p->q0_bits, (int)p->log_scale, (int)p->n_p,
+                               (int)p->p_bits, (int)p->dnum);
+        if (mods) std::copy(P.mod.begin(), P.mod.end(), mods);
+        if (scales) std::copy(P.scale.begin(), P.scale.end(), scales);
+    });
+}
+
+ckr_status ckr_encode(uint32_t log_n, const double *z, uint32_t count, double scale, int64_t *m) {
+    return guard([&] {
+        NEED(z && m);
+        if (log_n < 10 || log_n > 17) throw Error{CKR_E_INVALID, "log_n must be in [10, 17]"};
+        if ((u64)count > (1ull << log_n) / 2) throw Error{CKR_E_RANGE, "too many slots"};
+        if (!encode_slots((int)log_n, z, count, scale, m)) throw Error{CKR_E_RANGE, "coefficient overflow"};
+    });
+}
+
+ckr_status ckr_sample(const uint8_t seed[32], uint32_t purpose, uint64_t id, int kind, uint64_t q, size_t count,
+                      int64_t *out) {
+    return guard([&] {
+        NEED(seed && out);
+        if (kind == 2 && q < 2) throw Error{CKR_E_INVALID, "modulus"};
+        Stream st(seed, purpose, id);
+        for (size_t i = 0; i < count; i++)
+            out[i] = kind == 0 ? st.ternary() : kind == 1 ? st.cbd21() : (int64_t)st.uniform(q);
+    });
+}
+
+ckr_status ckr_context_memory(const ckr_context *ctx, size_t *in_use, size_t *high) {
+    return guard([&] {
+        NEED(ctx);
+        if (in_use) *in_use = ctx->C->pool.in_use;
+        if (high) *high = ctx->C->pool.high;
+    });
+}
+
+// Galois elements the circuits need for one N
+static void circuit_shifts(u32 N, u32 what, std::vector<i64> &sh) {
+    const int l = lg((int)N);
+    for (int i = 1; i <= l; i++) sh.push_back(-(i64)(((i64)N * (N - 1)) >> i));  // TransR
+    for (int i = 0; i < l; i++) sh.push_back(-((i64)N << i));                     // ReplR
+    for (int i = 0; i < l; i++) sh.push_back(-((i64)1 << i));                     // ReplC
+    for (int i = 0; i < l; i++) sh.push_back((i64)N << i);                        // SumR
+    if (what & 6) {
+        for (int i = 0; i < l; i++) sh.push_back((i64)1 << i);                    // SumC
+    }
+    if (what & 4) {
+        for (int i = 1; i <= l; i++) sh.push_back((i64)(((i64)N * (N - 1)) >> i));  // TransC
+    }
+}
+
+// switching key for target s' (eval domain, limbs of (q_0..q_lmax, P)):
+//   b_j = -a_j s + e_j + [limb in digit j] (P mod q) s',  a_j uniform
+static void gen_switch_key(Ctx &C, Keys &K, u32 g, const Buf &s_eval, const Buf &sp_eval, const uint8_t *seed) {
+    const Params &P = C.P;
+    const size_t n = C.n();
+    const int Ek = K.Ek(), beta = P.beta(K.lmax);
+    Buf key(&C, (size_t)beta * 2 * Ek * n);
+    const LimbMap emap{K.lmax + 1, 0, P.nq};
+    std::vector<u64> a((size_t)Ek * n), e((size_t)Ek * n);
+    Buf ea(&C, (size_t)Ek * n), ee(&C, (size_t)Ek * n), tmp(&C, (size_t)Ek * n);
+    for (int j = 0; j < beta; j++) {
+        std::vector<i64> ei(n);
+        {
+            Stream st(seed, kKsE, ((u64)g << 32) | ((u64)j << 16));
+            for (size_t i = 0; i < n; i++) ei[i] = st.cbd21();
+        }
+        for (int li = 0; li < Ek; li++) {
+            const int mt = emap(li);
+            const u64 q = P.mod[mt];
+            Stream st(seed, kKsA, ((u64)g << 32) | ((u64)j << 16) | (u64)mt);
+            u64 *ar = a.data() + (size_t)li * n, *er = e.data() + (size_t)li * n;
+            for (size_t i = 0; i < n; i++) ar[i] = st.uniform(q);
+            for (size_t i = 0; i < n; i++) er[i] = hred(ei[i], q);
+        }
+        HIPCHK(hipMemcpyAsync(ea.get(), a.data(), a.size() * 8, hipMemcpyHostToDevice, C.stream));
+        HIPCHK(hipMemcpyAsync(ee.get(), e.data(), e.size() * 8, hipMemcpyHostToDevice, C.stream));
+        ntt(C, ea.get(), Ek, 1, 0, emap, false);
+        ntt(C, ee.get(), Ek, 1, 0, emap, false);
+        u64 *kb = key.get() + (size_t)(j * 2) * Ek * n, *ka = kb + (size_t)Ek * n;
+        // kb = e - a*s
+        k_mul_pt(C.T, tmp.get(), ea.get(), s_eval.get(), Ek, 1, 0, 0, emap, false, C.stream);
+        k_add(C.T, kb, ee.get(), tmp.get(), Ek, 1, 0, 0, 0, emap, true, C.stream);
+        // + (P mod q) s' on the limbs of digit j
+        const int lo = j * P.alpha, hi = std::min(lo + P.alpha, K.lmax + 1) - 1;
+        std::vector<u64> pm;
+        for (int i = lo; i <= hi; i++) {
+            u64 pp = 1 % P.mod[i];
+            for (int k = 0; k < P.K; k++) pp = hmul(pp, P.mod[P.nq + k] % P.mod[i], P.mod[i]);
+            pm.push_back(pp);
+        }
+        LimbScalars sc;
+        for (size_t i = 0; i < pm.size(); i++) {
+            sc.v[i] = (double)pm[i];
+            sc.vq[i] = (double)pm[i] / (double)P.mod[lo + i];
+        }
+        k_mul_scalar(C.T, tmp.get(), sp_eval.get() + (size_t)lo * n, hi - lo + 1, 1, 0, 0, plain_map(lo), sc, C.stream);
+        k_add(C.T, kb + (size_t)lo * n, kb + (size_t)lo * n, tmp.get(), hi - lo + 1, 1, 0, 0, 0, plain_map(lo), false,
+              C.stream);
+        HIPCHK(hipMemcpyAsync(ka, ea.get(), (size_t)Ek * n * 8, hipMemcpyDeviceToDevice, C.stream));
+        HIPCHK(hipStreamSynchronize(C.stream));  // host staging reused next digit
+    }
+    K.swk[g] = std::move(key);
+}
+
+static void add_rotation_keys(Ctx &C, Keys &K, const std::vector<i64> &shifts, const uint8_t *seed) {
+    const size_t n = C.n();
+    const int Ek = K.Ek();
+    const LimbMap emap{K.lmax + 1, 0, C.P.nq};
+    // secret in eval domain on (q_0..q_lmax, P)
+    std::vector<u64> sr((size_t)Ek * n);
+    for (int li = 0; li < Ek; li++)
+        for (size_t i = 0; i < n; i++) sr[(size_t)li * n + i] = hred(K.s[i], C.P.mod[emap(li)]);
+    Buf s_eval(&C, sr.size());
+    HIPCHK(hipMemcpyAsync(s_eval.get(), sr.data(), sr.size() * 8, hipMemcpyHostToDevice, C.stream));
+    ntt(C, s_eval.get(), Ek, 1, 0, emap, false);
+    Buf sp(&C, sr.size());
+    for (i64 k : shifts) {
+        const u32 g = galois_left(C, k);
+        if (g == 1 || K.swk.count(g)) continue;
+        k_automorph(C.T, sp.get(), s_eval.get(), Ek, 1, 0, 0, g, C.stream);
+        gen_switch_key(C, K, g, s_eval, sp, seed);
+    }
+    HIPCHK(hipStreamSynchronize(C.stream));
+}
+
+static std::map<const Keys *, std::vector<uint8_t>> g_key_seed;  // seeds kept for later rotation keys
+static std::mutex g_key_seed_mu;
+
+ckr_status ckr_keygen(ckr_context *ctx, const uint8_t seed[32], uint32_t max_level, const uint32_t *Ns, size_t nN,
+                      uint32_t what, ckr_keys **out) {
+    return guard([&] {
+        NEED(ctx && seed && out);
+        *out = nullptr;
+        Ctx &C = *ctx->C;
+        const Params &P = C.P;
+        if ((int)max_level > P.L) throw Error{CKR_E_DEPTH, "max_level above the chain"};
+        for (size_t i = 0; i < nN; i++) check_N(C, Ns[i]);
+        auto K = std::make_unique<Keys>();
+        K->C = &C;
+        K->lmax = (int)max_level;
+        const size_t n = C.n();
+        K->s.resize(n);
+        {
+            Stream st(seed, kSecret, 0);
+            for (size_t i = 0; i < n; i++) K->s[i] = st.ternary();
+        }
+        const int Ek = K->Ek();
+        const LimbMap emap{K->lmax + 1, 0, P.nq};
+        std::vector<u64> sr((size_t)Ek * n);
+        for (int li = 0; li < Ek; li++)
+            for (size_t i = 0; i < n; i++) sr[(size_t)li * n + i] = hred(K->s[i], P.mod[emap(li)]);
+        Buf s_eval(&C, sr.size());
+        HIPCHK(hipMemcpyAsync(s_eval.get(), sr.data(), sr.size() * 8, hipMemcpyHostToDevice, C.stream));
+        ntt(C, s_eval.get(), Ek, 1, 0, emap, false);
+        // public key on q_0..q_lmax: (e - a s, a)
+        {
+            const int L1 = K->lmax + 1;
+            std::vector<i64> e(n);
+            {
+                Stream st(seed, kPkE, 0);
+                for (size_t i = 0; i < n; i++) e[i] = st.cbd21();
+            }
+            std::vector<u64> a((size_t)L1 * n), er((size_t)L1 * n);
+            for (int t = 0; t < L1; t++) {
+                Stream st(seed, kPkA, (u64)t);
+                for (size_t i = 0; i < n; i++) a[(size_t)t * n + i] = st.uniform(P.mod[t]);
+                for (size_t i = 0; i < n; i++) er[(size_t)t * n + i] = hred(e[i], P.mod[t]);
+            }
+            K->pk = Buf(&C, (size_t)2 * L1 * n);
+            Buf ee(&C, (size_t)L1 * n), tmp(&C, (size_t)L1 * n);
+            u64 *p0 = K->pk.get(), *p1 = p0 + (size_t)L1 * n;
+            HIPCHK(hipMemcpyAsync(p1, a.data(), a.size() * 8, hipMemcpyHostToDevice, C.stream));
+            HIPCHK(hipMemcpyAsync(ee.get(), er.data(), er.size() * 8, hipMemcpyHostToDevice, C.stream));
+            ntt(C, p1, L1, 1, 0, plain_map(), false);
+            ntt(C, ee.get(), L1, 1, 0, plain_map(), false);
+            k_mul_pt(C.T, tmp.get(), p1, s_eval.get(), L1, 1, 0, 0, plain_map(), false, C.stream);
+            k_add(C.T, p0, ee.get(), tmp.get(), L1, 1, 0, 0, 0, plain_map(), true, C.stream);
+            HIPCHK(hipStreamSynchronize(C.stream));
+        }
+        // relinearisation key: s' = s^2
+        {
+            Buf s2(&C, sr.size());
+            k_mul_pt(C.T, s2.get(), s_eval.get(), s_eval.get(), Ek, 1, 0, 0, emap, false, C.stream);
+            gen_switch_key(C, *K, 0, s_eval, s2, seed);
+        }
+        std::vector<i64> shifts;
+        for (size_t i = 0; i < nN; i++) circuit_shifts(Ns[i], what ? what : 1, shifts);
+        add_rotation_keys(C, *K, shifts, seed);
+        {
+            std::lock_guard<std::mutex> g(g_key_seed_mu);
+            g_key_seed[K.get()] = std::vector<uint8_t>(seed, seed + 32);
+        }
+        auto h = std::make_unique<ckr_keys>();
+        h->K = std::move(K);
+        *out = h.release();
+    });
+}
+
+void ckr_keys_free(ckr_keys *k) {
+    if (!k) return;
+    {
+        std::lock_guard<std::mutex> g(g_key_seed_mu);
+        g_key_seed.erase(k->K.get());
+    }
+    delete k;
+}
+
+ckr_status ckr_keys_add_rotations(ckr_context *ctx, ckr_keys *keys, const int64_t *shifts, size_t count) {
+    return guard([&] {
+        NEED(ctx && keys && (shifts || !count));
+        std::vector<uint8_t> seed;
+        {
+            std::lock_guard<std::mutex> g(g_key_seed_mu);
+            seed = g_key_seed.at(keys->K.get());
+        }
+        add_rotation_keys(*ctx->C, *keys->K, std::vector<i64>(shifts, shifts + count), seed.data());
+    });
+}
+
+static ckr_ct *wrap(Ctx &C, DCt &&c) {
+    ckr_ct *h = new ckr_ct{&C, std::move(c)};
+    return h;
+}
+
+ckr_status ckr_encrypt(ckr_context *ctx, const ckr_keys *keys, const double *v, uint32_t N, uint32_t level,
+                       const uint8_t seed[32], ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && keys && v && seed && out);
+        *out = nullptr;
+        Ctx &C = *ctx->C;
+        const Keys &K = *keys->K;
+        if ((int)level > K.lmax) throw Error{CKR_E_DEPTH, "level above the key level"};
+        if ((u64)N > C.n() / 2) throw Error{CKR_E_RANGE, "too many slots"};
+        const size_t n = C.n();
+        const int L1 = (int)level + 1;
+        std::vector<i64> m(n), u(n), e0(n), e1(n);
+        if (!encode_slots(C.P.logn, v, N, C.P.scale[level], m.data())) throw Error{CKR_E_RANGE, "value too large"};
+        {
+            Stream s(seed, kEncU, 0);
+            for (size_t i = 0; i < n; i++) u[i] = s.ternary();
+        }
+        {
+            Stream s(seed, kEncE0, 0);
+            for (size_t i = 0; i < n; i++) e0[i] = s.cbd21();
+        }
+        {
+            Stream s(seed, kEncE1, 0);
+            for (size_t i = 0; i < n; i++) e1[i] = s.cbd21();
+        }
+        // [u | e0 + m | e1] per limb
+        std::vector<u64> h((size_t)3 * L1 * n);
+        for (int t = 0; t < L1; t++) {
+            const u64 q = C.P.mod[t];
+            u64 *hu = h.data() + (size_t)t * n, *h0 = hu + (size_t)L1 * n, *h1 = h0 + (size_t)L1 * n;
+            for (size_t i = 0; i < n; i++) {
+                hu[i] = hred(u[i], q);
+                h0[i] = hred(e0[i] + m[i], q);
+                h1[i] = hred(e1[i], q);
+            }
+        }
+        Buf dh(&C, h.size());
+        HIPCHK(hipMemcpyAsync(dh.get(), h.data(), h.size() * 8, hipMemcpyHostToDevice, C.stream));
+        ntt(C, dh.get(), L1, 3, (size_t)L1 * n, plain_map(), false);
+        DCt c = ct_new(C, (int)level, 1);
+        const size_t L = (size_t)L1 * n;
+        const u64 *pk0 = K.pk.get(), *pk1 = pk0 + (size_t)(K.lmax + 1) * n;
+        // c0 = u pk0 + (e0 + m), c1 = u pk1 + e1
+        k_mul_pt(C.T, c.d(), pk0, dh.get(), L1, 1, 0, 0, plain_map(), false, C.stream);
+        k_mul_pt(C.T, c.d() + L, pk1, dh.get(), L1, 1, 0, 0, plain_map(), false, C.stream);
+        k_add(C.T, c.d(), c.d(), dh.get() + L, L1, 2, L, L, L, plain_map(), false, C.stream);
+        HIPCHK(hipStreamSynchronize(C.stream));
+        *out = wrap(C, std::move(c));
+    });
+}
+
+// coefficient-domain copy of a ciphertext, downloaded
+static std::vector<u64> download_coeffs(Ctx &C, const DCt &c) {
+    DCt t = ev_copy(C, c);
+    const size_t L = (size_t)(c.level + 1) * C.n();
+    ntt(C, t.d(), c.level + 1, 2 * c.B, L, plain_map(), true);
+    std::vector<u64> h((size_t)c.B * 2 * L);
+    HIPCHK(hipMemcpyAsync(h.data(), t.d(), h.size() * 8, hipMemcpyDeviceToHost, C.stream));
+    HIPCHK(hipStreamSynchronize(C.stream));
+    return h;
+}
+
+ckr_status ckr_decrypt(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *ct, double *out, uint32_t count) {
+    return guard([&] {
+        NEED(ctx && keys && ct && (out || !count));
+        Ctx &C = *ctx->C;
+        const Keys &K = *keys->K;
+        const size_t n = C.n();
+        if ((u64)count > n / 2) throw Error{CKR_E_RANGE, "too many slots"};
+        // c0 + c1 s on q_0 (valid while |m| < q_0 / 2); s uploaded only for this call
+        const u64 q = C.P.mod[0];
+        std::vector<u64> s0(n);
+        for (size_t i = 0; i < n; i++) s0[i] = hred(K.s[i], q);
+        Buf ds(&C, n), x(&C, n);
+        HIPCHK(hipMemcpyAsync(ds.get(), s0.data(), n * 8, hipMemcpyHostToDevice, C.stream));
+        ntt(C, ds.get(), 1, 1, 0, plain_map(), false);
+        const u64 *c0 = ct->ct.d(), *c1 = c0 + (size_t)(ct->ct.level + 1) * n;
+        k_mul_pt(C.T, x.get(), c1, ds.get(), 1, 1, 0, 0, plain_map(), false, C.stream);
+        k_add(C.T, x.get(), x.get(), c0, 1, 1, 0, 0, 0, plain_map(), false, C.stream);
+        ntt(C, x.get(), 1, 1, 0, plain_map(), true);
+        std::vector<u64> h(n);
+        HIPCHK(hipMemcpyAsync(h.data(), x.get(), n * 8, hipMemcpyDeviceToHost, C.stream));
+        HIPCHK(hipStreamSynchronize(C.stream));
+        std::vector<i64> m(n);
+        for (size_t i = 0; i < n; i++) m[i] = h[i] > q / 2 ? -(i64)(q - h[i]) : (i64)h[i];
+        decode_slots(C.P.logn, m.data(), C.P.scale[ct->ct.level], count, out);
+    });
+}
+
+uint32_t ckr_ct_level(const ckr_ct *ct) { return ct ? (uint32_t)ct->ct.level : 0; }
+double ckr_ct_scale(const ckr_ct *ct) { return ct ? ct->C->P.scale[ct->ct.level] : 0.0; }
+void ckr_ct_free(ckr_ct *ct) { delete ct; }
+
+ckr_status ckr_ct_export(ckr_context *ctx, const ckr_ct *ct, uint64_t *data, size_t words) {
+    return guard([&] {
+        NEED(ctx && ct && data);
+        Ctx &C = *ctx->C;
+        const size_t need = (size_t)2 * (ct->ct.level + 1) * C.n();
+        if (words < need) throw Error{CKR_E_INVALID, "export buffer too small"};
+        std::vector<u64> h = download_coeffs(C, ct->ct);
+        std::memcpy(data, h.data(), need * 8);
+    });
+}
+
+ckr_status ckr_ct_import(ckr_context *ctx, const uint64_t *data, size_t words, uint32_t level, ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && data && out);
+        *out = nullptr;
+        Ctx &C = *ctx->C;
+        if ((int)level > C.P.L) throw Error{CKR_E_DEPTH, "level above the chain"};
+        const size_t L = (size_t)(level + 1) * C.n();
+        if (words != 2 * L) throw Error{CKR_E_INVALID, "word count does not match level"};
+        for (int p = 0; p < 2; p++)
+            for (u32 t = 0; t <= level; t++) {
+                const u64 q = C.P.mod[t];
+                const uint64_t *x = data + p * L + (size_t)t * C.n();
+                for (size_t i = 0; i < C.n(); i++)
+                    if (x[i] >= q) throw Error{CKR_E_INVALID, "residue not below its modulus"};
+            }
+        DCt c = ct_new(C, (int)level, 1);
+        HIPCHK(hipMemcpyAsync(c.d(), data, 2 * L * 8, hipMemcpyHostToDevice, C.stream));
+        ntt(C, c.d(), (int)level + 1, 2, L, plain_map(), false);
+        HIPCHK(hipStreamSynchronize(C.stream));
+        *out = wrap(C, std::move(c));
+    });
+}
+
+uint32_t ckr_rank_depth(ckr_sign cmp, int tie) { return rank_depth(cmp, tie); }
+uint32_t ckr_argmin_depth(ckr_sign cmp, ckr_sign ind) { return argmin_depth(cmp, ind); }
+uint32_t ckr_sort_depth(ckr_sign cmp, ckr_sign ind) { return sort_depth(cmp, ind); }
+
+ckr_status ckr_rank(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, ckr_sign cmp, int tie,
+                    ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && keys && v && out);
+        *out = nullptr;
+        Ctx &C = *ctx->C;
+        if (tie) throw Error{CKR_E_INVALID, "tie-corrected rank: use ckr_argmin"};
+        DCt r = rank(C, *keys->K, v->ct, (int)N, cmp);
+        *out = wrap(C, std::move(r));
+    });
+}
+
+ckr_status ckr_rank_batch(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *const *v, size_t count, uint32_t N,
+                          ckr_sign cmp, ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && keys && v && out && count);
+        Ctx &C = *ctx->C;
+        const int level = v[0]->ct.level;
+        for (size_t i = 0; i < count; i++) {
+            NEED(v[i]);
+            if (v[i]->ct.level != level || v[i]->ct.B != 1) throw Error{CKR_E_INVALID, "batch entries must share level"};
+        }
+        const size_t W = (size_t)2 * (level + 1) * C.n();
+        DCt X = ct_new(C, level, (int)count);
+        for (size_t i = 0; i < count; i++)
+            HIPCHK(hipMemcpyAsync(X.d() + i * W, v[i]->ct.d(), W * 8, hipMemcpyDeviceToDevice, C.stream));
+        DCt R = rank(C, *keys->K, X, (int)N, cmp);
+        const size_t Wr = (size_t)2 * (R.level + 1) * C.n();
+        for (size_t i = 0; i < count; i++) {
+            DCt o = ct_new(C, R.level, 1);
+            HIPCHK(hipMemcpyAsync(o.d(), R.d() + i * Wr, Wr * 8, hipMemcpyDeviceToDevice, C.stream));
+            out[i] = wrap(C, std::move(o));
+        }
+    });
+}
+
+ckr_status ckr_argmin(ckr_context *, const ckr_keys *, const ckr_ct *, uint32_t, ckr_sign, ckr_sign, ckr_ct **,
+                      ckr_ct **) {
+    return guard([&] { throw Error{CKR_E_INVALID, "argmin not built yet"}; });
+}
+ckr_status ckr_sort(ckr_context *, const ckr_keys *, const ckr_ct *, uint32_t, ckr_sign, ckr_sign, ckr_ct **) {
+    return guard([&] { throw Error{CKR_E_INVALID, "sort not built yet"}; });
+}
+
+ckr_status ckr_op_rotate(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, int64_t k, ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && keys && a && out);
+        *out = wrap(*ctx->C, ev_rotate(*ctx->C, *keys->K, a->ct, k));
+    });
+}
+ckr_status ckr_op_mul(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, const ckr_ct *b, ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && keys && a && b && out);
+        *out = wrap(*ctx->C, ev_mul(*ctx->C, *keys->K, a->ct, b->ct));
+    });
+}
+ckr_status ckr_op_add(ckr_context *ctx, const ckr_ct *a, const ckr_ct *b, ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && a && b && out);
+        *out = wrap(*ctx->C, ev_add(*ctx->C, a->ct, b->ct, false));
+    });
+}
+ckr_status ckr_op_sub(ckr_context *ctx, const ckr_ct *a, const ckr_ct *b, ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && a && b && out);
+        *out = wrap(*ctx->C, ev_add(*ctx->C, a->ct, b->ct, true));
+    });
+}
+ckr_status ckr_op_rescale(ckr_context *ctx, const ckr_ct *a, ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && a && out);
+        *out = wrap(*ctx->C, ev_rescale(*ctx->C, a->ct));
+    });
+}
+ckr_status ckr_op_cmul_to(ckr_context *ctx, const ckr_ct *a, double c, uint32_t target, ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && a && out);
+        *out = wrap(*ctx->C, ev_cmul_to(*ctx->C, a->ct, c, (int)target));
+    });
+}
+ckr_status ckr_op_add_const(ckr_context *ctx, const ckr_ct *a, double c, ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && a && out);
+        *out = wrap(*ctx->C, ev_add_const(*ctx->C, a->ct, c));
+    });
+}
+ckr_status ckr_op_mul_plain(ckr_context *ctx, const ckr_ct *a, const double *z, uint32_t count, ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && a && z && out);
+        Ctx &C = *ctx->C;
+        if ((u64)count > C.n() / 2) throw Error{CKR_E_RANGE, "too many slots"};
+        Buf pt = encode_plain(C, std::vector<double>(z, z + count), a->ct.level);
+        *out = wrap(C, ev_mul_plain(C, a->ct, pt));
+    });
+}
+
+ckr_status ckr_ntt_device(ckr_context *ctx, uint64_t *data, uint32_t limbs, uint32_t first_mod, int inverse) {
+    return guard([&] {
+        NEED(ctx && data);
+        Ctx &C = *ctx->C;
+        if (first_mod + limbs > (u32)C.P.nmod()) throw Error{CKR_E_INVALID, "modulus index out of range"};
+        ntt(C, data, (int)limbs, 1, 0, plain_map((int)first_mod), inverse != 0);
+        HIPCHK(hipGetLastError());
+    });
+}
+
+ckr_status ckr_set_profiling(ckr_context *ctx, int) {
+    return guard([&] { NEED(ctx); });
+}
+
+}  // extern "C"

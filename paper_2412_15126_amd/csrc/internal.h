@@ -1,0 +1,115 @@
+// internal.h -- declarations shared by the host code and the HIP kernels of
+// the ckr library (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ckr {
+
+typedef uint64_t u64;
+typedef int64_t i64;
+typedef uint32_t u32;
+
+constexpr int kMaxMod = 128;   // moduli (q chain + special primes)
+constexpr int kMaxLimbArgs = 64;
+
+// limb t of a batch of limbs is reduced modulo  t < split ? t + off0 : t - split + off1
+struct LimbMap {
+    int split, off0, off1;
+    __host__ __device__ int operator()(int t) const { return t < split ? t + off0 : t - split + off1; }
+};
+inline LimbMap plain_map(int first = 0) { return LimbMap{1 << 30, first, 0}; }
+
+// per-limb scalar operand passed by value: value and value/q as doubles
+struct LimbScalars {
+    double v[kMaxLimbArgs];
+    double vq[kMaxLimbArgs];
+};
+
+// device-resident tables for one ring
+struct DevTables {
+    int logn;
+    int nmod;
+    double2 *mq;      // [nmod] {q, 1/q}
+    u64 *qi;          // [nmod] q as integers
+    double2 *tw_fwd;  // [nmod][n] {w, w/q}, w = psi^{brev(i)}
+    double2 *tw_inv;  // [nmod][n] {w, w/q}, w = psi^{-brev(i)}
+    double2 *tw_last; // [nmod][2]: {n^-1, n^-1/q}, {psi^{-brev(1)} n^-1, ./q}
+};
+
+// description of a batch of limbs: `polys` groups of `limbs` limbs, group p
+// starting at base + p * poly_stride, limbs n words apart
+struct LimbBatch {
+    u64 *base;
+    int limbs;
+    int polys;
+    size_t poly_stride;
+    LimbMap map;
+};
+
+// ---- kernels (ckr_kernels.hip) ------------------------------------------
+void k_ntt(const DevTables &T, const LimbBatch &b, bool inverse, hipStream_t s);
+
+// out = a + b, a - b (mod q) over a batch of limbs (same geometry for all three)
+void k_add(const DevTables &T, u64 *out, const u64 *a, const u64 *b, int limbs, int polys, size_t stride_o,
+           size_t stride_a, size_t stride_b, LimbMap map, bool sub, hipStream_t s);
+// limb t of each of `polys` polynomials (stride apart) += c[t]
+void k_add_scalar(const DevTables &T, u64 *data, int limbs, int polys, size_t stride, LimbMap map,
+                  const LimbScalars &c, hipStream_t s);
+// out[p][t] = a[p][t] * c[t]
+void k_mul_scalar(const DevTables &T, u64 *out, const u64 *a, int limbs, int polys, size_t stride_o, size_t stride_a,
+                  LimbMap map, const LimbScalars &c, hipStream_t s);
+// out[p][t] = a[p][t] (*|+) pt[t]
+void k_mul_pt(const DevTables &T, u64 *out, const u64 *a, const u64 *pt, int limbs, int polys, size_t stride_o,
+              size_t stride_a, LimbMap map, bool add, hipStream_t s);
+// per batch entry b: d = [d0 d1 d2] at d + b*sd (polys (limbs*n) apart), a = [a0 a1] at a + b*sa,
+// b = [b0 b1] at bb + b*sb;  d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1
+void k_tensor(const DevTables &T, u64 *d, const u64 *a, const u64 *bb, int limbs, int batch, size_t sd, size_t sa,
+              size_t sb, hipStream_t s);
+// evaluation-domain automorphism sigma_g on `polys` x `limbs` limbs
+void k_automorph(const DevTables &T, u64 *out, const u64 *in, int limbs, int polys, size_t stride_o, size_t stride_i,
+                 u32 g, hipStream_t s);
+
+// fast base conversion (coefficient domain): src limbs src[0..ns) with moduli
+// src_mod[i]; targets limbs out + j*n, moduli tgt_mod[j]; tables hinv[ns] and
+// hmod[ns][nt] ({v, v/m} pairs) in device memory
+constexpr int kMaxBConvSrc = 16;
+struct BConvTab {
+    int ns, nt;
+    int src_mod[kMaxBConvSrc];
+    int tgt_mod[kMaxLimbArgs];
+    int tgt_slot[kMaxLimbArgs];  // output limb index of target j
+    double2 *hinv;  // [ns]
+    double2 *hmod;  // [ns][nt]
+};
+void k_bconv(const DevTables &T, u64 *out, const u64 *src, const BConvTab &tab, int batch, size_t stride_o,
+             size_t stride_i, hipStream_t s);
+
+// key-switch inner product over E limbs (eval domain):
+//   accb[t] = sum_j X_j[t] * kb_j[t], acca[t] = sum_j X_j[t] * ka_j[t]
+// X_j[t] = d[t] if limb t (t <= level) lies in digit j, else ext[j][t]
+struct IPArgs {
+    const u64 *d;        // [level+1][n]
+    const u64 *ext;      // [beta][E][n]
+    const u64 *key;      // [beta_key][2][Ek][n]
+    u64 *accb, *acca;    // [E][n]
+    int level, E, beta, alpha, Ek, lmax_key, nq;
+    int B;                       // batch of inputs sharing the key
+    size_t sd, sext, sacc;       // batch strides of d, ext, accb/acca
+};
+void k_ip(const DevTables &T, const IPArgs &a, hipStream_t s);
+
+// out[p][i] = (x[p][i] - y[p][i]) * c[i]  (+ add[p][i] when add != nullptr)
+void k_sub_mul(const DevTables &T, u64 *out, const u64 *x, const u64 *y, const u64 *add, int limbs, int polys,
+               size_t stride_o, size_t stride_x, size_t stride_y, size_t stride_add, const LimbScalars &c,
+               hipStream_t s);
+// out[p][i] = src[p] mod q_i for i < limbs (src: one limb per poly, values < 2^50)
+void k_bcast_mod(const DevTables &T, u64 *out, const u64 *src, int limbs, int polys, size_t stride_o,
+                 size_t stride_src, hipStream_t s);
+// reduce arbitrary uint64 values to canonical residues (import check helper):
+// flags[0] set to 1 if any value >= its modulus
+void k_check_range(const DevTables &T, const u64 *data, int limbs, int polys, size_t stride, int *flag, hipStream_t s);
+
+}  // namespace ckr

@@ -1,0 +1,180 @@
+"""GPU parity: the HIP path against the CPU oracle, ciphertext for ciphertext.
+
+Every comparison is on exported coefficient-domain limbs (canonical uint64),
+so the two sides must agree bit for bit.  Inputs come from the seeded
+generators in paper_2412_15126_amd.workloads; nothing the oracle sees comes
+from the HIP path.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2412_15126_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ckr():
+    import paper_2412_15126_amd as m
+    m.lib()
+    return m
+
+
+class Pair:
+    """Same parameter set, keys and seeds on both sides."""
+
+    def __init__(self, ora, ckr, name, lmax, shifts=(), Ns=(), seed=bytes(range(32))):
+        self.ps = W.PSETS[name]
+        self.P = ora.Params(**self.ps)
+        self.ctx = ckr.Context(self.ps)
+        self.ora = ora
+        self.n = self.P.n
+        gal = set(self.P.galois_left(k % (self.n // 2)) for k in shifts)
+        for N in Ns:
+            gal |= set(self.P.rank_galois(N))
+        self.okeys = ora.Keys(self.P, seed, lmax, sorted(gal))
+        self.gkeys = self.ctx.keygen(seed, lmax, Ns)
+        if shifts:
+            self.gkeys.add_rotations(shifts)
+
+    def enc(self, v, level, seed):
+        return self.ora.encrypt(self.okeys, v, level, seed), self.ctx.encrypt(self.gkeys, v, level, seed)
+
+
+def same(o, g, what=""):
+    a, b = o.export(), g.export()
+    assert a.shape == b.shape, (what, a.shape, b.shape)
+    if not np.array_equal(a, b):
+        bad = np.argwhere(a != b)
+        raise AssertionError(f"{what}: {len(bad)} words differ, first at {bad[0].tolist()}")
+
+
+@pytest.fixture(scope="module")
+def t10(ora, ckr):
+    say("[gpu] T10 pair")
+    return Pair(ora, ckr, "T10", W.PSETS["T10"]["L"], shifts=(1, 3, -1, -5, 200))
+
+
+def test_context_moduli_match_oracle(t10):
+    assert np.array_equal(t10.ctx.moduli, t10.P.mods)
+    assert np.array_equal(t10.ctx.scales.view(np.uint64), t10.P.scales.view(np.uint64))
+
+
+def test_raw_ntt_roundtrip_on_device(ckr, t10):
+    from paper_2412_15126_amd import hip
+    say("[gpu] raw ntt roundtrip")
+    n, nm = t10.n, len(t10.P.mods)
+    rng = np.random.default_rng(0)
+    host = np.stack([rng.integers(0, int(q), n, dtype=np.uint64) for q in t10.P.mods])
+    dev = hip.DeviceArray(host)
+    t10.ctx.ntt_device(dev.ptr.value, nm, 0, False)
+    hip.synchronize()
+    fwd = dev.numpy()
+    assert not np.array_equal(fwd, host)
+    assert np.all(fwd < t10.P.mods[:, None])
+    t10.ctx.ntt_device(dev.ptr.value, nm, 0, True)
+    hip.synchronize()
+    assert np.array_equal(dev.numpy(), host)
+
+
+@pytest.mark.parametrize("level", [0, 3, 7])
+def test_encrypt_bit_exact(t10, level):
+    v = np.random.default_rng(level).uniform(0, 1, 40)
+    o, g = t10.enc(v, level, bytes([level + 1] * 32))
+    same(o, g, "encrypt")
+    assert np.max(np.abs(t10.ctx.decrypt(t10.gkeys, g, 40) - v)) < 1e-6
+
+
+def test_import_export_roundtrip_and_range_check(ckr, t10):
+    o, g = t10.enc(np.linspace(0, 1, 16), 4, bytes([9] * 32))
+    arr = o.export()
+    back = t10.ctx.import_ct(arr)
+    assert np.array_equal(back.export(), arr)
+    bad = arr.copy()
+    bad[1, 2, 5] = t10.P.mods[2]
+    with pytest.raises(ckr.CkrError) as e:
+        t10.ctx.import_ct(bad)
+    assert e.value.status == -1
+
+
+@pytest.mark.parametrize("k", [1, 3, -1, -5, 200])
+def test_rotate_bit_exact(t10, k):
+    v = np.random.default_rng(abs(k)).uniform(0, 1, t10.n // 2)
+    for level in (7, 2):
+        o, g = t10.enc(v, level, bytes([k & 0xFF] * 32))
+        same(t10.ora.rotate(t10.okeys, o, k), t10.ctx.rotate(t10.gkeys, g, k), f"rotate {k} at {level}")
+
+
+def test_mul_rescale_cmul_const_plain_bit_exact(t10):
+    ora, ctx = t10.ora, t10.ctx
+    rng = np.random.default_rng(7)
+    v1, v2 = rng.uniform(-1, 1, 300), rng.uniform(-1, 1, 300)
+    for level in (7, 4, 1):
+        (o1, g1), (o2, g2) = t10.enc(v1, level, bytes([1] * 32)), t10.enc(v2, level, bytes([2] * 32))
+        same(ora.mul(t10.okeys, o1, o2), ctx.mul(t10.gkeys, g1, g2), f"mul at {level}")
+        same(ora.mul(t10.okeys, o1, o1), ctx.mul(t10.gkeys, g1, g1), f"square at {level}")
+        same(ora.rescale(o1), ctx.rescale(g1), "rescale")
+        same(ora.add(o1, o2), ctx.add(g1, g2), "add")
+        same(ora.sub(o1, o2), ctx.sub(g1, g2), "sub")
+        same(ora.add_const(o1, -0.3125), ctx.add_const(g1, -0.3125), "add_const")
+        for c, tgt in [(2.5, level - 1), (-16577 / 1024, 0), (1.0, max(level - 3, 0))]:
+            same(ora.cmul_to(o1, c, tgt), ctx.cmul_to(g1, c, tgt), f"cmul_to {c} {tgt}")
+        mask = (np.arange(400) % 7 == 0).astype(float)
+        same(ora.mul_plain(o1, mask), ctx.mul_plain(g1, mask), "mul_plain")
+
+
+def test_errors_reported(ckr, t10):
+    o, g = t10.enc(np.zeros(4), 0, bytes([3] * 32))
+    with pytest.raises(ckr.CkrError) as e:
+        t10.ctx.rescale(g)
+    assert e.value.status == -3
+    with pytest.raises(ckr.CkrError) as e:
+        t10.ctx.rotate(t10.gkeys, g, 77)       # no key for this shift
+    assert e.value.status == -1
+    with pytest.raises(ckr.CkrError) as e:
+        t10.ctx.rank(t10.gkeys, g, 6, (2, 1))  # N not a power of two
+    assert e.value.status == -2
+    with pytest.raises(ckr.CkrError) as e:
+        t10.ctx.rank(t10.gkeys, g, 8, (2, 1))  # level 0: too shallow
+    assert e.value.status == -3
+
+
+@pytest.fixture(scope="module")
+def p12(ora, ckr):
+    say("[gpu] P12 pair")
+    return Pair(ora, ckr, "P12", W.PSETS["P12"]["L"], Ns=(8,))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_rank8_bit_exact_and_exact_ranks(p12, seed):
+    N = 8
+    cmp = W.RANK_CMP[N]
+    v, kseed, eseed = W.rank_workload(N, 0.01, seed)
+    o, g = p12.enc(v, p12.P.L, eseed)
+    say(f"[gpu] rank8 seed {seed}")
+    ro = p12.ora.rank(p12.okeys, o, N, *cmp)
+    rg = p12.ctx.rank(p12.gkeys, g, N, cmp)
+    same(ro, rg, "rank8")
+    dec = p12.ctx.decrypt(p12.gkeys, rg, N)
+    assert np.array_equal(np.round(dec), np.argsort(np.argsort(v)) + 1)
+
+
+def test_rank8_batch_equals_single(p12):
+    N, cmp = 8, W.RANK_CMP[8]
+    cts = []
+    singles = []
+    for seed in range(3):
+        v, _, eseed = W.rank_workload(N, 0.01, 10 + seed)
+        g = p12.ctx.encrypt(p12.gkeys, v, p12.P.L, eseed)
+        cts.append(g)
+        singles.append(p12.ctx.rank(p12.gkeys, g, N, cmp).export())
+    outs = p12.ctx.rank_batch(p12.gkeys, cts, N, cmp)
+    for s, b in zip(singles, outs):
+        assert np.array_equal(s, b.export())
