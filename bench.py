@@ -1,0 +1,162 @@
+#!/usr/bin/env python3
+"""Encrypted rank-128 throughput on one MI355X.
+
+One step = one batch of `--batch` encrypted rank queries of N = 128 values
+(uniform in [0,1), min gap 2^-10) at ring degree n = 2^16, run through the
+whole circuit: TransR/ReplR/ReplC re-encoding, all-pairs composite comparison
+(g applied 4 times, then f), SumR, +1/2.  Ciphertexts and keys are resident in
+HBM before the timed region starts.
+
+Prints one JSON line (see the design doc for the fields).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "encrypted rank-128 queries/s at n=2^16; NTT HBM GB/s vs peak; p99 latency"
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(pset, N, cmp, level, threads):
+    """The oracle, as it stands, timed on this host: one rank-128 query."""
+    from oracle import oracle as O
+    from paper_2412_15126_amd import workloads as W
+    O.set_threads(threads)
+    P = O.Params(**pset)
+    v, kseed, eseed = W.rank_workload(N, 2.0 ** -10, 0)
+    t = time.time()
+    K = O.Keys(P, kseed, level, P.rank_galois(N))
+    tk = time.time() - t
+    ct = O.encrypt(K, v, level, eseed)
+    t = time.time()
+    R = O.rank(K, ct, N, *cmp)
+    tr = time.time() - t
+    exact = np.array_equal(np.round(O.decrypt(K, R, N)), np.argsort(np.argsort(v)) + 1)
+    return {"value": 1.0 / tr, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"1 rank-{N} query at n=2^16 (keygen {tk:.1f}s excluded), {tr:.1f}s wall, ranks exact={exact}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the path shards by query, "
+              "see DESIGN.md; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+
+    import paper_2412_15126_amd as ckr
+    from paper_2412_15126_amd import hip
+    from paper_2412_15126_amd import workloads as W
+
+    pset = W.PSETS["P16"]
+    N, cmp, level = 128, W.RANK_CMP[128], 17
+    B = max(1, args.batch)
+    ctx = ckr.Context(pset)
+    stream = hip.Stream()
+    ctx.set_stream(stream.h.value)
+    _, kseed, _ = W.rank_workload(N, 2.0 ** -10, 0)
+    t = time.time()
+    keys = ctx.keygen(kseed, level, [N])
+    log(f"[bench] keygen {time.time() - t:.1f}s")
+    cts = []
+    vals = []
+    for q in range(B):
+        v, _, eseed = W.rank_workload(N, 2.0 ** -10, 1000 + q)
+        cts.append(ctx.encrypt(keys, v, level, eseed))
+        vals.append(v)
+
+    def step():
+        if B == 1:
+            return [ctx.rank(keys, cts[0], N, cmp)]
+        return ctx.rank_batch(keys, cts, N, cmp)
+
+    for _ in range(args.warmup):
+        out = step()
+    ctx.synchronize()
+    # correctness of what is timed: decrypted ranks are exact
+    exact = all(np.array_equal(np.round(ctx.decrypt(keys, o, N)), np.argsort(np.argsort(v)) + 1)
+                for o, v in zip(out, vals))
+    log(f"[bench] warmup done, ranks exact: {exact}")
+
+    # timed region: every launch bracketed by events on the context stream
+    ctx.set_profiling(True)
+    ctx.profile_reset()
+    ev = [hip.Event() for _ in range(args.steps + 1)]
+    ctx.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for s in range(args.steps):
+        out = step()
+        ev[s + 1].record(stream)
+    ctx.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.set_profiling(False)
+    step_ms = [ev[s].elapsed_ms(ev[s + 1]) for s in range(args.steps)]
+    total_ms = ev[0].elapsed_ms(ev[-1])
+    prof = ctx.profile()
+    log(f"[bench] timed {args.steps} steps: {total_ms:.1f} ms on device, {wall * 1e3:.1f} ms wall")
+
+    # dominant kernel: most device time
+    dom = max(prof, key=lambda k: prof[k][1])
+    launches, ms, nbytes = prof[dom]
+    achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    ntt_cats = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col"]
+    ntt_ms = sum(prof[c][1] for c in ntt_cats)
+    ntt_bytes = sum(prof[c][2] for c in ntt_cats)
+    breakdown = {k: {"launches": int(v[0]), "ms": round(v[1], 3),
+                     "GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else 0.0} for k, v in prof.items()}
+
+    secs = max(wall, total_ms * 1e-3)
+    value = B * args.steps / secs
+    lat = np.array(step_ms)
+    res = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(secs * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "rank N=128 at n=2^16 (q0 50-bit + 23 rescale primes near 2^40, 7 special 50-bit "
+                               "primes, dnum=3, scale 2^40), encrypted at level 17, comparator g^4 then f",
+                   "batch": B, "ranks_exact": bool(exact)},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
+                       "per": "step of " + str(B) + " queries"},
+        "ntt_GBps": round(ntt_bytes / (ntt_ms * 1e-3) / 1e9, 1) if ntt_ms > 0 else 0.0,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "launches": int(launches), "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2)},
+        "kernels": breakdown,
+    }
+    if rank == 0 and not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        log(f"[bench] cpu baseline with {threads} threads")
+        res["cpu_baseline"] = cpu_baseline(pset, N, cmp, level, threads)
+    if rank == 0:
+        print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -190,9 +190,20 @@ ckr_status ckr_op_mul_plain(ckr_context *ctx, const ckr_ct *a, const double *z, 
  * library's internal evaluation order; inverse(forward(x)) == x. */
 ckr_status ckr_ntt_device(ckr_context *ctx, uint64_t *data, uint32_t limbs, uint32_t first_mod, int inverse);
 
-/* Per-kernel timing of the last circuit call (rank/argmin/sort/batch), read
- * from HIP events recorded on the context stream when profiling is enabled. */
+/* Kernel timing.  While enabled, every kernel launch of the evaluator is
+ * bracketed by HIP events on the context stream and charged to a category
+ * (0 ntt_fwd_col, 1 ntt_fwd_row, 2 ntt_inv_row, 3 ntt_inv_col, 4 bconv, 5 ip,
+ * 6 tensor, 7 automorph, 8 combine, 9 elementwise, 10 copy) together with its
+ * algorithmic byte count (every operand read once, every result written
+ * once).  read returns the launches, summed milliseconds and summed bytes of
+ * one category since the last reset; it synchronises the stream. */
 ckr_status ckr_set_profiling(ckr_context *ctx, int enable);
+ckr_status ckr_profile_reset(ckr_context *ctx);
+ckr_status ckr_profile_read(ckr_context *ctx, int category, uint64_t *launches, double *total_ms, double *bytes);
+const char *ckr_profile_name(int category);
+
+/* Wait for all work issued on the context stream. */
+ckr_status ckr_synchronize(ckr_context *ctx);
 
 const char *ckr_last_error(void);
 

@@ -1080,3 +1080,108 @@ int ora_rank_galois(const ora_params *P, u32 N, u32 *out) {
 }
 
 u32 ora_galois_left(const ora_params *P, u64 k) { return gal_left(P, k); }
+
+/* ------------------------------------------------------------------ */
+/* Minimum with tie-correction (Order Statistic with k = 1, section    */
+/* 3.2, plus the Tie-Correction Offset of section 4)                    */
+/* ------------------------------------------------------------------ */
+/* multiply by the signed integer K without rescaling (scale unchanged) */
+ora_ct *ora_mul_int(const ora_ct *a, i64 K) { return mul_int(a, K); }
+
+/* levels: TransR mask, comparator, E, E*mask, SumR mask, scaling, indicator, O*V, SumC mask */
+int ora_argmin_depth(int cdg, int cdf, int idg, int idf) { return 1 + 3 * (cdg + cdf) + 3 + 1 + 3 * (idg + idf) + 2; }
+
+/* k = SumR(C + E (delta_{j>=i} - 1/2)), E = C (4 - 4C)  (= Rank + offset; the
+ * +1/2 of Rank and the -1/2 of the offset cancel).  O = Cmp(1.5, k) evaluated
+ * on (1.5 - k)/N: k >= 1 is integral, so k < 1.5 singles out rank 1.
+ * onehot = MaskR(O, 0); value = SumC(O * V) in slot 0. */
+int ora_argmin(const ora_keys *Kp, const ora_ct *V, u32 N, int cdg, int cdf, int idg, int idf, ora_ct **onehot,
+               ora_ct **value) {
+    int st = check_N(Kp->P, N);
+    if (st != ORA_OK) return st;
+    if (V->level < ora_argmin_depth(cdg, cdf, idg, idf)) return ORA_E_DEPTH;
+    ora_ct *C = ora_cmp_matrix(Kp, V, N, cdg, cdf, &st);
+    ora_ct *m4 = mul_int(C, -4);
+    ora_ct *w = ora_add_const(m4, 4.0);
+    ora_ct *E = ora_mul(Kp, C, w, &st);
+    double *tie = (double *)calloc((size_t)N * N, sizeof(double));
+    for (u32 i = 0; i < N; i++)
+        for (u32 j = 0; j < N; j++) tie[i * N + j] = j >= i ? 0.5 : -0.5;
+    ora_ct *Et = ora_mul_plain(E, tie, N * N, &st);
+    free(tie);
+    ora_ct *Ca = ora_cmul_to(C, 1.0, Et->level, &st);
+    ora_ct *X = ora_add(Ca, Et);
+    ora_ct *k = ora_sum_r(Kp, X, N, &st);
+    ora_ct *ks = ora_cmul_to(k, -1.0 / (double)N, k->level - 1, &st);
+    ora_ct *d = ora_add_const(ks, 1.5 / (double)N);
+    ora_ct *O = ora_cmp_sign(Kp, d, idg, idf, &st);
+    double *row = (double *)calloc(N, sizeof(double));
+    for (u32 j = 0; j < N; j++) row[j] = 1.0;
+    *onehot = ora_mul_plain(O, row, N, &st);
+    free(row);
+    ora_ct *Va = ora_cmul_to(V, 1.0, O->level, &st);
+    ora_ct *P = ora_mul(Kp, O, Va, &st);
+    *value = ora_sum_c(Kp, P, N, &st);
+    ora_ct_free(C); ora_ct_free(m4); ora_ct_free(w); ora_ct_free(E); ora_ct_free(Et); ora_ct_free(Ca);
+    ora_ct_free(X); ora_ct_free(k); ora_ct_free(ks); ora_ct_free(d); ora_ct_free(O); ora_ct_free(Va); ora_ct_free(P);
+    return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* Sorting (Algorithm Sorting, section 3.3), distinct inputs            */
+/* ------------------------------------------------------------------ */
+/* levels: Rank, scaling, indicator, indicator product, M*V_R, SumC mask, TransC mask */
+int ora_sort_depth(int cdg, int cdf, int idg, int idf) { return ora_rank_depth(cdg, cdf) + 5 + 3 * (idg + idf); }
+
+/* R = Rank(V); R_R = ReplR(R); X = R_R - (1^N || ... || N^N);
+ * M = Ind_0(X) = Cmp(X, -1/2) (1 - Cmp(X, 1/2)), the comparisons evaluated on
+ * (X + 1/2)/N and (X - 1/2)/N; S = TransC(SumC(M * ReplR(V))). */
+ora_ct *ora_sort(const ora_keys *Kp, const ora_ct *V, u32 N, int cdg, int cdf, int idg, int idf, int *status) {
+    int st = check_N(Kp->P, N);
+    if (st != ORA_OK) { *status = st; return NULL; }
+    if (V->level < ora_sort_depth(cdg, cdf, idg, idf)) { *status = ORA_E_DEPTH; return NULL; }
+    ora_ct *R = ora_rank(Kp, V, N, cdg, cdf, &st);
+    ora_ct *RR = ora_repl_r(Kp, R, N, &st);
+    double *steps = (double *)calloc((size_t)N * N, sizeof(double));
+    for (u32 i = 0; i < N; i++)
+        for (u32 j = 0; j < N; j++) steps[i * N + j] = -(double)(i + 1);
+    ora_ct *X = ora_add_plain(RR, steps, N * N, &st);
+    free(steps);
+    ora_ct *Xs = ora_cmul_to(X, 1.0 / (double)N, X->level - 1, &st);
+    ora_ct *d1 = ora_add_const(Xs, 0.5 / (double)N);
+    ora_ct *d2 = ora_add_const(Xs, -0.5 / (double)N);
+    ora_ct *c1 = ora_cmp_sign(Kp, d1, idg, idf, &st);
+    ora_ct *c2 = ora_cmp_sign(Kp, d2, idg, idf, &st);
+    ora_ct *n2 = mul_int(c2, -1);
+    ora_ct *o2 = ora_add_const(n2, 1.0);
+    ora_ct *M = ora_mul(Kp, c1, o2, &st);
+    ora_ct *VR = ora_repl_r(Kp, V, N, &st);
+    ora_ct *VRa = ora_cmul_to(VR, 1.0, M->level, &st);
+    ora_ct *P = ora_mul(Kp, M, VRa, &st);
+    ora_ct *SC = ora_sum_c(Kp, P, N, &st);
+    ora_ct *S = ora_trans_c(Kp, SC, N, &st);
+    ora_ct_free(R); ora_ct_free(RR); ora_ct_free(X); ora_ct_free(Xs); ora_ct_free(d1); ora_ct_free(d2);
+    ora_ct_free(c1); ora_ct_free(c2); ora_ct_free(n2); ora_ct_free(o2); ora_ct_free(M); ora_ct_free(VR);
+    ora_ct_free(VRa); ora_ct_free(P); ora_ct_free(SC);
+    *status = st;
+    return S;
+}
+
+/* Galois elements needed by the circuits: bit 0 rank, bit 1 argmin (adds
+ * SumC), bit 2 sort (adds SumC and TransC) */
+int ora_circuit_galois(const ora_params *P, u32 N, int what, u32 *out) {
+    int cnt = ora_rank_galois(P, N, out), lg = ilog2(N);
+    u64 h = P->n / 2;
+    u64 shifts[64]; int ns = 0;
+    if (what & 6)
+        for (int i = 0; i < lg; i++) shifts[ns++] = (u64)1 << i;                  /* SumC (left) */
+    if (what & 4)
+        for (int i = 1; i <= lg; i++) shifts[ns++] = ((u64)N * (N - 1)) >> i;     /* TransC (left) */
+    for (int s = 0; s < ns; s++) {
+        u32 g = gal_left(P, shifts[s] % h);
+        int dup = 0;
+        for (int k = 0; k < cnt; k++) if (out[k] == g) dup = 1;
+        if (!dup) out[cnt++] = g;
+    }
+    return cnt;
+}

@@ -28,7 +28,7 @@ def build(force=False):
         return _LIB
     tmp = _LIB + ".tmp"
     cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-           "-Wall", "-Wno-unused-function", "-o", tmp, _SRC, "-lquadmath", "-lm"]
+           "-Wall", "-Wno-unused-function", "-Wno-maybe-uninitialized", "-o", tmp, _SRC, "-lquadmath", "-lm"]
     subprocess.check_call(cmd)
     os.replace(tmp, _LIB)
     return _LIB
@@ -94,6 +94,13 @@ def lib():
             "ora_rank_depth": (C.c_int, [C.c_int, C.c_int]),
             "ora_rank_galois": (C.c_int, [vp, C.c_uint32, u32p]),
             "ora_galois_left": (C.c_uint32, [vp, C.c_uint64]),
+            "ora_mul_int": (vp, [vp, C.c_int64]),
+            "ora_argmin_depth": (C.c_int, [C.c_int] * 4),
+            "ora_argmin": (C.c_int, [vp, vp, C.c_uint32, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(vp),
+                                     C.POINTER(vp)]),
+            "ora_sort_depth": (C.c_int, [C.c_int] * 4),
+            "ora_sort": (vp, [vp, vp, C.c_uint32, C.c_int, C.c_int, C.c_int, C.c_int, intp]),
+            "ora_circuit_galois": (C.c_int, [vp, C.c_uint32, C.c_int, u32p]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -148,6 +155,11 @@ class Params:
 
     def galois_left(self, k):
         return int(lib().ora_galois_left(self.ptr, k))
+
+    def circuit_galois(self, N, what):
+        out = np.zeros(256, np.uint32)
+        c = lib().ora_circuit_galois(self.ptr, N, what, _p(out, u32p))
+        return [int(x) for x in out[:c]]
 
     def rank_galois(self, N):
         out = np.zeros(256, np.uint32)
@@ -379,3 +391,28 @@ def rescale_poly(params, x, level):
     out = np.zeros((level, params.n), np.uint64)
     lib().ora_rescale_poly(params.ptr, _p(x, u64p), level, _p(out, u64p))
     return out
+
+
+def mul_int(a, K):
+    return Ct(lib().ora_mul_int(a.ptr, int(K)), a.params)
+
+
+def argmin_depth(cmp, ind):
+    return lib().ora_argmin_depth(cmp[0], cmp[1], ind[0], ind[1])
+
+
+def argmin(keys, a, N, cmp, ind):
+    """(onehot, value) ciphertexts of the tie-corrected minimum."""
+    oh, val = C.c_void_p(), C.c_void_p()
+    st = lib().ora_argmin(keys.ptr, a.ptr, N, cmp[0], cmp[1], ind[0], ind[1], C.byref(oh), C.byref(val))
+    if st != 0:
+        raise OracleError(f"argmin: status {STATUS.get(st, st)}")
+    return Ct(oh.value, a.params), Ct(val.value, a.params)
+
+
+def sort_depth(cmp, ind):
+    return lib().ora_sort_depth(cmp[0], cmp[1], ind[0], ind[1])
+
+
+def sort(keys, a, N, cmp, ind):
+    return _ct(lib().ora_sort, a.params, keys.ptr, a.ptr, N, cmp[0], cmp[1], ind[0], ind[1], what="sort")

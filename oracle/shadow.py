@@ -166,3 +166,52 @@ def min_onehot(v, N, slots, cmp="ideal"):
     O = np.where(np.abs(k - 1.0) < 0.5, 1.0, 0.0) * embed(np.ones(N), slots)
     val = sum_c(O * x, N)
     return O, val, k
+
+
+# ---------------------------------------------------------------------------
+# The circuits exactly as the CKKS code evaluates them (composite comparator,
+# one-sided indicator for the minimum, merged tie-correction SumR).
+# ---------------------------------------------------------------------------
+def sign_composite(d, dg, df):
+    """f^{d_f}(g^{d_g}(d)): the composite's odd sign approximation."""
+    for _ in range(dg):
+        d = poly7(d, G_COEF)
+    for _ in range(df):
+        d = poly7(d, F_COEF)
+    return d
+
+
+def argmin_circuit(v, N, slots, cmp, ind):
+    """k = SumR(C + E*(delta - 1/2)) with E = C(4 - 4C) (= rank + tie offset);
+    O = Cmp(1.5, k) on (1.5 - k)/N; value = SumC(O * V).  Returns (O masked to
+    row 0, value slot vector, k)."""
+    x = embed(v, slots)
+    VR = repl_r(x, N)
+    VC = repl_c(trans_r(x, N), N)
+    Cm = (sign_composite(VR - VC, *cmp) + 1.0) / 2.0
+    E = Cm * (4.0 - 4.0 * Cm)
+    tie = np.zeros(slots)
+    for i in range(N):
+        tie[i * N:(i + 1) * N] = np.where(np.arange(N) >= i, 0.5, -0.5)
+    k = sum_r(Cm + E * tie, N)
+    d = (1.5 - k) / N
+    O = (sign_composite(d, *ind) + 1.0) / 2.0
+    val = sum_c(O * x, N)
+    return mask_row(O, N, 0), val, k
+
+
+def sort_circuit(v, N, slots, cmp, ind):
+    """Algorithm Sorting with Ind_0(x) = Cmp(x, -1/2) (1 - Cmp(x, 1/2)) on x/N."""
+    x = embed(v, slots)
+    R, _ = rank(v, N, slots, cmp)
+    RR = repl_r(R, N)
+    steps = np.zeros(slots)
+    for k in range(N):
+        steps[k * N:(k + 1) * N] = k + 1
+    X = RR - steps
+    c1 = (sign_composite((X + 0.5) / N, *ind) + 1.0) / 2.0
+    c2 = (sign_composite((X - 0.5) / N, *ind) + 1.0) / 2.0
+    M = c1 * (1.0 - c2)
+    VR = repl_r(x, N)
+    SC = sum_c(M * VR, N)
+    return trans_c(SC, N)

@@ -79,6 +79,10 @@ _SIGS = {
     "ckr_op_mul_plain": (C.c_int, [vp, vp, dblp, C.c_uint32, C.POINTER(vp)]),
     "ckr_ntt_device": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32, C.c_int]),
     "ckr_set_profiling": (C.c_int, [vp, C.c_int]),
+    "ckr_profile_reset": (C.c_int, [vp]),
+    "ckr_profile_read": (C.c_int, [vp, C.c_int, C.POINTER(C.c_uint64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "ckr_profile_name": (C.c_char_p, [C.c_int]),
+    "ckr_synchronize": (C.c_int, [vp]),
 }
 
 _lib = None
@@ -136,6 +140,14 @@ def sample(seed, purpose, oid, kind, q, count):
 
 def rank_depth(cmp):
     return int(lib().ckr_rank_depth(sign(cmp), 0))
+
+
+def argmin_depth(cmp, ind):
+    return int(lib().ckr_argmin_depth(sign(cmp), sign(ind)))
+
+
+def sort_depth(cmp, ind):
+    return int(lib().ckr_sort_depth(sign(cmp), sign(ind)))
 
 
 # ---- device objects -----------------------------------------------------------
@@ -198,6 +210,16 @@ class Context:
         _ok(lib().ckr_rank(self.h, keys.h, ct.h, N, sign(cmp), 0, C.byref(h)))
         return Ct(self, h)
 
+    def argmin(self, keys, ct, N, cmp, ind):
+        oh, val = vp(), vp()
+        _ok(lib().ckr_argmin(self.h, keys.h, ct.h, N, sign(cmp), sign(ind), C.byref(oh), C.byref(val)))
+        return Ct(self, oh), Ct(self, val)
+
+    def sort(self, keys, ct, N, cmp, ind):
+        h = vp()
+        _ok(lib().ckr_sort(self.h, keys.h, ct.h, N, sign(cmp), sign(ind), C.byref(h)))
+        return Ct(self, h)
+
     def rank_batch(self, keys, cts, N, cmp):
         arr = (vp * len(cts))(*[c.h for c in cts])
         out = (vp * len(cts))()
@@ -234,6 +256,24 @@ class Context:
     def mul_plain(self, a, z):
         z = np.ascontiguousarray(z, np.float64)
         return self._unary(lib().ckr_op_mul_plain, a.h, _p(z, dblp), len(z))
+
+    def synchronize(self):
+        _ok(lib().ckr_synchronize(self.h))
+
+    def set_profiling(self, on):
+        _ok(lib().ckr_set_profiling(self.h, int(on)))
+
+    def profile_reset(self):
+        _ok(lib().ckr_profile_reset(self.h))
+
+    def profile(self):
+        """{category: (launches, total_ms, bytes)} since the last reset."""
+        out = {}
+        for c in range(11):
+            a, b, d = C.c_uint64(), C.c_double(), C.c_double()
+            _ok(lib().ckr_profile_read(self.h, c, C.byref(a), C.byref(b), C.byref(d)))
+            out[lib().ckr_profile_name(c).decode()] = (a.value, b.value, d.value)
+        return out
 
     def ntt_device(self, ptr, limbs, first_mod, inverse):
         _ok(lib().ckr_ntt_device(self.h, vp(ptr), limbs, first_mod, int(inverse)))

@@ -208,29 +208,34 @@ static void launch_pass(const DevTables &T, const LimbBatch &b, hipStream_t s) {
 }
 
 template <int L1, int E1, int C1, int L2, int E2, int C2>
-static void ntt_two_pass(const DevTables &T, const LimbBatch &b, bool inverse, hipStream_t s) {
+static void ntt_one_pass(const DevTables &T, const LimbBatch &b, bool inverse, int pass, hipStream_t s) {
     if (!inverse) {
-        launch_pass<L1, E1, C1, true, false>(T, b, s);
-        launch_pass<L2, E2, C2, false, false>(T, b, s);
+        if (pass == 0) launch_pass<L1, E1, C1, true, false>(T, b, s);
+        else launch_pass<L2, E2, C2, false, false>(T, b, s);
     } else {
-        launch_pass<L2, E2, C2, false, true>(T, b, s);
-        launch_pass<L1, E1, C1, true, true>(T, b, s);
+        if (pass == 0) launch_pass<L2, E2, C2, false, true>(T, b, s);
+        else launch_pass<L1, E1, C1, true, true>(T, b, s);
+    }
+}
+
+void k_ntt_pass(const DevTables &T, const LimbBatch &b, bool inverse, int pass, hipStream_t s) {
+    if (b.limbs * b.polys == 0) return;
+    switch (T.logn) {
+    case 10: ntt_one_pass<5, 4, 16, 5, 4, 32>(T, b, inverse, pass, s); break;
+    case 11: ntt_one_pass<6, 3, 16, 5, 4, 32>(T, b, inverse, pass, s); break;
+    case 12: ntt_one_pass<6, 3, 16, 6, 3, 16>(T, b, inverse, pass, s); break;
+    case 13: ntt_one_pass<7, 4, 16, 6, 3, 16>(T, b, inverse, pass, s); break;
+    case 14: ntt_one_pass<7, 4, 16, 7, 4, 16>(T, b, inverse, pass, s); break;
+    case 15: ntt_one_pass<8, 4, 16, 7, 4, 16>(T, b, inverse, pass, s); break;
+    case 16: ntt_one_pass<8, 4, 16, 8, 4, 16>(T, b, inverse, pass, s); break;
+    case 17: ntt_one_pass<9, 4, 16, 8, 4, 16>(T, b, inverse, pass, s); break;
+    default: break;
     }
 }
 
 void k_ntt(const DevTables &T, const LimbBatch &b, bool inverse, hipStream_t s) {
-    if (b.limbs * b.polys == 0) return;
-    switch (T.logn) {
-    case 10: ntt_two_pass<5, 4, 16, 5, 4, 32>(T, b, inverse, s); break;
-    case 11: ntt_two_pass<6, 3, 16, 5, 4, 32>(T, b, inverse, s); break;
-    case 12: ntt_two_pass<6, 3, 16, 6, 3, 16>(T, b, inverse, s); break;
-    case 13: ntt_two_pass<7, 4, 16, 6, 3, 16>(T, b, inverse, s); break;
-    case 14: ntt_two_pass<7, 4, 16, 7, 4, 16>(T, b, inverse, s); break;
-    case 15: ntt_two_pass<8, 4, 16, 7, 4, 16>(T, b, inverse, s); break;
-    case 16: ntt_two_pass<8, 4, 16, 8, 4, 16>(T, b, inverse, s); break;
-    case 17: ntt_two_pass<9, 4, 16, 8, 4, 16>(T, b, inverse, s); break;
-    default: break;
-    }
+    k_ntt_pass(T, b, inverse, 0, s);
+    k_ntt_pass(T, b, inverse, 1, s);
 }
 
 // ------------------------------------------------------------------------

@@ -139,7 +139,28 @@ struct PlainKey {
     bool operator<(const PlainKey &o) const { return std::tie(kind, N, level) < std::tie(o.kind, o.N, o.level); }
 };
 
+enum ProfCat {
+    kNttFwdCol, kNttFwdRow, kNttInvRow, kNttInvCol, kBConv, kIP, kTensor, kAutomorph, kCombine, kElem, kCopy, kNCat
+};
+static const char *kCatName[kNCat] = {"ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "bconv", "ip",
+                                      "tensor", "automorph", "combine", "elementwise", "copy"};
+
+// opt-in per-category kernel timing with HIP events on the context stream
+struct Prof {
+    bool on = false;
+    struct Rec {
+        int cat;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> spare;
+    u64 launches[kNCat] = {};
+    double ms[kNCat] = {}, bytes[kNCat] = {};
+};
+
 struct Ctx {
+    Prof prof;
     Params P;
     DevTables T{};
     hipStream_t stream = nullptr;
@@ -161,6 +182,11 @@ struct Ctx {
     ~Ctx() {
         plain.clear();
         if (stream) (void)hipStreamSynchronize(stream);
+        for (auto &r : prof.pending) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (hipEvent_t e : prof.spare) (void)hipEventDestroy(e);
         pool.trim();
         for (void *p : table_mem) (void)hipFree(p);
     }
@@ -194,9 +220,52 @@ static DCt ct_new(Ctx &C, int level, int B) {
     return c;
 }
 
+static hipEvent_t prof_event(Ctx &C) {
+    if (!C.prof.spare.empty()) {
+        hipEvent_t e = C.prof.spare.back();
+        C.prof.spare.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+}
+
+// run `launch` on the context stream; when profiling, bracket it with events
+template <class F>
+static void timed(Ctx &C, int cat, double bytes, F &&launch) {
+    if (!C.prof.on) {
+        launch();
+        return;
+    }
+    hipEvent_t a = prof_event(C), b = prof_event(C);
+    HIPCHK(hipEventRecord(a, C.stream));
+    launch();
+    HIPCHK(hipEventRecord(b, C.stream));
+    C.prof.pending.push_back({cat, a, b, bytes});
+}
+
+static void prof_resolve(Ctx &C) {
+    if (C.prof.pending.empty()) return;
+    HIPCHK(hipStreamSynchronize(C.stream));
+    for (auto &r : C.prof.pending) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+        C.prof.launches[r.cat]++;
+        C.prof.ms[r.cat] += ms;
+        C.prof.bytes[r.cat] += r.bytes;
+        C.prof.spare.push_back(r.a);
+        C.prof.spare.push_back(r.b);
+    }
+    C.prof.pending.clear();
+}
+
+// each pass reads and writes every limb once: 16 n bytes per limb
 static void ntt(Ctx &C, u64 *base, int limbs, int polys, size_t stride, LimbMap map, bool inv) {
     LimbBatch b{base, limbs, polys, stride, map};
-    k_ntt(C.T, b, inv, C.stream);
+    const double bytes = 16.0 * C.P.n * limbs * polys;
+    timed(C, inv ? kNttInvRow : kNttFwdCol, bytes, [&] { k_ntt_pass(C.T, b, inv, 0, C.stream); });
+    timed(C, inv ? kNttInvCol : kNttFwdRow, bytes, [&] { k_ntt_pass(C.T, b, inv, 1, C.stream); });
 }
 
 // 2-D strided device copy: `rows` rows of `width` words
@@ -348,14 +417,17 @@ static DCt ev_add(Ctx &C, const DCt &a, const DCt &b, bool sub) {
     check_same(a, b);
     DCt o = ct_new(C, a.level, a.B);
     const size_t L = (size_t)(a.level + 1) * C.n();
-    k_add(C.T, o.d(), a.d(), b.d(), a.level + 1, 2 * a.B, L, L, L, plain_map(), sub, C.stream);
+    timed(C, kElem, 24.0 * L * a.B * 2, [&] {
+        k_add(C.T, o.d(), a.d(), b.d(), a.level + 1, 2 * a.B, L, L, L, plain_map(), sub, C.stream);
+    });
     return o;
 }
 
 static DCt ev_copy(Ctx &C, const DCt &a) {
     DCt o = ct_new(C, a.level, a.B);
-    HIPCHK(hipMemcpyAsync(o.d(), a.d(), (size_t)a.B * 2 * (a.level + 1) * C.n() * 8, hipMemcpyDeviceToDevice,
-                          C.stream));
+    const size_t words = (size_t)a.B * 2 * (a.level + 1) * C.n();
+    timed(C, kCopy, 16.0 * words,
+          [&] { HIPCHK(hipMemcpyAsync(o.d(), a.d(), words * 8, hipMemcpyDeviceToDevice, C.stream)); });
     return o;
 }
 
@@ -365,7 +437,44 @@ static DCt ev_add_const(Ctx &C, const DCt &a, double c) {
     const i64 K = std::llround(c * C.P.scale[a.level]);
     LimbScalars s;
     scalars_of(C, K, a.level + 1, plain_map(), s);
-    k_add_scalar(C.T, o.d(), a.level + 1, a.B, (size_t)2 * (a.level + 1) * C.n(), plain_map(), s, C.stream);
+    timed(C, kElem, 16.0 * (a.level + 1) * C.n() * a.B, [&] {
+        k_add_scalar(C.T, o.d(), a.level + 1, a.B, (size_t)2 * (a.level + 1) * C.n(), plain_map(), s, C.stream);
+    });
+    return o;
+}
+
+// multiply by a signed integer without rescaling (the scale is unchanged)
+static DCt ev_mul_int(Ctx &C, const DCt &a, i64 K) {
+    DCt o = ct_new(C, a.level, a.B);
+    LimbScalars s;
+    scalars_of(C, K, a.level + 1, plain_map(), s);
+    const size_t L = (size_t)(a.level + 1) * C.n();
+    timed(C, kElem, 16.0 * L * 2 * a.B, [&] {
+        k_mul_scalar(C.T, o.d(), a.d(), a.level + 1, 2 * a.B, L, L, plain_map(), s, C.stream);
+    });
+    return o;
+}
+
+// concatenate batches of equal level / split a batch back
+static DCt stack(Ctx &C, const std::vector<const DCt *> &parts) {
+    int B = 0;
+    for (auto *p : parts) {
+        if (p->level != parts[0]->level) throw Error{CKR_E_INVALID, "stack: level mismatch"};
+        B += p->B;
+    }
+    DCt o = ct_new(C, parts[0]->level, B);
+    const size_t W = (size_t)2 * (o.level + 1) * C.n();
+    size_t off = 0;
+    for (auto *p : parts) {
+        HIPCHK(hipMemcpyAsync(o.d() + off * W, p->d(), p->B * W * 8, hipMemcpyDeviceToDevice, C.stream));
+        off += p->B;
+    }
+    return o;
+}
+static DCt slice(Ctx &C, const DCt &a, int first, int count) {
+    DCt o = ct_new(C, a.level, count);
+    const size_t W = (size_t)2 * (a.level + 1) * C.n();
+    HIPCHK(hipMemcpyAsync(o.d(), a.d() + first * W, count * W * 8, hipMemcpyDeviceToDevice, C.stream));
     return o;
 }
 
@@ -376,17 +485,19 @@ static DCt ev_rescale(Ctx &C, const DCt &a) {
     const size_t n = C.n(), L = (size_t)(l + 1) * n;
     const int P2 = 2 * a.B;
     Buf last(&C, (size_t)P2 * n);
-    copy2d(C, last.get(), n, a.d() + (size_t)l * n, L, n, P2);
+    timed(C, kCopy, 16.0 * n * P2, [&] { copy2d(C, last.get(), n, a.d() + (size_t)l * n, L, n, P2); });
     ntt(C, last.get(), 1, P2, n, plain_map(l), true);
     Buf y(&C, (size_t)P2 * l * n);
-    k_bcast_mod(C.T, y.get(), last.get(), l, P2, (size_t)l * n, n, C.stream);
+    timed(C, kElem, 8.0 * n * P2 * (l + 1), [&] { k_bcast_mod(C.T, y.get(), last.get(), l, P2, (size_t)l * n, n, C.stream); });
     ntt(C, y.get(), l, P2, (size_t)l * n, plain_map(), false);
     DCt o = ct_new(C, l - 1, a.B);
     std::vector<u64> inv(l);
     for (int i = 0; i < l; i++) inv[i] = hinv(C.P.mod[l] % C.P.mod[i], C.P.mod[i]);
     LimbScalars s;
     scalars_of_vals(C, inv, s);
-    k_sub_mul(C.T, o.d(), a.d(), y.get(), nullptr, l, P2, (size_t)l * n, L, (size_t)l * n, 0, s, C.stream);
+    timed(C, kCombine, 24.0 * n * l * P2, [&] {
+        k_sub_mul(C.T, o.d(), a.d(), y.get(), nullptr, l, P2, (size_t)l * n, L, (size_t)l * n, 0, s, C.stream);
+    });
     return o;
 }
 
@@ -401,8 +512,10 @@ static DCt ev_cmul_to(Ctx &C, const DCt &a, double c, int target) {
     LimbScalars s;
     scalars_of(C, K, l2 + 1, plain_map(), s);
     const size_t n = C.n();
-    k_mul_scalar(C.T, m.d(), a.d(), l2 + 1, 2 * a.B, (size_t)(l2 + 1) * n, (size_t)(a.level + 1) * n, plain_map(), s,
-                 C.stream);
+    timed(C, kElem, 16.0 * n * (l2 + 1) * 2 * a.B, [&] {
+        k_mul_scalar(C.T, m.d(), a.d(), l2 + 1, 2 * a.B, (size_t)(l2 + 1) * n, (size_t)(a.level + 1) * n, plain_map(),
+                     s, C.stream);
+    });
     return ev_rescale(C, m);
 }
 
@@ -416,7 +529,7 @@ static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_
     const int beta = P.beta(l), E = l + 1 + P.K;
     // coefficient-domain copy of d
     Buf dc(&C, (size_t)B * (l + 1) * n);
-    copy2d(C, dc.get(), (size_t)(l + 1) * n, d, sd, (size_t)(l + 1) * n, B);
+    timed(C, kCopy, 16.0 * n * (l + 1) * B, [&] { copy2d(C, dc.get(), (size_t)(l + 1) * n, d, sd, (size_t)(l + 1) * n, B); });
     ntt(C, dc.get(), l + 1, B, (size_t)(l + 1) * n, plain_map(), true);
     // ModUp: base conversion of each digit to the other limbs, then NTT
     const size_t sext = (size_t)beta * E * n;
@@ -424,7 +537,10 @@ static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_
     for (int j = 0; j < beta; j++) {
         const int lo = j * P.alpha, hi = std::min(lo + P.alpha, l + 1) - 1;
         u64 *ej = ext.get() + (size_t)j * E * n;
-        k_bconv(C.T, ej, dc.get() + (size_t)lo * n, modup_tab(C, l, j), B, sext, (size_t)(l + 1) * n, C.stream);
+        const BConvTab &tab = modup_tab(C, l, j);
+        timed(C, kBConv, 8.0 * n * (tab.ns + tab.nt) * B, [&] {
+            k_bconv(C.T, ej, dc.get() + (size_t)lo * n, tab, B, sext, (size_t)(l + 1) * n, C.stream);
+        });
         if (lo > 0) ntt(C, ej, lo, B, sext, plain_map(), false);
         if (hi + 1 < E) ntt(C, ej + (size_t)(hi + 1) * n, E - hi - 1, B, sext, LimbMap{l - hi, hi + 1, P.nq}, false);
     }
@@ -448,12 +564,15 @@ static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_
     ia.sd = sd;
     ia.sext = sext;
     ia.sacc = sacc;
-    k_ip(C.T, ia, C.stream);
+    timed(C, kIP, 8.0 * n * E * (3.0 * beta + 2) * B, [&] { k_ip(C.T, ia, C.stream); });
     // ModDown: (x_Q - BConv_{P->Q}(x_P)) * P^{-1}
     ntt(C, acc.get() + (size_t)(l + 1) * n, P.K, 2 * B, (size_t)E * n, plain_map(P.nq), true);
     Buf conv(&C, (size_t)2 * B * (l + 1) * n);
-    k_bconv(C.T, conv.get(), acc.get() + (size_t)(l + 1) * n, moddown_tab(C, l), 2 * B, (size_t)(l + 1) * n,
-            (size_t)E * n, C.stream);
+    const BConvTab &mdt = moddown_tab(C, l);
+    timed(C, kBConv, 8.0 * n * (mdt.ns + mdt.nt) * 2 * B, [&] {
+        k_bconv(C.T, conv.get(), acc.get() + (size_t)(l + 1) * n, mdt, 2 * B, (size_t)(l + 1) * n, (size_t)E * n,
+                C.stream);
+    });
     ntt(C, conv.get(), l + 1, 2 * B, (size_t)(l + 1) * n, plain_map(), false);
     std::vector<u64> pinv(l + 1);
     for (int i = 0; i <= l; i++) {
@@ -465,9 +584,13 @@ static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_
     LimbScalars s;
     scalars_of_vals(C, pinv, s);
     const size_t Lc = (size_t)(l + 1) * n;
-    k_sub_mul(C.T, ob, acc.get(), conv.get(), addb, l + 1, B, sob, sacc, 2 * Lc, saddb, s, C.stream);
-    k_sub_mul(C.T, oa, acc.get() + (size_t)E * n, conv.get() + Lc, nullptr, l + 1, B, soa, sacc, 2 * Lc, 0, s,
-              C.stream);
+    timed(C, kCombine, 8.0 * Lc * B * (addb ? 4 : 3), [&] {
+        k_sub_mul(C.T, ob, acc.get(), conv.get(), addb, l + 1, B, sob, sacc, 2 * Lc, saddb, s, C.stream);
+    });
+    timed(C, kCombine, 24.0 * Lc * B, [&] {
+        k_sub_mul(C.T, oa, acc.get() + (size_t)E * n, conv.get() + Lc, nullptr, l + 1, B, soa, sacc, 2 * Lc, 0, s,
+                  C.stream);
+    });
 }
 
 static const Buf &find_key(const Keys &K, u32 g) {
@@ -483,11 +606,13 @@ static DCt ev_mul(Ctx &C, const Keys &K, const DCt &a, const DCt &b) {
     if (l < 1) throw Error{CKR_E_DEPTH, "mul at level 0"};
     const size_t n = C.n(), L = (size_t)(l + 1) * n;
     Buf d(&C, (size_t)a.B * 3 * L);
-    k_tensor(C.T, d.get(), a.d(), b.d(), l + 1, a.B, 3 * L, 2 * L, 2 * L, C.stream);
+    timed(C, kTensor, 56.0 * L * a.B, [&] { k_tensor(C.T, d.get(), a.d(), b.d(), l + 1, a.B, 3 * L, 2 * L, 2 * L, C.stream); });
     DCt r = ct_new(C, l, a.B);
     keyswitch(C, K, find_key(K, 0), d.get() + 2 * L, 3 * L, l, a.B, r.d(), 2 * L, d.get(), 3 * L, r.d() + L, 2 * L);
     // poly 1 still needs d1: out_a was written without it
-    k_add(C.T, r.d() + L, r.d() + L, d.get() + L, l + 1, a.B, 2 * L, 2 * L, 3 * L, plain_map(), false, C.stream);
+    timed(C, kElem, 24.0 * L * a.B, [&] {
+        k_add(C.T, r.d() + L, r.d() + L, d.get() + L, l + 1, a.B, 2 * L, 2 * L, 3 * L, plain_map(), false, C.stream);
+    });
     return ev_rescale(C, r);
 }
 
@@ -505,7 +630,7 @@ static DCt ev_rotate(Ctx &C, const Keys &K, const DCt &a, i64 k) {
     const int l = a.level;
     const size_t n = C.n(), L = (size_t)(l + 1) * n;
     DCt r = ct_new(C, l, a.B);
-    k_automorph(C.T, r.d(), a.d(), l + 1, 2 * a.B, L, L, g, C.stream);
+    timed(C, kAutomorph, 32.0 * L * a.B, [&] { k_automorph(C.T, r.d(), a.d(), l + 1, 2 * a.B, L, L, g, C.stream); });
     DCt o = ct_new(C, l, a.B);
     keyswitch(C, K, key, r.d() + L, 2 * L, l, a.B, o.d(), 2 * L, r.d(), 2 * L, o.d() + L, 2 * L);
     return o;
@@ -540,9 +665,9 @@ static std::vector<double> plain_values(int kind, int N) {
         for (int i = 0; i < N; i++)
             for (int j = 0; j < N; j++) z[(size_t)i * N + j] = (j >= i) ? 0.5 : -0.5;
         break;
-    case kSteps:  // (1^N || 2^N || ... || N^N)
+    case kSteps:  // -(1^N || 2^N || ... || N^N)
         for (int i = 0; i < N; i++)
-            for (int j = 0; j < N; j++) z[(size_t)i * N + j] = (double)(i + 1);
+            for (int j = 0; j < N; j++) z[(size_t)i * N + j] = -(double)(i + 1);
         break;
     default: throw Error{CKR_E_INVALID, "plaintext kind"};
     }
@@ -565,14 +690,18 @@ static const Buf &get_plain(Ctx &C, int kind, int N, int level) {
 static DCt ev_mul_plain(Ctx &C, const DCt &a, const Buf &pt) {
     const size_t L = (size_t)(a.level + 1) * C.n();
     DCt m = ct_new(C, a.level, a.B);
-    k_mul_pt(C.T, m.d(), a.d(), pt.get(), a.level + 1, 2 * a.B, L, L, plain_map(), false, C.stream);
+    timed(C, kElem, 8.0 * L * (4 * a.B + 1), [&] {
+        k_mul_pt(C.T, m.d(), a.d(), pt.get(), a.level + 1, 2 * a.B, L, L, plain_map(), false, C.stream);
+    });
     return ev_rescale(C, m);
 }
 
 static DCt ev_add_plain(Ctx &C, const DCt &a, const Buf &pt) {
     const size_t L = (size_t)(a.level + 1) * C.n();
     DCt o = ev_copy(C, a);
-    k_mul_pt(C.T, o.d(), a.d(), pt.get(), a.level + 1, a.B, 2 * L, 2 * L, plain_map(), true, C.stream);
+    timed(C, kElem, 8.0 * L * (2 * a.B + 1), [&] {
+        k_mul_pt(C.T, o.d(), a.d(), pt.get(), a.level + 1, a.B, 2 * L, 2 * L, plain_map(), true, C.stream);
+    });
     return o;
 }
 
@@ -671,9 +800,12 @@ static void check_N(const Ctx &C, u32 N) {
     if (N < 2 || (N & (N - 1)) || (u64)N * N > C.n() / 2) throw Error{CKR_E_RANGE, "N must be a power of two with N^2 <= n/2"};
 }
 
+// levels: TransR mask, comparator, SumR mask (+ E and E * tie mask with tie-correction)
 uint32_t rank_depth(ckr_sign c, int tie) { return 2 + 3 * (c.d_g + c.d_f) + (tie ? 2 : 0); }
+// tie-corrected rank, scaling, indicator, O * V, SumC mask
 uint32_t argmin_depth(ckr_sign c, ckr_sign i) { return rank_depth(c, 1) + 1 + 3 * (i.d_g + i.d_f) + 2; }
-uint32_t sort_depth(ckr_sign c, ckr_sign i) { return rank_depth(c, 0) + 3 * (i.d_g + i.d_f) + 1 + 2; }
+// rank, scaling, indicator, indicator product, M * V_R, SumC mask, TransC mask
+uint32_t sort_depth(ckr_sign c, ckr_sign i) { return rank_depth(c, 0) + 5 + 3 * (i.d_g + i.d_f); }
 
 // C = Cmp(V_R, V_C): C[i][j] = Cmp(v_j, v_i)
 static DCt cmp_matrix(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, DCt *VR_out = nullptr) {
@@ -686,12 +818,54 @@ static DCt cmp_matrix(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, 
     return cmp_sign(C, K, D, cmp);
 }
 
-static DCt rank(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp) {
+static DCt rank(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, DCt *VR_out = nullptr) {
     check_N(C, (u32)N);
     if ((u32)V.level < rank_depth(cmp, 0)) throw Error{CKR_E_DEPTH, "not enough levels for rank"};
-    DCt Cm = cmp_matrix(C, K, V, N, cmp);
+    DCt Cm = cmp_matrix(C, K, V, N, cmp, VR_out);
     DCt S = sum_r(C, K, Cm, N);
     return ev_add_plain(C, S, get_plain(C, kHalfRow0, N, S.level));
+}
+
+// minimum with tie-correction: k = SumR(C + E (delta_{j>=i} - 1/2)), E = C (4 - 4C)
+// (rank plus offset; their +1/2 and -1/2 cancel); O = Cmp(1.5, k) on (1.5 - k)/N
+// (k >= 1 is integral); onehot = MaskR(O, 0); value = SumC(O * V)
+static void argmin(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, ckr_sign ind, DCt &onehot,
+                   DCt &value) {
+    check_N(C, (u32)N);
+    if ((u32)V.level < argmin_depth(cmp, ind)) throw Error{CKR_E_DEPTH, "not enough levels for argmin"};
+    DCt Cm = cmp_matrix(C, K, V, N, cmp);
+    DCt w = ev_add_const(C, ev_mul_int(C, Cm, -4), 4.0);
+    DCt E = ev_mul(C, K, Cm, w);
+    DCt Et = ev_mul_plain(C, E, get_plain(C, kTieMask, N, E.level));
+    DCt Ca = ev_cmul_to(C, Cm, 1.0, Et.level);
+    DCt k = sum_r(C, K, ev_add(C, Ca, Et, false), N);
+    DCt d = ev_add_const(C, ev_cmul_to(C, k, -1.0 / (double)N, k.level - 1), 1.5 / (double)N);
+    DCt O = cmp_sign(C, K, d, ind);
+    onehot = ev_mul_plain(C, O, get_plain(C, kMaskRow0, N, O.level));
+    DCt Va = ev_cmul_to(C, V, 1.0, O.level);
+    value = sum_c(C, K, ev_mul(C, K, O, Va), N);
+}
+
+// Algorithm Sorting: M = Ind_0(ReplR(R) - (1^N || ... || N^N)) with
+// Ind_0(x) = Cmp(x, -1/2) (1 - Cmp(x, 1/2)) on (x +- 1/2)/N; S = TransC(SumC(M * ReplR(V)))
+static DCt sort(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, ckr_sign ind) {
+    check_N(C, (u32)N);
+    if ((u32)V.level < sort_depth(cmp, ind)) throw Error{CKR_E_DEPTH, "not enough levels for sort"};
+    DCt VR;
+    DCt R = rank(C, K, V, N, cmp, &VR);
+    DCt RR = repl_r(C, K, R, N);
+    DCt X = ev_add_plain(C, RR, get_plain(C, kSteps, N, RR.level));
+    DCt Xs = ev_cmul_to(C, X, 1.0 / (double)N, X.level - 1);
+    DCt d1 = ev_add_const(C, Xs, 0.5 / (double)N);
+    DCt d2 = ev_add_const(C, Xs, -0.5 / (double)N);
+    // both comparisons in one batched pass
+    DCt cc = cmp_sign(C, K, stack(C, {&d1, &d2}), ind);
+    const int B = V.B;
+    DCt c1 = slice(C, cc, 0, B), c2 = slice(C, cc, B, B);
+    DCt M = ev_mul(C, K, c1, ev_add_const(C, ev_mul_int(C, c2, -1), 1.0));
+    DCt VRa = ev_cmul_to(C, VR, 1.0, M.level);
+    DCt SC = sum_c(C, K, ev_mul(C, K, M, VRa), N);
+    return trans_c(C, K, SC, N);
 }
 
 }  // namespace ckr
@@ -1185,12 +1359,28 @@ ckr_status ckr_rank_batch(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *
     });
 }
 
-ckr_status ckr_argmin(ckr_context *, const ckr_keys *, const ckr_ct *, uint32_t, ckr_sign, ckr_sign, ckr_ct **,
-                      ckr_ct **) {
-    return guard([&] { throw Error{CKR_E_INVALID, "argmin not built yet"}; });
+ckr_status ckr_argmin(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, ckr_sign cmp,
+                      ckr_sign ind, ckr_ct **onehot, ckr_ct **value) {
+    return guard([&] {
+        NEED(ctx && keys && v && onehot && value);
+        *onehot = *value = nullptr;
+        Ctx &C = *ctx->C;
+        DCt oh, val;
+        argmin(C, *keys->K, v->ct, (int)N, cmp, ind, oh, val);
+        *onehot = wrap(C, std::move(oh));
+        *value = wrap(C, std::move(val));
+    });
 }
-ckr_status ckr_sort(ckr_context *, const ckr_keys *, const ckr_ct *, uint32_t, ckr_sign, ckr_sign, ckr_ct **) {
-    return guard([&] { throw Error{CKR_E_INVALID, "sort not built yet"}; });
+
+ckr_status ckr_sort(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, ckr_sign cmp, ckr_sign ind,
+                    ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && keys && v && out);
+        *out = nullptr;
+        Ctx &C = *ctx->C;
+        DCt r = sort(C, *keys->K, v->ct, (int)N, cmp, ind);
+        *out = wrap(C, std::move(r));
+    });
 }
 
 ckr_status ckr_op_rotate(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, int64_t k, ckr_ct **out) {
@@ -1255,8 +1445,43 @@ ckr_status ckr_ntt_device(ckr_context *ctx, uint64_t *data, uint32_t limbs, uint
     });
 }
 
-ckr_status ckr_set_profiling(ckr_context *ctx, int) {
-    return guard([&] { NEED(ctx); });
+ckr_status ckr_set_profiling(ckr_context *ctx, int enable) {
+    return guard([&] {
+        NEED(ctx);
+        Ctx &C = *ctx->C;
+        prof_resolve(C);
+        C.prof.on = enable != 0;
+    });
+}
+
+ckr_status ckr_profile_reset(ckr_context *ctx) {
+    return guard([&] {
+        NEED(ctx);
+        Ctx &C = *ctx->C;
+        prof_resolve(C);
+        for (int c = 0; c < kNCat; c++) C.prof.launches[c] = 0, C.prof.ms[c] = 0, C.prof.bytes[c] = 0;
+    });
+}
+
+ckr_status ckr_profile_read(ckr_context *ctx, int category, uint64_t *launches, double *total_ms, double *bytes) {
+    return guard([&] {
+        NEED(ctx);
+        if (category < 0 || category >= kNCat) throw Error{CKR_E_INVALID, "profile category"};
+        Ctx &C = *ctx->C;
+        prof_resolve(C);
+        if (launches) *launches = C.prof.launches[category];
+        if (total_ms) *total_ms = C.prof.ms[category];
+        if (bytes) *bytes = C.prof.bytes[category];
+    });
+}
+
+const char *ckr_profile_name(int category) { return category >= 0 && category < kNCat ? kCatName[category] : nullptr; }
+
+ckr_status ckr_synchronize(ckr_context *ctx) {
+    return guard([&] {
+        NEED(ctx);
+        HIPCHK(hipStreamSynchronize(ctx->C->stream));
+    });
 }
 
 }  // extern "C"

@@ -51,6 +51,8 @@ struct LimbBatch {
 
 // ---- kernels (ckr_kernels.hip) ------------------------------------------
 void k_ntt(const DevTables &T, const LimbBatch &b, bool inverse, hipStream_t s);
+// one pass of the two-pass transform: pass 0 runs first (columns forward, rows inverse)
+void k_ntt_pass(const DevTables &T, const LimbBatch &b, bool inverse, int pass, hipStream_t s);
 
 // out = a + b, a - b (mod q) over a batch of limbs (same geometry for all three)
 void k_add(const DevTables &T, u64 *out, const u64 *a, const u64 *b, int limbs, int polys, size_t stride_o,

@@ -25,13 +25,22 @@ PSETS = {
     "P12": dict(logn=12, L=11, q0_bits=44, log_scale=36, K=4, p_bits=40, dnum=3),
     # rank on N <= 128 at n = 2^16 (log QP ~ 1320 bits)
     "P16": dict(logn=16, L=23, q0_bits=50, log_scale=40, K=7, p_bits=50, dnum=3),
+    # tie-corrected argmin and sort on N <= 128 at n = 2^17 (40 levels, log QP ~ 2150 bits)
+    "P17": dict(logn=17, L=40, q0_bits=50, log_scale=40, K=10, p_bits=50, dnum=4),
     # small rings used by the unit and parity tests
+    "T12D": dict(logn=12, L=34, q0_bits=44, log_scale=36, K=9, p_bits=40, dnum=4),
     "T10": dict(logn=10, L=7, q0_bits=44, log_scale=36, K=3, p_bits=46, dnum=3),
     "T13": dict(logn=13, L=11, q0_bits=44, log_scale=36, K=4, p_bits=40, dnum=3),
 }
 
 # Comparator compositions (d_g, d_f) per workload: g applied d_g times, then f d_f times.
 RANK_CMP = {8: (2, 1), 16: (3, 1), 32: (3, 1), 64: (4, 1), 128: (4, 1)}
+# tie-corrected argmin: (comparator, one-sided indicator)
+ARGMIN_CMP = {8: ((3, 1), (2, 1)), 16: ((4, 1), (3, 2)), 32: ((4, 2), (3, 2)), 64: ((4, 2), (3, 2)),
+              128: ((4, 2), (3, 2))}
+# sort: (comparator, two-sided indicator)
+SORT_CMP = {8: ((3, 1), (3, 2)), 16: ((4, 1), (3, 2)), 32: ((4, 1), (3, 2)), 64: ((4, 1), (4, 2)),
+            128: ((4, 1), (4, 2))}
 
 
 def min_gap_uniform(N, gap, rng):
@@ -53,6 +62,13 @@ def tied_pool(N, pool, gap, rng):
 
 def seed_bytes(rng):
     return bytes(rng.integers(0, 256, 32, dtype=np.uint8).tolist())
+
+
+def tied_workload(N, seed, gap=2.0 ** -10):
+    """(values, key seed, encryption seed) with 25 % duplicated values."""
+    rng = np.random.default_rng(seed)
+    v = tied_pool(N, N - N // 4, gap, rng)
+    return v, seed_bytes(rng), seed_bytes(rng)
 
 
 def rank_workload(N, gap, seed):

@@ -1,0 +1,77 @@
+"""Writes the stored expected values under tests/golden/ by running the
+oracle only (never the HIP path).  Usage: python tests/golden/make_golden.py"""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import oracle as O  # noqa: E402
+from paper_2412_15126_amd import workloads as W  # noqa: E402
+
+
+def rank128_p16():
+    N, level = 128, 17
+    O.set_threads(min(16, os.cpu_count() or 1))
+    P = O.Params(**W.PSETS["P16"])
+    v, kseed, eseed = W.rank_workload(N, 2.0 ** -10, 0)
+    K = O.Keys(P, kseed, level, P.rank_galois(N))
+    ct = O.encrypt(K, v, level, eseed)
+    R = O.rank(K, ct, N, *W.RANK_CMP[N])
+    arr = R.export()
+    dec = O.decrypt(K, R, N)
+    return {"_what": "oracle rank of N=128 at n=2^16 (P16), workload seed 0, encryption level 17, "
+                     "comparator g^4 then f: sha256 of the exported output ciphertext and its decoded ranks",
+            "sha256": hashlib.sha256(arr.tobytes()).hexdigest(),
+            "decoded": [float(x) for x in dec],
+            "exact": [int(x) for x in np.argsort(np.argsort(v)) + 1]}
+
+
+def argmin128_p17():
+    N = 128
+    cmp, ind = W.ARGMIN_CMP[N]
+    O.set_threads(min(16, os.cpu_count() or 1))
+    P = O.Params(**W.PSETS["P17"])
+    level = P.L
+    v, kseed, eseed = W.tied_workload(N, 0)
+    K = O.Keys(P, kseed, level, P.circuit_galois(N, 2))
+    ct = O.encrypt(K, v, level, eseed)
+    oh, val = O.argmin(K, ct, N, cmp, ind)
+    a, b = oh.export(), val.export()
+    return {"_what": "oracle tie-corrected argmin of N=128 at n=2^17 (P17), tied workload seed 0 (96 distinct values "
+                     "+ 32 duplicates), encryption level 40, comparator g^4 f^2, indicator g^3 f^2: sha256 of the "
+                     "exported one-hot and value ciphertexts and their decoded slots",
+            "sha256_onehot": hashlib.sha256(a.tobytes()).hexdigest(),
+            "sha256_value": hashlib.sha256(b.tobytes()).hexdigest(),
+            "onehot": [float(x) for x in O.decrypt(K, oh, N)],
+            "value": float(O.decrypt(K, val, 1)[0]),
+            "argmin": int(np.argmin(v)), "min": float(v.min())}
+
+
+def sort128_p17():
+    N = 128
+    cmp, ind = W.SORT_CMP[N]
+    O.set_threads(min(16, os.cpu_count() or 1))
+    P = O.Params(**W.PSETS["P17"])
+    level = P.L
+    v, kseed, eseed = W.rank_workload(N, 2.0 ** -10, 0)
+    K = O.Keys(P, kseed, level, P.circuit_galois(N, 4))
+    ct = O.encrypt(K, v, level, eseed)
+    S = O.sort(K, ct, N, cmp, ind)
+    a = S.export()
+    return {"_what": "oracle sort of N=128 at n=2^17 (P17), workload seed 0, encryption level 40, comparator g^4 f, "
+                     "indicator g^4 f^2: sha256 of the exported output ciphertext and its decoded slots",
+            "sha256": hashlib.sha256(a.tobytes()).hexdigest(),
+            "decoded": [float(x) for x in O.decrypt(K, S, N)],
+            "sorted": [float(x) for x in np.sort(v)]}
+
+
+if __name__ == "__main__":
+    which = sys.argv[1:] or ["rank128_p16", "argmin128_p17", "sort128_p17"]
+    for name in which:
+        json.dump(globals()[name](), open(os.path.join(HERE, name + ".json"), "w"), indent=1)
+        print("wrote", name + ".json", flush=True)

@@ -173,3 +173,59 @@ def test_oracle_matrix_ops_match_shadow(ora, p12):
         got = ora.decrypt(keys, fn(keys, col, N), 2 * N * N)
         want = sfn(S.trans_r(x, N), N)[:2 * N * N]
         assert np.max(np.abs(got - want)) < 1e-4, name
+
+
+@pytest.fixture(scope="module")
+def t12d(ora):
+    P = ora.Params(**W.PSETS["T12D"])
+    keys = ora.Keys(P, bytes(range(32)), P.L, P.circuit_galois(8, 6))
+    return P, keys
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_oracle_argmin8_ties_matches_shadow(ora, t12d, seed):
+    P, keys = t12d
+    N = 8
+    cmp, ind = W.ARGMIN_CMP[N]
+    v, _, eseed = W.tied_workload(N, seed, 0.01)
+    assert len(set(v.tolist())) < N                   # the workload has ties
+    ct = ora.encrypt(keys, v, P.L, eseed)
+    oh, val = ora.argmin(keys, ct, N, cmp, ind)
+    assert oh.level == P.L - ora.argmin_depth(cmp, ind) + 1 and val.level == P.L - ora.argmin_depth(cmp, ind)
+    got_oh, got_val = ora.decrypt(keys, oh, N), ora.decrypt(keys, val, 1)[0]
+    sh_oh, sh_val, _ = S.argmin_circuit(v, N, P.n // 2, cmp, ind)
+    assert np.max(np.abs(got_oh - sh_oh[:N])) < 1e-3 and abs(got_val - sh_val[0]) < 1e-3
+    want = np.zeros(N)
+    want[int(np.argmin(v))] = 1.0                    # lowest index among the minima
+    assert np.array_equal(np.round(got_oh), want)
+    assert abs(got_val - v.min()) < 0.01
+
+
+def test_oracle_sort8_matches_shadow(ora, t12d):
+    P, keys = t12d
+    N = 8
+    cmp, ind = W.SORT_CMP[N]
+    v, _, eseed = W.rank_workload(N, 0.01, 3)
+    ct = ora.encrypt(keys, v, P.L, eseed)
+    s = ora.sort(keys, ct, N, cmp, ind)
+    assert s.level == P.L - ora.sort_depth(cmp, ind)
+    got = ora.decrypt(keys, s, N)
+    assert np.max(np.abs(got - S.sort_circuit(v, N, P.n // 2, cmp, ind)[:N])) < 1e-3
+    assert np.max(np.abs(got - np.sort(v))) < 1e-3
+
+
+@pytest.mark.parametrize("N", [8, 32, 128])
+def test_shadow_argmin_and_sort_compositions(N):
+    """The compositions used per N give a correct one-hot / sorted vector (plaintext shadow)."""
+    cmp, ind = W.ARGMIN_CMP[N]
+    gap = 0.01 if N == 8 else 2.0 ** -10
+    for seed in range(10):
+        v, _, _ = W.tied_workload(N, seed, gap)
+        oh, val, _ = S.argmin_circuit(v, N, 2 * N * N, cmp, ind)
+        want = np.zeros(N)
+        want[int(np.argmin(v))] = 1.0
+        assert np.max(np.abs(oh[:N] - want)) < 0.1
+    cmp, ind = W.SORT_CMP[N]
+    for seed in range(10):
+        v, _, _ = W.rank_workload(N, gap, seed)
+        assert np.max(np.abs(S.sort_circuit(v, N, 2 * N * N, cmp, ind)[:N] - np.sort(v))) < 1e-3

@@ -1,0 +1,151 @@
+"""GPU parity of the tie-corrected argmin and of sorting.
+
+Small ring (n = 2^12, 35 primes): element-by-element against the oracle run
+in the test.  Full size (n = 2^17, 41 + 10 primes, N = 128): against the
+digests written by tests/golden/make_golden.py (oracle only)."""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2412_15126_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def small(ora):
+    import paper_2412_15126_amd as ckr
+    ps = W.PSETS["T12D"]
+    P = ora.Params(**ps)
+    seed = bytes(range(32))
+    say("[gpu] T12D keys")
+    okeys = ora.Keys(P, seed, P.L, P.circuit_galois(8, 6))
+    ctx = ckr.Context(ps)
+    gkeys = ctx.keygen(seed, P.L, [8], what=6)
+    return dict(P=P, okeys=okeys, ctx=ctx, gkeys=gkeys, ckr=ckr)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_argmin8_with_ties_bit_exact(ora, small, seed):
+    P, ctx = small["P"], small["ctx"]
+    N = 8
+    cmp, ind = W.ARGMIN_CMP[N]
+    v, _, eseed = W.tied_workload(N, seed, 0.01)
+    say(f"[gpu] argmin8 seed {seed}")
+    o = ora.encrypt(small["okeys"], v, P.L, eseed)
+    g = ctx.encrypt(small["gkeys"], v, P.L, eseed)
+    ooh, oval = ora.argmin(small["okeys"], o, N, cmp, ind)
+    goh, gval = ctx.argmin(small["gkeys"], g, N, cmp, ind)
+    assert np.array_equal(ooh.export(), goh.export())
+    assert np.array_equal(oval.export(), gval.export())
+    want = np.zeros(N)
+    want[int(np.argmin(v))] = 1.0
+    assert np.array_equal(np.round(ctx.decrypt(small["gkeys"], goh, N)), want)
+    assert abs(ctx.decrypt(small["gkeys"], gval, 1)[0] - v.min()) < 0.01
+
+
+def test_argmin8_all_equal_picks_first(ora, small):
+    P, ctx = small["P"], small["ctx"]
+    N = 8
+    cmp, ind = W.ARGMIN_CMP[N]
+    v = np.full(N, 0.375)
+    o = ora.encrypt(small["okeys"], v, P.L, bytes([7] * 32))
+    g = ctx.encrypt(small["gkeys"], v, P.L, bytes([7] * 32))
+    ooh, oval = ora.argmin(small["okeys"], o, N, cmp, ind)
+    goh, gval = ctx.argmin(small["gkeys"], g, N, cmp, ind)
+    assert np.array_equal(ooh.export(), goh.export()) and np.array_equal(oval.export(), gval.export())
+    assert np.array_equal(np.round(ctx.decrypt(small["gkeys"], goh, N)), np.eye(N)[0])
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_sort8_bit_exact(ora, small, seed):
+    P, ctx = small["P"], small["ctx"]
+    N = 8
+    cmp, ind = W.SORT_CMP[N]
+    v, _, eseed = W.rank_workload(N, 0.01, 20 + seed)
+    say(f"[gpu] sort8 seed {seed}")
+    o = ora.encrypt(small["okeys"], v, P.L, eseed)
+    g = ctx.encrypt(small["gkeys"], v, P.L, eseed)
+    so = ora.sort(small["okeys"], o, N, cmp, ind)
+    sg = ctx.sort(small["gkeys"], g, N, cmp, ind)
+    assert np.array_equal(so.export(), sg.export())
+    assert np.max(np.abs(ctx.decrypt(small["gkeys"], sg, N) - np.sort(v))) < 1e-3
+
+
+def test_circuit_depth_errors(small):
+    ckr, ctx = small["ckr"], small["ctx"]
+    g = ctx.encrypt(small["gkeys"], np.linspace(0, 1, 8), 20, bytes([1] * 32))
+    for call in (lambda: ctx.argmin(small["gkeys"], g, 8, *W.ARGMIN_CMP[8]),
+                 lambda: ctx.sort(small["gkeys"], g, 8, *W.SORT_CMP[8])):
+        with pytest.raises(ckr.CkrError) as e:
+            call()
+        assert e.value.status == -3
+
+
+@pytest.fixture(scope="module")
+def p17():
+    import paper_2412_15126_amd as ckr
+    say("[gpu] P17 context")
+    ps = W.PSETS["P17"]
+    return ckr.Context(ps), ps
+
+
+def test_argmin128_full_size_matches_golden(p17):
+    ctx, ps = p17
+    gold = json.load(open(os.path.join(GOLD, "argmin128_p17.json")))
+    N = 128
+    cmp, ind = W.ARGMIN_CMP[N]
+    v, kseed, eseed = W.tied_workload(N, 0)
+    say("[gpu] P17 argmin keygen")
+    keys = ctx.keygen(kseed, ps["L"], [N], what=2)
+    g = ctx.encrypt(keys, v, ps["L"], eseed)
+    say("[gpu] P17 argmin")
+    oh, val = ctx.argmin(keys, g, N, cmp, ind)
+    assert hashlib.sha256(oh.export().tobytes()).hexdigest() == gold["sha256_onehot"]
+    assert hashlib.sha256(val.export().tobytes()).hexdigest() == gold["sha256_value"]
+    dec = ctx.decrypt(keys, oh, N)
+    assert int(np.argmax(dec)) == int(np.argmin(v)) == gold["argmin"]
+    assert np.array_equal(np.round(dec), np.eye(N)[gold["argmin"]])
+    assert abs(ctx.decrypt(keys, val, 1)[0] - v.min()) < 1e-3
+
+
+def test_sort128_full_size_matches_golden(p17):
+    ctx, ps = p17
+    gold = json.load(open(os.path.join(GOLD, "sort128_p17.json")))
+    N = 128
+    cmp, ind = W.SORT_CMP[N]
+    v, kseed, eseed = W.rank_workload(N, 2.0 ** -10, 0)
+    say("[gpu] P17 sort keygen")
+    keys = ctx.keygen(kseed, ps["L"], [N], what=4)
+    g = ctx.encrypt(keys, v, ps["L"], eseed)
+    say("[gpu] P17 sort")
+    s = ctx.sort(keys, g, N, cmp, ind)
+    assert hashlib.sha256(s.export().tobytes()).hexdigest() == gold["sha256"]
+    assert np.max(np.abs(ctx.decrypt(keys, s, N) - np.sort(v))) < 1e-3
+
+
+def test_p17_encrypt_mul_bit_exact(ora, p17):
+    """n = 2^17 transforms, relinearisation and rescale against the oracle."""
+    ctx, ps = p17
+    ora.set_threads(min(16, os.cpu_count() or 1))
+    P = ora.Params(**ps)
+    seed = bytes(range(5, 37))
+    say("[gpu] P17 relin keys")
+    okeys = ora.Keys(P, seed, ps["L"], [])
+    gkeys = ctx.keygen(seed, ps["L"], [])
+    v = np.random.default_rng(3).uniform(0, 1, 1000)
+    for level in (ps["L"], 9):
+        o = ora.encrypt(okeys, v, level, bytes([2] * 32))
+        g = ctx.encrypt(gkeys, v, level, bytes([2] * 32))
+        assert np.array_equal(o.export(), g.export())
+        assert np.array_equal(ora.mul(okeys, o, o).export(), ctx.mul(gkeys, g, g).export())

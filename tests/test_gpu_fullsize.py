@@ -1,0 +1,77 @@
+"""Full-size parity: rank of N = 128 at n = 2^16 (24 + 7 primes, dnum = 3,
+encryption level 17) -- the workload bench.py times -- against the oracle run
+in the test on the host, bit for bit, plus the stored digest written by
+tests/golden/make_golden.py (oracle only)."""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2412_15126_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "rank128_p16.json")
+N, LEVEL = 128, 17
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def full(ora):
+    import paper_2412_15126_amd as ckr
+    ora.set_threads(min(16, os.cpu_count() or 1))
+    ps = W.PSETS["P16"]
+    v, kseed, eseed = W.rank_workload(N, 2.0 ** -10, 0)
+    say("[gpu] P16 oracle keygen")
+    P = ora.Params(**ps)
+    okeys = ora.Keys(P, kseed, LEVEL, P.rank_galois(N))
+    say("[gpu] P16 device keygen")
+    ctx = ckr.Context(ps)
+    gkeys = ctx.keygen(kseed, LEVEL, [N])
+    return dict(P=P, okeys=okeys, ctx=ctx, gkeys=gkeys, v=v, eseed=eseed)
+
+
+def test_encrypt_rotate_mul_full_size(ora, full):
+    say("[gpu] P16 encrypt/rotate/mul")
+    o = ora.encrypt(full["okeys"], full["v"], LEVEL, full["eseed"])
+    g = full["ctx"].encrypt(full["gkeys"], full["v"], LEVEL, full["eseed"])
+    assert np.array_equal(o.export(), g.export())
+    shift = -(N * (N - 1) >> 1)     # first TransR rotation
+    assert np.array_equal(ora.rotate(full["okeys"], o, shift).export(),
+                          full["ctx"].rotate(full["gkeys"], g, shift).export())
+    assert np.array_equal(ora.mul(full["okeys"], o, o).export(), full["ctx"].mul(full["gkeys"], g, g).export())
+
+
+def test_rank128_full_size_bit_exact(ora, full):
+    say("[gpu] P16 rank-128 device")
+    g = full["ctx"].encrypt(full["gkeys"], full["v"], LEVEL, full["eseed"])
+    rg = full["ctx"].rank(full["gkeys"], g, N, W.RANK_CMP[N]).export()
+    say("[gpu] P16 rank-128 oracle")
+    o = ora.encrypt(full["okeys"], full["v"], LEVEL, full["eseed"])
+    ro = ora.rank(full["okeys"], o, N, *W.RANK_CMP[N]).export()
+    assert rg.shape == (2, 1, 1 << 16)
+    assert np.array_equal(ro, rg)
+    gold = json.load(open(GOLD))
+    assert hashlib.sha256(rg.tobytes()).hexdigest() == gold["sha256"]
+    dec = full["ctx"].decrypt(full["gkeys"], full["ctx"].import_ct(rg), N)
+    assert np.array_equal(np.round(dec), np.argsort(np.argsort(full["v"])) + 1)
+    assert np.max(np.abs(dec - np.array(gold["decoded"]))) < 1e-6
+
+
+def test_rank128_batch_equals_single_full_size(full):
+    say("[gpu] P16 batch of 3")
+    ctx, keys = full["ctx"], full["gkeys"]
+    cts, singles = [], []
+    for s in range(3):
+        v, _, eseed = W.rank_workload(N, 2.0 ** -10, 100 + s)
+        c = ctx.encrypt(keys, v, LEVEL, eseed)
+        cts.append(c)
+        singles.append(ctx.rank(keys, c, N, W.RANK_CMP[N]).export())
+    for s, b in zip(singles, ctx.rank_batch(keys, cts, N, W.RANK_CMP[N])):
+        assert np.array_equal(s, b.export())
