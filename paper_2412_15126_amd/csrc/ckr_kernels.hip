@@ -370,15 +370,28 @@ __global__ void ew_bconv(u64 *out, const u64 *src, BConvTab tab, int logn, size_
     for (int j = 0; j < tab.nt; j++) {
         const double tq = mq[tab.tgt_mod[j]].x, two_t = 2.0 * tq;
         double acc = 0.0;
+        if (tq * (2 * kMaxBConvSrc) < C52) {
+            // every lazy product is below 2t: the whole sum stays below 2^52, exact
 #pragma unroll
-        for (int i = 0; i < kMaxBConvSrc; i++) {
-            if (i < tab.ns) {
-                const double2 h = tab.hmod[i * tab.nt + j];
-                acc += mm_lazy(y[i], h.x, h.y, tq);
-                acc = acc >= two_t ? acc - two_t : acc;
+            for (int i = 0; i < kMaxBConvSrc; i++) {
+                if (i < tab.ns) {
+                    const double2 h = tab.hmod[i * tab.nt + j];
+                    acc += mm_lazy(y[i], h.x, h.y, tq);
+                }
             }
+            const double2 Q = mq[tab.tgt_mod[j]];
+            ob[(size_t)tab.tgt_slot[j] * n + c] = d2u(red_any(acc, Q.x, Q.y));
+        } else {
+#pragma unroll
+            for (int i = 0; i < kMaxBConvSrc; i++) {
+                if (i < tab.ns) {
+                    const double2 h = tab.hmod[i * tab.nt + j];
+                    acc += mm_lazy(y[i], h.x, h.y, tq);
+                    acc = acc >= two_t ? acc - two_t : acc;
+                }
+            }
+            ob[(size_t)tab.tgt_slot[j] * n + c] = d2u(red1(acc, tq));
         }
-        ob[(size_t)tab.tgt_slot[j] * n + c] = d2u(red1(acc, tq));
     }
 }
 
