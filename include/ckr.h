@@ -156,11 +156,19 @@ ckr_status ckr_argmin(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, u
 ckr_status ckr_sort(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, ckr_sign cmp, ckr_sign ind,
                     ckr_ct **out);
 
-/* Rank on `count` ciphertexts of equal N and level, run as one batched pass:
- * every kernel launch covers all of them.  Outputs equal count single calls,
- * bit for bit. */
+/* Batched execution: `count` ciphertexts of equal N and level run through one
+ * circuit together -- every kernel launch covers all of them.  kind: 1 rank,
+ * 2 argmin (outputs out[2i] one-hot, out[2i+1] value), 3 sort (out[i]).
+ * With graphs enabled (the default) the first call for a shape (kind, N,
+ * level, count, comparators) runs eagerly, the second captures the circuit
+ * into a hipGraph owned by `keys`, later calls replay it.  Outputs equal
+ * `count` single calls, bit for bit. */
+ckr_status ckr_run_batch(ckr_context *ctx, const ckr_keys *keys, int kind, uint32_t N, ckr_sign cmp, ckr_sign ind,
+                         const ckr_ct *const *v, size_t count, ckr_ct **out);
 ckr_status ckr_rank_batch(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *const *v, size_t count, uint32_t N,
                           ckr_sign cmp, ckr_ct **out);
+/* Enable (default) or disable hipGraph capture of batched circuits. */
+ckr_status ckr_context_set_graphs(ckr_context *ctx, int enable);
 
 /* Ciphertext access.  export: words = 2*(level+1)*n uint64 (layout above). */
 uint32_t ckr_ct_level(const ckr_ct *ct);

@@ -83,6 +83,8 @@ _SIGS = {
     "ckr_profile_read": (C.c_int, [vp, C.c_int, C.POINTER(C.c_uint64), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "ckr_profile_name": (C.c_char_p, [C.c_int]),
     "ckr_synchronize": (C.c_int, [vp]),
+    "ckr_run_batch": (C.c_int, [vp, vp, C.c_int, C.c_uint32, Sign, Sign, C.POINTER(vp), C.c_size_t, C.POINTER(vp)]),
+    "ckr_context_set_graphs": (C.c_int, [vp, C.c_int]),
 }
 
 _lib = None
@@ -219,6 +221,19 @@ class Context:
         h = vp()
         _ok(lib().ckr_sort(self.h, keys.h, ct.h, N, sign(cmp), sign(ind), C.byref(h)))
         return Ct(self, h)
+
+    def set_graphs(self, on):
+        _ok(lib().ckr_context_set_graphs(self.h, int(on)))
+
+    def run_batch(self, keys, kind, cts, N, cmp, ind=(0, 0)):
+        """kind: 'rank', 'argmin' (returns (onehot, value) pairs) or 'sort'."""
+        k = {"rank": 1, "argmin": 2, "sort": 3}[kind]
+        per = 2 if kind == "argmin" else 1
+        arr = (vp * len(cts))(*[c.h for c in cts])
+        out = (vp * (per * len(cts)))()
+        _ok(lib().ckr_run_batch(self.h, keys.h, k, N, sign(cmp), sign(ind), arr, len(cts), out))
+        res = [Ct(self, vp(o)) for o in out]
+        return [tuple(res[2 * i:2 * i + 2]) for i in range(len(cts))] if per == 2 else res
 
     def rank_batch(self, keys, cts, N, cmp):
         arr = (vp * len(cts))(*[c.h for c in cts])

@@ -9,6 +9,8 @@
 // exact modular integer arithmetic.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace ckr {
@@ -67,10 +69,11 @@ __device__ __forceinline__ double red_any(double x, double q, double qinv) {
 // LDS exchanges; a round's LOGE-bit window of the local index selects which
 // elements a thread holds.  Values stay lazily reduced: [0, 4q) in the
 // forward direction, [0, 2q) in the inverse, canonical at the end.
-template <int LOGS, int LOGE, int C, bool COLPASS, bool INV>
+template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool FUSE>
 __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
     ntt_pass(u64 *__restrict__ base, size_t poly_stride, int limbs, LimbMap map, int logn,
-             const double2 *__restrict__ mq, const double2 *__restrict__ twtab, const double2 *__restrict__ twlast) {
+             const double2 *__restrict__ mq, const double2 *__restrict__ twtab, const double2 *__restrict__ twlast,
+             const NttFuse fz) {
     constexpr int S = 1 << LOGS, E = 1 << LOGE, TPC = S / E, NT = C * TPC;
     constexpr int NR = (LOGS + LOGE - 1) / LOGE;
     constexpr int SP = S + (S >> 4) + 1;
@@ -82,8 +85,32 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
     const int mod = map(t);
     const size_t n = (size_t)1 << logn;
     u64 *data = base + (size_t)p * poly_stride + (size_t)t * n;
-    const double q = mq[mod].x, two_q = 2.0 * q;
+    const double q = mq[mod].x, two_q = 2.0 * q, qinv = mq[mod].y;
     const double2 *tw = twtab + (size_t)mod * n;
+    constexpr bool PRO = FUSE && COLPASS && !INV;   // prologue: broadcast-reduce one limb
+    constexpr bool EPI = FUSE && !COLPASS && !INV;  // epilogue: (x - y) * c (+ add)
+    const u64 *psrc = PRO ? fz.src + (size_t)p * fz.src_stride : nullptr;
+    u64 *pout = nullptr;
+    const u64 *px = nullptr, *padd = nullptr;
+    double ec = 0.0, ecq = 0.0;
+    if (EPI) {
+        const size_t pb = (size_t)(p >> 1), pk = (size_t)(p & 1);
+        pout = fz.out + pb * fz.out_stride + pk * fz.out_off + (size_t)t * n;
+        px = fz.x + pb * fz.x_stride + pk * fz.x_off + (size_t)t * n;
+        if (fz.add && (fz.add_mask >> pk & 1)) padd = fz.add + pb * fz.add_stride + pk * fz.add_off + (size_t)t * n;
+        ec = fz.c.v[t];
+        ecq = fz.c.vq[t];
+    }
+    // final value of the element at position pos of this limb, stored
+    auto emit = [&](size_t pos, double y) {
+        if (EPI) {
+            double r = red1(mm_lazy(u2d(px[pos]) - y + q, ec, ecq, q), q);
+            if (padd) r = red1(r + u2d(padd[pos]), q);
+            pout[pos] = d2u(r);
+        } else {
+            data[pos] = d2u(y);
+        }
+    };
 
     const int ncol = (int)(n >> LOGS);
     const int c0 = blockIdx.x * C;
@@ -106,7 +133,10 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
         const bool direct = COLPASS || w >= 3;
         // ---- load
         if (rho == 0) {
-            if (direct) {
+            if (PRO) {
+#pragma unroll
+                for (int k = 0; k < E; k++) x[k] = red_any(u2d(psrc[gaddr(rbase | (k << w))]), q, qinv);
+            } else if (direct) {
 #pragma unroll
                 for (int k = 0; k < E; k++) x[k] = u2d(data[gaddr(rbase | (k << w))]);
             } else {
@@ -179,14 +209,13 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
             }
             if (direct) {
 #pragma unroll
-                for (int k = 0; k < E; k++) data[gaddr(rbase | (k << w))] = d2u(x[k]);
+                for (int k = 0; k < E; k++) emit(gaddr(rbase | (k << w)), x[k]);
             } else {
                 __syncthreads();
 #pragma unroll
                 for (int k = 0; k < E; k++) lds[lidx(cl, rbase | (k << w))] = x[k];
                 __syncthreads();
-                u64 *dst = data + (size_t)c0 * S;
-                for (int i = tid; i < C * S; i += NT) dst[i] = d2u(lds[lidx(i / S, i % S)]);
+                for (int i = tid; i < C * S; i += NT) emit((size_t)c0 * S + i, lds[lidx(i / S, i % S)]);
             }
         } else {
             __syncthreads();
@@ -198,20 +227,26 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
 }
 
 template <int LOGS, int LOGE, int C, bool COLPASS, bool INV>
-static void launch_pass(const DevTables &T, const LimbBatch &b, hipStream_t s) {
+static void launch_pass(const DevTables &T, const LimbBatch &b, hipStream_t s, const NttFuse *f = nullptr) {
     const int logn = T.logn;
     const int blocks = (1 << (logn - LOGS)) / C;
     dim3 grid(blocks, b.limbs * b.polys);
     dim3 block(C * (1 << (LOGS - LOGE)));
-    hipLaunchKernelGGL((ntt_pass<LOGS, LOGE, C, COLPASS, INV>), grid, block, 0, s, b.base, b.poly_stride, b.limbs,
-                       b.map, logn, T.mq, INV ? T.tw_inv : T.tw_fwd, T.tw_last);
+    const double2 *tw = INV ? T.tw_inv : T.tw_fwd;
+    if (f && !INV && (COLPASS ? f->pro : f->epi))
+        hipLaunchKernelGGL((ntt_pass<LOGS, LOGE, C, COLPASS, INV, true>), grid, block, 0, s, b.base, b.poly_stride,
+                           b.limbs, b.map, logn, T.mq, tw, T.tw_last, *f);
+    else
+        hipLaunchKernelGGL((ntt_pass<LOGS, LOGE, C, COLPASS, INV, false>), grid, block, 0, s, b.base, b.poly_stride,
+                           b.limbs, b.map, logn, T.mq, tw, T.tw_last, NttFuse{});
 }
 
 template <int L1, int E1, int C1, int L2, int E2, int C2>
-static void ntt_one_pass(const DevTables &T, const LimbBatch &b, bool inverse, int pass, hipStream_t s) {
+static void ntt_one_pass(const DevTables &T, const LimbBatch &b, bool inverse, int pass, hipStream_t s,
+                         const NttFuse *f = nullptr) {
     if (!inverse) {
-        if (pass == 0) launch_pass<L1, E1, C1, true, false>(T, b, s);
-        else launch_pass<L2, E2, C2, false, false>(T, b, s);
+        if (pass == 0) launch_pass<L1, E1, C1, true, false>(T, b, s, f);
+        else launch_pass<L2, E2, C2, false, false>(T, b, s, f);
     } else {
         if (pass == 0) launch_pass<L2, E2, C2, false, true>(T, b, s);
         else launch_pass<L1, E1, C1, true, true>(T, b, s);
@@ -229,6 +264,21 @@ void k_ntt_pass(const DevTables &T, const LimbBatch &b, bool inverse, int pass, 
     case 15: ntt_one_pass<8, 4, 16, 7, 4, 16>(T, b, inverse, pass, s); break;
     case 16: ntt_one_pass<8, 4, 16, 8, 4, 16>(T, b, inverse, pass, s); break;
     case 17: ntt_one_pass<9, 4, 16, 8, 4, 16>(T, b, inverse, pass, s); break;
+    default: break;
+    }
+}
+
+void k_ntt_fused(const DevTables &T, const LimbBatch &b, const NttFuse &f, int pass, hipStream_t s) {
+    if (b.limbs * b.polys == 0) return;
+    switch (T.logn) {
+    case 10: ntt_one_pass<5, 4, 16, 5, 4, 32>(T, b, false, pass, s, &f); break;
+    case 11: ntt_one_pass<6, 3, 16, 5, 4, 32>(T, b, false, pass, s, &f); break;
+    case 12: ntt_one_pass<6, 3, 16, 6, 3, 16>(T, b, false, pass, s, &f); break;
+    case 13: ntt_one_pass<7, 4, 16, 6, 3, 16>(T, b, false, pass, s, &f); break;
+    case 14: ntt_one_pass<7, 4, 16, 7, 4, 16>(T, b, false, pass, s, &f); break;
+    case 15: ntt_one_pass<8, 4, 16, 7, 4, 16>(T, b, false, pass, s, &f); break;
+    case 16: ntt_one_pass<8, 4, 16, 8, 4, 16>(T, b, false, pass, s, &f); break;
+    case 17: ntt_one_pass<9, 4, 16, 8, 4, 16>(T, b, false, pass, s, &f); break;
     default: break;
     }
 }
@@ -349,107 +399,97 @@ __global__ void ew_automorph(u64 *out, const u64 *in, int limbs, size_t so, size
     out[p * so + t * n + i] = in[p * si + t * n + src];
 }
 
-// fast base conversion; grid.x over coefficients, grid.y over the batch.
-// y_i = [x_i * hinv_i]_{q_i} once per source, then for every target t:
-// sum_i y_i * hmod[i][t] mod t, kept in [0, 2t) while accumulating.
-__global__ void ew_bconv(u64 *out, const u64 *src, BConvTab tab, int logn, size_t so, size_t si, const double2 *mq) {
+// fast base conversion; grid.x over coefficients, grid.y over the batch,
+// grid.z over groups of `tpg` targets.  y_i = [x_i * hinv_i]_{q_i} once per
+// source, then for each target t: sum_i y_i * hmod[i][t] mod t.  Lazy products
+// are < 2t, so for t < 2^47 the NS-term sum stays exact below 2^52 and is
+// reduced once; larger targets reduce after every term.
+template <int NS>
+__global__ void __launch_bounds__(256)
+    ew_bconv(u64 *out, const u64 *src, BConvTab tab, int logn, size_t so, size_t si, const double2 *mq, int tpg) {
+    __shared__ double2 hm[NS * kMaxLimbArgs];
+    __shared__ double3 tq3[kMaxLimbArgs];
     const size_t n = (size_t)1 << logn;
+    const int j0 = blockIdx.z * tpg, j1 = min(j0 + tpg, tab.nt), nj = j1 - j0;
+    for (int k = threadIdx.x; k < NS * nj; k += blockDim.x) {
+        const int i = k / nj, j = k - i * nj;
+        hm[i * kMaxLimbArgs + j] = tab.hmod[i * tab.nt + j0 + j];
+    }
+    for (int j = threadIdx.x; j < nj; j += blockDim.x) {
+        const double2 Q = mq[tab.tgt_mod[j0 + j]];
+        tq3[j] = make_double3(Q.x, Q.y, (double)tab.tgt_slot[j0 + j]);
+    }
+    __syncthreads();
     const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
     const u64 *sb = src + blockIdx.y * si;
     u64 *ob = out + blockIdx.y * so;
-    double y[kMaxBConvSrc];
+    double y[NS];
 #pragma unroll
-    for (int i = 0; i < kMaxBConvSrc; i++) {
-        if (i < tab.ns) {
-            const double q = mq[tab.src_mod[i]].x;
-            const double2 h = tab.hinv[i];
-            y[i] = red1(mm_lazy(u2d(sb[(size_t)i * n + c]), h.x, h.y, q), q);
-        }
+    for (int i = 0; i < NS; i++) {
+        const double q = mq[tab.src_mod[i]].x;
+        const double2 h = tab.hinv[i];
+        y[i] = red1(mm_lazy(u2d(sb[(size_t)i * n + c]), h.x, h.y, q), q);
     }
-    for (int j = 0; j < tab.nt; j++) {
-        const double tq = mq[tab.tgt_mod[j]].x, two_t = 2.0 * tq;
+    for (int j = 0; j < nj; j++) {
+        const double3 T3 = tq3[j];
+        const double tq = T3.x, two_t = 2.0 * tq;
         double acc = 0.0;
-        if (tq * (2 * kMaxBConvSrc) < C52) {
-            // every lazy product is below 2t: the whole sum stays below 2^52, exact
+        if (tq * (2 * NS) < C52) {
 #pragma unroll
-            for (int i = 0; i < kMaxBConvSrc; i++) {
-                if (i < tab.ns) {
-                    const double2 h = tab.hmod[i * tab.nt + j];
-                    acc += mm_lazy(y[i], h.x, h.y, tq);
-                }
+            for (int i = 0; i < NS; i++) {
+                const double2 h = hm[i * kMaxLimbArgs + j];
+                acc += mm_lazy(y[i], h.x, h.y, tq);
             }
-            const double2 Q = mq[tab.tgt_mod[j]];
-            ob[(size_t)tab.tgt_slot[j] * n + c] = d2u(red_any(acc, Q.x, Q.y));
+            acc = red_any(acc, tq, T3.y);
         } else {
 #pragma unroll
-            for (int i = 0; i < kMaxBConvSrc; i++) {
-                if (i < tab.ns) {
-                    const double2 h = tab.hmod[i * tab.nt + j];
-                    acc += mm_lazy(y[i], h.x, h.y, tq);
-                    acc = acc >= two_t ? acc - two_t : acc;
-                }
+            for (int i = 0; i < NS; i++) {
+                const double2 h = hm[i * kMaxLimbArgs + j];
+                acc += mm_lazy(y[i], h.x, h.y, tq);
+                acc = acc >= two_t ? acc - two_t : acc;
             }
-            ob[(size_t)tab.tgt_slot[j] * n + c] = d2u(red1(acc, tq));
+            acc = red1(acc, tq);
         }
+        ob[(size_t)T3.z * n + c] = d2u(acc);
     }
 }
 
+// one thread per (target limb, coefficient) walks the whole batch: each key
+// word is read once per batch, not once per query
 __global__ void ew_ip(IPArgs a, int logn, const double2 *mq) {
+    constexpr int kMaxBeta = 8;
     const size_t n = (size_t)1 << logn;
     const size_t c = ((size_t)blockIdx.x * blockDim.x + threadIdx.x);
     if (c >= n) return;
     const int t = blockIdx.y;  // target limb in [0, E)
-    const int bi = blockIdx.z;
-    a.d += bi * a.sd;
-    a.ext += bi * a.sext;
-    a.accb += bi * a.sacc;
-    a.acca += bi * a.sacc;
     const int mod = t <= a.level ? t : a.nq + (t - a.level - 1);
     const int kl = t <= a.level ? t : a.lmax_key + 1 + (t - a.level - 1);
     const double2 Q = mq[mod];
-    double sb = 0.0, sa = 0.0;
-    for (int j = 0; j < a.beta; j++) {
-        const u64 *xs = (t <= a.level && t / a.alpha == j) ? a.d + (size_t)t * n
-                                                           : a.ext + ((size_t)j * a.E + t) * n;
-        const double x = u2d(xs[c]);
-        const double kb = u2d(a.key[(((size_t)j * 2 + 0) * a.Ek + kl) * n + c]);
-        const double ka = u2d(a.key[(((size_t)j * 2 + 1) * a.Ek + kl) * n + c]);
-        sb = red1(sb + pos1(mm_signed(x, kb, Q.x, Q.y), Q.x), Q.x);
-        sa = red1(sa + pos1(mm_signed(x, ka, Q.x, Q.y), Q.x), Q.x);
+    double kb[kMaxBeta], ka[kMaxBeta];
+#pragma unroll
+    for (int j = 0; j < kMaxBeta; j++) {
+        if (j < a.beta) {
+            kb[j] = u2d(a.key[(((size_t)j * 2 + 0) * a.Ek + kl) * n + c]);
+            ka[j] = u2d(a.key[(((size_t)j * 2 + 1) * a.Ek + kl) * n + c]);
+        }
     }
-    a.accb[(size_t)t * n + c] = d2u(sb);
-    a.acca[(size_t)t * n + c] = d2u(sa);
-}
-
-__global__ void ew_sub_mul(u64 *out, const u64 *x, const u64 *y, const u64 *add, int limbs, size_t so, size_t sx,
-                           size_t sy, size_t sadd, int logn, const double2 *mq, LimbScalars c) {
-    EW_PROLOGUE
-    const double q = mq[t].x;
-    const double w = c.v[t], wq = c.vq[t];
-    const ulonglong2 vx = *(const ulonglong2 *)(x + p * sx + t * n + i);
-    const ulonglong2 vy = *(const ulonglong2 *)(y + p * sy + t * n + i);
-    double r0 = red1(mm_lazy(u2d(vx.x) - u2d(vy.x) + q, w, wq, q), q);
-    double r1 = red1(mm_lazy(u2d(vx.y) - u2d(vy.y) + q, w, wq, q), q);
-    if (add) {
-        const ulonglong2 va = *(const ulonglong2 *)(add + p * sadd + t * n + i);
-        r0 = red1(r0 + u2d(va.x), q);
-        r1 = red1(r1 + u2d(va.y), q);
+    const int own = (t <= a.level) ? t / a.alpha : -1;  // digit holding limb t, if any
+    for (int bi = 0; bi < a.B; bi++) {
+        double sb = 0.0, sa = 0.0;
+#pragma unroll
+        for (int j = 0; j < kMaxBeta; j++) {
+            if (j < a.beta) {
+                const u64 *xs = (j == own) ? a.d + bi * a.sd + (size_t)t * n
+                                           : a.ext + bi * a.sext + ((size_t)j * a.E + t) * n;
+                const double x = u2d(xs[c]);
+                sb = red1(sb + pos1(mm_signed(x, kb[j], Q.x, Q.y), Q.x), Q.x);
+                sa = red1(sa + pos1(mm_signed(x, ka[j], Q.x, Q.y), Q.x), Q.x);
+            }
+        }
+        a.accb[bi * a.sacc + (size_t)t * n + c] = d2u(sb);
+        a.acca[bi * a.sacc + (size_t)t * n + c] = d2u(sa);
     }
-    ulonglong2 r;
-    r.x = d2u(r0);
-    r.y = d2u(r1);
-    *(ulonglong2 *)(out + p * so + t * n + i) = r;
-}
-
-__global__ void ew_bcast_mod(u64 *out, const u64 *src, int limbs, size_t so, size_t ss, int logn, const double2 *mq) {
-    EW_PROLOGUE
-    const double2 Q = mq[t];
-    const ulonglong2 v = *(const ulonglong2 *)(src + p * ss + i);
-    ulonglong2 r;
-    r.x = d2u(red_any(u2d(v.x), Q.x, Q.y));
-    r.y = d2u(red_any(u2d(v.y), Q.x, Q.y));
-    *(ulonglong2 *)(out + p * so + t * n + i) = r;
 }
 
 __global__ void ew_check_range(const u64 *data, int limbs, size_t stride, int logn, const u64 *qi, int *flag) {
@@ -497,22 +537,27 @@ void k_automorph(const DevTables &T, u64 *out, const u64 *in, int limbs, int pol
 }
 void k_bconv(const DevTables &T, u64 *out, const u64 *src, const BConvTab &tab, int batch, size_t so, size_t si,
              hipStream_t s) {
-    dim3 grid((unsigned)(((1u << T.logn) + 255) / 256), (unsigned)batch);
-    hipLaunchKernelGGL(ew_bconv, grid, dim3(256), 0, s, out, src, tab, T.logn, so, si, T.mq);
+    // split the targets into groups so small batches still fill the chip
+    const int blocks = (int)(((1u << T.logn) + 255) / 256) * batch;
+    int groups = std::max(1, std::min(tab.nt, 2048 / std::max(blocks, 1)));
+    const int tpg = (tab.nt + groups - 1) / groups;
+    groups = (tab.nt + tpg - 1) / tpg;
+    dim3 grid((unsigned)(((1u << T.logn) + 255) / 256), (unsigned)batch, (unsigned)groups);
+#define BCONV_CASE(K)                                                                                       \
+    case K:                                                                                                 \
+        hipLaunchKernelGGL(ew_bconv<K>, grid, dim3(256), 0, s, out, src, tab, T.logn, so, si, T.mq, tpg); \
+        break;
+    switch (tab.ns) {
+        BCONV_CASE(1) BCONV_CASE(2) BCONV_CASE(3) BCONV_CASE(4) BCONV_CASE(5) BCONV_CASE(6) BCONV_CASE(7)
+        BCONV_CASE(8) BCONV_CASE(9) BCONV_CASE(10) BCONV_CASE(11) BCONV_CASE(12) BCONV_CASE(13) BCONV_CASE(14)
+        BCONV_CASE(15) BCONV_CASE(16)
+    default: break;
+    }
+#undef BCONV_CASE
 }
 void k_ip(const DevTables &T, const IPArgs &a, hipStream_t s) {
-    dim3 grid((unsigned)(((1u << T.logn) + 255) / 256), (unsigned)a.E, (unsigned)a.B);
+    dim3 grid((unsigned)(((1u << T.logn) + 255) / 256), (unsigned)a.E);
     hipLaunchKernelGGL(ew_ip, grid, dim3(256), 0, s, a, T.logn, T.mq);
-}
-void k_sub_mul(const DevTables &T, u64 *out, const u64 *x, const u64 *y, const u64 *add, int limbs, int polys,
-               size_t so, size_t sx, size_t sy, size_t sadd, const LimbScalars &c, hipStream_t s) {
-    hipLaunchKernelGGL(ew_sub_mul, ew_grid(T.logn, limbs * polys), dim3(256), 0, s, out, x, y, add, limbs, so, sx, sy,
-                       sadd, T.logn, T.mq, c);
-}
-void k_bcast_mod(const DevTables &T, u64 *out, const u64 *src, int limbs, int polys, size_t so, size_t ss,
-                 hipStream_t s) {
-    hipLaunchKernelGGL(ew_bcast_mod, ew_grid(T.logn, limbs * polys), dim3(256), 0, s, out, src, limbs, so, ss, T.logn,
-                       T.mq);
 }
 void k_check_range(const DevTables &T, const u64 *data, int limbs, int polys, size_t stride, int *flag,
                    hipStream_t s) {

@@ -15,6 +15,9 @@
 #include <string>
 #include <tuple>
 #include <unordered_map>
+#include <unordered_set>
+#include <set>
+#include <functional>
 #include <vector>
 
 #include "../../include/ckr.h"
@@ -43,8 +46,45 @@ class Pool {
 
     static size_t round(size_t b) { return (b + 65535) & ~size_t(65535); }
 
+    // While a graph is being captured, every block the capture obtains is
+    // tracked; blocks freed during the capture are reused only by the capture
+    // and then handed to the graph (its replays write them).
+    void begin_capture() {
+        capturing_ = true;
+        cap_set_.clear();
+        cap_free_.clear();
+    }
+    std::vector<std::pair<void *, size_t>> end_capture() {
+        capturing_ = false;
+        std::vector<std::pair<void *, size_t>> owned;
+        for (auto &kv : cap_free_)
+            for (void *p : kv.second) owned.push_back({p, kv.first});
+        cap_free_.clear();
+        cap_set_.clear();
+        return owned;
+    }
+    void release_owned(const std::vector<std::pair<void *, size_t>> &owned) {
+        for (auto &b : owned) cache_[b.second].push_back(b.first);
+    }
+
     void *get(size_t bytes) {
         bytes = round(bytes);
+        if (capturing_) {
+            auto cf = cap_free_.find(bytes);
+            if (cf != cap_free_.end() && !cf->second.empty()) {
+                void *p = cf->second.back();
+                cf->second.pop_back();
+                in_use += bytes;
+                high = std::max(high, in_use);
+                return p;
+            }
+        }
+        void *p = get_uncaptured(bytes);
+        if (capturing_) cap_set_.insert(p);
+        return p;
+    }
+
+    void *get_uncaptured(size_t bytes) {
         auto it = cache_.find(bytes);
         if (it != cache_.end() && !it->second.empty()) {
             void *p = it->second.back();
@@ -53,14 +93,14 @@ class Pool {
             high = std::max(high, in_use);
             return p;
         }
-        if (budget && held + bytes > budget) trim();
+        if (budget && held + bytes > budget && !capturing_) trim();
         if (budget && held + bytes > budget) throw Error{CKR_E_NOMEM, "HBM budget exceeded"};
         void *p = nullptr;
         if (ualloc) {
             p = ualloc(bytes, user);
         } else if (hipMalloc(&p, bytes) != hipSuccess) {
             (void)hipGetLastError();
-            trim();
+            if (!capturing_) trim();
             p = nullptr;
             if (hipMalloc(&p, bytes) != hipSuccess) {
                 (void)hipGetLastError();
@@ -77,7 +117,8 @@ class Pool {
         if (!p) return;
         bytes = round(bytes);
         in_use -= bytes;
-        cache_[bytes].push_back(p);
+        if (capturing_ && cap_set_.count(p)) cap_free_[bytes].push_back(p);
+        else cache_[bytes].push_back(p);
     }
     // return cached blocks to the allocator (stream-ordered frees are safe
     // because the caller synchronises first)
@@ -95,6 +136,9 @@ class Pool {
 
   private:
     std::unordered_map<size_t, std::vector<void *>> cache_;
+    bool capturing_ = false;
+    std::unordered_set<void *> cap_set_;
+    std::unordered_map<size_t, std::vector<void *>> cap_free_;
 };
 
 struct Ctx;
@@ -161,6 +205,8 @@ struct Prof {
 
 struct Ctx {
     Prof prof;
+    bool graphs = true;           // capture batched circuits into hipGraphs
+    hipStream_t own_stream = nullptr;
     Params P;
     DevTables T{};
     hipStream_t stream = nullptr;
@@ -189,6 +235,7 @@ struct Ctx {
         for (hipEvent_t e : prof.spare) (void)hipEventDestroy(e);
         pool.trim();
         for (void *p : table_mem) (void)hipFree(p);
+        if (own_stream) (void)hipStreamDestroy(own_stream);
     }
 };
 
@@ -198,12 +245,38 @@ void Buf::release() {
     p_ = nullptr;
 }
 
+// a batched circuit captured once into a hipGraph and replayed: it reads a
+// plan-owned input batch and writes plan-owned outputs
+struct GraphPlan {
+    Ctx *C = nullptr;
+    DCt in;
+    std::vector<DCt> outs;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<std::pair<void *, size_t>> owned;  // temporaries the replays write
+    ~GraphPlan() {
+        if (C && C->stream) (void)hipStreamSynchronize(C->stream);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (C) C->pool.release_owned(owned);
+    }
+};
+
+struct PlanKey {
+    int kind, N, level, B, cg, cf, ig, iff;
+    bool operator<(const PlanKey &o) const {
+        return std::tie(kind, N, level, B, cg, cf, ig, iff) < std::tie(o.kind, o.N, o.level, o.B, o.cg, o.cf, o.ig, o.iff);
+    }
+};
+
 struct Keys {
     Ctx *C = nullptr;
     int lmax = 0;
     std::vector<i64> s;               // ternary secret, host only
     Buf pk;                           // [2][lmax+1][n] eval domain
     std::map<u32, Buf> swk;           // galois element (0 = relinearisation) -> [beta][2][Ek][n]
+    std::set<PlanKey> warm;           // circuits run once eagerly (caches filled)
+    std::map<PlanKey, std::unique_ptr<GraphPlan>> plans;  // destroyed before the keys they read
     int Ek() const { return lmax + 1 + C->P.K; }
 };
 
@@ -266,6 +339,16 @@ static void ntt(Ctx &C, u64 *base, int limbs, int polys, size_t stride, LimbMap 
     const double bytes = 16.0 * C.P.n * limbs * polys;
     timed(C, inv ? kNttInvRow : kNttFwdCol, bytes, [&] { k_ntt_pass(C.T, b, inv, 0, C.stream); });
     timed(C, inv ? kNttInvCol : kNttFwdRow, bytes, [&] { k_ntt_pass(C.T, b, inv, 1, C.stream); });
+}
+
+// forward transform with the fused prologue / epilogue of NttFuse
+static void ntt_fused(Ctx &C, u64 *base, int limbs, int polys, size_t stride, LimbMap map, const NttFuse &f) {
+    LimbBatch b{base, limbs, polys, stride, map};
+    const double limb = 8.0 * C.P.n, all = limb * limbs * polys;
+    const double b0 = f.pro ? limb * polys + all : 2 * all;
+    const double b1 = f.epi ? 3 * all + (f.add ? all * __builtin_popcount(f.add_mask) / 2 : 0) : 2 * all;
+    timed(C, kNttFwdCol, b0, [&] { k_ntt_fused(C.T, b, f, 0, C.stream); });
+    timed(C, kNttFwdRow, b1, [&] { k_ntt_fused(C.T, b, f, 1, C.stream); });
 }
 
 // 2-D strided device copy: `rows` rows of `width` words
@@ -478,7 +561,10 @@ static DCt slice(Ctx &C, const DCt &a, int first, int count) {
     return o;
 }
 
-// floor-form rescale: c_i <- (c_i - [c_l]_{q_i}) * q_l^{-1} mod q_i
+// floor-form rescale: c_i <- (c_i - [c_l]_{q_i}) * q_l^{-1} mod q_i.  The
+// last limb is brought to the coefficient domain, then one fused forward
+// transform reduces it modulo every q_i (prologue) and writes the combined
+// result (epilogue).
 static DCt ev_rescale(Ctx &C, const DCt &a) {
     const int l = a.level;
     if (l < 1) throw Error{CKR_E_DEPTH, "rescale at level 0"};
@@ -487,17 +573,23 @@ static DCt ev_rescale(Ctx &C, const DCt &a) {
     Buf last(&C, (size_t)P2 * n);
     timed(C, kCopy, 16.0 * n * P2, [&] { copy2d(C, last.get(), n, a.d() + (size_t)l * n, L, n, P2); });
     ntt(C, last.get(), 1, P2, n, plain_map(l), true);
-    Buf y(&C, (size_t)P2 * l * n);
-    timed(C, kElem, 8.0 * n * P2 * (l + 1), [&] { k_bcast_mod(C.T, y.get(), last.get(), l, P2, (size_t)l * n, n, C.stream); });
-    ntt(C, y.get(), l, P2, (size_t)l * n, plain_map(), false);
     DCt o = ct_new(C, l - 1, a.B);
     std::vector<u64> inv(l);
     for (int i = 0; i < l; i++) inv[i] = hinv(C.P.mod[l] % C.P.mod[i], C.P.mod[i]);
-    LimbScalars s;
-    scalars_of_vals(C, inv, s);
-    timed(C, kCombine, 24.0 * n * l * P2, [&] {
-        k_sub_mul(C.T, o.d(), a.d(), y.get(), nullptr, l, P2, (size_t)l * n, L, (size_t)l * n, 0, s, C.stream);
-    });
+    NttFuse f;
+    f.pro = true;
+    f.src = last.get();
+    f.src_stride = n;
+    f.epi = true;
+    f.out = o.d();
+    f.out_stride = (size_t)2 * l * n;
+    f.out_off = (size_t)l * n;
+    f.x = a.d();
+    f.x_stride = 2 * L;
+    f.x_off = L;
+    scalars_of_vals(C, inv, f.c);
+    Buf y(&C, (size_t)P2 * l * n);
+    ntt_fused(C, y.get(), l, P2, (size_t)l * n, plain_map(), f);
     return o;
 }
 
@@ -521,8 +613,10 @@ static DCt ev_cmul_to(Ctx &C, const DCt &a, double c, int target) {
 
 // hybrid key switch of d (B polys, eval domain, limbs 0..l, batch stride sd):
 //   out_b = ModDown(sum_j ModUp_j(d) * key_j.b) (+ add_b),  out_a likewise
-static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_t sd, int l, int B, u64 *ob,
-                      size_t sob, const u64 *addb, size_t saddb, u64 *oa, size_t soa) {
+// Output poly k (0: b part, 1: a part) of batch entry b goes to out + b*so + k*out_off
+// and, when bit k of add_mask is set, has add + b*sadd + k*add_off added.
+static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_t sd, int l, int B, u64 *out,
+                      size_t so, size_t out_off, const u64 *add, size_t sadd, size_t add_off, int add_mask) {
     const Params &P = C.P;
     if (l > K.lmax) throw Error{CKR_E_DEPTH, "ciphertext above key level"};
     const size_t n = C.n();
@@ -565,7 +659,7 @@ static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_
     ia.sext = sext;
     ia.sacc = sacc;
     timed(C, kIP, 8.0 * n * E * (3.0 * beta + 2) * B, [&] { k_ip(C.T, ia, C.stream); });
-    // ModDown: (x_Q - BConv_{P->Q}(x_P)) * P^{-1}
+    // ModDown: (x_Q - BConv_{P->Q}(x_P)) * P^{-1}, the combine fused into the last NTT pass
     ntt(C, acc.get() + (size_t)(l + 1) * n, P.K, 2 * B, (size_t)E * n, plain_map(P.nq), true);
     Buf conv(&C, (size_t)2 * B * (l + 1) * n);
     const BConvTab &mdt = moddown_tab(C, l);
@@ -573,7 +667,6 @@ static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_
         k_bconv(C.T, conv.get(), acc.get() + (size_t)(l + 1) * n, mdt, 2 * B, (size_t)(l + 1) * n, (size_t)E * n,
                 C.stream);
     });
-    ntt(C, conv.get(), l + 1, 2 * B, (size_t)(l + 1) * n, plain_map(), false);
     std::vector<u64> pinv(l + 1);
     for (int i = 0; i <= l; i++) {
         const u64 q = P.mod[i];
@@ -581,16 +674,20 @@ static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_
         for (int k = 0; k < P.K; k++) pp = hmul(pp, P.mod[P.nq + k] % q, q);
         pinv[i] = hinv(pp, q);
     }
-    LimbScalars s;
-    scalars_of_vals(C, pinv, s);
-    const size_t Lc = (size_t)(l + 1) * n;
-    timed(C, kCombine, 8.0 * Lc * B * (addb ? 4 : 3), [&] {
-        k_sub_mul(C.T, ob, acc.get(), conv.get(), addb, l + 1, B, sob, sacc, 2 * Lc, saddb, s, C.stream);
-    });
-    timed(C, kCombine, 24.0 * Lc * B, [&] {
-        k_sub_mul(C.T, oa, acc.get() + (size_t)E * n, conv.get() + Lc, nullptr, l + 1, B, soa, sacc, 2 * Lc, 0, s,
-                  C.stream);
-    });
+    NttFuse f;
+    f.epi = true;
+    f.out = out;
+    f.out_stride = so;
+    f.out_off = out_off;
+    f.x = acc.get();
+    f.x_stride = sacc;
+    f.x_off = (size_t)E * n;
+    f.add = add;
+    f.add_stride = sadd;
+    f.add_off = add_off;
+    f.add_mask = add ? add_mask : 0;
+    scalars_of_vals(C, pinv, f.c);
+    ntt_fused(C, conv.get(), l + 1, 2 * B, (size_t)(l + 1) * n, plain_map(), f);
 }
 
 static const Buf &find_key(const Keys &K, u32 g) {
@@ -608,11 +705,8 @@ static DCt ev_mul(Ctx &C, const Keys &K, const DCt &a, const DCt &b) {
     Buf d(&C, (size_t)a.B * 3 * L);
     timed(C, kTensor, 56.0 * L * a.B, [&] { k_tensor(C.T, d.get(), a.d(), b.d(), l + 1, a.B, 3 * L, 2 * L, 2 * L, C.stream); });
     DCt r = ct_new(C, l, a.B);
-    keyswitch(C, K, find_key(K, 0), d.get() + 2 * L, 3 * L, l, a.B, r.d(), 2 * L, d.get(), 3 * L, r.d() + L, 2 * L);
-    // poly 1 still needs d1: out_a was written without it
-    timed(C, kElem, 24.0 * L * a.B, [&] {
-        k_add(C.T, r.d() + L, r.d() + L, d.get() + L, l + 1, a.B, 2 * L, 2 * L, 3 * L, plain_map(), false, C.stream);
-    });
+    // (d0 + KS_b(d2), d1 + KS_a(d2))
+    keyswitch(C, K, find_key(K, 0), d.get() + 2 * L, 3 * L, l, a.B, r.d(), 2 * L, L, d.get(), 3 * L, L, 3);
     return ev_rescale(C, r);
 }
 
@@ -632,7 +726,8 @@ static DCt ev_rotate(Ctx &C, const Keys &K, const DCt &a, i64 k) {
     DCt r = ct_new(C, l, a.B);
     timed(C, kAutomorph, 32.0 * L * a.B, [&] { k_automorph(C.T, r.d(), a.d(), l + 1, 2 * a.B, L, L, g, C.stream); });
     DCt o = ct_new(C, l, a.B);
-    keyswitch(C, K, key, r.d() + L, 2 * L, l, a.B, o.d(), 2 * L, r.d(), 2 * L, o.d() + L, 2 * L);
+    // (sigma(c0) + KS_b(sigma(c1)), KS_a(sigma(c1)))
+    keyswitch(C, K, key, r.d() + L, 2 * L, l, a.B, o.d(), 2 * L, L, r.d(), 2 * L, L, 1);
     return o;
 }
 
@@ -868,6 +963,81 @@ static DCt sort(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, ckr_si
     return trans_c(C, K, SC, N);
 }
 
+// Run `circuit` on a batch of single ciphertexts of equal level.  With graphs
+// enabled, the first call for a shape runs eagerly (filling plaintext and
+// table caches), the second captures the circuit into a hipGraph, later calls
+// copy the inputs into the plan's input batch and replay it.  Every path
+// launches the same kernels in the same order: outputs are bit-identical.
+using Circuit = std::function<std::vector<DCt>(const DCt &)>;
+
+static std::vector<DCt> run_circuit(Ctx &C, Keys &K, const PlanKey &key, const std::vector<const DCt *> &in,
+                                    const Circuit &circuit) {
+    const int B = (int)in.size();
+    const size_t W = (size_t)2 * (key.level + 1) * C.n();
+    auto fill = [&](DCt &X) {
+        for (int i = 0; i < B; i++)
+            HIPCHK(hipMemcpyAsync(X.d() + i * W, in[i]->d(), W * 8, hipMemcpyDeviceToDevice, C.stream));
+    };
+    const bool use_graph = C.graphs && !C.prof.on;
+    auto it = K.plans.find(key);
+    if (!use_graph || (it == K.plans.end() && !K.warm.count(key))) {
+        DCt X = ct_new(C, key.level, B);
+        fill(X);
+        std::vector<DCt> outs = circuit(X);
+        K.warm.insert(key);
+        return outs;
+    }
+    if (it == K.plans.end()) {
+        auto plan = std::make_unique<GraphPlan>();
+        plan->C = &C;
+        plan->in = ct_new(C, key.level, B);
+        HIPCHK(hipStreamSynchronize(C.stream));
+        HIPCHK(hipStreamBeginCapture(C.stream, hipStreamCaptureModeRelaxed));
+        C.pool.begin_capture();
+        try {
+            plan->outs = circuit(plan->in);
+        } catch (...) {
+            plan->owned = C.pool.end_capture();
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(C.stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        plan->owned = C.pool.end_capture();
+        HIPCHK(hipStreamEndCapture(C.stream, &plan->graph));
+        HIPCHK(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
+        it = K.plans.emplace(key, std::move(plan)).first;
+    }
+    GraphPlan &pl = *it->second;
+    fill(pl.in);
+    HIPCHK(hipGraphLaunch(pl.exec, C.stream));
+    std::vector<DCt> outs;
+    for (const DCt &o : pl.outs) outs.push_back(slice(C, o, 0, o.B));
+    return outs;
+}
+
+enum CircuitKind { kRankCircuit = 1, kArgminCircuit = 2, kSortCircuit = 3 };
+
+static std::vector<DCt> run_kind(Ctx &C, Keys &K, int kind, int N, ckr_sign cmp, ckr_sign ind,
+                                 const std::vector<const DCt *> &in) {
+    if (in.empty()) throw Error{CKR_E_INVALID, "empty batch"};
+    const int level = in[0]->level;
+    for (auto *c : in)
+        if (c->level != level || c->B != 1) throw Error{CKR_E_INVALID, "batch entries must be single ciphertexts of one level"};
+    PlanKey key{kind, N, level, (int)in.size(), cmp.d_g, cmp.d_f, ind.d_g, ind.d_f};
+    Circuit f;
+    if (kind == kRankCircuit) f = [&](const DCt &X) { std::vector<DCt> o; o.push_back(rank(C, K, X, N, cmp)); return o; };
+    else if (kind == kSortCircuit) f = [&](const DCt &X) { std::vector<DCt> o; o.push_back(sort(C, K, X, N, cmp, ind)); return o; };
+    else if (kind == kArgminCircuit)
+        f = [&](const DCt &X) {
+            std::vector<DCt> o(2);
+            argmin(C, K, X, N, cmp, ind, o[0], o[1]);
+            return o;
+        };
+    else throw Error{CKR_E_INVALID, "unknown circuit"};
+    return run_circuit(C, K, key, in, f);
+}
+
 }  // namespace ckr
 
 // ========================================================================
@@ -930,8 +1100,13 @@ ckr_status ckr_context_create(const ckr_params *p, int dev, size_t budget, ckr_c
         C.P = make_params((int)p->log_n, (int)p->n_q, (int)p->q0_bits, (int)p->log_scale, (int)p->n_p,
                           (int)p->p_bits, (int)p->dnum);
         if (C.P.alpha > kMaxBConvSrc || C.P.K > kMaxBConvSrc) throw Error{CKR_E_INVALID, "digit too large"};
+        if (C.P.dnum > 8) throw Error{CKR_E_INVALID, "at most 8 key-switching digits"};
+        if (C.P.nmod() > kMaxLimbArgs) throw Error{CKR_E_INVALID, "too many primes"};
         C.pool.budget = budget;
         setup_tables(C);
+        // a stream of the context's own (default priority): graph capture needs a non-null stream
+        HIPCHK(hipStreamCreate(&C.own_stream));
+        C.stream = C.own_stream;
         *out = ctx.release();
     });
 }
@@ -1335,27 +1510,35 @@ ckr_status ckr_rank(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uin
     });
 }
 
-ckr_status ckr_rank_batch(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *const *v, size_t count, uint32_t N,
-                          ckr_sign cmp, ckr_ct **out) {
+// outputs of batch entry i: out[i] (rank, sort) or out[2i], out[2i+1] (argmin one-hot, value)
+ckr_status ckr_run_batch(ckr_context *ctx, const ckr_keys *keys, int kind, uint32_t N, ckr_sign cmp, ckr_sign ind,
+                         const ckr_ct *const *v, size_t count, ckr_ct **out) {
     return guard([&] {
         NEED(ctx && keys && v && out && count);
         Ctx &C = *ctx->C;
-        const int level = v[0]->ct.level;
+        std::vector<const DCt *> in;
         for (size_t i = 0; i < count; i++) {
             NEED(v[i]);
-            if (v[i]->ct.level != level || v[i]->ct.B != 1) throw Error{CKR_E_INVALID, "batch entries must share level"};
+            in.push_back(&v[i]->ct);
         }
-        const size_t W = (size_t)2 * (level + 1) * C.n();
-        DCt X = ct_new(C, level, (int)count);
+        std::vector<DCt> outs = run_kind(C, *keys->K, kind, (int)N, cmp, ind, in);
+        const size_t per = outs.size();
+        std::vector<ckr_ct *> made;
         for (size_t i = 0; i < count; i++)
-            HIPCHK(hipMemcpyAsync(X.d() + i * W, v[i]->ct.d(), W * 8, hipMemcpyDeviceToDevice, C.stream));
-        DCt R = rank(C, *keys->K, X, (int)N, cmp);
-        const size_t Wr = (size_t)2 * (R.level + 1) * C.n();
-        for (size_t i = 0; i < count; i++) {
-            DCt o = ct_new(C, R.level, 1);
-            HIPCHK(hipMemcpyAsync(o.d(), R.d() + i * Wr, Wr * 8, hipMemcpyDeviceToDevice, C.stream));
-            out[i] = wrap(C, std::move(o));
-        }
+            for (size_t k = 0; k < per; k++) made.push_back(wrap(C, slice(C, outs[k], (int)i, 1)));
+        for (size_t i = 0; i < made.size(); i++) out[i] = made[i];
+    });
+}
+
+ckr_status ckr_rank_batch(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *const *v, size_t count, uint32_t N,
+                          ckr_sign cmp, ckr_ct **out) {
+    return ckr_run_batch(ctx, keys, kRankCircuit, N, cmp, ckr_sign{0, 0}, v, count, out);
+}
+
+ckr_status ckr_context_set_graphs(ckr_context *ctx, int enable) {
+    return guard([&] {
+        NEED(ctx);
+        ctx->C->graphs = enable != 0;
     });
 }
 

@@ -54,6 +54,27 @@ void k_ntt(const DevTables &T, const LimbBatch &b, bool inverse, hipStream_t s);
 // one pass of the two-pass transform: pass 0 runs first (columns forward, rows inverse)
 void k_ntt_pass(const DevTables &T, const LimbBatch &b, bool inverse, int pass, hipStream_t s);
 
+// optional fused prologue / epilogue of the forward transform.
+// prologue (first pass): limb t of poly p is read from src + p*src_stride (one
+//   limb per poly) and reduced modulo the limb's own prime.
+// epilogue (last pass): instead of storing y, poly p = 2b + k stores
+//   out = (x - y) * c[t] (+ add when bit k of add_mask is set), where each of
+//   out, x, add addresses poly p at base + b*stride + k*off.
+struct NttFuse {
+    bool pro = false, epi = false;
+    const u64 *src = nullptr;
+    size_t src_stride = 0;
+    u64 *out = nullptr;
+    size_t out_stride = 0, out_off = 0;
+    const u64 *x = nullptr;
+    size_t x_stride = 0, x_off = 0;
+    const u64 *add = nullptr;
+    size_t add_stride = 0, add_off = 0;
+    int add_mask = 0;
+    LimbScalars c;
+};
+void k_ntt_fused(const DevTables &T, const LimbBatch &b, const NttFuse &f, int pass, hipStream_t s);
+
 // out = a + b, a - b (mod q) over a batch of limbs (same geometry for all three)
 void k_add(const DevTables &T, u64 *out, const u64 *a, const u64 *b, int limbs, int polys, size_t stride_o,
            size_t stride_a, size_t stride_b, LimbMap map, bool sub, hipStream_t s);
@@ -103,13 +124,6 @@ struct IPArgs {
 };
 void k_ip(const DevTables &T, const IPArgs &a, hipStream_t s);
 
-// out[p][i] = (x[p][i] - y[p][i]) * c[i]  (+ add[p][i] when add != nullptr)
-void k_sub_mul(const DevTables &T, u64 *out, const u64 *x, const u64 *y, const u64 *add, int limbs, int polys,
-               size_t stride_o, size_t stride_x, size_t stride_y, size_t stride_add, const LimbScalars &c,
-               hipStream_t s);
-// out[p][i] = src[p] mod q_i for i < limbs (src: one limb per poly, values < 2^50)
-void k_bcast_mod(const DevTables &T, u64 *out, const u64 *src, int limbs, int polys, size_t stride_o,
-                 size_t stride_src, hipStream_t s);
 // reduce arbitrary uint64 values to canonical residues (import check helper):
 // flags[0] set to 1 if any value >= its modulus
 void k_check_range(const DevTables &T, const u64 *data, int limbs, int polys, size_t stride, int *flag, hipStream_t s);

@@ -178,3 +178,22 @@ def test_rank8_batch_equals_single(p12):
     outs = p12.ctx.rank_batch(p12.gkeys, cts, N, cmp)
     for s, b in zip(singles, outs):
         assert np.array_equal(s, b.export())
+
+
+def test_rank8_graph_replays_equal_eager(p12):
+    """Batched rank through hipGraph capture: call 1 runs eagerly, call 2 captures
+    and replays, calls 3-4 replay; eager single calls run in between.  Every
+    replay must equal the eager single-query results."""
+    N, cmp = 8, W.RANK_CMP[8]
+    cts, singles = [], []
+    for seed in range(4):
+        v, _, eseed = W.rank_workload(N, 0.01, 40 + seed)
+        g = p12.ctx.encrypt(p12.gkeys, v, p12.P.L, eseed)
+        cts.append(g)
+        singles.append(p12.ctx.rank(p12.gkeys, g, N, cmp).export())
+    for rep in range(4):
+        outs = p12.ctx.run_batch(p12.gkeys, "rank", cts, N, cmp)
+        for s, b in zip(singles, outs):
+            assert np.array_equal(s, b.export()), f"replay {rep}"
+        # eager work between replays
+        p12.ctx.rank(p12.gkeys, cts[rep], N, cmp)
