@@ -86,6 +86,12 @@ def main():
     def step():
         return ctx.run_batch(keys, "rank", cts, N, cmp)
 
+    # NTT tile autotuning on a dispatch of the size the circuit issues
+    tune_limbs = min(2 * B * (level + 1), 1152)
+    table = ctx.autotune(tune_limbs, 3)
+    chosen = [[int(np.argmin(table[i][p])) for p in range(2)] for i in range(2)]
+    log(f"[bench] autotune ({tune_limbs} limbs): variants fwd {chosen[0]} inv {chosen[1]}")
+
     # a plain device copy of known size: the reference for HBM byte counters
     calib = hip.DeviceArray(np.zeros(COPY_BYTES // 8, np.uint64))
     calib2 = hip.DeviceArray(np.zeros(COPY_BYTES // 8, np.uint64))
@@ -154,7 +160,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "rank N=128 at n=2^16 (q0 50-bit + 23 rescale primes near 2^40, 7 special 50-bit "
                                "primes, dnum=3, scale 2^40), encrypted at level 17, comparator g^4 then f",
-                   "batch": B, "ranks_exact": bool(exact)},
+                   "batch": B, "ranks_exact": bool(exact), "graphs": True,
+                   "ntt_variants": {"fwd": chosen[0], "inv": chosen[1]}},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
                        "per": "step of " + str(B) + " queries"},
         "ntt_GBps": round(ntt_bytes / (ntt_ms * 1e-3) / 1e9, 1) if ntt_ms > 0 else 0.0,

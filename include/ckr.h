@@ -210,6 +210,15 @@ ckr_status ckr_profile_reset(ckr_context *ctx);
 ckr_status ckr_profile_read(ckr_context *ctx, int category, uint64_t *launches, double *total_ms, double *bytes);
 const char *ckr_profile_name(int category);
 
+/* NTT autotuner: times each compiled tile variant (elements per thread x
+ * columns per workgroup) of every (direction, pass) on `limbs` limbs, `iters`
+ * repetitions, and keeps the fastest for this context.  ms, if not NULL,
+ * receives the 2 x 2 x 4 average milliseconds [inverse][pass][variant].
+ * Every variant computes the same transform bit for bit. */
+ckr_status ckr_autotune(ckr_context *ctx, uint32_t limbs, uint32_t iters, float *ms);
+/* Force one tile variant (0..3) for a (direction, pass). */
+ckr_status ckr_ntt_variant(ckr_context *ctx, int inverse, int pass, int variant);
+
 /* Wait for all work issued on the context stream. */
 ckr_status ckr_synchronize(ckr_context *ctx);
 

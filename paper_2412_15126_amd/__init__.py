@@ -85,6 +85,8 @@ _SIGS = {
     "ckr_synchronize": (C.c_int, [vp]),
     "ckr_run_batch": (C.c_int, [vp, vp, C.c_int, C.c_uint32, Sign, Sign, C.POINTER(vp), C.c_size_t, C.POINTER(vp)]),
     "ckr_context_set_graphs": (C.c_int, [vp, C.c_int]),
+    "ckr_autotune": (C.c_int, [vp, C.c_uint32, C.c_uint32, C.POINTER(C.c_float)]),
+    "ckr_ntt_variant": (C.c_int, [vp, C.c_int, C.c_int, C.c_int]),
 }
 
 _lib = None
@@ -221,6 +223,15 @@ class Context:
         h = vp()
         _ok(lib().ckr_sort(self.h, keys.h, ct.h, N, sign(cmp), sign(ind), C.byref(h)))
         return Ct(self, h)
+
+    def autotune(self, limbs, iters=5):
+        """Pick the fastest NTT tile per (direction, pass); returns the timing table [inv][pass][variant] in ms."""
+        ms = (C.c_float * 16)()
+        _ok(lib().ckr_autotune(self.h, limbs, iters, ms))
+        return np.array(ms[:], dtype=np.float64).reshape(2, 2, 4)
+
+    def ntt_variant(self, inverse, pass_, variant):
+        _ok(lib().ckr_ntt_variant(self.h, int(inverse), int(pass_), int(variant)))
 
     def set_graphs(self, on):
         _ok(lib().ckr_context_set_graphs(self.h, int(on)))

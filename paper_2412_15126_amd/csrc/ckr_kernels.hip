@@ -241,46 +241,67 @@ static void launch_pass(const DevTables &T, const LimbBatch &b, hipStream_t s, c
                            b.limbs, b.map, logn, T.mq, tw, T.tw_last, NttFuse{});
 }
 
-template <int L1, int E1, int C1, int L2, int E2, int C2>
-static void ntt_one_pass(const DevTables &T, const LimbBatch &b, bool inverse, int pass, hipStream_t s,
-                         const NttFuse *f = nullptr) {
-    if (!inverse) {
-        if (pass == 0) launch_pass<L1, E1, C1, true, false>(T, b, s, f);
-        else launch_pass<L2, E2, C2, false, false>(T, b, s, f);
+// tile variants: (elements per thread 2^LOGE, columns per workgroup C)
+//   passes of 2^8 and 2^9 points: 0 (16, 16), 1 (16, 8), 2 (8, 16), 3 (16, 32) / (8, 8)
+//   smaller passes: one fixed tile
+template <int LOGS, bool COLPASS, bool INV>
+static void pass_variant(const DevTables &T, const LimbBatch &b, hipStream_t s, const NttFuse *f, int v) {
+    if constexpr (LOGS == 8 || LOGS == 9) {
+        switch (v) {
+        case 1: launch_pass<LOGS, 4, 8, COLPASS, INV>(T, b, s, f); return;
+        case 2: launch_pass<LOGS, 3, 16, COLPASS, INV>(T, b, s, f); return;
+        case 3: launch_pass<LOGS, (LOGS == 8 ? 4 : 3), (LOGS == 8 ? 32 : 8), COLPASS, INV>(T, b, s, f); return;
+        default: launch_pass<LOGS, 4, 16, COLPASS, INV>(T, b, s, f); return;
+        }
+    } else if constexpr (LOGS == 7) {
+        launch_pass<7, 4, 16, COLPASS, INV>(T, b, s, f);
+    } else if constexpr (LOGS == 6) {
+        launch_pass<6, 3, 16, COLPASS, INV>(T, b, s, f);
     } else {
-        if (pass == 0) launch_pass<L2, E2, C2, false, true>(T, b, s);
-        else launch_pass<L1, E1, C1, true, true>(T, b, s);
+        launch_pass<5, 4, (COLPASS ? 16 : 32), COLPASS, INV>(T, b, s, f);
+    }
+}
+
+// pass 0 runs first: the column pass (log n1 = ceil(logn/2) points) forward,
+// the row pass (floor(logn/2) points) inverse
+template <int L1, int L2>
+static void pass_dispatch(const DevTables &T, const LimbBatch &b, bool inv, int pass, hipStream_t s, const NttFuse *f,
+                          int v) {
+    if (!inv) {
+        if (pass == 0) pass_variant<L1, true, false>(T, b, s, f, v);
+        else pass_variant<L2, false, false>(T, b, s, f, v);
+    } else {
+        if (pass == 0) pass_variant<L2, false, true>(T, b, s, f, v);
+        else pass_variant<L1, true, true>(T, b, s, f, v);
+    }
+}
+
+static void run_pass(const DevTables &T, const LimbBatch &b, bool inv, int pass, hipStream_t s, const NttFuse *f,
+                     int v) {
+    if (b.limbs * b.polys == 0) return;
+    switch (T.logn) {
+    case 10: pass_dispatch<5, 5>(T, b, inv, pass, s, f, v); break;
+    case 11: pass_dispatch<6, 5>(T, b, inv, pass, s, f, v); break;
+    case 12: pass_dispatch<6, 6>(T, b, inv, pass, s, f, v); break;
+    case 13: pass_dispatch<7, 6>(T, b, inv, pass, s, f, v); break;
+    case 14: pass_dispatch<7, 7>(T, b, inv, pass, s, f, v); break;
+    case 15: pass_dispatch<8, 7>(T, b, inv, pass, s, f, v); break;
+    case 16: pass_dispatch<8, 8>(T, b, inv, pass, s, f, v); break;
+    case 17: pass_dispatch<9, 8>(T, b, inv, pass, s, f, v); break;
+    default: break;
     }
 }
 
 void k_ntt_pass(const DevTables &T, const LimbBatch &b, bool inverse, int pass, hipStream_t s) {
-    if (b.limbs * b.polys == 0) return;
-    switch (T.logn) {
-    case 10: ntt_one_pass<5, 4, 16, 5, 4, 32>(T, b, inverse, pass, s); break;
-    case 11: ntt_one_pass<6, 3, 16, 5, 4, 32>(T, b, inverse, pass, s); break;
-    case 12: ntt_one_pass<6, 3, 16, 6, 3, 16>(T, b, inverse, pass, s); break;
-    case 13: ntt_one_pass<7, 4, 16, 6, 3, 16>(T, b, inverse, pass, s); break;
-    case 14: ntt_one_pass<7, 4, 16, 7, 4, 16>(T, b, inverse, pass, s); break;
-    case 15: ntt_one_pass<8, 4, 16, 7, 4, 16>(T, b, inverse, pass, s); break;
-    case 16: ntt_one_pass<8, 4, 16, 8, 4, 16>(T, b, inverse, pass, s); break;
-    case 17: ntt_one_pass<9, 4, 16, 8, 4, 16>(T, b, inverse, pass, s); break;
-    default: break;
-    }
+    run_pass(T, b, inverse, pass, s, nullptr, T.ntt_variant[inverse][pass]);
+}
+
+void k_ntt_pass_variant(const DevTables &T, const LimbBatch &b, bool inverse, int pass, int variant, hipStream_t s) {
+    run_pass(T, b, inverse, pass, s, nullptr, variant);
 }
 
 void k_ntt_fused(const DevTables &T, const LimbBatch &b, const NttFuse &f, int pass, hipStream_t s) {
-    if (b.limbs * b.polys == 0) return;
-    switch (T.logn) {
-    case 10: ntt_one_pass<5, 4, 16, 5, 4, 32>(T, b, false, pass, s, &f); break;
-    case 11: ntt_one_pass<6, 3, 16, 5, 4, 32>(T, b, false, pass, s, &f); break;
-    case 12: ntt_one_pass<6, 3, 16, 6, 3, 16>(T, b, false, pass, s, &f); break;
-    case 13: ntt_one_pass<7, 4, 16, 6, 3, 16>(T, b, false, pass, s, &f); break;
-    case 14: ntt_one_pass<7, 4, 16, 7, 4, 16>(T, b, false, pass, s, &f); break;
-    case 15: ntt_one_pass<8, 4, 16, 7, 4, 16>(T, b, false, pass, s, &f); break;
-    case 16: ntt_one_pass<8, 4, 16, 8, 4, 16>(T, b, false, pass, s, &f); break;
-    case 17: ntt_one_pass<9, 4, 16, 8, 4, 16>(T, b, false, pass, s, &f); break;
-    default: break;
-    }
+    run_pass(T, b, false, pass, s, &f, T.ntt_variant[0][pass]);
 }
 
 void k_ntt(const DevTables &T, const LimbBatch &b, bool inverse, hipStream_t s) {

@@ -1660,6 +1660,60 @@ ckr_status ckr_profile_read(ckr_context *ctx, int category, uint64_t *launches, 
 
 const char *ckr_profile_name(int category) { return category >= 0 && category < kNCat ? kCatName[category] : nullptr; }
 
+// Time every NTT tile variant on `limbs` limbs of zeros (timing does not depend
+// on the values) and keep the fastest per (direction, pass).  ms receives
+// [inverse][pass][variant] averages (2*2*kNttVariants floats) when not NULL.
+ckr_status ckr_autotune(ckr_context *ctx, uint32_t limbs, uint32_t iters, float *ms) {
+    return guard([&] {
+        NEED(ctx);
+        Ctx &C = *ctx->C;
+        if (limbs == 0 || limbs > (u32)C.P.nmod() * 64) throw Error{CKR_E_INVALID, "limbs"};
+        iters = std::max(1u, iters);
+        const size_t n = C.n();
+        Buf buf(&C, (size_t)limbs * n);
+        HIPCHK(hipMemsetAsync(buf.get(), 0, (size_t)limbs * n * 8, C.stream));
+        // limbs cycle through the q chain
+        const int nq = C.P.nq;
+        std::vector<hipEvent_t> ev(2);
+        for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+        for (int inv = 0; inv < 2; inv++)
+            for (int pass = 0; pass < 2; pass++) {
+                float best = 1e30f;
+                int bestv = 0;
+                for (int v = 0; v < kNttVariants; v++) {
+                    auto launch = [&] {
+                        for (u32 off = 0; off < limbs; off += (u32)nq) {
+                            const int cnt = (int)std::min<u32>((u32)nq, limbs - off);
+                            LimbBatch b{buf.get() + (size_t)off * n, cnt, 1, 0, plain_map()};
+                            k_ntt_pass_variant(C.T, b, inv != 0, pass, v, C.stream);
+                        }
+                    };
+                    launch();  // warm
+                    HIPCHK(hipEventRecord(ev[0], C.stream));
+                    for (u32 it = 0; it < iters; it++) launch();
+                    HIPCHK(hipEventRecord(ev[1], C.stream));
+                    HIPCHK(hipEventSynchronize(ev[1]));
+                    float t = 0;
+                    HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
+                    t /= (float)iters;
+                    if (ms) ms[(inv * 2 + pass) * kNttVariants + v] = t;
+                    if (t < best) best = t, bestv = v;
+                }
+                C.T.ntt_variant[inv][pass] = bestv;
+            }
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    });
+}
+
+ckr_status ckr_ntt_variant(ckr_context *ctx, int inverse, int pass, int variant) {
+    return guard([&] {
+        NEED(ctx);
+        if (inverse < 0 || inverse > 1 || pass < 0 || pass > 1 || variant < 0 || variant >= kNttVariants)
+            throw Error{CKR_E_INVALID, "variant"};
+        ctx->C->T.ntt_variant[inverse][pass] = variant;
+    });
+}
+
 ckr_status ckr_synchronize(ckr_context *ctx) {
     return guard([&] {
         NEED(ctx);

@@ -37,7 +37,9 @@ struct DevTables {
     double2 *tw_fwd;  // [nmod][n] {w, w/q}, w = psi^{brev(i)}
     double2 *tw_inv;  // [nmod][n] {w, w/q}, w = psi^{-brev(i)}
     double2 *tw_last; // [nmod][2]: {n^-1, n^-1/q}, {psi^{-brev(1)} n^-1, ./q}
+    int ntt_variant[2][2] = {{0, 0}, {0, 0}};  // [inverse][pass]: tile variant chosen by the autotuner
 };
+constexpr int kNttVariants = 4;
 
 // description of a batch of limbs: `polys` groups of `limbs` limbs, group p
 // starting at base + p * poly_stride, limbs n words apart
@@ -53,6 +55,8 @@ struct LimbBatch {
 void k_ntt(const DevTables &T, const LimbBatch &b, bool inverse, hipStream_t s);
 // one pass of the two-pass transform: pass 0 runs first (columns forward, rows inverse)
 void k_ntt_pass(const DevTables &T, const LimbBatch &b, bool inverse, int pass, hipStream_t s);
+// the same pass with an explicit tile variant (autotuning); variant < kNttVariants
+void k_ntt_pass_variant(const DevTables &T, const LimbBatch &b, bool inverse, int pass, int variant, hipStream_t s);
 
 // optional fused prologue / epilogue of the forward transform.
 // prologue (first pass): limb t of poly p is read from src + p*src_stride (one

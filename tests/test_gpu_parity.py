@@ -197,3 +197,32 @@ def test_rank8_graph_replays_equal_eager(p12):
             assert np.array_equal(s, b.export()), f"replay {rep}"
         # eager work between replays
         p12.ctx.rank(p12.gkeys, cts[rep], N, cmp)
+
+
+@pytest.mark.parametrize("name", ["T10", "P12", "P16", "P17"])
+def test_ntt_tile_variants_bit_identical(ckr, name):
+    """Every NTT tile variant the autotuner may pick computes the same transform."""
+    from paper_2412_15126_amd import hip
+    ps = W.PSETS[name]
+    ctx = ckr.Context(ps)
+    n, nm = 1 << ps["logn"], len(ctx.moduli)
+    limbs = min(nm, 6)
+    rng = np.random.default_rng(1)
+    host = np.stack([rng.integers(0, int(q), n, dtype=np.uint64) for q in ctx.moduli[:limbs]])
+    ref = None
+    for v in range(4):
+        for inv in (0, 1):
+            for ps_ in (0, 1):
+                ctx.ntt_variant(inv, ps_, v)
+        dev = hip.DeviceArray(host)
+        ctx.ntt_device(dev.ptr.value, limbs, 0, False)
+        hip.synchronize()
+        fwd = dev.numpy()
+        ctx.ntt_device(dev.ptr.value, limbs, 0, True)
+        hip.synchronize()
+        assert np.array_equal(dev.numpy(), host), f"variant {v} roundtrip"
+        if ref is None:
+            ref = fwd
+        assert np.array_equal(fwd, ref), f"variant {v} forward differs"
+    table = ctx.autotune(limbs * 4, 2)
+    assert table.shape == (2, 2, 4) and np.all(table > 0)
