@@ -170,6 +170,34 @@ ckr_status ckr_rank_batch(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *
 /* Enable (default) or disable hipGraph capture of batched circuits. */
 ckr_status ckr_context_set_graphs(ckr_context *ctx, int enable);
 
+/* Serving.  A server owns one worker thread per context it routes to; each
+ * worker repeatedly takes the oldest pending request of its context plus up
+ * to max_batch pending requests of the same circuit, N and level, admits them
+ * against hbm_budget (bytes of circuit working set in flight; 0 = unbounded;
+ * each route's per-query working set is measured on its first batch, which
+ * runs alone), runs them as one batched circuit (graph-captured after the
+ * first call of a shape) and completes their tickets.  Requests arriving
+ * while a batch runs join the next batch; routes on different contexts run
+ * on different streams and overlap on the device.  A request whose working
+ * set alone exceeds the budget fails with CKR_E_NOMEM.  Results are the same
+ * bits as single calls.  The ciphertext passed to submit must stay alive
+ * until its ticket completes.  API calls on a context are serialised with
+ * its worker by a per-context lock. */
+typedef struct ckr_server ckr_server;
+ckr_status ckr_server_create(size_t hbm_budget, uint32_t max_batch, ckr_server **out);
+/* kind 1 rank, 2 argmin, 3 sort; all routes are added before the first submit */
+ckr_status ckr_server_add_route(ckr_server *srv, int kind, uint32_t N, ckr_context *ctx, const ckr_keys *keys,
+                                ckr_sign cmp, ckr_sign ind);
+ckr_status ckr_server_submit(ckr_server *srv, int kind, uint32_t N, const ckr_ct *v, uint64_t *ticket);
+/* timeout_ms < 0 waits forever; CKR_E_BUSY on timeout.  outs receives 1
+ * (rank, sort) or 2 (argmin) ciphertexts; latency_ms (3 values, may be NULL):
+ * submit-to-done, submit-to-start, batch size. */
+ckr_status ckr_server_wait(ckr_server *srv, uint64_t ticket, int timeout_ms, ckr_ct **outs, size_t n_outs,
+                           double *latency_ms);
+/* stats: completed requests, batches run, high-water bytes in flight, pending requests */
+ckr_status ckr_server_stats(ckr_server *srv, double *stats);
+void ckr_server_free(ckr_server *srv);
+
 /* Ciphertext access.  export: words = 2*(level+1)*n uint64 (layout above). */
 uint32_t ckr_ct_level(const ckr_ct *ct);
 double ckr_ct_scale(const ckr_ct *ct);

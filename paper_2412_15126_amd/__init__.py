@@ -86,6 +86,12 @@ _SIGS = {
     "ckr_run_batch": (C.c_int, [vp, vp, C.c_int, C.c_uint32, Sign, Sign, C.POINTER(vp), C.c_size_t, C.POINTER(vp)]),
     "ckr_context_set_graphs": (C.c_int, [vp, C.c_int]),
     "ckr_autotune": (C.c_int, [vp, C.c_uint32, C.c_uint32, C.POINTER(C.c_float)]),
+    "ckr_server_create": (C.c_int, [C.c_size_t, C.c_uint32, C.POINTER(vp)]),
+    "ckr_server_add_route": (C.c_int, [vp, C.c_int, C.c_uint32, vp, vp, Sign, Sign]),
+    "ckr_server_submit": (C.c_int, [vp, C.c_int, C.c_uint32, vp, C.POINTER(C.c_uint64)]),
+    "ckr_server_wait": (C.c_int, [vp, C.c_uint64, C.c_int, C.POINTER(vp), C.c_size_t, C.POINTER(C.c_double)]),
+    "ckr_server_stats": (C.c_int, [vp, C.POINTER(C.c_double)]),
+    "ckr_server_free": (None, [vp]),
     "ckr_ntt_variant": (C.c_int, [vp, C.c_int, C.c_int, C.c_int]),
 }
 
@@ -340,3 +346,58 @@ class Ct:
         if getattr(self, "h", None) and getattr(self.ctx, "h", None):
             lib().ckr_ct_free(self.h)
             self.h = None
+
+
+KINDS = {"rank": 1, "argmin": 2, "sort": 3}
+
+
+class Server:
+    """Continuous-batching request server over one or more contexts (ckr_server_*)."""
+
+    def __init__(self, hbm_budget=0, max_batch=8):
+        h = vp()
+        _ok(lib().ckr_server_create(hbm_budget, max_batch, C.byref(h)))
+        self.h = h
+        self.ctx_of = {}
+        self._alive = {}
+
+    def add_route(self, kind, N, ctx, keys, cmp, ind=(0, 0)):
+        _ok(lib().ckr_server_add_route(self.h, KINDS[kind], N, ctx.h, keys.h, sign(cmp), sign(ind)))
+        self.ctx_of[(kind, N)] = ctx
+
+    def submit(self, kind, N, ct):
+        t = C.c_uint64()
+        _ok(lib().ckr_server_submit(self.h, KINDS[kind], N, ct.h, C.byref(t)))
+        self._alive[t.value] = ct          # the input must outlive the request
+        self._kind = getattr(self, "_kind", {})
+        self._kind[t.value] = (kind, N)
+        return t.value
+
+    def wait(self, ticket, timeout_ms=-1):
+        """(outputs, (latency_ms, queue_ms, batch))"""
+        kind, N = self._kind[ticket]
+        per = 2 if kind == "argmin" else 1
+        outs = (vp * per)()
+        lat = (C.c_double * 3)()
+        st = lib().ckr_server_wait(self.h, ticket, timeout_ms, outs, per, lat)
+        if st == -6:
+            raise TimeoutError("ticket not finished")
+        self._alive.pop(ticket, None)
+        self._kind.pop(ticket, None)
+        _ok(st)
+        ctx = self.ctx_of[(kind, N)]
+        return [Ct(ctx, vp(o)) for o in outs], (lat[0], lat[1], int(lat[2]))
+
+    def stats(self):
+        st = (C.c_double * 4)()
+        _ok(lib().ckr_server_stats(self.h, st))
+        return {"completed": int(st[0]), "batches": int(st[1]), "inflight_high_bytes": int(st[2]),
+                "pending": int(st[3])}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ckr_server_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

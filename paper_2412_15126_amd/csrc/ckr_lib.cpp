@@ -16,6 +16,10 @@
 #include <tuple>
 #include <unordered_map>
 #include <unordered_set>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <thread>
 #include <set>
 #include <functional>
 #include <vector>
@@ -26,6 +30,7 @@
 
 namespace ckr {
 
+#define HIPCHK_NOTHROW(x) (void)(x)
 #define HIPCHK(x)                                                                               \
     do {                                                                                        \
         hipError_t e_ = (x);                                                                    \
@@ -64,10 +69,12 @@ class Pool {
         return owned;
     }
     void release_owned(const std::vector<std::pair<void *, size_t>> &owned) {
+        std::lock_guard<std::recursive_mutex> g(pmu_);
         for (auto &b : owned) cache_[b.second].push_back(b.first);
     }
 
     void *get(size_t bytes) {
+        std::lock_guard<std::recursive_mutex> g(pmu_);
         bytes = round(bytes);
         if (capturing_) {
             auto cf = cap_free_.find(bytes);
@@ -115,6 +122,7 @@ class Pool {
     }
     void put(void *p, size_t bytes) {
         if (!p) return;
+        std::lock_guard<std::recursive_mutex> g(pmu_);
         bytes = round(bytes);
         in_use -= bytes;
         if (capturing_ && cap_set_.count(p)) cap_free_[bytes].push_back(p);
@@ -123,6 +131,7 @@ class Pool {
     // return cached blocks to the allocator (stream-ordered frees are safe
     // because the caller synchronises first)
     void trim() {
+        std::lock_guard<std::recursive_mutex> g(pmu_);
         for (auto &kv : cache_) {
             for (void *p : kv.second) {
                 if (ufree) ufree(p, user);
@@ -135,6 +144,7 @@ class Pool {
     ~Pool() { trim(); }
 
   private:
+    std::recursive_mutex pmu_;
     std::unordered_map<size_t, std::vector<void *>> cache_;
     bool capturing_ = false;
     std::unordered_set<void *> cap_set_;
@@ -217,6 +227,7 @@ struct Ctx {
     std::map<int, BConvTab> moddown;                // level
     std::map<PlainKey, Buf> plain;                  // encoded plaintexts, eval domain
     std::mutex mu;
+    std::recursive_mutex mu_run;  // held while enqueueing work: API calls vs. server workers
     size_t n() const { return P.n; }
 
     void *table_alloc(size_t bytes) {
@@ -1038,6 +1049,243 @@ static std::vector<DCt> run_kind(Ctx &C, Keys &K, int kind, int N, ckr_sign cmp,
     return run_circuit(C, K, key, in, f);
 }
 
+// ------------------------------------------------------------------------
+// serving: continuous batching over a request queue with HBM admission
+// ------------------------------------------------------------------------
+static double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Route {
+    int kind, N;
+    Ctx *C;
+    Keys *K;
+    ckr_sign cmp, ind;
+    size_t bytes_per_query = 0;  // measured on the route's first batch
+};
+
+struct Request {
+    u64 ticket;
+    int route;
+    const DCt *in;  // caller-owned, alive until the ticket completes
+    double t_submit = 0, t_start = 0, t_done = 0;
+    std::vector<DCt> outs;
+    int status = CKR_OK;
+    std::string err;
+    bool done = false;
+    int batch = 0;
+};
+
+class Server {
+  public:
+    Server(size_t budget, int max_batch) : budget_(budget), max_batch_(std::max(1, max_batch)) {}
+    ~Server() { stop(); }
+
+    int add_route(const Route &r) {
+        std::lock_guard<std::mutex> g(mu_);
+        if (started_) throw Error{CKR_E_BUSY, "routes must be added before the first submit"};
+        routes_.push_back(r);
+        return (int)routes_.size() - 1;
+    }
+
+    u64 submit(int kind, int N, const DCt &v) {
+        std::lock_guard<std::mutex> g(mu_);
+        int route = -1;
+        for (size_t i = 0; i < routes_.size(); i++)
+            if (routes_[i].kind == kind && routes_[i].N == N) route = (int)i;
+        if (route < 0) throw Error{CKR_E_INVALID, "no route for this circuit and N"};
+        if (v.B != 1) throw Error{CKR_E_INVALID, "submit one ciphertext"};
+        auto rq = std::make_unique<Request>();
+        rq->route = route;
+        rq->in = &v;
+        rq->t_submit = now_ms();
+        start_locked();
+        const u64 t = ++next_ticket_;
+        rq->ticket = t;
+        pending_.push_back(t);
+        reqs_[t] = std::move(rq);
+        cv_.notify_all();
+        return t;
+    }
+
+    // waits for the ticket; moves its outputs out and forgets it
+    int wait(u64 ticket, int timeout_ms, std::vector<DCt> &outs, double *lat_ms, std::string &err, Ctx **ctx) {
+        std::unique_lock<std::mutex> lk(mu_);
+        auto it = reqs_.find(ticket);
+        if (it == reqs_.end()) throw Error{CKR_E_INVALID, "unknown ticket"};
+        Request *r = it->second.get();
+        auto ready = [&] { return r->done; };
+        if (timeout_ms < 0) cv_.wait(lk, ready);
+        else if (!cv_.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready)) return CKR_E_BUSY;
+        if (lat_ms) {
+            lat_ms[0] = r->t_done - r->t_submit;
+            lat_ms[1] = r->t_start - r->t_submit;
+            lat_ms[2] = (double)r->batch;
+        }
+        const int st = r->status;
+        err = r->err;
+        outs = std::move(r->outs);
+        *ctx = routes_[r->route].C;
+        std::unique_ptr<Request> keep = std::move(it->second);
+        reqs_.erase(it);
+        lk.unlock();
+        return st;
+    }
+
+    void stats(double *out) {
+        std::lock_guard<std::mutex> g(mu_);
+        out[0] = (double)completed_;
+        out[1] = (double)batches_;
+        out[2] = (double)inflight_high_;
+        out[3] = (double)pending_.size();
+    }
+
+    void stop() {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stop_ = true;
+            cv_.notify_all();
+        }
+        for (auto &t : workers_) t.join();
+        workers_.clear();
+    }
+
+  private:
+    static std::recursive_mutex &ctx_mu(Ctx *C) { return C->mu_run; }
+
+    void start_locked() {
+        if (started_) return;
+        started_ = true;
+        std::vector<Ctx *> ctxs;
+        for (auto &r : routes_)
+            if (std::find(ctxs.begin(), ctxs.end(), r.C) == ctxs.end()) ctxs.push_back(r.C);
+        for (Ctx *c : ctxs) workers_.emplace_back([this, c] { work(c); });
+    }
+
+    // oldest pending request of this context, then up to max_batch of the same route and level
+    bool pick(Ctx *C, std::vector<Request *> &batch, size_t &bytes) {
+        batch.clear();
+        Request *first = nullptr;
+        for (u64 t : pending_) {
+            Request *r = reqs_[t].get();
+            if (routes_[r->route].C == C) {
+                first = r;
+                break;
+            }
+        }
+        if (!first) return false;
+        const Route &rt = routes_[first->route];
+        int cap = rt.bytes_per_query ? max_batch_ : 1;  // first batch of a route measures its working set
+        for (u64 t : pending_) {
+            Request *r = reqs_[t].get();
+            if ((int)batch.size() < cap && r->route == first->route && r->in->level == first->in->level) batch.push_back(r);
+        }
+        const size_t per = rt.bytes_per_query;
+        if (budget_ && per) {
+            while (!batch.empty() && inflight_ + per * batch.size() > budget_) batch.pop_back();
+            if (batch.empty()) {
+                if (inflight_ == 0) {  // one query alone does not fit: fail it
+                    first->status = CKR_E_NOMEM;
+                    first->err = "request exceeds the HBM budget";
+                    first->done = true;
+                    first->t_done = now_ms();
+                    pending_.erase(std::find(pending_.begin(), pending_.end(), first->ticket));
+                    cv_.notify_all();
+                }
+                return false;
+            }
+        }
+        bytes = per * batch.size();
+        return true;
+    }
+
+    void work(Ctx *C) {
+        HIPCHK_NOTHROW(hipSetDevice(C->device));
+        hipEvent_t done_ev = nullptr;
+        HIPCHK_NOTHROW(hipEventCreateWithFlags(&done_ev, hipEventDisableTiming));
+        std::unique_lock<std::mutex> lk(mu_);
+        for (;;) {
+            std::vector<Request *> batch;
+            size_t bytes = 0;
+            cv_.wait(lk, [&] { return stop_ || pick(C, batch, bytes); });
+            if (stop_ && batch.empty()) break;
+            for (Request *r : batch) pending_.erase(std::find(pending_.begin(), pending_.end(), r->ticket));
+            inflight_ += bytes;
+            inflight_high_ = std::max(inflight_high_, inflight_);
+            const Route rt = routes_[batch[0]->route];
+            const bool measure = rt.bytes_per_query == 0;
+            lk.unlock();
+            const double t0 = now_ms();
+            std::vector<std::vector<DCt>> per(batch.size());
+            int st = CKR_OK;
+            std::string err;
+            size_t measured = 0;
+            try {
+                {
+                    // enqueue under the context lock, wait outside it
+                    std::lock_guard<std::recursive_mutex> cg(ctx_mu(C));
+                    if (measure) HIPCHK(hipStreamSynchronize(C->stream));
+                    const size_t base = C->pool.in_use;
+                    C->pool.high = base;
+                    std::vector<const DCt *> in;
+                    for (Request *r : batch) in.push_back(r->in);
+                    // the measuring batch runs eagerly so the pool sees its whole working set
+                    const bool graphs = C->graphs;
+                    if (measure) C->graphs = false;
+                    std::vector<DCt> outs;
+                    try {
+                        outs = run_kind(*C, *rt.K, rt.kind, rt.N, rt.cmp, rt.ind, in);
+                    } catch (...) {
+                        C->graphs = graphs;
+                        throw;
+                    }
+                    C->graphs = graphs;
+                    for (size_t i = 0; i < batch.size(); i++)
+                        for (auto &o : outs) per[i].push_back(slice(*C, o, (int)i, 1));
+                    measured = (C->pool.high - base) / batch.size();
+                    HIPCHK(hipEventRecord(done_ev, C->stream));
+                }
+                HIPCHK(hipEventSynchronize(done_ev));
+            } catch (const Error &e) {
+                st = e.status;
+                err = e.msg;
+            } catch (const std::exception &e) {
+                st = CKR_E_INVALID;
+                err = e.what();
+            }
+            const double t1 = now_ms();
+            lk.lock();
+            if (measure && measured) routes_[batch[0]->route].bytes_per_query = measured;
+            inflight_ -= bytes;
+            for (size_t i = 0; i < batch.size(); i++) {
+                Request *r = batch[i];
+                r->status = st;
+                r->err = err;
+                if (st == CKR_OK) r->outs = std::move(per[i]);
+                r->t_start = t0;
+                r->t_done = t1;
+                r->batch = (int)batch.size();
+                r->done = true;
+            }
+            completed_ += batch.size();
+            batches_++;
+            cv_.notify_all();
+        }
+        if (done_ev) (void)hipEventDestroy(done_ev);
+    }
+
+    std::mutex mu_;
+    std::condition_variable cv_;
+    std::vector<Route> routes_;
+    std::deque<u64> pending_;
+    std::unordered_map<u64, std::unique_ptr<Request>> reqs_;
+    std::vector<std::thread> workers_;
+    size_t budget_, inflight_ = 0, inflight_high_ = 0;
+    int max_batch_;
+    u64 next_ticket_ = 0, completed_ = 0, batches_ = 0;
+    bool stop_ = false, started_ = false;
+};
+
 }  // namespace ckr
 
 // ========================================================================
@@ -1275,6 +1523,7 @@ ckr_status ckr_keygen(ckr_context *ctx, const uint8_t seed[32], uint32_t max_lev
                       uint32_t what, ckr_keys **out) {
     return guard([&] {
         NEED(ctx && seed && out);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         *out = nullptr;
         Ctx &C = *ctx->C;
         const Params &P = C.P;
@@ -1353,6 +1602,7 @@ void ckr_keys_free(ckr_keys *k) {
 ckr_status ckr_keys_add_rotations(ckr_context *ctx, ckr_keys *keys, const int64_t *shifts, size_t count) {
     return guard([&] {
         NEED(ctx && keys && (shifts || !count));
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         std::vector<uint8_t> seed;
         {
             std::lock_guard<std::mutex> g(g_key_seed_mu);
@@ -1371,6 +1621,7 @@ ckr_status ckr_encrypt(ckr_context *ctx, const ckr_keys *keys, const double *v, 
                        const uint8_t seed[32], ckr_ct **out) {
     return guard([&] {
         NEED(ctx && keys && v && seed && out);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         *out = nullptr;
         Ctx &C = *ctx->C;
         const Keys &K = *keys->K;
@@ -1432,6 +1683,7 @@ static std::vector<u64> download_coeffs(Ctx &C, const DCt &c) {
 ckr_status ckr_decrypt(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *ct, double *out, uint32_t count) {
     return guard([&] {
         NEED(ctx && keys && ct && (out || !count));
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         Ctx &C = *ctx->C;
         const Keys &K = *keys->K;
         const size_t n = C.n();
@@ -1463,6 +1715,7 @@ void ckr_ct_free(ckr_ct *ct) { delete ct; }
 ckr_status ckr_ct_export(ckr_context *ctx, const ckr_ct *ct, uint64_t *data, size_t words) {
     return guard([&] {
         NEED(ctx && ct && data);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         Ctx &C = *ctx->C;
         const size_t need = (size_t)2 * (ct->ct.level + 1) * C.n();
         if (words < need) throw Error{CKR_E_INVALID, "export buffer too small"};
@@ -1474,6 +1727,7 @@ ckr_status ckr_ct_export(ckr_context *ctx, const ckr_ct *ct, uint64_t *data, siz
 ckr_status ckr_ct_import(ckr_context *ctx, const uint64_t *data, size_t words, uint32_t level, ckr_ct **out) {
     return guard([&] {
         NEED(ctx && data && out);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         *out = nullptr;
         Ctx &C = *ctx->C;
         if ((int)level > C.P.L) throw Error{CKR_E_DEPTH, "level above the chain"};
@@ -1502,6 +1756,7 @@ ckr_status ckr_rank(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uin
                     ckr_ct **out) {
     return guard([&] {
         NEED(ctx && keys && v && out);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         *out = nullptr;
         Ctx &C = *ctx->C;
         if (tie) throw Error{CKR_E_INVALID, "tie-corrected rank: use ckr_argmin"};
@@ -1515,6 +1770,7 @@ ckr_status ckr_run_batch(ckr_context *ctx, const ckr_keys *keys, int kind, uint3
                          const ckr_ct *const *v, size_t count, ckr_ct **out) {
     return guard([&] {
         NEED(ctx && keys && v && out && count);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         Ctx &C = *ctx->C;
         std::vector<const DCt *> in;
         for (size_t i = 0; i < count; i++) {
@@ -1535,6 +1791,69 @@ ckr_status ckr_rank_batch(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *
     return ckr_run_batch(ctx, keys, kRankCircuit, N, cmp, ckr_sign{0, 0}, v, count, out);
 }
 
+struct ckr_server {
+    std::unique_ptr<Server> S;
+};
+
+ckr_status ckr_server_create(size_t hbm_budget, uint32_t max_batch, ckr_server **out) {
+    return guard([&] {
+        NEED(out);
+        auto h = std::make_unique<ckr_server>();
+        h->S = std::make_unique<Server>(hbm_budget, (int)max_batch);
+        *out = h.release();
+    });
+}
+
+ckr_status ckr_server_add_route(ckr_server *srv, int kind, uint32_t N, ckr_context *ctx, const ckr_keys *keys,
+                                ckr_sign cmp, ckr_sign ind) {
+    return guard([&] {
+        NEED(srv && ctx && keys);
+        if (kind < 1 || kind > 3) throw Error{CKR_E_INVALID, "kind"};
+        check_N(*ctx->C, N);
+        Route r{kind, (int)N, ctx->C.get(), keys->K.get(), cmp, ind};
+        srv->S->add_route(r);
+    });
+}
+
+ckr_status ckr_server_submit(ckr_server *srv, int kind, uint32_t N, const ckr_ct *v, uint64_t *ticket) {
+    return guard([&] {
+        NEED(srv && v && ticket);
+        *ticket = srv->S->submit(kind, (int)N, v->ct);
+    });
+}
+
+ckr_status ckr_server_wait(ckr_server *srv, uint64_t ticket, int timeout_ms, ckr_ct **outs, size_t n_outs,
+                           double *latency_ms) {
+    std::vector<DCt> o;
+    std::string err;
+    int st = CKR_OK;
+    Ctx *C = nullptr;
+    ckr_status g = guard([&] {
+        NEED(srv && (outs || !n_outs));
+        st = srv->S->wait(ticket, timeout_ms, o, latency_ms, err, &C);
+    });
+    if (g != CKR_OK) return g;
+    if (st != CKR_OK) {
+        g_last_error = err.empty() ? "request failed" : err;
+        return (ckr_status)st;
+    }
+    if (o.size() > n_outs) {
+        g_last_error = "output array too small";
+        return CKR_E_INVALID;
+    }
+    for (size_t i = 0; i < o.size(); i++) outs[i] = new ckr_ct{C, std::move(o[i])};
+    return CKR_OK;
+}
+
+ckr_status ckr_server_stats(ckr_server *srv, double *stats) {
+    return guard([&] {
+        NEED(srv && stats);
+        srv->S->stats(stats);
+    });
+}
+
+void ckr_server_free(ckr_server *srv) { delete srv; }
+
 ckr_status ckr_context_set_graphs(ckr_context *ctx, int enable) {
     return guard([&] {
         NEED(ctx);
@@ -1546,6 +1865,7 @@ ckr_status ckr_argmin(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, u
                       ckr_sign ind, ckr_ct **onehot, ckr_ct **value) {
     return guard([&] {
         NEED(ctx && keys && v && onehot && value);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         *onehot = *value = nullptr;
         Ctx &C = *ctx->C;
         DCt oh, val;
@@ -1559,6 +1879,7 @@ ckr_status ckr_sort(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uin
                     ckr_ct **out) {
     return guard([&] {
         NEED(ctx && keys && v && out);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         *out = nullptr;
         Ctx &C = *ctx->C;
         DCt r = sort(C, *keys->K, v->ct, (int)N, cmp, ind);
@@ -1569,48 +1890,56 @@ ckr_status ckr_sort(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uin
 ckr_status ckr_op_rotate(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, int64_t k, ckr_ct **out) {
     return guard([&] {
         NEED(ctx && keys && a && out);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         *out = wrap(*ctx->C, ev_rotate(*ctx->C, *keys->K, a->ct, k));
     });
 }
 ckr_status ckr_op_mul(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, const ckr_ct *b, ckr_ct **out) {
     return guard([&] {
         NEED(ctx && keys && a && b && out);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         *out = wrap(*ctx->C, ev_mul(*ctx->C, *keys->K, a->ct, b->ct));
     });
 }
 ckr_status ckr_op_add(ckr_context *ctx, const ckr_ct *a, const ckr_ct *b, ckr_ct **out) {
     return guard([&] {
         NEED(ctx && a && b && out);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         *out = wrap(*ctx->C, ev_add(*ctx->C, a->ct, b->ct, false));
     });
 }
 ckr_status ckr_op_sub(ckr_context *ctx, const ckr_ct *a, const ckr_ct *b, ckr_ct **out) {
     return guard([&] {
         NEED(ctx && a && b && out);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         *out = wrap(*ctx->C, ev_add(*ctx->C, a->ct, b->ct, true));
     });
 }
 ckr_status ckr_op_rescale(ckr_context *ctx, const ckr_ct *a, ckr_ct **out) {
     return guard([&] {
         NEED(ctx && a && out);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         *out = wrap(*ctx->C, ev_rescale(*ctx->C, a->ct));
     });
 }
 ckr_status ckr_op_cmul_to(ckr_context *ctx, const ckr_ct *a, double c, uint32_t target, ckr_ct **out) {
     return guard([&] {
         NEED(ctx && a && out);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         *out = wrap(*ctx->C, ev_cmul_to(*ctx->C, a->ct, c, (int)target));
     });
 }
 ckr_status ckr_op_add_const(ckr_context *ctx, const ckr_ct *a, double c, ckr_ct **out) {
     return guard([&] {
         NEED(ctx && a && out);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         *out = wrap(*ctx->C, ev_add_const(*ctx->C, a->ct, c));
     });
 }
 ckr_status ckr_op_mul_plain(ckr_context *ctx, const ckr_ct *a, const double *z, uint32_t count, ckr_ct **out) {
     return guard([&] {
         NEED(ctx && a && z && out);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         Ctx &C = *ctx->C;
         if ((u64)count > C.n() / 2) throw Error{CKR_E_RANGE, "too many slots"};
         Buf pt = encode_plain(C, std::vector<double>(z, z + count), a->ct.level);
@@ -1621,6 +1950,7 @@ ckr_status ckr_op_mul_plain(ckr_context *ctx, const ckr_ct *a, const double *z, 
 ckr_status ckr_ntt_device(ckr_context *ctx, uint64_t *data, uint32_t limbs, uint32_t first_mod, int inverse) {
     return guard([&] {
         NEED(ctx && data);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         Ctx &C = *ctx->C;
         if (first_mod + limbs > (u32)C.P.nmod()) throw Error{CKR_E_INVALID, "modulus index out of range"};
         ntt(C, data, (int)limbs, 1, 0, plain_map((int)first_mod), inverse != 0);
@@ -1631,6 +1961,7 @@ ckr_status ckr_ntt_device(ckr_context *ctx, uint64_t *data, uint32_t limbs, uint
 ckr_status ckr_set_profiling(ckr_context *ctx, int enable) {
     return guard([&] {
         NEED(ctx);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         Ctx &C = *ctx->C;
         prof_resolve(C);
         C.prof.on = enable != 0;
@@ -1640,6 +1971,7 @@ ckr_status ckr_set_profiling(ckr_context *ctx, int enable) {
 ckr_status ckr_profile_reset(ckr_context *ctx) {
     return guard([&] {
         NEED(ctx);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         Ctx &C = *ctx->C;
         prof_resolve(C);
         for (int c = 0; c < kNCat; c++) C.prof.launches[c] = 0, C.prof.ms[c] = 0, C.prof.bytes[c] = 0;
@@ -1649,6 +1981,7 @@ ckr_status ckr_profile_reset(ckr_context *ctx) {
 ckr_status ckr_profile_read(ckr_context *ctx, int category, uint64_t *launches, double *total_ms, double *bytes) {
     return guard([&] {
         NEED(ctx);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         if (category < 0 || category >= kNCat) throw Error{CKR_E_INVALID, "profile category"};
         Ctx &C = *ctx->C;
         prof_resolve(C);
@@ -1666,6 +1999,7 @@ const char *ckr_profile_name(int category) { return category >= 0 && category < 
 ckr_status ckr_autotune(ckr_context *ctx, uint32_t limbs, uint32_t iters, float *ms) {
     return guard([&] {
         NEED(ctx);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         Ctx &C = *ctx->C;
         if (limbs == 0 || limbs > (u32)C.P.nmod() * 64) throw Error{CKR_E_INVALID, "limbs"};
         iters = std::max(1u, iters);
@@ -1717,6 +2051,7 @@ ckr_status ckr_ntt_variant(ckr_context *ctx, int inverse, int pass, int variant)
 ckr_status ckr_synchronize(ckr_context *ctx) {
     return guard([&] {
         NEED(ctx);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         HIPCHK(hipStreamSynchronize(ctx->C->stream));
     });
 }
