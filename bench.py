@@ -48,6 +48,101 @@ def cpu_baseline(pset, N, cmp, level, threads):
             "sample": f"1 rank-{N} query at n=2^16 (keygen {tk:.1f}s excluded), {tr:.1f}s wall, ranks exact={exact}"}
 
 
+def serve(args):
+    """Served mix: Poisson arrivals, rank N=128 at n=2^16, argmin N=64 and sort
+    N in {32,64,128} at n=2^17, continuous batching with an HBM budget."""
+    import paper_2412_15126_amd as ckr
+    from paper_2412_15126_amd import workloads as W
+
+    p16, p17 = W.PSETS["P16"], W.PSETS["P17"]
+    t = time.time()
+    a = ckr.Context(p16)
+    ka = a.keygen(bytes(range(32)), 17, [128])
+    b = ckr.Context(p17)
+    kb = b.keygen(bytes(range(3, 35)), p17["L"], [32, 64, 128], what=6)
+    a.autotune(2 * 8 * 18, 2)
+    b.autotune(2 * 4 * 41, 2)
+    log(f"[serve] keys ready in {time.time() - t:.1f}s")
+    srv = ckr.Server(hbm_budget=args.hbm_budget << 30, max_batch=args.max_batch)
+    srv.add_route("rank", 128, a, ka, W.RANK_CMP[128])
+    srv.add_route("argmin", 64, b, kb, *W.ARGMIN_CMP[64])
+    for N in (32, 64, 128):
+        srv.add_route("sort", N, b, kb, *W.SORT_CMP[N])
+
+    rng = np.random.default_rng(11)
+    arrivals, tnow = [], 0.0
+    while True:
+        tnow += rng.exponential(1.0 / args.rate)
+        if tnow > args.serve_seconds:
+            break
+        arrivals.append(tnow)
+    jobs = []
+    for i, ta in enumerate(arrivals):
+        kind = ["rank", "argmin", "sort"][int(rng.integers(0, 3))]
+        if kind == "rank":
+            N, ctx, keys, lvl = 128, a, ka, 17
+            v, _, e = W.rank_workload(N, 2.0 ** -10, 5000 + i)
+        elif kind == "argmin":
+            N, ctx, keys, lvl = 64, b, kb, p17["L"]
+            v, _, e = W.tied_workload(N, 5000 + i)
+        else:
+            N = int(rng.choice([32, 64, 128]))
+            ctx, keys, lvl = b, kb, p17["L"]
+            v, _, e = W.rank_workload(N, 2.0 ** -10, 5000 + i)
+        jobs.append(dict(t=ta, kind=kind, N=N, ctx=ctx, keys=keys, ct=ctx.encrypt(keys, v, lvl, e), v=v))
+    log(f"[serve] {len(jobs)} requests encrypted")
+    # warm each route once (its first batch runs alone and measures its working set)
+    for kind, N, ctx, keys, lvl in [("rank", 128, a, ka, 17), ("argmin", 64, b, kb, p17["L"])] + \
+            [("sort", N, b, kb, p17["L"]) for N in (32, 64, 128)]:
+        v, _, e = W.rank_workload(N, 2.0 ** -10, 99)
+        srv.wait(srv.submit(kind, N, ctx.encrypt(keys, v, lvl, e)))
+    log("[serve] routes warm")
+    t0 = time.perf_counter()
+    for j in jobs:
+        dt = t0 + j["t"] - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        j["ticket"] = srv.submit(j["kind"], j["N"], j["ct"])
+    for j in jobs:
+        j["outs"], (j["lat"], j["queue"], j["batch"]) = srv.wait(j["ticket"])
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    lat = np.array([j["lat"] for j in jobs])
+    # the same queries alone: bit-identical outputs
+    same = True
+    for kind in ("rank", "argmin", "sort"):
+        for j in [j for j in jobs if j["kind"] == kind][:2]:
+            cmp, ind = {"rank": (W.RANK_CMP[128], (0, 0)), "argmin": W.ARGMIN_CMP[64], "sort": W.SORT_CMP[j["N"]]}[kind]
+            if kind == "rank":
+                alone = [j["ctx"].rank(j["keys"], j["ct"], j["N"], cmp)]
+            elif kind == "argmin":
+                alone = list(j["ctx"].argmin(j["keys"], j["ct"], j["N"], cmp, ind))
+            else:
+                alone = [j["ctx"].sort(j["keys"], j["ct"], j["N"], cmp, ind)]
+            same &= all(np.array_equal(x.export(), y.export()) for x, y in zip(alone, j["outs"]))
+    by_kind = {}
+    for kind in ("rank", "argmin", "sort"):
+        l = np.array([j["lat"] for j in jobs if j["kind"] == kind])
+        if len(l):
+            by_kind[kind] = {"count": int(len(l)), "p50_ms": round(float(np.percentile(l, 50)), 2),
+                             "p99_ms": round(float(np.percentile(l, 99)), 2)}
+    res = {
+        "metric": "served queries/s (Poisson arrivals) with p50/p99 latency",
+        "value": round(len(jobs) / wall, 3), "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
+        "data": "synthetic", "dtype": "u64",
+        "config": {"workload": f"Poisson {args.rate}/s for {args.serve_seconds}s: rank N=128 (n=2^16), argmin N=64 and "
+                               "sort N in {32,64,128} (n=2^17), equal shares", "max_batch": args.max_batch,
+                   "hbm_budget_GiB": args.hbm_budget},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2)},
+        "by_kind": by_kind,
+        "batches": st["batches"], "mean_batch": round(float(np.mean([j["batch"] for j in jobs])), 2),
+        "inflight_high_GiB": round(st["inflight_high_bytes"] / 2 ** 30, 2),
+        "hbm_high_GiB": round((a.memory()[1] + b.memory()[1]) / 2 ** 30, 2),
+        "same_alone_as_in_mix": bool(same),
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,12 +150,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="served mix with Poisson arrivals instead of the batch run")
+    ap.add_argument("--rate", type=float, default=4.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--max-batch", type=int, default=8)
+    ap.add_argument("--hbm-budget", type=int, default=64, help="GiB of circuit working set in flight")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the path shards by query, "
               "see DESIGN.md; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
+    if args.serve:
+        return serve(args)
 
     import paper_2412_15126_amd as ckr
     from paper_2412_15126_amd import hip

@@ -20,6 +20,7 @@
 #include <condition_variable>
 #include <deque>
 #include <thread>
+#include <atomic>
 #include <set>
 #include <functional>
 #include <vector>
@@ -1426,6 +1427,22 @@ ckr_status ckr_context_memory(const ckr_context *ctx, size_t *in_use, size_t *hi
     });
 }
 
+// run fn(i) for i in [0, count) on up to 16 host threads (independent streams per i)
+static void parallel_for(int count, const std::function<void(int)> &fn) {
+    const int T = std::max(1, std::min<int>({count, 16, (int)std::thread::hardware_concurrency()}));
+    if (T <= 1) {
+        for (int i = 0; i < count; i++) fn(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    std::atomic<int> next{0};
+    for (int t = 0; t < T; t++)
+        th.emplace_back([&] {
+            for (int i = next++; i < count; i = next++) fn(i);
+        });
+    for (auto &x : th) x.join();
+}
+
 // Galois elements the circuits need for one N
 static void circuit_shifts(u32 N, u32 what, std::vector<i64> &sh) {
     const int l = lg((int)N);
@@ -1457,14 +1474,14 @@ static void gen_switch_key(Ctx &C, Keys &K, u32 g, const Buf &s_eval, const Buf 
             Stream st(seed, kKsE, ((u64)g << 32) | ((u64)j << 16));
             for (size_t i = 0; i < n; i++) ei[i] = st.cbd21();
         }
-        for (int li = 0; li < Ek; li++) {
+        parallel_for(Ek, [&](int li) {
             const int mt = emap(li);
             const u64 q = P.mod[mt];
             Stream st(seed, kKsA, ((u64)g << 32) | ((u64)j << 16) | (u64)mt);
             u64 *ar = a.data() + (size_t)li * n, *er = e.data() + (size_t)li * n;
             for (size_t i = 0; i < n; i++) ar[i] = st.uniform(q);
             for (size_t i = 0; i < n; i++) er[i] = hred(ei[i], q);
-        }
+        });
         HIPCHK(hipMemcpyAsync(ea.get(), a.data(), a.size() * 8, hipMemcpyHostToDevice, C.stream));
         HIPCHK(hipMemcpyAsync(ee.get(), e.data(), e.size() * 8, hipMemcpyHostToDevice, C.stream));
         ntt(C, ea.get(), Ek, 1, 0, emap, false);
