@@ -148,7 +148,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--ntt-chunk", type=int, default=0, help="limbs per cached NTT chunk (0: whole batch; -1: choose by timing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true", help="served mix with Poisson arrivals instead of the batch run")
     ap.add_argument("--rate", type=float, default=4.0)
@@ -193,6 +194,23 @@ def main():
     table = ctx.autotune(tune_limbs, 3)
     chosen = [[int(np.argmin(table[i][p])) for p in range(2)] for i in range(2)]
     log(f"[bench] autotune ({tune_limbs} limbs): variants fwd {chosen[0]} inv {chosen[1]}")
+    chunk = args.ntt_chunk
+    if chunk < 0:
+        # pick the cache chunk by timing one batched step per candidate
+        best = None
+        for cand in (0, 96, 192, 384):
+            ctx.set_ntt_chunk(cand)
+            step()
+            ctx.synchronize()
+            t_ = time.perf_counter()
+            step()
+            ctx.synchronize()
+            dt = time.perf_counter() - t_
+            log(f"[bench] ntt chunk {cand}: {dt * 1e3:.1f} ms/step (eager)")
+            if best is None or dt < best[0]:
+                best = (dt, cand)
+        chunk = best[1]
+    ctx.set_ntt_chunk(chunk)
 
     # a plain device copy of known size: the reference for HBM byte counters
     calib = hip.DeviceArray(np.zeros(COPY_BYTES // 8, np.uint64))
@@ -200,6 +218,27 @@ def main():
     hip.rt().hipMemcpy(calib2.ptr, calib.ptr, COPY_BYTES, 3)
     hip.synchronize()
     del calib, calib2
+
+    def timed_steps(fn, steps):
+        ev = [hip.Event() for _ in range(steps + 1)]
+        ctx.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        for s_ in range(steps):
+            fn()
+            ev[s_ + 1].record(stream)
+        ctx.synchronize()
+        wall_ = time.perf_counter() - t0
+        return wall_, [ev[s_].elapsed_ms(ev[s_ + 1]) for s_ in range(steps)], ev[0].elapsed_ms(ev[-1])
+
+    # the plain one-query-at-a-time path (same circuit, batch of one, graph replay)
+    one = [cts[0]]
+    for _ in range(2):
+        ctx.run_batch(keys, "rank", one, N, cmp)
+    w1, lat1, _ = timed_steps(lambda: ctx.run_batch(keys, "rank", one, N, cmp), args.steps)
+    single = {"queries_per_s": round(args.steps / w1, 3), "p50_ms": round(float(np.percentile(lat1, 50)), 3),
+              "p99_ms": round(float(np.percentile(lat1, 99)), 3)}
+    log(f"[bench] one query at a time: {single}")
 
     for _ in range(max(2, args.warmup)):   # the first call runs eagerly, the second captures the graph
         out = step()
@@ -209,18 +248,8 @@ def main():
                 for o, v in zip(out, vals))
     log(f"[bench] warmup done, ranks exact: {exact}")
 
-    # timed region: hipGraph replays, one event pair per step
-    ev = [hip.Event() for _ in range(args.steps + 1)]
-    ctx.synchronize()
-    t0 = time.perf_counter()
-    ev[0].record(stream)
-    for s in range(args.steps):
-        out = step()
-        ev[s + 1].record(stream)
-    ctx.synchronize()
-    wall = time.perf_counter() - t0
-    step_ms = [ev[s].elapsed_ms(ev[s + 1]) for s in range(args.steps)]
-    total_ms = ev[0].elapsed_ms(ev[-1])
+    # timed region: hipGraph replays of the batched circuit, one event pair per step
+    wall, step_ms, total_ms = timed_steps(step, args.steps)
     log(f"[bench] timed {args.steps} steps: {total_ms:.1f} ms on device, {wall * 1e3:.1f} ms wall")
 
     # kernel durations: the same steps again with every launch bracketed by
@@ -263,9 +292,10 @@ def main():
         "config": {"workload": "rank N=128 at n=2^16 (q0 50-bit + 23 rescale primes near 2^40, 7 special 50-bit "
                                "primes, dnum=3, scale 2^40), encrypted at level 17, comparator g^4 then f",
                    "batch": B, "ranks_exact": bool(exact), "graphs": True,
-                   "ntt_variants": {"fwd": chosen[0], "inv": chosen[1]}},
+                   "ntt_variants": {"fwd": chosen[0], "inv": chosen[1]}, "ntt_chunk_limbs": chunk},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
                        "per": "step of " + str(B) + " queries"},
+        "one_at_a_time": single,
         "ntt_GBps": round(ntt_bytes / (ntt_ms * 1e-3) / 1e9, 1) if ntt_ms > 0 else 0.0,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,

@@ -244,6 +244,10 @@ const char *ckr_profile_name(int category);
  * receives the 2 x 2 x 4 average milliseconds [inverse][pass][variant].
  * Every variant computes the same transform bit for bit. */
 ckr_status ckr_autotune(ckr_context *ctx, uint32_t limbs, uint32_t iters, float *ms);
+/* Run transforms of more than `limbs` limbs in chunks of whole polynomials
+ * (0 = never), so each chunk's second pass reads data still in the
+ * last-level cache.  Results do not depend on the chunking. */
+ckr_status ckr_set_ntt_chunk(ckr_context *ctx, uint32_t limbs);
 /* Force one tile variant (0..3) for a (direction, pass). */
 ckr_status ckr_ntt_variant(ckr_context *ctx, int inverse, int pass, int variant);
 

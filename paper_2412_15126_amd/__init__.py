@@ -93,6 +93,7 @@ _SIGS = {
     "ckr_server_stats": (C.c_int, [vp, C.POINTER(C.c_double)]),
     "ckr_server_free": (None, [vp]),
     "ckr_ntt_variant": (C.c_int, [vp, C.c_int, C.c_int, C.c_int]),
+    "ckr_set_ntt_chunk": (C.c_int, [vp, C.c_uint32]),
 }
 
 _lib = None
@@ -235,6 +236,9 @@ class Context:
         ms = (C.c_float * 16)()
         _ok(lib().ckr_autotune(self.h, limbs, iters, ms))
         return np.array(ms[:], dtype=np.float64).reshape(2, 2, 4)
+
+    def set_ntt_chunk(self, limbs):
+        _ok(lib().ckr_set_ntt_chunk(self.h, int(limbs)))
 
     def ntt_variant(self, inverse, pass_, variant):
         _ok(lib().ckr_ntt_variant(self.h, int(inverse), int(pass_), int(variant)))

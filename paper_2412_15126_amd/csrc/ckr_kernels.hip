@@ -73,7 +73,7 @@ template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool FUSE>
 __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
     ntt_pass(u64 *__restrict__ base, size_t poly_stride, int limbs, LimbMap map, int logn,
              const double2 *__restrict__ mq, const double2 *__restrict__ twtab, const double2 *__restrict__ twlast,
-             const NttFuse fz) {
+             const NttFuse fz, const u64 *__restrict__ src, size_t src_stride) {
     constexpr int S = 1 << LOGS, E = 1 << LOGE, TPC = S / E, NT = C * TPC;
     constexpr int NR = (LOGS + LOGE - 1) / LOGE;
     constexpr int SP = S + (S >> 4) + 1;
@@ -85,19 +85,23 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
     const int mod = map(t);
     const size_t n = (size_t)1 << logn;
     u64 *data = base + (size_t)p * poly_stride + (size_t)t * n;
+    constexpr bool FIRST = (COLPASS != INV);  // the pass that runs first reads the input
+    const u64 *din = (FIRST && src) ? src + (size_t)p * src_stride + (size_t)t * n : data;
     const double q = mq[mod].x, two_q = 2.0 * q, qinv = mq[mod].y;
     const double2 *tw = twtab + (size_t)mod * n;
     constexpr bool PRO = FUSE && COLPASS && !INV;   // prologue: broadcast-reduce one limb
     constexpr bool EPI = FUSE && !COLPASS && !INV;  // epilogue: (x - y) * c (+ add)
     const u64 *psrc = PRO ? fz.src + (size_t)p * fz.src_stride : nullptr;
     u64 *pout = nullptr;
-    const u64 *px = nullptr, *padd = nullptr;
+    const u64 *px = nullptr, *padd = nullptr, *padd2 = nullptr;
     double ec = 0.0, ecq = 0.0;
     if (EPI) {
         const size_t pb = (size_t)(p >> 1), pk = (size_t)(p & 1);
         pout = fz.out + pb * fz.out_stride + pk * fz.out_off + (size_t)t * n;
         px = fz.x + pb * fz.x_stride + pk * fz.x_off + (size_t)t * n;
         if (fz.add && (fz.add_mask >> pk & 1)) padd = fz.add + pb * fz.add_stride + pk * fz.add_off + (size_t)t * n;
+        if (fz.add2 && (fz.add2_mask >> pk & 1))
+            padd2 = fz.add2 + pb * fz.add2_stride + pk * fz.add2_off + (size_t)t * n;
         ec = fz.c.v[t];
         ecq = fz.c.vq[t];
     }
@@ -106,6 +110,7 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
         if (EPI) {
             double r = red1(mm_lazy(u2d(px[pos]) - y + q, ec, ecq, q), q);
             if (padd) r = red1(r + u2d(padd[pos]), q);
+            if (padd2) r = red1(r + u2d(padd2[pos]), q);
             pout[pos] = d2u(r);
         } else {
             data[pos] = d2u(y);
@@ -138,11 +143,11 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
                 for (int k = 0; k < E; k++) x[k] = red_any(u2d(psrc[gaddr(rbase | (k << w))]), q, qinv);
             } else if (direct) {
 #pragma unroll
-                for (int k = 0; k < E; k++) x[k] = u2d(data[gaddr(rbase | (k << w))]);
+                for (int k = 0; k < E; k++) x[k] = u2d(din[gaddr(rbase | (k << w))]);
             } else {
                 // rows are contiguous: the tile is C*S consecutive words
-                const u64 *src = data + (size_t)c0 * S;
-                for (int i = tid; i < C * S; i += NT) lds[lidx(i / S, i % S)] = u2d(src[i]);
+                const u64 *tile = din + (size_t)c0 * S;
+                for (int i = tid; i < C * S; i += NT) lds[lidx(i / S, i % S)] = u2d(tile[i]);
                 __syncthreads();
 #pragma unroll
                 for (int k = 0; k < E; k++) x[k] = lds[lidx(cl, rbase | (k << w))];
@@ -235,10 +240,10 @@ static void launch_pass(const DevTables &T, const LimbBatch &b, hipStream_t s, c
     const double2 *tw = INV ? T.tw_inv : T.tw_fwd;
     if (f && !INV && (COLPASS ? f->pro : f->epi))
         hipLaunchKernelGGL((ntt_pass<LOGS, LOGE, C, COLPASS, INV, true>), grid, block, 0, s, b.base, b.poly_stride,
-                           b.limbs, b.map, logn, T.mq, tw, T.tw_last, *f);
+                           b.limbs, b.map, logn, T.mq, tw, T.tw_last, *f, b.src, b.src_stride);
     else
         hipLaunchKernelGGL((ntt_pass<LOGS, LOGE, C, COLPASS, INV, false>), grid, block, 0, s, b.base, b.poly_stride,
-                           b.limbs, b.map, logn, T.mq, tw, T.tw_last, NttFuse{});
+                           b.limbs, b.map, logn, T.mq, tw, T.tw_last, NttFuse{}, b.src, b.src_stride);
 }
 
 // tile variants: (elements per thread 2^LOGE, columns per workgroup C)

@@ -217,6 +217,7 @@ struct Prof {
 struct Ctx {
     Prof prof;
     bool graphs = true;           // capture batched circuits into hipGraphs
+    int ntt_chunk = 0;            // limbs per two-pass chunk (0: whole dispatch), keeps pass-1 output in cache
     hipStream_t own_stream = nullptr;
     Params P;
     DevTables T{};
@@ -345,22 +346,56 @@ static void prof_resolve(Ctx &C) {
     C.prof.pending.clear();
 }
 
-// each pass reads and writes every limb once: 16 n bytes per limb
-static void ntt(Ctx &C, u64 *base, int limbs, int polys, size_t stride, LimbMap map, bool inv) {
-    LimbBatch b{base, limbs, polys, stride, map};
-    const double bytes = 16.0 * C.P.n * limbs * polys;
-    timed(C, inv ? kNttInvRow : kNttFwdCol, bytes, [&] { k_ntt_pass(C.T, b, inv, 0, C.stream); });
-    timed(C, inv ? kNttInvCol : kNttFwdRow, bytes, [&] { k_ntt_pass(C.T, b, inv, 1, C.stream); });
+// Each pass reads and writes every limb once: 16 n bytes per limb.  Large
+// dispatches run in chunks of whole polynomials so the second pass reads the
+// first pass's output while it is still in the last-level cache.
+template <class F>
+static void for_chunks(Ctx &C, int limbs, int polys, F &&f) {
+    int per = polys;
+    if (C.ntt_chunk > 0 && limbs * polys > C.ntt_chunk) per = std::max(1, C.ntt_chunk / std::max(limbs, 1));
+    for (int p0 = 0; p0 < polys; p0 += per) f(p0, std::min(per, polys - p0));
 }
 
-// forward transform with the fused prologue / epilogue of NttFuse
+static void ntt(Ctx &C, u64 *base, int limbs, int polys, size_t stride, LimbMap map, bool inv,
+                const u64 *src = nullptr, size_t src_stride = 0) {
+    for_chunks(C, limbs, polys, [&](int p0, int np) {
+        LimbBatch b{base + (size_t)p0 * stride, limbs, np, stride, map};
+        if (src) {
+            b.src = src + (size_t)p0 * src_stride;
+            b.src_stride = src_stride;
+        }
+        const double bytes = 16.0 * C.P.n * limbs * np;
+        timed(C, inv ? kNttInvRow : kNttFwdCol, bytes, [&] { k_ntt_pass(C.T, b, inv, 0, C.stream); });
+        timed(C, inv ? kNttInvCol : kNttFwdRow, bytes, [&] { k_ntt_pass(C.T, b, inv, 1, C.stream); });
+    });
+}
+
+// forward transform with the fused prologue / epilogue of NttFuse.  The
+// epilogue addresses poly p = 2b + k, so chunks hold whole (b) pairs.
 static void ntt_fused(Ctx &C, u64 *base, int limbs, int polys, size_t stride, LimbMap map, const NttFuse &f) {
-    LimbBatch b{base, limbs, polys, stride, map};
-    const double limb = 8.0 * C.P.n, all = limb * limbs * polys;
-    const double b0 = f.pro ? limb * polys + all : 2 * all;
-    const double b1 = f.epi ? 3 * all + (f.add ? all * __builtin_popcount(f.add_mask) / 2 : 0) : 2 * all;
-    timed(C, kNttFwdCol, b0, [&] { k_ntt_fused(C.T, b, f, 0, C.stream); });
-    timed(C, kNttFwdRow, b1, [&] { k_ntt_fused(C.T, b, f, 1, C.stream); });
+    const double limb = 8.0 * C.P.n;
+    int per = polys;
+    if (C.ntt_chunk > 0 && limbs * polys > C.ntt_chunk) per = std::max(2, (C.ntt_chunk / std::max(limbs, 1)) & ~1);
+    for (int p0 = 0; p0 < polys; p0 += per) {
+        const int np = std::min(per, polys - p0);
+        LimbBatch b{base + (size_t)p0 * stride, limbs, np, stride, map};
+        NttFuse g = f;
+        const size_t b0 = (size_t)(p0 >> 1);  // first batch entry of the chunk
+        if (g.pro) g.src = f.src + (size_t)p0 * f.src_stride;
+        if (g.epi) {
+            g.out = f.out + b0 * f.out_stride;
+            g.x = f.x + b0 * f.x_stride;
+            if (g.add) g.add = f.add + b0 * f.add_stride;
+            if (g.add2) g.add2 = f.add2 + b0 * f.add2_stride;
+        }
+        const double all = limb * limbs * np;
+        const double b0b = g.pro ? limb * np + all : 2 * all;
+        const double b1b = g.epi ? 3 * all + (g.add ? all * __builtin_popcount(g.add_mask) / 2 : 0) +
+                                       (g.add2 ? all * __builtin_popcount(g.add2_mask) / 2 : 0)
+                                 : 2 * all;
+        timed(C, kNttFwdCol, b0b, [&] { k_ntt_fused(C.T, b, g, 0, C.stream); });
+        timed(C, kNttFwdRow, b1b, [&] { k_ntt_fused(C.T, b, g, 1, C.stream); });
+    }
 }
 
 // 2-D strided device copy: `rows` rows of `width` words
@@ -583,8 +618,7 @@ static DCt ev_rescale(Ctx &C, const DCt &a) {
     const size_t n = C.n(), L = (size_t)(l + 1) * n;
     const int P2 = 2 * a.B;
     Buf last(&C, (size_t)P2 * n);
-    timed(C, kCopy, 16.0 * n * P2, [&] { copy2d(C, last.get(), n, a.d() + (size_t)l * n, L, n, P2); });
-    ntt(C, last.get(), 1, P2, n, plain_map(l), true);
+    ntt(C, last.get(), 1, P2, n, plain_map(l), true, a.d() + (size_t)l * n, L);
     DCt o = ct_new(C, l - 1, a.B);
     std::vector<u64> inv(l);
     for (int i = 0; i < l; i++) inv[i] = hinv(C.P.mod[l] % C.P.mod[i], C.P.mod[i]);
@@ -628,15 +662,15 @@ static DCt ev_cmul_to(Ctx &C, const DCt &a, double c, int target) {
 // Output poly k (0: b part, 1: a part) of batch entry b goes to out + b*so + k*out_off
 // and, when bit k of add_mask is set, has add + b*sadd + k*add_off added.
 static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_t sd, int l, int B, u64 *out,
-                      size_t so, size_t out_off, const u64 *add, size_t sadd, size_t add_off, int add_mask) {
+                      size_t so, size_t out_off, const u64 *add, size_t sadd, size_t add_off, int add_mask,
+                      const u64 *add2 = nullptr, size_t sadd2 = 0, size_t add2_off = 0, int add2_mask = 0) {
     const Params &P = C.P;
     if (l > K.lmax) throw Error{CKR_E_DEPTH, "ciphertext above key level"};
     const size_t n = C.n();
     const int beta = P.beta(l), E = l + 1 + P.K;
     // coefficient-domain copy of d
     Buf dc(&C, (size_t)B * (l + 1) * n);
-    timed(C, kCopy, 16.0 * n * (l + 1) * B, [&] { copy2d(C, dc.get(), (size_t)(l + 1) * n, d, sd, (size_t)(l + 1) * n, B); });
-    ntt(C, dc.get(), l + 1, B, (size_t)(l + 1) * n, plain_map(), true);
+    ntt(C, dc.get(), l + 1, B, (size_t)(l + 1) * n, plain_map(), true, d, sd);
     // ModUp: base conversion of each digit to the other limbs, then NTT
     const size_t sext = (size_t)beta * E * n;
     Buf ext(&C, (size_t)B * sext);
@@ -670,7 +704,8 @@ static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_
     ia.sd = sd;
     ia.sext = sext;
     ia.sacc = sacc;
-    timed(C, kIP, 8.0 * n * E * (3.0 * beta + 2) * B, [&] { k_ip(C.T, ia, C.stream); });
+    // per target limb: beta inputs and 2 outputs per batch entry, 2*beta key limbs once
+    timed(C, kIP, 8.0 * n * E * ((beta + 2.0) * B + 2.0 * beta), [&] { k_ip(C.T, ia, C.stream); });
     // ModDown: (x_Q - BConv_{P->Q}(x_P)) * P^{-1}, the combine fused into the last NTT pass
     ntt(C, acc.get() + (size_t)(l + 1) * n, P.K, 2 * B, (size_t)E * n, plain_map(P.nq), true);
     Buf conv(&C, (size_t)2 * B * (l + 1) * n);
@@ -698,6 +733,10 @@ static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_
     f.add_stride = sadd;
     f.add_off = add_off;
     f.add_mask = add ? add_mask : 0;
+    f.add2 = add2;
+    f.add2_stride = sadd2;
+    f.add2_off = add2_off;
+    f.add2_mask = add2 ? add2_mask : 0;
     scalars_of_vals(C, pinv, f.c);
     ntt_fused(C, conv.get(), l + 1, 2 * B, (size_t)(l + 1) * n, plain_map(), f);
 }
@@ -740,6 +779,21 @@ static DCt ev_rotate(Ctx &C, const Keys &K, const DCt &a, i64 k) {
     DCt o = ct_new(C, l, a.B);
     // (sigma(c0) + KS_b(sigma(c1)), KS_a(sigma(c1)))
     keyswitch(C, K, key, r.d() + L, 2 * L, l, a.B, o.d(), 2 * L, L, r.d(), 2 * L, L, 1);
+    return o;
+}
+
+// X + (X rotated left by k): the addition rides in the key switch's epilogue
+static DCt ev_rotate_add(Ctx &C, const Keys &K, const DCt &a, i64 k) {
+    const u32 g = galois_left(C, k);
+    if (g == 1) return ev_add(C, a, a, false);
+    const Buf &key = find_key(K, g);
+    const int l = a.level;
+    const size_t n = C.n(), L = (size_t)(l + 1) * n;
+    DCt r = ct_new(C, l, a.B);
+    timed(C, kAutomorph, 32.0 * L * a.B, [&] { k_automorph(C.T, r.d(), a.d(), l + 1, 2 * a.B, L, L, g, C.stream); });
+    DCt o = ct_new(C, l, a.B);
+    // (a0 + sigma(a0) + KS_b(sigma(a1)), a1 + KS_a(sigma(a1)))
+    keyswitch(C, K, key, r.d() + L, 2 * L, l, a.B, o.d(), 2 * L, L, r.d(), 2 * L, L, 1, a.d(), 2 * L, L, 3);
     return o;
 }
 
@@ -821,40 +875,39 @@ static int lg(int N) {
     return r;
 }
 
-static DCt add_rot(Ctx &C, const Keys &K, const DCt &X, i64 k) {
-    DCt r = ev_rotate(C, K, X, k);
-    return ev_add(C, X, r, false);
+// X_{i+1} = X_i + rot(X_i, shift(i)) for i in [from, to), starting from V
+template <class Shift>
+static DCt rot_add_chain(Ctx &C, const Keys &K, const DCt &V, int from, int to, Shift shift) {
+    DCt X;
+    const DCt *cur = &V;
+    for (int i = from; i < to; i++) {
+        X = ev_rotate_add(C, K, *cur, shift(i));
+        cur = &X;
+    }
+    return cur == &V ? ev_copy(C, V) : std::move(X);
 }
 
 static DCt trans_r(Ctx &C, const Keys &K, const DCt &V, int N) {
-    DCt X = ev_copy(C, V);
-    for (int i = 1; i <= lg(N); i++) X = add_rot(C, K, X, -(i64)(((i64)N * (N - 1)) >> i));
+    DCt X = rot_add_chain(C, K, V, 1, lg(N) + 1, [&](int i) { return -(i64)(((i64)N * (N - 1)) >> i); });
     return ev_mul_plain(C, X, get_plain(C, kMaskCol0, N, X.level));
 }
 static DCt trans_c(Ctx &C, const Keys &K, const DCt &V, int N) {
-    DCt X = ev_copy(C, V);
-    for (int i = 1; i <= lg(N); i++) X = add_rot(C, K, X, (i64)(((i64)N * (N - 1)) >> i));
+    DCt X = rot_add_chain(C, K, V, 1, lg(N) + 1, [&](int i) { return (i64)(((i64)N * (N - 1)) >> i); });
     return ev_mul_plain(C, X, get_plain(C, kMaskRow0, N, X.level));
 }
 static DCt sum_r(Ctx &C, const Keys &K, const DCt &V, int N) {
-    DCt X = ev_copy(C, V);
-    for (int i = 0; i < lg(N); i++) X = add_rot(C, K, X, (i64)N << i);
+    DCt X = rot_add_chain(C, K, V, 0, lg(N), [&](int i) { return (i64)N << i; });
     return ev_mul_plain(C, X, get_plain(C, kMaskRow0, N, X.level));
 }
 static DCt sum_c(Ctx &C, const Keys &K, const DCt &V, int N) {
-    DCt X = ev_copy(C, V);
-    for (int i = 0; i < lg(N); i++) X = add_rot(C, K, X, (i64)1 << i);
+    DCt X = rot_add_chain(C, K, V, 0, lg(N), [&](int i) { return (i64)1 << i; });
     return ev_mul_plain(C, X, get_plain(C, kMaskCol0, N, X.level));
 }
 static DCt repl_r(Ctx &C, const Keys &K, const DCt &V, int N) {
-    DCt X = ev_copy(C, V);
-    for (int i = 0; i < lg(N); i++) X = add_rot(C, K, X, -((i64)N << i));
-    return X;
+    return rot_add_chain(C, K, V, 0, lg(N), [&](int i) { return -((i64)N << i); });
 }
 static DCt repl_c(Ctx &C, const Keys &K, const DCt &V, int N) {
-    DCt X = ev_copy(C, V);
-    for (int i = 0; i < lg(N); i++) X = add_rot(C, K, X, -((i64)1 << i));
-    return X;
+    return rot_add_chain(C, K, V, 0, lg(N), [&](int i) { return -((i64)1 << i); });
 }
 
 // ------------------------------------------------------------------------
@@ -889,12 +942,14 @@ static DCt cmp_sign(Ctx &C, const Keys &K, const DCt &D, ckr_sign cmp) {
     const int total = cmp.d_g + cmp.d_f;
     if (total < 1) throw Error{CKR_E_INVALID, "empty comparator"};
     if (D.level < 3 * total) throw Error{CKR_E_DEPTH, "comparator depth"};
-    DCt X = ev_copy(C, D);
+    DCt X;
+    const DCt *cur = &D;
     for (int r = 0; r < total; r++) {
         const double *c = r < cmp.d_g ? kG : kF;
         double cc[4];
         for (int i = 0; i < 4; i++) cc[i] = (r == total - 1) ? c[i] * 0.5 : c[i];
-        X = poly7(C, K, X, cc);
+        X = poly7(C, K, *cur, cc);
+        cur = &X;
     }
     return ev_add_const(C, X, 0.5);
 }
@@ -2053,6 +2108,14 @@ ckr_status ckr_autotune(ckr_context *ctx, uint32_t limbs, uint32_t iters, float 
                 C.T.ntt_variant[inv][pass] = bestv;
             }
         for (auto &e : ev) (void)hipEventDestroy(e);
+    });
+}
+
+ckr_status ckr_set_ntt_chunk(ckr_context *ctx, uint32_t limbs) {
+    return guard([&] {
+        NEED(ctx);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
+        ctx->C->ntt_chunk = (int)limbs;
     });
 }
 

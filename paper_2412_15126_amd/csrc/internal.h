@@ -49,6 +49,8 @@ struct LimbBatch {
     int polys;
     size_t poly_stride;
     LimbMap map;
+    const u64 *src = nullptr;  // when set, the first pass reads limb t of poly p from src + p*src_stride + t*n
+    size_t src_stride = 0;
 };
 
 // ---- kernels (ckr_kernels.hip) ------------------------------------------
@@ -75,6 +77,9 @@ struct NttFuse {
     const u64 *add = nullptr;
     size_t add_stride = 0, add_off = 0;
     int add_mask = 0;
+    const u64 *add2 = nullptr;  // a second addend, addressed like add
+    size_t add2_stride = 0, add2_off = 0;
+    int add2_mask = 0;
     LimbScalars c;
 };
 void k_ntt_fused(const DevTables &T, const LimbBatch &b, const NttFuse &f, int pass, hipStream_t s);

@@ -226,3 +226,19 @@ def test_ntt_tile_variants_bit_identical(ckr, name):
         assert np.array_equal(fwd, ref), f"variant {v} forward differs"
     table = ctx.autotune(limbs * 4, 2)
     assert table.shape == (2, 2, 4) and np.all(table > 0)
+
+
+def test_rank8_ntt_chunking_bit_identical(p12):
+    """Cache-chunked transforms give the same ciphertexts as whole dispatches."""
+    N, cmp = 8, W.RANK_CMP[8]
+    cts = [p12.ctx.encrypt(p12.gkeys, W.rank_workload(N, 0.01, 60 + s)[0], p12.P.L, bytes([s] * 32)) for s in range(3)]
+    p12.ctx.set_graphs(False)
+    try:
+        ref = [o.export() for o in p12.ctx.run_batch(p12.gkeys, "rank", cts, N, cmp)]
+        for chunk in (1, 5, 24):
+            p12.ctx.set_ntt_chunk(chunk)
+            got = [o.export() for o in p12.ctx.run_batch(p12.gkeys, "rank", cts, N, cmp)]
+            assert all(np.array_equal(a, b) for a, b in zip(ref, got)), chunk
+    finally:
+        p12.ctx.set_ntt_chunk(0)
+        p12.ctx.set_graphs(True)
