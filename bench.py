@@ -62,6 +62,8 @@ def serve(args):
     kb = b.keygen(bytes(range(3, 35)), p17["L"], [32, 64, 128], what=6)
     a.autotune(2 * 8 * 18, 2)
     b.autotune(2 * 4 * 41, 2)
+    a.autotune_row_ip(8, 2)
+    b.autotune_row_ip(4, 2)
     log(f"[serve] keys ready in {time.time() - t:.1f}s")
     srv = ckr.Server(hbm_budget=args.hbm_budget << 30, max_batch=args.max_batch)
     srv.add_route("rank", 128, a, ka, W.RANK_CMP[128])
@@ -194,6 +196,9 @@ def main():
     table = ctx.autotune(tune_limbs, 3)
     chosen = [[int(np.argmin(table[i][p])) for p in range(2)] for i in range(2)]
     log(f"[bench] autotune ({tune_limbs} limbs): variants fwd {chosen[0]} inv {chosen[1]}")
+    ip_ms = ctx.autotune_row_ip(B, 3)
+    ip_var = int(np.argmin(ip_ms))
+    log(f"[bench] fused row pass + inner product tile: variant {ip_var} ({np.round(ip_ms, 3).tolist()} ms)")
     chunk = args.ntt_chunk
     if chunk < 0:
         # pick the cache chunk by timing one batched step per candidate
@@ -292,7 +297,7 @@ def main():
         "config": {"workload": "rank N=128 at n=2^16 (q0 50-bit + 23 rescale primes near 2^40, 7 special 50-bit "
                                "primes, dnum=3, scale 2^40), encrypted at level 17, comparator g^4 then f",
                    "batch": B, "ranks_exact": bool(exact), "graphs": True,
-                   "ntt_variants": {"fwd": chosen[0], "inv": chosen[1]}, "ntt_chunk_limbs": chunk},
+                   "ntt_variants": {"fwd": chosen[0], "inv": chosen[1]}, "row_ip_variant": ip_var, "ntt_chunk_limbs": chunk},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
                        "per": "step of " + str(B) + " queries"},
         "one_at_a_time": single,

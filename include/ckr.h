@@ -228,8 +228,9 @@ ckr_status ckr_ntt_device(ckr_context *ctx, uint64_t *data, uint32_t limbs, uint
 
 /* Kernel timing.  While enabled, every kernel launch of the evaluator is
  * bracketed by HIP events on the context stream and charged to a category
- * (0 ntt_fwd_col, 1 ntt_fwd_row, 2 ntt_inv_row, 3 ntt_inv_col, 4 bconv, 5 ip,
- * 6 tensor, 7 automorph, 8 combine, 9 elementwise, 10 copy) together with its
+ * (0 ntt_fwd_col, 1 ntt_fwd_row, 2 ntt_inv_row, 3 ntt_inv_col, 4 bconv, 5 ntt_row_ip
+ * (forward row pass fused with the key-switch inner product),
+ * 6 tensor, 7 automorph, 8 elementwise, 9 copy) together with its
  * algorithmic byte count (every operand read once, every result written
  * once).  read returns the launches, summed milliseconds and summed bytes of
  * one category since the last reset; it synchronises the stream. */
@@ -244,12 +245,23 @@ const char *ckr_profile_name(int category);
  * receives the 2 x 2 x 4 average milliseconds [inverse][pass][variant].
  * Every variant computes the same transform bit for bit. */
 ckr_status ckr_autotune(ckr_context *ctx, uint32_t limbs, uint32_t iters, float *ms);
+/* Autotuner of the key switch's fused forward row pass + inner product: times
+ * every tile variant on a synthetic key switch at the top level with `batch`
+ * ciphertexts sharing the key (all-zero operands; device memory of about
+ * batch * (dnum + 2) * (L + 1 + K) limbs is taken from the context pool for
+ * the run), `iters` repetitions, and keeps the fastest.  ms, if not NULL,
+ * receives 7 average milliseconds [variant].  Every variant computes the same
+ * result bit for bit.  Errors: CKR_E_INVALID for batch 0 or above 4096. */
+ckr_status ckr_autotune_row_ip(ckr_context *ctx, uint32_t batch, uint32_t iters, float *ms);
 /* Run transforms of more than `limbs` limbs in chunks of whole polynomials
  * (0 = never), so each chunk's second pass reads data still in the
  * last-level cache.  Results do not depend on the chunking. */
 ckr_status ckr_set_ntt_chunk(ckr_context *ctx, uint32_t limbs);
 /* Force one tile variant (0..3) for a (direction, pass). */
 ckr_status ckr_ntt_variant(ckr_context *ctx, int inverse, int pass, int variant);
+/* Force one tile variant (0..6) of the key switch's fused forward row pass +
+ * inner product (rows of 2^8 points; other ring sizes have one tile). */
+ckr_status ckr_row_ip_variant(ckr_context *ctx, int variant);
 
 /* Wait for all work issued on the context stream. */
 ckr_status ckr_synchronize(ckr_context *ctx);

@@ -93,6 +93,8 @@ _SIGS = {
     "ckr_server_stats": (C.c_int, [vp, C.POINTER(C.c_double)]),
     "ckr_server_free": (None, [vp]),
     "ckr_ntt_variant": (C.c_int, [vp, C.c_int, C.c_int, C.c_int]),
+    "ckr_autotune_row_ip": (C.c_int, [vp, C.c_uint32, C.c_uint32, C.POINTER(C.c_float)]),
+    "ckr_row_ip_variant": (C.c_int, [vp, C.c_int]),
     "ckr_set_ntt_chunk": (C.c_int, [vp, C.c_uint32]),
 }
 
@@ -237,11 +239,20 @@ class Context:
         _ok(lib().ckr_autotune(self.h, limbs, iters, ms))
         return np.array(ms[:], dtype=np.float64).reshape(2, 2, 4)
 
+    def autotune_row_ip(self, batch, iters=3):
+        """Pick the fastest tile of the fused row pass + key-switch inner product; returns ms per variant."""
+        ms = (C.c_float * 7)()
+        _ok(lib().ckr_autotune_row_ip(self.h, int(batch), int(iters), ms))
+        return np.array(ms[:], dtype=np.float64)
+
     def set_ntt_chunk(self, limbs):
         _ok(lib().ckr_set_ntt_chunk(self.h, int(limbs)))
 
     def ntt_variant(self, inverse, pass_, variant):
         _ok(lib().ckr_ntt_variant(self.h, int(inverse), int(pass_), int(variant)))
+
+    def row_ip_variant(self, variant):
+        _ok(lib().ckr_row_ip_variant(self.h, int(variant)))
 
     def set_graphs(self, on):
         _ok(lib().ckr_context_set_graphs(self.h, int(on)))
@@ -305,11 +316,15 @@ class Context:
     def profile(self):
         """{category: (launches, total_ms, bytes)} since the last reset."""
         out = {}
-        for c in range(11):
+        c = 0
+        while True:
+            name = lib().ckr_profile_name(c)
+            if name is None:
+                return out
             a, b, d = C.c_uint64(), C.c_double(), C.c_double()
             _ok(lib().ckr_profile_read(self.h, c, C.byref(a), C.byref(b), C.byref(d)))
-            out[lib().ckr_profile_name(c).decode()] = (a.value, b.value, d.value)
-        return out
+            out[name.decode()] = (a.value, b.value, d.value)
+            c += 1
 
     def ntt_device(self, ptr, limbs, first_mod, inverse):
         _ok(lib().ckr_ntt_device(self.h, vp(ptr), limbs, first_mod, int(inverse)))

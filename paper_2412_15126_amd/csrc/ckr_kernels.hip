@@ -69,63 +69,29 @@ __device__ __forceinline__ double red_any(double x, double q, double qinv) {
 // LDS exchanges; a round's LOGE-bit window of the local index selects which
 // elements a thread holds.  Values stay lazily reduced: [0, 4q) in the
 // forward direction, [0, 2q) in the inverse, canonical at the end.
-template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool FUSE>
-__global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
-    ntt_pass(u64 *__restrict__ base, size_t poly_stride, int limbs, LimbMap map, int logn,
-             const double2 *__restrict__ mq, const double2 *__restrict__ twtab, const double2 *__restrict__ twlast,
-             const NttFuse fz, const u64 *__restrict__ src, size_t src_stride) {
+// The butterfly core of one pass over the C columns (rows) c0 .. c0+C-1 of
+// one limb: reads din (PRO: any uint64, reduced first), runs the pass's
+// stages and hands every final value to emit(k, pos, y), k in [0, E) being
+// the thread's ordinal of that element (the same position for every call
+// from the same thread).
+template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool PRO, class Emit>
+__device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, int logn, int mod, double q,
+                                          double qinv, const double2 *__restrict__ tw,
+                                          const double2 *__restrict__ twlast, double *lds, Emit &&emit) {
     constexpr int S = 1 << LOGS, E = 1 << LOGE, TPC = S / E, NT = C * TPC;
     constexpr int NR = (LOGS + LOGE - 1) / LOGE;
     constexpr int SP = S + (S >> 4) + 1;
     constexpr bool FINAL = (INV == COLPASS);
-    __shared__ double lds[C * SP];
-
-    const int job = blockIdx.y;
-    const int p = job / limbs, t = job - p * limbs;
-    const int mod = map(t);
-    const size_t n = (size_t)1 << logn;
-    u64 *data = base + (size_t)p * poly_stride + (size_t)t * n;
-    constexpr bool FIRST = (COLPASS != INV);  // the pass that runs first reads the input
-    const u64 *din = (FIRST && src) ? src + (size_t)p * src_stride + (size_t)t * n : data;
-    const double q = mq[mod].x, two_q = 2.0 * q, qinv = mq[mod].y;
-    const double2 *tw = twtab + (size_t)mod * n;
-    constexpr bool PRO = FUSE && COLPASS && !INV;   // prologue: broadcast-reduce one limb
-    constexpr bool EPI = FUSE && !COLPASS && !INV;  // epilogue: (x - y) * c (+ add)
-    const u64 *psrc = PRO ? fz.src + (size_t)p * fz.src_stride : nullptr;
-    u64 *pout = nullptr;
-    const u64 *px = nullptr, *padd = nullptr, *padd2 = nullptr;
-    double ec = 0.0, ecq = 0.0;
-    if (EPI) {
-        const size_t pb = (size_t)(p >> 1), pk = (size_t)(p & 1);
-        pout = fz.out + pb * fz.out_stride + pk * fz.out_off + (size_t)t * n;
-        px = fz.x + pb * fz.x_stride + pk * fz.x_off + (size_t)t * n;
-        if (fz.add && (fz.add_mask >> pk & 1)) padd = fz.add + pb * fz.add_stride + pk * fz.add_off + (size_t)t * n;
-        if (fz.add2 && (fz.add2_mask >> pk & 1))
-            padd2 = fz.add2 + pb * fz.add2_stride + pk * fz.add2_off + (size_t)t * n;
-        ec = fz.c.v[t];
-        ecq = fz.c.vq[t];
-    }
-    // final value of the element at position pos of this limb, stored
-    auto emit = [&](size_t pos, double y) {
-        if (EPI) {
-            double r = red1(mm_lazy(u2d(px[pos]) - y + q, ec, ecq, q), q);
-            if (padd) r = red1(r + u2d(padd[pos]), q);
-            if (padd2) r = red1(r + u2d(padd2[pos]), q);
-            pout[pos] = d2u(r);
-        } else {
-            data[pos] = d2u(y);
-        }
-    };
-
-    const int ncol = (int)(n >> LOGS);
-    const int c0 = blockIdx.x * C;
+    const double two_q = 2.0 * q;
+    const int ncol = 1 << (logn - LOGS);
     const int tid = threadIdx.x;
     const int cl = COLPASS ? (tid % C) : (tid / TPC);
     const int tau = COLPASS ? (tid / C) : (tid % TPC);
     const int c = c0 + cl;
     const int g0 = COLPASS ? 0 : (logn - LOGS);
     const int cpart = COLPASS ? 0 : c;
-    auto gaddr = [&](int r) -> size_t { return COLPASS ? (size_t)r * ncol + c : (size_t)c * S + r; };
+    // positions within one limb fit 32 bits (n <= 2^17): offsets from a uniform base
+    auto gaddr = [&](int r) -> u32 { return COLPASS ? (u32)(r * ncol + c) : (u32)(c * S + r); };
     auto lidx = [&](int cc, int r) -> int { return cc * SP + r + (r >> 4); };
 
     double x[E];
@@ -140,13 +106,13 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
         if (rho == 0) {
             if (PRO) {
 #pragma unroll
-                for (int k = 0; k < E; k++) x[k] = red_any(u2d(psrc[gaddr(rbase | (k << w))]), q, qinv);
+                for (int k = 0; k < E; k++) x[k] = red_any(u2d(din[gaddr(rbase | (k << w))]), q, qinv);
             } else if (direct) {
 #pragma unroll
                 for (int k = 0; k < E; k++) x[k] = u2d(din[gaddr(rbase | (k << w))]);
             } else {
                 // rows are contiguous: the tile is C*S consecutive words
-                const u64 *tile = din + (size_t)c0 * S;
+                const u64 *tile = din + (u32)(c0 * S);
                 for (int i = tid; i < C * S; i += NT) lds[lidx(i / S, i % S)] = u2d(tile[i]);
                 __syncthreads();
 #pragma unroll
@@ -214,13 +180,17 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
             }
             if (direct) {
 #pragma unroll
-                for (int k = 0; k < E; k++) emit(gaddr(rbase | (k << w)), x[k]);
+                for (int k = 0; k < E; k++) emit(k, gaddr(rbase | (k << w)), x[k]);
             } else {
                 __syncthreads();
 #pragma unroll
                 for (int k = 0; k < E; k++) lds[lidx(cl, rbase | (k << w))] = x[k];
                 __syncthreads();
-                for (int i = tid; i < C * S; i += NT) emit((size_t)c0 * S + i, lds[lidx(i / S, i % S)]);
+#pragma unroll
+                for (int k = 0; k < E; k++) {
+                    const int i = tid + k * NT;
+                    emit(k, (u32)(c0 * S + i), lds[lidx(i / S, i % S)]);
+                }
             }
         } else {
             __syncthreads();
@@ -229,6 +199,144 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
             __syncthreads();
         }
     }
+}
+
+// Forward transform (Cooley-Tukey, merged psi twiddles): stage g pairs indices
+// j, j + n/2^{g+1} with twiddle tw[2^g + (j >> (logn - g))].  The first logn1
+// stages act on columns {c + n2 r}, the rest on contiguous rows of n2.  The
+// inverse runs the Gentleman-Sande butterflies in the opposite stage order,
+// rows first, and folds n^{-1} into its final stage.
+//
+// A workgroup owns C columns (or rows) of S = 2^LOGS elements.  Each thread
+// holds E = 2^LOGE elements in registers and runs up to LOGE stages between
+// LDS exchanges; a round's LOGE-bit window of the local index selects which
+// elements a thread holds.  Values stay lazily reduced: [0, 4q) in the
+// forward direction, [0, 2q) in the inverse, canonical at the end.
+template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool FUSE>
+__global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
+    ntt_pass(u64 *__restrict__ base, size_t poly_stride, int limbs, LimbMap map, int logn,
+             const double2 *__restrict__ mq, const double2 *__restrict__ twtab, const double2 *__restrict__ twlast,
+             const NttFuse fz, const u64 *__restrict__ src, size_t src_stride) {
+    constexpr int S = 1 << LOGS;
+    constexpr int SP = S + (S >> 4) + 1;
+    __shared__ double lds[C * SP];
+
+    const int job = blockIdx.y;
+    const int p = job / limbs, t = job - p * limbs;
+    const int mod = map(t);
+    const size_t n = (size_t)1 << logn;
+    u64 *data = base + (size_t)p * poly_stride + (size_t)t * n;
+    constexpr bool FIRST = (COLPASS != INV);  // the pass that runs first reads the input
+    const u64 *din = (FIRST && src) ? src + (size_t)p * src_stride + (size_t)t * n : data;
+    const double q = mq[mod].x, qinv = mq[mod].y;
+    const double2 *tw = twtab + (size_t)mod * n;
+    constexpr bool PRO = FUSE && COLPASS && !INV;   // prologue: broadcast-reduce one limb
+    constexpr bool EPI = FUSE && !COLPASS && !INV;  // epilogue: (x - y) * c (+ add)
+    const int c0 = blockIdx.x * C;
+    if constexpr (EPI) {
+        const size_t pb = (size_t)(p >> 1), pk = (size_t)(p & 1);
+        u64 *pout = fz.out + pb * fz.out_stride + pk * fz.out_off + (size_t)t * n;
+        const u64 *px = fz.x + pb * fz.x_stride + pk * fz.x_off + (size_t)t * n;
+        const u64 *padd = nullptr, *padd2 = nullptr;
+        if (fz.add && (fz.add_mask >> pk & 1)) padd = fz.add + pb * fz.add_stride + pk * fz.add_off + (size_t)t * n;
+        if (fz.add2 && (fz.add2_mask >> pk & 1))
+            padd2 = fz.add2 + pb * fz.add2_stride + pk * fz.add2_off + (size_t)t * n;
+        const double ec = fz.c.v[t], ecq = fz.c.vq[t];
+        pass_core<LOGS, LOGE, C, COLPASS, INV, false>(din, c0, logn, mod, q, qinv, tw, twlast, lds,
+                                                      [&](int, u32 pos, double y) {
+            double r = red1(mm_lazy(u2d(px[pos]) - y + q, ec, ecq, q), q);
+            if (padd) r = red1(r + u2d(padd[pos]), q);
+            if (padd2) r = red1(r + u2d(padd2[pos]), q);
+            pout[pos] = d2u(r);
+        });
+    } else if constexpr (PRO) {
+        pass_core<LOGS, LOGE, C, COLPASS, INV, true>(fz.src + (size_t)p * fz.src_stride, c0, logn, mod, q, qinv, tw,
+                                                     twlast, lds, [&](int, u32 pos, double y) { data[pos] = d2u(y); });
+    } else {
+        pass_core<LOGS, LOGE, C, COLPASS, INV, false>(din, c0, logn, mod, q, qinv, tw, twlast, lds,
+                                                      [&](int, u32 pos, double y) { data[pos] = d2u(y); });
+    }
+}
+
+// Key-switch ModUp tail: the forward row pass of every digit's extended limb
+// t fused with the inner product against the switching key,
+//   accb[t] = sum_j X_j[t] kb_j[t],  acca[t] = sum_j X_j[t] ka_j[t],
+// X_j[t] = d[t] for the digit that holds limb t, else the row-pass output of
+// ext[j][t] (which has had its column pass).  One workgroup per (batch entry,
+// limb, tile of C rows); the extended limbs never go back to HBM in the
+// evaluation domain.  Workgroups are dealt to the 8 XCDs round-robin, so the
+// workgroup index is decoded as (xcd, then per-XCD sequence): the B batch
+// entries of one (limb, tile) run back to back on one XCD and read that
+// tile's key words from its L2.
+template <int LOGS, int LOGE, int C>
+__global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
+    ntt_row_ip(const IPArgs a, int logn, const double2 *__restrict__ mq, const double2 *__restrict__ twtab,
+               const double2 *__restrict__ twlast) {
+    constexpr int S = 1 << LOGS, E = 1 << LOGE, NT = C * (S / E);
+    constexpr int SP = S + (S >> 4) + 1;
+    __shared__ double lds[C * SP];
+    const size_t n = (size_t)1 << logn;
+    const int tiles = (int)(n >> LOGS) / C;
+    const int wg = blockIdx.x, xcd = wg & 7, seq = wg >> 3;
+    const int gl = seq / a.B, bi = seq - gl * a.B;
+    const int g = gl * 8 + xcd;
+    if (g >= a.E * tiles) return;
+    const int t = g / tiles, c0 = (g - t * tiles) * C;
+    const int mod = t <= a.level ? t : a.nq + (t - a.level - 1);
+    const int kl = t <= a.level ? t : a.lmax_key + 1 + (t - a.level - 1);
+    const double q = mq[mod].x, qinv = mq[mod].y;
+    const double2 *tw = twtab + (size_t)mod * n;
+    const int own = (t <= a.level) ? t / a.alpha : -1;  // digit holding limb t, if any
+    const int tid = threadIdx.x;
+    double sb[E], sa[E];
+#pragma unroll
+    for (int k = 0; k < E; k++) sb[k] = sa[k] = 0.0;
+    for (int j = 0; j < a.beta; j++) {
+        // this digit's key words, loaded before the butterflies so that their
+        // latency hides behind the pass (loaded at the point of use, each one
+        // would be a separate round trip)
+        const u64 *kb = a.key + (((size_t)j * 2 + 0) * a.Ek + kl) * n;
+        const u64 *ka = a.key + (((size_t)j * 2 + 1) * a.Ek + kl) * n;
+        u64 kbw[E], kaw[E];
+#pragma unroll
+        for (int k = 0; k < E; k++) {
+            const u32 pos = (u32)(c0 * S + tid + k * NT);
+            kbw[k] = kb[pos];
+            kaw[k] = ka[pos];
+        }
+        auto acc = [&](int k, u32, double x) {
+            sb[k] = red1(sb[k] + pos1(mm_signed(x, u2d(kbw[k]), q, qinv), q), q);
+            sa[k] = red1(sa[k] + pos1(mm_signed(x, u2d(kaw[k]), q, qinv), q), q);
+        };
+        if (j == own) {
+            const u64 *xs = a.d + bi * a.sd + (size_t)t * n;
+            double xv[E];
+#pragma unroll
+            for (int k = 0; k < E; k++) xv[k] = u2d(xs[(u32)(c0 * S + tid + k * NT)]);
+#pragma unroll
+            for (int k = 0; k < E; k++) acc(k, 0, xv[k]);
+        } else {
+            __syncthreads();  // the previous digit's last LDS reads are done
+            pass_core<LOGS, LOGE, C, false, false, false>(a.ext + bi * a.sext + ((size_t)j * a.E + t) * n, c0, logn,
+                                                          mod, q, qinv, tw, twlast, lds, acc);
+        }
+    }
+    u64 *ob = a.accb + bi * a.sacc + (size_t)t * n, *oa = a.acca + bi * a.sacc + (size_t)t * n;
+#pragma unroll
+    for (int k = 0; k < E; k++) {
+        const u32 pos = (u32)(c0 * S + tid + k * NT);
+        ob[pos] = d2u(sb[k]);
+        oa[pos] = d2u(sa[k]);
+    }
+}
+
+template <int LOGS, int LOGE, int C>
+static void launch_row_ip(const DevTables &T, const IPArgs &a, hipStream_t s) {
+    const int tiles = (1 << (T.logn - LOGS)) / C;
+    const int groups = a.E * tiles;
+    const unsigned blocks = (unsigned)(((groups + 7) / 8) * 8) * (unsigned)a.B;
+    hipLaunchKernelGGL((ntt_row_ip<LOGS, LOGE, C>), dim3(blocks), dim3(C * (1 << (LOGS - LOGE))), 0, s, a, T.logn,
+                       T.mq, T.tw_fwd, T.tw_last);
 }
 
 template <int LOGS, int LOGE, int C, bool COLPASS, bool INV>
@@ -293,6 +401,42 @@ static void run_pass(const DevTables &T, const LimbBatch &b, bool inv, int pass,
     case 15: pass_dispatch<8, 7>(T, b, inv, pass, s, f, v); break;
     case 16: pass_dispatch<8, 8>(T, b, inv, pass, s, f, v); break;
     case 17: pass_dispatch<9, 8>(T, b, inv, pass, s, f, v); break;
+    default: break;
+    }
+}
+
+// tiles of the fused row pass + inner product, (elements per thread, rows per
+// workgroup) for passes of 2^8 points: 0 (8, 16), 1 (8, 8), 2 (8, 4), 3 (8, 2),
+// 4 (4, 4), 5 (4, 2), 6 (4, 1); smaller passes: one fixed tile
+template <int LOGS>
+static void row_ip_variant(const DevTables &T, const IPArgs &a, hipStream_t s, int v) {
+    if constexpr (LOGS == 8) {
+        switch (v) {
+        case 1: launch_row_ip<8, 3, 8>(T, a, s); return;
+        case 2: launch_row_ip<8, 3, 4>(T, a, s); return;
+        case 3: launch_row_ip<8, 3, 2>(T, a, s); return;
+        case 4: launch_row_ip<8, 2, 4>(T, a, s); return;
+        case 5: launch_row_ip<8, 2, 2>(T, a, s); return;
+        case 6: launch_row_ip<8, 2, 1>(T, a, s); return;
+        default: launch_row_ip<8, 3, 16>(T, a, s); return;
+        }
+    } else if constexpr (LOGS == 7) {
+        launch_row_ip<7, 3, 4>(T, a, s);
+    } else if constexpr (LOGS == 6) {
+        launch_row_ip<6, 3, 8>(T, a, s);
+    } else {
+        launch_row_ip<5, 3, 16>(T, a, s);
+    }
+}
+
+void k_ntt_row_ip(const DevTables &T, const IPArgs &a, hipStream_t s) {
+    if (a.E == 0 || a.B == 0) return;
+    const int v = T.row_ip_variant;
+    switch (T.logn) {
+    case 10: case 11: row_ip_variant<5>(T, a, s, v); break;
+    case 12: case 13: row_ip_variant<6>(T, a, s, v); break;
+    case 14: case 15: row_ip_variant<7>(T, a, s, v); break;
+    case 16: case 17: row_ip_variant<8>(T, a, s, v); break;
     default: break;
     }
 }
@@ -481,43 +625,6 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-// one thread per (target limb, coefficient) walks the whole batch: each key
-// word is read once per batch, not once per query
-__global__ void ew_ip(IPArgs a, int logn, const double2 *mq) {
-    constexpr int kMaxBeta = 8;
-    const size_t n = (size_t)1 << logn;
-    const size_t c = ((size_t)blockIdx.x * blockDim.x + threadIdx.x);
-    if (c >= n) return;
-    const int t = blockIdx.y;  // target limb in [0, E)
-    const int mod = t <= a.level ? t : a.nq + (t - a.level - 1);
-    const int kl = t <= a.level ? t : a.lmax_key + 1 + (t - a.level - 1);
-    const double2 Q = mq[mod];
-    double kb[kMaxBeta], ka[kMaxBeta];
-#pragma unroll
-    for (int j = 0; j < kMaxBeta; j++) {
-        if (j < a.beta) {
-            kb[j] = u2d(a.key[(((size_t)j * 2 + 0) * a.Ek + kl) * n + c]);
-            ka[j] = u2d(a.key[(((size_t)j * 2 + 1) * a.Ek + kl) * n + c]);
-        }
-    }
-    const int own = (t <= a.level) ? t / a.alpha : -1;  // digit holding limb t, if any
-    for (int bi = 0; bi < a.B; bi++) {
-        double sb = 0.0, sa = 0.0;
-#pragma unroll
-        for (int j = 0; j < kMaxBeta; j++) {
-            if (j < a.beta) {
-                const u64 *xs = (j == own) ? a.d + bi * a.sd + (size_t)t * n
-                                           : a.ext + bi * a.sext + ((size_t)j * a.E + t) * n;
-                const double x = u2d(xs[c]);
-                sb = red1(sb + pos1(mm_signed(x, kb[j], Q.x, Q.y), Q.x), Q.x);
-                sa = red1(sa + pos1(mm_signed(x, ka[j], Q.x, Q.y), Q.x), Q.x);
-            }
-        }
-        a.accb[bi * a.sacc + (size_t)t * n + c] = d2u(sb);
-        a.acca[bi * a.sacc + (size_t)t * n + c] = d2u(sa);
-    }
-}
-
 __global__ void ew_check_range(const u64 *data, int limbs, size_t stride, int logn, const u64 *qi, int *flag) {
     EW_PROLOGUE
     const u64 q = qi[t];
@@ -580,10 +687,6 @@ void k_bconv(const DevTables &T, u64 *out, const u64 *src, const BConvTab &tab, 
     default: break;
     }
 #undef BCONV_CASE
-}
-void k_ip(const DevTables &T, const IPArgs &a, hipStream_t s) {
-    dim3 grid((unsigned)(((1u << T.logn) + 255) / 256), (unsigned)a.E);
-    hipLaunchKernelGGL(ew_ip, grid, dim3(256), 0, s, a, T.logn, T.mq);
 }
 void k_check_range(const DevTables &T, const u64 *data, int limbs, int polys, size_t stride, int *flag,
                    hipStream_t s) {

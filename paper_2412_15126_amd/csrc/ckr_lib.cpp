@@ -195,10 +195,10 @@ struct PlainKey {
 };
 
 enum ProfCat {
-    kNttFwdCol, kNttFwdRow, kNttInvRow, kNttInvCol, kBConv, kIP, kTensor, kAutomorph, kCombine, kElem, kCopy, kNCat
+    kNttFwdCol, kNttFwdRow, kNttInvRow, kNttInvCol, kBConv, kNttRowIP, kTensor, kAutomorph, kElem, kCopy, kNCat
 };
-static const char *kCatName[kNCat] = {"ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "bconv", "ip",
-                                      "tensor", "automorph", "combine", "elementwise", "copy"};
+static const char *kCatName[kNCat] = {"ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "bconv",
+                                      "ntt_row_ip", "tensor", "automorph", "elementwise", "copy"};
 
 // opt-in per-category kernel timing with HIP events on the context stream
 struct Prof {
@@ -368,6 +368,12 @@ static void ntt(Ctx &C, u64 *base, int limbs, int polys, size_t stride, LimbMap 
         timed(C, inv ? kNttInvRow : kNttFwdCol, bytes, [&] { k_ntt_pass(C.T, b, inv, 0, C.stream); });
         timed(C, inv ? kNttInvCol : kNttFwdRow, bytes, [&] { k_ntt_pass(C.T, b, inv, 1, C.stream); });
     });
+}
+
+// the first (column) pass of the forward transform only
+static void ntt_first(Ctx &C, u64 *base, int limbs, int polys, size_t stride, LimbMap map) {
+    LimbBatch b{base, limbs, polys, stride, map};
+    timed(C, kNttFwdCol, 16.0 * C.P.n * limbs * polys, [&] { k_ntt_pass(C.T, b, false, 0, C.stream); });
 }
 
 // forward transform with the fused prologue / epilogue of NttFuse.  The
@@ -681,10 +687,11 @@ static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_
         timed(C, kBConv, 8.0 * n * (tab.ns + tab.nt) * B, [&] {
             k_bconv(C.T, ej, dc.get() + (size_t)lo * n, tab, B, sext, (size_t)(l + 1) * n, C.stream);
         });
-        if (lo > 0) ntt(C, ej, lo, B, sext, plain_map(), false);
-        if (hi + 1 < E) ntt(C, ej + (size_t)(hi + 1) * n, E - hi - 1, B, sext, LimbMap{l - hi, hi + 1, P.nq}, false);
+        // column pass only: the row pass runs fused with the inner product below
+        if (lo > 0) ntt_first(C, ej, lo, B, sext, plain_map());
+        if (hi + 1 < E) ntt_first(C, ej + (size_t)(hi + 1) * n, E - hi - 1, B, sext, LimbMap{l - hi, hi + 1, P.nq});
     }
-    // inner product with the key digits
+    // row pass + inner product with the key digits
     const size_t sacc = (size_t)2 * E * n;
     Buf acc(&C, (size_t)B * sacc);
     IPArgs ia;
@@ -705,7 +712,7 @@ static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_
     ia.sext = sext;
     ia.sacc = sacc;
     // per target limb: beta inputs and 2 outputs per batch entry, 2*beta key limbs once
-    timed(C, kIP, 8.0 * n * E * ((beta + 2.0) * B + 2.0 * beta), [&] { k_ip(C.T, ia, C.stream); });
+    timed(C, kNttRowIP, 8.0 * n * E * ((beta + 2.0) * B + 2.0 * beta), [&] { k_ntt_row_ip(C.T, ia, C.stream); });
     // ModDown: (x_Q - BConv_{P->Q}(x_P)) * P^{-1}, the combine fused into the last NTT pass
     ntt(C, acc.get() + (size_t)(l + 1) * n, P.K, 2 * B, (size_t)E * n, plain_map(P.nq), true);
     Buf conv(&C, (size_t)2 * B * (l + 1) * n);
@@ -2111,6 +2118,61 @@ ckr_status ckr_autotune(ckr_context *ctx, uint32_t limbs, uint32_t iters, float 
     });
 }
 
+ckr_status ckr_autotune_row_ip(ckr_context *ctx, uint32_t batch, uint32_t iters, float *ms) {
+    return guard([&] {
+        NEED(ctx);
+        if (batch == 0 || batch > 4096) throw Error{CKR_E_INVALID, "batch"};
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
+        Ctx &C = *ctx->C;
+        const Params &P = C.P;
+        iters = std::max(1u, iters);
+        const size_t n = C.n();
+        const int l = P.nq - 1, E = l + 1 + P.K, beta = P.beta(l);
+        const int B = (int)batch;
+        Buf d(&C, (size_t)B * (l + 1) * n), ext(&C, (size_t)B * beta * E * n), key(&C, (size_t)beta * 2 * E * n),
+            acc(&C, (size_t)B * 2 * E * n);
+        for (const Buf *b : {&d, &ext, &key})
+            HIPCHK(hipMemsetAsync(b->get(), 0, b->words() * 8, C.stream));
+        IPArgs ia;
+        ia.d = d.get();
+        ia.ext = ext.get();
+        ia.key = key.get();
+        ia.accb = acc.get();
+        ia.acca = acc.get() + (size_t)E * n;
+        ia.level = l;
+        ia.E = E;
+        ia.beta = beta;
+        ia.alpha = P.alpha;
+        ia.Ek = E;
+        ia.lmax_key = l;
+        ia.nq = P.nq;
+        ia.B = B;
+        ia.sd = (size_t)(l + 1) * n;
+        ia.sext = (size_t)beta * E * n;
+        ia.sacc = (size_t)2 * E * n;
+        hipEvent_t ev[2];
+        for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+        const int keep = C.T.row_ip_variant;
+        float best = 1e30f;
+        int bestv = keep;
+        for (int v = 0; v < kRowIpVariants; v++) {
+            C.T.row_ip_variant = v;
+            k_ntt_row_ip(C.T, ia, C.stream);  // warm
+            HIPCHK(hipEventRecord(ev[0], C.stream));
+            for (u32 it = 0; it < iters; it++) k_ntt_row_ip(C.T, ia, C.stream);
+            HIPCHK(hipEventRecord(ev[1], C.stream));
+            HIPCHK(hipEventSynchronize(ev[1]));
+            float t = 0;
+            HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1]));
+            t /= (float)iters;
+            if (ms) ms[v] = t;
+            if (t < best) best = t, bestv = v;
+        }
+        C.T.row_ip_variant = bestv;
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    });
+}
+
 ckr_status ckr_set_ntt_chunk(ckr_context *ctx, uint32_t limbs) {
     return guard([&] {
         NEED(ctx);
@@ -2125,6 +2187,15 @@ ckr_status ckr_ntt_variant(ckr_context *ctx, int inverse, int pass, int variant)
         if (inverse < 0 || inverse > 1 || pass < 0 || pass > 1 || variant < 0 || variant >= kNttVariants)
             throw Error{CKR_E_INVALID, "variant"};
         ctx->C->T.ntt_variant[inverse][pass] = variant;
+    });
+}
+
+ckr_status ckr_row_ip_variant(ckr_context *ctx, int variant) {
+    return guard([&] {
+        NEED(ctx);
+        if (variant < 0 || variant >= kRowIpVariants) throw Error{CKR_E_INVALID, "variant"};
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
+        ctx->C->T.row_ip_variant = variant;
     });
 }
 

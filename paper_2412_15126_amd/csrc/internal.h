@@ -38,8 +38,10 @@ struct DevTables {
     double2 *tw_inv;  // [nmod][n] {w, w/q}, w = psi^{-brev(i)}
     double2 *tw_last; // [nmod][2]: {n^-1, n^-1/q}, {psi^{-brev(1)} n^-1, ./q}
     int ntt_variant[2][2] = {{0, 0}, {0, 0}};  // [inverse][pass]: tile variant chosen by the autotuner
+    int row_ip_variant = 2;                      // tile of the fused row pass + inner product
 };
 constexpr int kNttVariants = 4;
+constexpr int kRowIpVariants = 7;
 
 // description of a batch of limbs: `polys` groups of `limbs` limbs, group p
 // starting at base + p * poly_stride, limbs n words apart
@@ -131,7 +133,9 @@ struct IPArgs {
     int B;                       // batch of inputs sharing the key
     size_t sd, sext, sacc;       // batch strides of d, ext, accb/acca
 };
-void k_ip(const DevTables &T, const IPArgs &a, hipStream_t s);
+// computed with the forward row pass of ext fused in front: ext holds the
+// extended limbs after their column pass only
+void k_ntt_row_ip(const DevTables &T, const IPArgs &a, hipStream_t s);
 
 // reduce arbitrary uint64 values to canonical residues (import check helper):
 // flags[0] set to 1 if any value >= its modulus

@@ -31,7 +31,7 @@ class Pair:
     """Same parameter set, keys and seeds on both sides."""
 
     def __init__(self, ora, ckr, name, lmax, shifts=(), Ns=(), seed=bytes(range(32))):
-        self.ps = W.PSETS[name]
+        self.ps = W.PSETS[name] if isinstance(name, str) else name
         self.P = ora.Params(**self.ps)
         self.ctx = ckr.Context(self.ps)
         self.ora = ora
@@ -226,6 +226,42 @@ def test_ntt_tile_variants_bit_identical(ckr, name):
         assert np.array_equal(fwd, ref), f"variant {v} forward differs"
     table = ctx.autotune(limbs * 4, 2)
     assert table.shape == (2, 2, 4) and np.all(table > 0)
+
+
+@pytest.mark.parametrize("logn", [11, 13, 14, 15])
+def test_keyswitch_other_ring_sizes_bit_exact(ora, ckr, logn):
+    """Rotation and relinearisation (ModUp, fused row pass + inner product,
+    ModDown) at the ring sizes whose transforms use 5-, 6- and 7-bit rows."""
+    ps = dict(logn=logn, L=5, q0_bits=44, log_scale=36, K=3, p_bits=46, dnum=3)
+    say(f"[gpu] key switch at n=2^{logn}")
+    pr = Pair(ora, ckr, ps, ps["L"], shifts=(1, -7))
+    v = np.random.default_rng(logn).uniform(0, 1, pr.n // 2)
+    for level in (ps["L"], 2):
+        o, g = pr.enc(v, level, bytes([logn] * 32))
+        same(o, g, "encrypt")
+        same(ora.rotate(pr.okeys, o, 1), pr.ctx.rotate(pr.gkeys, g, 1), f"rotate level {level}")
+        same(ora.rotate(pr.okeys, o, -7), pr.ctx.rotate(pr.gkeys, g, -7), f"rotate -7 level {level}")
+        same(ora.mul(pr.okeys, o, o), pr.ctx.mul(pr.gkeys, g, g), f"mul level {level}")
+
+
+def test_row_ip_tile_variants_bit_identical(ckr):
+    """Every tile of the fused row pass + inner product gives the same
+    relinearised product at n = 2^16 (rows of 2^8 points)."""
+    ps = W.PSETS["P16"]
+    ctx = ckr.Context(ps)
+    keys = ctx.keygen(bytes(range(9, 41)), 9, [])
+    v = np.random.default_rng(5).uniform(0, 1, 1 << 15)
+    cts = [ctx.encrypt(keys, v, lv, bytes([lv] * 32)) for lv in (9, 4)]
+    ref = None
+    for var in range(7):
+        say(f"[gpu] row_ip variant {var}")
+        ctx.row_ip_variant(var)
+        got = [ctx.mul(keys, c, c).export() for c in cts]
+        if ref is None:
+            ref = got
+        assert all(np.array_equal(a, b) for a, b in zip(ref, got)), f"variant {var}"
+    ms = ctx.autotune_row_ip(4, 2)
+    assert ms.shape == (7,) and np.all(ms > 0)
 
 
 def test_rank8_ntt_chunking_bit_identical(p12):
