@@ -1009,7 +1009,9 @@ ora_ct *ora_poly7(const ora_keys *Kp, const ora_ct *x, const double a[4], int *s
 }
 
 /* g applied d_g times then f applied d_f times, the last polynomial scaled by 1/2, then + 1/2 */
-ora_ct *ora_cmp_sign(const ora_keys *Kp, const ora_ct *D, int dg, int df, int *st) {
+/* a * Cmp = a * (f^{d_f}(g^{d_g}(D)) + 1) / 2, the factor a/2 folded into
+ * the last polynomial and a/2 added as a constant */
+static ora_ct *cmp_sign_scaled(const ora_keys *Kp, const ora_ct *D, int dg, int df, double a, int *st) {
     if (dg + df < 1) { *st = ORA_E_INVALID; return NULL; }
     if (D->level < 3 * (dg + df)) { *st = ORA_E_DEPTH; return NULL; }
     ora_ct *X = ct_copy(D);
@@ -1017,11 +1019,15 @@ ora_ct *ora_cmp_sign(const ora_keys *Kp, const ora_ct *D, int dg, int df, int *s
     for (int r = 0; r < total; r++) {
         const double *c = r < dg ? G_COEF : F_COEF;
         double cc[4];
-        for (int i = 0; i < 4; i++) cc[i] = (r == total - 1) ? c[i] * 0.5 : c[i];
+        for (int i = 0; i < 4; i++) cc[i] = (r == total - 1) ? c[i] * (a * 0.5) : c[i];
         replace(&X, ora_poly7(Kp, X, cc, st));
     }
-    replace(&X, ora_add_const(X, 0.5));
+    replace(&X, ora_add_const(X, a * 0.5));
     return X;
+}
+
+ora_ct *ora_cmp_sign(const ora_keys *Kp, const ora_ct *D, int dg, int df, int *st) {
+    return cmp_sign_scaled(Kp, D, dg, df, 1.0, st);
 }
 
 /* ------------------------------------------------------------------ */
@@ -1035,16 +1041,20 @@ static int check_N(const ora_params *P, u32 N) {
 /* levels consumed by rank: MaskC of TransR, the comparator, MaskR of SumR */
 int ora_rank_depth(int dg, int df) { return 2 + 3 * (dg + df); }
 
-/* C = Cmp(V_R, V_C) as an N x N matrix (C[i][j] = Cmp(v_j, v_i)) */
-ora_ct *ora_cmp_matrix(const ora_keys *Kp, const ora_ct *V, u32 N, int dg, int df, int *st) {
+/* a * C with C = Cmp(V_R, V_C) as an N x N matrix (C[i][j] = Cmp(v_j, v_i)) */
+static ora_ct *cmp_matrix_scaled(const ora_keys *Kp, const ora_ct *V, u32 N, int dg, int df, double a, int *st) {
     ora_ct *VR = ora_repl_r(Kp, V, N, st);
     ora_ct *T = ora_trans_r(Kp, V, N, st);
     ora_ct *VC = ora_repl_c(Kp, T, N, st);
     ora_ct *VRa = ora_cmul_to(VR, 1.0, VC->level, st);
     ora_ct *D = ora_sub(VRa, VC);
-    ora_ct *C = ora_cmp_sign(Kp, D, dg, df, st);
+    ora_ct *C = cmp_sign_scaled(Kp, D, dg, df, a, st);
     ora_ct_free(VR); ora_ct_free(T); ora_ct_free(VC); ora_ct_free(VRa); ora_ct_free(D);
     return C;
+}
+
+ora_ct *ora_cmp_matrix(const ora_keys *Kp, const ora_ct *V, u32 N, int dg, int df, int *st) {
+    return cmp_matrix_scaled(Kp, V, N, dg, df, 1.0, st);
 }
 
 ora_ct *ora_rank(const ora_keys *Kp, const ora_ct *V, u32 N, int dg, int df, int *status) {
@@ -1088,33 +1098,79 @@ u32 ora_galois_left(const ora_params *P, u64 k) { return gal_left(P, k); }
 /* multiply by the signed integer K without rescaling (scale unchanged) */
 ora_ct *ora_mul_int(const ora_ct *a, i64 K) { return mul_int(a, K); }
 
-/* levels: TransR mask, comparator, E, E*mask, SumR mask, scaling, indicator, O*V, SumC mask */
-int ora_argmin_depth(int cdg, int cdf, int idg, int idf) { return 1 + 3 * (cdg + cdf) + 3 + 1 + 3 * (idg + idf) + 2; }
+/* Order statistic k (Algorithm Order Statistic, section 3.2), optionally with
+ * the tie-correction offset of section 4.  The indicator of "the k-th
+ * smallest" is one-sided at the ends (k = 1: Cmp(1.5, k_j); k = N:
+ * Cmp(k_j, N - 1/2); the k_j are integral) and the window
+ * Cmp(x, -1/2) (1 - Cmp(x, 1/2)) on x = k_j - k otherwise, every comparison
+ * taken on its argument divided by N.
+ *
+ * With tie-correction, k_j = SumR(C + E (delta_{j>=i} - 1/2)), E = C (4 - 4C)
+ * (rank plus offset; their +1/2 and -1/2 cancel), which is a permutation of
+ * 1..N: among equal values the lowest index is taken first.
+ * Without it, k_j is the rank R_j = SumR(C) + 1/2; the factor +-1/N is folded
+ * into the comparator's last polynomial, and SumR keeps no row mask: the
+ * other rows hold bounded garbage that O * V annihilates (V is zero outside
+ * row 0).  onehot = MaskR(O, 0); value = SumC(O * V) in slot 0. */
+int ora_order_stat_depth(u32 N, u32 k, int cdg, int cdf, int idg, int idf, int tie) {
+    int ind = 3 * (idg + idf) + ((k > 1 && k < N) ? 1 : 0);
+    /* TransR mask, comparator, [E, E*mask, SumR mask, scaling,] indicator, O*V, SumC mask */
+    return 1 + 3 * (cdg + cdf) + (tie ? 4 : 0) + ind + 2;
+}
 
-/* k = SumR(C + E (delta_{j>=i} - 1/2)), E = C (4 - 4C)  (= Rank + offset; the
- * +1/2 of Rank and the -1/2 of the offset cancel).  O = Cmp(1.5, k) evaluated
- * on (1.5 - k)/N: k >= 1 is integral, so k < 1.5 singles out rank 1.
- * onehot = MaskR(O, 0); value = SumC(O * V) in slot 0. */
-int ora_argmin(const ora_keys *Kp, const ora_ct *V, u32 N, int cdg, int cdf, int idg, int idf, ora_ct **onehot,
-               ora_ct **value) {
+int ora_argmin_depth(int cdg, int cdf, int idg, int idf) { return ora_order_stat_depth(2, 1, cdg, cdf, idg, idf, 1); }
+
+int ora_order_stat(const ora_keys *Kp, const ora_ct *V, u32 N, u32 k, int cdg, int cdf, int idg, int idf, int tie,
+                   ora_ct **onehot, ora_ct **value) {
     int st = check_N(Kp->P, N);
     if (st != ORA_OK) return st;
-    if (V->level < ora_argmin_depth(cdg, cdf, idg, idf)) return ORA_E_DEPTH;
-    ora_ct *C = ora_cmp_matrix(Kp, V, N, cdg, cdf, &st);
-    ora_ct *m4 = mul_int(C, -4);
-    ora_ct *w = ora_add_const(m4, 4.0);
-    ora_ct *E = ora_mul(Kp, C, w, &st);
-    double *tie = (double *)calloc((size_t)N * N, sizeof(double));
-    for (u32 i = 0; i < N; i++)
-        for (u32 j = 0; j < N; j++) tie[i * N + j] = j >= i ? 0.5 : -0.5;
-    ora_ct *Et = ora_mul_plain(E, tie, N * N, &st);
-    free(tie);
-    ora_ct *Ca = ora_cmul_to(C, 1.0, Et->level, &st);
-    ora_ct *X = ora_add(Ca, Et);
-    ora_ct *k = ora_sum_r(Kp, X, N, &st);
-    ora_ct *ks = ora_cmul_to(k, -1.0 / (double)N, k->level - 1, &st);
-    ora_ct *d = ora_add_const(ks, 1.5 / (double)N);
-    ora_ct *O = ora_cmp_sign(Kp, d, idg, idf, &st);
+    if (k < 1 || k > N) return ORA_E_INVALID;
+    if (V->level < ora_order_stat_depth(N, k, cdg, cdf, idg, idf, tie)) return ORA_E_DEPTH;
+    const double dN = (double)N, dk = (double)k;
+    ora_ct *base; /* k_j (times +-1/N) */
+    double off1, off2 = 0.0; /* constants giving the indicator argument(s) */
+    if (tie) {
+        ora_ct *C = ora_cmp_matrix(Kp, V, N, cdg, cdf, &st);
+        ora_ct *m4 = mul_int(C, -4);
+        ora_ct *w = ora_add_const(m4, 4.0);
+        ora_ct *E = ora_mul(Kp, C, w, &st);
+        double *tm = (double *)calloc((size_t)N * N, sizeof(double));
+        for (u32 i = 0; i < N; i++)
+            for (u32 j = 0; j < N; j++) tm[i * N + j] = j >= i ? 0.5 : -0.5;
+        ora_ct *Et = ora_mul_plain(E, tm, N * N, &st);
+        free(tm);
+        ora_ct *Ca = ora_cmul_to(C, 1.0, Et->level, &st);
+        ora_ct *X = ora_add(Ca, Et);
+        ora_ct *kv = ora_sum_r(Kp, X, N, &st);
+        base = ora_cmul_to(kv, k == 1 ? -1.0 / dN : 1.0 / dN, kv->level - 1, &st);
+        if (k == 1) off1 = 1.5 / dN;
+        else if (k == N) off1 = (0.5 - dN) / dN;
+        else off1 = (0.5 - dk) / dN, off2 = (-0.5 - dk) / dN;
+        ora_ct_free(C); ora_ct_free(m4); ora_ct_free(w); ora_ct_free(E); ora_ct_free(Et); ora_ct_free(Ca);
+        ora_ct_free(X); ora_ct_free(kv);
+    } else {
+        ora_ct *C = cmp_matrix_scaled(Kp, V, N, cdg, cdf, k == 1 ? -1.0 / dN : 1.0 / dN, &st);
+        base = ct_copy(C);
+        for (int i = 0; i < ilog2(N); i++) replace(&base, add_rot(Kp, base, (i64)N << i, &st));
+        if (k == 1) off1 = 1.0 / dN;
+        else if (k == N) off1 = (1.0 - dN) / dN;
+        else off1 = (1.0 - dk) / dN, off2 = -dk / dN;
+        ora_ct_free(C);
+    }
+    ora_ct *O;
+    if (k == 1 || k == N) {
+        ora_ct *y = ora_add_const(base, off1);
+        O = ora_cmp_sign(Kp, y, idg, idf, &st);
+        ora_ct_free(y);
+    } else {
+        ora_ct *d1 = ora_add_const(base, off1), *d2 = ora_add_const(base, off2);
+        ora_ct *c1 = ora_cmp_sign(Kp, d1, idg, idf, &st);
+        ora_ct *c2 = ora_cmp_sign(Kp, d2, idg, idf, &st);
+        ora_ct *n2 = mul_int(c2, -1);
+        ora_ct *o2 = ora_add_const(n2, 1.0);
+        O = ora_mul(Kp, c1, o2, &st);
+        ora_ct_free(d1); ora_ct_free(d2); ora_ct_free(c1); ora_ct_free(c2); ora_ct_free(n2); ora_ct_free(o2);
+    }
     double *row = (double *)calloc(N, sizeof(double));
     for (u32 j = 0; j < N; j++) row[j] = 1.0;
     *onehot = ora_mul_plain(O, row, N, &st);
@@ -1122,9 +1178,14 @@ int ora_argmin(const ora_keys *Kp, const ora_ct *V, u32 N, int cdg, int cdf, int
     ora_ct *Va = ora_cmul_to(V, 1.0, O->level, &st);
     ora_ct *P = ora_mul(Kp, O, Va, &st);
     *value = ora_sum_c(Kp, P, N, &st);
-    ora_ct_free(C); ora_ct_free(m4); ora_ct_free(w); ora_ct_free(E); ora_ct_free(Et); ora_ct_free(Ca);
-    ora_ct_free(X); ora_ct_free(k); ora_ct_free(ks); ora_ct_free(d); ora_ct_free(O); ora_ct_free(Va); ora_ct_free(P);
+    ora_ct_free(base); ora_ct_free(O); ora_ct_free(Va); ora_ct_free(P);
     return st;
+}
+
+/* the minimum with tie-correction: order statistic k = 1 */
+int ora_argmin(const ora_keys *Kp, const ora_ct *V, u32 N, int cdg, int cdf, int idg, int idf, ora_ct **onehot,
+               ora_ct **value) {
+    return ora_order_stat(Kp, V, N, 1, cdg, cdf, idg, idf, 1, onehot, value);
 }
 
 /* ------------------------------------------------------------------ */

@@ -98,6 +98,8 @@ def lib():
             "ora_argmin_depth": (C.c_int, [C.c_int] * 4),
             "ora_argmin": (C.c_int, [vp, vp, C.c_uint32, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(vp),
                                      C.POINTER(vp)]),
+            "ora_order_stat_depth": (C.c_int, [C.c_uint32, C.c_uint32] + [C.c_int] * 5),
+            "ora_order_stat": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32] + [C.c_int] * 5 + [C.POINTER(vp), C.POINTER(vp)]),
             "ora_sort_depth": (C.c_int, [C.c_int] * 4),
             "ora_sort": (vp, [vp, vp, C.c_uint32, C.c_int, C.c_int, C.c_int, C.c_int, intp]),
             "ora_circuit_galois": (C.c_int, [vp, C.c_uint32, C.c_int, u32p]),
@@ -407,6 +409,20 @@ def argmin(keys, a, N, cmp, ind):
     st = lib().ora_argmin(keys.ptr, a.ptr, N, cmp[0], cmp[1], ind[0], ind[1], C.byref(oh), C.byref(val))
     if st != 0:
         raise OracleError(f"argmin: status {STATUS.get(st, st)}")
+    return Ct(oh.value, a.params), Ct(val.value, a.params)
+
+
+def order_stat_depth(N, k, cmp, ind, tie):
+    return lib().ora_order_stat_depth(N, k, cmp[0], cmp[1], ind[0], ind[1], int(tie))
+
+
+def order_stat(keys, a, N, k, cmp, ind, tie):
+    """(onehot, value) ciphertexts of the k-th smallest element (tie-corrected if tie)."""
+    oh, val = C.c_void_p(), C.c_void_p()
+    st = lib().ora_order_stat(keys.ptr, a.ptr, N, k, cmp[0], cmp[1], ind[0], ind[1], int(tie), C.byref(oh),
+                              C.byref(val))
+    if st != 0:
+        raise OracleError(f"order_stat: status {STATUS.get(st, st)}")
     return Ct(oh.value, a.params), Ct(val.value, a.params)
 
 

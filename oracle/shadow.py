@@ -200,6 +200,41 @@ def argmin_circuit(v, N, slots, cmp, ind):
     return mask_row(O, N, 0), val, k
 
 
+def order_stat_circuit(v, N, slots, k, cmp, ind, tie):
+    """Order statistic k (section 3.2), optionally tie-corrected (section 4),
+    as the CKKS circuit evaluates it: the indicator is one-sided for k = 1
+    (Cmp(1.5, k_j)) and k = N (Cmp(k_j, N - 1/2)) and the window
+    Cmp(x, -1/2) (1 - Cmp(x, 1/2)) on x = k_j - k otherwise, every argument
+    divided by N.  Without tie-correction SumR keeps no row mask (the other
+    rows are annihilated by O * V).  Returns (O masked to row 0, value slot
+    vector, k_j vector)."""
+    x = embed(v, slots)
+    VR = repl_r(x, N)
+    VC = repl_c(trans_r(x, N), N)
+    Cm = (sign_composite(VR - VC, *cmp) + 1.0) / 2.0
+    if tie:
+        E = Cm * (4.0 - 4.0 * Cm)
+        tm = np.zeros(slots)
+        for i in range(N):
+            tm[i * N:(i + 1) * N] = np.where(np.arange(N) >= i, 0.5, -0.5)
+        kv = sum_r(Cm + E * tm, N)
+    else:
+        kv = Cm.copy()
+        for i in range(log2i(N)):
+            kv = kv + rot_left(kv, N << i)
+        kv = kv + 0.5          # the rank
+    if k == 1:
+        O = (sign_composite((1.5 - kv) / N, *ind) + 1.0) / 2.0
+    elif k == N:
+        O = (sign_composite((kv - (N - 0.5)) / N, *ind) + 1.0) / 2.0
+    else:
+        c1 = (sign_composite((kv - k + 0.5) / N, *ind) + 1.0) / 2.0
+        c2 = (sign_composite((kv - k - 0.5) / N, *ind) + 1.0) / 2.0
+        O = c1 * (1.0 - c2)
+    val = sum_c(O * x, N)
+    return mask_row(O, N, 0), val, kv
+
+
 def sort_circuit(v, N, slots, cmp, ind):
     """Algorithm Sorting with Ind_0(x) = Cmp(x, -1/2) (1 - Cmp(x, 1/2)) on x/N."""
     x = embed(v, slots)

@@ -27,6 +27,12 @@ PSETS = {
     "P16": dict(logn=16, L=23, q0_bits=50, log_scale=40, K=7, p_bits=50, dnum=3),
     # tie-corrected argmin and sort on N <= 128 at n = 2^17 (40 levels, log QP ~ 2150 bits)
     "P17": dict(logn=17, L=40, q0_bits=50, log_scale=40, K=10, p_bits=50, dnum=4),
+    # mixed rank / order-statistic batches at n = 2^16, each query encrypted at
+    # the level its circuit needs (36 levels, log QP ~ 1740 bits)
+    "P16D": dict(logn=16, L=36, q0_bits=50, log_scale=40, K=5, p_bits=50, dnum=8),
+    # tie-corrected order statistics for any k on N <= 128 at n = 2^17
+    # (44 levels, log QP ~ 2360 bits)
+    "P17O": dict(logn=17, L=44, q0_bits=50, log_scale=40, K=11, p_bits=50, dnum=4),
     # small rings used by the unit and parity tests
     "T12D": dict(logn=12, L=34, q0_bits=44, log_scale=36, K=9, p_bits=40, dnum=4),
     "T10": dict(logn=10, L=7, q0_bits=44, log_scale=36, K=3, p_bits=46, dnum=3),
@@ -38,6 +44,12 @@ RANK_CMP = {8: (2, 1), 16: (3, 1), 32: (3, 1), 64: (4, 1), 128: (4, 1)}
 # tie-corrected argmin: (comparator, one-sided indicator)
 ARGMIN_CMP = {8: ((3, 1), (2, 1)), 16: ((4, 1), (3, 2)), 32: ((4, 2), (3, 2)), 64: ((4, 2), (3, 2)),
               128: ((4, 2), (3, 2))}
+# order statistic k without tie-correction (distinct values), any k:
+# (comparator, indicator: one-sided for k = 1 and k = N, a window otherwise)
+ORDER_CMP = {8: ((3, 1), (2, 2)), 16: ((4, 1), (3, 2)), 32: ((4, 1), (3, 2)), 64: ((4, 1), (4, 2)),
+             128: ((4, 1), (4, 2))}
+# tie-corrected order statistic for k > 1 (k = 1 uses ARGMIN_CMP)
+ORDER_TIE_CMP = {8: ((3, 1), (2, 2)), 128: ((4, 2), (4, 2))}
 # sort: (comparator, two-sided indicator)
 SORT_CMP = {8: ((3, 1), (3, 2)), 16: ((4, 1), (3, 2)), 32: ((4, 1), (3, 2)), 64: ((4, 1), (4, 2)),
             128: ((4, 1), (4, 2))}
@@ -76,3 +88,18 @@ def rank_workload(N, gap, seed):
     rng = np.random.default_rng(seed)
     v = min_gap_uniform(N, gap, rng)
     return v, seed_bytes(rng), seed_bytes(rng)
+
+
+def mixed_workload(seed=7, count=64, Ns=(16, 32, 64, 128)):
+    """A batch of independent queries: kind "rank" or "argmin" with equal
+    odds, N drawn uniformly from Ns, values min-gap uniform (gap 2^-10).
+    Returns (key seed, [dict(kind, N, v, eseed)])."""
+    rng = np.random.default_rng(seed)
+    kseed = seed_bytes(rng)
+    qs = []
+    for _ in range(count):
+        kind = "rank" if rng.random() < 0.5 else "argmin"
+        N = int(rng.choice(Ns))
+        v = min_gap_uniform(N, 2.0 ** -10, rng)
+        qs.append(dict(kind=kind, N=N, v=v, eseed=seed_bytes(rng)))
+    return kseed, qs

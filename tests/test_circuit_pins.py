@@ -229,3 +229,72 @@ def test_shadow_argmin_and_sort_compositions(N):
     for seed in range(10):
         v, _, _ = W.rank_workload(N, gap, seed)
         assert np.max(np.abs(S.sort_circuit(v, N, 2 * N * N, cmp, ind)[:N] - np.sort(v))) < 1e-3
+
+
+def _kth(v, k):
+    """index of the k-th smallest (ties: lowest index first) and its value"""
+    order = np.argsort(v, kind="stable")
+    return int(order[k - 1]), float(np.sort(v)[k - 1])
+
+
+@pytest.mark.parametrize("N", [8, 16, 32, 64, 128])
+def test_shadow_order_statistic_without_ties(N):
+    """Order statistic k (section 3.2) on distinct values: the one-hot lands on
+    the k-th smallest and the value equals it, for k = 1, N/2 and N."""
+    cmp, ind = W.ORDER_CMP[N]
+    gap = 0.01 if N == 8 else 2.0 ** -10
+    for seed in range(12):
+        v, _, _ = W.rank_workload(N, gap, 300 + seed)
+        for k in sorted({1, max(2, N // 2), N}):
+            oh, val, kv = S.order_stat_circuit(v, N, 2 * N * N, k, cmp, ind, tie=False)
+            j, want = _kth(v, k)
+            assert np.array_equal(np.round(oh[:N]), np.eye(N)[j]), (seed, k)
+            assert abs(val[0] - want) < 1e-3, (seed, k)
+            # without tie-correction k_j is the rank (section 3.1)
+            assert np.array_equal(np.round(kv[:N]), np.argsort(np.argsort(v)) + 1)
+
+
+@pytest.mark.parametrize("N", [8, 128])
+def test_shadow_order_statistic_with_ties(N):
+    """Tie-corrected order statistic (section 4): among equal values the lowest
+    index comes first, so argmax lands on the highest index of the maxima."""
+    for seed in range(6 if N == 128 else 20):
+        v, _, _ = W.tied_workload(N, 40 + seed, 0.01 if N == 8 else 2.0 ** -10)
+        assert len(set(v.tolist())) < N
+        for k in (1, N // 2 + 1, N):
+            cmp, ind = W.ARGMIN_CMP[N] if k == 1 else W.ORDER_TIE_CMP[N]
+            oh, val, kv = S.order_stat_circuit(v, N, 2 * N * N, k, cmp, ind, tie=True)
+            j, want = _kth(v, k)
+            assert np.array_equal(np.round(oh[:N]), np.eye(N)[j]), (seed, k)
+            assert abs(val[0] - want) < 1e-2, (seed, k)
+            assert sorted(np.round(kv[:N]).astype(int).tolist()) == list(range(1, N + 1))
+
+
+def test_oracle_argmin_is_tie_corrected_order_statistic_one(ora, t12d):
+    P, keys = t12d
+    N = 8
+    cmp, ind = W.ARGMIN_CMP[N]
+    v, _, eseed = W.tied_workload(N, 5, 0.01)
+    ct = ora.encrypt(keys, v, P.L, eseed)
+    a_oh, a_val = ora.argmin(keys, ct, N, cmp, ind)
+    o_oh, o_val = ora.order_stat(keys, ct, N, 1, cmp, ind, True)
+    assert np.array_equal(a_oh.export(), o_oh.export()) and np.array_equal(a_val.export(), o_val.export())
+    assert ora.argmin_depth(cmp, ind) == ora.order_stat_depth(N, 1, cmp, ind, True)
+
+
+@pytest.mark.parametrize("k,tie", [(1, False), (3, False), (8, False), (3, True), (8, True)])
+def test_oracle_order_statistic_matches_shadow(ora, t12d, k, tie):
+    P, keys = t12d
+    N = 8
+    cmp, ind = (W.ARGMIN_CMP[N] if k == 1 else W.ORDER_TIE_CMP[N]) if tie else W.ORDER_CMP[N]
+    v, _, eseed = (W.tied_workload(N, 7, 0.01) if tie else W.rank_workload(N, 0.01, 7))
+    ct = ora.encrypt(keys, v, P.L, eseed)
+    oh, val = ora.order_stat(keys, ct, N, k, cmp, ind, tie)
+    depth = ora.order_stat_depth(N, k, cmp, ind, tie)
+    assert oh.level == P.L - depth + 1 and val.level == P.L - depth
+    got_oh, got_val = ora.decrypt(keys, oh, N), ora.decrypt(keys, val, 1)[0]
+    sh_oh, sh_val, _ = S.order_stat_circuit(v, N, P.n // 2, k, cmp, ind, tie)
+    assert np.max(np.abs(got_oh - sh_oh[:N])) < 1e-3 and abs(got_val - sh_val[0]) < 1e-3
+    j, want = _kth(v, k)
+    assert np.array_equal(np.round(got_oh), np.eye(N)[j])
+    assert abs(got_val - want) < 0.01
