@@ -139,10 +139,12 @@ ckr_status ckr_decrypt(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *ct,
 ckr_status ckr_rank(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, ckr_sign cmp, int tie_correct,
                     ckr_ct **out);
 
-/* Levels consumed by ckr_rank / ckr_argmin / ckr_sort for the given comparators. */
+/* Levels consumed by ckr_rank / ckr_argmin / ckr_sort / ckr_order_stat for
+ * the given comparators. */
 uint32_t ckr_rank_depth(ckr_sign cmp, int tie_correct);
 uint32_t ckr_argmin_depth(ckr_sign cmp, ckr_sign ind);
 uint32_t ckr_sort_depth(ckr_sign cmp, ckr_sign ind);
+uint32_t ckr_order_stat_depth(uint32_t N, uint32_t k, ckr_sign cmp, ckr_sign ind, int tie_correct);
 
 /* Minimum with tie-correction (Algorithm Order Statistic with k = 1):
  * onehot slots [0,N) hold 1 at the lowest index among the minima, 0
@@ -155,6 +157,43 @@ ckr_status ckr_argmin(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, u
  * increasing order. */
 ckr_status ckr_sort(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, ckr_sign cmp, ckr_sign ind,
                     ckr_ct **out);
+
+/* Order statistic k (Algorithm Order Statistic, section 3.2): onehot slots
+ * [0,N) hold 1 at the k-th smallest element and 0 elsewhere; value slot 0
+ * holds that element (k = 1 the minimum, k = N the maximum).  tie_correct != 0
+ * adds the tie-correction offset (section 4): equal values then take
+ * consecutive orders, lowest index first, so argmax lands on the highest
+ * index among the maxima; without it the values must be distinct.  `ind` is
+ * the indicator's composition: one-sided for k = 1 and k = N, the window
+ * Cmp(x, -1/2) (1 - Cmp(x, 1/2)) otherwise.  onehot sits at level(v) - depth
+ * + 1, value at level(v) - depth (ckr_order_stat_depth).  Errors: CKR_E_RANGE
+ * (N), CKR_E_INVALID (k outside [1, N], empty composition), CKR_E_DEPTH. */
+ckr_status ckr_order_stat(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, uint32_t k,
+                          ckr_sign cmp, ckr_sign ind, int tie_correct, ckr_ct **onehot, ckr_ct **value);
+
+/* One query of a mixed batch.  kind: 1 rank (tie_correct selects the
+ * tie-corrected rank), 2 argmin (the tie-corrected minimum; k and tie_correct
+ * ignored), 3 sort, 4 order statistic k.  v: a single ciphertext, borrowed. */
+typedef struct {
+    int kind;
+    uint32_t N;
+    uint32_t k;
+    int tie_correct;
+    ckr_sign cmp, ind;
+    const ckr_ct *v;
+} ckr_query;
+
+/* Run `count` independent queries of any kinds, sizes and levels as one unit
+ * (the batched execution of section 6's many-query setting): queries with the
+ * same circuit and level form a group whose kernel launches cover all of its
+ * members.  With graphs enabled (the default) the first call for a given mix
+ * runs eagerly, the second captures every group into one hipGraph owned by
+ * `keys`, and later calls with the same mix replay it as a single launch.
+ * out (2 * count entries, caller-owned results) receives at out[2i] query i's
+ * rank, sorted vector or one-hot and at out[2i+1] its value (order
+ * statistics) or NULL.  Results equal single calls bit for bit.  Errors: as
+ * the single calls; no output is produced on error. */
+ckr_status ckr_run_mixed(ckr_context *ctx, const ckr_keys *keys, const ckr_query *q, size_t count, ckr_ct **out);
 
 /* Batched execution: `count` ciphertexts of equal N and level run through one
  * circuit together -- every kernel launch covers all of them.  kind: 1 rank,

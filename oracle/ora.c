@@ -1120,6 +1120,37 @@ int ora_order_stat_depth(u32 N, u32 k, int cdg, int cdf, int idg, int idf, int t
 
 int ora_argmin_depth(int cdg, int cdf, int idg, int idf) { return ora_order_stat_depth(2, 1, cdg, cdf, idg, idf, 1); }
 
+/* tie-corrected rank k_j = SumR(C + E (delta_{j>=i} - 1/2)), E = C (4 - 4C):
+ * Rank plus the Tie-Correction Offset of section 4 (their +1/2 and -1/2
+ * cancel), a permutation of 1..N.  Levels: TransR mask, comparator, E,
+ * E * tie mask, SumR mask. */
+static ora_ct *tie_rank(const ora_keys *Kp, const ora_ct *V, u32 N, int cdg, int cdf, int *st) {
+    ora_ct *C = ora_cmp_matrix(Kp, V, N, cdg, cdf, st);
+    ora_ct *m4 = mul_int(C, -4);
+    ora_ct *w = ora_add_const(m4, 4.0);
+    ora_ct *E = ora_mul(Kp, C, w, st);
+    double *tm = (double *)calloc((size_t)N * N, sizeof(double));
+    for (u32 i = 0; i < N; i++)
+        for (u32 j = 0; j < N; j++) tm[i * N + j] = j >= i ? 0.5 : -0.5;
+    ora_ct *Et = ora_mul_plain(E, tm, N * N, st);
+    free(tm);
+    ora_ct *Ca = ora_cmul_to(C, 1.0, Et->level, st);
+    ora_ct *X = ora_add(Ca, Et);
+    ora_ct *kv = ora_sum_r(Kp, X, N, st);
+    ora_ct_free(C); ora_ct_free(m4); ora_ct_free(w); ora_ct_free(E); ora_ct_free(Et); ora_ct_free(Ca);
+    ora_ct_free(X);
+    return kv;
+}
+
+ora_ct *ora_rank_tie(const ora_keys *Kp, const ora_ct *V, u32 N, int dg, int df, int *status) {
+    int st = check_N(Kp->P, N);
+    if (st != ORA_OK) { *status = st; return NULL; }
+    if (V->level < ora_rank_depth(dg, df) + 2) { *status = ORA_E_DEPTH; return NULL; }
+    ora_ct *kv = tie_rank(Kp, V, N, dg, df, &st);
+    *status = st;
+    return kv;
+}
+
 int ora_order_stat(const ora_keys *Kp, const ora_ct *V, u32 N, u32 k, int cdg, int cdf, int idg, int idf, int tie,
                    ora_ct **onehot, ora_ct **value) {
     int st = check_N(Kp->P, N);
@@ -1130,24 +1161,12 @@ int ora_order_stat(const ora_keys *Kp, const ora_ct *V, u32 N, u32 k, int cdg, i
     ora_ct *base; /* k_j (times +-1/N) */
     double off1, off2 = 0.0; /* constants giving the indicator argument(s) */
     if (tie) {
-        ora_ct *C = ora_cmp_matrix(Kp, V, N, cdg, cdf, &st);
-        ora_ct *m4 = mul_int(C, -4);
-        ora_ct *w = ora_add_const(m4, 4.0);
-        ora_ct *E = ora_mul(Kp, C, w, &st);
-        double *tm = (double *)calloc((size_t)N * N, sizeof(double));
-        for (u32 i = 0; i < N; i++)
-            for (u32 j = 0; j < N; j++) tm[i * N + j] = j >= i ? 0.5 : -0.5;
-        ora_ct *Et = ora_mul_plain(E, tm, N * N, &st);
-        free(tm);
-        ora_ct *Ca = ora_cmul_to(C, 1.0, Et->level, &st);
-        ora_ct *X = ora_add(Ca, Et);
-        ora_ct *kv = ora_sum_r(Kp, X, N, &st);
+        ora_ct *kv = tie_rank(Kp, V, N, cdg, cdf, &st);
         base = ora_cmul_to(kv, k == 1 ? -1.0 / dN : 1.0 / dN, kv->level - 1, &st);
         if (k == 1) off1 = 1.5 / dN;
         else if (k == N) off1 = (0.5 - dN) / dN;
         else off1 = (0.5 - dk) / dN, off2 = (-0.5 - dk) / dN;
-        ora_ct_free(C); ora_ct_free(m4); ora_ct_free(w); ora_ct_free(E); ora_ct_free(Et); ora_ct_free(Ca);
-        ora_ct_free(X); ora_ct_free(kv);
+        ora_ct_free(kv);
     } else {
         ora_ct *C = cmp_matrix_scaled(Kp, V, N, cdg, cdf, k == 1 ? -1.0 / dN : 1.0 / dN, &st);
         base = ct_copy(C);

@@ -98,6 +98,7 @@ def lib():
             "ora_argmin_depth": (C.c_int, [C.c_int] * 4),
             "ora_argmin": (C.c_int, [vp, vp, C.c_uint32, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(vp),
                                      C.POINTER(vp)]),
+            "ora_rank_tie": (vp, [vp, vp, C.c_uint32, C.c_int, C.c_int, intp]),
             "ora_order_stat_depth": (C.c_int, [C.c_uint32, C.c_uint32] + [C.c_int] * 5),
             "ora_order_stat": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32] + [C.c_int] * 5 + [C.POINTER(vp), C.POINTER(vp)]),
             "ora_sort_depth": (C.c_int, [C.c_int] * 4),
@@ -335,6 +336,11 @@ def rank(keys, a, N, dg, df):
 
 def rank_depth(dg, df):
     return lib().ora_rank_depth(dg, df)
+
+
+def rank_tie(keys, a, N, dg, df):
+    """tie-corrected rank (rank plus the tie-correction offset): a permutation of 1..N"""
+    return _ct(lib().ora_rank_tie, a.params, keys.ptr, a.ptr, N, dg, df, what="rank_tie")
 
 
 # ---- primitive pins -------------------------------------------------------

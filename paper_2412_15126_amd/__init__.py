@@ -35,6 +35,11 @@ class Sign(C.Structure):
     _fields_ = [("d_g", C.c_uint8), ("d_f", C.c_uint8)]
 
 
+class Query(C.Structure):
+    _fields_ = [("kind", C.c_int), ("N", C.c_uint32), ("k", C.c_uint32), ("tie_correct", C.c_int),
+                ("cmp", Sign), ("ind", Sign), ("v", C.c_void_p)]
+
+
 vp = C.c_void_p
 u64p = C.POINTER(C.c_uint64)
 i64p = C.POINTER(C.c_int64)
@@ -60,6 +65,10 @@ _SIGS = {
     "ckr_rank": (C.c_int, [vp, vp, vp, C.c_uint32, Sign, C.c_int, C.POINTER(vp)]),
     "ckr_rank_depth": (C.c_uint32, [Sign, C.c_int]),
     "ckr_argmin_depth": (C.c_uint32, [Sign, Sign]),
+    "ckr_order_stat_depth": (C.c_uint32, [C.c_uint32, C.c_uint32, Sign, Sign, C.c_int]),
+    "ckr_order_stat": (C.c_int, [vp, vp, vp, C.c_uint32, C.c_uint32, Sign, Sign, C.c_int, C.POINTER(vp),
+                                 C.POINTER(vp)]),
+    "ckr_run_mixed": (C.c_int, [vp, vp, C.POINTER(Query), C.c_size_t, C.POINTER(vp)]),
     "ckr_sort_depth": (C.c_uint32, [Sign, Sign]),
     "ckr_argmin": (C.c_int, [vp, vp, vp, C.c_uint32, Sign, Sign, C.POINTER(vp), C.POINTER(vp)]),
     "ckr_sort": (C.c_int, [vp, vp, vp, C.c_uint32, Sign, Sign, C.POINTER(vp)]),
@@ -151,8 +160,12 @@ def sample(seed, purpose, oid, kind, q, count):
     return out
 
 
-def rank_depth(cmp):
-    return int(lib().ckr_rank_depth(sign(cmp), 0))
+def rank_depth(cmp, tie=False):
+    return int(lib().ckr_rank_depth(sign(cmp), int(tie)))
+
+
+def order_stat_depth(N, k, cmp, ind, tie):
+    return int(lib().ckr_order_stat_depth(N, k, sign(cmp), sign(ind), int(tie)))
 
 
 def argmin_depth(cmp, ind):
@@ -218,10 +231,17 @@ class Context:
         return Ct(self, h)
 
     # -- circuits
-    def rank(self, keys, ct, N, cmp):
+    def rank(self, keys, ct, N, cmp, tie=False):
         h = vp()
-        _ok(lib().ckr_rank(self.h, keys.h, ct.h, N, sign(cmp), 0, C.byref(h)))
+        _ok(lib().ckr_rank(self.h, keys.h, ct.h, N, sign(cmp), int(tie), C.byref(h)))
         return Ct(self, h)
+
+    def order_stat(self, keys, ct, N, k, cmp, ind, tie):
+        """(onehot, value) of the k-th smallest element."""
+        oh, val = vp(), vp()
+        _ok(lib().ckr_order_stat(self.h, keys.h, ct.h, N, k, sign(cmp), sign(ind), int(tie), C.byref(oh),
+                                 C.byref(val)))
+        return Ct(self, oh), Ct(self, val)
 
     def argmin(self, keys, ct, N, cmp, ind):
         oh, val = vp(), vp()
@@ -266,6 +286,22 @@ class Context:
         _ok(lib().ckr_run_batch(self.h, keys.h, k, N, sign(cmp), sign(ind), arr, len(cts), out))
         res = [Ct(self, vp(o)) for o in out]
         return [tuple(res[2 * i:2 * i + 2]) for i in range(len(cts))] if per == 2 else res
+
+    def run_mixed(self, keys, queries):
+        """queries: dicts with kind ('rank', 'argmin', 'sort', 'order'), N, ct, cmp and, as
+        needed, ind, k, tie.  Returns per query a Ct or an (onehot, value) pair."""
+        kinds = {"rank": 1, "argmin": 2, "sort": 3, "order": 4}
+        arr = (Query * len(queries))()
+        for a, q in zip(arr, queries):
+            a.kind, a.N, a.k, a.tie_correct = kinds[q["kind"]], q["N"], q.get("k", 1), int(q.get("tie", False))
+            a.cmp, a.ind, a.v = sign(q["cmp"]), sign(q.get("ind", (0, 0))), q["ct"].h.value
+        out = (vp * (2 * len(queries)))()
+        _ok(lib().ckr_run_mixed(self.h, keys.h, arr, len(queries), out))
+        res = []
+        for i in range(len(queries)):
+            a, b = out[2 * i], out[2 * i + 1]
+            res.append((Ct(self, vp(a)), Ct(self, vp(b))) if b else Ct(self, vp(a)))
+        return res
 
     def rank_batch(self, keys, cts, N, cmp):
         arr = (vp * len(cts))(*[c.h for c in cts])

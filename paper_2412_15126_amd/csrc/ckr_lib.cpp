@@ -262,7 +262,7 @@ void Buf::release() {
 // plan-owned input batch and writes plan-owned outputs
 struct GraphPlan {
     Ctx *C = nullptr;
-    DCt in;
+    std::vector<DCt> in;  // one input batch per query group
     std::vector<DCt> outs;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -275,12 +275,22 @@ struct GraphPlan {
     }
 };
 
-struct PlanKey {
-    int kind, N, level, B, cg, cf, ig, iff;
-    bool operator<(const PlanKey &o) const {
-        return std::tie(kind, N, level, B, cg, cf, ig, iff) < std::tie(o.kind, o.N, o.level, o.B, o.cg, o.cf, o.ig, o.iff);
+// one circuit: kind (rank, order statistic, sort), N, the order statistic's k
+// and tie-correction flag, comparator and indicator compositions
+struct Spec {
+    int kind = 0, N = 0, k = 0, tie = 0;
+    ckr_sign cmp{0, 0}, ind{0, 0};
+    auto tup() const { return std::make_tuple(kind, N, k, tie, cmp.d_g, cmp.d_f, ind.d_g, ind.d_f); }
+};
+// a group of B inputs of one level running one circuit
+struct GroupKey {
+    Spec s;
+    int level = 0, B = 0;
+    bool operator<(const GroupKey &o) const {
+        return std::tuple_cat(s.tup(), std::make_tuple(level, B)) < std::tuple_cat(o.s.tup(), std::make_tuple(o.level, o.B));
     }
 };
+using PlanKey = std::vector<GroupKey>;
 
 struct Keys {
     Ctx *C = nullptr;
@@ -944,8 +954,9 @@ static DCt poly7(Ctx &C, const Keys &K, const DCt &x, const double a[4]) {
     return ev_add(C, s1, v1, false);
 }
 
-// (f^{d_f}(g^{d_g}(D)) + 1) / 2 with the 1/2 folded into the last polynomial
-static DCt cmp_sign(Ctx &C, const Keys &K, const DCt &D, ckr_sign cmp) {
+// a * (f^{d_f}(g^{d_g}(D)) + 1) / 2 with the factor a/2 folded into the last
+// polynomial and a/2 added as a constant
+static DCt cmp_sign(Ctx &C, const Keys &K, const DCt &D, ckr_sign cmp, double a = 1.0) {
     const int total = cmp.d_g + cmp.d_f;
     if (total < 1) throw Error{CKR_E_INVALID, "empty comparator"};
     if (D.level < 3 * total) throw Error{CKR_E_DEPTH, "comparator depth"};
@@ -954,11 +965,11 @@ static DCt cmp_sign(Ctx &C, const Keys &K, const DCt &D, ckr_sign cmp) {
     for (int r = 0; r < total; r++) {
         const double *c = r < cmp.d_g ? kG : kF;
         double cc[4];
-        for (int i = 0; i < 4; i++) cc[i] = (r == total - 1) ? c[i] * 0.5 : c[i];
+        for (int i = 0; i < 4; i++) cc[i] = (r == total - 1) ? c[i] * (a * 0.5) : c[i];
         X = poly7(C, K, *cur, cc);
         cur = &X;
     }
-    return ev_add_const(C, X, 0.5);
+    return ev_add_const(C, X, a * 0.5);
 }
 
 // ------------------------------------------------------------------------
@@ -971,20 +982,25 @@ static void check_N(const Ctx &C, u32 N) {
 
 // levels: TransR mask, comparator, SumR mask (+ E and E * tie mask with tie-correction)
 uint32_t rank_depth(ckr_sign c, int tie) { return 2 + 3 * (c.d_g + c.d_f) + (tie ? 2 : 0); }
-// tie-corrected rank, scaling, indicator, O * V, SumC mask
-uint32_t argmin_depth(ckr_sign c, ckr_sign i) { return rank_depth(c, 1) + 1 + 3 * (i.d_g + i.d_f) + 2; }
+// order statistic k: TransR mask, comparator, [E, E * tie mask, SumR mask,
+// scaling,] indicator (+1 for the two-sided window), O * V, SumC mask
+uint32_t order_stat_depth(int N, int k, ckr_sign c, ckr_sign i, int tie) {
+    return 1 + 3 * (c.d_g + c.d_f) + (tie ? 4 : 0) + 3 * (i.d_g + i.d_f) + ((k > 1 && k < N) ? 1 : 0) + 2;
+}
+uint32_t argmin_depth(ckr_sign c, ckr_sign i) { return order_stat_depth(2, 1, c, i, 1); }
 // rank, scaling, indicator, indicator product, M * V_R, SumC mask, TransC mask
 uint32_t sort_depth(ckr_sign c, ckr_sign i) { return rank_depth(c, 0) + 5 + 3 * (i.d_g + i.d_f); }
 
 // C = Cmp(V_R, V_C): C[i][j] = Cmp(v_j, v_i)
-static DCt cmp_matrix(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, DCt *VR_out = nullptr) {
+static DCt cmp_matrix(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, DCt *VR_out = nullptr,
+                      double a = 1.0) {
     DCt VR = repl_r(C, K, V, N);
     DCt T = trans_r(C, K, V, N);
     DCt VC = repl_c(C, K, T, N);
     DCt VRa = ev_cmul_to(C, VR, 1.0, VC.level);
     DCt D = ev_add(C, VRa, VC, true);
     if (VR_out) *VR_out = std::move(VR);
-    return cmp_sign(C, K, D, cmp);
+    return cmp_sign(C, K, D, cmp, a);
 }
 
 static DCt rank(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, DCt *VR_out = nullptr) {
@@ -995,21 +1011,64 @@ static DCt rank(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, DCt *V
     return ev_add_plain(C, S, get_plain(C, kHalfRow0, N, S.level));
 }
 
-// minimum with tie-correction: k = SumR(C + E (delta_{j>=i} - 1/2)), E = C (4 - 4C)
-// (rank plus offset; their +1/2 and -1/2 cancel); O = Cmp(1.5, k) on (1.5 - k)/N
-// (k >= 1 is integral); onehot = MaskR(O, 0); value = SumC(O * V)
-static void argmin(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, ckr_sign ind, DCt &onehot,
-                   DCt &value) {
+// tie-corrected rank k_j = SumR(C + E (delta_{j>=i} - 1/2)), E = C (4 - 4C):
+// rank plus the tie-correction offset (their +1/2 and -1/2 cancel), a
+// permutation of 1..N with equal values ranked in index order
+static DCt tie_rank(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp) {
     check_N(C, (u32)N);
-    if ((u32)V.level < argmin_depth(cmp, ind)) throw Error{CKR_E_DEPTH, "not enough levels for argmin"};
+    if ((u32)V.level < rank_depth(cmp, 1)) throw Error{CKR_E_DEPTH, "not enough levels for the tie-corrected rank"};
     DCt Cm = cmp_matrix(C, K, V, N, cmp);
     DCt w = ev_add_const(C, ev_mul_int(C, Cm, -4), 4.0);
     DCt E = ev_mul(C, K, Cm, w);
     DCt Et = ev_mul_plain(C, E, get_plain(C, kTieMask, N, E.level));
     DCt Ca = ev_cmul_to(C, Cm, 1.0, Et.level);
-    DCt k = sum_r(C, K, ev_add(C, Ca, Et, false), N);
-    DCt d = ev_add_const(C, ev_cmul_to(C, k, -1.0 / (double)N, k.level - 1), 1.5 / (double)N);
-    DCt O = cmp_sign(C, K, d, ind);
+    return sum_r(C, K, ev_add(C, Ca, Et, false), N);
+}
+
+// Order statistic k (Algorithm Order Statistic), optionally with the
+// tie-correction offset.  The indicator of "the k-th smallest" is one-sided at
+// the ends (k = 1: Cmp(1.5, k_j); k = N: Cmp(k_j, N - 1/2); the k_j are
+// integral) and the window Cmp(x, -1/2) (1 - Cmp(x, 1/2)) on x = k_j - k
+// otherwise, every comparison taken on its argument divided by N.
+// With tie-correction k_j = SumR(C + E (delta_{j>=i} - 1/2)), E = C (4 - 4C)
+// (rank plus offset; their +1/2 and -1/2 cancel), a permutation of 1..N.
+// Without it k_j is the rank SumR(C) + 1/2, the factor +-1/N folded into the
+// comparator's last polynomial and no row mask on SumR: the other rows hold
+// bounded garbage that O * V annihilates (V is zero outside row 0).
+// onehot = MaskR(O, 0); value = SumC(O * V) in slot 0.
+static void order_stat(Ctx &C, const Keys &K, const DCt &V, int N, int k, int tie, ckr_sign cmp, ckr_sign ind,
+                       DCt &onehot, DCt &value) {
+    check_N(C, (u32)N);
+    if (k < 1 || k > N) throw Error{CKR_E_INVALID, "k must lie in [1, N]"};
+    if ((u32)V.level < order_stat_depth(N, k, cmp, ind, tie))
+        throw Error{CKR_E_DEPTH, "not enough levels for the order statistic"};
+    const double dN = (double)N, dk = (double)k;
+    DCt base;  // k_j times -1/N (k = 1) or 1/N
+    double off1, off2 = 0.0;
+    if (tie) {
+        DCt kv = tie_rank(C, K, V, N, cmp);
+        base = ev_cmul_to(C, kv, k == 1 ? -1.0 / dN : 1.0 / dN, kv.level - 1);
+        if (k == 1) off1 = 1.5 / dN;
+        else if (k == N) off1 = (0.5 - dN) / dN;
+        else off1 = (0.5 - dk) / dN, off2 = (-0.5 - dk) / dN;
+    } else {
+        DCt Cm = cmp_matrix(C, K, V, N, cmp, nullptr, k == 1 ? -1.0 / dN : 1.0 / dN);
+        base = rot_add_chain(C, K, Cm, 0, lg(N), [&](int i) { return (i64)N << i; });
+        if (k == 1) off1 = 1.0 / dN;
+        else if (k == N) off1 = (1.0 - dN) / dN;
+        else off1 = (1.0 - dk) / dN, off2 = -dk / dN;
+    }
+    DCt O;
+    if (k == 1 || k == N) {
+        O = cmp_sign(C, K, ev_add_const(C, base, off1), ind);
+    } else {
+        DCt d1 = ev_add_const(C, base, off1), d2 = ev_add_const(C, base, off2);
+        // both comparisons in one batched pass
+        DCt cc = cmp_sign(C, K, stack(C, {&d1, &d2}), ind);
+        const int B = V.B;
+        DCt c1 = slice(C, cc, 0, B), c2 = slice(C, cc, B, B);
+        O = ev_mul(C, K, c1, ev_add_const(C, ev_mul_int(C, c2, -1), 1.0));
+    }
     onehot = ev_mul_plain(C, O, get_plain(C, kMaskRow0, N, O.level));
     DCt Va = ev_cmul_to(C, V, 1.0, O.level);
     value = sum_c(C, K, ev_mul(C, K, O, Va), N);
@@ -1037,25 +1096,81 @@ static DCt sort(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, ckr_si
     return trans_c(C, K, SC, N);
 }
 
-// Run `circuit` on a batch of single ciphertexts of equal level.  With graphs
-// enabled, the first call for a shape runs eagerly (filling plaintext and
-// table caches), the second captures the circuit into a hipGraph, later calls
-// copy the inputs into the plan's input batch and replay it.  Every path
-// launches the same kernels in the same order: outputs are bit-identical.
-using Circuit = std::function<std::vector<DCt>(const DCt &)>;
+enum CircuitKind { kRankCircuit = 1, kArgminCircuit = 2, kSortCircuit = 3, kOrderCircuit = 4 };
 
-static std::vector<DCt> run_circuit(Ctx &C, Keys &K, const PlanKey &key, const std::vector<const DCt *> &in,
-                                    const Circuit &circuit) {
-    const int B = (int)in.size();
-    const size_t W = (size_t)2 * (key.level + 1) * C.n();
-    auto fill = [&](DCt &X) {
-        for (int i = 0; i < B; i++)
-            HIPCHK(hipMemcpyAsync(X.d() + i * W, in[i]->d(), W * 8, hipMemcpyDeviceToDevice, C.stream));
+// levels a circuit consumes
+static uint32_t spec_depth(const Spec &s) {
+    if (s.kind == kRankCircuit) return rank_depth(s.cmp, s.tie);
+    if (s.kind == kSortCircuit) return sort_depth(s.cmp, s.ind);
+    return order_stat_depth(s.N, s.k, s.cmp, s.ind, s.tie);
+}
+
+// the circuit of a (kind, N, compositions) request; argmin is the
+// tie-corrected order statistic k = 1
+static Spec spec_of(const Ctx &C, int kind, int N, int k, int tie, ckr_sign cmp, ckr_sign ind) {
+    check_N(C, (u32)N);
+    Spec s;
+    s.N = N;
+    s.cmp = cmp;
+    if (kind == kRankCircuit) {
+        s.kind = kind;
+        s.tie = tie != 0;
+    } else if (kind == kSortCircuit) {
+        s.kind = kind;
+        s.ind = ind;
+    } else if (kind == kArgminCircuit || kind == kOrderCircuit) {
+        s.kind = kOrderCircuit;
+        s.k = kind == kArgminCircuit ? 1 : k;
+        s.tie = kind == kArgminCircuit ? 1 : (tie != 0);
+        s.ind = ind;
+        if (s.k < 1 || s.k > N) throw Error{CKR_E_INVALID, "k must lie in [1, N]"};
+    } else {
+        throw Error{CKR_E_INVALID, "unknown circuit kind"};
+    }
+    if (s.cmp.d_g + s.cmp.d_f < 1 || (s.kind != kRankCircuit && s.ind.d_g + s.ind.d_f < 1))
+        throw Error{CKR_E_INVALID, "empty comparator"};
+    return s;
+}
+
+static std::vector<DCt> eval_spec(Ctx &C, const Keys &K, const Spec &s, const DCt &X) {
+    std::vector<DCt> o;
+    if (s.kind == kRankCircuit) {
+        o.push_back(s.tie ? tie_rank(C, K, X, s.N, s.cmp) : rank(C, K, X, s.N, s.cmp));
+    } else if (s.kind == kSortCircuit) {
+        o.push_back(sort(C, K, X, s.N, s.cmp, s.ind));
+    } else {
+        o.resize(2);
+        order_stat(C, K, X, s.N, s.k, s.tie, s.cmp, s.ind, o[0], o[1]);
+    }
+    return o;
+}
+
+// Run query groups (each a circuit on a batch of single ciphertexts of one
+// level) as one unit.  With graphs enabled, the first call for a plan runs
+// eagerly (filling plaintext and table caches), the second captures every
+// group's circuit into one hipGraph, later calls copy the inputs into the
+// plan's input batches and replay it with a single launch.  Every path
+// launches the same kernels in the same order: outputs are bit-identical.
+using Circuit = std::function<std::vector<DCt>(const std::vector<DCt> &)>;
+
+static std::vector<DCt> run_circuit(Ctx &C, Keys &K, const PlanKey &key,
+                                    const std::vector<std::vector<const DCt *>> &in, const Circuit &circuit) {
+    auto fill = [&](std::vector<DCt> &X) {
+        for (size_t g = 0; g < key.size(); g++) {
+            const size_t W = (size_t)2 * (key[g].level + 1) * C.n();
+            for (int i = 0; i < key[g].B; i++)
+                HIPCHK(hipMemcpyAsync(X[g].d() + i * W, in[g][i]->d(), W * 8, hipMemcpyDeviceToDevice, C.stream));
+        }
+    };
+    auto inputs = [&] {
+        std::vector<DCt> X;
+        for (const GroupKey &g : key) X.push_back(ct_new(C, g.level, g.B));
+        return X;
     };
     const bool use_graph = C.graphs && !C.prof.on;
     auto it = K.plans.find(key);
     if (!use_graph || (it == K.plans.end() && !K.warm.count(key))) {
-        DCt X = ct_new(C, key.level, B);
+        std::vector<DCt> X = inputs();
         fill(X);
         std::vector<DCt> outs = circuit(X);
         K.warm.insert(key);
@@ -1064,7 +1179,7 @@ static std::vector<DCt> run_circuit(Ctx &C, Keys &K, const PlanKey &key, const s
     if (it == K.plans.end()) {
         auto plan = std::make_unique<GraphPlan>();
         plan->C = &C;
-        plan->in = ct_new(C, key.level, B);
+        plan->in = inputs();
         HIPCHK(hipStreamSynchronize(C.stream));
         HIPCHK(hipStreamBeginCapture(C.stream, hipStreamCaptureModeRelaxed));
         C.pool.begin_capture();
@@ -1090,26 +1205,42 @@ static std::vector<DCt> run_circuit(Ctx &C, Keys &K, const PlanKey &key, const s
     return outs;
 }
 
-enum CircuitKind { kRankCircuit = 1, kArgminCircuit = 2, kSortCircuit = 3 };
+// groups[g] runs specs[g] on the single ciphertexts in[g] (all of one level);
+// returns each group's batched outputs
+static std::vector<std::vector<DCt>> run_groups(Ctx &C, Keys &K, const std::vector<Spec> &specs,
+                                                const std::vector<std::vector<const DCt *>> &in) {
+    PlanKey key;
+    for (size_t g = 0; g < specs.size(); g++) {
+        if (in[g].empty()) throw Error{CKR_E_INVALID, "empty batch"};
+        const int level = in[g][0]->level;
+        for (auto *c : in[g])
+            if (c->level != level || c->B != 1)
+                throw Error{CKR_E_INVALID, "batch entries must be single ciphertexts of one level"};
+        if ((u32)level < spec_depth(specs[g])) throw Error{CKR_E_DEPTH, "not enough levels for the circuit"};
+        if (level > K.lmax) throw Error{CKR_E_DEPTH, "ciphertext above key level"};
+        key.push_back(GroupKey{specs[g], level, (int)in[g].size()});
+    }
+    Circuit f = [&](const std::vector<DCt> &X) {
+        std::vector<DCt> outs;
+        for (size_t g = 0; g < specs.size(); g++)
+            for (DCt &o : eval_spec(C, K, specs[g], X[g])) outs.push_back(std::move(o));
+        return outs;
+    };
+    std::vector<DCt> flat = run_circuit(C, K, key, in, f);
+    std::vector<std::vector<DCt>> res(specs.size());
+    size_t pos = 0;
+    for (size_t g = 0; g < specs.size(); g++) {
+        const int per = specs[g].kind == kOrderCircuit ? 2 : 1;
+        for (int j = 0; j < per; j++) res[g].push_back(std::move(flat[pos++]));
+    }
+    return res;
+}
 
 static std::vector<DCt> run_kind(Ctx &C, Keys &K, int kind, int N, ckr_sign cmp, ckr_sign ind,
                                  const std::vector<const DCt *> &in) {
-    if (in.empty()) throw Error{CKR_E_INVALID, "empty batch"};
-    const int level = in[0]->level;
-    for (auto *c : in)
-        if (c->level != level || c->B != 1) throw Error{CKR_E_INVALID, "batch entries must be single ciphertexts of one level"};
-    PlanKey key{kind, N, level, (int)in.size(), cmp.d_g, cmp.d_f, ind.d_g, ind.d_f};
-    Circuit f;
-    if (kind == kRankCircuit) f = [&](const DCt &X) { std::vector<DCt> o; o.push_back(rank(C, K, X, N, cmp)); return o; };
-    else if (kind == kSortCircuit) f = [&](const DCt &X) { std::vector<DCt> o; o.push_back(sort(C, K, X, N, cmp, ind)); return o; };
-    else if (kind == kArgminCircuit)
-        f = [&](const DCt &X) {
-            std::vector<DCt> o(2);
-            argmin(C, K, X, N, cmp, ind, o[0], o[1]);
-            return o;
-        };
-    else throw Error{CKR_E_INVALID, "unknown circuit"};
-    return run_circuit(C, K, key, in, f);
+    const Spec s = spec_of(C, kind, N, 1, kind == kArgminCircuit, cmp, ind);
+    std::vector<std::vector<DCt>> r = run_groups(C, K, {s}, {in});
+    return std::move(r[0]);
 }
 
 // ------------------------------------------------------------------------
@@ -1829,6 +1960,9 @@ ckr_status ckr_ct_import(ckr_context *ctx, const uint64_t *data, size_t words, u
 
 uint32_t ckr_rank_depth(ckr_sign cmp, int tie) { return rank_depth(cmp, tie); }
 uint32_t ckr_argmin_depth(ckr_sign cmp, ckr_sign ind) { return argmin_depth(cmp, ind); }
+uint32_t ckr_order_stat_depth(uint32_t N, uint32_t k, ckr_sign cmp, ckr_sign ind, int tie_correct) {
+    return order_stat_depth((int)N, (int)k, cmp, ind, tie_correct != 0);
+}
 uint32_t ckr_sort_depth(ckr_sign cmp, ckr_sign ind) { return sort_depth(cmp, ind); }
 
 ckr_status ckr_rank(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, ckr_sign cmp, int tie,
@@ -1838,8 +1972,7 @@ ckr_status ckr_rank(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uin
         std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         *out = nullptr;
         Ctx &C = *ctx->C;
-        if (tie) throw Error{CKR_E_INVALID, "tie-corrected rank: use ckr_argmin"};
-        DCt r = rank(C, *keys->K, v->ct, (int)N, cmp);
+        DCt r = tie ? tie_rank(C, *keys->K, v->ct, (int)N, cmp) : rank(C, *keys->K, v->ct, (int)N, cmp);
         *out = wrap(C, std::move(r));
     });
 }
@@ -1948,9 +2081,57 @@ ckr_status ckr_argmin(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, u
         *onehot = *value = nullptr;
         Ctx &C = *ctx->C;
         DCt oh, val;
-        argmin(C, *keys->K, v->ct, (int)N, cmp, ind, oh, val);
+        order_stat(C, *keys->K, v->ct, (int)N, 1, 1, cmp, ind, oh, val);
         *onehot = wrap(C, std::move(oh));
         *value = wrap(C, std::move(val));
+    });
+}
+
+ckr_status ckr_order_stat(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, uint32_t k,
+                          ckr_sign cmp, ckr_sign ind, int tie_correct, ckr_ct **onehot, ckr_ct **value) {
+    return guard([&] {
+        NEED(ctx && keys && v && onehot && value);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
+        *onehot = *value = nullptr;
+        Ctx &C = *ctx->C;
+        DCt oh, val;
+        order_stat(C, *keys->K, v->ct, (int)N, (int)k, tie_correct != 0, cmp, ind, oh, val);
+        *onehot = wrap(C, std::move(oh));
+        *value = wrap(C, std::move(val));
+    });
+}
+
+ckr_status ckr_run_mixed(ckr_context *ctx, const ckr_keys *keys, const ckr_query *q, size_t count, ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && keys && q && out && count);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
+        Ctx &C = *ctx->C;
+        // group queries by (circuit, level) in order of first appearance
+        std::vector<Spec> specs;
+        std::vector<int> levels;
+        std::vector<std::vector<const DCt *>> in;
+        std::vector<std::pair<int, int>> where(count);  // (group, index in group)
+        for (size_t i = 0; i < count; i++) {
+            NEED(q[i].v);
+            const Spec s = spec_of(C, q[i].kind, (int)q[i].N, (int)q[i].k, q[i].tie_correct, q[i].cmp, q[i].ind);
+            const int level = q[i].v->ct.level;
+            int g = 0;
+            while (g < (int)specs.size() && !(specs[g].tup() == s.tup() && levels[g] == level)) g++;
+            if (g == (int)specs.size()) {
+                specs.push_back(s);
+                levels.push_back(level);
+                in.emplace_back();
+            }
+            where[i] = {g, (int)in[g].size()};
+            in[g].push_back(&q[i].v->ct);
+        }
+        std::vector<std::vector<DCt>> outs = run_groups(C, *keys->K, specs, in);
+        std::vector<ckr_ct *> made(2 * count, nullptr);
+        for (size_t i = 0; i < count; i++) {
+            const auto [g, j] = where[i];
+            for (size_t o = 0; o < outs[g].size(); o++) made[2 * i + o] = wrap(C, slice(C, outs[g][o], j, 1));
+        }
+        for (size_t i = 0; i < made.size(); i++) out[i] = made[i];
     });
 }
 

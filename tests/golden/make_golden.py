@@ -70,8 +70,65 @@ def sort128_p17():
             "sorted": [float(x) for x in np.sort(v)]}
 
 
+def mixed_p16d():
+    """two queries of the mixed batch (seed 7): the first rank and the first
+    argmin (order statistic k = 1, no tie-correction) of N = 128, each
+    encrypted at the level its circuit needs, keys at the top level"""
+    O.set_threads(min(16, os.cpu_count() or 1))
+    P = O.Params(**W.PSETS["P16D"])
+    kseed, qs = W.mixed_workload(7, 64)
+    N = 128
+    ir = next(i for i, q in enumerate(qs) if q["kind"] == "rank" and q["N"] == N)
+    ia = next(i for i, q in enumerate(qs) if q["kind"] == "argmin" and q["N"] == N)
+    gal = sorted(set(P.circuit_galois(N, 2)) | set(P.rank_galois(N)))
+    K = O.Keys(P, kseed, P.L, gal)
+    rc = W.RANK_CMP[N]
+    ac, ai = W.ORDER_CMP[N]
+    lr, la = O.rank_depth(*rc), O.order_stat_depth(N, 1, ac, ai, False)
+    q = qs[ir]
+    R = O.rank(K, O.encrypt(K, q["v"], lr, q["eseed"]), N, *rc)
+    out = {"_what": "oracle results of two queries of the mixed rank/argmin batch (mixed_workload seed 7, 64 "
+                    "queries) at n=2^16 (P16D, keys at level 36): the first rank query of N=128 (encrypted at "
+                    "level 17, comparator g^4 f) and the first argmin query of N=128 (order statistic k=1 without "
+                    "tie-correction, encrypted at level 36, comparator g^4 f, indicator g^4 f^2): sha256 of the "
+                    "exported ciphertexts and decoded slots",
+           "rank_index": ir, "rank_level": lr, "rank_sha256": hashlib.sha256(R.export().tobytes()).hexdigest(),
+           "rank_decoded": [float(x) for x in O.decrypt(K, R, N)],
+           "rank_exact": [int(x) for x in np.argsort(np.argsort(q["v"])) + 1]}
+    q = qs[ia]
+    oh, val = O.order_stat(K, O.encrypt(K, q["v"], la, q["eseed"]), N, 1, ac, ai, False)
+    out.update({"argmin_index": ia, "argmin_level": la,
+                "argmin_sha256_onehot": hashlib.sha256(oh.export().tobytes()).hexdigest(),
+                "argmin_sha256_value": hashlib.sha256(val.export().tobytes()).hexdigest(),
+                "argmin_onehot": [float(x) for x in O.decrypt(K, oh, N)],
+                "argmin_value": float(O.decrypt(K, val, 1)[0]),
+                "argmin": int(np.argmin(q["v"])), "min": float(q["v"].min())})
+    return out
+
+
+def argmax128_p17o():
+    N, k = 128, 128
+    cmp, ind = W.ORDER_TIE_CMP[N]
+    O.set_threads(min(16, os.cpu_count() or 1))
+    P = O.Params(**W.PSETS["P17O"])
+    level = P.L
+    v, kseed, eseed = W.tied_workload(N, 0)
+    K = O.Keys(P, kseed, level, P.circuit_galois(N, 2))
+    ct = O.encrypt(K, v, level, eseed)
+    oh, val = O.order_stat(K, ct, N, k, cmp, ind, True)
+    top = int(np.flatnonzero(v == v.max())[-1])
+    return {"_what": "oracle tie-corrected argmax (order statistic k=N) of N=128 at n=2^17 (P17O), tied workload "
+                     "seed 0 (96 distinct values + 32 duplicates), encryption level 44, comparator g^4 f^2, indicator "
+                     "g^4 f^2: sha256 of the exported one-hot and value ciphertexts and their decoded slots",
+            "sha256_onehot": hashlib.sha256(oh.export().tobytes()).hexdigest(),
+            "sha256_value": hashlib.sha256(val.export().tobytes()).hexdigest(),
+            "onehot": [float(x) for x in O.decrypt(K, oh, N)],
+            "value": float(O.decrypt(K, val, 1)[0]),
+            "argmax": top, "max": float(v.max())}
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["rank128_p16", "argmin128_p17", "sort128_p17"]
+    which = sys.argv[1:] or ["rank128_p16", "argmin128_p17", "sort128_p17", "mixed_p16d", "argmax128_p17o"]
     for name in which:
         json.dump(globals()[name](), open(os.path.join(HERE, name + ".json"), "w"), indent=1)
         print("wrote", name + ".json", flush=True)

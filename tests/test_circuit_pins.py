@@ -298,3 +298,22 @@ def test_oracle_order_statistic_matches_shadow(ora, t12d, k, tie):
     j, want = _kth(v, k)
     assert np.array_equal(np.round(got_oh), np.eye(N)[j])
     assert abs(got_val - want) < 0.01
+
+
+def test_oracle_tie_corrected_rank_is_a_permutation(ora, t12d):
+    """Rank plus the tie-correction offset (section 4): equal values take
+    consecutive ranks in index order, so the result is a permutation."""
+    P, keys = t12d
+    N = 8
+    cmp = W.ORDER_TIE_CMP[N][0]
+    v, _, eseed = W.tied_workload(N, 11, 0.01)
+    assert len(set(v.tolist())) < N
+    ct = ora.encrypt(keys, v, P.L, eseed)
+    r = ora.rank_tie(keys, ct, N, *cmp)
+    assert r.level == P.L - ora.rank_depth(*cmp) - 2
+    got = ora.decrypt(keys, r, N)
+    want = np.empty(N)
+    want[np.argsort(v, kind="stable")] = np.arange(1, N + 1)
+    assert np.max(np.abs(got - want)) < 0.05
+    _, _, kv = S.order_stat_circuit(v, N, P.n // 2, 1, cmp, W.ORDER_TIE_CMP[N][1], True)
+    assert np.max(np.abs(got - kv[:N])) < 5e-3    # values up to N; CKKS error of E = C (4 - 4C)

@@ -172,3 +172,118 @@ def test_argmin_and_sort_batched_graphs_equal_single(ora, small):
             for s, o in zip(singles, outs):
                 o = o if isinstance(o, tuple) else (o,)
                 assert all(np.array_equal(a, b.export()) for a, b in zip(s, o)), (kind, rep)
+
+
+def _order_cmp(N, k, tie):
+    return (W.ARGMIN_CMP[N] if k == 1 else W.ORDER_TIE_CMP[N]) if tie else W.ORDER_CMP[N]
+
+
+def _kth_index(v, k):
+    return int(np.argsort(v, kind="stable")[k - 1])
+
+
+@pytest.mark.parametrize("k,tie", [(1, False), (4, False), (8, False), (4, True), (8, True)])
+def test_order_statistic8_bit_exact(ora, small, k, tie):
+    """Order statistic k with and without tie-correction (one-sided indicator at
+    the ends, window in the middle) against the oracle."""
+    P, ctx = small["P"], small["ctx"]
+    N = 8
+    cmp, ind = _order_cmp(N, k, tie)
+    v, _, eseed = W.tied_workload(N, 20 + k, 0.01) if tie else W.rank_workload(N, 0.01, 20 + k)
+    say(f"[gpu] order statistic k={k} tie={tie}")
+    o = ora.encrypt(small["okeys"], v, P.L, eseed)
+    g = ctx.encrypt(small["gkeys"], v, P.L, eseed)
+    ooh, oval = ora.order_stat(small["okeys"], o, N, k, cmp, ind, tie)
+    goh, gval = ctx.order_stat(small["gkeys"], g, N, k, cmp, ind, tie)
+    assert np.array_equal(ooh.export(), goh.export())
+    assert np.array_equal(oval.export(), gval.export())
+    assert np.array_equal(np.round(ctx.decrypt(small["gkeys"], goh, N)), np.eye(N)[_kth_index(v, k)])
+    assert abs(ctx.decrypt(small["gkeys"], gval, 1)[0] - np.sort(v)[k - 1]) < 0.01
+
+
+def test_tie_corrected_rank8_bit_exact(ora, small):
+    P, ctx = small["P"], small["ctx"]
+    N = 8
+    cmp = W.ORDER_TIE_CMP[N][0]
+    v, _, eseed = W.tied_workload(N, 11, 0.01)
+    o = ora.encrypt(small["okeys"], v, P.L, eseed)
+    g = ctx.encrypt(small["gkeys"], v, P.L, eseed)
+    ro = ora.rank_tie(small["okeys"], o, N, *cmp)
+    rg = ctx.rank(small["gkeys"], g, N, cmp, tie=True)
+    assert np.array_equal(ro.export(), rg.export())
+    want = np.empty(N)
+    want[np.argsort(v, kind="stable")] = np.arange(1, N + 1)
+    assert np.array_equal(np.round(ctx.decrypt(small["gkeys"], rg, N)), want)
+
+
+def test_mixed_batch_small_ring_bit_exact(ora, small):
+    """Queries of every kind, several levels and group sizes in one run_mixed
+    call (eager, then captured, then replayed): every output equals the
+    oracle's result for that query alone."""
+    P, ctx, okeys, gkeys = small["P"], small["ctx"], small["okeys"], small["gkeys"]
+    N = 8
+    specs = [dict(kind="rank", cmp=W.RANK_CMP[N]), dict(kind="rank", cmp=W.RANK_CMP[N]),
+             dict(kind="order", k=1, tie=False), dict(kind="rank", cmp=W.RANK_CMP[N], level=P.L),
+             dict(kind="order", k=3, tie=True), dict(kind="order", k=1, tie=False),
+             dict(kind="sort"), dict(kind="argmin"), dict(kind="rank", cmp=W.ORDER_TIE_CMP[N][0], tie=True)]
+    queries, want = [], []
+    for i, s in enumerate(specs):
+        tie = s.get("tie", False)
+        v, _, eseed = W.tied_workload(N, 60 + i, 0.01) if tie or s["kind"] == "argmin" else W.rank_workload(N, 0.01, 60 + i)
+        if s["kind"] == "rank":
+            cmp, ind = s["cmp"], (0, 0)
+            level = s.get("level", ora.rank_depth(*cmp) + (2 if tie else 0))
+        elif s["kind"] == "order":
+            cmp, ind = _order_cmp(N, s["k"], tie)
+            level = ora.order_stat_depth(N, s["k"], cmp, ind, tie)
+        elif s["kind"] == "sort":
+            cmp, ind = W.SORT_CMP[N]
+            level = ora.sort_depth(cmp, ind)
+        else:
+            cmp, ind = W.ARGMIN_CMP[N]
+            level = ora.argmin_depth(cmp, ind)
+        o = ora.encrypt(okeys, v, level, eseed)
+        if s["kind"] == "rank":
+            want.append([(ora.rank_tie(okeys, o, N, *cmp) if tie else ora.rank(okeys, o, N, *cmp)).export()])
+        elif s["kind"] == "order":
+            want.append([x.export() for x in ora.order_stat(okeys, o, N, s["k"], cmp, ind, tie)])
+        elif s["kind"] == "sort":
+            want.append([ora.sort(okeys, o, N, cmp, ind).export()])
+        else:
+            want.append([x.export() for x in ora.argmin(okeys, o, N, cmp, ind)])
+        q = dict(kind=s["kind"], N=N, cmp=cmp, ind=ind, k=s.get("k", 1), tie=tie,
+                 ct=ctx.encrypt(gkeys, v, level, eseed))
+        queries.append(q)
+    for rep in range(3):
+        say(f"[gpu] mixed batch, call {rep}")
+        outs = ctx.run_mixed(gkeys, queries)
+        for i, (o, w) in enumerate(zip(outs, want)):
+            got = [x.export() for x in (o if isinstance(o, tuple) else (o,))]
+            assert len(got) == len(w) and all(np.array_equal(a, b) for a, b in zip(got, w)), (rep, i, specs[i])
+
+
+@pytest.fixture(scope="module")
+def p17o():
+    import paper_2412_15126_amd as ckr
+    say("[gpu] P17O context")
+    ps = W.PSETS["P17O"]
+    return ckr.Context(ps), ps
+
+
+def test_argmax128_with_ties_matches_golden(p17o):
+    ctx, ps = p17o
+    gold = json.load(open(os.path.join(GOLD, "argmax128_p17o.json")))
+    N = 128
+    cmp, ind = W.ORDER_TIE_CMP[N]
+    v, kseed, eseed = W.tied_workload(N, 0)
+    say("[gpu] P17O argmax keygen")
+    keys = ctx.keygen(kseed, ps["L"], [N], what=2)
+    g = ctx.encrypt(keys, v, ps["L"], eseed)
+    say("[gpu] P17O argmax")
+    oh, val = ctx.order_stat(keys, g, N, N, cmp, ind, True)
+    assert hashlib.sha256(oh.export().tobytes()).hexdigest() == gold["sha256_onehot"]
+    assert hashlib.sha256(val.export().tobytes()).hexdigest() == gold["sha256_value"]
+    top = int(np.flatnonzero(v == v.max())[-1])          # ties: the highest index among the maxima
+    assert top == gold["argmax"]
+    assert np.array_equal(np.round(ctx.decrypt(keys, oh, N)), np.eye(N)[top])
+    assert abs(ctx.decrypt(keys, val, 1)[0] - v.max()) < 5e-3
