@@ -145,6 +145,79 @@ def serve(args):
     print(json.dumps(res), flush=True)
 
 
+def mixed(args):
+    """Batched mix: 64 independent rank / argmin queries (N in {16, 32, 64, 128},
+    seed 7), each encrypted at the level its circuit needs, at n=2^16 (P16D);
+    one step = all 64 as one graph launch, against the same queries run one at
+    a time (each its own captured graph)."""
+    import paper_2412_15126_amd as ckr
+    from paper_2412_15126_amd import workloads as W
+
+    ps = W.PSETS["P16D"]
+    ctx = ckr.Context(ps)
+    kseed, qs = W.mixed_workload(7, 64)
+    t = time.time()
+    keys = ctx.keygen(kseed, ps["L"], [16, 32, 64, 128], what=2)
+    log(f"[mixed] keys ready in {time.time() - t:.1f}s")
+    ctx.autotune(2 * 8 * 37, 2)
+    ctx.autotune_row_ip(8, 2)
+    queries = []
+    for q in qs:
+        N = q["N"]
+        if q["kind"] == "rank":
+            cmp, ind = W.RANK_CMP[N], (0, 0)
+            d = dict(kind="rank", level=ckr.rank_depth(cmp))
+        else:
+            cmp, ind = W.ORDER_CMP[N]
+            d = dict(kind="order", k=1, tie=False, level=ckr.order_stat_depth(N, 1, cmp, ind, False))
+        d.update(N=N, cmp=cmp, ind=ind, v=q["v"], ct=ctx.encrypt(keys, q["v"], d["level"], q["eseed"]))
+        queries.append(d)
+    for _ in range(2):      # eager run and capture of every single-query plan
+        for q in queries:
+            ctx.run_mixed(keys, [q])
+    ctx.synchronize()
+    t = time.time()
+    for q in queries:
+        ctx.run_mixed(keys, [q])
+    ctx.synchronize()
+    t_single = time.time() - t
+    for _ in range(2 + args.warmup):
+        outs = ctx.run_mixed(keys, queries)
+    ctx.synchronize()
+    lat = []
+    t0 = time.time()
+    for _ in range(args.steps):
+        ts = time.time()
+        outs = ctx.run_mixed(keys, queries)
+        ctx.synchronize()
+        lat.append((time.time() - ts) * 1e3)
+    wall = time.time() - t0
+    ok = True
+    for q, o in zip(queries, outs):
+        N, v = q["N"], q["v"]
+        if q["kind"] == "rank":
+            ok &= bool(np.array_equal(np.round(ctx.decrypt(keys, o, N)), np.argsort(np.argsort(v)) + 1))
+        else:
+            ok &= bool(np.array_equal(np.round(ctx.decrypt(keys, o[0], N)), np.eye(N)[int(np.argmin(v))]))
+    res = {
+        "metric": "mixed batch queries/s (64 rank/argmin queries, N in {16..128}, one graph launch) at n=2^16",
+        "value": round(len(queries) * args.steps / wall, 3), "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True, "data": "synthetic", "dtype": "u64",
+        "config": {"workload": "64 queries (mixed_workload seed 7): rank and argmin (order statistic k=1, no "
+                               "tie-correction) with equal odds, N uniform in {16,32,64,128}, gap 2^-10, each "
+                               "encrypted at the level its circuit needs; n=2^16, q0 50-bit + 36 primes near 2^40, "
+                               "5 special 50-bit primes, dnum=8"},
+        "one_at_a_time": {"queries_per_s": round(len(queries) / t_single, 3), "ms_total": round(t_single * 1e3, 2)},
+        "speedup_vs_one_at_a_time": round(t_single / (wall / args.steps), 3),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2),
+                       "per": "step of 64 queries"},
+        "results_exact": ok,
+        "levels": sorted({q["level"] for q in queries}),
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +227,7 @@ def main():
     ap.add_argument("--ntt-chunk", type=int, default=0, help="limbs per cached NTT chunk (0: whole batch; -1: choose by timing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true", help="served mix with Poisson arrivals instead of the batch run")
+    ap.add_argument("--mixed", action="store_true", help="64 mixed rank/argmin queries in one launch instead")
     ap.add_argument("--rate", type=float, default=4.0)
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--max-batch", type=int, default=8)
@@ -166,6 +240,8 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
     if args.serve:
         return serve(args)
+    if args.mixed:
+        return mixed(args)
 
     import paper_2412_15126_amd as ckr
     from paper_2412_15126_amd import hip
