@@ -271,7 +271,7 @@ def main():
     tune_limbs = min(2 * B * (level + 1), 1152)
     table = ctx.autotune(tune_limbs, 3)
     chosen = [[int(np.argmin(table[i][p])) for p in range(2)] for i in range(2)]
-    log(f"[bench] autotune ({tune_limbs} limbs): variants fwd {chosen[0]} inv {chosen[1]}")
+    log(f"[bench] autotune ({tune_limbs} limbs): variants fwd {chosen[0]} inv {chosen[1]}; ms {np.round(table, 3).tolist()}")
     ip_ms = ctx.autotune_row_ip(B, 3)
     ip_var = int(np.argmin(ip_ms))
     log(f"[bench] fused row pass + inner product tile: variant {ip_var} ({np.round(ip_ms, 3).tolist()} ms)")
@@ -325,8 +325,8 @@ def main():
         out = step()
     ctx.synchronize()
     # correctness of what is timed: decrypted ranks are exact
-    exact = all(np.array_equal(np.round(ctx.decrypt(keys, o, N)), np.argsort(np.argsort(v)) + 1)
-                for o, v in zip(out, vals))
+    errs = [np.max(np.abs(ctx.decrypt(keys, o, N) - (np.argsort(np.argsort(v)) + 1))) for o, v in zip(out, vals)]
+    exact = bool(max(errs) < 0.5)
     log(f"[bench] warmup done, ranks exact: {exact}")
 
     # timed region: hipGraph replays of the batched circuit, one event pair per step
@@ -384,6 +384,17 @@ def main():
                      "profiled_steps": psteps},
         "kernels": breakdown,
     }
+    # the configs' "composed 4 times": the best 4-fold split (g^3 f) on the same
+    # queries, untimed; reported next to the 5-fold comparator timed above
+    cmp4 = (3, 1)
+    l4 = ckr.rank_depth(cmp4)
+    cts4 = [ctx.encrypt(keys, v, l4, W.rank_workload(N, 2.0 ** -10, 1000 + q)[2]) for q, v in enumerate(vals)]
+    errs4 = [np.max(np.abs(ctx.decrypt(keys, o, N) - (np.argsort(np.argsort(v)) + 1)))
+             for o, v in zip(ctx.run_batch(keys, "rank", cts4, N, cmp4), vals)]
+    res["rank_error"] = {"g4f (timed)": {"max": round(float(max(errs)), 4), "queries_exact": int(sum(e < 0.5 for e in errs))},
+                         "g3f (4 compositions)": {"max": round(float(max(errs4)), 4),
+                                                  "queries_exact": int(sum(e < 0.5 for e in errs4))},
+                         "queries": len(vals)}
     if rank == 0 and not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log(f"[bench] cpu baseline with {threads} threads")

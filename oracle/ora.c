@@ -1071,6 +1071,69 @@ ora_ct *ora_rank(const ora_keys *Kp, const ora_ct *V, u32 N, int dg, int df, int
     return R;
 }
 
+/* Multi-Ciphertext Ranking (section 5, Algorithm Multi-Ciphertext Ranking):
+ * v split into L blocks B_1..B_L of b values each (slots [0,b) of separate
+ * ciphertexts, one level).  C_{i,j} = Cmp(ReplR(B_i), ReplC(TransR(B_j))) is
+ * evaluated for j >= i only; the blocks below the diagonal follow from
+ * Equation (3), C_{i,j} = (1 - C_{j,i})^T, taken column-wise:
+ *   R_i = TransC(SumC(sum_{j<i} (1 - C_{j,i}))) + SumR(sum_{j>=i} C_{i,j}) + 1/2,
+ * where sum_{j<i} (1 - C_{j,i}) is evaluated as (i - 1) - sum_{j<i} C_{j,i}
+ * (one constant add).  The SumR term is brought down to the TransC term's
+ * level, so every R_i leaves at level(B) - depth. */
+int ora_rank_multi_depth(int dg, int df) { return 3 + 3 * (dg + df); }
+
+int ora_rank_multi(const ora_keys *Kp, ora_ct *const *Bk, u32 L, u32 b, int dg, int df, ora_ct **R) {
+    int st = check_N(Kp->P, b);
+    if (st != ORA_OK) return st;
+    if (L < 1) return ORA_E_INVALID;
+    for (u32 i = 0; i < L; i++)
+        if (Bk[i]->level != Bk[0]->level) return ORA_E_INVALID;
+    if (Bk[0]->level < ora_rank_multi_depth(dg, df)) return ORA_E_DEPTH;
+    ora_ct **VR = (ora_ct **)calloc(L, sizeof(ora_ct *)), **VC = (ora_ct **)calloc(L, sizeof(ora_ct *));
+    ora_ct **Cm = (ora_ct **)calloc((size_t)L * L, sizeof(ora_ct *));
+    for (u32 i = 0; i < L; i++) {
+        VR[i] = ora_repl_r(Kp, Bk[i], b, &st);
+        ora_ct *T = ora_trans_r(Kp, Bk[i], b, &st);
+        VC[i] = ora_repl_c(Kp, T, b, &st);
+        ora_ct_free(T);
+    }
+    for (u32 i = 0; i < L; i++)
+        for (u32 j = i; j < L; j++) {
+            ora_ct *VRa = ora_cmul_to(VR[i], 1.0, VC[j]->level, &st);
+            ora_ct *D = ora_sub(VRa, VC[j]);
+            Cm[i * L + j] = ora_cmp_sign(Kp, D, dg, df, &st);
+            ora_ct_free(VRa); ora_ct_free(D);
+        }
+    const int lc = Cm[0]->level; /* comparator output level */
+    double *half = (double *)malloc(b * sizeof(double));
+    for (u32 t = 0; t < b; t++) half[t] = 0.5;
+    for (u32 i = 0; i < L; i++) {
+        ora_ct *S = ct_copy(Cm[i * L + i]);
+        for (u32 j = i + 1; j < L; j++) replace(&S, ora_add(S, Cm[i * L + j]));
+        ora_ct *Rr = ora_sum_r(Kp, S, b, &st);
+        ora_ct *X = ora_cmul_to(Rr, 1.0, lc - 2, &st);
+        if (i > 0) {
+            ora_ct *Tc = ct_copy(Cm[0 * L + i]);
+            for (u32 j = 1; j < i; j++) replace(&Tc, ora_add(Tc, Cm[j * L + i]));
+            ora_ct *nT = mul_int(Tc, -1);
+            ora_ct *Y = ora_add_const(nT, (double)i);
+            ora_ct *SC = ora_sum_c(Kp, Y, b, &st);
+            ora_ct *TC = ora_trans_c(Kp, SC, b, &st);
+            replace(&X, ora_add(X, TC));
+            ora_ct_free(Tc); ora_ct_free(nT); ora_ct_free(Y); ora_ct_free(SC); ora_ct_free(TC);
+        }
+        R[i] = ora_add_plain(X, half, b, &st);
+        ora_ct_free(S); ora_ct_free(Rr); ora_ct_free(X);
+    }
+    free(half);
+    for (u32 i = 0; i < L; i++) {
+        ora_ct_free(VR[i]); ora_ct_free(VC[i]);
+        for (u32 j = i; j < L; j++) ora_ct_free(Cm[i * L + j]);
+    }
+    free(VR); free(VC); free(Cm);
+    return st;
+}
+
 /* Galois elements needed by rank on N elements (left shifts as powers of 5) */
 int ora_rank_galois(const ora_params *P, u32 N, u32 *out) {
     int cnt = 0, lg = ilog2(N);

@@ -98,6 +98,8 @@ def lib():
             "ora_argmin_depth": (C.c_int, [C.c_int] * 4),
             "ora_argmin": (C.c_int, [vp, vp, C.c_uint32, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(vp),
                                      C.POINTER(vp)]),
+            "ora_rank_multi_depth": (C.c_int, [C.c_int, C.c_int]),
+            "ora_rank_multi": (C.c_int, [vp, C.POINTER(vp), C.c_uint32, C.c_uint32, C.c_int, C.c_int, C.POINTER(vp)]),
             "ora_rank_tie": (vp, [vp, vp, C.c_uint32, C.c_int, C.c_int, intp]),
             "ora_order_stat_depth": (C.c_int, [C.c_uint32, C.c_uint32] + [C.c_int] * 5),
             "ora_order_stat": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32] + [C.c_int] * 5 + [C.POINTER(vp), C.POINTER(vp)]),
@@ -178,6 +180,14 @@ class Keys:
         if not self.ptr:
             raise OracleError("keygen failed")
         self.lmax = lmax
+        self.galois = set(int(g) for g in gal)
+
+    def need(self, N, what):
+        """raise unless the keys hold every rotation the circuits `what` on N need
+        (the C circuits do not check for a missing key)"""
+        missing = set(self.params.circuit_galois(N, what)) - self.galois
+        if missing:
+            raise OracleError(f"keys lack {len(missing)} rotation keys needed for N={N}")
 
     def __del__(self):
         if getattr(self, "ptr", None):
@@ -331,6 +341,7 @@ def cmp_matrix(keys, a, N, dg, df):
 
 
 def rank(keys, a, N, dg, df):
+    keys.need(N, 1)
     return _ct(lib().ora_rank, a.params, keys.ptr, a.ptr, N, dg, df, what="rank")
 
 
@@ -338,8 +349,25 @@ def rank_depth(dg, df):
     return lib().ora_rank_depth(dg, df)
 
 
+def rank_multi_depth(dg, df):
+    return lib().ora_rank_multi_depth(dg, df)
+
+
+def rank_multi(keys, blocks, b, dg, df):
+    """Multi-ciphertext ranking of len(blocks) blocks of b values; returns the L rank blocks."""
+    keys.need(b, 4)
+    L = len(blocks)
+    arr = (C.c_void_p * L)(*[x.ptr for x in blocks])
+    out = (C.c_void_p * L)()
+    st = lib().ora_rank_multi(keys.ptr, arr, L, b, dg, df, out)
+    if st != 0:
+        raise OracleError(f"rank_multi: status {STATUS.get(st, st)}")
+    return [Ct(out[i], blocks[0].params) for i in range(L)]
+
+
 def rank_tie(keys, a, N, dg, df):
     """tie-corrected rank (rank plus the tie-correction offset): a permutation of 1..N"""
+    keys.need(N, 1)
     return _ct(lib().ora_rank_tie, a.params, keys.ptr, a.ptr, N, dg, df, what="rank_tie")
 
 
@@ -411,6 +439,7 @@ def argmin_depth(cmp, ind):
 
 def argmin(keys, a, N, cmp, ind):
     """(onehot, value) ciphertexts of the tie-corrected minimum."""
+    keys.need(N, 2)
     oh, val = C.c_void_p(), C.c_void_p()
     st = lib().ora_argmin(keys.ptr, a.ptr, N, cmp[0], cmp[1], ind[0], ind[1], C.byref(oh), C.byref(val))
     if st != 0:
@@ -424,6 +453,7 @@ def order_stat_depth(N, k, cmp, ind, tie):
 
 def order_stat(keys, a, N, k, cmp, ind, tie):
     """(onehot, value) ciphertexts of the k-th smallest element (tie-corrected if tie)."""
+    keys.need(N, 2)
     oh, val = C.c_void_p(), C.c_void_p()
     st = lib().ora_order_stat(keys.ptr, a.ptr, N, k, cmp[0], cmp[1], ind[0], ind[1], int(tie), C.byref(oh),
                               C.byref(val))
@@ -437,4 +467,5 @@ def sort_depth(cmp, ind):
 
 
 def sort(keys, a, N, cmp, ind):
+    keys.need(N, 4)
     return _ct(lib().ora_sort, a.params, keys.ptr, a.ptr, N, cmp[0], cmp[1], ind[0], ind[1], what="sort")

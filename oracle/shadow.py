@@ -235,6 +235,27 @@ def order_stat_circuit(v, N, slots, k, cmp, ind, tie):
     return mask_row(O, N, 0), val, kv
 
 
+def rank_multi_circuit(v, b, slots, cmp):
+    """Multi-Ciphertext Ranking (section 5) on blocks of b values:
+    C_{i,j} = Cmp(ReplR(B_i), ReplC(TransR(B_j))) for j >= i and
+    R_i = TransC(SumC((i - 1) - sum_{j<i} C_{j,i})) + SumR(sum_{j>=i} C_{i,j}) + 1/2
+    (Equation (3) for the blocks below the diagonal).  Returns [R_1..R_L]."""
+    L = len(v) // b
+    blocks = [embed(v[i * b:(i + 1) * b], slots) for i in range(L)]
+    VR = [repl_r(x, b) for x in blocks]
+    VC = [repl_c(trans_r(x, b), b) for x in blocks]
+    C = {(i, j): (sign_composite(VR[i] - VC[j], *cmp) + 1.0) / 2.0 for i in range(L) for j in range(i, L)}
+    half = embed(np.full(b, 0.5), slots)
+    out = []
+    for i in range(L):
+        R = sum_r(sum(C[(i, j)] for j in range(i, L)), b)
+        if i > 0:
+            T = sum(C[(j, i)] for j in range(i))
+            R = R + trans_c(sum_c(i - T, b), b)
+        out.append(R + half)
+    return out
+
+
 def sort_circuit(v, N, slots, cmp, ind):
     """Algorithm Sorting with Ind_0(x) = Cmp(x, -1/2) (1 - Cmp(x, 1/2)) on x/N."""
     x = embed(v, slots)

@@ -50,6 +50,8 @@ ORDER_CMP = {8: ((3, 1), (2, 2)), 16: ((4, 1), (3, 2)), 32: ((4, 1), (3, 2)), 64
              128: ((4, 1), (4, 2))}
 # tie-corrected order statistic for k > 1 (k = 1 uses ARGMIN_CMP)
 ORDER_TIE_CMP = {8: ((3, 1), (2, 2)), 128: ((4, 2), (4, 2))}
+# multi-ciphertext rank (blocks of b values, N = L b): comparator per total N
+MULTI_RANK_CMP = {64: (4, 1), 128: (4, 1), 256: (4, 2), 512: (4, 2), 1024: (4, 2)}
 # sort: (comparator, two-sided indicator)
 SORT_CMP = {8: ((3, 1), (3, 2)), 16: ((4, 1), (3, 2)), 32: ((4, 1), (3, 2)), 64: ((4, 1), (4, 2)),
             128: ((4, 1), (4, 2))}

@@ -317,3 +317,44 @@ def test_oracle_tie_corrected_rank_is_a_permutation(ora, t12d):
     assert np.max(np.abs(got - want)) < 0.05
     _, _, kv = S.order_stat_circuit(v, N, P.n // 2, 1, cmp, W.ORDER_TIE_CMP[N][1], True)
     assert np.max(np.abs(got - kv[:N])) < 5e-3    # values up to N; CKKS error of E = C (4 - 4C)
+
+
+@pytest.mark.parametrize("N,b", [(64, 32), (256, 64), (512, 128)])
+def test_shadow_multi_ciphertext_rank(N, b):
+    """Multi-ciphertext ranking (section 5) with Equation (3) for the lower
+    blocks equals the all-pairs sum over one N x N matrix and the exact ranks."""
+    cmp = W.MULTI_RANK_CMP[N]
+    for seed in range(3):
+        v, _, _ = W.rank_workload(N, 2.0 ** -10, 500 + seed)
+        R = np.concatenate([r[:b] for r in S.rank_multi_circuit(v, b, 2 * b * b, cmp)])
+        C = (S.sign_composite(v[None, :] - v[:, None], *cmp) + 1.0) / 2.0   # C[m][n] = Cmp(v_n, v_m)
+        assert np.max(np.abs(R - (C.sum(axis=0) + 0.5))) < 1e-9
+        assert np.array_equal(np.round(R), np.argsort(np.argsort(v)) + 1)
+
+
+@pytest.mark.parametrize("N", [64, 128])
+def test_oracle_multi_ciphertext_rank_matches_shadow(ora, t12d, N):
+    """the oracle's decoded multi-ciphertext ranks match the shadow and are exact"""
+    P, _ = t12d
+    b = 32                                   # 2^floor(log2 sqrt(n/2)) at n = 2^12
+    cmp = W.MULTI_RANK_CMP[N]
+    v, _, eseed = W.rank_workload(N, 2.0 ** -10, 600 + N)
+    level = ora.rank_multi_depth(*cmp) + 1
+    keys = ora.Keys(P, bytes(range(32)), level, P.circuit_galois(b, 4))
+    blocks = [ora.encrypt(keys, v[i * b:(i + 1) * b], level, bytes([i]) + eseed[1:]) for i in range(N // b)]
+    R = ora.rank_multi(keys, blocks, b, *cmp)
+    assert all(r.level == level - ora.rank_multi_depth(*cmp) for r in R)
+    got = np.concatenate([ora.decrypt(keys, r, b) for r in R])
+    sh = np.concatenate([r[:b] for r in S.rank_multi_circuit(v, b, P.n // 2, cmp)])
+    # each key-switched rotation leaves a systematic ~5e-6 error in slot 0 of
+    # every block; the self-comparisons on the diagonal (difference ~0, where
+    # g^4 f is steepest, slope ~880) carry it into the ranks as ~0.01
+    assert np.max(np.abs(got - sh)) < 0.02
+    assert np.array_equal(np.round(got), np.argsort(np.argsort(v)) + 1)
+
+
+def test_oracle_refuses_circuit_without_its_rotation_keys(ora, t12d):
+    P, keys = t12d                           # keys for N = 8 only
+    ct = ora.encrypt(keys, np.linspace(0, 1, 32), P.L, bytes([3] * 32))
+    with pytest.raises(ora.OracleError):
+        ora.rank(keys, ct, 32, 3, 1)
