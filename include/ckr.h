@@ -171,6 +171,20 @@ ckr_status ckr_sort(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uin
 ckr_status ckr_order_stat(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, uint32_t k,
                           ckr_sign cmp, ckr_sign ind, int tie_correct, ckr_ct **onehot, ckr_ct **value);
 
+/* Multi-ciphertext ranking (section 5, Algorithm Multi-Ciphertext Ranking),
+ * for vectors with N^2 > n/2: v is split into L blocks of b values (b a power
+ * of two with b^2 <= n/2), block i holding v[i*b .. (i+1)*b) in slots [0,b)
+ * of blocks[i], all blocks single ciphertexts at one level.  out (L entries,
+ * caller-owned) receives in out[i] the fractional ranks of block i's elements
+ * among all L*b values, slots [0,b), at level(blocks) - ckr_rank_multi_depth.
+ * Comparisons run for block pairs j >= i only (Equation (3) gives the rest),
+ * in batched comparator passes.  Keys need the rotations of ckr_keygen's
+ * sort set for N = b.  Errors: CKR_E_RANGE (b), CKR_E_INVALID (L = 0, mixed
+ * levels), CKR_E_DEPTH. */
+ckr_status ckr_rank_multi(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *const *blocks, uint32_t L, uint32_t b,
+                          ckr_sign cmp, ckr_ct **out);
+uint32_t ckr_rank_multi_depth(ckr_sign cmp);
+
 /* One query of a mixed batch.  kind: 1 rank (tie_correct selects the
  * tie-corrected rank), 2 argmin (the tie-corrected minimum; k and tie_correct
  * ignored), 3 sort, 4 order statistic k.  v: a single ciphertext, borrowed. */

@@ -69,6 +69,8 @@ _SIGS = {
     "ckr_order_stat": (C.c_int, [vp, vp, vp, C.c_uint32, C.c_uint32, Sign, Sign, C.c_int, C.POINTER(vp),
                                  C.POINTER(vp)]),
     "ckr_run_mixed": (C.c_int, [vp, vp, C.POINTER(Query), C.c_size_t, C.POINTER(vp)]),
+    "ckr_rank_multi": (C.c_int, [vp, vp, C.POINTER(vp), C.c_uint32, C.c_uint32, Sign, C.POINTER(vp)]),
+    "ckr_rank_multi_depth": (C.c_uint32, [Sign]),
     "ckr_sort_depth": (C.c_uint32, [Sign, Sign]),
     "ckr_argmin": (C.c_int, [vp, vp, vp, C.c_uint32, Sign, Sign, C.POINTER(vp), C.POINTER(vp)]),
     "ckr_sort": (C.c_int, [vp, vp, vp, C.c_uint32, Sign, Sign, C.POINTER(vp)]),
@@ -164,6 +166,10 @@ def rank_depth(cmp, tie=False):
     return int(lib().ckr_rank_depth(sign(cmp), int(tie)))
 
 
+def rank_multi_depth(cmp):
+    return int(lib().ckr_rank_multi_depth(sign(cmp)))
+
+
 def order_stat_depth(N, k, cmp, ind, tie):
     return int(lib().ckr_order_stat_depth(N, k, sign(cmp), sign(ind), int(tie)))
 
@@ -235,6 +241,13 @@ class Context:
         h = vp()
         _ok(lib().ckr_rank(self.h, keys.h, ct.h, N, sign(cmp), int(tie), C.byref(h)))
         return Ct(self, h)
+
+    def rank_multi(self, keys, blocks, b, cmp):
+        """Multi-ciphertext ranking: blocks of b values -> one rank block per input block."""
+        arr = (vp * len(blocks))(*[x.h for x in blocks])
+        out = (vp * len(blocks))()
+        _ok(lib().ckr_rank_multi(self.h, keys.h, arr, len(blocks), b, sign(cmp), out))
+        return [Ct(self, vp(o)) for o in out]
 
     def order_stat(self, keys, ct, N, k, cmp, ind, tie):
         """(onehot, value) of the k-th smallest element."""

@@ -624,6 +624,15 @@ static DCt slice(Ctx &C, const DCt &a, int first, int count) {
     return o;
 }
 
+// entries idx[0], idx[1], ... of batch a, in that order
+static DCt gather(Ctx &C, const DCt &a, const std::vector<int> &idx) {
+    DCt o = ct_new(C, a.level, (int)idx.size());
+    const size_t W = (size_t)2 * (a.level + 1) * C.n();
+    for (size_t k = 0; k < idx.size(); k++)
+        HIPCHK(hipMemcpyAsync(o.d() + k * W, a.d() + (size_t)idx[k] * W, W * 8, hipMemcpyDeviceToDevice, C.stream));
+    return o;
+}
+
 // floor-form rescale: c_i <- (c_i - [c_l]_{q_i}) * q_l^{-1} mod q_i.  The
 // last limb is brought to the coefficient domain, then one fused forward
 // transform reduces it modulo every q_i (prologue) and writes the combined
@@ -1023,6 +1032,56 @@ static DCt tie_rank(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp) {
     DCt Et = ev_mul_plain(C, E, get_plain(C, kTieMask, N, E.level));
     DCt Ca = ev_cmul_to(C, Cm, 1.0, Et.level);
     return sum_r(C, K, ev_add(C, Ca, Et, false), N);
+}
+
+// Multi-Ciphertext Ranking (section 5): L blocks of b values (batch entries of
+// Bk).  C_{i,j} = Cmp(ReplR(B_i), ReplC(TransR(B_j))) runs for j >= i only, in
+// batched comparator passes of up to kPairChunk pairs; the blocks below the
+// diagonal follow from Equation (3), C_{i,j} = (1 - C_{j,i})^T, taken
+// column-wise:
+//   R_i = TransC(SumC((i - 1) - sum_{j<i} C_{j,i})) + SumR(sum_{j>=i} C_{i,j}) + 1/2
+// (1-based i), the SumR term brought down to the TransC term's level.
+uint32_t rank_multi_depth(ckr_sign c) { return 3 + 3 * (c.d_g + c.d_f); }
+constexpr int kPairChunk = 32;
+
+static DCt rank_multi(Ctx &C, const Keys &K, const DCt &Bk, int b, ckr_sign cmp) {
+    check_N(C, (u32)b);
+    const int L = Bk.B;
+    if (L < 1) throw Error{CKR_E_INVALID, "no blocks"};
+    if ((u32)Bk.level < rank_multi_depth(cmp)) throw Error{CKR_E_DEPTH, "not enough levels for the ranking"};
+    DCt VR = repl_r(C, K, Bk, b);
+    DCt VC = repl_c(C, K, trans_r(C, K, Bk, b), b);
+    DCt VRa = ev_cmul_to(C, VR, 1.0, VC.level);
+    std::vector<std::pair<int, int>> pairs;
+    for (int i = 0; i < L; i++)
+        for (int j = i; j < L; j++) pairs.push_back({i, j});
+    std::vector<DCt> Srow(L), Tcol(L);
+    auto acc = [&](DCt &sum, DCt &&x) { sum = sum.B ? ev_add(C, sum, x, false) : std::move(x); };
+    for (size_t p0 = 0; p0 < pairs.size(); p0 += kPairChunk) {
+        const size_t np = std::min<size_t>(kPairChunk, pairs.size() - p0);
+        std::vector<int> ii, jj;
+        for (size_t p = p0; p < p0 + np; p++) ii.push_back(pairs[p].first), jj.push_back(pairs[p].second);
+        DCt Cm = cmp_sign(C, K, ev_add(C, gather(C, VRa, ii), gather(C, VC, jj), true), cmp);
+        for (size_t p = 0; p < np; p++) {
+            const int i = ii[p], j = jj[p];
+            acc(Srow[i], slice(C, Cm, (int)p, 1));
+            if (j > i) acc(Tcol[j], slice(C, Cm, (int)p, 1));
+        }
+    }
+    std::vector<const DCt *> sp;
+    for (const DCt &x : Srow) sp.push_back(&x);
+    DCt Rr = sum_r(C, K, stack(C, sp), b);
+    DCt R = ev_cmul_to(C, Rr, 1.0, Rr.level - 1);
+    if (L > 1) {
+        std::vector<DCt> X;
+        for (int i = 1; i < L; i++) X.push_back(ev_add_const(C, ev_mul_int(C, Tcol[i], -1), (double)i));
+        std::vector<const DCt *> xp;
+        for (const DCt &x : X) xp.push_back(&x);
+        DCt TC = trans_c(C, K, sum_c(C, K, stack(C, xp), b), b);
+        DCt head = slice(C, R, 0, 1), tail = ev_add(C, slice(C, R, 1, L - 1), TC, false);
+        R = stack(C, {&head, &tail});
+    }
+    return ev_add_plain(C, R, get_plain(C, kHalfRow0, b, R.level));
 }
 
 // Order statistic k (Algorithm Order Statistic), optionally with the
@@ -1960,6 +2019,7 @@ ckr_status ckr_ct_import(ckr_context *ctx, const uint64_t *data, size_t words, u
 
 uint32_t ckr_rank_depth(ckr_sign cmp, int tie) { return rank_depth(cmp, tie); }
 uint32_t ckr_argmin_depth(ckr_sign cmp, ckr_sign ind) { return argmin_depth(cmp, ind); }
+uint32_t ckr_rank_multi_depth(ckr_sign cmp) { return rank_multi_depth(cmp); }
 uint32_t ckr_order_stat_depth(uint32_t N, uint32_t k, ckr_sign cmp, ckr_sign ind, int tie_correct) {
     return order_stat_depth((int)N, (int)k, cmp, ind, tie_correct != 0);
 }
@@ -2098,6 +2158,26 @@ ckr_status ckr_order_stat(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *
         order_stat(C, *keys->K, v->ct, (int)N, (int)k, tie_correct != 0, cmp, ind, oh, val);
         *onehot = wrap(C, std::move(oh));
         *value = wrap(C, std::move(val));
+    });
+}
+
+ckr_status ckr_rank_multi(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *const *blocks, uint32_t L, uint32_t b,
+                          ckr_sign cmp, ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && keys && blocks && out && L);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
+        Ctx &C = *ctx->C;
+        std::vector<const DCt *> in;
+        for (u32 i = 0; i < L; i++) {
+            NEED(blocks[i]);
+            if (blocks[i]->ct.B != 1 || blocks[i]->ct.level != blocks[0]->ct.level)
+                throw Error{CKR_E_INVALID, "blocks must be single ciphertexts of one level"};
+            in.push_back(&blocks[i]->ct);
+        }
+        DCt R = rank_multi(C, *keys->K, stack(C, in), (int)b, cmp);
+        std::vector<ckr_ct *> made;
+        for (u32 i = 0; i < L; i++) made.push_back(wrap(C, slice(C, R, (int)i, 1)));
+        for (u32 i = 0; i < L; i++) out[i] = made[i];
     });
 }
 

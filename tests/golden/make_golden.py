@@ -127,8 +127,30 @@ def argmax128_p17o():
             "argmax": top, "max": float(v.max())}
 
 
+def rank512_p16_multi():
+    """multi-ciphertext ranking of N = 512 values in 4 blocks of 128 at n = 2^16"""
+    N, b = 512, 128
+    cmp = W.MULTI_RANK_CMP[N]
+    O.set_threads(min(16, os.cpu_count() or 1))
+    P = O.Params(**W.PSETS["P16"])
+    level = O.rank_multi_depth(*cmp)
+    v, kseed, eseed = W.rank_workload(N, 2.0 ** -10, 0)
+    K = O.Keys(P, kseed, level, P.circuit_galois(b, 4))
+    blocks = [O.encrypt(K, v[i * b:(i + 1) * b], level, bytes([i]) + eseed[1:]) for i in range(N // b)]
+    R = O.rank_multi(K, blocks, b, *cmp)
+    dec = np.concatenate([O.decrypt(K, r, b) for r in R])
+    return {"_what": "oracle multi-ciphertext ranking (section 5) of N=512 values (workload seed 0, gap 2^-10) in 4 "
+                     "blocks of 128 at n=2^16 (P16), blocks encrypted at level 21 with seeds (i, eseed[1:]), "
+                     "comparator g^4 f^2: sha256 of each exported rank block and the decoded ranks",
+            "level": level,
+            "sha256": [hashlib.sha256(r.export().tobytes()).hexdigest() for r in R],
+            "decoded": [float(x) for x in dec],
+            "exact": [int(x) for x in np.argsort(np.argsort(v)) + 1]}
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["rank128_p16", "argmin128_p17", "sort128_p17", "mixed_p16d", "argmax128_p17o"]
+    which = sys.argv[1:] or ["rank128_p16", "argmin128_p17", "sort128_p17", "mixed_p16d", "argmax128_p17o",
+                             "rank512_p16_multi"]
     for name in which:
         json.dump(globals()[name](), open(os.path.join(HERE, name + ".json"), "w"), indent=1)
         print("wrote", name + ".json", flush=True)

@@ -287,3 +287,51 @@ def test_argmax128_with_ties_matches_golden(p17o):
     assert top == gold["argmax"]
     assert np.array_equal(np.round(ctx.decrypt(keys, oh, N)), np.eye(N)[top])
     assert abs(ctx.decrypt(keys, val, 1)[0] - v.max()) < 5e-3
+
+
+@pytest.mark.parametrize("N", [64, 128])
+def test_multi_ciphertext_rank_bit_exact(ora, N):
+    """Multi-ciphertext ranking (section 5) on blocks of 32 at n = 2^12 against
+    the oracle, block for block."""
+    import paper_2412_15126_amd as ckr
+    ps = W.PSETS["T12D"]
+    P = ora.Params(**ps)
+    b = 32
+    cmp = W.MULTI_RANK_CMP[N]
+    level = ora.rank_multi_depth(*cmp) + 1
+    seed = bytes(range(2, 34))
+    okeys = ora.Keys(P, seed, level, P.circuit_galois(b, 4))
+    ctx = ckr.Context(ps)
+    gkeys = ctx.keygen(seed, level, [b], what=4)
+    v, _, eseed = W.rank_workload(N, 2.0 ** -10, 700 + N)
+    say(f"[gpu] multi-ciphertext rank N={N}")
+    ob = [ora.encrypt(okeys, v[i * b:(i + 1) * b], level, bytes([i]) + eseed[1:]) for i in range(N // b)]
+    gb = [ctx.encrypt(gkeys, v[i * b:(i + 1) * b], level, bytes([i]) + eseed[1:]) for i in range(N // b)]
+    Ro = ora.rank_multi(okeys, ob, b, *cmp)
+    Rg = ctx.rank_multi(gkeys, gb, b, cmp)
+    assert len(Rg) == N // b
+    for o, g in zip(Ro, Rg):
+        assert np.array_equal(o.export(), g.export())
+    got = np.concatenate([ctx.decrypt(gkeys, r, b) for r in Rg])
+    assert np.array_equal(np.round(got), np.argsort(np.argsort(v)) + 1)
+
+
+def test_multi_ciphertext_rank512_full_size_matches_golden():
+    """N = 512 values in 4 blocks of 128 at n = 2^16 against oracle digests."""
+    import paper_2412_15126_amd as ckr
+    gold = json.load(open(os.path.join(GOLD, "rank512_p16_multi.json")))
+    ps = W.PSETS["P16"]
+    N, b = 512, 128
+    cmp = W.MULTI_RANK_CMP[N]
+    level = ckr.rank_multi_depth(cmp)
+    assert level == gold["level"]
+    v, kseed, eseed = W.rank_workload(N, 2.0 ** -10, 0)
+    ctx = ckr.Context(ps)
+    say("[gpu] P16 multi-ciphertext keys")
+    keys = ctx.keygen(kseed, level, [b], what=4)
+    blocks = [ctx.encrypt(keys, v[i * b:(i + 1) * b], level, bytes([i]) + eseed[1:]) for i in range(N // b)]
+    say("[gpu] P16 multi-ciphertext rank of 512")
+    R = ctx.rank_multi(keys, blocks, b, cmp)
+    assert [hashlib.sha256(r.export().tobytes()).hexdigest() for r in R] == gold["sha256"]
+    got = np.concatenate([ctx.decrypt(keys, r, b) for r in R])
+    assert np.array_equal(np.round(got), np.argsort(np.argsort(v)) + 1)
