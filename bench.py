@@ -218,6 +218,122 @@ def mixed(args):
     print(json.dumps(res), flush=True)
 
 
+def circuit_bench(args):
+    """The other circuits at their full sizes: tie-corrected argmin / argmax of
+    N=128 (25% duplicates) and sort of N=128 at n=2^17, multi-ciphertext rank
+    of N=512 in 4 blocks of 128 at n=2^16.  One step = one batch of queries
+    (graph-captured for the single-ciphertext circuits)."""
+    import paper_2412_15126_amd as ckr
+    from paper_2412_15126_amd import hip
+    from paper_2412_15126_amd import workloads as W
+
+    name = args.workload
+    spec = {
+        "argmin128": dict(pset="P17", N=128, q=dict(kind="order", k=1, tie=True), ci=W.ARGMIN_CMP[128], what=2,
+                          desc="tie-corrected argmin of N=128 (96 distinct values + 32 duplicates, gap 2^-10) at "
+                               "n=2^17 (41 + 10 primes, dnum=4), encrypted at level 40, comparator g^4 f^2, "
+                               "indicator g^3 f^2"),
+        "argmax128": dict(pset="P17O", N=128, q=dict(kind="order", k=128, tie=True), ci=W.ORDER_TIE_CMP[128], what=2,
+                          desc="tie-corrected argmax of N=128 (96 distinct values + 32 duplicates, gap 2^-10) at "
+                               "n=2^17 (45 + 11 primes, dnum=4), encrypted at level 44, comparator and indicator "
+                               "g^4 f^2"),
+        "sort128": dict(pset="P17", N=128, q=dict(kind="sort"), ci=W.SORT_CMP[128], what=4,
+                        desc="sort of N=128 (gap 2^-10) at n=2^17 (41 + 10 primes, dnum=4), encrypted at level 40, "
+                             "comparator g^4 f, indicator g^4 f^2"),
+        "rank512": dict(pset="P16", N=512, b=128, ci=(W.MULTI_RANK_CMP[512], None), what=4,
+                        desc="multi-ciphertext rank of N=512 (gap 2^-10) in 4 blocks of 128 at n=2^16 (24 + 7 "
+                             "primes, dnum=3), blocks encrypted at level 21, comparator g^4 f^2"),
+    }[name]
+    ps = W.PSETS[spec["pset"]]
+    N = spec["N"]
+    cmp, ind = spec["ci"]
+    multi = "b" in spec
+    b = spec.get("b", N)
+    level = ckr.rank_multi_depth(cmp) if multi else ps["L"]
+    B = max(1, args.batch if args.batch != 32 else (1 if multi else 4))
+    ctx = ckr.Context(ps)
+    stream = hip.Stream()
+    ctx.set_stream(stream.h.value)
+    t = time.time()
+    keys = ctx.keygen(bytes(range(11, 43)), level, [b], what=spec["what"])
+    log(f"[{name}] keygen {time.time() - t:.1f}s")
+    ctx.autotune(2 * 4 * (level + 1), 2)
+    ctx.autotune_row_ip(4, 2)
+    queries, vals = [], []
+    for i in range(B):
+        tie = spec.get("q", {}).get("tie", False)
+        v, _, eseed = W.tied_workload(N, 2000 + i) if tie else W.rank_workload(N, 2.0 ** -10, 2000 + i)
+        vals.append(v)
+        if multi:
+            queries.append([ctx.encrypt(keys, v[j * b:(j + 1) * b], level, bytes([j]) + eseed[1:])
+                            for j in range(N // b)])
+        else:
+            queries.append(dict(spec["q"], N=N, cmp=cmp, ind=ind, ct=ctx.encrypt(keys, v, level, eseed)))
+
+    def step():
+        if multi:
+            return [ctx.rank_multi(keys, blk, b, cmp) for blk in queries]
+        return ctx.run_mixed(keys, queries)
+
+    def check(outs):
+        worst = 0.0
+        for v, o in zip(vals, outs):
+            if multi:
+                got = np.concatenate([ctx.decrypt(keys, r, b) for r in o])
+                worst = max(worst, float(np.max(np.abs(got - (np.argsort(np.argsort(v)) + 1)))))
+            elif spec["q"]["kind"] == "sort":
+                worst = max(worst, float(np.max(np.abs(ctx.decrypt(keys, o, N) - np.sort(v)))))
+            else:
+                k = spec["q"]["k"]
+                j = int(np.argsort(v, kind="stable")[k - 1])
+                oh = np.round(ctx.decrypt(keys, o[0], N))
+                if not np.array_equal(oh, np.eye(N)[j]):
+                    return False, float("inf")
+                worst = max(worst, abs(float(ctx.decrypt(keys, o[1], 1)[0]) - float(np.sort(v)[k - 1])))
+        bound = 0.5 if multi else 5e-3
+        return worst < bound, worst
+
+    for _ in range(2 + args.warmup):
+        outs = step()
+    ctx.synchronize()
+    ok, worst = check(outs)
+    log(f"[{name}] warmup done, results correct: {ok} (worst error {worst:.3g})")
+    ev = [hip.Event() for _ in range(args.steps + 1)]
+    ctx.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for s_ in range(args.steps):
+        step()
+        ev[s_ + 1].record(stream)
+    ctx.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [ev[s_].elapsed_ms(ev[s_ + 1]) for s_ in range(args.steps)]
+    ctx.set_profiling(True)
+    ctx.profile_reset()
+    step()
+    ctx.synchronize()
+    ctx.set_profiling(False)
+    prof = ctx.profile()
+    dom = max(prof, key=lambda k: prof[k][1])
+    launches, ms, nbytes = prof[dom]
+    achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    res = {
+        "metric": f"{name} queries/s", "value": round(B * args.steps / wall, 3), "unit": "queries/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True, "data": "synthetic", "dtype": "u64",
+        "config": {"workload": spec["desc"], "batch": B, "correct": ok, "worst_error": worst},
+        "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
+                       "p99": round(float(np.percentile(step_ms, 99)), 3), "per": f"step of {B} queries"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "launches": int(launches), "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
+                     "profiled_steps": 1},
+        "kernels": {k: {"launches": int(v[0]), "ms": round(v[1], 3),
+                        "GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else 0.0} for k, v in prof.items()},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,6 +344,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true", help="served mix with Poisson arrivals instead of the batch run")
     ap.add_argument("--mixed", action="store_true", help="64 mixed rank/argmin queries in one launch instead")
+    ap.add_argument("--workload", default="rank128",
+                    choices=["rank128", "argmin128", "argmax128", "sort128", "rank512"],
+                    help="circuit to time (rank128: the headline metric)")
     ap.add_argument("--rate", type=float, default=4.0)
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--max-batch", type=int, default=8)
@@ -242,6 +361,8 @@ def main():
         return serve(args)
     if args.mixed:
         return mixed(args)
+    if args.workload != "rank128":
+        return circuit_bench(args)
 
     import paper_2412_15126_amd as ckr
     from paper_2412_15126_amd import hip
@@ -329,6 +450,18 @@ def main():
     exact = bool(max(errs) < 0.5)
     log(f"[bench] warmup done, ranks exact: {exact}")
 
+    # the configs' "composed 4 times": the best 4-fold split (g^3 f) on the same
+    # queries, untimed; reported next to the 5-fold comparator timed above
+    cmp4 = (3, 1)
+    l4 = ckr.rank_depth(cmp4)
+    cts4 = [ctx.encrypt(keys, v, l4, W.rank_workload(N, 2.0 ** -10, 1000 + q)[2]) for q, v in enumerate(vals)]
+    errs4 = [np.max(np.abs(ctx.decrypt(keys, o, N) - (np.argsort(np.argsort(v)) + 1)))
+             for o, v in zip(ctx.run_batch(keys, "rank", cts4, N, cmp4), vals)]
+    rank_error = {"g4f (timed)": {"max": round(float(max(errs)), 4), "queries_exact": int(sum(e < 0.5 for e in errs))},
+                  "g3f (4 compositions)": {"max": round(float(max(errs4)), 4),
+                                           "queries_exact": int(sum(e < 0.5 for e in errs4))},
+                  "queries": len(vals)}
+
     # timed region: hipGraph replays of the batched circuit, one event pair per step
     wall, step_ms, total_ms = timed_steps(step, args.steps)
     log(f"[bench] timed {args.steps} steps: {total_ms:.1f} ms on device, {wall * 1e3:.1f} ms wall")
@@ -383,18 +516,8 @@ def main():
                      "launches": int(launches), "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
                      "profiled_steps": psteps},
         "kernels": breakdown,
+        "rank_error": rank_error,
     }
-    # the configs' "composed 4 times": the best 4-fold split (g^3 f) on the same
-    # queries, untimed; reported next to the 5-fold comparator timed above
-    cmp4 = (3, 1)
-    l4 = ckr.rank_depth(cmp4)
-    cts4 = [ctx.encrypt(keys, v, l4, W.rank_workload(N, 2.0 ** -10, 1000 + q)[2]) for q, v in enumerate(vals)]
-    errs4 = [np.max(np.abs(ctx.decrypt(keys, o, N) - (np.argsort(np.argsort(v)) + 1)))
-             for o, v in zip(ctx.run_batch(keys, "rank", cts4, N, cmp4), vals)]
-    res["rank_error"] = {"g4f (timed)": {"max": round(float(max(errs)), 4), "queries_exact": int(sum(e < 0.5 for e in errs))},
-                         "g3f (4 compositions)": {"max": round(float(max(errs4)), 4),
-                                                  "queries_exact": int(sum(e < 0.5 for e in errs4))},
-                         "queries": len(vals)}
     if rank == 0 and not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log(f"[bench] cpu baseline with {threads} threads")
