@@ -55,6 +55,15 @@ __device__ __forceinline__ double red_any(double x, double q, double qinv) {
     return r >= q ? r - q : r;
 }
 
+// Evaluation-domain automorphism sigma_g: position i holds a(psi^{2 brev(i) + 1}),
+// and sigma_g(a) at i is a at the position of exponent (2 brev(i) + 1) g.  The
+// map keeps aligned blocks of 2^k positions together (for every k), so
+// gathers through it stay coalesced.
+__device__ __forceinline__ u32 gal_src(u32 i, int logn, u32 g) {
+    const u32 e = (u32)((((u64)(__brev(i) >> (32 - logn)) * 2 + 1) * g) & ((2u << logn) - 1));
+    return __brev((e - 1) >> 1) >> (32 - logn);
+}
+
 // ------------------------------------------------------------------------
 // negacyclic NTT: one pass of a two-pass decomposition n = n1 * n2
 // ------------------------------------------------------------------------
@@ -77,7 +86,8 @@ __device__ __forceinline__ double red_any(double x, double q, double qinv) {
 template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool PRO, class Emit>
 __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, int logn, int mod, double q,
                                           double qinv, const double2 *__restrict__ tw,
-                                          const double2 *__restrict__ twlast, double *lds, Emit &&emit) {
+                                          const double2 *__restrict__ twlast, double *lds, Emit &&emit,
+                                          u32 gal = 0) {
     constexpr int S = 1 << LOGS, E = 1 << LOGE, TPC = S / E, NT = C * TPC;
     constexpr int NR = (LOGS + LOGE - 1) / LOGE;
     constexpr int SP = S + (S >> 4) + 1;
@@ -108,12 +118,22 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
 #pragma unroll
                 for (int k = 0; k < E; k++) x[k] = red_any(u2d(din[gaddr(rbase | (k << w))]), q, qinv);
             } else if (direct) {
+                if (gal > 1) {
 #pragma unroll
-                for (int k = 0; k < E; k++) x[k] = u2d(din[gaddr(rbase | (k << w))]);
+                    for (int k = 0; k < E; k++) x[k] = u2d(din[gal_src(gaddr(rbase | (k << w)), logn, gal)]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < E; k++) x[k] = u2d(din[gaddr(rbase | (k << w))]);
+                }
             } else {
                 // rows are contiguous: the tile is C*S consecutive words
                 const u64 *tile = din + (u32)(c0 * S);
-                for (int i = tid; i < C * S; i += NT) lds[lidx(i / S, i % S)] = u2d(tile[i]);
+                if (gal > 1) {
+                    for (int i = tid; i < C * S; i += NT)
+                        lds[lidx(i / S, i % S)] = u2d(din[gal_src((u32)(c0 * S + i), logn, gal)]);
+                } else {
+                    for (int i = tid; i < C * S; i += NT) lds[lidx(i / S, i % S)] = u2d(tile[i]);
+                }
                 __syncthreads();
 #pragma unroll
                 for (int k = 0; k < E; k++) x[k] = lds[lidx(cl, rbase | (k << w))];
@@ -216,7 +236,7 @@ template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool FUSE>
 __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
     ntt_pass(u64 *__restrict__ base, size_t poly_stride, int limbs, LimbMap map, int logn,
              const double2 *__restrict__ mq, const double2 *__restrict__ twtab, const double2 *__restrict__ twlast,
-             const NttFuse fz, const u64 *__restrict__ src, size_t src_stride) {
+             const NttFuse fz, const u64 *__restrict__ src, size_t src_stride, u32 gal) {
     constexpr int S = 1 << LOGS;
     constexpr int SP = S + (S >> 4) + 1;
     __shared__ double lds[C * SP];
@@ -233,6 +253,7 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
     constexpr bool PRO = FUSE && COLPASS && !INV;   // prologue: broadcast-reduce one limb
     constexpr bool EPI = FUSE && !COLPASS && !INV;  // epilogue: (x - y) * c (+ add)
     const int c0 = blockIdx.x * C;
+    const u32 g = (FIRST && src) ? gal : 0;  // automorphism applied while reading the input
     if constexpr (EPI) {
         const size_t pb = (size_t)(p >> 1), pk = (size_t)(p & 1);
         u64 *pout = fz.out + pb * fz.out_stride + pk * fz.out_off + (size_t)t * n;
@@ -242,10 +263,11 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
         if (fz.add2 && (fz.add2_mask >> pk & 1))
             padd2 = fz.add2 + pb * fz.add2_stride + pk * fz.add2_off + (size_t)t * n;
         const double ec = fz.c.v[t], ecq = fz.c.vq[t];
+        const u32 ag = fz.add_gal;
         pass_core<LOGS, LOGE, C, COLPASS, INV, false>(din, c0, logn, mod, q, qinv, tw, twlast, lds,
                                                       [&](int, u32 pos, double y) {
             double r = red1(mm_lazy(u2d(px[pos]) - y + q, ec, ecq, q), q);
-            if (padd) r = red1(r + u2d(padd[pos]), q);
+            if (padd) r = red1(r + u2d(padd[ag > 1 ? gal_src(pos, logn, ag) : pos]), q);
             if (padd2) r = red1(r + u2d(padd2[pos]), q);
             pout[pos] = d2u(r);
         });
@@ -254,7 +276,7 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
                                                      twlast, lds, [&](int, u32 pos, double y) { data[pos] = d2u(y); });
     } else {
         pass_core<LOGS, LOGE, C, COLPASS, INV, false>(din, c0, logn, mod, q, qinv, tw, twlast, lds,
-                                                      [&](int, u32 pos, double y) { data[pos] = d2u(y); });
+                                                      [&](int, u32 pos, double y) { data[pos] = d2u(y); }, g);
     }
 }
 
@@ -311,8 +333,13 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
         if (j == own) {
             const u64 *xs = a.d + bi * a.sd + (size_t)t * n;
             double xv[E];
+            if (a.gal > 1) {
 #pragma unroll
-            for (int k = 0; k < E; k++) xv[k] = u2d(xs[(u32)(c0 * S + tid + k * NT)]);
+                for (int k = 0; k < E; k++) xv[k] = u2d(xs[gal_src((u32)(c0 * S + tid + k * NT), logn, a.gal)]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < E; k++) xv[k] = u2d(xs[(u32)(c0 * S + tid + k * NT)]);
+            }
 #pragma unroll
             for (int k = 0; k < E; k++) acc(k, 0, xv[k]);
         } else {
@@ -348,10 +375,10 @@ static void launch_pass(const DevTables &T, const LimbBatch &b, hipStream_t s, c
     const double2 *tw = INV ? T.tw_inv : T.tw_fwd;
     if (f && !INV && (COLPASS ? f->pro : f->epi))
         hipLaunchKernelGGL((ntt_pass<LOGS, LOGE, C, COLPASS, INV, true>), grid, block, 0, s, b.base, b.poly_stride,
-                           b.limbs, b.map, logn, T.mq, tw, T.tw_last, *f, b.src, b.src_stride);
+                           b.limbs, b.map, logn, T.mq, tw, T.tw_last, *f, b.src, b.src_stride, b.gal);
     else
         hipLaunchKernelGGL((ntt_pass<LOGS, LOGE, C, COLPASS, INV, false>), grid, block, 0, s, b.base, b.poly_stride,
-                           b.limbs, b.map, logn, T.mq, tw, T.tw_last, NttFuse{}, b.src, b.src_stride);
+                           b.limbs, b.map, logn, T.mq, tw, T.tw_last, NttFuse{}, b.src, b.src_stride, b.gal);
 }
 
 // tile variants: (elements per thread 2^LOGE, columns per workgroup C)
@@ -564,9 +591,7 @@ __global__ void ew_automorph(u64 *out, const u64 *in, int limbs, size_t so, size
     const size_t n = (size_t)1 << logn;
     const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const u32 e = (u32)((((u64)(__brev(i) >> (32 - logn)) * 2 + 1) * g) & (2 * n - 1));
-    const u32 src = __brev((e - 1) >> 1) >> (32 - logn);
-    out[p * so + t * n + i] = in[p * si + t * n + src];
+    out[p * so + t * n + i] = in[p * si + t * n + gal_src(i, logn, g)];
 }
 
 // fast base conversion; grid.x over coefficients, grid.y over the batch,

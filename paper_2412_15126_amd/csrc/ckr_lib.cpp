@@ -367,12 +367,13 @@ static void for_chunks(Ctx &C, int limbs, int polys, F &&f) {
 }
 
 static void ntt(Ctx &C, u64 *base, int limbs, int polys, size_t stride, LimbMap map, bool inv,
-                const u64 *src = nullptr, size_t src_stride = 0) {
+                const u64 *src = nullptr, size_t src_stride = 0, u32 gal = 0) {
     for_chunks(C, limbs, polys, [&](int p0, int np) {
         LimbBatch b{base + (size_t)p0 * stride, limbs, np, stride, map};
         if (src) {
             b.src = src + (size_t)p0 * src_stride;
             b.src_stride = src_stride;
+            b.gal = gal;
         }
         const double bytes = 16.0 * C.P.n * limbs * np;
         timed(C, inv ? kNttInvRow : kNttFwdCol, bytes, [&] { k_ntt_pass(C.T, b, inv, 0, C.stream); });
@@ -686,16 +687,19 @@ static DCt ev_cmul_to(Ctx &C, const DCt &a, double c, int target) {
 //   out_b = ModDown(sum_j ModUp_j(d) * key_j.b) (+ add_b),  out_a likewise
 // Output poly k (0: b part, 1: a part) of batch entry b goes to out + b*so + k*out_off
 // and, when bit k of add_mask is set, has add + b*sadd + k*add_off added.
+// With gal > 1, d and add are read through the automorphism sigma_gal: the
+// rotation's permutation rides in the key switch's loads.
 static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_t sd, int l, int B, u64 *out,
                       size_t so, size_t out_off, const u64 *add, size_t sadd, size_t add_off, int add_mask,
-                      const u64 *add2 = nullptr, size_t sadd2 = 0, size_t add2_off = 0, int add2_mask = 0) {
+                      const u64 *add2 = nullptr, size_t sadd2 = 0, size_t add2_off = 0, int add2_mask = 0,
+                      u32 gal = 0) {
     const Params &P = C.P;
     if (l > K.lmax) throw Error{CKR_E_DEPTH, "ciphertext above key level"};
     const size_t n = C.n();
     const int beta = P.beta(l), E = l + 1 + P.K;
     // coefficient-domain copy of d
     Buf dc(&C, (size_t)B * (l + 1) * n);
-    ntt(C, dc.get(), l + 1, B, (size_t)(l + 1) * n, plain_map(), true, d, sd);
+    ntt(C, dc.get(), l + 1, B, (size_t)(l + 1) * n, plain_map(), true, d, sd, gal);
     // ModUp: base conversion of each digit to the other limbs, then NTT
     const size_t sext = (size_t)beta * E * n;
     Buf ext(&C, (size_t)B * sext);
@@ -730,6 +734,7 @@ static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_
     ia.sd = sd;
     ia.sext = sext;
     ia.sacc = sacc;
+    ia.gal = gal;
     // per target limb: beta inputs and 2 outputs per batch entry, 2*beta key limbs once
     timed(C, kNttRowIP, 8.0 * n * E * ((beta + 2.0) * B + 2.0 * beta), [&] { k_ntt_row_ip(C.T, ia, C.stream); });
     // ModDown: (x_Q - BConv_{P->Q}(x_P)) * P^{-1}, the combine fused into the last NTT pass
@@ -759,6 +764,7 @@ static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_
     f.add_stride = sadd;
     f.add_off = add_off;
     f.add_mask = add ? add_mask : 0;
+    f.add_gal = gal;
     f.add2 = add2;
     f.add2_stride = sadd2;
     f.add2_off = add2_off;
@@ -800,11 +806,9 @@ static DCt ev_rotate(Ctx &C, const Keys &K, const DCt &a, i64 k) {
     const Buf &key = find_key(K, g);
     const int l = a.level;
     const size_t n = C.n(), L = (size_t)(l + 1) * n;
-    DCt r = ct_new(C, l, a.B);
-    timed(C, kAutomorph, 32.0 * L * a.B, [&] { k_automorph(C.T, r.d(), a.d(), l + 1, 2 * a.B, L, L, g, C.stream); });
     DCt o = ct_new(C, l, a.B);
-    // (sigma(c0) + KS_b(sigma(c1)), KS_a(sigma(c1)))
-    keyswitch(C, K, key, r.d() + L, 2 * L, l, a.B, o.d(), 2 * L, L, r.d(), 2 * L, L, 1);
+    // (sigma(c0) + KS_b(sigma(c1)), KS_a(sigma(c1))), sigma applied while reading c0 and c1
+    keyswitch(C, K, key, a.d() + L, 2 * L, l, a.B, o.d(), 2 * L, L, a.d(), 2 * L, L, 1, nullptr, 0, 0, 0, g);
     return o;
 }
 
@@ -815,11 +819,9 @@ static DCt ev_rotate_add(Ctx &C, const Keys &K, const DCt &a, i64 k) {
     const Buf &key = find_key(K, g);
     const int l = a.level;
     const size_t n = C.n(), L = (size_t)(l + 1) * n;
-    DCt r = ct_new(C, l, a.B);
-    timed(C, kAutomorph, 32.0 * L * a.B, [&] { k_automorph(C.T, r.d(), a.d(), l + 1, 2 * a.B, L, L, g, C.stream); });
     DCt o = ct_new(C, l, a.B);
-    // (a0 + sigma(a0) + KS_b(sigma(a1)), a1 + KS_a(sigma(a1)))
-    keyswitch(C, K, key, r.d() + L, 2 * L, l, a.B, o.d(), 2 * L, L, r.d(), 2 * L, L, 1, a.d(), 2 * L, L, 3);
+    // (a0 + sigma(a0) + KS_b(sigma(a1)), a1 + KS_a(sigma(a1))), sigma applied while reading a0 and a1
+    keyswitch(C, K, key, a.d() + L, 2 * L, l, a.B, o.d(), 2 * L, L, a.d(), 2 * L, L, 1, a.d(), 2 * L, L, 3, g);
     return o;
 }
 

@@ -53,6 +53,7 @@ struct LimbBatch {
     LimbMap map;
     const u64 *src = nullptr;  // when set, the first pass reads limb t of poly p from src + p*src_stride + t*n
     size_t src_stride = 0;
+    u32 gal = 0;  // when > 1, the first pass reads its input through the automorphism sigma_gal (src must be set)
 };
 
 // ---- kernels (ckr_kernels.hip) ------------------------------------------
@@ -79,6 +80,7 @@ struct NttFuse {
     const u64 *add = nullptr;
     size_t add_stride = 0, add_off = 0;
     int add_mask = 0;
+    u32 add_gal = 0;            // when > 1, add is read through the automorphism sigma_add_gal
     const u64 *add2 = nullptr;  // a second addend, addressed like add
     size_t add2_stride = 0, add2_off = 0;
     int add2_mask = 0;
@@ -132,6 +134,7 @@ struct IPArgs {
     int level, E, beta, alpha, Ek, lmax_key, nq;
     int B;                       // batch of inputs sharing the key
     size_t sd, sext, sacc;       // batch strides of d, ext, accb/acca
+    u32 gal = 0;                 // when > 1, d is read through the automorphism sigma_gal
 };
 // computed with the forward row pass of ext fused in front: ext holds the
 // extended limbs after their column pass only
