@@ -293,7 +293,8 @@ ckr_status ckr_profile_read(ckr_context *ctx, int category, uint64_t *launches, 
 const char *ckr_profile_name(int category);
 
 /* NTT autotuner: times each compiled tile variant (elements per thread x
- * columns per workgroup) of every (direction, pass) on `limbs` limbs, `iters`
+ * columns per workgroup) of every (direction, pass) on `limbs` limbs (one launch
+ * over polynomials of the whole q chain, then the rest), `iters`
  * repetitions, and keeps the fastest for this context.  ms, if not NULL,
  * receives the 2 x 2 x 4 average milliseconds [inverse][pass][variant].
  * Every variant computes the same transform bit for bit. */

@@ -359,6 +359,7 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
 
 template <int LOGS, int LOGE, int C>
 static void launch_row_ip(const DevTables &T, const IPArgs &a, hipStream_t s) {
+    static_assert(C * (1 << (LOGS - LOGE)) <= 1024, "workgroup larger than 1024 threads");
     const int tiles = (1 << (T.logn - LOGS)) / C;
     const int groups = a.E * tiles;
     const unsigned blocks = (unsigned)(((groups + 7) / 8) * 8) * (unsigned)a.B;
@@ -368,6 +369,7 @@ static void launch_row_ip(const DevTables &T, const IPArgs &a, hipStream_t s) {
 
 template <int LOGS, int LOGE, int C, bool COLPASS, bool INV>
 static void launch_pass(const DevTables &T, const LimbBatch &b, hipStream_t s, const NttFuse *f = nullptr) {
+    static_assert(C * (1 << (LOGS - LOGE)) <= 1024, "workgroup larger than 1024 threads");
     const int logn = T.logn;
     const int blocks = (1 << (logn - LOGS)) / C;
     dim3 grid(blocks, b.limbs * b.polys);
@@ -382,15 +384,15 @@ static void launch_pass(const DevTables &T, const LimbBatch &b, hipStream_t s, c
 }
 
 // tile variants: (elements per thread 2^LOGE, columns per workgroup C)
-//   passes of 2^8 and 2^9 points: 0 (16, 16), 1 (16, 8), 2 (8, 16), 3 (16, 32) / (8, 8)
+//   passes of 2^8 and 2^9 points: 0 (16, 16), 1 (8, 32) / (16, 32), 2 (8, 16), 3 (8, 8)
 //   smaller passes: one fixed tile
 template <int LOGS, bool COLPASS, bool INV>
 static void pass_variant(const DevTables &T, const LimbBatch &b, hipStream_t s, const NttFuse *f, int v) {
     if constexpr (LOGS == 8 || LOGS == 9) {
         switch (v) {
-        case 1: launch_pass<LOGS, 4, 8, COLPASS, INV>(T, b, s, f); return;
+        case 1: launch_pass<LOGS, (LOGS == 8 ? 3 : 4), 32, COLPASS, INV>(T, b, s, f); return;
         case 2: launch_pass<LOGS, 3, 16, COLPASS, INV>(T, b, s, f); return;
-        case 3: launch_pass<LOGS, (LOGS == 8 ? 4 : 3), (LOGS == 8 ? 32 : 8), COLPASS, INV>(T, b, s, f); return;
+        case 3: launch_pass<LOGS, 3, 8, COLPASS, INV>(T, b, s, f); return;
         default: launch_pass<LOGS, 4, 16, COLPASS, INV>(T, b, s, f); return;
         }
     } else if constexpr (LOGS == 7) {

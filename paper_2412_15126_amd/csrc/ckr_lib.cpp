@@ -2357,10 +2357,16 @@ ckr_status ckr_autotune(ckr_context *ctx, uint32_t limbs, uint32_t iters, float 
                 float best = 1e30f;
                 int bestv = 0;
                 for (int v = 0; v < kNttVariants; v++) {
+                    // one launch over whole polynomials of nq limbs (the shape the circuits
+                    // issue), then the remainder
                     auto launch = [&] {
-                        for (u32 off = 0; off < limbs; off += (u32)nq) {
-                            const int cnt = (int)std::min<u32>((u32)nq, limbs - off);
-                            LimbBatch b{buf.get() + (size_t)off * n, cnt, 1, 0, plain_map()};
+                        const u32 full = limbs / (u32)nq, rest = limbs - full * (u32)nq;
+                        if (full) {
+                            LimbBatch b{buf.get(), nq, (int)full, (size_t)nq * n, plain_map()};
+                            k_ntt_pass_variant(C.T, b, inv != 0, pass, v, C.stream);
+                        }
+                        if (rest) {
+                            LimbBatch b{buf.get() + (size_t)full * nq * n, (int)rest, 1, 0, plain_map()};
                             k_ntt_pass_variant(C.T, b, inv != 0, pass, v, C.stream);
                         }
                     };
