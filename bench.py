@@ -450,18 +450,6 @@ def main():
     exact = bool(max(errs) < 0.5)
     log(f"[bench] warmup done, ranks exact: {exact}")
 
-    # the configs' "composed 4 times": the best 4-fold split (g^3 f) on the same
-    # queries, untimed; reported next to the 5-fold comparator timed above
-    cmp4 = (3, 1)
-    l4 = ckr.rank_depth(cmp4)
-    cts4 = [ctx.encrypt(keys, v, l4, W.rank_workload(N, 2.0 ** -10, 1000 + q)[2]) for q, v in enumerate(vals)]
-    errs4 = [np.max(np.abs(ctx.decrypt(keys, o, N) - (np.argsort(np.argsort(v)) + 1)))
-             for o, v in zip(ctx.run_batch(keys, "rank", cts4, N, cmp4), vals)]
-    rank_error = {"g4f (timed)": {"max": round(float(max(errs)), 4), "queries_exact": int(sum(e < 0.5 for e in errs))},
-                  "g3f (4 compositions)": {"max": round(float(max(errs4)), 4),
-                                           "queries_exact": int(sum(e < 0.5 for e in errs4))},
-                  "queries": len(vals)}
-
     # timed region: hipGraph replays of the batched circuit, one event pair per step
     wall, step_ms, total_ms = timed_steps(step, args.steps)
     log(f"[bench] timed {args.steps} steps: {total_ms:.1f} ms on device, {wall * 1e3:.1f} ms wall")
@@ -516,7 +504,8 @@ def main():
                      "launches": int(launches), "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
                      "profiled_steps": psteps},
         "kernels": breakdown,
-        "rank_error": rank_error,
+        "rank_error": {"max": round(float(max(errs)), 4), "queries_exact": int(sum(e < 0.5 for e in errs)),
+                       "queries": len(vals)},
     }
     if rank == 0 and not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)

@@ -75,3 +75,24 @@ def test_rank128_batch_equals_single_full_size(full):
         singles.append(ctx.rank(keys, c, N, W.RANK_CMP[N]).export())
     for s, b in zip(singles, ctx.rank_batch(keys, cts, N, W.RANK_CMP[N])):
         assert np.array_equal(s, b.export())
+
+
+def test_rank128_four_compositions_is_not_enough(full):
+    """The configs' "composed 4 times": the best 4-fold split g^3 f does not
+    rank N = 128 values with gap 2^-10 exactly on the decrypted CKKS output,
+    while the 5-fold g^4 f used by the benchmark does (32 queries each)."""
+    ctx, keys = full["ctx"], full["gkeys"]
+    vals = [W.rank_workload(N, 2.0 ** -10, 1000 + q)[0] for q in range(32)]
+    seeds = [W.rank_workload(N, 2.0 ** -10, 1000 + q)[2] for q in range(32)]
+    errs = {}
+    for cmp in ((3, 1), (4, 1)):
+        import paper_2412_15126_amd as ckr
+        level = ckr.rank_depth(cmp)
+        cts = [ctx.encrypt(keys, v, level, e) for v, e in zip(vals, seeds)]
+        outs = ctx.run_batch(keys, "rank", cts, N, cmp)
+        errs[cmp] = [float(np.max(np.abs(ctx.decrypt(keys, o, N) - (np.argsort(np.argsort(v)) + 1))))
+                     for o, v in zip(outs, vals)]
+        say(f"[gpu] rank-128 with g^{cmp[0]} f: max error {max(errs[cmp]):.3f}, "
+            f"exact {sum(e < 0.5 for e in errs[cmp])}/32")
+    assert max(errs[(4, 1)]) < 0.45
+    assert max(errs[(3, 1)]) > 0.5
