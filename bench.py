@@ -29,6 +29,35 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC = os.path.join(ROOT, "profiles", "rank128_n16_b32_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2412_15126_amd", "csrc", f) for f in ("ckr_kernels.hip", "internal.h")]
+
+
+def measured_traffic(category):
+    """HBM bytes per launch of `category` from the committed rocprofv3 counter
+    runs of this workload, or None once the kernel sources differ from the
+    ones those counters were taken on."""
+    import hashlib
+    if not os.path.exists(TRAFFIC):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    rows = {}
+    src = None
+    for line in open(TRAFFIC):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        if f[0] == "sources":
+            src = f[1]
+        else:
+            rows[f[0]] = dict(launches=int(f[1]), algorithmic=int(f[2]), read=int(f[3]), write=int(f[4]))
+    if src != h.hexdigest() or category not in rows:
+        return None
+    return rows[category]
+
+
 def cpu_baseline(pset, N, cmp, level, threads):
     """The oracle, as it stands, timed on this host: one rank-128 query."""
     from oracle import oracle as O
@@ -502,11 +531,16 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
                      "launches": int(launches), "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
+                     "algorithmic_bytes_per_launch": int(nbytes / max(launches, 1)),
                      "profiled_steps": psteps},
         "kernels": breakdown,
         "rank_error": {"max": round(float(max(errs)), 4), "queries_exact": int(sum(e < 0.5 for e in errs)),
                        "queries": len(vals)},
     }
+    tr = measured_traffic(dom) if B == 32 else None
+    if tr:
+        res["roofline"]["traffic"] = tr["read"] + tr["write"]
+        res["roofline"]["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     if rank == 0 and not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log(f"[bench] cpu baseline with {threads} threads")
