@@ -1134,6 +1134,64 @@ int ora_rank_multi(const ora_keys *Kp, ora_ct *const *Bk, u32 L, u32 b, int dg, 
     return st;
 }
 
+/* Multi-Ciphertext Sorting (section 5, Algorithm Multi-Ciphertext Sorting):
+ * R_1..R_L = multi-ciphertext ranks of the blocks; for output block i and
+ * source block j, M_{i,j} = Ind_0(ReplR(R_j) - (b(i-1)+1 || ... || b i)) with
+ * Ind_0(x) = Cmp(x, -1/2) (1 - Cmp(x, 1/2)) on (x +- 1/2)/N (N = L b);
+ * S_i = TransC(SumC(sum_j M_{i,j} * ReplR(B_j))).  Distinct inputs. */
+int ora_sort_multi_depth(int cdg, int cdf, int idg, int idf) {
+    /* multi rank, scaling, indicator, indicator product, M * V_R, SumC mask, TransC mask */
+    return ora_rank_multi_depth(cdg, cdf) + 5 + 3 * (idg + idf);
+}
+
+int ora_sort_multi(const ora_keys *Kp, ora_ct *const *Bk, u32 L, u32 b, int cdg, int cdf, int idg, int idf,
+                   ora_ct **S) {
+    int st = check_N(Kp->P, b);
+    if (st != ORA_OK) return st;
+    if (L < 1) return ORA_E_INVALID;
+    for (u32 i = 0; i < L; i++)
+        if (Bk[i]->level != Bk[0]->level) return ORA_E_INVALID;
+    if (Bk[0]->level < ora_sort_multi_depth(cdg, cdf, idg, idf)) return ORA_E_DEPTH;
+    const double dN = (double)L * (double)b;
+    ora_ct **R = (ora_ct **)calloc(L, sizeof(ora_ct *));
+    st = ora_rank_multi(Kp, Bk, L, b, cdg, cdf, R);
+    ora_ct **RR = (ora_ct **)calloc(L, sizeof(ora_ct *)), **VR = (ora_ct **)calloc(L, sizeof(ora_ct *));
+    for (u32 j = 0; j < L; j++) {
+        RR[j] = ora_repl_r(Kp, R[j], b, &st);
+        VR[j] = ora_repl_r(Kp, Bk[j], b, &st);
+    }
+    double *steps = (double *)calloc((size_t)b * b, sizeof(double));
+    for (u32 i = 0; i < L; i++) {
+        for (u32 r = 0; r < b; r++)
+            for (u32 c = 0; c < b; c++) steps[r * b + c] = -((double)b * i + r + 1);
+        ora_ct *acc = NULL;
+        for (u32 j = 0; j < L; j++) {
+            ora_ct *X = ora_add_plain(RR[j], steps, b * b, &st);
+            ora_ct *Xs = ora_cmul_to(X, 1.0 / dN, X->level - 1, &st);
+            ora_ct *d1 = ora_add_const(Xs, 0.5 / dN);
+            ora_ct *d2 = ora_add_const(Xs, -0.5 / dN);
+            ora_ct *c1 = ora_cmp_sign(Kp, d1, idg, idf, &st);
+            ora_ct *c2 = ora_cmp_sign(Kp, d2, idg, idf, &st);
+            ora_ct *n2 = mul_int(c2, -1);
+            ora_ct *o2 = ora_add_const(n2, 1.0);
+            ora_ct *M = ora_mul(Kp, c1, o2, &st);
+            ora_ct *VRa = ora_cmul_to(VR[j], 1.0, M->level, &st);
+            ora_ct *P = ora_mul(Kp, M, VRa, &st);
+            if (acc) replace(&acc, ora_add(acc, P)), ora_ct_free(P);
+            else acc = P;
+            ora_ct_free(X); ora_ct_free(Xs); ora_ct_free(d1); ora_ct_free(d2); ora_ct_free(c1); ora_ct_free(c2);
+            ora_ct_free(n2); ora_ct_free(o2); ora_ct_free(M); ora_ct_free(VRa);
+        }
+        ora_ct *SC = ora_sum_c(Kp, acc, b, &st);
+        S[i] = ora_trans_c(Kp, SC, b, &st);
+        ora_ct_free(acc); ora_ct_free(SC);
+    }
+    free(steps);
+    for (u32 j = 0; j < L; j++) { ora_ct_free(R[j]); ora_ct_free(RR[j]); ora_ct_free(VR[j]); }
+    free(R); free(RR); free(VR);
+    return st;
+}
+
 /* Galois elements needed by rank on N elements (left shifts as powers of 5) */
 int ora_rank_galois(const ora_params *P, u32 N, u32 *out) {
     int cnt = 0, lg = ilog2(N);

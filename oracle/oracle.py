@@ -100,6 +100,8 @@ def lib():
                                      C.POINTER(vp)]),
             "ora_rank_multi_depth": (C.c_int, [C.c_int, C.c_int]),
             "ora_rank_multi": (C.c_int, [vp, C.POINTER(vp), C.c_uint32, C.c_uint32, C.c_int, C.c_int, C.POINTER(vp)]),
+            "ora_sort_multi_depth": (C.c_int, [C.c_int] * 4),
+            "ora_sort_multi": (C.c_int, [vp, C.POINTER(vp), C.c_uint32, C.c_uint32] + [C.c_int] * 4 + [C.POINTER(vp)]),
             "ora_rank_tie": (vp, [vp, vp, C.c_uint32, C.c_int, C.c_int, intp]),
             "ora_order_stat_depth": (C.c_int, [C.c_uint32, C.c_uint32] + [C.c_int] * 5),
             "ora_order_stat": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32] + [C.c_int] * 5 + [C.POINTER(vp), C.POINTER(vp)]),
@@ -362,6 +364,22 @@ def rank_multi(keys, blocks, b, dg, df):
     st = lib().ora_rank_multi(keys.ptr, arr, L, b, dg, df, out)
     if st != 0:
         raise OracleError(f"rank_multi: status {STATUS.get(st, st)}")
+    return [Ct(out[i], blocks[0].params) for i in range(L)]
+
+
+def sort_multi_depth(cmp, ind):
+    return lib().ora_sort_multi_depth(cmp[0], cmp[1], ind[0], ind[1])
+
+
+def sort_multi(keys, blocks, b, cmp, ind):
+    """Multi-ciphertext sorting of len(blocks) blocks of b distinct values; returns the L sorted blocks."""
+    keys.need(b, 4)
+    L = len(blocks)
+    arr = (C.c_void_p * L)(*[x.ptr for x in blocks])
+    out = (C.c_void_p * L)()
+    st = lib().ora_sort_multi(keys.ptr, arr, L, b, cmp[0], cmp[1], ind[0], ind[1], out)
+    if st != 0:
+        raise OracleError(f"sort_multi: status {STATUS.get(st, st)}")
     return [Ct(out[i], blocks[0].params) for i in range(L)]
 
 

@@ -256,6 +256,29 @@ def rank_multi_circuit(v, b, slots, cmp):
     return out
 
 
+def sort_multi_circuit(v, b, slots, cmp, ind):
+    """Multi-Ciphertext Sorting (section 5): M_{i,j} = Ind_0(ReplR(R_j) - steps_i)
+    on (x +- 1/2)/N, S_i = TransC(SumC(sum_j M_{i,j} ReplR(B_j))).  Returns [S_1..S_L]."""
+    N = len(v)
+    L = N // b
+    R = rank_multi_circuit(v, b, slots, cmp)
+    RR = [repl_r(r, b) for r in R]
+    VR = [repl_r(embed(v[j * b:(j + 1) * b], slots), b) for j in range(L)]
+    out = []
+    for i in range(L):
+        steps = np.zeros(slots)
+        for r in range(b):
+            steps[r * b:(r + 1) * b] = b * i + r + 1
+        acc = 0.0
+        for j in range(L):
+            X = (RR[j] - steps) / N
+            c1 = (sign_composite(X + 0.5 / N, *ind) + 1.0) / 2.0
+            c2 = (sign_composite(X - 0.5 / N, *ind) + 1.0) / 2.0
+            acc = acc + c1 * (1.0 - c2) * VR[j]
+        out.append(trans_c(sum_c(acc, b), b))
+    return out
+
+
 def sort_circuit(v, N, slots, cmp, ind):
     """Algorithm Sorting with Ind_0(x) = Cmp(x, -1/2) (1 - Cmp(x, 1/2)) on x/N."""
     x = embed(v, slots)

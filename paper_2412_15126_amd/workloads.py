@@ -33,9 +33,12 @@ PSETS = {
     # tie-corrected order statistics for any k on N <= 128 at n = 2^17
     # (44 levels, log QP ~ 2360 bits)
     "P17O": dict(logn=17, L=44, q0_bits=50, log_scale=40, K=11, p_bits=50, dnum=4),
+    # multi-ciphertext sort of N = 512 in blocks of 256 at n = 2^17 (47 levels, log QP ~ 2480 bits)
+    "P17S": dict(logn=17, L=47, q0_bits=50, log_scale=40, K=12, p_bits=50, dnum=4),
     # small rings used by the unit and parity tests
     "T12D": dict(logn=12, L=34, q0_bits=44, log_scale=36, K=9, p_bits=40, dnum=4),
     "T10": dict(logn=10, L=7, q0_bits=44, log_scale=36, K=3, p_bits=46, dnum=3),
+    "T12E": dict(logn=12, L=46, q0_bits=44, log_scale=36, K=12, p_bits=40, dnum=4),
     "T13": dict(logn=13, L=11, q0_bits=44, log_scale=36, K=4, p_bits=40, dnum=3),
 }
 
@@ -52,6 +55,8 @@ ORDER_CMP = {8: ((3, 1), (2, 2)), 16: ((4, 1), (3, 2)), 32: ((4, 1), (3, 2)), 64
 ORDER_TIE_CMP = {8: ((3, 1), (2, 2)), 128: ((4, 2), (4, 2))}
 # multi-ciphertext rank (blocks of b values, N = L b): comparator per total N
 MULTI_RANK_CMP = {64: (4, 1), 128: (4, 1), 256: (4, 2), 512: (4, 2), 1024: (4, 2)}
+# multi-ciphertext sort: (comparator, two-sided indicator) per total N
+MULTI_SORT_CMP = {64: ((4, 2), (4, 2)), 128: ((4, 2), (4, 2)), 512: ((4, 2), (5, 2))}
 # sort: (comparator, two-sided indicator)
 SORT_CMP = {8: ((3, 1), (3, 2)), 16: ((4, 1), (3, 2)), 32: ((4, 1), (3, 2)), 64: ((4, 1), (4, 2)),
             128: ((4, 1), (4, 2))}

@@ -148,9 +148,31 @@ def rank512_p16_multi():
             "exact": [int(x) for x in np.argsort(np.argsort(v)) + 1]}
 
 
+def sort512_p17s_multi():
+    """multi-ciphertext sorting of N = 512 values in 2 blocks of 256 at n = 2^17"""
+    N, b = 512, 256
+    cmp, ind = W.MULTI_SORT_CMP[N]
+    O.set_threads(min(16, os.cpu_count() or 1))
+    P = O.Params(**W.PSETS["P17S"])
+    level = O.sort_multi_depth(cmp, ind)
+    v, kseed, eseed = W.rank_workload(N, 2.0 ** -10, 0)
+    K = O.Keys(P, kseed, level, P.circuit_galois(b, 4))
+    blocks = [O.encrypt(K, v[i * b:(i + 1) * b], level, bytes([i]) + eseed[1:]) for i in range(N // b)]
+    out = O.sort_multi(K, blocks, b, cmp, ind)
+    dec = np.concatenate([O.decrypt(K, o, b) for o in out])
+    return {"_what": "oracle multi-ciphertext sorting (section 5) of N=512 values (workload seed 0, gap 2^-10) in 2 "
+                     "blocks of 256 at n=2^17 (P17S), blocks encrypted at level 47 with seeds (i, eseed[1:]), "
+                     "comparator g^4 f^2, indicator g^5 f^2: sha256 of each exported sorted block and the decoded "
+                     "values",
+            "level": level,
+            "sha256": [hashlib.sha256(o.export().tobytes()).hexdigest() for o in out],
+            "decoded": [float(x) for x in dec],
+            "sorted": [float(x) for x in np.sort(v)]}
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["rank128_p16", "argmin128_p17", "sort128_p17", "mixed_p16d", "argmax128_p17o",
-                             "rank512_p16_multi"]
+                             "rank512_p16_multi", "sort512_p17s_multi"]
     for name in which:
         json.dump(globals()[name](), open(os.path.join(HERE, name + ".json"), "w"), indent=1)
         print("wrote", name + ".json", flush=True)

@@ -358,3 +358,30 @@ def test_oracle_refuses_circuit_without_its_rotation_keys(ora, t12d):
     ct = ora.encrypt(keys, np.linspace(0, 1, 32), P.L, bytes([3] * 32))
     with pytest.raises(ora.OracleError):
         ora.rank(keys, ct, 32, 3, 1)
+
+
+@pytest.mark.parametrize("N,b", [(64, 32), (128, 32)])
+def test_shadow_multi_ciphertext_sort(N, b):
+    """Multi-ciphertext sorting (section 5) returns the sorted vector block by block."""
+    cmp, ind = W.MULTI_SORT_CMP[N]
+    for seed in range(3):
+        v, _, _ = W.rank_workload(N, 0.01 if N == 64 else 2.0 ** -10, 900 + seed)
+        got = np.concatenate([s[:b] for s in S.sort_multi_circuit(v, b, 2 * b * b, cmp, ind)])
+        assert np.max(np.abs(got - np.sort(v))) < 1e-4
+
+
+def test_oracle_multi_ciphertext_sort_matches_shadow(ora):
+    ps = W.PSETS["T12E"]
+    P = ora.Params(**ps)
+    N, b = 64, 32
+    cmp, ind = W.MULTI_SORT_CMP[N]
+    level = ora.sort_multi_depth(cmp, ind)
+    keys = ora.Keys(P, bytes(range(4, 36)), level, P.circuit_galois(b, 4))
+    v, _, eseed = W.rank_workload(N, 0.01, 950)
+    blocks = [ora.encrypt(keys, v[i * b:(i + 1) * b], level, bytes([i]) + eseed[1:]) for i in range(N // b)]
+    out = ora.sort_multi(keys, blocks, b, cmp, ind)
+    assert all(o.level == 0 for o in out)
+    got = np.concatenate([ora.decrypt(keys, o, b) for o in out])
+    sh = np.concatenate([s[:b] for s in S.sort_multi_circuit(v, b, P.n // 2, cmp, ind)])
+    assert np.max(np.abs(got - sh)) < 1e-3
+    assert np.max(np.abs(got - np.sort(v))) < 1e-3
