@@ -185,6 +185,17 @@ ckr_status ckr_rank_multi(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *
                           ckr_sign cmp, ckr_ct **out);
 uint32_t ckr_rank_multi_depth(ckr_sign cmp);
 
+/* Multi-ciphertext sorting (section 5, Algorithm Multi-Ciphertext Sorting) of
+ * L blocks of b distinct values laid out as for ckr_rank_multi.  out (L
+ * entries, caller-owned) receives in out[i] the i-th block of the sorted vector
+ * (the values of ranks i*b+1 .. (i+1)*b) in slots [0,b), at level(blocks) -
+ * ckr_sort_multi_depth.  All L^2 indicators Ind_0(ReplR(R_j) - ranks of block
+ * i) run in one batched comparator pass.  Keys: the sort set for N = b.
+ * Errors: as ckr_rank_multi. */
+ckr_status ckr_sort_multi(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *const *blocks, uint32_t L, uint32_t b,
+                          ckr_sign cmp, ckr_sign ind, ckr_ct **out);
+uint32_t ckr_sort_multi_depth(ckr_sign cmp, ckr_sign ind);
+
 /* One query of a mixed batch.  kind: 1 rank (tie_correct selects the
  * tie-corrected rank), 2 argmin (the tie-corrected minimum; k and tie_correct
  * ignored), 3 sort, 4 order statistic k.  v: a single ciphertext, borrowed. */

@@ -71,6 +71,8 @@ _SIGS = {
     "ckr_run_mixed": (C.c_int, [vp, vp, C.POINTER(Query), C.c_size_t, C.POINTER(vp)]),
     "ckr_rank_multi": (C.c_int, [vp, vp, C.POINTER(vp), C.c_uint32, C.c_uint32, Sign, C.POINTER(vp)]),
     "ckr_rank_multi_depth": (C.c_uint32, [Sign]),
+    "ckr_sort_multi": (C.c_int, [vp, vp, C.POINTER(vp), C.c_uint32, C.c_uint32, Sign, Sign, C.POINTER(vp)]),
+    "ckr_sort_multi_depth": (C.c_uint32, [Sign, Sign]),
     "ckr_sort_depth": (C.c_uint32, [Sign, Sign]),
     "ckr_argmin": (C.c_int, [vp, vp, vp, C.c_uint32, Sign, Sign, C.POINTER(vp), C.POINTER(vp)]),
     "ckr_sort": (C.c_int, [vp, vp, vp, C.c_uint32, Sign, Sign, C.POINTER(vp)]),
@@ -170,6 +172,10 @@ def rank_multi_depth(cmp):
     return int(lib().ckr_rank_multi_depth(sign(cmp)))
 
 
+def sort_multi_depth(cmp, ind):
+    return int(lib().ckr_sort_multi_depth(sign(cmp), sign(ind)))
+
+
 def order_stat_depth(N, k, cmp, ind, tie):
     return int(lib().ckr_order_stat_depth(N, k, sign(cmp), sign(ind), int(tie)))
 
@@ -247,6 +253,13 @@ class Context:
         arr = (vp * len(blocks))(*[x.h for x in blocks])
         out = (vp * len(blocks))()
         _ok(lib().ckr_rank_multi(self.h, keys.h, arr, len(blocks), b, sign(cmp), out))
+        return [Ct(self, vp(o)) for o in out]
+
+    def sort_multi(self, keys, blocks, b, cmp, ind):
+        """Multi-ciphertext sorting: blocks of b distinct values -> the sorted vector, block by block."""
+        arr = (vp * len(blocks))(*[x.h for x in blocks])
+        out = (vp * len(blocks))()
+        _ok(lib().ckr_sort_multi(self.h, keys.h, arr, len(blocks), b, sign(cmp), sign(ind), out))
         return [Ct(self, vp(o)) for o in out]
 
     def order_stat(self, keys, ct, N, k, cmp, ind, tie):

@@ -190,8 +190,10 @@ struct DCt {
 };
 
 struct PlainKey {
-    int kind, N, level;
-    bool operator<(const PlainKey &o) const { return std::tie(kind, N, level) < std::tie(o.kind, o.N, o.level); }
+    int kind, N, level, arg;
+    bool operator<(const PlainKey &o) const {
+        return std::tie(kind, N, level, arg) < std::tie(o.kind, o.N, o.level, o.arg);
+    }
 };
 
 enum ProfCat {
@@ -826,7 +828,8 @@ static DCt ev_rotate_add(Ctx &C, const Keys &K, const DCt &a, i64 k) {
 }
 
 // plaintext holding z on slots [0, count) at scale D_level, eval domain [level+1][n]
-enum PlainKind { kMaskRow0 = 1, kMaskCol0 = 2, kHalfRow0 = 3, kTieMask = 4, kSteps = 5, kNegHalfRow0 = 6 };
+enum PlainKind { kMaskRow0 = 1, kMaskCol0 = 2, kHalfRow0 = 3, kTieMask = 4, kSteps = 5, kNegHalfRow0 = 6,
+                 kStepsBlock = 7 };
 
 static Buf encode_plain(Ctx &C, const std::vector<double> &z, int level) {
     const size_t n = C.n();
@@ -843,7 +846,7 @@ static Buf encode_plain(Ctx &C, const std::vector<double> &z, int level) {
     return b;
 }
 
-static std::vector<double> plain_values(int kind, int N) {
+static std::vector<double> plain_values(int kind, int N, int arg) {
     std::vector<double> z((size_t)N * N, 0.0);
     switch (kind) {
     case kMaskRow0: for (int j = 0; j < N; j++) z[j] = 1.0; break;
@@ -858,19 +861,23 @@ static std::vector<double> plain_values(int kind, int N) {
         for (int i = 0; i < N; i++)
             for (int j = 0; j < N; j++) z[(size_t)i * N + j] = -(double)(i + 1);
         break;
+    case kStepsBlock:  // -((N arg + 1)^N || ... || (N arg + N)^N): the ranks of output block arg
+        for (int i = 0; i < N; i++)
+            for (int j = 0; j < N; j++) z[(size_t)i * N + j] = -((double)N * arg + i + 1);
+        break;
     default: throw Error{CKR_E_INVALID, "plaintext kind"};
     }
     return z;
 }
 
-static const Buf &get_plain(Ctx &C, int kind, int N, int level) {
-    PlainKey key{kind, N, level};
+static const Buf &get_plain(Ctx &C, int kind, int N, int level, int arg = 0) {
+    PlainKey key{kind, N, level, arg};
     {
         std::lock_guard<std::mutex> g(C.mu);
         auto it = C.plain.find(key);
         if (it != C.plain.end()) return it->second;
     }
-    Buf b = encode_plain(C, plain_values(kind, N), level);
+    Buf b = encode_plain(C, plain_values(kind, N, arg), level);
     std::lock_guard<std::mutex> g(C.mu);
     return C.plain.emplace(key, std::move(b)).first->second;
 }
@@ -1084,6 +1091,46 @@ static DCt rank_multi(Ctx &C, const Keys &K, const DCt &Bk, int b, ckr_sign cmp)
         R = stack(C, {&head, &tail});
     }
     return ev_add_plain(C, R, get_plain(C, kHalfRow0, b, R.level));
+}
+
+// Multi-Ciphertext Sorting (section 5): R = multi-ciphertext ranks; for output
+// block i and source block j, M_{i,j} = Ind_0(ReplR(R_j) - (b(i-1)+1 || ... || b i))
+// with Ind_0(x) = Cmp(x, -1/2) (1 - Cmp(x, 1/2)) on (x +- 1/2)/N, all L^2
+// indicators in one batched comparator pass; S_i = TransC(SumC(sum_j M_{i,j} ReplR(B_j))).
+uint32_t sort_multi_depth(ckr_sign c, ckr_sign i) { return rank_multi_depth(c) + 5 + 3 * (i.d_g + i.d_f); }
+
+static DCt sort_multi(Ctx &C, const Keys &K, const DCt &Bk, int b, ckr_sign cmp, ckr_sign ind) {
+    check_N(C, (u32)b);
+    const int L = Bk.B;
+    if (L < 1) throw Error{CKR_E_INVALID, "no blocks"};
+    if ((u32)Bk.level < sort_multi_depth(cmp, ind)) throw Error{CKR_E_DEPTH, "not enough levels for the sort"};
+    const double dN = (double)L * (double)b;
+    DCt R = rank_multi(C, K, Bk, b, cmp);
+    DCt RR = repl_r(C, K, R, b);
+    DCt VR = repl_r(C, K, Bk, b);
+    std::vector<DCt> Xi;  // entry i*L + j: ReplR(R_j) - steps of output block i
+    for (int i = 0; i < L; i++) Xi.push_back(ev_add_plain(C, RR, get_plain(C, kStepsBlock, b, RR.level, i)));
+    std::vector<const DCt *> xp;
+    for (const DCt &x : Xi) xp.push_back(&x);
+    DCt Xs = ev_cmul_to(C, stack(C, xp), 1.0 / dN, RR.level - 1);
+    DCt d1 = ev_add_const(C, Xs, 0.5 / dN), d2 = ev_add_const(C, Xs, -0.5 / dN);
+    const int P = L * L;
+    DCt cc = cmp_sign(C, K, stack(C, {&d1, &d2}), ind);
+    DCt c1 = slice(C, cc, 0, P), c2 = slice(C, cc, P, P);
+    DCt M = ev_mul(C, K, c1, ev_add_const(C, ev_mul_int(C, c2, -1), 1.0));
+    std::vector<int> jj;
+    for (int i = 0; i < L; i++)
+        for (int j = 0; j < L; j++) jj.push_back(j);
+    DCt Pm = ev_mul(C, K, M, ev_cmul_to(C, gather(C, VR, jj), 1.0, M.level));
+    std::vector<DCt> Si;
+    for (int i = 0; i < L; i++) {
+        DCt acc = slice(C, Pm, i * L, 1);
+        for (int j = 1; j < L; j++) acc = ev_add(C, acc, slice(C, Pm, i * L + j, 1), false);
+        Si.push_back(std::move(acc));
+    }
+    std::vector<const DCt *> sp;
+    for (const DCt &x : Si) sp.push_back(&x);
+    return trans_c(C, K, sum_c(C, K, stack(C, sp), b), b);
 }
 
 // Order statistic k (Algorithm Order Statistic), optionally with the
@@ -2022,6 +2069,7 @@ ckr_status ckr_ct_import(ckr_context *ctx, const uint64_t *data, size_t words, u
 uint32_t ckr_rank_depth(ckr_sign cmp, int tie) { return rank_depth(cmp, tie); }
 uint32_t ckr_argmin_depth(ckr_sign cmp, ckr_sign ind) { return argmin_depth(cmp, ind); }
 uint32_t ckr_rank_multi_depth(ckr_sign cmp) { return rank_multi_depth(cmp); }
+uint32_t ckr_sort_multi_depth(ckr_sign cmp, ckr_sign ind) { return sort_multi_depth(cmp, ind); }
 uint32_t ckr_order_stat_depth(uint32_t N, uint32_t k, ckr_sign cmp, ckr_sign ind, int tie_correct) {
     return order_stat_depth((int)N, (int)k, cmp, ind, tie_correct != 0);
 }
@@ -2179,6 +2227,26 @@ ckr_status ckr_rank_multi(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *
         DCt R = rank_multi(C, *keys->K, stack(C, in), (int)b, cmp);
         std::vector<ckr_ct *> made;
         for (u32 i = 0; i < L; i++) made.push_back(wrap(C, slice(C, R, (int)i, 1)));
+        for (u32 i = 0; i < L; i++) out[i] = made[i];
+    });
+}
+
+ckr_status ckr_sort_multi(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *const *blocks, uint32_t L, uint32_t b,
+                          ckr_sign cmp, ckr_sign ind, ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && keys && blocks && out && L);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
+        Ctx &C = *ctx->C;
+        std::vector<const DCt *> in;
+        for (u32 i = 0; i < L; i++) {
+            NEED(blocks[i]);
+            if (blocks[i]->ct.B != 1 || blocks[i]->ct.level != blocks[0]->ct.level)
+                throw Error{CKR_E_INVALID, "blocks must be single ciphertexts of one level"};
+            in.push_back(&blocks[i]->ct);
+        }
+        DCt S = sort_multi(C, *keys->K, stack(C, in), (int)b, cmp, ind);
+        std::vector<ckr_ct *> made;
+        for (u32 i = 0; i < L; i++) made.push_back(wrap(C, slice(C, S, (int)i, 1)));
         for (u32 i = 0; i < L; i++) out[i] = made[i];
     });
 }

@@ -335,3 +335,30 @@ def test_multi_ciphertext_rank512_full_size_matches_golden():
     assert [hashlib.sha256(r.export().tobytes()).hexdigest() for r in R] == gold["sha256"]
     got = np.concatenate([ctx.decrypt(keys, r, b) for r in R])
     assert np.array_equal(np.round(got), np.argsort(np.argsort(v)) + 1)
+
+
+def test_multi_ciphertext_sort_bit_exact(ora):
+    """Multi-ciphertext sorting (section 5) of 64 values in 2 blocks of 32 at
+    n = 2^12 against the oracle, block for block."""
+    import paper_2412_15126_amd as ckr
+    ps = W.PSETS["T12E"]
+    P = ora.Params(**ps)
+    N, b = 64, 32
+    cmp, ind = W.MULTI_SORT_CMP[N]
+    level = ora.sort_multi_depth(cmp, ind)
+    seed = bytes(range(4, 36))
+    okeys = ora.Keys(P, seed, level, P.circuit_galois(b, 4))
+    ctx = ckr.Context(ps)
+    gkeys = ctx.keygen(seed, level, [b], what=4)
+    assert ckr.sort_multi_depth(cmp, ind) == level
+    v, _, eseed = W.rank_workload(N, 0.01, 950)
+    say("[gpu] multi-ciphertext sort of 64")
+    ob = [ora.encrypt(okeys, v[i * b:(i + 1) * b], level, bytes([i]) + eseed[1:]) for i in range(N // b)]
+    gb = [ctx.encrypt(gkeys, v[i * b:(i + 1) * b], level, bytes([i]) + eseed[1:]) for i in range(N // b)]
+    So = ora.sort_multi(okeys, ob, b, cmp, ind)
+    Sg = ctx.sort_multi(gkeys, gb, b, cmp, ind)
+    for o, g in zip(So, Sg):
+        assert np.array_equal(o.export(), g.export())
+    got = np.concatenate([ctx.decrypt(gkeys, s, b) for s in Sg])
+    assert np.max(np.abs(got - np.sort(v))) < 1e-3
+
