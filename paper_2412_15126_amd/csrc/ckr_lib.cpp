@@ -994,6 +994,10 @@ static DCt cmp_sign(Ctx &C, const Keys &K, const DCt &D, ckr_sign cmp, double a 
 // Rank (Algorithm Rank), argmin (Order Statistic with k = 1 and the
 // tie-correction offset), Sorting
 // ------------------------------------------------------------------------
+static void check_sign(ckr_sign c) {
+    if (c.d_g + c.d_f < 1) throw Error{CKR_E_INVALID, "empty comparator composition"};
+}
+
 static void check_N(const Ctx &C, u32 N) {
     if (N < 2 || (N & (N - 1)) || (u64)N * N > C.n() / 2) throw Error{CKR_E_RANGE, "N must be a power of two with N^2 <= n/2"};
 }
@@ -1023,6 +1027,7 @@ static DCt cmp_matrix(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, 
 
 static DCt rank(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, DCt *VR_out = nullptr) {
     check_N(C, (u32)N);
+    check_sign(cmp);
     if ((u32)V.level < rank_depth(cmp, 0)) throw Error{CKR_E_DEPTH, "not enough levels for rank"};
     DCt Cm = cmp_matrix(C, K, V, N, cmp, VR_out);
     DCt S = sum_r(C, K, Cm, N);
@@ -1034,6 +1039,7 @@ static DCt rank(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, DCt *V
 // permutation of 1..N with equal values ranked in index order
 static DCt tie_rank(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp) {
     check_N(C, (u32)N);
+    check_sign(cmp);
     if ((u32)V.level < rank_depth(cmp, 1)) throw Error{CKR_E_DEPTH, "not enough levels for the tie-corrected rank"};
     DCt Cm = cmp_matrix(C, K, V, N, cmp);
     DCt w = ev_add_const(C, ev_mul_int(C, Cm, -4), 4.0);
@@ -1055,6 +1061,7 @@ constexpr int kPairChunk = 32;
 
 static DCt rank_multi(Ctx &C, const Keys &K, const DCt &Bk, int b, ckr_sign cmp) {
     check_N(C, (u32)b);
+    check_sign(cmp);
     const int L = Bk.B;
     if (L < 1) throw Error{CKR_E_INVALID, "no blocks"};
     if ((u32)Bk.level < rank_multi_depth(cmp)) throw Error{CKR_E_DEPTH, "not enough levels for the ranking"};
@@ -1101,6 +1108,8 @@ uint32_t sort_multi_depth(ckr_sign c, ckr_sign i) { return rank_multi_depth(c) +
 
 static DCt sort_multi(Ctx &C, const Keys &K, const DCt &Bk, int b, ckr_sign cmp, ckr_sign ind) {
     check_N(C, (u32)b);
+    check_sign(cmp);
+    check_sign(ind);
     const int L = Bk.B;
     if (L < 1) throw Error{CKR_E_INVALID, "no blocks"};
     if ((u32)Bk.level < sort_multi_depth(cmp, ind)) throw Error{CKR_E_DEPTH, "not enough levels for the sort"};
@@ -1147,6 +1156,8 @@ static DCt sort_multi(Ctx &C, const Keys &K, const DCt &Bk, int b, ckr_sign cmp,
 static void order_stat(Ctx &C, const Keys &K, const DCt &V, int N, int k, int tie, ckr_sign cmp, ckr_sign ind,
                        DCt &onehot, DCt &value) {
     check_N(C, (u32)N);
+    check_sign(cmp);
+    check_sign(ind);
     if (k < 1 || k > N) throw Error{CKR_E_INVALID, "k must lie in [1, N]"};
     if ((u32)V.level < order_stat_depth(N, k, cmp, ind, tie))
         throw Error{CKR_E_DEPTH, "not enough levels for the order statistic"};
@@ -1186,6 +1197,8 @@ static void order_stat(Ctx &C, const Keys &K, const DCt &V, int N, int k, int ti
 // Ind_0(x) = Cmp(x, -1/2) (1 - Cmp(x, 1/2)) on (x +- 1/2)/N; S = TransC(SumC(M * ReplR(V)))
 static DCt sort(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, ckr_sign ind) {
     check_N(C, (u32)N);
+    check_sign(cmp);
+    check_sign(ind);
     if ((u32)V.level < sort_depth(cmp, ind)) throw Error{CKR_E_DEPTH, "not enough levels for sort"};
     DCt VR;
     DCt R = rank(C, K, V, N, cmp, &VR);

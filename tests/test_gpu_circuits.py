@@ -362,3 +362,44 @@ def test_multi_ciphertext_sort_bit_exact(ora):
     got = np.concatenate([ctx.decrypt(gkeys, s, b) for s in Sg])
     assert np.max(np.abs(got - np.sort(v))) < 1e-3
 
+
+
+@pytest.mark.parametrize("N,cmp", [(2, (2, 1)), (32, (3, 1))])
+def test_rank_smallest_and_largest_N_bit_exact(ora, N, cmp):
+    """N = 2 (one rotation per re-encoding) and N = 32 (the largest power of two
+    whose N x N matrix fits the 2048 slots of n = 2^12) against the oracle."""
+    import paper_2412_15126_amd as ckr
+    ps = W.PSETS["T12D"]
+    P = ora.Params(**ps)
+    level = ora.rank_depth(*cmp)
+    seed = bytes(range(7, 39))
+    okeys = ora.Keys(P, seed, level, P.rank_galois(N))
+    ctx = ckr.Context(ps)
+    gkeys = ctx.keygen(seed, level, [N])
+    v, _, eseed = W.rank_workload(N, 0.01, 31 + N)
+    say(f"[gpu] rank of {N}")
+    ro = ora.rank(okeys, ora.encrypt(okeys, v, level, eseed), N, *cmp)
+    rg = ctx.rank(gkeys, ctx.encrypt(gkeys, v, level, eseed), N, cmp)
+    assert np.array_equal(ro.export(), rg.export())
+    assert np.array_equal(np.round(ctx.decrypt(gkeys, rg, N)), np.argsort(np.argsort(v)) + 1)
+
+
+def test_circuit_argument_errors(small):
+    """Range, argument and level errors come back as status codes, with no
+    output and no kernel launched on bad input."""
+    ckr, ctx, keys, P = small["ckr"], small["ctx"], small["gkeys"], small["P"]
+    g = ctx.encrypt(keys, np.linspace(0.1, 0.9, 8), P.L, bytes([9] * 32))
+    h = ctx.encrypt(keys, np.linspace(0.1, 0.9, 8), P.L - 1, bytes([9] * 32))
+    cases = [
+        (lambda: ctx.rank(keys, g, 64, (3, 1)), -2),                       # 64^2 > 2048 slots
+        (lambda: ctx.order_stat(keys, g, 8, 0, (3, 1), (2, 2), False), -1),  # k outside [1, N]
+        (lambda: ctx.order_stat(keys, g, 8, 9, (3, 1), (2, 2), False), -1),
+        (lambda: ctx.order_stat(keys, g, 8, 1, (0, 0), (2, 2), False), -1),  # empty comparator
+        (lambda: ctx.rank_multi(keys, [g, h], 8, (3, 1)), -1),             # blocks of two levels
+        (lambda: ctx.sort_multi(keys, [g, h], 8, (3, 1), (3, 2)), -1),
+        (lambda: ctx.run_mixed(keys, [dict(kind="order", N=8, k=12, cmp=(3, 1), ind=(2, 2), ct=g)]), -1),
+    ]
+    for i, (call, status) in enumerate(cases):
+        with pytest.raises(ckr.CkrError) as e:
+            call()
+        assert e.value.status == status, i
