@@ -33,7 +33,7 @@ PSETS = {
     # tie-corrected order statistics for any k on N <= 128 at n = 2^17
     # (44 levels, log QP ~ 2360 bits)
     "P17O": dict(logn=17, L=44, q0_bits=50, log_scale=40, K=11, p_bits=50, dnum=4),
-    # multi-ciphertext sort of N = 512 in blocks of 256 at n = 2^17 (47 levels, log QP ~ 2480 bits)
+    # multi-ciphertext sort of N = 512 in blocks of 256 at n = 2^17 (47 levels, log QP ~ 2530 bits)
     "P17S": dict(logn=17, L=47, q0_bits=50, log_scale=40, K=12, p_bits=50, dnum=4),
     # small rings used by the unit and parity tests
     "T12D": dict(logn=12, L=34, q0_bits=44, log_scale=36, K=9, p_bits=40, dnum=4),

@@ -403,3 +403,26 @@ def test_circuit_argument_errors(small):
         with pytest.raises(ckr.CkrError) as e:
             call()
         assert e.value.status == status, i
+
+
+
+
+def test_multi_ciphertext_sort512_full_size_matches_golden():
+    """N = 512 values in 2 blocks of 256 at n = 2^17 against oracle digests."""
+    import paper_2412_15126_amd as ckr
+    gold = json.load(open(os.path.join(GOLD, "sort512_p17s_multi.json")))
+    ps = W.PSETS["P17S"]
+    N, b = 512, 256
+    cmp, ind = W.MULTI_SORT_CMP[N]
+    level = ckr.sort_multi_depth(cmp, ind)
+    assert level == gold["level"]
+    v, kseed, eseed = W.rank_workload(N, 2.0 ** -10, 0)
+    ctx = ckr.Context(ps)
+    say("[gpu] P17S multi-ciphertext keys")
+    keys = ctx.keygen(kseed, level, [b], what=4)
+    blocks = [ctx.encrypt(keys, v[i * b:(i + 1) * b], level, bytes([i]) + eseed[1:]) for i in range(N // b)]
+    say("[gpu] P17S multi-ciphertext sort of 512")
+    S = ctx.sort_multi(keys, blocks, b, cmp, ind)
+    assert [hashlib.sha256(s.export().tobytes()).hexdigest() for s in S] == gold["sha256"]
+    got = np.concatenate([ctx.decrypt(keys, s, b) for s in S])
+    assert np.max(np.abs(got - np.sort(v))) < 1e-3
