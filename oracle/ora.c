@@ -57,6 +57,11 @@ typedef unsigned __int128 u128;
 #define ORA_E_RANGE (-2)
 #define ORA_E_DEPTH (-3)
 
+/* comparator: the f/g composite of section 2.2, g applied d_g times then f
+ * applied d_f times (cheb = 0), or the Chebyshev interpolant of Eq. (1) with
+ * cheb = D levels (d_g = d_f = 0) */
+typedef struct { int dg, df, cheb; } ora_cmp;
+
 /* ------------------------------------------------------------------ */
 /* modular arithmetic on canonical residues                            */
 /* ------------------------------------------------------------------ */
@@ -1008,16 +1013,172 @@ ora_ct *ora_poly7(const ora_keys *Kp, const ora_ct *x, const double a[4], int *s
     return p;
 }
 
-/* g applied d_g times then f applied d_f times, the last polynomial scaled by 1/2, then + 1/2 */
-/* a * Cmp = a * (f^{d_f}(g^{d_g}(D)) + 1) / 2, the factor a/2 folded into
- * the last polynomial and a/2 added as a constant */
-static ora_ct *cmp_sign_scaled(const ora_keys *Kp, const ora_ct *D, int dg, int df, double a, int *st) {
-    if (dg + df < 1) { *st = ORA_E_INVALID; return NULL; }
-    if (D->level < 3 * (dg + df)) { *st = ORA_E_DEPTH; return NULL; }
+/* ------------------------------------------------------------------ */
+/* Chebyshev comparator (section 2.2): Eq. (1) as a function of         */
+/* d = x - y, interpolated on [-1, 1] at the 2M = 2^(D-1) Chebyshev      */
+/* nodes (degree 2M - 1), evaluated with the Paterson-Stockmeyer         */
+/* algorithm in the Chebyshev basis in D levels.                          */
+/* ------------------------------------------------------------------ */
+/* Interpolation coefficients: c_k = (2/2M) sum_j f(x_j) T_k(x_j) over the
+ * nodes x_j = cos(pi (j + 1/2) / 2M), halved for k = 0.  f is 1 on the M
+ * positive nodes and 0 on the others, so the sum is a geometric cosine sum:
+ * c_0 = 1/2, c_k = 0 for even k > 0, and for odd k
+ *   c_k = (-1)^((k-1)/2) / (2M sin(pi k / 4M)).
+ * Evaluated in binary128 and rounded once to double. */
+void ora_cheb_step_coeffs(int D, double *c) {
+    const long M = 1L << (D - 2);
+    c[0] = 0.5;
+    for (long k = 1; k < 2 * M; k++) {
+        if ((k & 1) == 0) { c[k] = 0.0; continue; }
+        __float128 den = (__float128)(2 * M) * sinq(M_PIq * (__float128)k / (__float128)(4 * M));
+        __float128 v = (((k - 1) / 2) & 1 ? -1.0Q : 1.0Q) / den;
+        c[k] = (double)v;
+    }
+}
+
+/* x brought down to `level` (a copy when it is already there) */
+static ora_ct *align_to(const ora_ct *x, int level, int *st) {
+    return x->level == level ? ct_copy(x) : ora_cmul_to(x, 1.0, level, st);
+}
+
+/* 2 a b - s (s = NULL: the constant 1), a and b first brought to one level */
+static ora_ct *cheb_step(const ora_keys *Kp, const ora_ct *a, const ora_ct *b, const ora_ct *s, int *st) {
+    int lv = a->level < b->level ? a->level : b->level;
+    ora_ct *A = align_to(a, lv, st), *B = align_to(b, lv, st);
+    ora_ct *pr = ora_mul(Kp, A, B, st);
+    ora_ct *p2 = mul_int(pr, 2);
+    ora_ct *out;
+    if (s) {
+        ora_ct *S = align_to(s, p2->level, st);
+        out = ora_sub(p2, S);
+        ora_ct_free(S);
+    } else {
+        out = ora_add_const(p2, -1.0);
+    }
+    ora_ct_free(A); ora_ct_free(B); ora_ct_free(pr); ora_ct_free(p2);
+    return out;
+}
+
+typedef struct {
+    const ora_keys *Kp;
+    int k;           /* baby steps T_1 .. T_{k-1}, all at level lb */
+    int lb;
+    ora_ct **Tb;     /* [k] baby steps brought to level lb (index 0 unused) */
+    ora_ct **G;      /* giant steps G_r = T_{k 2^r} */
+} cheb_ctx;
+
+/* sum_{i<n} c_i T_i for n = k 2^r.  r = 0: a linear combination of the baby
+ * steps, sum_i round(c_i D_{lb-1} q_lb / D_lb) T_i over T_1 and every i with
+ * c_i != 0, one rescale, then + c_0.  r > 0: with K = k 2^(r-1), the
+ * division p = q T_K + s of the Chebyshev identity
+ * T_{K+j} = 2 T_j T_K - T_{K-j}:
+ *   q_0 = c_K, q_j = 2 c_{K+j};  s_0 = c_0, s_i = c_i - c_{2K-i}  (0 < i, j < K),
+ * then p = q(x) * G_{r-1} + s(x), each factor brought to the other's level. */
+static ora_ct *cheb_rec(const cheb_ctx *X, const double *c, int r, int *st) {
+    const ora_params *P = X->Kp->P;
+    if (r == 0) {
+        const int t = X->lb - 1;
+        ora_ct *acc = NULL;
+        for (int i = 1; i < X->k; i++) {
+            if (i > 1 && c[i] == 0.0) continue;
+            i64 K = llround(((c[i] * P->scale[t]) * (double)P->mod[t + 1]) / P->scale[X->lb]);
+            ora_ct *term = mul_int(X->Tb[i], K);
+            if (acc) { replace(&acc, ora_add(acc, term)); ora_ct_free(term); }
+            else acc = term;
+        }
+        ora_ct *res = ora_rescale(acc);
+        ora_ct_free(acc);
+        replace(&res, ora_add_const(res, c[0]));
+        return res;
+    }
+    const int K = X->k << (r - 1);
+    double *q = (double *)malloc(K * sizeof(double)), *s = (double *)malloc(K * sizeof(double));
+    q[0] = c[K];
+    s[0] = c[0];
+    for (int j = 1; j < K; j++) {
+        q[j] = 2.0 * c[K + j];
+        s[j] = c[j] - c[2 * K - j];
+    }
+    ora_ct *Q = cheb_rec(X, q, r - 1, st);
+    ora_ct *S = cheb_rec(X, s, r - 1, st);
+    ora_ct *Ga = align_to(X->G[r - 1], Q->level, st);
+    ora_ct *pr = ora_mul(X->Kp, Q, Ga, st);
+    ora_ct *Sa = align_to(S, pr->level, st);
+    ora_ct *out = ora_add(pr, Sa);
+    ora_ct_free(Q); ora_ct_free(S); ora_ct_free(Ga); ora_ct_free(pr); ora_ct_free(Sa);
+    free(q); free(s);
+    return out;
+}
+
+int ora_cheb_depth(u32 deg1) { int b = ilog2(deg1); return b + 1; }
+
+/* p(x) = sum_{i < deg1} c_i T_i(x) for deg1 = 2^B (B >= 1), by the
+ * Paterson-Stockmeyer algorithm in the Chebyshev basis with k = 2^l baby
+ * steps, l = ceil(B/2), and m = B - l giant steps:
+ *   T_1 = x, T_{2j} = 2 T_j^2 - 1, T_{2j+1} = 2 T_j T_{j+1} - T_1 (j >= 1),
+ *   G_0 = T_k, G_r = 2 G_{r-1}^2 - 1,
+ * the baby steps brought to one level before the linear combinations.
+ * x at level L leaves at level L - B - 1. */
+ora_ct *ora_cheb_eval(const ora_keys *Kp, const ora_ct *x, const double *c, u32 deg1, int *st) {
+    const int B = ilog2(deg1);
+    if (deg1 < 2 || (1u << B) != deg1) { *st = ORA_E_INVALID; return NULL; }
+    if (x->level < B + 1) { *st = ORA_E_DEPTH; return NULL; }
+    const int l = (B + 1) / 2, m = B - l, k = 1 << l;
+    const int top = m > 0 ? k : k - 1; /* T_k is needed only as G_0 */
+    ora_ct **T = (ora_ct **)calloc(k + 1, sizeof(ora_ct *));
+    T[1] = ct_copy(x);
+    for (int j = 2; j <= top; j++)
+        T[j] = (j & 1) ? cheb_step(Kp, T[j / 2], T[j / 2 + 1], T[1], st) : cheb_step(Kp, T[j / 2], T[j / 2], NULL, st);
+    cheb_ctx X;
+    X.Kp = Kp;
+    X.k = k;
+    X.lb = x->level - l;
+    X.Tb = (ora_ct **)calloc(k, sizeof(ora_ct *));
+    for (int i = 1; i < k; i++) X.Tb[i] = align_to(T[i], X.lb, st);
+    X.G = (ora_ct **)calloc(m > 0 ? m : 1, sizeof(ora_ct *));
+    if (m > 0) {
+        X.G[0] = ct_copy(T[k]);
+        for (int r = 1; r < m; r++) X.G[r] = cheb_step(Kp, X.G[r - 1], X.G[r - 1], NULL, st);
+    }
+    ora_ct *p = cheb_rec(&X, c, m, st);
+    for (int j = 1; j <= top; j++) ora_ct_free(T[j]);
+    for (int i = 1; i < k; i++) ora_ct_free(X.Tb[i]);
+    for (int r = 0; r < m; r++) ora_ct_free(X.G[r]);
+    free(T); free(X.Tb); free(X.G);
+    return p;
+}
+
+/* ------------------------------------------------------------------ */
+/* comparator dispatch                                                  */
+/* ------------------------------------------------------------------ */
+/* levels the comparator takes: 3 per degree-7 polynomial of the f/g
+ * composite, D for the Chebyshev interpolant */
+static int cmp_levels(ora_cmp c) { return c.cheb > 0 ? c.cheb : 3 * (c.dg + c.df); }
+
+static int cmp_valid(ora_cmp c) {
+    if (c.cheb != 0) return c.dg == 0 && c.df == 0 && c.cheb >= 2 && c.cheb <= 16;
+    return c.dg >= 0 && c.df >= 0 && c.dg + c.df >= 1;
+}
+
+/* a * Cmp on the difference D.  f/g: a * (f^{d_f}(g^{d_g}(D)) + 1) / 2,
+ * the factor a/2 folded into the last polynomial and a/2 added as a
+ * constant.  Chebyshev: sum_k (a c_k) T_k(D). */
+static ora_ct *cmp_sign_scaled(const ora_keys *Kp, const ora_ct *D, ora_cmp cm, double a, int *st) {
+    if (!cmp_valid(cm)) { *st = ORA_E_INVALID; return NULL; }
+    if (D->level < cmp_levels(cm)) { *st = ORA_E_DEPTH; return NULL; }
+    if (cm.cheb > 0) {
+        const u32 deg1 = 1u << (cm.cheb - 1);
+        double *c = (double *)malloc(deg1 * sizeof(double));
+        ora_cheb_step_coeffs(cm.cheb, c);
+        for (u32 i = 0; i < deg1; i++) c[i] = c[i] * a;
+        ora_ct *r = ora_cheb_eval(Kp, D, c, deg1, st);
+        free(c);
+        return r;
+    }
     ora_ct *X = ct_copy(D);
-    int total = dg + df;
+    int total = cm.dg + cm.df;
     for (int r = 0; r < total; r++) {
-        const double *c = r < dg ? G_COEF : F_COEF;
+        const double *c = r < cm.dg ? G_COEF : F_COEF;
         double cc[4];
         for (int i = 0; i < 4; i++) cc[i] = (r == total - 1) ? c[i] * (a * 0.5) : c[i];
         replace(&X, ora_poly7(Kp, X, cc, st));
@@ -1026,8 +1187,8 @@ static ora_ct *cmp_sign_scaled(const ora_keys *Kp, const ora_ct *D, int dg, int 
     return X;
 }
 
-ora_ct *ora_cmp_sign(const ora_keys *Kp, const ora_ct *D, int dg, int df, int *st) {
-    return cmp_sign_scaled(Kp, D, dg, df, 1.0, st);
+ora_ct *ora_cmp_sign(const ora_keys *Kp, const ora_ct *D, ora_cmp cm, int *st) {
+    return cmp_sign_scaled(Kp, D, cm, 1.0, st);
 }
 
 /* ------------------------------------------------------------------ */
@@ -1039,29 +1200,29 @@ static int check_N(const ora_params *P, u32 N) {
 }
 
 /* levels consumed by rank: MaskC of TransR, the comparator, MaskR of SumR */
-int ora_rank_depth(int dg, int df) { return 2 + 3 * (dg + df); }
+int ora_rank_depth(ora_cmp cm) { return 2 + cmp_levels(cm); }
 
 /* a * C with C = Cmp(V_R, V_C) as an N x N matrix (C[i][j] = Cmp(v_j, v_i)) */
-static ora_ct *cmp_matrix_scaled(const ora_keys *Kp, const ora_ct *V, u32 N, int dg, int df, double a, int *st) {
+static ora_ct *cmp_matrix_scaled(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, double a, int *st) {
     ora_ct *VR = ora_repl_r(Kp, V, N, st);
     ora_ct *T = ora_trans_r(Kp, V, N, st);
     ora_ct *VC = ora_repl_c(Kp, T, N, st);
     ora_ct *VRa = ora_cmul_to(VR, 1.0, VC->level, st);
     ora_ct *D = ora_sub(VRa, VC);
-    ora_ct *C = cmp_sign_scaled(Kp, D, dg, df, a, st);
+    ora_ct *C = cmp_sign_scaled(Kp, D, cm, a, st);
     ora_ct_free(VR); ora_ct_free(T); ora_ct_free(VC); ora_ct_free(VRa); ora_ct_free(D);
     return C;
 }
 
-ora_ct *ora_cmp_matrix(const ora_keys *Kp, const ora_ct *V, u32 N, int dg, int df, int *st) {
-    return cmp_matrix_scaled(Kp, V, N, dg, df, 1.0, st);
+ora_ct *ora_cmp_matrix(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, int *st) {
+    return cmp_matrix_scaled(Kp, V, N, cm, 1.0, st);
 }
 
-ora_ct *ora_rank(const ora_keys *Kp, const ora_ct *V, u32 N, int dg, int df, int *status) {
+ora_ct *ora_rank(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, int *status) {
     int st = check_N(Kp->P, N);
     if (st != ORA_OK) { *status = st; return NULL; }
-    if (V->level < ora_rank_depth(dg, df)) { *status = ORA_E_DEPTH; return NULL; }
-    ora_ct *C = ora_cmp_matrix(Kp, V, N, dg, df, &st);
+    if (V->level < ora_rank_depth(cm)) { *status = ORA_E_DEPTH; return NULL; }
+    ora_ct *C = ora_cmp_matrix(Kp, V, N, cm, &st);
     ora_ct *S = ora_sum_r(Kp, C, N, &st);
     double *half = (double *)malloc(N * sizeof(double));
     for (u32 j = 0; j < N; j++) half[j] = 0.5;
@@ -1080,15 +1241,15 @@ ora_ct *ora_rank(const ora_keys *Kp, const ora_ct *V, u32 N, int dg, int df, int
  * where sum_{j<i} (1 - C_{j,i}) is evaluated as (i - 1) - sum_{j<i} C_{j,i}
  * (one constant add).  The SumR term is brought down to the TransC term's
  * level, so every R_i leaves at level(B) - depth. */
-int ora_rank_multi_depth(int dg, int df) { return 3 + 3 * (dg + df); }
+int ora_rank_multi_depth(ora_cmp cm) { return 3 + cmp_levels(cm); }
 
-int ora_rank_multi(const ora_keys *Kp, ora_ct *const *Bk, u32 L, u32 b, int dg, int df, ora_ct **R) {
+int ora_rank_multi(const ora_keys *Kp, ora_ct *const *Bk, u32 L, u32 b, ora_cmp cm, ora_ct **R) {
     int st = check_N(Kp->P, b);
     if (st != ORA_OK) return st;
     if (L < 1) return ORA_E_INVALID;
     for (u32 i = 0; i < L; i++)
         if (Bk[i]->level != Bk[0]->level) return ORA_E_INVALID;
-    if (Bk[0]->level < ora_rank_multi_depth(dg, df)) return ORA_E_DEPTH;
+    if (Bk[0]->level < ora_rank_multi_depth(cm)) return ORA_E_DEPTH;
     ora_ct **VR = (ora_ct **)calloc(L, sizeof(ora_ct *)), **VC = (ora_ct **)calloc(L, sizeof(ora_ct *));
     ora_ct **Cm = (ora_ct **)calloc((size_t)L * L, sizeof(ora_ct *));
     for (u32 i = 0; i < L; i++) {
@@ -1101,7 +1262,7 @@ int ora_rank_multi(const ora_keys *Kp, ora_ct *const *Bk, u32 L, u32 b, int dg, 
         for (u32 j = i; j < L; j++) {
             ora_ct *VRa = ora_cmul_to(VR[i], 1.0, VC[j]->level, &st);
             ora_ct *D = ora_sub(VRa, VC[j]);
-            Cm[i * L + j] = ora_cmp_sign(Kp, D, dg, df, &st);
+            Cm[i * L + j] = ora_cmp_sign(Kp, D, cm, &st);
             ora_ct_free(VRa); ora_ct_free(D);
         }
     const int lc = Cm[0]->level; /* comparator output level */
@@ -1139,22 +1300,22 @@ int ora_rank_multi(const ora_keys *Kp, ora_ct *const *Bk, u32 L, u32 b, int dg, 
  * source block j, M_{i,j} = Ind_0(ReplR(R_j) - (b(i-1)+1 || ... || b i)) with
  * Ind_0(x) = Cmp(x, -1/2) (1 - Cmp(x, 1/2)) on (x +- 1/2)/N (N = L b);
  * S_i = TransC(SumC(sum_j M_{i,j} * ReplR(B_j))).  Distinct inputs. */
-int ora_sort_multi_depth(int cdg, int cdf, int idg, int idf) {
+int ora_sort_multi_depth(ora_cmp cm, ora_cmp ci) {
     /* multi rank, scaling, indicator, indicator product, M * V_R, SumC mask, TransC mask */
-    return ora_rank_multi_depth(cdg, cdf) + 5 + 3 * (idg + idf);
+    return ora_rank_multi_depth(cm) + 5 + cmp_levels(ci);
 }
 
-int ora_sort_multi(const ora_keys *Kp, ora_ct *const *Bk, u32 L, u32 b, int cdg, int cdf, int idg, int idf,
+int ora_sort_multi(const ora_keys *Kp, ora_ct *const *Bk, u32 L, u32 b, ora_cmp cm, ora_cmp ci,
                    ora_ct **S) {
     int st = check_N(Kp->P, b);
     if (st != ORA_OK) return st;
     if (L < 1) return ORA_E_INVALID;
     for (u32 i = 0; i < L; i++)
         if (Bk[i]->level != Bk[0]->level) return ORA_E_INVALID;
-    if (Bk[0]->level < ora_sort_multi_depth(cdg, cdf, idg, idf)) return ORA_E_DEPTH;
+    if (Bk[0]->level < ora_sort_multi_depth(cm, ci)) return ORA_E_DEPTH;
     const double dN = (double)L * (double)b;
     ora_ct **R = (ora_ct **)calloc(L, sizeof(ora_ct *));
-    st = ora_rank_multi(Kp, Bk, L, b, cdg, cdf, R);
+    st = ora_rank_multi(Kp, Bk, L, b, cm, R);
     ora_ct **RR = (ora_ct **)calloc(L, sizeof(ora_ct *)), **VR = (ora_ct **)calloc(L, sizeof(ora_ct *));
     for (u32 j = 0; j < L; j++) {
         RR[j] = ora_repl_r(Kp, R[j], b, &st);
@@ -1170,8 +1331,8 @@ int ora_sort_multi(const ora_keys *Kp, ora_ct *const *Bk, u32 L, u32 b, int cdg,
             ora_ct *Xs = ora_cmul_to(X, 1.0 / dN, X->level - 1, &st);
             ora_ct *d1 = ora_add_const(Xs, 0.5 / dN);
             ora_ct *d2 = ora_add_const(Xs, -0.5 / dN);
-            ora_ct *c1 = ora_cmp_sign(Kp, d1, idg, idf, &st);
-            ora_ct *c2 = ora_cmp_sign(Kp, d2, idg, idf, &st);
+            ora_ct *c1 = ora_cmp_sign(Kp, d1, ci, &st);
+            ora_ct *c2 = ora_cmp_sign(Kp, d2, ci, &st);
             ora_ct *n2 = mul_int(c2, -1);
             ora_ct *o2 = ora_add_const(n2, 1.0);
             ora_ct *M = ora_mul(Kp, c1, o2, &st);
@@ -1233,20 +1394,20 @@ ora_ct *ora_mul_int(const ora_ct *a, i64 K) { return mul_int(a, K); }
  * into the comparator's last polynomial, and SumR keeps no row mask: the
  * other rows hold bounded garbage that O * V annihilates (V is zero outside
  * row 0).  onehot = MaskR(O, 0); value = SumC(O * V) in slot 0. */
-int ora_order_stat_depth(u32 N, u32 k, int cdg, int cdf, int idg, int idf, int tie) {
-    int ind = 3 * (idg + idf) + ((k > 1 && k < N) ? 1 : 0);
+int ora_order_stat_depth(u32 N, u32 k, ora_cmp cm, ora_cmp ci, int tie) {
+    int ind = cmp_levels(ci) + ((k > 1 && k < N) ? 1 : 0);
     /* TransR mask, comparator, [E, E*mask, SumR mask, scaling,] indicator, O*V, SumC mask */
-    return 1 + 3 * (cdg + cdf) + (tie ? 4 : 0) + ind + 2;
+    return 1 + cmp_levels(cm) + (tie ? 4 : 0) + ind + 2;
 }
 
-int ora_argmin_depth(int cdg, int cdf, int idg, int idf) { return ora_order_stat_depth(2, 1, cdg, cdf, idg, idf, 1); }
+int ora_argmin_depth(ora_cmp cm, ora_cmp ci) { return ora_order_stat_depth(2, 1, cm, ci, 1); }
 
 /* tie-corrected rank k_j = SumR(C + E (delta_{j>=i} - 1/2)), E = C (4 - 4C):
  * Rank plus the Tie-Correction Offset of section 4 (their +1/2 and -1/2
  * cancel), a permutation of 1..N.  Levels: TransR mask, comparator, E,
  * E * tie mask, SumR mask. */
-static ora_ct *tie_rank(const ora_keys *Kp, const ora_ct *V, u32 N, int cdg, int cdf, int *st) {
-    ora_ct *C = ora_cmp_matrix(Kp, V, N, cdg, cdf, st);
+static ora_ct *tie_rank(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, int *st) {
+    ora_ct *C = ora_cmp_matrix(Kp, V, N, cm, st);
     ora_ct *m4 = mul_int(C, -4);
     ora_ct *w = ora_add_const(m4, 4.0);
     ora_ct *E = ora_mul(Kp, C, w, st);
@@ -1263,33 +1424,33 @@ static ora_ct *tie_rank(const ora_keys *Kp, const ora_ct *V, u32 N, int cdg, int
     return kv;
 }
 
-ora_ct *ora_rank_tie(const ora_keys *Kp, const ora_ct *V, u32 N, int dg, int df, int *status) {
+ora_ct *ora_rank_tie(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, int *status) {
     int st = check_N(Kp->P, N);
     if (st != ORA_OK) { *status = st; return NULL; }
-    if (V->level < ora_rank_depth(dg, df) + 2) { *status = ORA_E_DEPTH; return NULL; }
-    ora_ct *kv = tie_rank(Kp, V, N, dg, df, &st);
+    if (V->level < ora_rank_depth(cm) + 2) { *status = ORA_E_DEPTH; return NULL; }
+    ora_ct *kv = tie_rank(Kp, V, N, cm, &st);
     *status = st;
     return kv;
 }
 
-int ora_order_stat(const ora_keys *Kp, const ora_ct *V, u32 N, u32 k, int cdg, int cdf, int idg, int idf, int tie,
+int ora_order_stat(const ora_keys *Kp, const ora_ct *V, u32 N, u32 k, ora_cmp cm, ora_cmp ci, int tie,
                    ora_ct **onehot, ora_ct **value) {
     int st = check_N(Kp->P, N);
     if (st != ORA_OK) return st;
     if (k < 1 || k > N) return ORA_E_INVALID;
-    if (V->level < ora_order_stat_depth(N, k, cdg, cdf, idg, idf, tie)) return ORA_E_DEPTH;
+    if (V->level < ora_order_stat_depth(N, k, cm, ci, tie)) return ORA_E_DEPTH;
     const double dN = (double)N, dk = (double)k;
     ora_ct *base; /* k_j (times +-1/N) */
     double off1, off2 = 0.0; /* constants giving the indicator argument(s) */
     if (tie) {
-        ora_ct *kv = tie_rank(Kp, V, N, cdg, cdf, &st);
+        ora_ct *kv = tie_rank(Kp, V, N, cm, &st);
         base = ora_cmul_to(kv, k == 1 ? -1.0 / dN : 1.0 / dN, kv->level - 1, &st);
         if (k == 1) off1 = 1.5 / dN;
         else if (k == N) off1 = (0.5 - dN) / dN;
         else off1 = (0.5 - dk) / dN, off2 = (-0.5 - dk) / dN;
         ora_ct_free(kv);
     } else {
-        ora_ct *C = cmp_matrix_scaled(Kp, V, N, cdg, cdf, k == 1 ? -1.0 / dN : 1.0 / dN, &st);
+        ora_ct *C = cmp_matrix_scaled(Kp, V, N, cm, k == 1 ? -1.0 / dN : 1.0 / dN, &st);
         base = ct_copy(C);
         for (int i = 0; i < ilog2(N); i++) replace(&base, add_rot(Kp, base, (i64)N << i, &st));
         if (k == 1) off1 = 1.0 / dN;
@@ -1300,12 +1461,12 @@ int ora_order_stat(const ora_keys *Kp, const ora_ct *V, u32 N, u32 k, int cdg, i
     ora_ct *O;
     if (k == 1 || k == N) {
         ora_ct *y = ora_add_const(base, off1);
-        O = ora_cmp_sign(Kp, y, idg, idf, &st);
+        O = ora_cmp_sign(Kp, y, ci, &st);
         ora_ct_free(y);
     } else {
         ora_ct *d1 = ora_add_const(base, off1), *d2 = ora_add_const(base, off2);
-        ora_ct *c1 = ora_cmp_sign(Kp, d1, idg, idf, &st);
-        ora_ct *c2 = ora_cmp_sign(Kp, d2, idg, idf, &st);
+        ora_ct *c1 = ora_cmp_sign(Kp, d1, ci, &st);
+        ora_ct *c2 = ora_cmp_sign(Kp, d2, ci, &st);
         ora_ct *n2 = mul_int(c2, -1);
         ora_ct *o2 = ora_add_const(n2, 1.0);
         O = ora_mul(Kp, c1, o2, &st);
@@ -1323,25 +1484,25 @@ int ora_order_stat(const ora_keys *Kp, const ora_ct *V, u32 N, u32 k, int cdg, i
 }
 
 /* the minimum with tie-correction: order statistic k = 1 */
-int ora_argmin(const ora_keys *Kp, const ora_ct *V, u32 N, int cdg, int cdf, int idg, int idf, ora_ct **onehot,
+int ora_argmin(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, ora_cmp ci, ora_ct **onehot,
                ora_ct **value) {
-    return ora_order_stat(Kp, V, N, 1, cdg, cdf, idg, idf, 1, onehot, value);
+    return ora_order_stat(Kp, V, N, 1, cm, ci, 1, onehot, value);
 }
 
 /* ------------------------------------------------------------------ */
 /* Sorting (Algorithm Sorting, section 3.3), distinct inputs            */
 /* ------------------------------------------------------------------ */
 /* levels: Rank, scaling, indicator, indicator product, M*V_R, SumC mask, TransC mask */
-int ora_sort_depth(int cdg, int cdf, int idg, int idf) { return ora_rank_depth(cdg, cdf) + 5 + 3 * (idg + idf); }
+int ora_sort_depth(ora_cmp cm, ora_cmp ci) { return ora_rank_depth(cm) + 5 + cmp_levels(ci); }
 
 /* R = Rank(V); R_R = ReplR(R); X = R_R - (1^N || ... || N^N);
  * M = Ind_0(X) = Cmp(X, -1/2) (1 - Cmp(X, 1/2)), the comparisons evaluated on
  * (X + 1/2)/N and (X - 1/2)/N; S = TransC(SumC(M * ReplR(V))). */
-ora_ct *ora_sort(const ora_keys *Kp, const ora_ct *V, u32 N, int cdg, int cdf, int idg, int idf, int *status) {
+ora_ct *ora_sort(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, ora_cmp ci, int *status) {
     int st = check_N(Kp->P, N);
     if (st != ORA_OK) { *status = st; return NULL; }
-    if (V->level < ora_sort_depth(cdg, cdf, idg, idf)) { *status = ORA_E_DEPTH; return NULL; }
-    ora_ct *R = ora_rank(Kp, V, N, cdg, cdf, &st);
+    if (V->level < ora_sort_depth(cm, ci)) { *status = ORA_E_DEPTH; return NULL; }
+    ora_ct *R = ora_rank(Kp, V, N, cm, &st);
     ora_ct *RR = ora_repl_r(Kp, R, N, &st);
     double *steps = (double *)calloc((size_t)N * N, sizeof(double));
     for (u32 i = 0; i < N; i++)
@@ -1351,8 +1512,8 @@ ora_ct *ora_sort(const ora_keys *Kp, const ora_ct *V, u32 N, int cdg, int cdf, i
     ora_ct *Xs = ora_cmul_to(X, 1.0 / (double)N, X->level - 1, &st);
     ora_ct *d1 = ora_add_const(Xs, 0.5 / (double)N);
     ora_ct *d2 = ora_add_const(Xs, -0.5 / (double)N);
-    ora_ct *c1 = ora_cmp_sign(Kp, d1, idg, idf, &st);
-    ora_ct *c2 = ora_cmp_sign(Kp, d2, idg, idf, &st);
+    ora_ct *c1 = ora_cmp_sign(Kp, d1, ci, &st);
+    ora_ct *c2 = ora_cmp_sign(Kp, d2, ci, &st);
     ora_ct *n2 = mul_int(c2, -1);
     ora_ct *o2 = ora_add_const(n2, 1.0);
     ora_ct *M = ora_mul(Kp, c1, o2, &st);

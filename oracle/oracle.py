@@ -37,6 +37,17 @@ def build(force=False):
 _lib = None
 
 
+class OraCmp(C.Structure):
+    """comparator: (d_g, d_f) of the f/g composite, or cheb = D levels of the Chebyshev interpolant"""
+    _fields_ = [("dg", C.c_int), ("df", C.c_int), ("cheb", C.c_int)]
+
+
+def _cmp(spec):
+    """(d_g, d_f) or (0, 0, D) -> OraCmp"""
+    spec = tuple(int(x) for x in spec)
+    return OraCmp(spec[0], spec[1], spec[2] if len(spec) > 2 else 0)
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -88,26 +99,29 @@ def lib():
             "ora_repl_r": (vp, [vp, vp, C.c_uint32, intp]),
             "ora_repl_c": (vp, [vp, vp, C.c_uint32, intp]),
             "ora_poly7": (vp, [vp, vp, dblp, intp]),
-            "ora_cmp_sign": (vp, [vp, vp, C.c_int, C.c_int, intp]),
-            "ora_cmp_matrix": (vp, [vp, vp, C.c_uint32, C.c_int, C.c_int, intp]),
-            "ora_rank": (vp, [vp, vp, C.c_uint32, C.c_int, C.c_int, intp]),
-            "ora_rank_depth": (C.c_int, [C.c_int, C.c_int]),
+            "ora_cmp_sign": (vp, [vp, vp, OraCmp, intp]),
+            "ora_cmp_matrix": (vp, [vp, vp, C.c_uint32, OraCmp, intp]),
+            "ora_rank": (vp, [vp, vp, C.c_uint32, OraCmp, intp]),
+            "ora_rank_depth": (C.c_int, [OraCmp]),
             "ora_rank_galois": (C.c_int, [vp, C.c_uint32, u32p]),
             "ora_galois_left": (C.c_uint32, [vp, C.c_uint64]),
             "ora_mul_int": (vp, [vp, C.c_int64]),
-            "ora_argmin_depth": (C.c_int, [C.c_int] * 4),
-            "ora_argmin": (C.c_int, [vp, vp, C.c_uint32, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(vp),
-                                     C.POINTER(vp)]),
-            "ora_rank_multi_depth": (C.c_int, [C.c_int, C.c_int]),
-            "ora_rank_multi": (C.c_int, [vp, C.POINTER(vp), C.c_uint32, C.c_uint32, C.c_int, C.c_int, C.POINTER(vp)]),
-            "ora_sort_multi_depth": (C.c_int, [C.c_int] * 4),
-            "ora_sort_multi": (C.c_int, [vp, C.POINTER(vp), C.c_uint32, C.c_uint32] + [C.c_int] * 4 + [C.POINTER(vp)]),
-            "ora_rank_tie": (vp, [vp, vp, C.c_uint32, C.c_int, C.c_int, intp]),
-            "ora_order_stat_depth": (C.c_int, [C.c_uint32, C.c_uint32] + [C.c_int] * 5),
-            "ora_order_stat": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32] + [C.c_int] * 5 + [C.POINTER(vp), C.POINTER(vp)]),
-            "ora_sort_depth": (C.c_int, [C.c_int] * 4),
-            "ora_sort": (vp, [vp, vp, C.c_uint32, C.c_int, C.c_int, C.c_int, C.c_int, intp]),
+            "ora_argmin_depth": (C.c_int, [OraCmp, OraCmp]),
+            "ora_argmin": (C.c_int, [vp, vp, C.c_uint32, OraCmp, OraCmp, C.POINTER(vp), C.POINTER(vp)]),
+            "ora_rank_multi_depth": (C.c_int, [OraCmp]),
+            "ora_rank_multi": (C.c_int, [vp, C.POINTER(vp), C.c_uint32, C.c_uint32, OraCmp, C.POINTER(vp)]),
+            "ora_sort_multi_depth": (C.c_int, [OraCmp, OraCmp]),
+            "ora_sort_multi": (C.c_int, [vp, C.POINTER(vp), C.c_uint32, C.c_uint32, OraCmp, OraCmp, C.POINTER(vp)]),
+            "ora_rank_tie": (vp, [vp, vp, C.c_uint32, OraCmp, intp]),
+            "ora_order_stat_depth": (C.c_int, [C.c_uint32, C.c_uint32, OraCmp, OraCmp, C.c_int]),
+            "ora_order_stat": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32, OraCmp, OraCmp, C.c_int, C.POINTER(vp),
+                                         C.POINTER(vp)]),
+            "ora_sort_depth": (C.c_int, [OraCmp, OraCmp]),
+            "ora_sort": (vp, [vp, vp, C.c_uint32, OraCmp, OraCmp, intp]),
             "ora_circuit_galois": (C.c_int, [vp, C.c_uint32, C.c_int, u32p]),
+            "ora_cheb_step_coeffs": (None, [C.c_int, dblp]),
+            "ora_cheb_depth": (C.c_int, [C.c_uint32]),
+            "ora_cheb_eval": (vp, [vp, vp, dblp, C.c_uint32, intp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -334,41 +348,61 @@ def poly7(keys, a, coeffs):
     return _ct(lib().ora_poly7, a.params, keys.ptr, a.ptr, _p(c, dblp), what="poly7")
 
 
-def cmp_sign(keys, a, dg, df):
-    return _ct(lib().ora_cmp_sign, a.params, keys.ptr, a.ptr, dg, df, what="cmp_sign")
+# A comparator is given as (d_g, d_f) for the f/g composite or (0, 0, D) for
+# the Chebyshev interpolant taking D levels; the functions taking "dg, df"
+# accept the Chebyshev depth as a third argument.
+def cmp_sign(keys, a, dg, df, cheb=0):
+    return _ct(lib().ora_cmp_sign, a.params, keys.ptr, a.ptr, _cmp((dg, df, cheb)), what="cmp_sign")
 
 
-def cmp_matrix(keys, a, N, dg, df):
-    return _ct(lib().ora_cmp_matrix, a.params, keys.ptr, a.ptr, N, dg, df, what="cmp_matrix")
+def cmp_matrix(keys, a, N, dg, df, cheb=0):
+    return _ct(lib().ora_cmp_matrix, a.params, keys.ptr, a.ptr, N, _cmp((dg, df, cheb)), what="cmp_matrix")
 
 
-def rank(keys, a, N, dg, df):
+def rank(keys, a, N, dg, df, cheb=0):
     keys.need(N, 1)
-    return _ct(lib().ora_rank, a.params, keys.ptr, a.ptr, N, dg, df, what="rank")
+    return _ct(lib().ora_rank, a.params, keys.ptr, a.ptr, N, _cmp((dg, df, cheb)), what="rank")
 
 
-def rank_depth(dg, df):
-    return lib().ora_rank_depth(dg, df)
+def rank_depth(dg, df, cheb=0):
+    return lib().ora_rank_depth(_cmp((dg, df, cheb)))
 
 
-def rank_multi_depth(dg, df):
-    return lib().ora_rank_multi_depth(dg, df)
+def rank_multi_depth(dg, df, cheb=0):
+    return lib().ora_rank_multi_depth(_cmp((dg, df, cheb)))
 
 
-def rank_multi(keys, blocks, b, dg, df):
+def cheb_step_coeffs(D):
+    """the oracle's Chebyshev coefficients of the comparison function (2^(D-1) of them)"""
+    c = np.zeros(1 << (D - 1))
+    lib().ora_cheb_step_coeffs(D, _p(c, dblp))
+    return c
+
+
+def cheb_depth(deg1):
+    return lib().ora_cheb_depth(deg1)
+
+
+def cheb_eval(keys, a, coeffs):
+    """sum_i coeffs[i] T_i(x) (len(coeffs) a power of two) by Paterson-Stockmeyer"""
+    c = np.ascontiguousarray(coeffs, np.float64)
+    return _ct(lib().ora_cheb_eval, a.params, keys.ptr, a.ptr, _p(c, dblp), len(c), what="cheb_eval")
+
+
+def rank_multi(keys, blocks, b, dg, df, cheb=0):
     """Multi-ciphertext ranking of len(blocks) blocks of b values; returns the L rank blocks."""
     keys.need(b, 4)
     L = len(blocks)
     arr = (C.c_void_p * L)(*[x.ptr for x in blocks])
     out = (C.c_void_p * L)()
-    st = lib().ora_rank_multi(keys.ptr, arr, L, b, dg, df, out)
+    st = lib().ora_rank_multi(keys.ptr, arr, L, b, _cmp((dg, df, cheb)), out)
     if st != 0:
         raise OracleError(f"rank_multi: status {STATUS.get(st, st)}")
     return [Ct(out[i], blocks[0].params) for i in range(L)]
 
 
 def sort_multi_depth(cmp, ind):
-    return lib().ora_sort_multi_depth(cmp[0], cmp[1], ind[0], ind[1])
+    return lib().ora_sort_multi_depth(_cmp(cmp), _cmp(ind))
 
 
 def sort_multi(keys, blocks, b, cmp, ind):
@@ -377,16 +411,16 @@ def sort_multi(keys, blocks, b, cmp, ind):
     L = len(blocks)
     arr = (C.c_void_p * L)(*[x.ptr for x in blocks])
     out = (C.c_void_p * L)()
-    st = lib().ora_sort_multi(keys.ptr, arr, L, b, cmp[0], cmp[1], ind[0], ind[1], out)
+    st = lib().ora_sort_multi(keys.ptr, arr, L, b, _cmp(cmp), _cmp(ind), out)
     if st != 0:
         raise OracleError(f"sort_multi: status {STATUS.get(st, st)}")
     return [Ct(out[i], blocks[0].params) for i in range(L)]
 
 
-def rank_tie(keys, a, N, dg, df):
+def rank_tie(keys, a, N, dg, df, cheb=0):
     """tie-corrected rank (rank plus the tie-correction offset): a permutation of 1..N"""
     keys.need(N, 1)
-    return _ct(lib().ora_rank_tie, a.params, keys.ptr, a.ptr, N, dg, df, what="rank_tie")
+    return _ct(lib().ora_rank_tie, a.params, keys.ptr, a.ptr, N, _cmp((dg, df, cheb)), what="rank_tie")
 
 
 # ---- primitive pins -------------------------------------------------------
@@ -452,38 +486,37 @@ def mul_int(a, K):
 
 
 def argmin_depth(cmp, ind):
-    return lib().ora_argmin_depth(cmp[0], cmp[1], ind[0], ind[1])
+    return lib().ora_argmin_depth(_cmp(cmp), _cmp(ind))
 
 
 def argmin(keys, a, N, cmp, ind):
     """(onehot, value) ciphertexts of the tie-corrected minimum."""
     keys.need(N, 2)
     oh, val = C.c_void_p(), C.c_void_p()
-    st = lib().ora_argmin(keys.ptr, a.ptr, N, cmp[0], cmp[1], ind[0], ind[1], C.byref(oh), C.byref(val))
+    st = lib().ora_argmin(keys.ptr, a.ptr, N, _cmp(cmp), _cmp(ind), C.byref(oh), C.byref(val))
     if st != 0:
         raise OracleError(f"argmin: status {STATUS.get(st, st)}")
     return Ct(oh.value, a.params), Ct(val.value, a.params)
 
 
 def order_stat_depth(N, k, cmp, ind, tie):
-    return lib().ora_order_stat_depth(N, k, cmp[0], cmp[1], ind[0], ind[1], int(tie))
+    return lib().ora_order_stat_depth(N, k, _cmp(cmp), _cmp(ind), int(tie))
 
 
 def order_stat(keys, a, N, k, cmp, ind, tie):
     """(onehot, value) ciphertexts of the k-th smallest element (tie-corrected if tie)."""
     keys.need(N, 2)
     oh, val = C.c_void_p(), C.c_void_p()
-    st = lib().ora_order_stat(keys.ptr, a.ptr, N, k, cmp[0], cmp[1], ind[0], ind[1], int(tie), C.byref(oh),
-                              C.byref(val))
+    st = lib().ora_order_stat(keys.ptr, a.ptr, N, k, _cmp(cmp), _cmp(ind), int(tie), C.byref(oh), C.byref(val))
     if st != 0:
         raise OracleError(f"order_stat: status {STATUS.get(st, st)}")
     return Ct(oh.value, a.params), Ct(val.value, a.params)
 
 
 def sort_depth(cmp, ind):
-    return lib().ora_sort_depth(cmp[0], cmp[1], ind[0], ind[1])
+    return lib().ora_sort_depth(_cmp(cmp), _cmp(ind))
 
 
 def sort(keys, a, N, cmp, ind):
     keys.need(N, 4)
-    return _ct(lib().ora_sort, a.params, keys.ptr, a.ptr, N, cmp[0], cmp[1], ind[0], ind[1], what="sort")
+    return _ct(lib().ora_sort, a.params, keys.ptr, a.ptr, N, _cmp(cmp), _cmp(ind), what="sort")

@@ -11,9 +11,13 @@ algorithms step by step:
 Rotations are cyclic over `slots` positions: x << k means new[j] = x[j+k].
 
 The comparator is either the ideal function of Eq. (1) applied to the pair
-(x, y), or the f/g composite of section 2.2 applied to x - y.
+(x, y), the f/g composite of section 2.2 applied to x - y, or the Chebyshev
+interpolant of Eq. (1) on [-1, 1] (section 2.2).  A comparator spec is a
+tuple (d_g, d_f) for the composite or (0, 0, D) for the Chebyshev
+interpolant of degree 2^(D-1) - 1, whose evaluation takes D levels.
 """
 import numpy as np
+from numpy.polynomial import chebyshev as _cheb
 
 F_COEF = (35 / 16, -35 / 16, 21 / 16, -5 / 16)
 G_COEF = (4589 / 1024, -16577 / 1024, 25614 / 1024, -12860 / 1024)
@@ -101,11 +105,34 @@ def cmp_composite(d, dg, df):
     return (d + 1.0) / 2.0
 
 
+def cheb_step_coeffs(D):
+    """Chebyshev coefficients of the interpolant of Eq. (1) (as a function
+    of d = x - y) at the 2M = 2^(D-1) Chebyshev nodes of [-1, 1]: degree
+    2M - 1, c_0 = 1/2, c_k = 0 for even k > 0 and, for odd k,
+    c_k = (-1)^((k-1)/2) / (2M sin(pi k / 4M)) (the node sum in closed form)."""
+    M = 1 << (D - 2)
+    c = np.zeros(2 * M)
+    c[0] = 0.5
+    k = np.arange(1, 2 * M, 2)
+    c[1::2] = np.where((k - 1) // 2 % 2 == 0, 1.0, -1.0) / (2 * M * np.sin(np.pi * k / (4 * M)))
+    return c
+
+
+def is_cheb(cmp):
+    return len(cmp) == 3 and cmp[2] > 0
+
+
+def cmp_of(d, cmp):
+    """Cmp on the difference d under the spec cmp (composite or Chebyshev)."""
+    if is_cheb(cmp):
+        return _cheb.chebval(d, cheb_step_coeffs(cmp[2]))
+    return (sign_composite(d, cmp[0], cmp[1]) + 1.0) / 2.0
+
+
 def comparator(cmp):
     if cmp == "ideal":
         return lambda x, y: cmp_ideal(x, y)
-    dg, df = cmp
-    return lambda x, y: cmp_composite(x - y, dg, df)
+    return lambda x, y: cmp_of(x - y, cmp)
 
 
 def embed(v, slots):
@@ -188,14 +215,14 @@ def argmin_circuit(v, N, slots, cmp, ind):
     x = embed(v, slots)
     VR = repl_r(x, N)
     VC = repl_c(trans_r(x, N), N)
-    Cm = (sign_composite(VR - VC, *cmp) + 1.0) / 2.0
+    Cm = cmp_of(VR - VC, cmp)
     E = Cm * (4.0 - 4.0 * Cm)
     tie = np.zeros(slots)
     for i in range(N):
         tie[i * N:(i + 1) * N] = np.where(np.arange(N) >= i, 0.5, -0.5)
     k = sum_r(Cm + E * tie, N)
     d = (1.5 - k) / N
-    O = (sign_composite(d, *ind) + 1.0) / 2.0
+    O = cmp_of(d, ind)
     val = sum_c(O * x, N)
     return mask_row(O, N, 0), val, k
 
@@ -211,7 +238,7 @@ def order_stat_circuit(v, N, slots, k, cmp, ind, tie):
     x = embed(v, slots)
     VR = repl_r(x, N)
     VC = repl_c(trans_r(x, N), N)
-    Cm = (sign_composite(VR - VC, *cmp) + 1.0) / 2.0
+    Cm = cmp_of(VR - VC, cmp)
     if tie:
         E = Cm * (4.0 - 4.0 * Cm)
         tm = np.zeros(slots)
@@ -224,12 +251,12 @@ def order_stat_circuit(v, N, slots, k, cmp, ind, tie):
             kv = kv + rot_left(kv, N << i)
         kv = kv + 0.5          # the rank
     if k == 1:
-        O = (sign_composite((1.5 - kv) / N, *ind) + 1.0) / 2.0
+        O = cmp_of((1.5 - kv) / N, ind)
     elif k == N:
-        O = (sign_composite((kv - (N - 0.5)) / N, *ind) + 1.0) / 2.0
+        O = cmp_of((kv - (N - 0.5)) / N, ind)
     else:
-        c1 = (sign_composite((kv - k + 0.5) / N, *ind) + 1.0) / 2.0
-        c2 = (sign_composite((kv - k - 0.5) / N, *ind) + 1.0) / 2.0
+        c1 = cmp_of((kv - k + 0.5) / N, ind)
+        c2 = cmp_of((kv - k - 0.5) / N, ind)
         O = c1 * (1.0 - c2)
     val = sum_c(O * x, N)
     return mask_row(O, N, 0), val, kv
@@ -244,7 +271,7 @@ def rank_multi_circuit(v, b, slots, cmp):
     blocks = [embed(v[i * b:(i + 1) * b], slots) for i in range(L)]
     VR = [repl_r(x, b) for x in blocks]
     VC = [repl_c(trans_r(x, b), b) for x in blocks]
-    C = {(i, j): (sign_composite(VR[i] - VC[j], *cmp) + 1.0) / 2.0 for i in range(L) for j in range(i, L)}
+    C = {(i, j): cmp_of(VR[i] - VC[j], cmp) for i in range(L) for j in range(i, L)}
     half = embed(np.full(b, 0.5), slots)
     out = []
     for i in range(L):
@@ -272,8 +299,8 @@ def sort_multi_circuit(v, b, slots, cmp, ind):
         acc = 0.0
         for j in range(L):
             X = (RR[j] - steps) / N
-            c1 = (sign_composite(X + 0.5 / N, *ind) + 1.0) / 2.0
-            c2 = (sign_composite(X - 0.5 / N, *ind) + 1.0) / 2.0
+            c1 = cmp_of(X + 0.5 / N, ind)
+            c2 = cmp_of(X - 0.5 / N, ind)
             acc = acc + c1 * (1.0 - c2) * VR[j]
         out.append(trans_c(sum_c(acc, b), b))
     return out
@@ -288,8 +315,8 @@ def sort_circuit(v, N, slots, cmp, ind):
     for k in range(N):
         steps[k * N:(k + 1) * N] = k + 1
     X = RR - steps
-    c1 = (sign_composite((X + 0.5) / N, *ind) + 1.0) / 2.0
-    c2 = (sign_composite((X - 0.5) / N, *ind) + 1.0) / 2.0
+    c1 = cmp_of((X + 0.5) / N, ind)
+    c2 = cmp_of((X - 0.5) / N, ind)
     M = c1 * (1.0 - c2)
     VR = repl_r(x, N)
     SC = sum_c(M * VR, N)

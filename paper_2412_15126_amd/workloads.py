@@ -53,6 +53,11 @@ ORDER_CMP = {8: ((3, 1), (2, 2)), 16: ((4, 1), (3, 2)), 32: ((4, 1), (3, 2)), 64
              128: ((4, 1), (4, 2))}
 # tie-corrected order statistic for k > 1 (k = 1 uses ARGMIN_CMP)
 ORDER_TIE_CMP = {8: ((3, 1), (2, 2)), 128: ((4, 2), (4, 2))}
+# Chebyshev comparator (0, 0, D): the interpolant of the comparison function
+# taking D levels (degree 2^(D-1) - 1), the paper's choice for rank and minimum
+# at N <= 256 (up to degree 2^11, i.e. D = 12); per N, the depth whose ranks
+# round exactly at the workload's minimum gap
+CHEB_CMP = {8: (0, 0, 8), 128: (0, 0, 12)}
 # multi-ciphertext rank (blocks of b values, N = L b): comparator per total N
 MULTI_RANK_CMP = {64: (4, 1), 128: (4, 1), 256: (4, 2), 512: (4, 2), 1024: (4, 2)}
 # multi-ciphertext sort: (comparator, two-sided indicator) per total N
