@@ -66,11 +66,19 @@ typedef struct {
     uint32_t dnum;
 } ckr_params;
 
-/* Comparator composition: g applied d_g times, then f applied d_f times
- * (section 2.2).  Each application consumes 3 levels. */
+/* Comparator (section 2.2), one of:
+ *  - the f/g composite: g applied d_g times, then f applied d_f times
+ *    (cheb = 0, d_g + d_f >= 1); each application consumes 3 levels;
+ *  - the Chebyshev interpolant of the comparison function of Eq. (1) on
+ *    [-1, 1] at the 2^(cheb-1) Chebyshev nodes (degree 2^(cheb-1) - 1),
+ *    evaluated by Paterson-Stockmeyer in the Chebyshev basis in cheb levels
+ *    (d_g = d_f = 0, 2 <= cheb <= 16).  The paper's experiments use this
+ *    form for rank and minimum at N <= 256, up to degree 2^11 (cheb = 12).
+ * Any other combination is rejected with CKR_E_INVALID. */
 typedef struct {
     uint8_t d_g;
     uint8_t d_f;
+    uint8_t cheb;
 } ckr_sign;
 
 /* Create a context on HIP device `hip_device`.  hbm_budget bounds the bytes
@@ -274,6 +282,16 @@ void ckr_ct_free(ckr_ct *ct);
  * circuits use; exposed for testing and custom circuits). */
 ckr_status ckr_op_rotate(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, int64_t k, ckr_ct **out);
 ckr_status ckr_op_mul(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, const ckr_ct *b, ckr_ct **out);
+/* sum_{i < deg1} coeffs[i] T_i(a) for a Chebyshev series of deg1 = 2^B terms
+ * (1 <= B <= 15), the evaluation behind the Chebyshev comparator (section
+ * 2.2): Paterson-Stockmeyer in the Chebyshev basis with 2^ceil(B/2) baby
+ * steps, brought to one level and combined with integer constants (one
+ * rescale, then + c_0) for every leaf of the division by the giant steps
+ * T_{2^ceil(B/2) 2^r}.  The slots of a must lie in [-1, 1].  Consumes B + 1
+ * levels (CKR_E_DEPTH if a has fewer); coeffs is borrowed for the call; a
+ * length that is not a power of two is CKR_E_INVALID. */
+ckr_status ckr_op_cheb_eval(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, const double *coeffs,
+                            uint32_t deg1, ckr_ct **out);
 ckr_status ckr_op_add(ckr_context *ctx, const ckr_ct *a, const ckr_ct *b, ckr_ct **out);
 ckr_status ckr_op_sub(ckr_context *ctx, const ckr_ct *a, const ckr_ct *b, ckr_ct **out);
 ckr_status ckr_op_rescale(ckr_context *ctx, const ckr_ct *a, ckr_ct **out);

@@ -32,7 +32,7 @@ class Params(C.Structure):
 
 
 class Sign(C.Structure):
-    _fields_ = [("d_g", C.c_uint8), ("d_f", C.c_uint8)]
+    _fields_ = [("d_g", C.c_uint8), ("d_f", C.c_uint8), ("cheb", C.c_uint8)]
 
 
 class Query(C.Structure):
@@ -84,6 +84,7 @@ _SIGS = {
     "ckr_ct_free": (None, [vp]),
     "ckr_op_rotate": (C.c_int, [vp, vp, vp, C.c_int64, C.POINTER(vp)]),
     "ckr_op_mul": (C.c_int, [vp, vp, vp, vp, C.POINTER(vp)]),
+    "ckr_op_cheb_eval": (C.c_int, [vp, vp, vp, dblp, C.c_uint32, C.POINTER(vp)]),
     "ckr_op_add": (C.c_int, [vp, vp, vp, C.POINTER(vp)]),
     "ckr_op_sub": (C.c_int, [vp, vp, vp, C.POINTER(vp)]),
     "ckr_op_rescale": (C.c_int, [vp, vp, C.POINTER(vp)]),
@@ -139,7 +140,8 @@ def _p(a, t):
 
 
 def sign(cmp):
-    return Sign(int(cmp[0]), int(cmp[1]))
+    """(d_g, d_f) for the f/g composite, (0, 0, D) for the Chebyshev comparator of D levels"""
+    return Sign(int(cmp[0]), int(cmp[1]), int(cmp[2]) if len(cmp) > 2 else 0)
 
 
 # ---- host-only helpers ------------------------------------------------------
@@ -346,6 +348,11 @@ class Context:
 
     def mul(self, keys, a, b):
         return self._unary(lib().ckr_op_mul, keys.h, a.h, b.h)
+
+    def cheb_eval(self, keys, a, coeffs):
+        """sum_i coeffs[i] T_i(a) by Paterson-Stockmeyer (len(coeffs) a power of two)"""
+        c = np.ascontiguousarray(coeffs, np.float64)
+        return self._unary(lib().ckr_op_cheb_eval, keys.h, a.h, _p(c, dblp), len(c))
 
     def add(self, a, b):
         return self._unary(lib().ckr_op_add, a.h, b.h)

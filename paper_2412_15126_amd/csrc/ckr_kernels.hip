@@ -680,6 +680,45 @@ void k_mul_scalar(const DevTables &T, u64 *out, const u64 *a, int limbs, int pol
     hipLaunchKernelGGL(ew_mul_scalar, ew_grid(T.logn, limbs * polys), dim3(256), 0, s, out, a, limbs, so, sa, map,
                        T.logn, T.mq, c);
 }
+// one thread per coefficient position of one limb of one polynomial: the nt
+// term values are loaded once and every output's combination is accumulated
+// lazily in [0, 2q); the constants are uniform across the workgroup.
+template <int NT>
+__global__ void __launch_bounds__(256) ew_lincomb(const LinComb a, const double2 *__restrict__ kt, int logn,
+                                                  const double2 *__restrict__ mq) {
+    const size_t n = (size_t)1 << logn;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int t = blockIdx.y, pb = blockIdx.z;  // limb; batch entry * 2 + polynomial
+    const double q = mq[t].x, two_q = 2.0 * q;
+    const size_t entry = (size_t)2 * a.limbs * n;
+    const size_t off = (size_t)(pb >> 1) * entry + (size_t)(pb & 1) * a.limbs * n + (size_t)t * n + i;
+    double x[NT];
+#pragma unroll
+    for (int j = 0; j < NT; j++) x[j] = j < a.nt ? u2d(a.term[j][off]) : 0.0;
+    for (int o = 0; o < a.nout; o++) {
+        const double2 *kk = kt + (size_t)o * a.nt * a.limbs + t;
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < NT; j++) {
+            if (j < a.nt) {
+                const double2 w = kk[(size_t)j * a.limbs];
+                acc += mm_lazy(x[j], w.x, w.y, q);
+                acc = acc >= two_q ? acc - two_q : acc;
+            }
+        }
+        a.out[(size_t)o * a.B * entry + off] = d2u(red1(acc, q));
+    }
+}
+
+void k_lincomb(const DevTables &T, const LinComb &a, hipStream_t s) {
+    const dim3 grid((unsigned)(((1u << T.logn) + 255) / 256), (unsigned)a.limbs, (unsigned)(2 * a.B));
+    if (a.nt <= 8) hipLaunchKernelGGL(ew_lincomb<8>, grid, dim3(256), 0, s, a, a.k, T.logn, T.mq);
+    else if (a.nt <= 16) hipLaunchKernelGGL(ew_lincomb<16>, grid, dim3(256), 0, s, a, a.k, T.logn, T.mq);
+    else if (a.nt <= 32) hipLaunchKernelGGL(ew_lincomb<32>, grid, dim3(256), 0, s, a, a.k, T.logn, T.mq);
+    else hipLaunchKernelGGL(ew_lincomb<64>, grid, dim3(256), 0, s, a, a.k, T.logn, T.mq);
+}
+
 void k_mul_pt(const DevTables &T, u64 *out, const u64 *a, const u64 *pt, int limbs, int polys, size_t so, size_t sa,
               LimbMap map, bool add, hipStream_t s) {
     hipLaunchKernelGGL(ew_mul_pt, ew_grid(T.logn, limbs * polys), dim3(256), 0, s, out, a, pt, limbs, so, sa, map,

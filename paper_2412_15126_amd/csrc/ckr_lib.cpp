@@ -230,6 +230,7 @@ struct Ctx {
     std::map<std::pair<int, int>, BConvTab> modup;  // (level, digit)
     std::map<int, BConvTab> moddown;                // level
     std::map<PlainKey, Buf> plain;                  // encoded plaintexts, eval domain
+    std::map<std::vector<u64>, Buf> lincomb;        // Chebyshev linear-combination constants
     std::mutex mu;
     std::recursive_mutex mu_run;  // held while enqueueing work: API calls vs. server workers
     size_t n() const { return P.n; }
@@ -281,8 +282,10 @@ struct GraphPlan {
 // and tie-correction flag, comparator and indicator compositions
 struct Spec {
     int kind = 0, N = 0, k = 0, tie = 0;
-    ckr_sign cmp{0, 0}, ind{0, 0};
-    auto tup() const { return std::make_tuple(kind, N, k, tie, cmp.d_g, cmp.d_f, ind.d_g, ind.d_f); }
+    ckr_sign cmp{0, 0, 0}, ind{0, 0, 0};
+    auto tup() const {
+        return std::make_tuple(kind, N, k, tie, cmp.d_g, cmp.d_f, cmp.cheb, ind.d_g, ind.d_f, ind.cheb);
+    }
 };
 // a group of B inputs of one level running one circuit
 struct GroupKey {
@@ -972,12 +975,238 @@ static DCt poly7(Ctx &C, const Keys &K, const DCt &x, const double a[4]) {
     return ev_add(C, s1, v1, false);
 }
 
-// a * (f^{d_f}(g^{d_g}(D)) + 1) / 2 with the factor a/2 folded into the last
-// polynomial and a/2 added as a constant
+// ------------------------------------------------------------------------
+// Chebyshev comparator (section 2.2): the comparison function as a function
+// of d = x - y, interpolated at the 2^(D-1) Chebyshev nodes of [-1, 1] and
+// evaluated by the Paterson-Stockmeyer algorithm in the Chebyshev basis.
+// For sum_{i < 2^B} c_i T_i(x): k = 2^l baby steps (l = ceil(B/2)) and
+// m = B - l giant steps,
+//   T_1 = x, T_{2j} = 2 T_j^2 - 1, T_{2j+1} = 2 T_j T_{j+1} - T_1,
+//   G_0 = T_k, G_r = 2 G_{r-1}^2 - 1,
+// and p = q G_{r-1} + s recursively (Chebyshev division by T_K, K = k 2^(r-1):
+// q_0 = c_K, q_j = 2 c_{K+j}, s_0 = c_0, s_i = c_i - c_{2K-i}) down to
+// polynomials of degree < k, each a linear combination of the baby steps
+// brought to one level (integer constants, one rescale, then + c_0).  x at
+// level L leaves at level L - B - 1.
+//
+// On the GPU every stage runs batched: the baby steps of one level form one
+// product batch, all 2^m linear combinations are one fused kernel over the
+// baby steps, and each level of the division tree is one product batch.
+// The leaves are ordered so that the tree folds by halves: leaf index =
+// sum_r choice_r 2^(m-r), choice_r = 0 for the quotient, 1 for the
+// remainder of the split at tree level r (r = m at the root).
+// ------------------------------------------------------------------------
+constexpr int kChebMaxDepth = 16;
+constexpr int kChebChunk = 256;  // batch entries per product launch in the Chebyshev evaluation
+
+static int cmp_levels(ckr_sign c) { return c.cheb ? c.cheb : 3 * (c.d_g + c.d_f); }
+
+static void cheb_split(const std::vector<double> &c, int k, int r, int m, int idx,
+                       std::vector<std::vector<double>> &leaves) {
+    if (r == 0) {
+        leaves[idx] = c;
+        return;
+    }
+    const int K = k << (r - 1);
+    std::vector<double> q(K), s(K);
+    q[0] = c[K];
+    s[0] = c[0];
+    for (int j = 1; j < K; j++) {
+        q[j] = 2.0 * c[K + j];
+        s[j] = c[j] - c[2 * K - j];
+    }
+    cheb_split(q, k, r - 1, m, idx, leaves);
+    cheb_split(s, k, r - 1, m, idx + (1 << (m - r)), leaves);
+}
+
+// per-limb constants of the linear combinations: [leaf][term][limb] at level lb
+static const Buf &lincomb_table(Ctx &C, const std::vector<std::vector<double>> &leaves, const std::vector<int> &terms,
+                                int lb) {
+    std::vector<u64> key;
+    key.push_back((u64)lb);
+    for (int i : terms) key.push_back((u64)i);
+    for (const auto &lf : leaves)
+        for (int i : terms) {
+            u64 b;
+            std::memcpy(&b, &lf[i], 8);
+            key.push_back(b);
+        }
+    {
+        std::lock_guard<std::mutex> g(C.mu);
+        auto it = C.lincomb.find(key);
+        if (it != C.lincomb.end()) return it->second;
+    }
+    const int t = lb - 1, limbs = lb + 1;
+    std::vector<double2> tab(leaves.size() * terms.size() * limbs);
+    size_t w = 0;
+    for (const auto &lf : leaves)
+        for (int i : terms) {
+            const i64 K = std::llround(((lf[i] * C.P.scale[t]) * (double)C.P.mod[t + 1]) / C.P.scale[lb]);
+            for (int l = 0; l < limbs; l++) {
+                const u64 q = C.P.mod[l], v = hred(K, q);
+                tab[w++] = double2{(double)v, (double)v / (double)q};
+            }
+        }
+    Buf b(&C, tab.size() * 2);
+    HIPCHK(hipMemcpyAsync(b.get(), tab.data(), tab.size() * sizeof(double2), hipMemcpyHostToDevice, C.stream));
+    HIPCHK(hipStreamSynchronize(C.stream));  // tab goes out of scope
+    std::lock_guard<std::mutex> g(C.mu);
+    return C.lincomb.emplace(std::move(key), std::move(b)).first->second;
+}
+
+// x brought to `level` (none of the work when it is already there)
+static const DCt &aligned(Ctx &C, const DCt &x, int level, DCt &store) {
+    if (x.level == level) return x;
+    store = ev_cmul_to(C, x, 1.0, level);
+    return store;
+}
+
+// pairs (a_i, b_i) multiplied, doubled and reduced by s_i (nullptr: by 1),
+// in product launches of at most kChebChunk entries; every a_i, b_i at one level
+static std::vector<DCt> cheb_steps(Ctx &C, const Keys &K, const std::vector<const DCt *> &a,
+                                   const std::vector<const DCt *> &b, const DCt *s) {
+    std::vector<DCt> out;
+    const int B = a[0]->B;
+    const int per = std::max(1, kChebChunk / B);
+    for (size_t c0 = 0; c0 < a.size(); c0 += per) {
+        const size_t c1 = std::min(a.size(), c0 + per);
+        std::vector<const DCt *> la(a.begin() + c0, a.begin() + c1), lb(b.begin() + c0, b.begin() + c1);
+        DCt P = ev_mul_int(C, ev_mul(C, K, stack(C, la), stack(C, lb)), 2);
+        DCt sub;
+        if (s) {
+            DCt sa;
+            const DCt &S = aligned(C, *s, P.level, sa);
+            std::vector<const DCt *> rep(c1 - c0, &S);
+            sub = ev_add(C, P, stack(C, rep), true);
+        } else {
+            sub = ev_add_const(C, P, -1.0);
+        }
+        for (size_t i = 0; i < c1 - c0; i++) out.push_back(slice(C, sub, (int)i * B, B));
+    }
+    return out;
+}
+
+static DCt cheb_eval(Ctx &C, const Keys &K, const DCt &x, const std::vector<double> &c) {
+    const int deg1 = (int)c.size();
+    int Bd = 0;
+    while ((1 << Bd) < deg1) Bd++;
+    if (deg1 < 2 || (1 << Bd) != deg1 || Bd + 1 > kChebMaxDepth)
+        throw Error{CKR_E_INVALID, "Chebyshev series length must be a power of two in [2, 2^15]"};
+    if (x.level < Bd + 1) throw Error{CKR_E_DEPTH, "not enough levels for the Chebyshev series"};
+    const int l = (Bd + 1) / 2, m = Bd - l, k = 1 << l, top = m > 0 ? k : k - 1, B = x.B;
+    const int lb = x.level - l;
+
+    // division tree and the baby steps its leaves use (T_1 always)
+    std::vector<std::vector<double>> leaves((size_t)1 << m);
+    cheb_split(c, k, m, m, 0, leaves);
+    std::vector<int> terms{1};
+    for (int i = 2; i < k; i++)
+        for (const auto &lf : leaves)
+            if (lf[i] != 0.0) {
+                terms.push_back(i);
+                break;
+            }
+    if ((int)terms.size() > kMaxLinTerms) throw Error{CKR_E_INVALID, "too many baby steps"};
+
+    // baby steps by level: T_j for j in (2^(r-1), 2^r] from operands at level x.level - (r-1)
+    std::vector<DCt> T(top + 1);
+    std::vector<const DCt *> Tp(top + 1, nullptr);
+    Tp[1] = &x;
+    for (int r = 1; r <= l; r++) {
+        const int lo = std::max(2, (1 << (r - 1)) + 1), hi = std::min(1 << r, top);
+        if (lo > hi) continue;
+        const int lev = x.level - (r - 1);
+        std::map<int, DCt> al;
+        auto op = [&](int i) -> const DCt * {
+            if (Tp[i]->level == lev) return Tp[i];
+            auto it = al.find(i);
+            if (it == al.end()) it = al.emplace(i, ev_cmul_to(C, *Tp[i], 1.0, lev)).first;
+            return &it->second;
+        };
+        std::vector<int> odd, even;
+        for (int j = lo; j <= hi; j++) (j & 1 ? odd : even).push_back(j);
+        for (int pass = 0; pass < 2; pass++) {
+            const std::vector<int> &js = pass == 0 ? odd : even;
+            if (js.empty()) continue;
+            std::vector<const DCt *> a, b;
+            for (int j : js) {
+                a.push_back(op(j / 2));
+                b.push_back(op(pass == 0 ? j / 2 + 1 : j / 2));
+            }
+            std::vector<DCt> res = cheb_steps(C, K, a, b, pass == 0 ? &x : nullptr);
+            for (size_t i = 0; i < js.size(); i++) {
+                T[js[i]] = std::move(res[i]);
+                Tp[js[i]] = &T[js[i]];
+            }
+        }
+    }
+
+    // the used baby steps at level lb, then every leaf combination in one kernel
+    std::vector<DCt> Tb(k);
+    LinComb lc{};
+    lc.nt = (int)terms.size();
+    lc.nout = (int)leaves.size();
+    lc.limbs = lb + 1;
+    lc.B = B;
+    for (int i = 0; i < lc.nt; i++) {
+        const int ti = terms[i];
+        const DCt &src = aligned(C, *Tp[ti], lb, Tb[ti]);
+        lc.term[i] = src.d();
+    }
+    DCt Y = ct_new(C, lb, lc.nout * B);
+    lc.out = Y.d();
+    lc.k = (const double2 *)lincomb_table(C, leaves, terms, lb).get();
+    timed(C, kElem, 8.0 * (lc.nt + lc.nout) * 2.0 * lc.limbs * C.n() * B, [&] { k_lincomb(C.T, lc, C.stream); });
+    Y = ev_rescale(C, Y);
+    const size_t W = (size_t)2 * (Y.level + 1) * C.n();
+    for (int j = 0; j < lc.nout; j++) {
+        LimbScalars cs;
+        scalars_of(C, std::llround(leaves[j][0] * C.P.scale[Y.level]), Y.level + 1, plain_map(), cs);
+        timed(C, kElem, 16.0 * (Y.level + 1) * C.n() * B, [&] {
+            k_add_scalar(C.T, Y.d() + (size_t)j * B * W, Y.level + 1, B, W, plain_map(), cs, C.stream);
+        });
+    }
+    if (m == 0) return Y;
+
+    // giant steps, then the division tree level by level
+    std::vector<DCt> G(m);
+    G[0] = std::move(T[k]);
+    for (int r = 1; r < m; r++) G[r] = std::move(cheb_steps(C, K, {&G[r - 1]}, {&G[r - 1]}, nullptr)[0]);
+    T.clear();
+    Tb.clear();
+    for (int r = 1; r <= m; r++) {
+        const int h = 1 << (m - r);  // parents at this level
+        DCt ga;
+        const DCt &Ga = aligned(C, G[r - 1], Y.level, ga);
+        std::vector<DCt> prods;
+        const int per = std::max(1, kChebChunk / B);
+        for (int p0 = 0; p0 < h; p0 += per) {
+            const int cnt = std::min(per, h - p0);
+            std::vector<const DCt *> rep(cnt, &Ga);
+            prods.push_back(ev_mul(C, K, slice(C, Y, p0 * B, cnt * B), stack(C, rep)));
+        }
+        std::vector<const DCt *> pp;
+        for (const DCt &d : prods) pp.push_back(&d);
+        DCt P = prods.size() == 1 ? std::move(prods[0]) : stack(C, pp);
+        DCt S = ev_cmul_to(C, slice(C, Y, h * B, h * B), 1.0, P.level);
+        Y = ev_add(C, P, S, false);
+    }
+    return Y;
+}
+
+// a * Cmp on the difference D.  f/g composite: a * (f^{d_f}(g^{d_g}(D)) + 1) / 2
+// with the factor a/2 folded into the last polynomial and a/2 added as a
+// constant.  Chebyshev: the interpolant's coefficients times a.
 static DCt cmp_sign(Ctx &C, const Keys &K, const DCt &D, ckr_sign cmp, double a = 1.0) {
+    if (D.level < cmp_levels(cmp)) throw Error{CKR_E_DEPTH, "comparator depth"};
+    if (cmp.cheb) {
+        std::vector<double> c((size_t)1 << (cmp.cheb - 1));
+        cheb_step_coeffs(cmp.cheb, c.data());
+        for (double &v : c) v = v * a;
+        return cheb_eval(C, K, D, c);
+    }
     const int total = cmp.d_g + cmp.d_f;
     if (total < 1) throw Error{CKR_E_INVALID, "empty comparator"};
-    if (D.level < 3 * total) throw Error{CKR_E_DEPTH, "comparator depth"};
     DCt X;
     const DCt *cur = &D;
     for (int r = 0; r < total; r++) {
@@ -994,8 +1223,12 @@ static DCt cmp_sign(Ctx &C, const Keys &K, const DCt &D, ckr_sign cmp, double a 
 // Rank (Algorithm Rank), argmin (Order Statistic with k = 1 and the
 // tie-correction offset), Sorting
 // ------------------------------------------------------------------------
+static bool sign_valid(ckr_sign c) {
+    if (c.cheb) return c.d_g == 0 && c.d_f == 0 && c.cheb >= 2 && c.cheb <= kChebMaxDepth;
+    return c.d_g + c.d_f >= 1;
+}
 static void check_sign(ckr_sign c) {
-    if (c.d_g + c.d_f < 1) throw Error{CKR_E_INVALID, "empty comparator composition"};
+    if (!sign_valid(c)) throw Error{CKR_E_INVALID, "empty comparator composition or bad Chebyshev depth"};
 }
 
 static void check_N(const Ctx &C, u32 N) {
@@ -1003,15 +1236,15 @@ static void check_N(const Ctx &C, u32 N) {
 }
 
 // levels: TransR mask, comparator, SumR mask (+ E and E * tie mask with tie-correction)
-uint32_t rank_depth(ckr_sign c, int tie) { return 2 + 3 * (c.d_g + c.d_f) + (tie ? 2 : 0); }
+uint32_t rank_depth(ckr_sign c, int tie) { return 2 + cmp_levels(c) + (tie ? 2 : 0); }
 // order statistic k: TransR mask, comparator, [E, E * tie mask, SumR mask,
 // scaling,] indicator (+1 for the two-sided window), O * V, SumC mask
 uint32_t order_stat_depth(int N, int k, ckr_sign c, ckr_sign i, int tie) {
-    return 1 + 3 * (c.d_g + c.d_f) + (tie ? 4 : 0) + 3 * (i.d_g + i.d_f) + ((k > 1 && k < N) ? 1 : 0) + 2;
+    return 1 + cmp_levels(c) + (tie ? 4 : 0) + cmp_levels(i) + ((k > 1 && k < N) ? 1 : 0) + 2;
 }
 uint32_t argmin_depth(ckr_sign c, ckr_sign i) { return order_stat_depth(2, 1, c, i, 1); }
 // rank, scaling, indicator, indicator product, M * V_R, SumC mask, TransC mask
-uint32_t sort_depth(ckr_sign c, ckr_sign i) { return rank_depth(c, 0) + 5 + 3 * (i.d_g + i.d_f); }
+uint32_t sort_depth(ckr_sign c, ckr_sign i) { return rank_depth(c, 0) + 5 + cmp_levels(i); }
 
 // C = Cmp(V_R, V_C): C[i][j] = Cmp(v_j, v_i)
 static DCt cmp_matrix(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, DCt *VR_out = nullptr,
@@ -1056,7 +1289,7 @@ static DCt tie_rank(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp) {
 // column-wise:
 //   R_i = TransC(SumC((i - 1) - sum_{j<i} C_{j,i})) + SumR(sum_{j>=i} C_{i,j}) + 1/2
 // (1-based i), the SumR term brought down to the TransC term's level.
-uint32_t rank_multi_depth(ckr_sign c) { return 3 + 3 * (c.d_g + c.d_f); }
+uint32_t rank_multi_depth(ckr_sign c) { return 3 + cmp_levels(c); }
 constexpr int kPairChunk = 32;
 
 static DCt rank_multi(Ctx &C, const Keys &K, const DCt &Bk, int b, ckr_sign cmp) {
@@ -1104,7 +1337,7 @@ static DCt rank_multi(Ctx &C, const Keys &K, const DCt &Bk, int b, ckr_sign cmp)
 // block i and source block j, M_{i,j} = Ind_0(ReplR(R_j) - (b(i-1)+1 || ... || b i))
 // with Ind_0(x) = Cmp(x, -1/2) (1 - Cmp(x, 1/2)) on (x +- 1/2)/N, all L^2
 // indicators in one batched comparator pass; S_i = TransC(SumC(sum_j M_{i,j} ReplR(B_j))).
-uint32_t sort_multi_depth(ckr_sign c, ckr_sign i) { return rank_multi_depth(c) + 5 + 3 * (i.d_g + i.d_f); }
+uint32_t sort_multi_depth(ckr_sign c, ckr_sign i) { return rank_multi_depth(c) + 5 + cmp_levels(i); }
 
 static DCt sort_multi(Ctx &C, const Keys &K, const DCt &Bk, int b, ckr_sign cmp, ckr_sign ind) {
     check_N(C, (u32)b);
@@ -1248,7 +1481,7 @@ static Spec spec_of(const Ctx &C, int kind, int N, int k, int tie, ckr_sign cmp,
     } else {
         throw Error{CKR_E_INVALID, "unknown circuit kind"};
     }
-    if (s.cmp.d_g + s.cmp.d_f < 1 || (s.kind != kRankCircuit && s.ind.d_g + s.ind.d_f < 1))
+    if (!sign_valid(s.cmp) || (s.kind != kRankCircuit && !sign_valid(s.ind)))
         throw Error{CKR_E_INVALID, "empty comparator"};
     return s;
 }
@@ -2322,6 +2555,14 @@ ckr_status ckr_op_mul(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, c
         NEED(ctx && keys && a && b && out);
         std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         *out = wrap(*ctx->C, ev_mul(*ctx->C, *keys->K, a->ct, b->ct));
+    });
+}
+ckr_status ckr_op_cheb_eval(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, const double *coeffs,
+                            uint32_t deg1, ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && keys && a && coeffs && out);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
+        *out = wrap(*ctx->C, cheb_eval(*ctx->C, *keys->K, a->ct, std::vector<double>(coeffs, coeffs + deg1)));
     });
 }
 ckr_status ckr_op_add(ckr_context *ctx, const ckr_ct *a, const ckr_ct *b, ckr_ct **out) {

@@ -253,6 +253,25 @@ static void dif(std::vector<cq> &x, int logn, const FftTables &T, bool conj) {
     }
 }
 
+// With n = 2^(D-1) nodes x_j = cos(pi (j + 1/2) / n), the interpolation
+// coefficient is c_k = (2/n) sum_{x_j > 0} cos(k pi (j + 1/2) / n) (halved for
+// k = 0); the positive nodes are j < n/2, and the cosine sum over them is
+// sin(k pi / 2) / (2 sin(k pi / 2n)): zero for even k > 0, and for odd k
+// c_k = (-1)^((k-1)/2) / (n sin(k pi / 2n)).
+void cheb_step_coeffs(int D, double *c) {
+    const long n = 1L << (D - 1);
+    c[0] = 0.5;
+    for (long k = 1; k < n; k++) {
+        if (k % 2 == 0) {
+            c[k] = 0.0;
+            continue;
+        }
+        const __float128 s = sinq(M_PIq * (__float128)k / (__float128)(2 * n));
+        const __float128 sign = ((k - 1) / 2) % 2 ? -1 : 1;
+        c[k] = (double)(sign / ((__float128)n * s));
+    }
+}
+
 bool encode_slots(int logn, const double *z, u32 count, double scale, i64 *m) {
     const FftTables &T = tables(logn);
     const u64 n = 1ull << logn;

@@ -66,4 +66,10 @@ bool encode_slots(int logn, const double *z, u32 count, double scale, i64 *m);
 // real parts of slots [0, count) of the polynomial m / scale
 void decode_slots(int logn, const i64 *m, double scale, u32 count, double *z);
 
+// ---- Chebyshev interpolant of the comparison function (binary128) ----
+// c[0 .. 2^(D-1)): coefficients of the degree 2^(D-1) - 1 interpolant, at the
+// 2^(D-1) Chebyshev nodes of [-1, 1], of the function that is 1 for d > 0
+// and 0 for d < 0
+void cheb_step_coeffs(int D, double *c);
+
 }  // namespace ckr

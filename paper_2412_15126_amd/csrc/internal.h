@@ -97,6 +97,19 @@ void k_add_scalar(const DevTables &T, u64 *data, int limbs, int polys, size_t st
 // out[p][t] = a[p][t] * c[t]
 void k_mul_scalar(const DevTables &T, u64 *out, const u64 *a, int limbs, int polys, size_t stride_o, size_t stride_a,
                   LimbMap map, const LimbScalars &c, hipStream_t s);
+// Linear combinations with integer constants of nt ciphertext batches of one
+// level (limbs q_0 .. q_{limbs-1}), B entries each:
+//   out[o][b] = sum_i K[o][i] * term[i][b]   (mod q_t, every limb t),
+// out laid out [nout][B][2][limbs][n].  K is given per limb as
+// k[(o * nt + i) * limbs + t] = (K mod q_t, (K mod q_t) / q_t).
+constexpr int kMaxLinTerms = 64;
+struct LinComb {
+    const u64 *term[kMaxLinTerms];
+    u64 *out = nullptr;
+    const double2 *k = nullptr;
+    int nt = 0, nout = 0, limbs = 0, B = 0;
+};
+void k_lincomb(const DevTables &T, const LinComb &a, hipStream_t s);
 // out[p][t] = a[p][t] (*|+) pt[t]
 void k_mul_pt(const DevTables &T, u64 *out, const u64 *a, const u64 *pt, int limbs, int polys, size_t stride_o,
               size_t stride_a, LimbMap map, bool add, hipStream_t s);
