@@ -170,9 +170,28 @@ def sort512_p17s_multi():
             "sorted": [float(x) for x in np.sort(v)]}
 
 
+def rank128_p16_cheb():
+    """rank of N = 128 at n = 2^16 with the Chebyshev comparator of 12 levels"""
+    N = 128
+    cmp = W.CHEB_CMP[N]
+    O.set_threads(min(16, os.cpu_count() or 1))
+    P = O.Params(**W.PSETS["P16"])
+    level = O.rank_depth(*cmp)
+    v, kseed, eseed = W.rank_workload(N, 2.0 ** -10, 0)
+    K = O.Keys(P, kseed, level, P.rank_galois(N))
+    R = O.rank(K, O.encrypt(K, v, level, eseed), N, *cmp)
+    return {"_what": "oracle rank of N=128 at n=2^16 (P16), workload seed 0, encryption level 14, Chebyshev "
+                     "comparator of degree 2^11 - 1 (12 levels): sha256 of the exported output ciphertext and its "
+                     "decoded ranks",
+            "level": level,
+            "sha256": hashlib.sha256(R.export().tobytes()).hexdigest(),
+            "decoded": [float(x) for x in O.decrypt(K, R, N)],
+            "exact": [int(x) for x in np.argsort(np.argsort(v)) + 1]}
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["rank128_p16", "argmin128_p17", "sort128_p17", "mixed_p16d", "argmax128_p17o",
-                             "rank512_p16_multi", "sort512_p17s_multi"]
+                             "rank512_p16_multi", "sort512_p17s_multi", "rank128_p16_cheb"]
     for name in which:
         json.dump(globals()[name](), open(os.path.join(HERE, name + ".json"), "w"), indent=1)
         print("wrote", name + ".json", flush=True)

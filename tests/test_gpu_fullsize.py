@@ -96,3 +96,29 @@ def test_rank128_four_compositions_is_not_enough(full):
             f"exact {sum(e < 0.5 for e in errs[cmp])}/32")
     assert max(errs[(4, 1)]) < 0.45
     assert max(errs[(3, 1)]) > 0.5
+
+
+def test_rank128_chebyshev_full_size_matches_golden(full):
+    """The paper's comparator for rank (Chebyshev, degree 2^11 - 1, 12
+    levels) at the bench's shape: a batch of 32 queries in one captured graph,
+    query 0 against the oracle-written digest, all ranks exact."""
+    gold = json.load(open(os.path.join(os.path.dirname(GOLD), "rank128_p16_cheb.json")))
+    cmp = W.CHEB_CMP[N]
+    ctx = full["ctx"]
+    level = gold["level"]
+    assert level == ctx_rank_depth(cmp)
+    say("[gpu] P16 device keygen at level 14")
+    gk = ctx.keygen(W.rank_workload(N, 2.0 ** -10, 0)[1], level, [N])   # keys depend on their top level
+    qs = [(full["v"], full["eseed"])] + [W.rank_workload(N, 2.0 ** -10, 300 + i)[::2] for i in range(31)]
+    cts = [ctx.encrypt(gk, v, level, e) for v, e in qs]
+    for rep in range(2):     # eager, then captured
+        say(f"[gpu] P16 rank-128 chebyshev batch of 32, pass {rep}")
+        outs = ctx.run_batch(gk, "rank", cts, N, cmp)
+        assert hashlib.sha256(outs[0].export().tobytes()).hexdigest() == gold["sha256"]
+    for (v, _), o in zip(qs, outs):
+        assert np.array_equal(np.round(ctx.decrypt(gk, o, N)), np.argsort(np.argsort(v)) + 1)
+
+
+def ctx_rank_depth(cmp):
+    import paper_2412_15126_amd as ckr
+    return ckr.rank_depth(cmp)
