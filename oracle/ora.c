@@ -1187,6 +1187,18 @@ static ora_ct *cmp_sign_scaled(const ora_keys *Kp, const ora_ct *D, ora_cmp cm, 
     return X;
 }
 
+/* A Chebyshev indicator of degree 2^(D-1) - 1 grows like cosh(n y / sqrt(1 - x^2))
+ * at x + iy: the imaginary parts its argument inherits (the comparator's
+ * slope amplifies the slots' imaginary noise) must be removed first.  x is
+ * projected onto its real part as x + conj(x), conj = sigma_{2n-1}, with the
+ * factor 1/2 folded into the scaling that precedes it. */
+static ora_ct *plus_conj(const ora_keys *Kp, const ora_ct *x, int *st) {
+    ora_ct *c = ora_apply_galois(Kp, x, (u32)(2 * x->P->n - 1), st);
+    ora_ct *r = ora_add(x, c);
+    ora_ct_free(c);
+    return r;
+}
+
 ora_ct *ora_cmp_sign(const ora_keys *Kp, const ora_ct *D, ora_cmp cm, int *st) {
     return cmp_sign_scaled(Kp, D, cm, 1.0, st);
 }
@@ -1328,7 +1340,8 @@ int ora_sort_multi(const ora_keys *Kp, ora_ct *const *Bk, u32 L, u32 b, ora_cmp 
         ora_ct *acc = NULL;
         for (u32 j = 0; j < L; j++) {
             ora_ct *X = ora_add_plain(RR[j], steps, b * b, &st);
-            ora_ct *Xs = ora_cmul_to(X, 1.0 / dN, X->level - 1, &st);
+            ora_ct *Xs = ora_cmul_to(X, ci.cheb > 0 ? 0.5 / dN : 1.0 / dN, X->level - 1, &st);
+            if (ci.cheb > 0) replace(&Xs, plus_conj(Kp, Xs, &st));
             ora_ct *d1 = ora_add_const(Xs, 0.5 / dN);
             ora_ct *d2 = ora_add_const(Xs, -0.5 / dN);
             ora_ct *c1 = ora_cmp_sign(Kp, d1, ci, &st);
@@ -1396,8 +1409,9 @@ ora_ct *ora_mul_int(const ora_ct *a, i64 K) { return mul_int(a, K); }
  * row 0).  onehot = MaskR(O, 0); value = SumC(O * V) in slot 0. */
 int ora_order_stat_depth(u32 N, u32 k, ora_cmp cm, ora_cmp ci, int tie) {
     int ind = cmp_levels(ci) + ((k > 1 && k < N) ? 1 : 0);
-    /* TransR mask, comparator, [E, E*mask, SumR mask, scaling,] indicator, O*V, SumC mask */
-    return 1 + cmp_levels(cm) + (tie ? 4 : 0) + ind + 2;
+    /* TransR mask, comparator, [E, E*mask, SumR mask, scaling,] indicator, O*V, SumC mask;
+     * without tie-correction a Chebyshev indicator keeps the SumR mask */
+    return 1 + cmp_levels(cm) + (tie ? 4 : 0) + ((!tie && ci.cheb > 0) ? 1 : 0) + ind + 2;
 }
 
 int ora_argmin_depth(ora_cmp cm, ora_cmp ci) { return ora_order_stat_depth(2, 1, cm, ci, 1); }
@@ -1440,24 +1454,34 @@ int ora_order_stat(const ora_keys *Kp, const ora_ct *V, u32 N, u32 k, ora_cmp cm
     if (k < 1 || k > N) return ORA_E_INVALID;
     if (V->level < ora_order_stat_depth(N, k, cm, ci, tie)) return ORA_E_DEPTH;
     const double dN = (double)N, dk = (double)k;
+    /* a Chebyshev indicator takes the real part of its argument (plus_conj),
+     * the 1/2 folded into the scaling; without tie-correction its argument
+     * also keeps the SumR row mask, so that every slot lies in [-1, 1] */
+    const int proj = ci.cheb > 0;
+    const double sN = proj ? 2.0 * dN : dN;
     ora_ct *base; /* k_j (times +-1/N) */
     double off1, off2 = 0.0; /* constants giving the indicator argument(s) */
     if (tie) {
         ora_ct *kv = tie_rank(Kp, V, N, cm, &st);
-        base = ora_cmul_to(kv, k == 1 ? -1.0 / dN : 1.0 / dN, kv->level - 1, &st);
+        base = ora_cmul_to(kv, k == 1 ? -1.0 / sN : 1.0 / sN, kv->level - 1, &st);
         if (k == 1) off1 = 1.5 / dN;
         else if (k == N) off1 = (0.5 - dN) / dN;
         else off1 = (0.5 - dk) / dN, off2 = (-0.5 - dk) / dN;
         ora_ct_free(kv);
     } else {
-        ora_ct *C = cmp_matrix_scaled(Kp, V, N, cm, k == 1 ? -1.0 / dN : 1.0 / dN, &st);
-        base = ct_copy(C);
-        for (int i = 0; i < ilog2(N); i++) replace(&base, add_rot(Kp, base, (i64)N << i, &st));
+        ora_ct *C = cmp_matrix_scaled(Kp, V, N, cm, k == 1 ? -1.0 / sN : 1.0 / sN, &st);
+        if (proj) {
+            base = ora_sum_r(Kp, C, N, &st);
+        } else {
+            base = ct_copy(C);
+            for (int i = 0; i < ilog2(N); i++) replace(&base, add_rot(Kp, base, (i64)N << i, &st));
+        }
         if (k == 1) off1 = 1.0 / dN;
         else if (k == N) off1 = (1.0 - dN) / dN;
         else off1 = (1.0 - dk) / dN, off2 = -dk / dN;
         ora_ct_free(C);
     }
+    if (proj) replace(&base, plus_conj(Kp, base, &st));
     ora_ct *O;
     if (k == 1 || k == N) {
         ora_ct *y = ora_add_const(base, off1);
@@ -1509,7 +1533,8 @@ ora_ct *ora_sort(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, ora_cmp
         for (u32 j = 0; j < N; j++) steps[i * N + j] = -(double)(i + 1);
     ora_ct *X = ora_add_plain(RR, steps, N * N, &st);
     free(steps);
-    ora_ct *Xs = ora_cmul_to(X, 1.0 / (double)N, X->level - 1, &st);
+    ora_ct *Xs = ora_cmul_to(X, ci.cheb > 0 ? 0.5 / (double)N : 1.0 / (double)N, X->level - 1, &st);
+    if (ci.cheb > 0) replace(&Xs, plus_conj(Kp, Xs, &st));
     ora_ct *d1 = ora_add_const(Xs, 0.5 / (double)N);
     ora_ct *d2 = ora_add_const(Xs, -0.5 / (double)N);
     ora_ct *c1 = ora_cmp_sign(Kp, d1, ci, &st);
@@ -1545,5 +1570,6 @@ int ora_circuit_galois(const ora_params *P, u32 N, int what, u32 *out) {
         for (int k = 0; k < cnt; k++) if (out[k] == g) dup = 1;
         if (!dup) out[cnt++] = g;
     }
+    if (what & 6) out[cnt++] = (u32)(2 * P->n - 1); /* conjugation: real part of a Chebyshev indicator's argument */
     return cnt;
 }

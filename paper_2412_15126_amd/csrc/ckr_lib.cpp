@@ -817,9 +817,8 @@ static DCt ev_rotate(Ctx &C, const Keys &K, const DCt &a, i64 k) {
     return o;
 }
 
-// X + (X rotated left by k): the addition rides in the key switch's epilogue
-static DCt ev_rotate_add(Ctx &C, const Keys &K, const DCt &a, i64 k) {
-    const u32 g = galois_left(C, k);
+// X + sigma_g(X): the addition rides in the key switch's epilogue
+static DCt ev_galois_add(Ctx &C, const Keys &K, const DCt &a, u32 g) {
     if (g == 1) return ev_add(C, a, a, false);
     const Buf &key = find_key(K, g);
     const int l = a.level;
@@ -829,6 +828,16 @@ static DCt ev_rotate_add(Ctx &C, const Keys &K, const DCt &a, i64 k) {
     keyswitch(C, K, key, a.d() + L, 2 * L, l, a.B, o.d(), 2 * L, L, a.d(), 2 * L, L, 1, a.d(), 2 * L, L, 3, g);
     return o;
 }
+
+// X + (X rotated left by k)
+static DCt ev_rotate_add(Ctx &C, const Keys &K, const DCt &a, i64 k) { return ev_galois_add(C, K, a, galois_left(C, k)); }
+
+// A Chebyshev indicator of degree 2^(D-1) - 1 grows like cosh(n y / sqrt(1 - x^2))
+// at x + iy, and its argument inherits imaginary parts (the comparator's
+// slope amplifies the slots' imaginary noise): the argument is projected onto
+// its real part as X + conj(X), conj = sigma_{2n-1}, with the factor 1/2
+// folded into the scaling before it.
+static DCt ev_plus_conj(Ctx &C, const Keys &K, const DCt &a) { return ev_galois_add(C, K, a, (u32)(2 * C.n() - 1)); }
 
 // plaintext holding z on slots [0, count) at scale D_level, eval domain [level+1][n]
 enum PlainKind { kMaskRow0 = 1, kMaskCol0 = 2, kHalfRow0 = 3, kTieMask = 4, kSteps = 5, kNegHalfRow0 = 6,
@@ -1240,7 +1249,7 @@ uint32_t rank_depth(ckr_sign c, int tie) { return 2 + cmp_levels(c) + (tie ? 2 :
 // order statistic k: TransR mask, comparator, [E, E * tie mask, SumR mask,
 // scaling,] indicator (+1 for the two-sided window), O * V, SumC mask
 uint32_t order_stat_depth(int N, int k, ckr_sign c, ckr_sign i, int tie) {
-    return 1 + cmp_levels(c) + (tie ? 4 : 0) + cmp_levels(i) + ((k > 1 && k < N) ? 1 : 0) + 2;
+    return 1 + cmp_levels(c) + (tie ? 4 : 0) + ((!tie && i.cheb) ? 1 : 0) + cmp_levels(i) + ((k > 1 && k < N) ? 1 : 0) + 2;
 }
 uint32_t argmin_depth(ckr_sign c, ckr_sign i) { return order_stat_depth(2, 1, c, i, 1); }
 // rank, scaling, indicator, indicator product, M * V_R, SumC mask, TransC mask
@@ -1354,7 +1363,8 @@ static DCt sort_multi(Ctx &C, const Keys &K, const DCt &Bk, int b, ckr_sign cmp,
     for (int i = 0; i < L; i++) Xi.push_back(ev_add_plain(C, RR, get_plain(C, kStepsBlock, b, RR.level, i)));
     std::vector<const DCt *> xp;
     for (const DCt &x : Xi) xp.push_back(&x);
-    DCt Xs = ev_cmul_to(C, stack(C, xp), 1.0 / dN, RR.level - 1);
+    DCt Xs = ev_cmul_to(C, stack(C, xp), ind.cheb ? 0.5 / dN : 1.0 / dN, RR.level - 1);
+    if (ind.cheb) Xs = ev_plus_conj(C, K, Xs);
     DCt d1 = ev_add_const(C, Xs, 0.5 / dN), d2 = ev_add_const(C, Xs, -0.5 / dN);
     const int P = L * L;
     DCt cc = cmp_sign(C, K, stack(C, {&d1, &d2}), ind);
@@ -1395,21 +1405,27 @@ static void order_stat(Ctx &C, const Keys &K, const DCt &V, int N, int k, int ti
     if ((u32)V.level < order_stat_depth(N, k, cmp, ind, tie))
         throw Error{CKR_E_DEPTH, "not enough levels for the order statistic"};
     const double dN = (double)N, dk = (double)k;
+    // a Chebyshev indicator takes the real part of its argument (the 1/2 in
+    // the scaling); without tie-correction its argument keeps the SumR row
+    // mask, so that every slot lies in [-1, 1]
+    const bool proj = ind.cheb != 0;
+    const double sN = proj ? 2.0 * dN : dN;
     DCt base;  // k_j times -1/N (k = 1) or 1/N
     double off1, off2 = 0.0;
     if (tie) {
         DCt kv = tie_rank(C, K, V, N, cmp);
-        base = ev_cmul_to(C, kv, k == 1 ? -1.0 / dN : 1.0 / dN, kv.level - 1);
+        base = ev_cmul_to(C, kv, k == 1 ? -1.0 / sN : 1.0 / sN, kv.level - 1);
         if (k == 1) off1 = 1.5 / dN;
         else if (k == N) off1 = (0.5 - dN) / dN;
         else off1 = (0.5 - dk) / dN, off2 = (-0.5 - dk) / dN;
     } else {
-        DCt Cm = cmp_matrix(C, K, V, N, cmp, nullptr, k == 1 ? -1.0 / dN : 1.0 / dN);
-        base = rot_add_chain(C, K, Cm, 0, lg(N), [&](int i) { return (i64)N << i; });
+        DCt Cm = cmp_matrix(C, K, V, N, cmp, nullptr, k == 1 ? -1.0 / sN : 1.0 / sN);
+        base = proj ? sum_r(C, K, Cm, N) : rot_add_chain(C, K, Cm, 0, lg(N), [&](int i) { return (i64)N << i; });
         if (k == 1) off1 = 1.0 / dN;
         else if (k == N) off1 = (1.0 - dN) / dN;
         else off1 = (1.0 - dk) / dN, off2 = -dk / dN;
     }
+    if (proj) base = ev_plus_conj(C, K, base);
     DCt O;
     if (k == 1 || k == N) {
         O = cmp_sign(C, K, ev_add_const(C, base, off1), ind);
@@ -1437,7 +1453,8 @@ static DCt sort(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, ckr_si
     DCt R = rank(C, K, V, N, cmp, &VR);
     DCt RR = repl_r(C, K, R, N);
     DCt X = ev_add_plain(C, RR, get_plain(C, kSteps, N, RR.level));
-    DCt Xs = ev_cmul_to(C, X, 1.0 / (double)N, X.level - 1);
+    DCt Xs = ev_cmul_to(C, X, ind.cheb ? 0.5 / (double)N : 1.0 / (double)N, X.level - 1);
+    if (ind.cheb) Xs = ev_plus_conj(C, K, Xs);
     DCt d1 = ev_add_const(C, Xs, 0.5 / (double)N);
     DCt d2 = ev_add_const(C, Xs, -0.5 / (double)N);
     // both comparisons in one batched pass
@@ -2059,7 +2076,7 @@ static void gen_switch_key(Ctx &C, Keys &K, u32 g, const Buf &s_eval, const Buf 
     K.swk[g] = std::move(key);
 }
 
-static void add_rotation_keys(Ctx &C, Keys &K, const std::vector<i64> &shifts, const uint8_t *seed) {
+static void add_galois_keys(Ctx &C, Keys &K, const std::vector<u32> &gals, const uint8_t *seed) {
     const size_t n = C.n();
     const int Ek = K.Ek();
     const LimbMap emap{K.lmax + 1, 0, C.P.nq};
@@ -2071,13 +2088,18 @@ static void add_rotation_keys(Ctx &C, Keys &K, const std::vector<i64> &shifts, c
     HIPCHK(hipMemcpyAsync(s_eval.get(), sr.data(), sr.size() * 8, hipMemcpyHostToDevice, C.stream));
     ntt(C, s_eval.get(), Ek, 1, 0, emap, false);
     Buf sp(&C, sr.size());
-    for (i64 k : shifts) {
-        const u32 g = galois_left(C, k);
+    for (u32 g : gals) {
         if (g == 1 || K.swk.count(g)) continue;
         k_automorph(C.T, sp.get(), s_eval.get(), Ek, 1, 0, 0, g, C.stream);
         gen_switch_key(C, K, g, s_eval, sp, seed);
     }
     HIPCHK(hipStreamSynchronize(C.stream));
+}
+
+static void add_rotation_keys(Ctx &C, Keys &K, const std::vector<i64> &shifts, const uint8_t *seed) {
+    std::vector<u32> gals;
+    for (i64 k : shifts) gals.push_back(galois_left(C, k));
+    add_galois_keys(C, K, gals, seed);
 }
 
 static std::map<const Keys *, std::vector<uint8_t>> g_key_seed;  // seeds kept for later rotation keys
@@ -2144,6 +2166,8 @@ ckr_status ckr_keygen(ckr_context *ctx, const uint8_t seed[32], uint32_t max_lev
         std::vector<i64> shifts;
         for (size_t i = 0; i < nN; i++) circuit_shifts(Ns[i], what ? what : 1, shifts);
         add_rotation_keys(C, *K, shifts, seed);
+        // conjugation: the real part of a Chebyshev indicator's argument
+        if (nN && (what & 6)) add_galois_keys(C, *K, {(u32)(2 * C.n() - 1)}, seed);
         {
             std::lock_guard<std::mutex> g(g_key_seed_mu);
             g_key_seed[K.get()] = std::vector<uint8_t>(seed, seed + 32);

@@ -189,9 +189,31 @@ def rank128_p16_cheb():
             "exact": [int(x) for x in np.argsort(np.argsort(v)) + 1]}
 
 
+def argmin128_p17_cheb():
+    """tie-corrected argmin of N = 128 at n = 2^17, Chebyshev comparator and indicator of 12 levels each"""
+    N = 128
+    cmp = ind = W.CHEB_CMP[N]
+    O.set_threads(min(16, os.cpu_count() or 1))
+    P = O.Params(**W.PSETS["P17"])
+    level = O.order_stat_depth(N, 1, cmp, ind, True)
+    v, kseed, eseed = W.tied_workload(N, 0)
+    K = O.Keys(P, kseed, level, P.circuit_galois(N, 2))
+    oh, val = O.order_stat(K, O.encrypt(K, v, level, eseed), N, 1, cmp, ind, True)
+    return {"_what": "oracle tie-corrected argmin of N=128 (tied workload seed 0) at n=2^17 (P17), encryption level "
+                     "31, Chebyshev comparator and indicator of degree 2^11 - 1: sha256 of the exported one-hot and "
+                     "value ciphertexts and their decoded contents",
+            "level": level,
+            "sha256": [hashlib.sha256(oh.export().tobytes()).hexdigest(),
+                       hashlib.sha256(val.export().tobytes()).hexdigest()],
+            "onehot": [float(x) for x in O.decrypt(K, oh, N)],
+            "value": float(O.decrypt(K, val, 1)[0]),
+            "argmin": int(np.argsort(v, kind="stable")[0]), "min": float(v.min())}
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["rank128_p16", "argmin128_p17", "sort128_p17", "mixed_p16d", "argmax128_p17o",
-                             "rank512_p16_multi", "sort512_p17s_multi", "rank128_p16_cheb"]
+                             "rank512_p16_multi", "sort512_p17s_multi", "rank128_p16_cheb",
+                             "argmin128_p17_cheb"]
     for name in which:
         json.dump(globals()[name](), open(os.path.join(HERE, name + ".json"), "w"), indent=1)
         print("wrote", name + ".json", flush=True)

@@ -119,6 +119,49 @@ def test_argmin128_full_size_matches_golden(p17):
     assert abs(ctx.decrypt(keys, val, 1)[0] - v.min()) < 5e-3   # indicator leakage: 0.0016 measured
 
 
+def test_argmin128_chebyshev_full_size_matches_golden(p17):
+    """The paper's setting for the minimum: Chebyshev comparator and
+    indicator of degree 2^11 - 1 (12 levels each), tie-corrected, N = 128."""
+    ctx, ps = p17
+    gold = json.load(open(os.path.join(GOLD, "argmin128_p17_cheb.json")))
+    N = 128
+    cmp = ind = W.CHEB_CMP[N]
+    level = gold["level"]
+    import paper_2412_15126_amd as ckr
+    assert level == ckr.order_stat_depth(N, 1, cmp, ind, True)
+    v, kseed, eseed = W.tied_workload(N, 0)
+    say("[gpu] P17 chebyshev argmin keygen")
+    keys = ctx.keygen(kseed, level, [N], what=2)
+    say("[gpu] P17 chebyshev argmin")
+    oh, val = ctx.order_stat(keys, ctx.encrypt(keys, v, level, eseed), N, 1, cmp, ind, True)
+    assert [hashlib.sha256(c.export().tobytes()).hexdigest() for c in (oh, val)] == gold["sha256"]
+    assert np.array_equal(np.round(ctx.decrypt(keys, oh, N)), np.eye(N)[gold["argmin"]])
+    assert abs(ctx.decrypt(keys, val, 1)[0] - v.min()) < 0.02
+
+
+def test_argmin128_chebyshev_real_part_projection(p17):
+    """The Chebyshev indicator's argument is projected onto its real part:
+    without it, an imaginary part of ~1e-3 inherited from the comparator made
+    one slot of one of these queries blow up to 231 (the degree-2047
+    indicator grows like cosh(n y / sqrt(1 - x^2)) off the real axis).  Every
+    query's one-hot is right and agrees with the slot-level shadow."""
+    from oracle import shadow as S
+    import paper_2412_15126_amd as ckr
+    ctx, ps = p17
+    N = 128
+    cmp = ind = W.CHEB_CMP[N]
+    level = ckr.order_stat_depth(N, 1, cmp, ind, True)
+    keys = ctx.keygen(bytes(range(11, 43)), level, [N], what=2)
+    for seed in range(2000, 2004):
+        v, _, eseed = W.tied_workload(N, seed)
+        say(f"[gpu] P17 chebyshev argmin seed {seed}")
+        oh, val = ctx.order_stat(keys, ctx.encrypt(keys, v, level, eseed), N, 1, cmp, ind, True)
+        d = ctx.decrypt(keys, oh, N)
+        sh, _, _ = S.order_stat_circuit(v, N, 1 << 16, 1, cmp, ind, True)
+        assert np.max(np.abs(d - sh[:N])) < 0.02, seed
+        assert np.array_equal(np.round(d), np.eye(N)[np.argsort(v, kind="stable")[0]]), seed
+
+
 def test_sort128_full_size_matches_golden(p17):
     ctx, ps = p17
     gold = json.load(open(os.path.join(GOLD, "sort128_p17.json")))
