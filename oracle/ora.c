@@ -1554,6 +1554,59 @@ ora_ct *ora_sort(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, ora_cmp
     return S;
 }
 
+/* Column-form Sorting (section 3.3, the variant that saves the final
+ * transposition): the comparator's operands are swapped and SumR becomes
+ * SumC, so the ranks come out as a column, R'_i = SumC(Cmp(V_C, V_R)) + 1/2
+ * at slot i N; the rest runs with rows and columns exchanged and
+ * ReplC(TransR(V)) from the rank in place of ReplR(V):
+ *   X = ReplC(R') - (1 || 2 || ... || N)^N  (column k holds k + 1),
+ *   M = Ind_0(X) = Cmp(X, -1/2) (1 - Cmp(X, 1/2)) on (X +- 1/2)/N,
+ *   S = SumR(M * ReplC(TransR(V))), the sorted vector in row 0.
+ * Levels: TransR mask, comparator, SumC mask, scaling, indicator, indicator
+ * product, M * V_C, SumR mask. */
+int ora_sort_col_depth(ora_cmp cm, ora_cmp ci) { return ora_rank_depth(cm) + 4 + cmp_levels(ci); }
+
+ora_ct *ora_sort_col(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, ora_cmp ci, int *status) {
+    int st = check_N(Kp->P, N);
+    if (st != ORA_OK) { *status = st; return NULL; }
+    if (!cmp_valid(cm) || !cmp_valid(ci)) { *status = ORA_E_INVALID; return NULL; }
+    if (V->level < ora_sort_col_depth(cm, ci)) { *status = ORA_E_DEPTH; return NULL; }
+    const double dN = (double)N;
+    ora_ct *VR = ora_repl_r(Kp, V, N, &st);
+    ora_ct *T = ora_trans_r(Kp, V, N, &st);
+    ora_ct *VC = ora_repl_c(Kp, T, N, &st);
+    ora_ct *VRa = ora_cmul_to(VR, 1.0, VC->level, &st);
+    ora_ct *D = ora_sub(VC, VRa);
+    ora_ct *C = cmp_sign_scaled(Kp, D, cm, 1.0, &st);
+    ora_ct *SC = ora_sum_c(Kp, C, N, &st);
+    double *z = (double *)calloc((size_t)N * N, sizeof(double));
+    for (u32 i = 0; i < N; i++) z[(size_t)i * N] = 0.5;
+    ora_ct *R = ora_add_plain(SC, z, N * N, &st);
+    ora_ct *RC = ora_repl_c(Kp, R, N, &st);
+    for (u32 i = 0; i < N; i++)
+        for (u32 k = 0; k < N; k++) z[(size_t)i * N + k] = -(double)(k + 1);
+    ora_ct *X = ora_add_plain(RC, z, N * N, &st);
+    free(z);
+    ora_ct *Xs = ora_cmul_to(X, ci.cheb > 0 ? 0.5 / dN : 1.0 / dN, X->level - 1, &st);
+    if (ci.cheb > 0) replace(&Xs, plus_conj(Kp, Xs, &st));
+    ora_ct *d1 = ora_add_const(Xs, 0.5 / dN);
+    ora_ct *d2 = ora_add_const(Xs, -0.5 / dN);
+    ora_ct *c1 = ora_cmp_sign(Kp, d1, ci, &st);
+    ora_ct *c2 = ora_cmp_sign(Kp, d2, ci, &st);
+    ora_ct *n2 = mul_int(c2, -1);
+    ora_ct *o2 = ora_add_const(n2, 1.0);
+    ora_ct *M = ora_mul(Kp, c1, o2, &st);
+    ora_ct *VCa = ora_cmul_to(VC, 1.0, M->level, &st);
+    ora_ct *P = ora_mul(Kp, M, VCa, &st);
+    ora_ct *S = ora_sum_r(Kp, P, N, &st);
+    ora_ct_free(VR); ora_ct_free(T); ora_ct_free(VC); ora_ct_free(VRa); ora_ct_free(D); ora_ct_free(C);
+    ora_ct_free(SC); ora_ct_free(R); ora_ct_free(RC); ora_ct_free(X); ora_ct_free(Xs); ora_ct_free(d1);
+    ora_ct_free(d2); ora_ct_free(c1); ora_ct_free(c2); ora_ct_free(n2); ora_ct_free(o2); ora_ct_free(M);
+    ora_ct_free(VCa); ora_ct_free(P);
+    *status = st;
+    return S;
+}
+
 /* Galois elements needed by the circuits: bit 0 rank, bit 1 argmin (adds
  * SumC), bit 2 sort (adds SumC and TransC) */
 int ora_circuit_galois(const ora_params *P, u32 N, int what, u32 *out) {

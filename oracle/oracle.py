@@ -120,6 +120,8 @@ def lib():
             "ora_sort": (vp, [vp, vp, C.c_uint32, OraCmp, OraCmp, intp]),
             "ora_circuit_galois": (C.c_int, [vp, C.c_uint32, C.c_int, u32p]),
             "ora_cheb_step_coeffs": (None, [C.c_int, dblp]),
+            "ora_sort_col_depth": (C.c_int, [OraCmp, OraCmp]),
+            "ora_sort_col": (vp, [vp, vp, C.c_uint32, OraCmp, OraCmp, intp]),
             "ora_cheb_depth": (C.c_int, [C.c_uint32]),
             "ora_cheb_eval": (vp, [vp, vp, dblp, C.c_uint32, intp]),
         }
@@ -520,3 +522,13 @@ def sort_depth(cmp, ind):
 def sort(keys, a, N, cmp, ind):
     keys.need(N, 4)
     return _ct(lib().ora_sort, a.params, keys.ptr, a.ptr, N, _cmp(cmp), _cmp(ind), what="sort")
+
+
+def sort_col_depth(cmp, ind):
+    return lib().ora_sort_col_depth(_cmp(cmp), _cmp(ind))
+
+
+def sort_col(keys, a, N, cmp, ind):
+    """column-form sorting: swapped comparator operands, SumC ranks, no final transposition"""
+    keys.need(N, 2)
+    return _ct(lib().ora_sort_col, a.params, keys.ptr, a.ptr, N, _cmp(cmp), _cmp(ind), what="sort_col")

@@ -123,7 +123,9 @@ def is_cheb(cmp):
 
 
 def cmp_of(d, cmp):
-    """Cmp on the difference d under the spec cmp (composite or Chebyshev)."""
+    """Cmp on the difference d under the spec cmp (ideal, composite or Chebyshev)."""
+    if isinstance(cmp, str):
+        return cmp_ideal(d, 0.0)
     if is_cheb(cmp):
         return _cheb.chebval(d, cheb_step_coeffs(cmp[2]))
     return (sign_composite(d, cmp[0], cmp[1]) + 1.0) / 2.0
@@ -321,3 +323,24 @@ def sort_circuit(v, N, slots, cmp, ind):
     VR = repl_r(x, N)
     SC = sum_c(M * VR, N)
     return trans_c(SC, N)
+
+
+def sort_col_circuit(v, N, slots, cmp, ind):
+    """Column-form Sorting (section 3.3): ranks as a column, R' = SumC(Cmp(V_C, V_R)) + 1/2;
+    M = Ind_0(ReplC(R') - (1 || ... || N)^N) on (x +- 1/2)/N; S = SumR(M * ReplC(TransR(V)))."""
+    x = embed(v, slots)
+    VR = repl_r(x, N)
+    VC = repl_c(trans_r(x, N), N)
+    Cm = cmp_of(VC - VR, cmp)
+    half = np.zeros(slots)
+    half[0:N * N:N] = 0.5
+    R = sum_c(Cm, N) + half
+    RC = repl_c(R, N)
+    steps = np.zeros(slots)
+    for i in range(N):
+        steps[i * N:(i + 1) * N] = np.arange(1, N + 1)
+    X = RC - steps
+    c1 = cmp_of((X + 0.5) / N, ind)
+    c2 = cmp_of((X - 0.5) / N, ind)
+    M = c1 * (1.0 - c2)
+    return sum_r(M * VC, N)

@@ -385,3 +385,34 @@ def test_oracle_multi_ciphertext_sort_matches_shadow(ora):
     sh = np.concatenate([s[:b] for s in S.sort_multi_circuit(v, b, P.n // 2, cmp, ind)])
     assert np.max(np.abs(got - sh)) < 1e-3
     assert np.max(np.abs(got - np.sort(v))) < 1e-3
+
+
+@pytest.mark.parametrize("N", [8, 16, 64])
+def test_shadow_column_form_sort_is_exact_and_equals_row_form(N):
+    """Column-form sorting (section 3.3): with the ideal comparator and
+    indicator it returns the sorted vector in row 0 (nothing elsewhere), and
+    with the f/g composites it equals the row-form sort."""
+    rng = np.random.default_rng(N)
+    v = W.min_gap_uniform(N, 0.01 if N <= 16 else 2.0 ** -10, rng)
+    slots = 4 * N * N
+    out = S.sort_col_circuit(v, N, slots, "ideal", "ideal")
+    assert np.array_equal(out[:N], np.sort(v)) and not np.any(out[N:])
+    cmp, ind = W.SORT_CMP[N]
+    col = S.sort_col_circuit(v, N, slots, cmp, ind)
+    row = S.sort_circuit(v, N, slots, cmp, ind)
+    assert np.max(np.abs(col[:N] - row[:N])) < 1e-9
+
+
+def test_oracle_column_form_sort_matches_shadow(ora, t12d):
+    P, keys = t12d
+    N = 8
+    cmp, ind = W.SORT_CMP[N]
+    depth = ora.sort_col_depth(cmp, ind)
+    assert depth == ora.sort_depth(cmp, ind) - 1        # no TransC mask
+    v, _, eseed = W.rank_workload(N, 0.01, 4)
+    s = ora.sort_col(keys, ora.encrypt(keys, v, depth, eseed), N, cmp, ind)
+    assert s.level == 0
+    got = ora.decrypt(keys, s, N)
+    sh = S.sort_col_circuit(v, N, P.n // 2, cmp, ind)
+    assert np.max(np.abs(got - sh[:N])) < 1e-3
+    assert np.max(np.abs(got - np.sort(v))) < 1e-3
