@@ -280,6 +280,9 @@ def circuit_bench(args):
                                    "at n=2^17 (41 + 10 primes, dnum=4) with the Chebyshev comparator and indicator "
                                    "of degree 2^11 - 1 (12 levels each, the paper's setting for the minimum), "
                                    "encrypted at level 31"),
+        "sort128col": dict(pset="P17", N=128, q=dict(kind="sort_col"), ci=W.SORT_CMP[128], what=2, level="depth",
+                           desc="column-form sort of N=128 (gap 2^-10) at n=2^17 (41 + 10 primes, dnum=4), encrypted "
+                                "at level 39, comparator g^4 f, indicator g^4 f^2"),
         "rank512": dict(pset="P16", N=512, b=128, ci=(W.MULTI_RANK_CMP[512], None), what=4,
                         desc="multi-ciphertext rank of N=512 (gap 2^-10) in 4 blocks of 128 at n=2^16 (24 + 7 "
                              "primes, dnum=3), blocks encrypted at level 21, comparator g^4 f^2"),
@@ -300,6 +303,8 @@ def circuit_bench(args):
             level = ps["L"]
         elif spec["q"]["kind"] == "order":
             level = ckr.order_stat_depth(N, spec["q"]["k"], cmp, ind, spec["q"]["tie"])
+        elif spec["q"]["kind"] == "sort_col":
+            level = ckr.sort_col_depth(cmp, ind)
         else:
             level = ckr.rank_depth(cmp)
     B = max(1, args.batch if args.batch != 32 else spec.get("B", 1 if multi else 4))
@@ -343,7 +348,7 @@ def circuit_bench(args):
                 worst = max(worst, float(np.max(np.abs(got - (np.argsort(np.argsort(v)) + 1)))))
             elif spec["q"]["kind"] == "rank":
                 worst = max(worst, float(np.max(np.abs(ctx.decrypt(keys, o, N) - (np.argsort(np.argsort(v)) + 1)))))
-            elif spec["q"]["kind"] == "sort":
+            elif spec["q"]["kind"] in ("sort", "sort_col"):
                 worst = max(worst, float(np.max(np.abs(ctx.decrypt(keys, o, N) - np.sort(v)))))
             else:
                 k = spec["q"]["k"]
@@ -408,7 +413,7 @@ def main():
     ap.add_argument("--mixed", action="store_true", help="64 mixed rank/argmin queries in one launch instead")
     ap.add_argument("--workload", default="rank128",
                     choices=["rank128", "argmin128", "argmax128", "sort128", "rank512", "sort512", "rank128cheb",
-                             "argmin128cheb"],
+                             "argmin128cheb", "sort128col"],
                     help="circuit to time (rank128: the headline metric)")
     ap.add_argument("--rate", type=float, default=4.0)
     ap.add_argument("--serve-seconds", type=float, default=30.0)

@@ -152,6 +152,7 @@ ckr_status ckr_rank(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uin
 uint32_t ckr_rank_depth(ckr_sign cmp, int tie_correct);
 uint32_t ckr_argmin_depth(ckr_sign cmp, ckr_sign ind);
 uint32_t ckr_sort_depth(ckr_sign cmp, ckr_sign ind);
+uint32_t ckr_sort_col_depth(ckr_sign cmp, ckr_sign ind);
 uint32_t ckr_order_stat_depth(uint32_t N, uint32_t k, ckr_sign cmp, ckr_sign ind, int tie_correct);
 
 /* Minimum with tie-correction (Algorithm Order Statistic with k = 1):
@@ -165,6 +166,17 @@ ckr_status ckr_argmin(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, u
  * increasing order. */
 ckr_status ckr_sort(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, ckr_sign cmp, ckr_sign ind,
                     ckr_ct **out);
+
+/* Column-form sorting (section 3.3, the variant without the final
+ * transposition): the comparator's operands are swapped and the ranks are
+ * summed by SumC into column 0, the sort then runs with rows and columns
+ * exchanged and ReplC(TransR(v)) from the rank as the value matrix, and
+ * SumR leaves the sorted vector in slots [0,N).  One level
+ * (ckr_sort_col_depth = ckr_sort_depth - 1) and log N rotations fewer than
+ * ckr_sort; no TransC rotation keys needed (ckr_keygen's argmin set).
+ * Distinct inputs; errors as ckr_sort. */
+ckr_status ckr_sort_col(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, ckr_sign cmp,
+                        ckr_sign ind, ckr_ct **out);
 
 /* Order statistic k (Algorithm Order Statistic, section 3.2): onehot slots
  * [0,N) hold 1 at the k-th smallest element and 0 elsewhere; value slot 0
@@ -206,7 +218,8 @@ uint32_t ckr_sort_multi_depth(ckr_sign cmp, ckr_sign ind);
 
 /* One query of a mixed batch.  kind: 1 rank (tie_correct selects the
  * tie-corrected rank), 2 argmin (the tie-corrected minimum; k and tie_correct
- * ignored), 3 sort, 4 order statistic k.  v: a single ciphertext, borrowed. */
+ * ignored), 3 sort, 4 order statistic k, 5 column-form sort.  v: a single
+ * ciphertext, borrowed. */
 typedef struct {
     int kind;
     uint32_t N;
@@ -230,7 +243,8 @@ ckr_status ckr_run_mixed(ckr_context *ctx, const ckr_keys *keys, const ckr_query
 
 /* Batched execution: `count` ciphertexts of equal N and level run through one
  * circuit together -- every kernel launch covers all of them.  kind: 1 rank,
- * 2 argmin (outputs out[2i] one-hot, out[2i+1] value), 3 sort (out[i]).
+ * 2 argmin (outputs out[2i] one-hot, out[2i+1] value), 3 sort, 5 column-form
+ * sort (out[i]).
  * With graphs enabled (the default) the first call for a shape (kind, N,
  * level, count, comparators) runs eagerly, the second captures the circuit
  * into a hipGraph owned by `keys`, later calls replay it.  Outputs equal

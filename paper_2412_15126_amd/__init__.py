@@ -76,6 +76,8 @@ _SIGS = {
     "ckr_sort_depth": (C.c_uint32, [Sign, Sign]),
     "ckr_argmin": (C.c_int, [vp, vp, vp, C.c_uint32, Sign, Sign, C.POINTER(vp), C.POINTER(vp)]),
     "ckr_sort": (C.c_int, [vp, vp, vp, C.c_uint32, Sign, Sign, C.POINTER(vp)]),
+    "ckr_sort_col": (C.c_int, [vp, vp, vp, C.c_uint32, Sign, Sign, C.POINTER(vp)]),
+    "ckr_sort_col_depth": (C.c_uint32, [Sign, Sign]),
     "ckr_rank_batch": (C.c_int, [vp, vp, C.POINTER(vp), C.c_size_t, C.c_uint32, Sign, C.POINTER(vp)]),
     "ckr_ct_level": (C.c_uint32, [vp]),
     "ckr_ct_scale": (C.c_double, [vp]),
@@ -190,6 +192,10 @@ def sort_depth(cmp, ind):
     return int(lib().ckr_sort_depth(sign(cmp), sign(ind)))
 
 
+def sort_col_depth(cmp, ind):
+    return int(lib().ckr_sort_col_depth(sign(cmp), sign(ind)))
+
+
 # ---- device objects -----------------------------------------------------------
 class Context:
     def __init__(self, pset, device=0, hbm_budget=0):
@@ -281,6 +287,12 @@ class Context:
         _ok(lib().ckr_sort(self.h, keys.h, ct.h, N, sign(cmp), sign(ind), C.byref(h)))
         return Ct(self, h)
 
+    def sort_col(self, keys, ct, N, cmp, ind):
+        """column-form sort: no final transposition, one level fewer"""
+        h = vp()
+        _ok(lib().ckr_sort_col(self.h, keys.h, ct.h, N, sign(cmp), sign(ind), C.byref(h)))
+        return Ct(self, h)
+
     def autotune(self, limbs, iters=5):
         """Pick the fastest NTT tile per (direction, pass); returns the timing table [inv][pass][variant] in ms."""
         ms = (C.c_float * 16)()
@@ -307,7 +319,7 @@ class Context:
 
     def run_batch(self, keys, kind, cts, N, cmp, ind=(0, 0)):
         """kind: 'rank', 'argmin' (returns (onehot, value) pairs) or 'sort'."""
-        k = {"rank": 1, "argmin": 2, "sort": 3}[kind]
+        k = {"rank": 1, "argmin": 2, "sort": 3, "sort_col": 5}[kind]
         per = 2 if kind == "argmin" else 1
         arr = (vp * len(cts))(*[c.h for c in cts])
         out = (vp * (per * len(cts)))()
@@ -318,7 +330,7 @@ class Context:
     def run_mixed(self, keys, queries):
         """queries: dicts with kind ('rank', 'argmin', 'sort', 'order'), N, ct, cmp and, as
         needed, ind, k, tie.  Returns per query a Ct or an (onehot, value) pair."""
-        kinds = {"rank": 1, "argmin": 2, "sort": 3, "order": 4}
+        kinds = {"rank": 1, "argmin": 2, "sort": 3, "order": 4, "sort_col": 5}
         arr = (Query * len(queries))()
         for a, q in zip(arr, queries):
             a.kind, a.N, a.k, a.tie_correct = kinds[q["kind"]], q["N"], q.get("k", 1), int(q.get("tie", False))

@@ -841,7 +841,7 @@ static DCt ev_plus_conj(Ctx &C, const Keys &K, const DCt &a) { return ev_galois_
 
 // plaintext holding z on slots [0, count) at scale D_level, eval domain [level+1][n]
 enum PlainKind { kMaskRow0 = 1, kMaskCol0 = 2, kHalfRow0 = 3, kTieMask = 4, kSteps = 5, kNegHalfRow0 = 6,
-                 kStepsBlock = 7 };
+                 kStepsBlock = 7, kHalfCol0 = 8, kStepsCol = 9 };
 
 static Buf encode_plain(Ctx &C, const std::vector<double> &z, int level) {
     const size_t n = C.n();
@@ -876,6 +876,13 @@ static std::vector<double> plain_values(int kind, int N, int arg) {
     case kStepsBlock:  // -((N arg + 1)^N || ... || (N arg + N)^N): the ranks of output block arg
         for (int i = 0; i < N; i++)
             for (int j = 0; j < N; j++) z[(size_t)i * N + j] = -((double)N * arg + i + 1);
+        break;
+    case kHalfCol0:  // 1/2 on column 0
+        for (int i = 0; i < N; i++) z[(size_t)i * N] = 0.5;
+        break;
+    case kStepsCol:  // -(1 || 2 || ... || N)^N: column k holds -(k + 1)
+        for (int i = 0; i < N; i++)
+            for (int j = 0; j < N; j++) z[(size_t)i * N + j] = -(double)(j + 1);
         break;
     default: throw Error{CKR_E_INVALID, "plaintext kind"};
     }
@@ -1467,12 +1474,47 @@ static DCt sort(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, ckr_si
     return trans_c(C, K, SC, N);
 }
 
-enum CircuitKind { kRankCircuit = 1, kArgminCircuit = 2, kSortCircuit = 3, kOrderCircuit = 4 };
+// Column-form Sorting (section 3.3, the variant that saves the final
+// transposition): the comparator's operands are swapped and SumR becomes SumC,
+// so the ranks come out as a column, R'_i = SumC(Cmp(V_C, V_R)) + 1/2 at slot
+// i N; rows and columns are then exchanged, with ReplC(TransR(V)) from the
+// rank in place of ReplR(V):
+//   M = Ind_0(ReplC(R') - (1 || ... || N)^N),  S = SumR(M * ReplC(TransR(V))).
+// One level and log N rotations fewer than the row form.
+uint32_t sort_col_depth(ckr_sign c, ckr_sign i) { return rank_depth(c, 0) + 4 + cmp_levels(i); }
+
+static DCt sort_col(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, ckr_sign ind) {
+    check_N(C, (u32)N);
+    check_sign(cmp);
+    check_sign(ind);
+    if ((u32)V.level < sort_col_depth(cmp, ind)) throw Error{CKR_E_DEPTH, "not enough levels for sort"};
+    DCt VR = repl_r(C, K, V, N);
+    DCt VC = repl_c(C, K, trans_r(C, K, V, N), N);
+    DCt D = ev_add(C, VC, ev_cmul_to(C, VR, 1.0, VC.level), true);
+    DCt SC = sum_c(C, K, cmp_sign(C, K, D, cmp), N);
+    DCt R = ev_add_plain(C, SC, get_plain(C, kHalfCol0, N, SC.level));
+    DCt RC = repl_c(C, K, R, N);
+    DCt X = ev_add_plain(C, RC, get_plain(C, kStepsCol, N, RC.level));
+    DCt Xs = ev_cmul_to(C, X, ind.cheb ? 0.5 / (double)N : 1.0 / (double)N, X.level - 1);
+    if (ind.cheb) Xs = ev_plus_conj(C, K, Xs);
+    DCt d1 = ev_add_const(C, Xs, 0.5 / (double)N);
+    DCt d2 = ev_add_const(C, Xs, -0.5 / (double)N);
+    // both comparisons in one batched pass
+    DCt cc = cmp_sign(C, K, stack(C, {&d1, &d2}), ind);
+    const int B = V.B;
+    DCt c1 = slice(C, cc, 0, B), c2 = slice(C, cc, B, B);
+    DCt M = ev_mul(C, K, c1, ev_add_const(C, ev_mul_int(C, c2, -1), 1.0));
+    DCt VCa = ev_cmul_to(C, VC, 1.0, M.level);
+    return sum_r(C, K, ev_mul(C, K, M, VCa), N);
+}
+
+enum CircuitKind { kRankCircuit = 1, kArgminCircuit = 2, kSortCircuit = 3, kOrderCircuit = 4, kSortColCircuit = 5 };
 
 // levels a circuit consumes
 static uint32_t spec_depth(const Spec &s) {
     if (s.kind == kRankCircuit) return rank_depth(s.cmp, s.tie);
     if (s.kind == kSortCircuit) return sort_depth(s.cmp, s.ind);
+    if (s.kind == kSortColCircuit) return sort_col_depth(s.cmp, s.ind);
     return order_stat_depth(s.N, s.k, s.cmp, s.ind, s.tie);
 }
 
@@ -1486,7 +1528,7 @@ static Spec spec_of(const Ctx &C, int kind, int N, int k, int tie, ckr_sign cmp,
     if (kind == kRankCircuit) {
         s.kind = kind;
         s.tie = tie != 0;
-    } else if (kind == kSortCircuit) {
+    } else if (kind == kSortCircuit || kind == kSortColCircuit) {
         s.kind = kind;
         s.ind = ind;
     } else if (kind == kArgminCircuit || kind == kOrderCircuit) {
@@ -1509,6 +1551,8 @@ static std::vector<DCt> eval_spec(Ctx &C, const Keys &K, const Spec &s, const DC
         o.push_back(s.tie ? tie_rank(C, K, X, s.N, s.cmp) : rank(C, K, X, s.N, s.cmp));
     } else if (s.kind == kSortCircuit) {
         o.push_back(sort(C, K, X, s.N, s.cmp, s.ind));
+    } else if (s.kind == kSortColCircuit) {
+        o.push_back(sort_col(C, K, X, s.N, s.cmp, s.ind));
     } else {
         o.resize(2);
         order_stat(C, K, X, s.N, s.k, s.tie, s.cmp, s.ind, o[0], o[1]);
@@ -2344,6 +2388,7 @@ uint32_t ckr_order_stat_depth(uint32_t N, uint32_t k, ckr_sign cmp, ckr_sign ind
     return order_stat_depth((int)N, (int)k, cmp, ind, tie_correct != 0);
 }
 uint32_t ckr_sort_depth(ckr_sign cmp, ckr_sign ind) { return sort_depth(cmp, ind); }
+uint32_t ckr_sort_col_depth(ckr_sign cmp, ckr_sign ind) { return sort_col_depth(cmp, ind); }
 
 ckr_status ckr_rank(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, ckr_sign cmp, int tie,
                     ckr_ct **out) {
@@ -2563,6 +2608,18 @@ ckr_status ckr_sort(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uin
         *out = nullptr;
         Ctx &C = *ctx->C;
         DCt r = sort(C, *keys->K, v->ct, (int)N, cmp, ind);
+        *out = wrap(C, std::move(r));
+    });
+}
+
+ckr_status ckr_sort_col(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, ckr_sign cmp,
+                        ckr_sign ind, ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && keys && v && out);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
+        *out = nullptr;
+        Ctx &C = *ctx->C;
+        DCt r = sort_col(C, *keys->K, v->ct, (int)N, cmp, ind);
         *out = wrap(C, std::move(r));
     });
 }

@@ -210,10 +210,29 @@ def argmin128_p17_cheb():
             "argmin": int(np.argsort(v, kind="stable")[0]), "min": float(v.min())}
 
 
+def sort128_p17_col():
+    """column-form sort of N = 128 at n = 2^17"""
+    N = 128
+    cmp, ind = W.SORT_CMP[N]
+    O.set_threads(min(16, os.cpu_count() or 1))
+    P = O.Params(**W.PSETS["P17"])
+    level = O.sort_col_depth(cmp, ind)
+    v, kseed, eseed = W.rank_workload(N, 2.0 ** -10, 0)
+    K = O.Keys(P, kseed, level, P.circuit_galois(N, 2))
+    S = O.sort_col(K, O.encrypt(K, v, level, eseed), N, cmp, ind)
+    return {"_what": "oracle column-form sort of N=128 (workload seed 0, gap 2^-10) at n=2^17 (P17), encryption "
+                     "level 39, comparator g^4 f, indicator g^4 f^2: sha256 of the exported output and its decoded "
+                     "values",
+            "level": level,
+            "sha256": hashlib.sha256(S.export().tobytes()).hexdigest(),
+            "decoded": [float(x) for x in O.decrypt(K, S, N)],
+            "sorted": [float(x) for x in np.sort(v)]}
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["rank128_p16", "argmin128_p17", "sort128_p17", "mixed_p16d", "argmax128_p17o",
                              "rank512_p16_multi", "sort512_p17s_multi", "rank128_p16_cheb",
-                             "argmin128_p17_cheb"]
+                             "argmin128_p17_cheb", "sort128_p17_col"]
     for name in which:
         json.dump(globals()[name](), open(os.path.join(HERE, name + ".json"), "w"), indent=1)
         print("wrote", name + ".json", flush=True)

@@ -162,6 +162,50 @@ def test_argmin128_chebyshev_real_part_projection(p17):
         assert np.array_equal(np.round(d), np.eye(N)[np.argsort(v, kind="stable")[0]]), seed
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_sort8_column_form_bit_exact(ora, small, seed):
+    P, ctx = small["P"], small["ctx"]
+    N = 8
+    cmp, ind = W.SORT_CMP[N]
+    level = ora.sort_col_depth(cmp, ind)
+    assert level == small["ckr"].sort_col_depth(cmp, ind) == ora.sort_depth(cmp, ind) - 1
+    v, _, eseed = W.rank_workload(N, 0.01, 20 + seed)
+    say(f"[gpu] column-form sort8 seed {seed}")
+    o = ora.sort_col(small["okeys"], ora.encrypt(small["okeys"], v, level, eseed), N, cmp, ind)
+    g = ctx.sort_col(small["gkeys"], ctx.encrypt(small["gkeys"], v, level, eseed), N, cmp, ind)
+    assert np.array_equal(o.export(), g.export())
+    assert np.max(np.abs(ctx.decrypt(small["gkeys"], g, N) - np.sort(v))) < 1e-3
+
+
+def test_sort8_column_form_batch_equals_single(small):
+    ctx = small["ctx"]
+    N = 8
+    cmp, ind = W.SORT_CMP[N]
+    level = small["ckr"].sort_col_depth(cmp, ind)
+    qs = [W.rank_workload(N, 0.01, 40 + i) for i in range(3)]
+    cts = [ctx.encrypt(small["gkeys"], v, level, e) for v, _, e in qs]
+    singles = [ctx.sort_col(small["gkeys"], c, N, cmp, ind).export() for c in cts]
+    for rep in range(3):
+        say(f"[gpu] column-form sort8 batch pass {rep}")
+        outs = ctx.run_batch(small["gkeys"], "sort_col", cts, N, cmp, ind)
+        assert all(np.array_equal(a.export(), b) for a, b in zip(outs, singles))
+
+
+def test_sort128_column_form_full_size_matches_golden(p17):
+    ctx, ps = p17
+    gold = json.load(open(os.path.join(GOLD, "sort128_p17_col.json")))
+    N = 128
+    cmp, ind = W.SORT_CMP[N]
+    level = gold["level"]
+    v, kseed, eseed = W.rank_workload(N, 2.0 ** -10, 0)
+    say("[gpu] P17 column-form sort keygen")
+    keys = ctx.keygen(kseed, level, [N], what=2)
+    say("[gpu] P17 column-form sort")
+    s = ctx.sort_col(keys, ctx.encrypt(keys, v, level, eseed), N, cmp, ind)
+    assert hashlib.sha256(s.export().tobytes()).hexdigest() == gold["sha256"]
+    assert np.max(np.abs(ctx.decrypt(keys, s, N) - np.sort(v))) < 1e-3
+
+
 def test_sort128_full_size_matches_golden(p17):
     ctx, ps = p17
     gold = json.load(open(os.path.join(GOLD, "sort128_p17.json")))
