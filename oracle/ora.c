@@ -1507,6 +1507,52 @@ int ora_order_stat(const ora_keys *Kp, const ora_ct *V, u32 N, u32 k, ora_cmp cm
     return st;
 }
 
+/* Order statistic with the value by division (section 3.2): without
+ * tie-correction the mask O of the elements of rank k may hold several ones
+ * (equal values share a rank) or none, and the value is
+ * SumC(O * V) / SumC(O).  The division is Goldschmidt's: with the count
+ * normalised to x = (2 / (N + 1)) SumC(MaskR(O)) in (0, 2),
+ *   1/x ~ prod_{i<d} (1 + b^(2^i)),  b = 1 - x,
+ * relative error b^(2^d), d >= 2; the first factor is affine, each later
+ * one a squaring and a product.  value = ((2 / (N + 1)) SumC(O * V)) * prod.
+ * If no element has rank k the numerator is zero (up to noise) and the
+ * product at most 2^d.  Levels beyond the order statistic's (the count's
+ * SumC mask runs beside the value's): the normalisation, d for the products
+ * (the first also aligns a level), the final product -- d + 2. */
+int ora_order_stat_div_depth(u32 N, u32 k, ora_cmp cm, ora_cmp ci, int iters) {
+    return ora_order_stat_depth(N, k, cm, ci, 0) + iters + 2;
+}
+
+int ora_order_stat_div(const ora_keys *Kp, const ora_ct *V, u32 N, u32 k, ora_cmp cm, ora_cmp ci, int iters,
+                       ora_ct **onehot, ora_ct **value) {
+    if (iters < 2 || iters > 24) return ORA_E_INVALID;
+    int st = check_N(Kp->P, N);
+    if (st != ORA_OK) return st;
+    if (k < 1 || k > N) return ORA_E_INVALID;
+    if (V->level < ora_order_stat_div_depth(N, k, cm, ci, iters)) return ORA_E_DEPTH;
+    ora_ct *num;
+    st = ora_order_stat(Kp, V, N, k, cm, ci, 0, onehot, &num);
+    if (st != ORA_OK) return st;
+    const double s = 2.0 / ((double)N + 1.0);
+    ora_ct *den = ora_sum_c(Kp, *onehot, N, &st);
+    ora_ct *x = ora_cmul_to(den, s, den->level - 1, &st);
+    ora_ct *nx = mul_int(x, -1);
+    ora_ct *b = ora_add_const(nx, 1.0);   /* b = 1 - x */
+    ora_ct *a = ora_add_const(nx, 2.0);   /* 1 + b */
+    for (int i = 1; i < iters; i++) {
+        replace(&b, ora_mul(Kp, b, b, &st));                 /* b^(2^i) */
+        ora_ct *f = ora_add_const(b, 1.0);
+        ora_ct *aa = align_to(a, f->level, &st);
+        replace(&a, ora_mul(Kp, aa, f, &st));
+        ora_ct_free(f); ora_ct_free(aa);
+    }
+    ora_ct *na = ora_cmul_to(num, s, a->level, &st);
+    *value = ora_mul(Kp, na, a, &st);
+    ora_ct_free(num); ora_ct_free(den); ora_ct_free(x); ora_ct_free(nx); ora_ct_free(b); ora_ct_free(a);
+    ora_ct_free(na);
+    return st;
+}
+
 /* the minimum with tie-correction: order statistic k = 1 */
 int ora_argmin(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, ora_cmp ci, ora_ct **onehot,
                ora_ct **value) {

@@ -121,6 +121,9 @@ def lib():
             "ora_circuit_galois": (C.c_int, [vp, C.c_uint32, C.c_int, u32p]),
             "ora_cheb_step_coeffs": (None, [C.c_int, dblp]),
             "ora_sort_col_depth": (C.c_int, [OraCmp, OraCmp]),
+            "ora_order_stat_div_depth": (C.c_int, [C.c_uint32, C.c_uint32, OraCmp, OraCmp, C.c_int]),
+            "ora_order_stat_div": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32, OraCmp, OraCmp, C.c_int, C.POINTER(vp),
+                                             C.POINTER(vp)]),
             "ora_sort_col": (vp, [vp, vp, C.c_uint32, OraCmp, OraCmp, intp]),
             "ora_cheb_depth": (C.c_int, [C.c_uint32]),
             "ora_cheb_eval": (vp, [vp, vp, dblp, C.c_uint32, intp]),
@@ -532,3 +535,17 @@ def sort_col(keys, a, N, cmp, ind):
     """column-form sorting: swapped comparator operands, SumC ranks, no final transposition"""
     keys.need(N, 2)
     return _ct(lib().ora_sort_col, a.params, keys.ptr, a.ptr, N, _cmp(cmp), _cmp(ind), what="sort_col")
+
+
+def order_stat_div_depth(N, k, cmp, ind, iters):
+    return lib().ora_order_stat_div_depth(N, k, _cmp(cmp), _cmp(ind), iters)
+
+
+def order_stat_div(keys, a, N, k, cmp, ind, iters):
+    """(mask, value): order statistic k without tie-correction, value = SumC(O V) / SumC(O) by Goldschmidt"""
+    keys.need(N, 2)
+    oh, val = C.c_void_p(), C.c_void_p()
+    st = lib().ora_order_stat_div(keys.ptr, a.ptr, N, k, _cmp(cmp), _cmp(ind), iters, C.byref(oh), C.byref(val))
+    if st != 0:
+        raise OracleError(f"order_stat_div: status {STATUS.get(st, st)}")
+    return Ct(oh.value, a.params), Ct(val.value, a.params)

@@ -344,3 +344,23 @@ def sort_col_circuit(v, N, slots, cmp, ind):
     c2 = cmp_of((X - 0.5) / N, ind)
     M = c1 * (1.0 - c2)
     return sum_r(M * VC, N)
+
+
+def goldschmidt_inverse(x, iters):
+    """prod_{i<iters} (1 + b^(2^i)), b = 1 - x: Goldschmidt's 1/x for x in (0, 2)"""
+    b = 1.0 - x
+    a = 1.0 + b
+    for _ in range(1, iters):
+        b = b * b
+        a = a * (1.0 + b)
+    return a
+
+
+def order_stat_div_circuit(v, N, slots, k, cmp, ind, iters):
+    """Order statistic k without tie-correction, value = SumC(O V) / SumC(O)
+    (section 3.2) with the count normalised by 2 / (N + 1) and inverted by
+    Goldschmidt.  Returns (mask row 0, value slot vector)."""
+    O, num, _ = order_stat_circuit(v, N, slots, k, cmp, ind, False)
+    s = 2.0 / (N + 1.0)
+    den = sum_c(O, N)
+    return O, (s * num) * goldschmidt_inverse(s * den, iters)

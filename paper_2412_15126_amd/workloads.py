@@ -95,6 +95,17 @@ def tied_workload(N, seed, gap=2.0 ** -10):
     return v, seed_bytes(rng), seed_bytes(rng)
 
 
+def tripled_workload(N, seed, triples=1, gap=2.0 ** -10):
+    """(values, key seed, encryption seed): N - 2 triples distinct values (min gap), `triples` of them
+    appearing three times, shuffled; a tripled value's fractional rank is an integer shared by three
+    elements."""
+    rng = np.random.default_rng(seed)
+    base = min_gap_uniform(N - 2 * triples, gap, rng)
+    v = np.concatenate([base, np.repeat(base[:triples], 2)])
+    rng.shuffle(v)
+    return v, seed_bytes(rng), seed_bytes(rng)
+
+
 def rank_workload(N, gap, seed):
     """(values, key seed, encryption seed) of one seeded rank query."""
     rng = np.random.default_rng(seed)

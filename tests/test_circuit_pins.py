@@ -416,3 +416,61 @@ def test_oracle_column_form_sort_matches_shadow(ora, t12d):
     sh = S.sort_col_circuit(v, N, P.n // 2, cmp, ind)
     assert np.max(np.abs(got - sh[:N])) < 1e-3
     assert np.max(np.abs(got - np.sort(v))) < 1e-3
+
+
+@pytest.mark.parametrize("x", [0.02, 0.3, 1.0, 1.7])
+def test_goldschmidt_closed_form(x):
+    """prod_{i<d} (1 + b^(2^i)) = (1 - b^(2^d)) / (1 - b) with b = 1 - x: the
+    inverse of x up to the relative error b^(2^d)."""
+    for d in (2, 5, 9):
+        b = 1.0 - x
+        assert abs(S.goldschmidt_inverse(x, d) - (1.0 - b ** (2 ** d)) / x) < 1e-9 / x
+
+
+def _tripled_case(N, seed):
+    v, _, eseed = W.tripled_workload(N, seed, triples=1, gap=0.01 if N <= 16 else 2.0 ** -10)
+    u, c = np.unique(v, return_counts=True)
+    t = u[np.argmax(c)]                       # the tripled value
+    below = int(np.sum(v < t))
+    return v, eseed, t, below
+
+
+@pytest.mark.parametrize("N", [8, 32])
+def test_shadow_order_stat_division(N):
+    """Section 3.2's value by division: with the ideal comparator and
+    indicator, the mask of rank |L| + 2 has the three copies of the tripled
+    value and the quotient is that value; rank |L| + 1 has no element and
+    the value is 0; a one-hot rank gives its element."""
+    v, _, t, below = _tripled_case(N, 3)
+    d = 9
+    for k, want in ((below + 2, t), (below + 1, 0.0)):
+        O, val = S.order_stat_div_circuit(v, N, 4 * N * N, k, "ideal", "ideal", d)
+        assert np.sum(O[:N]) == (3 if want else 0)
+        assert abs(val[0] - want) < 1e-6
+    distinct = [k for k in range(1, N + 1) if k < below + 1 or k > below + 3]
+    k = distinct[0]
+    _, val = S.order_stat_div_circuit(v, N, 4 * N * N, k, "ideal", "ideal", d)
+    rank = (np.argsort(np.argsort(v)) + 1).astype(float)
+    assert abs(val[0] - v[rank == k][0]) < 1e-6 * N
+
+
+@pytest.fixture(scope="module")
+def t12e(ora):
+    P = ora.Params(**W.PSETS["T12E"])
+    return P, ora.Keys(P, bytes(range(1, 33)), P.L, P.circuit_galois(8, 2))
+
+
+def test_oracle_order_stat_division_matches_shadow(ora, t12e):
+    P, keys = t12e
+    N, d = 8, 6
+    cmp, ind = W.ORDER_CMP[N]
+    v, eseed, t, below = _tripled_case(N, 5)
+    k = below + 2
+    depth = ora.order_stat_div_depth(N, k, cmp, ind, d)
+    assert depth == ora.order_stat_depth(N, k, cmp, ind, False) + d + 2
+    oh, val = ora.order_stat_div(keys, ora.encrypt(keys, v, depth, eseed), N, k, cmp, ind, d)
+    assert val.level == 0
+    got = ora.decrypt(keys, val, 1)[0]
+    sO, sval = S.order_stat_div_circuit(v, N, P.n // 2, k, cmp, ind, d)
+    assert abs(got - sval[0]) < 1e-3 and abs(got - t) < 1e-3
+    assert np.array_equal(np.round(ora.decrypt(keys, oh, N)), (v == t).astype(float))
