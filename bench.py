@@ -283,6 +283,10 @@ def circuit_bench(args):
         "sort128col": dict(pset="P17", N=128, q=dict(kind="sort_col"), ci=W.SORT_CMP[128], what=2, level="depth",
                            desc="column-form sort of N=128 (gap 2^-10) at n=2^17 (41 + 10 primes, dnum=4), encrypted "
                                 "at level 39, comparator g^4 f, indicator g^4 f^2"),
+        "kth64div": dict(pset="P17S", N=64, q=dict(kind="div"), ci=W.ORDER_CMP[64], what=2, iters=8,
+                         desc="order statistic with the value by division (8 Goldschmidt steps) of N=64 values with "
+                              "four tripled ones (gap 2^-10) at n=2^17 (48 + 12 primes, dnum=4), k = the rank of the "
+                              "smallest tripled value, encrypted at level 47, comparator g^4 f, indicator g^4 f^2"),
         "rank512": dict(pset="P16", N=512, b=128, ci=(W.MULTI_RANK_CMP[512], None), what=4,
                         desc="multi-ciphertext rank of N=512 (gap 2^-10) in 4 blocks of 128 at n=2^16 (24 + 7 "
                              "primes, dnum=3), blocks encrypted at level 21, comparator g^4 f^2"),
@@ -319,7 +323,10 @@ def circuit_bench(args):
     queries, vals = [], []
     for i in range(B):
         tie = spec.get("q", {}).get("tie", False)
-        v, _, eseed = W.tied_workload(N, 2000 + i) if tie else W.rank_workload(N, 2.0 ** -10, 2000 + i)
+        if spec.get("q", {}).get("kind") == "div":
+            v, _, eseed = W.tripled_workload(N, 2000 + i, triples=4)
+        else:
+            v, _, eseed = W.tied_workload(N, 2000 + i) if tie else W.rank_workload(N, 2.0 ** -10, 2000 + i)
         vals.append(v)
         if multi:
             queries.append([ctx.encrypt(keys, v[j * b:(j + 1) * b], level, bytes([j]) + eseed[1:])
@@ -330,7 +337,22 @@ def circuit_bench(args):
                 q["ind"] = ind
             queries.append(q)
 
+    def div_k(v):
+        u, c = np.unique(v, return_counts=True)
+        t = u[c == 3].min()
+        return int(np.sum(v < t)) + 2, float(t)
+
     def step():
+        if spec.get("q", {}).get("kind") == "div":
+            # one batched call per k (each query's k is the rank of its smallest tripled value)
+            outs = [None] * B
+            ks = [div_k(v)[0] for v in vals]
+            for k in sorted(set(ks)):
+                idx = [i for i in range(B) if ks[i] == k]
+                res = ctx.order_stat_div(keys, [queries[i]["ct"] for i in idx], N, k, cmp, ind, spec["iters"])
+                for i, r in zip(idx, res):
+                    outs[i] = r
+            return outs
         if msort:
             return [ctx.sort_multi(keys, blk, b, cmp, ind) for blk in queries]
         if multi:
@@ -346,6 +368,8 @@ def circuit_bench(args):
             elif multi:
                 got = np.concatenate([ctx.decrypt(keys, r, b) for r in o])
                 worst = max(worst, float(np.max(np.abs(got - (np.argsort(np.argsort(v)) + 1)))))
+            elif spec["q"]["kind"] == "div":
+                worst = max(worst, abs(float(ctx.decrypt(keys, o[1], 1)[0]) - div_k(v)[1]))
             elif spec["q"]["kind"] == "rank":
                 worst = max(worst, float(np.max(np.abs(ctx.decrypt(keys, o, N) - (np.argsort(np.argsort(v)) + 1)))))
             elif spec["q"]["kind"] in ("sort", "sort_col"):
@@ -413,7 +437,7 @@ def main():
     ap.add_argument("--mixed", action="store_true", help="64 mixed rank/argmin queries in one launch instead")
     ap.add_argument("--workload", default="rank128",
                     choices=["rank128", "argmin128", "argmax128", "sort128", "rank512", "sort512", "rank128cheb",
-                             "argmin128cheb", "sort128col"],
+                             "argmin128cheb", "sort128col", "kth64div"],
                     help="circuit to time (rank128: the headline metric)")
     ap.add_argument("--rate", type=float, default=4.0)
     ap.add_argument("--serve-seconds", type=float, default=30.0)

@@ -191,6 +191,22 @@ ckr_status ckr_sort_col(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v,
 ckr_status ckr_order_stat(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, uint32_t k,
                           ckr_sign cmp, ckr_sign ind, int tie_correct, ckr_ct **onehot, ckr_ct **value);
 
+/* Order statistic k without tie-correction, with the value by division
+ * (section 3.2): the mask O (onehot, slots [0,N)) marks every element of
+ * fractional rank k -- several when equal values share that rank, none when
+ * no element has it -- and value slot 0 holds SumC(O v) / SumC(O), computed
+ * with `iters` (2..24) Goldschmidt steps on the count normalised by
+ * 2/(N + 1) (relative error (1 - x)^(2^iters), x = 2 count / (N + 1)).  With
+ * no element of rank k the value is 0 up to noise times 2^iters.  The
+ * `count` inputs (single ciphertexts at one level, borrowed) run as one
+ * batch; onehot[i] / value[i] (caller-owned) receive input i's results, the
+ * value at level(v) - ckr_order_stat_div_depth.  Errors: as ckr_order_stat,
+ * CKR_E_INVALID for iters outside [2, 24] or inputs at different levels. */
+ckr_status ckr_order_stat_div(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *const *v, size_t count, uint32_t N,
+                              uint32_t k, ckr_sign cmp, ckr_sign ind, uint32_t iters, ckr_ct **onehot,
+                              ckr_ct **value);
+uint32_t ckr_order_stat_div_depth(uint32_t N, uint32_t k, ckr_sign cmp, ckr_sign ind, uint32_t iters);
+
 /* Multi-ciphertext ranking (section 5, Algorithm Multi-Ciphertext Ranking),
  * for vectors with N^2 > n/2: v is split into L blocks of b values (b a power
  * of two with b^2 <= n/2), block i holding v[i*b .. (i+1)*b) in slots [0,b)

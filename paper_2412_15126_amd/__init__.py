@@ -78,6 +78,9 @@ _SIGS = {
     "ckr_sort": (C.c_int, [vp, vp, vp, C.c_uint32, Sign, Sign, C.POINTER(vp)]),
     "ckr_sort_col": (C.c_int, [vp, vp, vp, C.c_uint32, Sign, Sign, C.POINTER(vp)]),
     "ckr_sort_col_depth": (C.c_uint32, [Sign, Sign]),
+    "ckr_order_stat_div": (C.c_int, [vp, vp, C.POINTER(vp), C.c_size_t, C.c_uint32, C.c_uint32, Sign, Sign,
+                                     C.c_uint32, C.POINTER(vp), C.POINTER(vp)]),
+    "ckr_order_stat_div_depth": (C.c_uint32, [C.c_uint32, C.c_uint32, Sign, Sign, C.c_uint32]),
     "ckr_rank_batch": (C.c_int, [vp, vp, C.POINTER(vp), C.c_size_t, C.c_uint32, Sign, C.POINTER(vp)]),
     "ckr_ct_level": (C.c_uint32, [vp]),
     "ckr_ct_scale": (C.c_double, [vp]),
@@ -192,6 +195,10 @@ def sort_depth(cmp, ind):
     return int(lib().ckr_sort_depth(sign(cmp), sign(ind)))
 
 
+def order_stat_div_depth(N, k, cmp, ind, iters):
+    return int(lib().ckr_order_stat_div_depth(N, k, sign(cmp), sign(ind), iters))
+
+
 def sort_col_depth(cmp, ind):
     return int(lib().ckr_sort_col_depth(sign(cmp), sign(ind)))
 
@@ -286,6 +293,13 @@ class Context:
         h = vp()
         _ok(lib().ckr_sort(self.h, keys.h, ct.h, N, sign(cmp), sign(ind), C.byref(h)))
         return Ct(self, h)
+
+    def order_stat_div(self, keys, cts, N, k, cmp, ind, iters):
+        """[(mask, value)] per input: order statistic k without tie-correction, value by Goldschmidt division"""
+        arr = (vp * len(cts))(*[c.h for c in cts])
+        oh, val = (vp * len(cts))(), (vp * len(cts))()
+        _ok(lib().ckr_order_stat_div(self.h, keys.h, arr, len(cts), N, k, sign(cmp), sign(ind), iters, oh, val))
+        return [(Ct(self, vp(oh[i])), Ct(self, vp(val[i]))) for i in range(len(cts))]
 
     def sort_col(self, keys, ct, N, cmp, ind):
         """column-form sort: no final transposition, one level fewer"""

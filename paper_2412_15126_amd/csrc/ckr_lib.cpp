@@ -1449,6 +1449,43 @@ static void order_stat(Ctx &C, const Keys &K, const DCt &V, int N, int k, int ti
     value = sum_c(C, K, ev_mul(C, K, O, Va), N);
 }
 
+// Order statistic with the value by division (section 3.2): without
+// tie-correction the mask O of rank k may hold several ones (equal values share
+// a rank) or none; value = SumC(O V) / SumC(O) by Goldschmidt's iteration on
+// the count normalised to x = (2 / (N + 1)) SumC(MaskR(O)) in (0, 2):
+//   1/x ~ prod_{i<d} (1 + b^(2^i)),  b = 1 - x  (relative error b^(2^d)),
+// the first factor affine, each later one a squaring and a product; then
+// value = ((2 / (N + 1)) SumC(O V)) * prod.  d + 2 levels beyond the order
+// statistic.
+uint32_t order_stat_div_depth(int N, int k, ckr_sign c, ckr_sign i, int iters) {
+    return order_stat_depth(N, k, c, i, 0) + iters + 2;
+}
+
+static void order_stat_div(Ctx &C, const Keys &K, const DCt &V, int N, int k, ckr_sign cmp, ckr_sign ind, int iters,
+                           DCt &onehot, DCt &value) {
+    if (iters < 2 || iters > 24) throw Error{CKR_E_INVALID, "Goldschmidt iterations must lie in [2, 24]"};
+    check_N(C, (u32)N);
+    if (k < 1 || k > N) throw Error{CKR_E_INVALID, "k must lie in [1, N]"};
+    if ((u32)V.level < order_stat_div_depth(N, k, cmp, ind, iters))
+        throw Error{CKR_E_DEPTH, "not enough levels for the order statistic with division"};
+    DCt num;
+    order_stat(C, K, V, N, k, 0, cmp, ind, onehot, num);
+    const double s = 2.0 / ((double)N + 1.0);
+    DCt den = sum_c(C, K, onehot, N);
+    DCt x = ev_cmul_to(C, den, s, den.level - 1);
+    DCt nx = ev_mul_int(C, x, -1);
+    DCt b = ev_add_const(C, nx, 1.0);
+    DCt a = ev_add_const(C, nx, 2.0);
+    for (int i = 1; i < iters; i++) {
+        b = ev_mul(C, K, b, b);
+        DCt f = ev_add_const(C, b, 1.0);
+        DCt sa;
+        const DCt &aa = aligned(C, a, f.level, sa);
+        a = ev_mul(C, K, aa, f);
+    }
+    value = ev_mul(C, K, ev_cmul_to(C, num, s, a.level), a);
+}
+
 // Algorithm Sorting: M = Ind_0(ReplR(R) - (1^N || ... || N^N)) with
 // Ind_0(x) = Cmp(x, -1/2) (1 - Cmp(x, 1/2)) on (x +- 1/2)/N; S = TransC(SumC(M * ReplR(V)))
 static DCt sort(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, ckr_sign ind) {
@@ -2609,6 +2646,37 @@ ckr_status ckr_sort(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uin
         Ctx &C = *ctx->C;
         DCt r = sort(C, *keys->K, v->ct, (int)N, cmp, ind);
         *out = wrap(C, std::move(r));
+    });
+}
+
+uint32_t ckr_order_stat_div_depth(uint32_t N, uint32_t k, ckr_sign cmp, ckr_sign ind, uint32_t iters) {
+    return order_stat_div_depth((int)N, (int)k, cmp, ind, (int)iters);
+}
+
+ckr_status ckr_order_stat_div(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *const *v, size_t count, uint32_t N,
+                              uint32_t k, ckr_sign cmp, ckr_sign ind, uint32_t iters, ckr_ct **onehot,
+                              ckr_ct **value) {
+    return guard([&] {
+        NEED(ctx && keys && v && count && onehot && value);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
+        Ctx &C = *ctx->C;
+        std::vector<const DCt *> in;
+        for (size_t i = 0; i < count; i++) {
+            NEED(v[i]);
+            if (v[i]->ct.level != v[0]->ct.level) throw Error{CKR_E_INVALID, "inputs at different levels"};
+            in.push_back(&v[i]->ct);
+        }
+        DCt X, oh, val;
+        const DCt *xp = &v[0]->ct;
+        if (count > 1) {
+            X = stack(C, in);
+            xp = &X;
+        }
+        order_stat_div(C, *keys->K, *xp, (int)N, (int)k, cmp, ind, (int)iters, oh, val);
+        for (size_t i = 0; i < count; i++) {
+            onehot[i] = wrap(C, slice(C, oh, (int)i, 1));
+            value[i] = wrap(C, slice(C, val, (int)i, 1));
+        }
     });
 }
 

@@ -229,10 +229,34 @@ def sort128_p17_col():
             "sorted": [float(x) for x in np.sort(v)]}
 
 
+def kth64_p17s_div():
+    """order statistic with the value by division, N = 64 with four tripled values, at n = 2^17"""
+    N, iters = 64, 8
+    cmp, ind = W.ORDER_CMP[N]
+    O.set_threads(min(16, os.cpu_count() or 1))
+    P = O.Params(**W.PSETS["P17S"])
+    v, kseed, eseed = W.tripled_workload(N, 0, triples=4)
+    u, c = np.unique(v, return_counts=True)
+    t = float(u[c == 3].min())
+    k = int(np.sum(v < t)) + 2
+    level = O.order_stat_div_depth(N, k, cmp, ind, iters)
+    K = O.Keys(P, kseed, level, P.circuit_galois(N, 2))
+    oh, val = O.order_stat_div(K, O.encrypt(K, v, level, eseed), N, k, cmp, ind, iters)
+    return {"_what": "oracle order statistic with the value by division (Goldschmidt, 8 steps) of N=64 values with "
+                     "four tripled ones (tripled workload seed 0, gap 2^-10) at n=2^17 (P17S), k = the rank of the "
+                     "smallest tripled value, comparator g^4 f, indicator g^4 f^2: sha256 of the exported mask and "
+                     "value ciphertexts and their decoded contents",
+            "level": level, "k": k, "iters": iters, "value_expected": t,
+            "sha256": [hashlib.sha256(oh.export().tobytes()).hexdigest(),
+                       hashlib.sha256(val.export().tobytes()).hexdigest()],
+            "mask": [float(x) for x in O.decrypt(K, oh, N)],
+            "value": float(O.decrypt(K, val, 1)[0])}
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["rank128_p16", "argmin128_p17", "sort128_p17", "mixed_p16d", "argmax128_p17o",
                              "rank512_p16_multi", "sort512_p17s_multi", "rank128_p16_cheb",
-                             "argmin128_p17_cheb", "sort128_p17_col"]
+                             "argmin128_p17_cheb", "sort128_p17_col", "kth64_p17s_div"]
     for name in which:
         json.dump(globals()[name](), open(os.path.join(HERE, name + ".json"), "w"), indent=1)
         print("wrote", name + ".json", flush=True)

@@ -206,6 +206,26 @@ def test_sort128_column_form_full_size_matches_golden(p17):
     assert np.max(np.abs(ctx.decrypt(keys, s, N) - np.sort(v))) < 1e-3
 
 
+def test_kth64_division_full_size_matches_golden(ora):
+    """Order statistic with the value by division at n = 2^17 (48 + 12
+    primes): N = 64 with four tripled values, k = the smallest tripled value's
+    rank, 8 Goldschmidt steps, against the oracle-written digests."""
+    import paper_2412_15126_amd as ckr
+    gold = json.load(open(os.path.join(GOLD, "kth64_p17s_div.json")))
+    N = 64
+    cmp, ind = W.ORDER_CMP[N]
+    v, kseed, eseed = W.tripled_workload(N, 0, triples=4)
+    ctx = ckr.Context(W.PSETS["P17S"])
+    say("[gpu] P17S division keygen")
+    keys = ctx.keygen(kseed, gold["level"], [N], what=2)
+    say("[gpu] P17S order statistic with division")
+    (oh, val), = ctx.order_stat_div(keys, [ctx.encrypt(keys, v, gold["level"], eseed)], N, gold["k"], cmp, ind,
+                                    gold["iters"])
+    assert [hashlib.sha256(c.export().tobytes()).hexdigest() for c in (oh, val)] == gold["sha256"]
+    assert abs(ctx.decrypt(keys, val, 1)[0] - gold["value_expected"]) < 1e-3
+    assert np.array_equal(np.round(ctx.decrypt(keys, oh, N)), (v == gold["value_expected"]).astype(float))
+
+
 def test_sort128_full_size_matches_golden(p17):
     ctx, ps = p17
     gold = json.load(open(os.path.join(GOLD, "sort128_p17.json")))
@@ -513,3 +533,57 @@ def test_multi_ciphertext_sort512_full_size_matches_golden():
     assert [hashlib.sha256(s.export().tobytes()).hexdigest() for s in S] == gold["sha256"]
     got = np.concatenate([ctx.decrypt(keys, s, b) for s in S])
     assert np.max(np.abs(got - np.sort(v))) < 1e-3
+
+
+@pytest.fixture(scope="module")
+def t12e(ora):
+    import paper_2412_15126_amd as ckr
+    ps = W.PSETS["T12E"]
+    P = ora.Params(**ps)
+    seed = bytes(range(1, 33))
+    say("[gpu] T12E keys")
+    okeys = ora.Keys(P, seed, P.L, P.circuit_galois(8, 2))
+    ctx = ckr.Context(ps)
+    return dict(P=P, okeys=okeys, ctx=ctx, gkeys=ctx.keygen(seed, P.L, [8], what=2), ckr=ckr)
+
+
+def _tripled(N, seed):
+    v, _, eseed = W.tripled_workload(N, seed, triples=1, gap=0.01)
+    u, c = np.unique(v, return_counts=True)
+    t = u[np.argmax(c)]
+    return v, eseed, t, int(np.sum(v < t))
+
+
+def test_order_stat_division_bit_exact(ora, t12e):
+    """Section 3.2's value by division: a mask with three ones (the tripled
+    value's rank), an empty one (no element of that rank) and a batch of
+    three inputs, against the oracle bit for bit."""
+    P, ctx = t12e["P"], t12e["ctx"]
+    N, d = 8, 6
+    cmp, ind = W.ORDER_CMP[N]
+    v, eseed, t, below = _tripled(N, 5)
+    for k, want in ((below + 2, t), (below + 1, 0.0)):
+        level = ora.order_stat_div_depth(N, k, cmp, ind, d)
+        assert level == t12e["ckr"].order_stat_div_depth(N, k, cmp, ind, d)
+        say(f"[gpu] order statistic with division k={k}")
+        ooh, oval = ora.order_stat_div(t12e["okeys"], ora.encrypt(t12e["okeys"], v, level, eseed), N, k, cmp, ind, d)
+        (goh, gval), = ctx.order_stat_div(t12e["gkeys"], [ctx.encrypt(t12e["gkeys"], v, level, eseed)], N, k, cmp,
+                                          ind, d)
+        assert np.array_equal(ooh.export(), goh.export()) and np.array_equal(oval.export(), gval.export())
+        assert abs(ctx.decrypt(t12e["gkeys"], gval, 1)[0] - want) < 2e-3
+    k = below + 2
+    level = ora.order_stat_div_depth(N, k, cmp, ind, d)
+    cts = [ctx.encrypt(t12e["gkeys"], v, level, bytes([i]) + eseed[1:]) for i in range(3)]
+    singles = [ctx.order_stat_div(t12e["gkeys"], [c], N, k, cmp, ind, d)[0] for c in cts]
+    batch = ctx.order_stat_div(t12e["gkeys"], cts, N, k, cmp, ind, d)
+    for (a, b), (c, e) in zip(batch, singles):
+        assert np.array_equal(a.export(), c.export()) and np.array_equal(b.export(), e.export())
+
+
+def test_order_stat_division_rejects_bad_iterations(t12e):
+    ctx, ckr = t12e["ctx"], t12e["ckr"]
+    ct = ctx.encrypt(t12e["gkeys"], np.zeros(8), 10, bytes(32))
+    for iters in (0, 1, 25):
+        with pytest.raises(ckr.CkrError) as e:
+            ctx.order_stat_div(t12e["gkeys"], [ct], 8, 2, W.ORDER_CMP[8][0], W.ORDER_CMP[8][1], iters)
+        assert e.value.status == -1
