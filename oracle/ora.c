@@ -989,27 +989,28 @@ ora_ct *ora_repl_c(const ora_keys *Kp, const ora_ct *V, u32 N, int *st) {
 static const double F_COEF[4] = {35.0 / 16, -35.0 / 16, 21.0 / 16, -5.0 / 16};
 static const double G_COEF[4] = {4589.0 / 1024, -16577.0 / 1024, 25614.0 / 1024, -12860.0 / 1024};
 
-/* a1 x + a3 x^3 + a5 x^5 + a7 x^7 at depth 3:
- *   x2 = x*x, x4 = x2*x2, t3 = (a3 x)*x2, t7 = (a7 x)*x2, h = x4*(t7 + a5 x),
- *   p = h + t3 + a1 x with the last two brought to level l-3 by cmul_to. */
+/* a1 x + a3 x^3 + a5 x^5 + a7 x^7 (a7 != 0) at depth 3 with four products:
+ *   y = x*x, t = (a7 x)*y = a7 x^3, y2 = y*y, h = y2*(t + a5 x) = a7 x^7 + a5 x^5,
+ *   p = h + (a3/a7) t + a1 x, the last two terms brought to level l-3 by cmul_to
+ * (a3 x^3 comes from t by a constant product instead of a fifth ciphertext
+ * product). */
 ora_ct *ora_poly7(const ora_keys *Kp, const ora_ct *x, const double a[4], int *st) {
     int l = x->level;
     if (l < 3) { *st = ORA_E_DEPTH; return NULL; }
-    ora_ct *x2 = ora_mul(Kp, x, x, st);
-    ora_ct *x4 = ora_mul(Kp, x2, x2, st);
-    ora_ct *u3 = ora_cmul_to(x, a[1], l - 1, st);
-    ora_ct *t3 = ora_mul(Kp, u3, x2, st);
+    if (a[3] == 0.0) { *st = ORA_E_INVALID; return NULL; }
+    ora_ct *y = ora_mul(Kp, x, x, st);
     ora_ct *u7 = ora_cmul_to(x, a[3], l - 1, st);
-    ora_ct *t7 = ora_mul(Kp, u7, x2, st);
+    ora_ct *t = ora_mul(Kp, u7, y, st);
+    ora_ct *y2 = ora_mul(Kp, y, y, st);
     ora_ct *u5 = ora_cmul_to(x, a[2], l - 2, st);
-    ora_ct *w = ora_add(t7, u5);
-    ora_ct *h = ora_mul(Kp, x4, w, st);
-    ora_ct *v3 = ora_cmul_to(t3, 1.0, l - 3, st);
+    ora_ct *w = ora_add(t, u5);
+    ora_ct *h = ora_mul(Kp, y2, w, st);
+    ora_ct *v3 = ora_cmul_to(t, a[1] / a[3], l - 3, st);
     ora_ct *v1 = ora_cmul_to(x, a[0], l - 3, st);
     ora_ct *s1 = ora_add(h, v3);
     ora_ct *p = ora_add(s1, v1);
-    ora_ct_free(x2); ora_ct_free(x4); ora_ct_free(u3); ora_ct_free(t3); ora_ct_free(u7); ora_ct_free(t7);
-    ora_ct_free(u5); ora_ct_free(w); ora_ct_free(h); ora_ct_free(v3); ora_ct_free(v1); ora_ct_free(s1);
+    ora_ct_free(y); ora_ct_free(u7); ora_ct_free(t); ora_ct_free(y2); ora_ct_free(u5); ora_ct_free(w);
+    ora_ct_free(h); ora_ct_free(v3); ora_ct_free(v1); ora_ct_free(s1);
     return p;
 }
 

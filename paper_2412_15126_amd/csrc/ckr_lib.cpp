@@ -970,25 +970,21 @@ static DCt repl_c(Ctx &C, const Keys &K, const DCt &V, int N) {
 static const double kF[4] = {35.0 / 16, -35.0 / 16, 21.0 / 16, -5.0 / 16};
 static const double kG[4] = {4589.0 / 1024, -16577.0 / 1024, 25614.0 / 1024, -12860.0 / 1024};
 
-// a1 x + a3 x^3 + a5 x^5 + a7 x^7 in three levels:
-//   x2 = x^2, x4 = x2^2, t3 = (a3 x) x2, t7 = (a7 x) x2, h = x4 (t7 + a5 x),
-//   result = h + t3 + a1 x, the last two brought down to level l-3 by constant products
+// a1 x + a3 x^3 + a5 x^5 + a7 x^7 (a7 != 0) in three levels and four products:
+//   y = x^2, t = (a7 x) y = a7 x^3, y2 = y^2, h = y2 (t + a5 x) = a7 x^7 + a5 x^5,
+//   result = h + (a3/a7) t + a1 x, the last two brought down to level l-3 by
+//   constant products (a3 x^3 from t instead of a fifth ciphertext product)
 static DCt poly7(Ctx &C, const Keys &K, const DCt &x, const double a[4]) {
     const int l = x.level;
     if (l < 3) throw Error{CKR_E_DEPTH, "poly7 needs three levels"};
-    DCt x2 = ev_mul(C, K, x, x);
-    DCt x4 = ev_mul(C, K, x2, x2);
-    DCt u3 = ev_cmul_to(C, x, a[1], l - 1);
-    DCt t3 = ev_mul(C, K, u3, x2);
-    DCt u7 = ev_cmul_to(C, x, a[3], l - 1);
-    DCt t7 = ev_mul(C, K, u7, x2);
-    DCt u5 = ev_cmul_to(C, x, a[2], l - 2);
-    DCt w = ev_add(C, t7, u5, false);
-    DCt h = ev_mul(C, K, x4, w);
-    DCt v3 = ev_cmul_to(C, t3, 1.0, l - 3);
-    DCt v1 = ev_cmul_to(C, x, a[0], l - 3);
-    DCt s1 = ev_add(C, h, v3, false);
-    return ev_add(C, s1, v1, false);
+    if (a[3] == 0.0) throw Error{CKR_E_INVALID, "poly7 needs a degree-7 term"};
+    DCt y = ev_mul(C, K, x, x);
+    DCt t = ev_mul(C, K, ev_cmul_to(C, x, a[3], l - 1), y);
+    DCt y2 = ev_mul(C, K, y, y);
+    DCt w = ev_add(C, t, ev_cmul_to(C, x, a[2], l - 2), false);
+    DCt h = ev_mul(C, K, y2, w);
+    DCt s1 = ev_add(C, h, ev_cmul_to(C, t, a[1] / a[3], l - 3), false);
+    return ev_add(C, s1, ev_cmul_to(C, x, a[0], l - 3), false);
 }
 
 // ------------------------------------------------------------------------
