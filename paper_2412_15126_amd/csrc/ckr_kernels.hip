@@ -104,6 +104,16 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
     auto gaddr = [&](int r) -> u32 { return COLPASS ? (u32)(r * ncol + c) : (u32)(c * S + r); };
     auto lidx = [&](int cc, int r) -> int { return cc * SP + r + (r >> 4); };
 
+    // A column pass uses only the first S twiddles of its limb's table, the
+    // same for every column: they are staged in LDS once per workgroup (after
+    // the C*SP data words), so the butterflies read them there.
+    const double2 *twc = tw;
+    if constexpr (COLPASS) {
+        double2 *twl = reinterpret_cast<double2 *>(lds + ((C * SP + 1) & ~1));
+        for (int i = tid; i < S; i += NT) twl[i] = tw[i];
+        __syncthreads();
+        twc = twl;
+    }
     double x[E];
 
 #pragma unroll
@@ -154,7 +164,7 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
                     if (k & (1 << kb)) continue;
                     const int k2 = k | (1 << kb);
                     const int r = rbase | (k << w);
-                    const double2 W = tw[(1 << g) + (cpart << s) + (r >> (LOGS - s))];
+                    const double2 W = twc[(1 << g) + (cpart << s) + (r >> (LOGS - s))];
                     double u = x[k];
                     u = u >= two_q ? u - two_q : u;
                     const double v = mm_lazy(x[k2], W.x, W.y, q);
@@ -181,7 +191,7 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
                         x[k2] = mm_lazy(d, N1.x, N1.y, q);
                     } else {
                         const int r = rbase | (k << w);
-                        const double2 W = tw[(1 << g) + (cpart << s) + (r >> (LOGS - s))];
+                        const double2 W = twc[(1 << g) + (cpart << s) + (r >> (LOGS - s))];
                         x[k] = sm >= two_q ? sm - two_q : sm;
                         x[k2] = mm_lazy(d, W.x, W.y, q);
                     }
@@ -239,7 +249,7 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
              const NttFuse fz, const u64 *__restrict__ src, size_t src_stride, u32 gal) {
     constexpr int S = 1 << LOGS;
     constexpr int SP = S + (S >> 4) + 1;
-    __shared__ double lds[C * SP];
+    __shared__ __align__(16) double lds[((C * SP + 1) & ~1) + (COLPASS ? 2 * S : 0)];
 
     const int job = blockIdx.y;
     const int p = job / limbs, t = job - p * limbs;
