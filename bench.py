@@ -7,7 +7,11 @@ whole circuit: TransR/ReplR/ReplC re-encoding, all-pairs composite comparison
 (g applied 4 times, then f), SumR, +1/2.  Ciphertexts and keys are resident in
 HBM before the timed region starts.
 
-Prints one JSON line (see the design doc for the fields).
+Prints one JSON line: the metric and its value, the dominant kernel's
+roofline (algorithmic bytes per launch over its measured launch time, against
+the 8 TB/s HBM peak, with the copy-calibrated HBM traffic of the profiled
+kernel sources), per-category kernel rates and the oracle timed on the host.
+Other workloads: --workload, --mixed, --serve.
 """
 import argparse
 import json
@@ -445,8 +449,8 @@ def main():
     ap.add_argument("--hbm-budget", type=int, default=64, help="GiB of circuit working set in flight")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}): the path shards by query, "
-              "see DESIGN.md; run with --gpus 1", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): queries are independent and would "
+              "shard across GPUs by query with replicated keys; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
     if args.serve:

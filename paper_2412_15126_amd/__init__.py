@@ -125,7 +125,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: run paper_2412_15126_amd/build.py (or __graft_entry__.build())")
+            raise ImportError(f"{LIB_PATH} is missing: run paper_2412_15126_amd/build.py")
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
