@@ -1215,6 +1215,32 @@ static int check_N(const ora_params *P, u32 N) {
 /* levels consumed by rank: MaskC of TransR, the comparator, MaskR of SumR */
 int ora_rank_depth(ora_cmp cm) { return 2 + cmp_levels(cm); }
 
+/* Rank of N values that are not a power of two (section 3.1): the vector is
+ * padded with zeros to the next power of two Np and the comparison matrix is
+ * masked to its N x N block after the comparison, so the padding takes part
+ * in no comparison; one more level. */
+static u32 pow2_ceil(u32 N) { u32 p = 1; while (p < N) p <<= 1; return p; }
+
+static int check_N_padded(const ora_params *P, u32 N) {
+    u32 Np = pow2_ceil(N);
+    if (N < 2 || (u64)Np * Np > P->n / 2) return ORA_E_RANGE;
+    return ORA_OK;
+}
+
+int ora_rank_depth_n(u32 N, ora_cmp cm, int tie) {
+    return ora_rank_depth(cm) + (tie ? 2 : 0) + (pow2_ceil(N) != N ? 1 : 0);
+}
+
+/* C restricted to its N x N block in the Np x Np layout */
+static ora_ct *block_mask(const ora_ct *C, u32 N, u32 Np, int *st) {
+    double *z = (double *)calloc((size_t)Np * Np, sizeof(double));
+    for (u32 i = 0; i < N; i++)
+        for (u32 j = 0; j < N; j++) z[(size_t)i * Np + j] = 1.0;
+    ora_ct *r = ora_mul_plain(C, z, Np * Np, st);
+    free(z);
+    return r;
+}
+
 /* a * C with C = Cmp(V_R, V_C) as an N x N matrix (C[i][j] = Cmp(v_j, v_i)) */
 static ora_ct *cmp_matrix_scaled(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, double a, int *st) {
     ora_ct *VR = ora_repl_r(Kp, V, N, st);
@@ -1232,11 +1258,13 @@ ora_ct *ora_cmp_matrix(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, i
 }
 
 ora_ct *ora_rank(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, int *status) {
-    int st = check_N(Kp->P, N);
+    int st = check_N_padded(Kp->P, N);
     if (st != ORA_OK) { *status = st; return NULL; }
-    if (V->level < ora_rank_depth(cm)) { *status = ORA_E_DEPTH; return NULL; }
-    ora_ct *C = ora_cmp_matrix(Kp, V, N, cm, &st);
-    ora_ct *S = ora_sum_r(Kp, C, N, &st);
+    if (V->level < ora_rank_depth_n(N, cm, 0)) { *status = ORA_E_DEPTH; return NULL; }
+    const u32 Np = pow2_ceil(N);
+    ora_ct *C = ora_cmp_matrix(Kp, V, Np, cm, &st);
+    if (Np != N) replace(&C, block_mask(C, N, Np, &st));
+    ora_ct *S = ora_sum_r(Kp, C, Np, &st);
     double *half = (double *)malloc(N * sizeof(double));
     for (u32 j = 0; j < N; j++) half[j] = 0.5;
     ora_ct *R = ora_add_plain(S, half, N, &st);
@@ -1368,7 +1396,8 @@ int ora_sort_multi(const ora_keys *Kp, ora_ct *const *Bk, u32 L, u32 b, ora_cmp 
 }
 
 /* Galois elements needed by rank on N elements (left shifts as powers of 5) */
-int ora_rank_galois(const ora_params *P, u32 N, u32 *out) {
+int ora_rank_galois(const ora_params *P, u32 Nr, u32 *out) {
+    const u32 N = pow2_ceil(Nr); /* the padded layout */
     int cnt = 0, lg = ilog2(N);
     u64 h = P->n / 2;
     u64 shifts[256]; int ns = 0;
@@ -1421,8 +1450,10 @@ int ora_argmin_depth(ora_cmp cm, ora_cmp ci) { return ora_order_stat_depth(2, 1,
  * Rank plus the Tie-Correction Offset of section 4 (their +1/2 and -1/2
  * cancel), a permutation of 1..N.  Levels: TransR mask, comparator, E,
  * E * tie mask, SumR mask. */
-static ora_ct *tie_rank(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, int *st) {
+static ora_ct *tie_rank(const ora_keys *Kp, const ora_ct *V, u32 Nr, ora_cmp cm, int *st) {
+    const u32 N = pow2_ceil(Nr); /* layout; Nr < N pads (section 3.1) */
     ora_ct *C = ora_cmp_matrix(Kp, V, N, cm, st);
+    if (N != Nr) replace(&C, block_mask(C, Nr, N, st));
     ora_ct *m4 = mul_int(C, -4);
     ora_ct *w = ora_add_const(m4, 4.0);
     ora_ct *E = ora_mul(Kp, C, w, st);
@@ -1440,9 +1471,9 @@ static ora_ct *tie_rank(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, 
 }
 
 ora_ct *ora_rank_tie(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, int *status) {
-    int st = check_N(Kp->P, N);
+    int st = check_N_padded(Kp->P, N);
     if (st != ORA_OK) { *status = st; return NULL; }
-    if (V->level < ora_rank_depth(cm) + 2) { *status = ORA_E_DEPTH; return NULL; }
+    if (V->level < ora_rank_depth_n(N, cm, 1)) { *status = ORA_E_DEPTH; return NULL; }
     ora_ct *kv = tie_rank(Kp, V, N, cm, &st);
     *status = st;
     return kv;
@@ -1656,7 +1687,8 @@ ora_ct *ora_sort_col(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, ora
 
 /* Galois elements needed by the circuits: bit 0 rank, bit 1 argmin (adds
  * SumC), bit 2 sort (adds SumC and TransC) */
-int ora_circuit_galois(const ora_params *P, u32 N, int what, u32 *out) {
+int ora_circuit_galois(const ora_params *P, u32 Nr, int what, u32 *out) {
+    const u32 N = pow2_ceil(Nr);
     int cnt = ora_rank_galois(P, N, out), lg = ilog2(N);
     u64 h = P->n / 2;
     u64 shifts[64]; int ns = 0;

@@ -121,6 +121,7 @@ def lib():
             "ora_circuit_galois": (C.c_int, [vp, C.c_uint32, C.c_int, u32p]),
             "ora_cheb_step_coeffs": (None, [C.c_int, dblp]),
             "ora_sort_col_depth": (C.c_int, [OraCmp, OraCmp]),
+            "ora_rank_depth_n": (C.c_int, [C.c_uint32, OraCmp, C.c_int]),
             "ora_order_stat_div_depth": (C.c_int, [C.c_uint32, C.c_uint32, OraCmp, OraCmp, C.c_int]),
             "ora_order_stat_div": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32, OraCmp, OraCmp, C.c_int, C.POINTER(vp),
                                              C.POINTER(vp)]),
@@ -549,3 +550,8 @@ def order_stat_div(keys, a, N, k, cmp, ind, iters):
     if st != 0:
         raise OracleError(f"order_stat_div: status {STATUS.get(st, st)}")
     return Ct(oh.value, a.params), Ct(val.value, a.params)
+
+
+def rank_depth_n(N, cmp, tie=False):
+    """levels of rank (tie-corrected if tie) on N values, one more when N is not a power of two"""
+    return lib().ora_rank_depth_n(N, _cmp(cmp), int(tie))

@@ -364,3 +364,19 @@ def order_stat_div_circuit(v, N, slots, k, cmp, ind, iters):
     s = 2.0 / (N + 1.0)
     den = sum_c(O, N)
     return O, (s * num) * goldschmidt_inverse(s * den, iters)
+
+
+def rank_padded(v, slots, cmp):
+    """Algorithm Rank on len(v) values that need not be a power of two
+    (section 3.1): zero-padded to the next power of two Np, the comparison
+    matrix masked to its N x N block before SumR."""
+    N = len(v)
+    Np = 1 << (N - 1).bit_length()
+    x = embed(v, slots)
+    VR = repl_r(x, Np)
+    VC = repl_c(trans_r(x, Np), Np)
+    Cm = comparator(cmp)(VR, VC)
+    block = np.zeros(slots)
+    for i in range(N):
+        block[i * Np:i * Np + N] = 1.0
+    return sum_r(Cm * block, Np) + embed(np.full(N, 0.5), slots)

@@ -474,3 +474,47 @@ def test_oracle_order_stat_division_matches_shadow(ora, t12e):
     sO, sval = S.order_stat_div_circuit(v, N, P.n // 2, k, cmp, ind, d)
     assert abs(got - sval[0]) < 1e-3 and abs(got - t) < 1e-3
     assert np.array_equal(np.round(ora.decrypt(keys, oh, N)), (v == t).astype(float))
+
+
+@pytest.mark.parametrize("N", [3, 5, 6, 7, 12])
+def test_shadow_padded_rank_is_exact(N):
+    """Rank of N values that are not a power of two (section 3.1): padded with
+    zeros and the comparison matrix masked to its N x N block, the ideal
+    comparator gives the exact ranks of the real values (the zeros of the
+    padding are not counted), ties included."""
+    rng = np.random.default_rng(N)
+    v = rng.uniform(0.0, 1.0, N)
+    v[N // 2] = v[0]                          # a tie
+    Np = 1 << (N - 1).bit_length()
+    R = S.rank_padded(v, 4 * Np * Np, "ideal")
+    less = (v[None, :] < v[:, None]).sum(axis=1)
+    equal = (v[None, :] == v[:, None]).sum(axis=1)
+    assert np.array_equal(R[:N], less + 0.5 * (equal + 1))
+
+
+def test_oracle_padded_rank_matches_shadow(ora, t12d):
+    P, keys = t12d
+    cmp = W.RANK_CMP[8]
+    for N in (5, 7):
+        depth = ora.rank_depth_n(N, cmp)
+        assert depth == ora.rank_depth(*cmp) + 1
+        assert ora.rank_depth_n(8, cmp) == ora.rank_depth(*cmp)
+        v, _, eseed = W.rank_workload(N, 0.01, N)
+        r = ora.rank(keys, ora.encrypt(keys, v, depth, eseed), N, *cmp)
+        assert r.level == 0
+        got = ora.decrypt(keys, r, N)
+        assert np.max(np.abs(got - S.rank_padded(v, P.n // 2, cmp)[:N])) < 1e-3
+        assert np.array_equal(np.round(got), np.argsort(np.argsort(v)) + 1)
+
+
+def test_oracle_padded_tie_rank_is_a_permutation(ora, t12d):
+    P, keys = t12d
+    cmp = W.ORDER_TIE_CMP[8][0]
+    N = 6
+    v = np.array([0.3, 0.7, 0.3, 0.1, 0.9, 0.7])
+    depth = ora.rank_depth_n(N, cmp, True)
+    r = ora.rank_tie(keys, ora.encrypt(keys, v, depth, bytes(range(2, 34))), N, *cmp)
+    got = ora.decrypt(keys, r, N)
+    want = np.empty(N)
+    want[np.argsort(v, kind="stable")] = np.arange(1, N + 1)
+    assert np.max(np.abs(got - want)) < 0.05
