@@ -124,7 +124,9 @@ ckr_status ckr_context_memory(const ckr_context *ctx, size_t *in_use, size_t *hi
  * and the rotation keys the circuits need for every N in Ns[0..nN).  Keys
  * cover limbs q_0..q_max_level plus the special primes and stay resident on
  * the device.  `what` selects circuits: bit 0 rank, bit 1 argmin, bit 2 sort
- * (their rotation sets differ). */
+ * (their rotation sets differ; bits 1 and 2 add the conjugation key).  An N
+ * that is not a power of two gets the keys of the next power of two, the
+ * layout its padded rank uses. */
 ckr_status ckr_keygen(ckr_context *ctx, const uint8_t seed[32], uint32_t max_level, const uint32_t *Ns, size_t nN,
                       uint32_t what, ckr_keys **out);
 void ckr_keys_free(ckr_keys *keys);
@@ -143,13 +145,19 @@ ckr_status ckr_decrypt(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *ct,
 
 /* Fractional ranking (Algorithm Rank): out slots [0,N) hold rank(v_j).
  * tie_correct != 0 adds the tie-correction offset (section 4), so the output
- * is a permutation of 1..N.  The output sits at level(v) - depth. */
+ * is a permutation of 1..N.  N need not be a power of two (section 3.1): the
+ * vector is then zero-padded to the next power of two Np (slots [N, Np) of v
+ * must be zero, as ckr_encrypt leaves them) and the comparison matrix is
+ * masked to its N x N block, one more level.  Keys: those of ckr_keygen for
+ * N (generated for Np).  The output sits at level(v) - ckr_rank_depth_n(N).
+ * Errors: CKR_E_RANGE (N < 2 or Np^2 > n/2), CKR_E_DEPTH, CKR_E_INVALID. */
 ckr_status ckr_rank(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, ckr_sign cmp, int tie_correct,
                     ckr_ct **out);
 
 /* Levels consumed by ckr_rank / ckr_argmin / ckr_sort / ckr_order_stat for
  * the given comparators. */
 uint32_t ckr_rank_depth(ckr_sign cmp, int tie_correct);
+uint32_t ckr_rank_depth_n(uint32_t N, ckr_sign cmp, int tie_correct);
 uint32_t ckr_argmin_depth(ckr_sign cmp, ckr_sign ind);
 uint32_t ckr_sort_depth(ckr_sign cmp, ckr_sign ind);
 uint32_t ckr_sort_col_depth(ckr_sign cmp, ckr_sign ind);

@@ -64,6 +64,7 @@ _SIGS = {
     "ckr_decrypt": (C.c_int, [vp, vp, vp, dblp, C.c_uint32]),
     "ckr_rank": (C.c_int, [vp, vp, vp, C.c_uint32, Sign, C.c_int, C.POINTER(vp)]),
     "ckr_rank_depth": (C.c_uint32, [Sign, C.c_int]),
+    "ckr_rank_depth_n": (C.c_uint32, [C.c_uint32, Sign, C.c_int]),
     "ckr_argmin_depth": (C.c_uint32, [Sign, Sign]),
     "ckr_order_stat_depth": (C.c_uint32, [C.c_uint32, C.c_uint32, Sign, Sign, C.c_int]),
     "ckr_order_stat": (C.c_int, [vp, vp, vp, C.c_uint32, C.c_uint32, Sign, Sign, C.c_int, C.POINTER(vp),
@@ -173,6 +174,11 @@ def sample(seed, purpose, oid, kind, q, count):
 
 def rank_depth(cmp, tie=False):
     return int(lib().ckr_rank_depth(sign(cmp), int(tie)))
+
+
+def rank_depth_n(N, cmp, tie=False):
+    """levels of rank on N values (one more when N is not a power of two)"""
+    return int(lib().ckr_rank_depth_n(N, sign(cmp), int(tie)))
 
 
 def rank_multi_depth(cmp):

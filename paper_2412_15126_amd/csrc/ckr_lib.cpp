@@ -841,7 +841,7 @@ static DCt ev_plus_conj(Ctx &C, const Keys &K, const DCt &a) { return ev_galois_
 
 // plaintext holding z on slots [0, count) at scale D_level, eval domain [level+1][n]
 enum PlainKind { kMaskRow0 = 1, kMaskCol0 = 2, kHalfRow0 = 3, kTieMask = 4, kSteps = 5, kNegHalfRow0 = 6,
-                 kStepsBlock = 7, kHalfCol0 = 8, kStepsCol = 9 };
+                 kStepsBlock = 7, kHalfCol0 = 8, kStepsCol = 9, kBlockMask = 10 };
 
 static Buf encode_plain(Ctx &C, const std::vector<double> &z, int level) {
     const size_t n = C.n();
@@ -876,6 +876,10 @@ static std::vector<double> plain_values(int kind, int N, int arg) {
     case kStepsBlock:  // -((N arg + 1)^N || ... || (N arg + N)^N): the ranks of output block arg
         for (int i = 0; i < N; i++)
             for (int j = 0; j < N; j++) z[(size_t)i * N + j] = -((double)N * arg + i + 1);
+        break;
+    case kBlockMask:  // 1 on the arg x arg block of the N x N layout
+        for (int i = 0; i < arg; i++)
+            for (int j = 0; j < arg; j++) z[(size_t)i * N + j] = 1.0;
         break;
     case kHalfCol0:  // 1/2 on column 0
         for (int i = 0; i < N; i++) z[(size_t)i * N] = 0.5;
@@ -1249,6 +1253,21 @@ static void check_N(const Ctx &C, u32 N) {
 
 // levels: TransR mask, comparator, SumR mask (+ E and E * tie mask with tie-correction)
 uint32_t rank_depth(ckr_sign c, int tie) { return 2 + cmp_levels(c) + (tie ? 2 : 0); }
+
+// Rank of N values that are not a power of two (section 3.1): zero-padded to
+// the next power of two Np, the comparison matrix masked to its N x N block
+// after the comparison so the padding takes part in no comparison; one more
+// level.
+static int pow2_ceil(int N) {
+    int p = 1;
+    while (p < N) p <<= 1;
+    return p;
+}
+static void check_N_padded(const Ctx &C, u32 N) {
+    const u64 Np = (u64)pow2_ceil((int)N);
+    if (N < 2 || Np * Np > C.n() / 2) throw Error{CKR_E_RANGE, "N must be >= 2 with next_pow2(N)^2 <= n/2"};
+}
+uint32_t rank_depth_n(int N, ckr_sign c, int tie) { return rank_depth(c, tie) + (pow2_ceil(N) != N ? 1 : 0); }
 // order statistic k: TransR mask, comparator, [E, E * tie mask, SumR mask,
 // scaling,] indicator (+1 for the two-sided window), O * V, SumC mask
 uint32_t order_stat_depth(int N, int k, ckr_sign c, ckr_sign i, int tie) {
@@ -1271,22 +1290,27 @@ static DCt cmp_matrix(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, 
 }
 
 static DCt rank(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, DCt *VR_out = nullptr) {
-    check_N(C, (u32)N);
+    check_N_padded(C, (u32)N);
     check_sign(cmp);
-    if ((u32)V.level < rank_depth(cmp, 0)) throw Error{CKR_E_DEPTH, "not enough levels for rank"};
-    DCt Cm = cmp_matrix(C, K, V, N, cmp, VR_out);
-    DCt S = sum_r(C, K, Cm, N);
+    if ((u32)V.level < rank_depth_n(N, cmp, 0)) throw Error{CKR_E_DEPTH, "not enough levels for rank"};
+    const int Np = pow2_ceil(N);
+    DCt Cm = cmp_matrix(C, K, V, Np, cmp, VR_out);
+    if (Np != N) Cm = ev_mul_plain(C, Cm, get_plain(C, kBlockMask, Np, Cm.level, N));
+    DCt S = sum_r(C, K, Cm, Np);
     return ev_add_plain(C, S, get_plain(C, kHalfRow0, N, S.level));
 }
 
 // tie-corrected rank k_j = SumR(C + E (delta_{j>=i} - 1/2)), E = C (4 - 4C):
 // rank plus the tie-correction offset (their +1/2 and -1/2 cancel), a
 // permutation of 1..N with equal values ranked in index order
-static DCt tie_rank(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp) {
-    check_N(C, (u32)N);
+static DCt tie_rank(Ctx &C, const Keys &K, const DCt &V, int Nr, ckr_sign cmp) {
+    check_N_padded(C, (u32)Nr);
     check_sign(cmp);
-    if ((u32)V.level < rank_depth(cmp, 1)) throw Error{CKR_E_DEPTH, "not enough levels for the tie-corrected rank"};
+    if ((u32)V.level < rank_depth_n(Nr, cmp, 1))
+        throw Error{CKR_E_DEPTH, "not enough levels for the tie-corrected rank"};
+    const int N = pow2_ceil(Nr);  // the layout; Nr < N pads
     DCt Cm = cmp_matrix(C, K, V, N, cmp);
+    if (N != Nr) Cm = ev_mul_plain(C, Cm, get_plain(C, kBlockMask, N, Cm.level, Nr));
     DCt w = ev_add_const(C, ev_mul_int(C, Cm, -4), 4.0);
     DCt E = ev_mul(C, K, Cm, w);
     DCt Et = ev_mul_plain(C, E, get_plain(C, kTieMask, N, E.level));
@@ -1545,7 +1569,7 @@ enum CircuitKind { kRankCircuit = 1, kArgminCircuit = 2, kSortCircuit = 3, kOrde
 
 // levels a circuit consumes
 static uint32_t spec_depth(const Spec &s) {
-    if (s.kind == kRankCircuit) return rank_depth(s.cmp, s.tie);
+    if (s.kind == kRankCircuit) return rank_depth_n(s.N, s.cmp, s.tie);
     if (s.kind == kSortCircuit) return sort_depth(s.cmp, s.ind);
     if (s.kind == kSortColCircuit) return sort_col_depth(s.cmp, s.ind);
     return order_stat_depth(s.N, s.k, s.cmp, s.ind, s.tie);
@@ -1554,7 +1578,8 @@ static uint32_t spec_depth(const Spec &s) {
 // the circuit of a (kind, N, compositions) request; argmin is the
 // tie-corrected order statistic k = 1
 static Spec spec_of(const Ctx &C, int kind, int N, int k, int tie, ckr_sign cmp, ckr_sign ind) {
-    check_N(C, (u32)N);
+    if (kind == kRankCircuit) check_N_padded(C, (u32)N);
+    else check_N(C, (u32)N);
     Spec s;
     s.N = N;
     s.cmp = cmp;
@@ -2085,7 +2110,8 @@ static void parallel_for(int count, const std::function<void(int)> &fn) {
 }
 
 // Galois elements the circuits need for one N
-static void circuit_shifts(u32 N, u32 what, std::vector<i64> &sh) {
+static void circuit_shifts(u32 Nr, u32 what, std::vector<i64> &sh) {
+    const u32 N = (u32)pow2_ceil((int)Nr);  // a padded rank uses the next power of two's layout
     const int l = lg((int)N);
     for (int i = 1; i <= l; i++) sh.push_back(-(i64)(((i64)N * (N - 1)) >> i));  // TransR
     for (int i = 0; i < l; i++) sh.push_back(-((i64)N << i));                     // ReplR
@@ -2191,7 +2217,7 @@ ckr_status ckr_keygen(ckr_context *ctx, const uint8_t seed[32], uint32_t max_lev
         Ctx &C = *ctx->C;
         const Params &P = C.P;
         if ((int)max_level > P.L) throw Error{CKR_E_DEPTH, "max_level above the chain"};
-        for (size_t i = 0; i < nN; i++) check_N(C, Ns[i]);
+        for (size_t i = 0; i < nN; i++) check_N_padded(C, Ns[i]);  // keys of the padded layout
         auto K = std::make_unique<Keys>();
         K->C = &C;
         K->lmax = (int)max_level;
@@ -2422,6 +2448,7 @@ uint32_t ckr_order_stat_depth(uint32_t N, uint32_t k, ckr_sign cmp, ckr_sign ind
 }
 uint32_t ckr_sort_depth(ckr_sign cmp, ckr_sign ind) { return sort_depth(cmp, ind); }
 uint32_t ckr_sort_col_depth(ckr_sign cmp, ckr_sign ind) { return sort_col_depth(cmp, ind); }
+uint32_t ckr_rank_depth_n(uint32_t N, ckr_sign cmp, int tie) { return rank_depth_n((int)N, cmp, tie); }
 
 ckr_status ckr_rank(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *v, uint32_t N, ckr_sign cmp, int tie,
                     ckr_ct **out) {
@@ -2479,7 +2506,8 @@ ckr_status ckr_server_add_route(ckr_server *srv, int kind, uint32_t N, ckr_conte
     return guard([&] {
         NEED(srv && ctx && keys);
         if (kind < 1 || kind > 3) throw Error{CKR_E_INVALID, "kind"};
-        check_N(*ctx->C, N);
+        if (kind == kRankCircuit) check_N_padded(*ctx->C, N);
+        else check_N(*ctx->C, N);
         Route r{kind, (int)N, ctx->C.get(), keys->K.get(), cmp, ind};
         srv->S->add_route(r);
     });

@@ -587,3 +587,32 @@ def test_order_stat_division_rejects_bad_iterations(t12e):
         with pytest.raises(ckr.CkrError) as e:
             ctx.order_stat_div(t12e["gkeys"], [ct], 8, 2, W.ORDER_CMP[8][0], W.ORDER_CMP[8][1], iters)
         assert e.value.status == -1
+
+
+@pytest.mark.parametrize("N,tie", [(5, False), (7, False), (6, True)])
+def test_padded_rank_bit_exact(ora, small, N, tie):
+    """Rank of N values that are not a power of two (section 3.1): zero-padded,
+    comparison matrix masked to its N x N block; single, batched and replayed
+    against the oracle."""
+    P, ctx = small["P"], small["ctx"]
+    cmp = W.ORDER_TIE_CMP[8][0] if tie else W.RANK_CMP[8]
+    level = ora.rank_depth_n(N, cmp, tie)
+    assert level == small["ckr"].rank_depth_n(N, cmp, tie)
+    qs = [(W.tied_workload(N, 30 + i, 0.01) if tie else W.rank_workload(N, 0.01, 30 + i)) for i in range(3)]
+    say(f"[gpu] padded rank N={N} tie={tie}")
+    for v, _, eseed in qs[:1]:
+        o = ora.encrypt(small["okeys"], v, level, eseed)
+        ro = ora.rank_tie(small["okeys"], o, N, *cmp) if tie else ora.rank(small["okeys"], o, N, *cmp)
+        rg = ctx.rank(small["gkeys"], ctx.encrypt(small["gkeys"], v, level, eseed), N, cmp, tie=tie)
+        assert np.array_equal(ro.export(), rg.export())
+        want = np.empty(N)
+        want[np.argsort(v, kind="stable")] = np.arange(1, N + 1)
+        if not tie:
+            want = np.argsort(np.argsort(v)) + 1
+        assert np.array_equal(np.round(ctx.decrypt(small["gkeys"], rg, N)), want)
+    if not tie:
+        cts = [ctx.encrypt(small["gkeys"], v, level, e) for v, _, e in qs]
+        singles = [ctx.rank(small["gkeys"], c, N, cmp).export() for c in cts]
+        for rep in range(3):
+            outs = ctx.run_batch(small["gkeys"], "rank", cts, N, cmp)
+            assert all(np.array_equal(a.export(), b) for a, b in zip(outs, singles))

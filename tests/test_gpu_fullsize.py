@@ -122,3 +122,25 @@ def test_rank128_chebyshev_full_size_matches_golden(full):
 def ctx_rank_depth(cmp):
     import paper_2412_15126_amd as ckr
     return ckr.rank_depth(cmp)
+
+
+def test_rank100_padded_full_size_bit_exact(ora):
+    """N = 100 values at n = 2^16, padded to the 128 layout with the
+    comparison matrix masked to its 100 x 100 block (section 3.1), against
+    the oracle run here; ranks exact."""
+    import paper_2412_15126_amd as ckr
+    N, cmp = 100, W.RANK_CMP[128]
+    level = ckr.rank_depth_n(N, cmp)
+    assert level == ora.rank_depth_n(N, cmp) == LEVEL + 1
+    v, kseed, eseed = W.rank_workload(N, 2.0 ** -10, 7)
+    ps = W.PSETS["P16"]
+    say("[gpu] P16 padded rank-100 device")
+    ctx = ckr.Context(ps)
+    gk = ctx.keygen(kseed, level, [N])
+    rg = ctx.rank(gk, ctx.encrypt(gk, v, level, eseed), N, cmp)
+    say("[gpu] P16 padded rank-100 oracle")
+    P = ora.Params(**ps)
+    ok = ora.Keys(P, kseed, level, P.rank_galois(N))
+    ro = ora.rank(ok, ora.encrypt(ok, v, level, eseed), N, *cmp)
+    assert np.array_equal(ro.export(), rg.export())
+    assert np.array_equal(np.round(ctx.decrypt(gk, rg, N)), np.argsort(np.argsort(v)) + 1)

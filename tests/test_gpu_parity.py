@@ -139,7 +139,10 @@ def test_errors_reported(ckr, t10):
         t10.ctx.rotate(t10.gkeys, g, 77)       # no key for this shift
     assert e.value.status == -1
     with pytest.raises(ckr.CkrError) as e:
-        t10.ctx.rank(t10.gkeys, g, 6, (2, 1))  # N not a power of two
+        t10.ctx.sort(t10.gkeys, g, 6, (2, 1), (2, 2))  # sort: N must be a power of two
+    assert e.value.status == -2
+    with pytest.raises(ckr.CkrError) as e:
+        t10.ctx.rank(t10.gkeys, g, 17, (2, 1))  # rank pads 17 to 32: 32^2 > 512 slots
     assert e.value.status == -2
     with pytest.raises(ckr.CkrError) as e:
         t10.ctx.rank(t10.gkeys, g, 8, (2, 1))  # level 0: too shallow
