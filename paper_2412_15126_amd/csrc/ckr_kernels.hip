@@ -611,22 +611,16 @@ __global__ void ew_automorph(u64 *out, const u64 *in, int limbs, size_t so, size
 // source, then for each target t: sum_i y_i * hmod[i][t] mod t.  Lazy products
 // are < 2t, so for t < 2^47 the NS-term sum stays exact below 2^52 and is
 // reduced once; larger targets reduce after every term.
+// The conversion constants are the same for every thread of a workgroup: they
+// are read through restrict pointers, which the compiler serves from the
+// scalar cache (no LDS staging, no barrier).
 template <int NS>
 __global__ void __launch_bounds__(256)
-    ew_bconv(u64 *out, const u64 *src, BConvTab tab, int logn, size_t so, size_t si, const double2 *mq, int tpg) {
-    __shared__ double2 hm[NS * kMaxLimbArgs];
-    __shared__ double3 tq3[kMaxLimbArgs];
+    ew_bconv(u64 *out, const u64 *__restrict__ src, BConvTab tab, const double2 *__restrict__ hmod,
+             const double2 *__restrict__ hinv, int logn, size_t so, size_t si, const double2 *__restrict__ mq,
+             int tpg) {
     const size_t n = (size_t)1 << logn;
-    const int j0 = blockIdx.z * tpg, j1 = min(j0 + tpg, tab.nt), nj = j1 - j0;
-    for (int k = threadIdx.x; k < NS * nj; k += blockDim.x) {
-        const int i = k / nj, j = k - i * nj;
-        hm[i * kMaxLimbArgs + j] = tab.hmod[i * tab.nt + j0 + j];
-    }
-    for (int j = threadIdx.x; j < nj; j += blockDim.x) {
-        const double2 Q = mq[tab.tgt_mod[j0 + j]];
-        tq3[j] = make_double3(Q.x, Q.y, (double)tab.tgt_slot[j0 + j]);
-    }
-    __syncthreads();
+    const int j0 = blockIdx.z * tpg, j1 = min(j0 + tpg, tab.nt);
     const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
     const u64 *sb = src + blockIdx.y * si;
@@ -635,30 +629,30 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int i = 0; i < NS; i++) {
         const double q = mq[tab.src_mod[i]].x;
-        const double2 h = tab.hinv[i];
+        const double2 h = hinv[i];
         y[i] = red1(mm_lazy(u2d(sb[(size_t)i * n + c]), h.x, h.y, q), q);
     }
-    for (int j = 0; j < nj; j++) {
-        const double3 T3 = tq3[j];
-        const double tq = T3.x, two_t = 2.0 * tq;
+    for (int j = j0; j < j1; j++) {
+        const double2 Q = mq[tab.tgt_mod[j]];
+        const double tq = Q.x, two_t = 2.0 * tq;
         double acc = 0.0;
         if (tq * (2 * NS) < C52) {
 #pragma unroll
             for (int i = 0; i < NS; i++) {
-                const double2 h = hm[i * kMaxLimbArgs + j];
+                const double2 h = hmod[i * tab.nt + j];
                 acc += mm_lazy(y[i], h.x, h.y, tq);
             }
-            acc = red_any(acc, tq, T3.y);
+            acc = red_any(acc, tq, Q.y);
         } else {
 #pragma unroll
             for (int i = 0; i < NS; i++) {
-                const double2 h = hm[i * kMaxLimbArgs + j];
+                const double2 h = hmod[i * tab.nt + j];
                 acc += mm_lazy(y[i], h.x, h.y, tq);
                 acc = acc >= two_t ? acc - two_t : acc;
             }
             acc = red1(acc, tq);
         }
-        ob[(size_t)T3.z * n + c] = d2u(acc);
+        ob[(size_t)tab.tgt_slot[j] * n + c] = d2u(acc);
     }
 }
 
@@ -754,7 +748,8 @@ void k_bconv(const DevTables &T, u64 *out, const u64 *src, const BConvTab &tab, 
     dim3 grid((unsigned)(((1u << T.logn) + 255) / 256), (unsigned)batch, (unsigned)groups);
 #define BCONV_CASE(K)                                                                                       \
     case K:                                                                                                 \
-        hipLaunchKernelGGL(ew_bconv<K>, grid, dim3(256), 0, s, out, src, tab, T.logn, so, si, T.mq, tpg); \
+        hipLaunchKernelGGL(ew_bconv<K>, grid, dim3(256), 0, s, out, src, tab, tab.hmod, tab.hinv, T.logn, so, si, \
+                           T.mq, tpg);                                                                        \
         break;
     switch (tab.ns) {
         BCONV_CASE(1) BCONV_CASE(2) BCONV_CASE(3) BCONV_CASE(4) BCONV_CASE(5) BCONV_CASE(6) BCONV_CASE(7)
