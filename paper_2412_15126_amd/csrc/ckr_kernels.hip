@@ -47,7 +47,7 @@ __device__ __forceinline__ double mm_signed(double x, double y, double q, double
 }
 __device__ __forceinline__ double red1(double x, double q) { return x >= q ? x - q : x; }  // [0,2q) -> [0,q)
 __device__ __forceinline__ double pos1(double x, double q) { return x < 0 ? x + q : x; }   // (-q,q) -> [0,q)
-// x in [0, 2^53) -> x mod q
+// integer-valued x in (-2^53, 2^53) -> x mod q in [0, q)
 __device__ __forceinline__ double red_any(double x, double q, double qinv) {
     double k = floor(x * qinv);
     double r = __fma_rn(-k, q, x);
@@ -336,9 +336,12 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
             kbw[k] = kb[pos];
             kaw[k] = ka[pos];
         }
+        // products in (-0.75q, 0.75q) accumulate unreduced: exact while the
+        // sums stay below 2^53 in magnitude (the library allows at most 8
+        // digits; a reduction every 8 keeps any count safe)
         auto acc = [&](int k, u32, double x) {
-            sb[k] = red1(sb[k] + pos1(mm_signed(x, u2d(kbw[k]), q, qinv), q), q);
-            sa[k] = red1(sa[k] + pos1(mm_signed(x, u2d(kaw[k]), q, qinv), q), q);
+            sb[k] += mm_signed(x, u2d(kbw[k]), q, qinv);
+            sa[k] += mm_signed(x, u2d(kaw[k]), q, qinv);
         };
         if (j == own) {
             const u64 *xs = a.d + bi * a.sd + (size_t)t * n;
@@ -357,13 +360,20 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
             pass_core<LOGS, LOGE, C, false, false, false>(a.ext + bi * a.sext + ((size_t)j * a.E + t) * n, c0, logn,
                                                           mod, q, qinv, tw, twlast, lds, acc);
         }
+        if ((j & 7) == 7) {
+#pragma unroll
+            for (int k = 0; k < E; k++) {
+                sb[k] = red_any(sb[k], q, qinv);
+                sa[k] = red_any(sa[k], q, qinv);
+            }
+        }
     }
     u64 *ob = a.accb + bi * a.sacc + (size_t)t * n, *oa = a.acca + bi * a.sacc + (size_t)t * n;
 #pragma unroll
     for (int k = 0; k < E; k++) {
         const u32 pos = (u32)(c0 * S + tid + k * NT);
-        ob[pos] = d2u(sb[k]);
-        oa[pos] = d2u(sa[k]);
+        ob[pos] = d2u(red_any(sb[k], q, qinv));
+        oa[pos] = d2u(red_any(sa[k], q, qinv));
     }
 }
 

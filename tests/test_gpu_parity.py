@@ -247,6 +247,20 @@ def test_keyswitch_other_ring_sizes_bit_exact(ora, ckr, logn):
         same(ora.mul(pr.okeys, o, o), pr.ctx.mul(pr.gkeys, g, g), f"mul level {level}")
 
 
+def test_keyswitch_many_digits_bit_exact(ora, ckr):
+    """One prime per digit and the library's largest digit count, 8 at the
+    top level: the inner product accumulates its 8 products unreduced before
+    reducing."""
+    ps = dict(logn=10, L=7, q0_bits=44, log_scale=36, K=1, p_bits=46, dnum=8)
+    say("[gpu] key switch with 8 digits")
+    pr = Pair(ora, ckr, ps, ps["L"], shifts=(3,))
+    v = np.random.default_rng(12).uniform(0, 1, pr.n // 2)
+    for level in (ps["L"], 5, 2):
+        o, g = pr.enc(v, level, bytes([level] * 32))
+        same(ora.rotate(pr.okeys, o, 3), pr.ctx.rotate(pr.gkeys, g, 3), f"rotate level {level}")
+        same(ora.mul(pr.okeys, o, o), pr.ctx.mul(pr.gkeys, g, g), f"mul level {level}")
+
+
 def test_row_ip_tile_variants_bit_identical(ckr):
     """Every tile of the fused row pass + inner product gives the same
     relinearised product at n = 2^16 (rows of 2^8 points)."""
