@@ -1424,24 +1424,40 @@ u32 ora_galois_left(const ora_params *P, u64 k) { return gal_left(P, k); }
 ora_ct *ora_mul_int(const ora_ct *a, i64 K) { return mul_int(a, K); }
 
 /* Order statistic k (Algorithm Order Statistic, section 3.2), optionally with
- * the tie-correction offset of section 4.  The indicator of "the k-th
- * smallest" is one-sided at the ends (k = 1: Cmp(1.5, k_j); k = N:
- * Cmp(k_j, N - 1/2); the k_j are integral) and the window
- * Cmp(x, -1/2) (1 - Cmp(x, 1/2)) on x = k_j - k otherwise, every comparison
- * taken on its argument divided by N.
+ * the tie-correction offset of section 4, generalised to a window of ranks
+ * [a, b] (a = b = k is the order statistic).  Section 4 obtains the median of
+ * an even count from the statistics N/2 and N/2 + 1 and a product by 1/2
+ * after the inner product; with the window [N/2, N/2 + 1] both are extracted
+ * by one mask, and value = SumC(O * V) / (b - a + 1) is the mean of the
+ * statistics a..b, the factor folded into the plaintext constant that brings V
+ * to the mask's level (no extra level; 1 when a = b).
+ *
+ * The indicator of "rank in [a, b]" is one-sided at the ends (a = 1:
+ * Cmp(b + 1/2, k_j); b = N: Cmp(k_j, a - 1/2); the k_j are integral) and the
+ * window Cmp(k_j, a - 1/2) (1 - Cmp(k_j, b + 1/2)) otherwise, every comparison
+ * taken on its argument divided by N.  a = 1 with b = N selects everything and
+ * is rejected.
  *
  * With tie-correction, k_j = SumR(C + E (delta_{j>=i} - 1/2)), E = C (4 - 4C)
  * (rank plus offset; their +1/2 and -1/2 cancel), which is a permutation of
- * 1..N: among equal values the lowest index is taken first.
+ * 1..N: among equal values the lowest index is taken first.  N that is not a
+ * power of two is padded (section 3.1) and needs tie-correction: the padding's
+ * k_j are 0, outside every window with a >= 1, or selected by the a = 1 window
+ * where V is zero; the one-hot keeps only the first N slots.
  * Without it, k_j is the rank R_j = SumR(C) + 1/2; the factor +-1/N is folded
  * into the comparator's last polynomial, and SumR keeps no row mask: the
  * other rows hold bounded garbage that O * V annihilates (V is zero outside
- * row 0).  onehot = MaskR(O, 0); value = SumC(O * V) in slot 0. */
-int ora_order_stat_depth(u32 N, u32 k, ora_cmp cm, ora_cmp ci, int tie) {
-    int ind = cmp_levels(ci) + ((k > 1 && k < N) ? 1 : 0);
-    /* TransR mask, comparator, [E, E*mask, SumR mask, scaling,] indicator, O*V, SumC mask;
+ * row 0).  onehot = MaskR(O, 0); value in slot 0. */
+int ora_order_range_depth(u32 N, u32 a, u32 b, ora_cmp cm, ora_cmp ci, int tie) {
+    int ind = cmp_levels(ci) + ((a > 1 && b < N) ? 1 : 0);
+    /* [block mask,] TransR mask, comparator, [E, E*mask, SumR mask, scaling,] indicator, O*V, SumC mask;
      * without tie-correction a Chebyshev indicator keeps the SumR mask */
-    return 1 + cmp_levels(cm) + (tie ? 4 : 0) + ((!tie && ci.cheb > 0) ? 1 : 0) + ind + 2;
+    return (pow2_ceil(N) != N ? 1 : 0) + 1 + cmp_levels(cm) + (tie ? 4 : 0) + ((!tie && ci.cheb > 0) ? 1 : 0) +
+           ind + 2;
+}
+
+int ora_order_stat_depth(u32 N, u32 k, ora_cmp cm, ora_cmp ci, int tie) {
+    return ora_order_range_depth(N, k, k, cm, ci, tie);
 }
 
 int ora_argmin_depth(ora_cmp cm, ora_cmp ci) { return ora_order_stat_depth(2, 1, cm, ci, 1); }
@@ -1479,43 +1495,44 @@ ora_ct *ora_rank_tie(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, int
     return kv;
 }
 
-int ora_order_stat(const ora_keys *Kp, const ora_ct *V, u32 N, u32 k, ora_cmp cm, ora_cmp ci, int tie,
-                   ora_ct **onehot, ora_ct **value) {
-    int st = check_N(Kp->P, N);
-    if (st != ORA_OK) return st;
-    if (k < 1 || k > N) return ORA_E_INVALID;
-    if (V->level < ora_order_stat_depth(N, k, cm, ci, tie)) return ORA_E_DEPTH;
-    const double dN = (double)N, dk = (double)k;
+static int order_range(const ora_keys *Kp, const ora_ct *V, u32 N, u32 a, u32 b, ora_cmp cm, ora_cmp ci,
+                       int tie, ora_ct **onehot, ora_ct **value) {
+    const u32 Np = pow2_ceil(N); /* the layout; N < Np pads */
+    if (a < 1 || a > b || b > N || (a == 1 && b == N)) return ORA_E_INVALID;
+    if (Np != N && !tie) return ORA_E_INVALID;
+    if (V->level < ora_order_range_depth(N, a, b, cm, ci, tie)) return ORA_E_DEPTH;
+    int st = ORA_OK;
+    const double dN = (double)N, da = (double)a, db = (double)b;
+    const int lower = a == 1; /* only the upper bound b + 1/2 is tested */
     /* a Chebyshev indicator takes the real part of its argument (plus_conj),
      * the 1/2 folded into the scaling; without tie-correction its argument
      * also keeps the SumR row mask, so that every slot lies in [-1, 1] */
     const int proj = ci.cheb > 0;
     const double sN = proj ? 2.0 * dN : dN;
-    ora_ct *base; /* k_j (times +-1/N) */
+    ora_ct *base; /* k_j (times -1/N when a = 1, else 1/N) */
     double off1, off2 = 0.0; /* constants giving the indicator argument(s) */
     if (tie) {
         ora_ct *kv = tie_rank(Kp, V, N, cm, &st);
-        base = ora_cmul_to(kv, k == 1 ? -1.0 / sN : 1.0 / sN, kv->level - 1, &st);
-        if (k == 1) off1 = 1.5 / dN;
-        else if (k == N) off1 = (0.5 - dN) / dN;
-        else off1 = (0.5 - dk) / dN, off2 = (-0.5 - dk) / dN;
+        base = ora_cmul_to(kv, lower ? -1.0 / sN : 1.0 / sN, kv->level - 1, &st);
+        if (lower) off1 = (db + 0.5) / dN;
+        else off1 = (0.5 - da) / dN, off2 = (-0.5 - db) / dN;
         ora_ct_free(kv);
     } else {
-        ora_ct *C = cmp_matrix_scaled(Kp, V, N, cm, k == 1 ? -1.0 / sN : 1.0 / sN, &st);
+        ora_ct *C = cmp_matrix_scaled(Kp, V, N, cm, lower ? -1.0 / sN : 1.0 / sN, &st);
         if (proj) {
             base = ora_sum_r(Kp, C, N, &st);
         } else {
             base = ct_copy(C);
             for (int i = 0; i < ilog2(N); i++) replace(&base, add_rot(Kp, base, (i64)N << i, &st));
         }
-        if (k == 1) off1 = 1.0 / dN;
-        else if (k == N) off1 = (1.0 - dN) / dN;
-        else off1 = (1.0 - dk) / dN, off2 = -dk / dN;
+        /* SumR(C) = R_j - 1/2 */
+        if (lower) off1 = db / dN;
+        else off1 = (1.0 - da) / dN, off2 = -db / dN;
         ora_ct_free(C);
     }
     if (proj) replace(&base, plus_conj(Kp, base, &st));
     ora_ct *O;
-    if (k == 1 || k == N) {
+    if (lower || b == N) {
         ora_ct *y = ora_add_const(base, off1);
         O = ora_cmp_sign(Kp, y, ci, &st);
         ora_ct_free(y);
@@ -1532,11 +1549,28 @@ int ora_order_stat(const ora_keys *Kp, const ora_ct *V, u32 N, u32 k, ora_cmp cm
     for (u32 j = 0; j < N; j++) row[j] = 1.0;
     *onehot = ora_mul_plain(O, row, N, &st);
     free(row);
-    ora_ct *Va = ora_cmul_to(V, 1.0, O->level, &st);
+    ora_ct *Va = ora_cmul_to(V, 1.0 / (db - da + 1.0), O->level, &st);
     ora_ct *P = ora_mul(Kp, O, Va, &st);
-    *value = ora_sum_c(Kp, P, N, &st);
+    *value = ora_sum_c(Kp, P, Np, &st);
     ora_ct_free(base); ora_ct_free(O); ora_ct_free(Va); ora_ct_free(P);
     return st;
+}
+
+int ora_order_stat(const ora_keys *Kp, const ora_ct *V, u32 N, u32 k, ora_cmp cm, ora_cmp ci, int tie,
+                   ora_ct **onehot, ora_ct **value) {
+    int st = check_N(Kp->P, N);
+    if (st != ORA_OK) return st;
+    if (k < 1 || k > N) return ORA_E_INVALID;
+    return order_range(Kp, V, N, k, k, cm, ci, tie, onehot, value);
+}
+
+/* mean of the order statistics a..b (the median of an even N is a = N/2,
+ * b = N/2 + 1; of an odd N, a = b = (N + 1)/2) */
+int ora_order_range(const ora_keys *Kp, const ora_ct *V, u32 N, u32 a, u32 b, ora_cmp cm, ora_cmp ci, int tie,
+                    ora_ct **onehot, ora_ct **value) {
+    int st = check_N_padded(Kp->P, N);
+    if (st != ORA_OK) return st;
+    return order_range(Kp, V, N, a, b, cm, ci, tie, onehot, value);
 }
 
 /* Order statistic with the value by division (section 3.2): without

@@ -116,6 +116,9 @@ def lib():
             "ora_order_stat_depth": (C.c_int, [C.c_uint32, C.c_uint32, OraCmp, OraCmp, C.c_int]),
             "ora_order_stat": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32, OraCmp, OraCmp, C.c_int, C.POINTER(vp),
                                          C.POINTER(vp)]),
+            "ora_order_range_depth": (C.c_int, [C.c_uint32, C.c_uint32, C.c_uint32, OraCmp, OraCmp, C.c_int]),
+            "ora_order_range": (C.c_int, [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32, OraCmp, OraCmp, C.c_int,
+                                          C.POINTER(vp), C.POINTER(vp)]),
             "ora_sort_depth": (C.c_int, [OraCmp, OraCmp]),
             "ora_sort": (vp, [vp, vp, C.c_uint32, OraCmp, OraCmp, intp]),
             "ora_circuit_galois": (C.c_int, [vp, C.c_uint32, C.c_int, u32p]),
@@ -517,6 +520,22 @@ def order_stat(keys, a, N, k, cmp, ind, tie):
     if st != 0:
         raise OracleError(f"order_stat: status {STATUS.get(st, st)}")
     return Ct(oh.value, a.params), Ct(val.value, a.params)
+
+
+def order_range_depth(N, a, b, cmp, ind, tie):
+    return lib().ora_order_range_depth(N, a, b, _cmp(cmp), _cmp(ind), int(tie))
+
+
+def order_range(keys, ct, N, a, b, cmp, ind, tie):
+    """(mask, value): the mask of the elements of rank a..b and the mean of
+    the order statistics a..b (the median for a = N/2, b = N/2 + 1); N need
+    not be a power of two when tie-corrected"""
+    keys.need(N, 2)
+    oh, val = C.c_void_p(), C.c_void_p()
+    st = lib().ora_order_range(keys.ptr, ct.ptr, N, a, b, _cmp(cmp), _cmp(ind), int(tie), C.byref(oh), C.byref(val))
+    if st != 0:
+        raise OracleError(f"order_range: status {STATUS.get(st, st)}")
+    return Ct(oh.value, ct.params), Ct(val.value, ct.params)
 
 
 def sort_depth(cmp, ind):

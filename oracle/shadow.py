@@ -380,3 +380,46 @@ def rank_padded(v, slots, cmp):
     for i in range(N):
         block[i * Np:i * Np + N] = 1.0
     return sum_r(Cm * block, Np) + embed(np.full(N, 0.5), slots)
+
+
+def order_range_circuit(v, slots, a, b, cmp, ind, tie):
+    """Mean of the order statistics a..b of the len(v) values (section 3.2,
+    with the median of section 4: a = N/2, b = N/2 + 1 for even N), as the
+    circuit evaluates it: the tie-corrected rank k_j (or, without
+    tie-correction, the rank) in the zero-padded layout of side Np, the
+    indicator Cmp(b + 1/2, k_j) when a = 1, Cmp(k_j, a - 1/2) when b = N and
+    Cmp(k_j, a - 1/2) (1 - Cmp(k_j, b + 1/2)) otherwise, every argument divided
+    by N; value = SumC(O x) / (b - a + 1).  Returns (O masked to the first N
+    slots of row 0, value slot vector, k_j vector)."""
+    N = len(v)
+    Np = 1 << (N - 1).bit_length()
+    x = embed(v, slots)
+    VR = repl_r(x, Np)
+    VC = repl_c(trans_r(x, Np), Np)
+    Cm = cmp_of(VR - VC, cmp)
+    if Np != N:
+        block = np.zeros(slots)
+        for i in range(N):
+            block[i * Np:i * Np + N] = 1.0
+        Cm = Cm * block
+    if tie:
+        E = Cm * (4.0 - 4.0 * Cm)
+        tm = np.zeros(slots)
+        for i in range(Np):
+            tm[i * Np:(i + 1) * Np] = np.where(np.arange(Np) >= i, 0.5, -0.5)
+        kv = sum_r(Cm + E * tm, Np)
+    else:
+        kv = Cm.copy()
+        for i in range(log2i(Np)):
+            kv = kv + rot_left(kv, Np << i)
+        kv = kv + 0.5
+    if a == 1:
+        O = cmp_of((b + 0.5 - kv) / N, ind)
+    elif b == N:
+        O = cmp_of((kv - a + 0.5) / N, ind)
+    else:
+        O = cmp_of((kv - a + 0.5) / N, ind) * (1.0 - cmp_of((kv - b - 0.5) / N, ind))
+    val = sum_c(O * x, Np) / (b - a + 1)
+    oh = np.zeros(slots)
+    oh[:N] = O[:N]
+    return oh, val, kv

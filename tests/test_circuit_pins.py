@@ -518,3 +518,113 @@ def test_oracle_padded_tie_rank_is_a_permutation(ora, t12d):
     want = np.empty(N)
     want[np.argsort(v, kind="stable")] = np.arange(1, N + 1)
     assert np.max(np.abs(got - want)) < 0.05
+
+
+def _window_mean(v, a, b):
+    """mean of the order statistics a..b (1-based) of v"""
+    return float(np.mean(np.sort(v)[a - 1:b]))
+
+
+@pytest.mark.parametrize("N", [5, 6, 7, 8, 12, 16])
+def test_shadow_order_range_ideal_is_exact(N):
+    """The rank window with the ideal comparator and indicator: the mask holds
+    exactly the elements of tie-corrected rank a..b (lowest index first among
+    equal values), the value is the mean of the statistics a..b, the median
+    of section 4 included (both middle statistics halved for an even N, the
+    middle one for an odd N), padded layouts included."""
+    rng = np.random.default_rng(70 + N)
+    v = np.round(rng.uniform(0.0, 1.0, N), 2)
+    v[N - 1] = v[1]                                   # a tie
+    Np = 1 << (N - 1).bit_length()
+    order = np.argsort(v, kind="stable")
+    windows = {(1, 1), (N, N), (1, N - 1), (2, N), (2, max(2, N - 2))}
+    windows.add((N // 2, N // 2 + 1) if N % 2 == 0 else ((N + 1) // 2, (N + 1) // 2))
+    for a, b in sorted(windows):
+        oh, val, kv = S.order_range_circuit(v, 4 * Np * Np, a, b, "ideal", "ideal", True)
+        want = np.zeros(N)
+        want[order[a - 1:b]] = 1.0
+        assert np.array_equal(oh[:N], want), (a, b)
+        assert abs(val[0] - _window_mean(v, a, b)) < 1e-12, (a, b)
+        assert np.all(oh[N:] == 0.0)
+    med = S.order_range_circuit(v, 4 * Np * Np, *(((N // 2, N // 2 + 1)) if N % 2 == 0 else
+                                                  ((N + 1) // 2, (N + 1) // 2)), "ideal", "ideal", True)[1][0]
+    assert abs(med - np.median(v)) < 1e-12
+
+
+@pytest.mark.parametrize("N", [8, 128])
+def test_shadow_order_range_reduces_to_order_statistic(N):
+    """a = b = k is the order statistic: identical slot vectors, both with and
+    without tie-correction, under the composite comparators."""
+    for tie in (False, True):
+        gap = 0.01 if N == 8 else 2.0 ** -10
+        v, _, _ = (W.tied_workload(N, 3, gap) if tie else W.rank_workload(N, gap, 3))
+        for k in (1, N // 2, N):
+            cmp, ind = (W.ARGMIN_CMP[N] if k == 1 else W.ORDER_TIE_CMP[N]) if tie else W.ORDER_CMP[N]
+            o1, v1, k1 = S.order_stat_circuit(v, N, 2 * N * N, k, cmp, ind, tie)
+            o2, v2, k2 = S.order_range_circuit(v, 2 * N * N, k, k, cmp, ind, tie)
+            assert np.array_equal(k1, k2) and np.array_equal(v1, v2) and np.array_equal(o1, o2)
+
+
+@pytest.mark.parametrize("N", [8, 128])
+def test_shadow_median_with_composites(N):
+    """Median of an even N (section 4) with the configured composites: the
+    window [N/2, N/2 + 1] selects both middle elements, the value is their
+    mean, distinct and tied inputs."""
+    gap = 0.01 if N == 8 else 2.0 ** -10
+    for seed in range(4):
+        for tie in (False, True):
+            v, _, _ = (W.tied_workload(N, 90 + seed, gap) if tie else W.rank_workload(N, gap, 90 + seed))
+            cmp, ind = W.ORDER_TIE_CMP[N] if tie else W.ORDER_CMP[N]
+            oh, val, _ = S.order_range_circuit(v, 2 * N * N, N // 2, N // 2 + 1, cmp, ind, tie)
+            order = np.argsort(v, kind="stable")
+            want = np.zeros(N)
+            want[order[N // 2 - 1:N // 2 + 1]] = 1.0
+            assert np.array_equal(np.round(oh[:N]), want), (seed, tie)
+            assert abs(val[0] - np.median(v)) < 1e-2, (seed, tie)
+
+
+def test_oracle_order_range_k_equals_order_statistic_bits(ora, t12d):
+    """The order statistic is the window a = b = k: identical ciphertexts."""
+    P, keys = t12d
+    N = 8
+    v, _, eseed = W.tied_workload(N, 11, 0.01)
+    ct = ora.encrypt(keys, v, P.L, eseed)
+    for k, tie in ((1, True), (5, True), (8, False)):
+        cmp, ind = (W.ARGMIN_CMP[N] if k == 1 else W.ORDER_TIE_CMP[N]) if tie else W.ORDER_CMP[N]
+        assert ora.order_range_depth(N, k, k, cmp, ind, tie) == ora.order_stat_depth(N, k, cmp, ind, tie)
+        a_oh, a_val = ora.order_stat(keys, ct, N, k, cmp, ind, tie)
+        b_oh, b_val = ora.order_range(keys, ct, N, k, k, cmp, ind, tie)
+        assert np.array_equal(a_oh.export(), b_oh.export()) and np.array_equal(a_val.export(), b_val.export())
+
+
+@pytest.mark.parametrize("N,a,b,tie", [(8, 4, 5, True), (8, 4, 5, False), (8, 1, 3, True), (8, 6, 8, False),
+                                       (6, 3, 4, True), (7, 4, 4, True), (5, 1, 2, True), (7, 5, 7, True)])
+def test_oracle_order_range_matches_shadow(ora, t12d, N, a, b, tie):
+    """Encrypted rank window (median, lower and upper ranges, padded N) against
+    the slot shadow and the exact mean of the statistics a..b."""
+    P, keys = t12d
+    cmp, ind = W.ORDER_TIE_CMP[8] if tie else W.ORDER_CMP[8]
+    v, _, eseed = (W.tied_workload(N, 20 + N, 0.01) if tie else W.rank_workload(N, 0.01, 20 + N))
+    depth = ora.order_range_depth(N, a, b, cmp, ind, tie)
+    pad = 1 if (N & (N - 1)) else 0
+    assert depth == ora.order_stat_depth(8, 2 if (a > 1 and b < N) else 1, cmp, ind, tie) + pad
+    oh, val = ora.order_range(keys, ora.encrypt(keys, v, depth, eseed), N, a, b, cmp, ind, tie)
+    assert val.level == 0 and oh.level == 1
+    got_oh, got_val = ora.decrypt(keys, oh, N), ora.decrypt(keys, val, 1)[0]
+    sh_oh, sh_val, _ = S.order_range_circuit(v, P.n // 2, a, b, cmp, ind, tie)
+    assert np.max(np.abs(got_oh - sh_oh[:N])) < 1e-3 and abs(got_val - sh_val[0]) < 1e-3
+    want = np.zeros(N)
+    want[np.argsort(v, kind="stable")[a - 1:b]] = 1.0
+    assert np.array_equal(np.round(got_oh), want)
+    assert abs(got_val - _window_mean(v, a, b)) < 0.01
+
+
+def test_oracle_order_range_rejects(ora, t12d):
+    P, keys = t12d
+    cmp, ind = W.ORDER_TIE_CMP[8]
+    ct = ora.encrypt(keys, np.linspace(0.1, 0.8, 8), P.L, bytes(32))
+    for N, a, b, tie in ((8, 1, 8, True), (8, 0, 2, True), (8, 3, 2, True), (8, 2, 9, True), (6, 2, 3, False)):
+        with pytest.raises(ora.OracleError, match="invalid"):
+            ora.order_range(keys, ct, N, a, b, cmp, ind, tie)
+    with pytest.raises(ora.OracleError, match="depth"):
+        ora.order_range(keys, ora.encrypt(keys, np.linspace(0.1, 0.8, 8), 3, bytes(32)), 8, 4, 5, cmp, ind, True)
