@@ -270,6 +270,10 @@ def circuit_bench(args):
                           desc="tie-corrected argmax of N=128 (96 distinct values + 32 duplicates, gap 2^-10) at "
                                "n=2^17 (45 + 11 primes, dnum=4), encrypted at level 44, comparator and indicator "
                                "g^4 f^2"),
+        "median128": dict(pset="P17O", N=128, q=dict(kind="median", tie=True), ci=W.ORDER_TIE_CMP[128], what=2,
+                          desc="tie-corrected median of N=128 (rank window [64, 65], the mean of the two middle "
+                               "statistics; 96 distinct values + 32 duplicates, gap 2^-10) at n=2^17 (45 + 11 "
+                               "primes, dnum=4), encrypted at level 44, comparator and indicator g^4 f^2"),
         "sort128": dict(pset="P17", N=128, q=dict(kind="sort"), ci=W.SORT_CMP[128], what=4,
                         desc="sort of N=128 (gap 2^-10) at n=2^17 (41 + 10 primes, dnum=4), encrypted at level 40, "
                              "comparator g^4 f, indicator g^4 f^2"),
@@ -347,6 +351,8 @@ def circuit_bench(args):
         return int(np.sum(v < t)) + 2, float(t)
 
     def step():
+        if spec.get("q", {}).get("kind") == "median":
+            return ctx.median(keys, [q["ct"] for q in queries], N, cmp, ind)
         if spec.get("q", {}).get("kind") == "div":
             # one batched call per k (each query's k is the rank of its smallest tripled value)
             outs = [None] * B
@@ -374,6 +380,12 @@ def circuit_bench(args):
                 worst = max(worst, float(np.max(np.abs(got - (np.argsort(np.argsort(v)) + 1)))))
             elif spec["q"]["kind"] == "div":
                 worst = max(worst, abs(float(ctx.decrypt(keys, o[1], 1)[0]) - div_k(v)[1]))
+            elif spec["q"]["kind"] == "median":
+                m = np.zeros(N)
+                m[np.argsort(v, kind="stable")[N // 2 - 1:N // 2 + 1]] = 1.0
+                if not np.array_equal(np.round(ctx.decrypt(keys, o[0], N)), m):
+                    return False, float("inf")
+                worst = max(worst, abs(float(ctx.decrypt(keys, o[1], 1)[0]) - float(np.median(v))))
             elif spec["q"]["kind"] == "rank":
                 worst = max(worst, float(np.max(np.abs(ctx.decrypt(keys, o, N) - (np.argsort(np.argsort(v)) + 1)))))
             elif spec["q"]["kind"] in ("sort", "sort_col"):
@@ -441,7 +453,7 @@ def main():
     ap.add_argument("--mixed", action="store_true", help="64 mixed rank/argmin queries in one launch instead")
     ap.add_argument("--workload", default="rank128",
                     choices=["rank128", "argmin128", "argmax128", "sort128", "rank512", "sort512", "rank128cheb",
-                             "argmin128cheb", "sort128col", "kth64div"],
+                             "argmin128cheb", "sort128col", "kth64div", "median128"],
                     help="circuit to time (rank128: the headline metric)")
     ap.add_argument("--rate", type=float, default=4.0)
     ap.add_argument("--serve-seconds", type=float, default=30.0)

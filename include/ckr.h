@@ -215,6 +215,30 @@ ckr_status ckr_order_stat_div(ckr_context *ctx, const ckr_keys *keys, const ckr_
                               ckr_ct **value);
 uint32_t ckr_order_stat_div_depth(uint32_t N, uint32_t k, ckr_sign cmp, ckr_sign ind, uint32_t iters);
 
+/* Order statistics over a window of ranks [a, b] (Algorithm Order Statistic,
+ * section 3.2, with its median remark of section 4): onehot slots [0,N) hold 1
+ * at the elements whose rank lies in [a, b] and 0 elsewhere; value slot 0
+ * holds the mean of the order statistics a..b (SumC(O v) / (b - a + 1)).  The
+ * median of an even N is a = N/2, b = N/2 + 1, of an odd N a = b = (N + 1)/2;
+ * a = b = k gives ckr_order_stat's result bit for bit.  With tie_correct != 0
+ * equal values take consecutive ranks, lowest index first, and N need not be
+ * a power of two (zero-padded to the next one, section 3.1; the keys must be
+ * made for that N); without it N is a power of two and the values distinct.
+ * The indicator `ind` is one-sided for a = 1 (Cmp(b + 1/2, k_j)) and b = N
+ * (Cmp(k_j, a - 1/2)), the window Cmp(k_j, a - 1/2) (1 - Cmp(k_j, b + 1/2))
+ * otherwise, each argument over N.  The `count` inputs (single ciphertexts at
+ * one level, borrowed) run as one batch (graph-captured after the first call
+ * of a shape); onehot[i] / value[i] (caller-owned) receive input i's results,
+ * onehot at level(v) - depth + 1, value at level(v) - depth
+ * (ckr_order_range_depth).  Errors: CKR_E_RANGE (N), CKR_E_INVALID (not
+ * 1 <= a <= b <= N, the window [1, N], a padded N without tie-correction,
+ * empty composition, inputs not single ciphertexts of one level),
+ * CKR_E_DEPTH. */
+ckr_status ckr_order_range(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *const *v, size_t count, uint32_t N,
+                           uint32_t a, uint32_t b, ckr_sign cmp, ckr_sign ind, int tie_correct, ckr_ct **onehot,
+                           ckr_ct **value);
+uint32_t ckr_order_range_depth(uint32_t N, uint32_t a, uint32_t b, ckr_sign cmp, ckr_sign ind, int tie_correct);
+
 /* Multi-ciphertext ranking (section 5, Algorithm Multi-Ciphertext Ranking),
  * for vectors with N^2 > n/2: v is split into L blocks of b values (b a power
  * of two with b^2 <= n/2), block i holding v[i*b .. (i+1)*b) in slots [0,b)

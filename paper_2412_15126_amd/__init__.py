@@ -82,6 +82,9 @@ _SIGS = {
     "ckr_order_stat_div": (C.c_int, [vp, vp, C.POINTER(vp), C.c_size_t, C.c_uint32, C.c_uint32, Sign, Sign,
                                      C.c_uint32, C.POINTER(vp), C.POINTER(vp)]),
     "ckr_order_stat_div_depth": (C.c_uint32, [C.c_uint32, C.c_uint32, Sign, Sign, C.c_uint32]),
+    "ckr_order_range": (C.c_int, [vp, vp, C.POINTER(vp), C.c_size_t, C.c_uint32, C.c_uint32, C.c_uint32, Sign, Sign,
+                                  C.c_int, C.POINTER(vp), C.POINTER(vp)]),
+    "ckr_order_range_depth": (C.c_uint32, [C.c_uint32, C.c_uint32, C.c_uint32, Sign, Sign, C.c_int]),
     "ckr_rank_batch": (C.c_int, [vp, vp, C.POINTER(vp), C.c_size_t, C.c_uint32, Sign, C.POINTER(vp)]),
     "ckr_ct_level": (C.c_uint32, [vp]),
     "ckr_ct_scale": (C.c_double, [vp]),
@@ -209,6 +212,15 @@ def sort_col_depth(cmp, ind):
     return int(lib().ckr_sort_col_depth(sign(cmp), sign(ind)))
 
 
+def order_range_depth(N, a, b, cmp, ind, tie):
+    return int(lib().ckr_order_range_depth(N, a, b, sign(cmp), sign(ind), int(tie)))
+
+
+def median_window(N):
+    """the rank window of the median: [N/2, N/2 + 1] for an even N, the middle rank for an odd N"""
+    return (N // 2, N // 2 + 1) if N % 2 == 0 else ((N + 1) // 2, (N + 1) // 2)
+
+
 # ---- device objects -----------------------------------------------------------
 class Context:
     def __init__(self, pset, device=0, hbm_budget=0):
@@ -306,6 +318,17 @@ class Context:
         oh, val = (vp * len(cts))(), (vp * len(cts))()
         _ok(lib().ckr_order_stat_div(self.h, keys.h, arr, len(cts), N, k, sign(cmp), sign(ind), iters, oh, val))
         return [(Ct(self, vp(oh[i])), Ct(self, vp(val[i]))) for i in range(len(cts))]
+
+    def order_range(self, keys, cts, N, a, b, cmp, ind, tie):
+        """[(mask, value)] per input: the elements of rank a..b and the mean of the order statistics a..b"""
+        arr = (vp * len(cts))(*[c.h for c in cts])
+        oh, val = (vp * len(cts))(), (vp * len(cts))()
+        _ok(lib().ckr_order_range(self.h, keys.h, arr, len(cts), N, a, b, sign(cmp), sign(ind), int(tie), oh, val))
+        return [(Ct(self, vp(oh[i])), Ct(self, vp(val[i]))) for i in range(len(cts))]
+
+    def median(self, keys, cts, N, cmp, ind, tie=True):
+        """[(mask, value)] per input: the median (section 4) as the rank window of median_window(N)"""
+        return self.order_range(keys, cts, N, *median_window(N), cmp, ind, tie)
 
     def sort_col(self, keys, ct, N, cmp, ind):
         """column-form sort: no final transposition, one level fewer"""

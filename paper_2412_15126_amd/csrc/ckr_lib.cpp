@@ -278,13 +278,13 @@ struct GraphPlan {
     }
 };
 
-// one circuit: kind (rank, order statistic, sort), N, the order statistic's k
+// one circuit: kind (rank, order statistic, sort), N, the order statistic's rank window
 // and tie-correction flag, comparator and indicator compositions
 struct Spec {
-    int kind = 0, N = 0, k = 0, tie = 0;
+    int kind = 0, N = 0, k = 0, k_hi = 0, tie = 0;  // order statistics: the rank window [k, k_hi]
     ckr_sign cmp{0, 0, 0}, ind{0, 0, 0};
     auto tup() const {
-        return std::make_tuple(kind, N, k, tie, cmp.d_g, cmp.d_f, cmp.cheb, ind.d_g, ind.d_f, ind.cheb);
+        return std::make_tuple(kind, N, k, k_hi, tie, cmp.d_g, cmp.d_f, cmp.cheb, ind.d_g, ind.d_f, ind.cheb);
     }
 };
 // a group of B inputs of one level running one circuit
@@ -1268,11 +1268,14 @@ static void check_N_padded(const Ctx &C, u32 N) {
     if (N < 2 || Np * Np > C.n() / 2) throw Error{CKR_E_RANGE, "N must be >= 2 with next_pow2(N)^2 <= n/2"};
 }
 uint32_t rank_depth_n(int N, ckr_sign c, int tie) { return rank_depth(c, tie) + (pow2_ceil(N) != N ? 1 : 0); }
-// order statistic k: TransR mask, comparator, [E, E * tie mask, SumR mask,
-// scaling,] indicator (+1 for the two-sided window), O * V, SumC mask
-uint32_t order_stat_depth(int N, int k, ckr_sign c, ckr_sign i, int tie) {
-    return 1 + cmp_levels(c) + (tie ? 4 : 0) + ((!tie && i.cheb) ? 1 : 0) + cmp_levels(i) + ((k > 1 && k < N) ? 1 : 0) + 2;
+// window of ranks [a, b] (the order statistic is a = b = k): [block mask,]
+// TransR mask, comparator, [E, E * tie mask, SumR mask, scaling,] indicator
+// (+1 for the two-sided window), O * V, SumC mask
+uint32_t order_range_depth(int N, int a, int b, ckr_sign c, ckr_sign i, int tie) {
+    return (pow2_ceil(N) != N ? 1 : 0) + 1 + cmp_levels(c) + (tie ? 4 : 0) + ((!tie && i.cheb) ? 1 : 0) +
+           cmp_levels(i) + ((a > 1 && b < N) ? 1 : 0) + 2;
 }
+uint32_t order_stat_depth(int N, int k, ckr_sign c, ckr_sign i, int tie) { return order_range_depth(N, k, k, c, i, tie); }
 uint32_t argmin_depth(ckr_sign c, ckr_sign i) { return order_stat_depth(2, 1, c, i, 1); }
 // rank, scaling, indicator, indicator product, M * V_R, SumC mask, TransC mask
 uint32_t sort_depth(ckr_sign c, ckr_sign i) { return rank_depth(c, 0) + 5 + cmp_levels(i); }
@@ -1417,44 +1420,56 @@ static DCt sort_multi(Ctx &C, const Keys &K, const DCt &Bk, int b, ckr_sign cmp,
 // the ends (k = 1: Cmp(1.5, k_j); k = N: Cmp(k_j, N - 1/2); the k_j are
 // integral) and the window Cmp(x, -1/2) (1 - Cmp(x, 1/2)) on x = k_j - k
 // otherwise, every comparison taken on its argument divided by N.
+// Order statistic (section 3.2) over a window of ranks [a, b]; a = b = k is
+// the order statistic k, the window [N/2, N/2 + 1] the median of an even N
+// (section 4), whose product by 1/2 after the inner product is folded into the
+// constant that brings V to the mask's level: value = SumC(O V) / (b - a + 1),
+// the mean of the statistics a..b, at no extra level.
 // With tie-correction k_j = SumR(C + E (delta_{j>=i} - 1/2)), E = C (4 - 4C)
-// (rank plus offset; their +1/2 and -1/2 cancel), a permutation of 1..N.
+// (rank plus offset; their +1/2 and -1/2 cancel), a permutation of 1..N.  N
+// that is not a power of two pads (section 3.1) and needs tie-correction: the
+// padding's k_j are 0, outside every window but a = 1, where V is zero there.
 // Without it k_j is the rank SumR(C) + 1/2, the factor +-1/N folded into the
 // comparator's last polynomial and no row mask on SumR: the other rows hold
 // bounded garbage that O * V annihilates (V is zero outside row 0).
-// onehot = MaskR(O, 0); value = SumC(O * V) in slot 0.
-static void order_stat(Ctx &C, const Keys &K, const DCt &V, int N, int k, int tie, ckr_sign cmp, ckr_sign ind,
-                       DCt &onehot, DCt &value) {
-    check_N(C, (u32)N);
+// Indicator: Cmp(b + 1/2, k_j) for a = 1, Cmp(k_j, a - 1/2) for b = N, the
+// window Cmp(k_j, a - 1/2) (1 - Cmp(k_j, b + 1/2)) otherwise, every argument
+// over N.  onehot = O on the first N slots of row 0; value in slot 0.
+static void order_range(Ctx &C, const Keys &K, const DCt &V, int N, int a, int b, int tie, ckr_sign cmp,
+                        ckr_sign ind, DCt &onehot, DCt &value) {
+    check_N_padded(C, (u32)N);
     check_sign(cmp);
     check_sign(ind);
-    if (k < 1 || k > N) throw Error{CKR_E_INVALID, "k must lie in [1, N]"};
-    if ((u32)V.level < order_stat_depth(N, k, cmp, ind, tie))
+    const int Np = pow2_ceil(N);  // the layout
+    if (a < 1 || a > b || b > N) throw Error{CKR_E_INVALID, "the rank window must satisfy 1 <= a <= b <= N"};
+    if (a == 1 && b == N) throw Error{CKR_E_INVALID, "the rank window [1, N] selects every element"};
+    if (Np != N && !tie) throw Error{CKR_E_INVALID, "N that is not a power of two needs tie-correction"};
+    if ((u32)V.level < order_range_depth(N, a, b, cmp, ind, tie))
         throw Error{CKR_E_DEPTH, "not enough levels for the order statistic"};
-    const double dN = (double)N, dk = (double)k;
+    const double dN = (double)N, da = (double)a, db = (double)b;
+    const bool lower = a == 1;  // only the upper bound b + 1/2 is tested
     // a Chebyshev indicator takes the real part of its argument (the 1/2 in
     // the scaling); without tie-correction its argument keeps the SumR row
     // mask, so that every slot lies in [-1, 1]
     const bool proj = ind.cheb != 0;
     const double sN = proj ? 2.0 * dN : dN;
-    DCt base;  // k_j times -1/N (k = 1) or 1/N
+    DCt base;  // k_j times -1/N (a = 1) or 1/N
     double off1, off2 = 0.0;
     if (tie) {
         DCt kv = tie_rank(C, K, V, N, cmp);
-        base = ev_cmul_to(C, kv, k == 1 ? -1.0 / sN : 1.0 / sN, kv.level - 1);
-        if (k == 1) off1 = 1.5 / dN;
-        else if (k == N) off1 = (0.5 - dN) / dN;
-        else off1 = (0.5 - dk) / dN, off2 = (-0.5 - dk) / dN;
+        base = ev_cmul_to(C, kv, lower ? -1.0 / sN : 1.0 / sN, kv.level - 1);
+        if (lower) off1 = (db + 0.5) / dN;
+        else off1 = (0.5 - da) / dN, off2 = (-0.5 - db) / dN;
     } else {
-        DCt Cm = cmp_matrix(C, K, V, N, cmp, nullptr, k == 1 ? -1.0 / sN : 1.0 / sN);
+        DCt Cm = cmp_matrix(C, K, V, N, cmp, nullptr, lower ? -1.0 / sN : 1.0 / sN);
         base = proj ? sum_r(C, K, Cm, N) : rot_add_chain(C, K, Cm, 0, lg(N), [&](int i) { return (i64)N << i; });
-        if (k == 1) off1 = 1.0 / dN;
-        else if (k == N) off1 = (1.0 - dN) / dN;
-        else off1 = (1.0 - dk) / dN, off2 = -dk / dN;
+        // SumR(C) = R_j - 1/2
+        if (lower) off1 = db / dN;
+        else off1 = (1.0 - da) / dN, off2 = -db / dN;
     }
     if (proj) base = ev_plus_conj(C, K, base);
     DCt O;
-    if (k == 1 || k == N) {
+    if (lower || b == N) {
         O = cmp_sign(C, K, ev_add_const(C, base, off1), ind);
     } else {
         DCt d1 = ev_add_const(C, base, off1), d2 = ev_add_const(C, base, off2);
@@ -1465,8 +1480,15 @@ static void order_stat(Ctx &C, const Keys &K, const DCt &V, int N, int k, int ti
         O = ev_mul(C, K, c1, ev_add_const(C, ev_mul_int(C, c2, -1), 1.0));
     }
     onehot = ev_mul_plain(C, O, get_plain(C, kMaskRow0, N, O.level));
-    DCt Va = ev_cmul_to(C, V, 1.0, O.level);
-    value = sum_c(C, K, ev_mul(C, K, O, Va), N);
+    DCt Va = ev_cmul_to(C, V, 1.0 / (db - da + 1.0), O.level);
+    value = sum_c(C, K, ev_mul(C, K, O, Va), Np);
+}
+
+static void order_stat(Ctx &C, const Keys &K, const DCt &V, int N, int k, int tie, ckr_sign cmp, ckr_sign ind,
+                       DCt &onehot, DCt &value) {
+    check_N(C, (u32)N);
+    if (k < 1 || k > N) throw Error{CKR_E_INVALID, "k must lie in [1, N]"};
+    order_range(C, K, V, N, k, k, tie, cmp, ind, onehot, value);
 }
 
 // Order statistic with the value by division (section 3.2): without
@@ -1572,7 +1594,7 @@ static uint32_t spec_depth(const Spec &s) {
     if (s.kind == kRankCircuit) return rank_depth_n(s.N, s.cmp, s.tie);
     if (s.kind == kSortCircuit) return sort_depth(s.cmp, s.ind);
     if (s.kind == kSortColCircuit) return sort_col_depth(s.cmp, s.ind);
-    return order_stat_depth(s.N, s.k, s.cmp, s.ind, s.tie);
+    return order_range_depth(s.N, s.k, s.k_hi, s.cmp, s.ind, s.tie);
 }
 
 // the circuit of a (kind, N, compositions) request; argmin is the
@@ -1591,7 +1613,7 @@ static Spec spec_of(const Ctx &C, int kind, int N, int k, int tie, ckr_sign cmp,
         s.ind = ind;
     } else if (kind == kArgminCircuit || kind == kOrderCircuit) {
         s.kind = kOrderCircuit;
-        s.k = kind == kArgminCircuit ? 1 : k;
+        s.k = s.k_hi = kind == kArgminCircuit ? 1 : k;
         s.tie = kind == kArgminCircuit ? 1 : (tie != 0);
         s.ind = ind;
         if (s.k < 1 || s.k > N) throw Error{CKR_E_INVALID, "k must lie in [1, N]"};
@@ -1613,7 +1635,7 @@ static std::vector<DCt> eval_spec(Ctx &C, const Keys &K, const Spec &s, const DC
         o.push_back(sort_col(C, K, X, s.N, s.cmp, s.ind));
     } else {
         o.resize(2);
-        order_stat(C, K, X, s.N, s.k, s.tie, s.cmp, s.ind, o[0], o[1]);
+        order_range(C, K, X, s.N, s.k, s.k_hi, s.tie, s.cmp, s.ind, o[0], o[1]);
     }
     return o;
 }
@@ -2584,6 +2606,50 @@ ckr_status ckr_order_stat(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *
         order_stat(C, *keys->K, v->ct, (int)N, (int)k, tie_correct != 0, cmp, ind, oh, val);
         *onehot = wrap(C, std::move(oh));
         *value = wrap(C, std::move(val));
+    });
+}
+
+uint32_t ckr_order_range_depth(uint32_t N, uint32_t a, uint32_t b, ckr_sign cmp, ckr_sign ind, int tie_correct) {
+    return order_range_depth((int)N, (int)a, (int)b, cmp, ind, tie_correct != 0);
+}
+
+ckr_status ckr_order_range(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *const *v, size_t count, uint32_t N,
+                           uint32_t a, uint32_t b, ckr_sign cmp, ckr_sign ind, int tie_correct, ckr_ct **onehot,
+                           ckr_ct **value) {
+    return guard([&] {
+        NEED(ctx && keys && v && count && onehot && value);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
+        Ctx &C = *ctx->C;
+        check_N_padded(C, N);
+        // every argument error before the first launch
+        if (a < 1 || a > b || b > N) throw Error{CKR_E_INVALID, "the rank window must satisfy 1 <= a <= b <= N"};
+        if (a == 1 && b == N) throw Error{CKR_E_INVALID, "the rank window [1, N] selects every element"};
+        if (pow2_ceil((int)N) != (int)N && !tie_correct)
+            throw Error{CKR_E_INVALID, "N that is not a power of two needs tie-correction"};
+        if (!sign_valid(cmp) || !sign_valid(ind)) throw Error{CKR_E_INVALID, "empty comparator"};
+        Spec s;
+        s.kind = kOrderCircuit;
+        s.N = (int)N;
+        s.k = (int)a;
+        s.k_hi = (int)b;
+        s.tie = tie_correct != 0;
+        s.cmp = cmp;
+        s.ind = ind;
+        std::vector<const DCt *> in;
+        for (size_t i = 0; i < count; i++) {
+            NEED(v[i]);
+            in.push_back(&v[i]->ct);
+        }
+        std::vector<std::vector<DCt>> r = run_groups(C, *keys->K, {s}, {in});
+        std::vector<ckr_ct *> made;
+        for (size_t i = 0; i < count; i++) {
+            made.push_back(wrap(C, slice(C, r[0][0], (int)i, 1)));
+            made.push_back(wrap(C, slice(C, r[0][1], (int)i, 1)));
+        }
+        for (size_t i = 0; i < count; i++) {
+            onehot[i] = made[2 * i];
+            value[i] = made[2 * i + 1];
+        }
     });
 }
 

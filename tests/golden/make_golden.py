@@ -253,10 +253,47 @@ def kth64_p17s_div():
             "value": float(O.decrypt(K, val, 1)[0])}
 
 
+def _median_case(N, pset, seed):
+    cmp, ind = W.ORDER_TIE_CMP[128]
+    O.set_threads(min(16, os.cpu_count() or 1))
+    P = O.Params(**W.PSETS[pset])
+    a, b = (N // 2, N // 2 + 1) if N % 2 == 0 else ((N + 1) // 2, (N + 1) // 2)
+    v, kseed, eseed = W.tied_workload(N, seed)
+    level = O.order_range_depth(N, a, b, cmp, ind, True)
+    K = O.Keys(P, kseed, level, P.circuit_galois(N, 2))
+    oh, val = O.order_range(K, O.encrypt(K, v, level, eseed), N, a, b, cmp, ind, True)
+    return {"level": level, "window": [a, b], "median": float(np.median(v)),
+            "sha256": [hashlib.sha256(oh.export().tobytes()).hexdigest(),
+                       hashlib.sha256(val.export().tobytes()).hexdigest()],
+            "mask": [float(x) for x in O.decrypt(K, oh, N)],
+            "value": float(O.decrypt(K, val, 1)[0])}
+
+
+def median128_p17o():
+    """tie-corrected median of N = 128 (window [64, 65]) at n = 2^17"""
+    d = _median_case(128, "P17O", 3)
+    d["_what"] = ("oracle tie-corrected median (rank window [64, 65], the mean of the two middle statistics) of "
+                  "N=128 at n=2^17 (P17O), tied workload seed 3 (96 distinct values + 32 duplicates), comparator "
+                  "and indicator g^4 f^2, encryption at the circuit's depth: sha256 of the exported mask and value "
+                  "ciphertexts and their decoded contents")
+    return d
+
+
+def median101_p17s():
+    """tie-corrected median of N = 101 values (rank 51), padded to the 128 layout, at n = 2^17"""
+    d = _median_case(101, "P17S", 4)
+    d["_what"] = ("oracle tie-corrected median (rank window [51, 51]) of N=101 values zero-padded to the 128 "
+                  "layout at n=2^17 (P17S), tied workload seed 4 (76 distinct values + 25 duplicates), comparator "
+                  "and indicator g^4 f^2, encryption at the circuit's depth: sha256 of the exported mask and value "
+                  "ciphertexts and their decoded contents")
+    return d
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["rank128_p16", "argmin128_p17", "sort128_p17", "mixed_p16d", "argmax128_p17o",
                              "rank512_p16_multi", "sort512_p17s_multi", "rank128_p16_cheb",
-                             "argmin128_p17_cheb", "sort128_p17_col", "kth64_p17s_div"]
+                             "argmin128_p17_cheb", "sort128_p17_col", "kth64_p17s_div", "median128_p17o",
+                             "median101_p17s"]
     for name in which:
         json.dump(globals()[name](), open(os.path.join(HERE, name + ".json"), "w"), indent=1)
         print("wrote", name + ".json", flush=True)

@@ -628,3 +628,22 @@ def test_oracle_order_range_rejects(ora, t12d):
             ora.order_range(keys, ct, N, a, b, cmp, ind, tie)
     with pytest.raises(ora.OracleError, match="depth"):
         ora.order_range(keys, ora.encrypt(keys, np.linspace(0.1, 0.8, 8), 3, bytes(32)), 8, 4, 5, cmp, ind, True)
+
+
+@pytest.mark.parametrize("name,N,seed", [("median128_p17o", 128, 3), ("median101_p17s", 101, 4)])
+def test_stored_median_goldens_are_medians(name, N, seed):
+    """The stored full-size median digests decode to a median: the mask marks
+    the middle element(s) of the regenerated workload (lowest index first
+    among equal values) and the value is np.median within 5e-3."""
+    path = os.path.join(os.path.dirname(__file__), "golden", name + ".json")
+    if not os.path.exists(path):
+        pytest.skip("golden not written")
+    d = json.load(open(path))
+    v, _, _ = W.tied_workload(N, seed)
+    a, b = d["window"]
+    assert (a, b) == ((N // 2, N // 2 + 1) if N % 2 == 0 else ((N + 1) // 2, (N + 1) // 2))
+    want = np.zeros(N)
+    want[np.argsort(v, kind="stable")[a - 1:b]] = 1.0
+    assert np.array_equal(np.round(d["mask"]), want)
+    assert abs(d["median"] - float(np.median(v))) == 0.0
+    assert abs(d["value"] - float(np.median(v))) < 5e-3

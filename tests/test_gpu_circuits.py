@@ -616,3 +616,112 @@ def test_padded_rank_bit_exact(ora, small, N, tie):
         for rep in range(3):
             outs = ctx.run_batch(small["gkeys"], "rank", cts, N, cmp)
             assert all(np.array_equal(a.export(), b) for a, b in zip(outs, singles))
+
+
+def _window_mask(v, a, b):
+    m = np.zeros(len(v))
+    m[np.argsort(v, kind="stable")[a - 1:b]] = 1.0
+    return m
+
+
+@pytest.mark.parametrize("N,a,b,tie", [(8, 4, 5, True), (8, 4, 5, False), (8, 1, 3, True), (8, 6, 8, False),
+                                       (8, 2, 7, True), (6, 3, 4, True), (7, 4, 4, True), (5, 1, 2, True),
+                                       (7, 5, 7, True)])
+def test_order_range_bit_exact(ora, small, N, a, b, tie):
+    """Order statistics over a rank window (the median of section 4, lower,
+    upper and inner windows, padded N) against the oracle bit for bit."""
+    P, ctx = small["P"], small["ctx"]
+    cmp, ind = W.ORDER_TIE_CMP[8] if tie else W.ORDER_CMP[8]
+    v, _, eseed = W.tied_workload(N, 20 + N, 0.01) if tie else W.rank_workload(N, 0.01, 20 + N)
+    level = ora.order_range_depth(N, a, b, cmp, ind, tie)
+    assert level == small["ckr"].order_range_depth(N, a, b, cmp, ind, tie)
+    say(f"[gpu] order range N={N} [{a}, {b}] tie={tie}")
+    ooh, oval = ora.order_range(small["okeys"], ora.encrypt(small["okeys"], v, level, eseed), N, a, b, cmp, ind, tie)
+    (goh, gval), = ctx.order_range(small["gkeys"], [ctx.encrypt(small["gkeys"], v, level, eseed)], N, a, b, cmp,
+                                   ind, tie)
+    assert np.array_equal(ooh.export(), goh.export()) and np.array_equal(oval.export(), gval.export())
+    assert np.array_equal(np.round(ctx.decrypt(small["gkeys"], goh, N)), _window_mask(v, a, b))
+    assert abs(ctx.decrypt(small["gkeys"], gval, 1)[0] - np.mean(np.sort(v)[a - 1:b])) < 0.01
+
+
+@pytest.mark.parametrize("N", [8, 7])
+def test_median_batch_and_replays_equal_single(ora, small, N):
+    """A batch of three medians (eager, captured, replayed) equals three single
+    calls bit for bit; the window a = b = k equals the order statistic."""
+    P, ctx, ckr = small["P"], small["ctx"], small["ckr"]
+    cmp, ind = W.ORDER_TIE_CMP[8]
+    a, b = ckr.median_window(N)
+    level = ckr.order_range_depth(N, a, b, cmp, ind, True)
+    qs = [W.tied_workload(N, 60 + i, 0.01) for i in range(3)]
+    cts = [ctx.encrypt(small["gkeys"], v, level, e) for v, _, e in qs]
+    say(f"[gpu] median batch N={N}")
+    singles = [ctx.median(small["gkeys"], [c], N, cmp, ind)[0] for c in cts]
+    for rep in range(3):
+        outs = ctx.median(small["gkeys"], cts, N, cmp, ind)
+        for (x, y), (s, t) in zip(outs, singles):
+            assert np.array_equal(x.export(), s.export()) and np.array_equal(y.export(), t.export()), rep
+    for (v, _, _), (_, val) in zip(qs, singles):
+        assert abs(ctx.decrypt(small["gkeys"], val, 1)[0] - np.median(v)) < 0.01
+    if N == 8:
+        k = 5
+        lk = ckr.order_stat_depth(N, k, cmp, ind, True)
+        c = ctx.encrypt(small["gkeys"], qs[0][0], lk, qs[0][2])
+        (r_oh, r_val), = ctx.order_range(small["gkeys"], [c], N, k, k, cmp, ind, True)
+        s_oh, s_val = ctx.order_stat(small["gkeys"], c, N, k, cmp, ind, True)
+        assert np.array_equal(r_oh.export(), s_oh.export()) and np.array_equal(r_val.export(), s_val.export())
+
+
+def test_order_range_errors(small):
+    ctx, ckr = small["ctx"], small["ckr"]
+    cmp, ind = W.ORDER_TIE_CMP[8]
+    ct = ctx.encrypt(small["gkeys"], np.linspace(0.1, 0.8, 8), small["P"].L, bytes(32))
+    for N, a, b, tie, st in ((8, 1, 8, True, -1), (8, 0, 2, True, -1), (8, 3, 2, True, -1), (8, 2, 9, True, -1),
+                             (6, 2, 3, False, -1), (1, 1, 1, True, -2), (64, 2, 3, True, -2)):
+        with pytest.raises(ckr.CkrError) as e:
+            ctx.order_range(small["gkeys"], [ct], N, a, b, cmp, ind, tie)
+        assert e.value.status == st, (N, a, b, tie)
+    low = ctx.encrypt(small["gkeys"], np.linspace(0.1, 0.8, 8), 3, bytes(32))
+    with pytest.raises(ckr.CkrError) as e:
+        ctx.order_range(small["gkeys"], [low], 8, 4, 5, cmp, ind, True)
+    assert e.value.status == -3
+
+
+def test_median128_with_ties_matches_golden(p17o):
+    """Tie-corrected median of N = 128 at n = 2^17 (window [64, 65]) against
+    the oracle's digests."""
+    ctx, ps = p17o
+    gold = json.load(open(os.path.join(GOLD, "median128_p17o.json")))
+    N = 128
+    cmp, ind = W.ORDER_TIE_CMP[N]
+    v, kseed, eseed = W.tied_workload(N, 3)
+    assert gold["level"] == 44 and gold["window"] == [64, 65]
+    say("[gpu] P17O median keygen")
+    keys = ctx.keygen(kseed, gold["level"], [N], what=2)
+    (oh, val), = ctx.median(keys, [ctx.encrypt(keys, v, gold["level"], eseed)], N, cmp, ind)
+    say("[gpu] P17O median done")
+    assert hashlib.sha256(oh.export().tobytes()).hexdigest() == gold["sha256"][0]
+    assert hashlib.sha256(val.export().tobytes()).hexdigest() == gold["sha256"][1]
+    assert np.array_equal(np.round(ctx.decrypt(keys, oh, N)), _window_mask(v, 64, 65))
+    assert abs(ctx.decrypt(keys, val, 1)[0] - np.median(v)) < 5e-3
+
+
+def test_median101_padded_full_size_matches_golden():
+    """Tie-corrected median of N = 101 values (rank 51) zero-padded to the 128
+    layout at n = 2^17 against the oracle's digests."""
+    import paper_2412_15126_amd as ckr
+    gold = json.load(open(os.path.join(GOLD, "median101_p17s.json")))
+    N = 101
+    cmp, ind = W.ORDER_TIE_CMP[128]
+    assert ckr.median_window(N) == tuple(gold["window"]) == (51, 51)
+    level = ckr.order_range_depth(N, 51, 51, cmp, ind, True)
+    assert level == gold["level"]
+    v, kseed, eseed = W.tied_workload(N, 4)
+    ctx = ckr.Context(W.PSETS["P17S"])
+    say("[gpu] P17S padded median keygen")
+    keys = ctx.keygen(kseed, level, [N], what=2)
+    (oh, val), = ctx.median(keys, [ctx.encrypt(keys, v, level, eseed)], N, cmp, ind)
+    say("[gpu] P17S padded median done")
+    assert hashlib.sha256(oh.export().tobytes()).hexdigest() == gold["sha256"][0]
+    assert hashlib.sha256(val.export().tobytes()).hexdigest() == gold["sha256"][1]
+    assert np.array_equal(np.round(ctx.decrypt(keys, oh, N)), _window_mask(v, 51, 51))
+    assert abs(ctx.decrypt(keys, val, 1)[0] - np.median(v)) < 5e-3
