@@ -86,8 +86,8 @@ __device__ __forceinline__ u32 gal_src(u32 i, int logn, u32 g) {
 template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool PRO, class Emit>
 __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, int logn, int mod, double q,
                                           double qinv, const double2 *__restrict__ tw,
-                                          const double2 *__restrict__ twlast, double *lds, Emit &&emit,
-                                          u32 gal = 0) {
+                                          const double *__restrict__ twq, const double2 *__restrict__ twlast,
+                                          double *lds, Emit &&emit, u32 gal = 0) {
     constexpr int S = 1 << LOGS, E = 1 << LOGE, TPC = S / E, NT = C * TPC;
     constexpr int NR = (LOGS + LOGE - 1) / LOGE;
     constexpr int SP = S + (S >> 4) + 1;
@@ -114,6 +114,17 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
         __syncthreads();
         twc = twl;
     }
+    // A row pass reads its twiddles from the w/q table alone (8 bytes each
+    // instead of 16) and recovers w = rint(w/q * q) exactly: |(w/q) q - w| <=
+    // w 2^-53 < 1/8 for w < 2^50, and the FMA rounds the exact product once.
+    auto twid = [&](int idx) -> double2 {
+        if constexpr (COLPASS) {
+            return twc[idx];
+        } else {
+            const double wq = twq[idx];
+            return make_double2(__fma_rn(wq, q, C52) - C52, wq);
+        }
+    };
     double x[E];
 
 #pragma unroll
@@ -164,7 +175,7 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
                     if (k & (1 << kb)) continue;
                     const int k2 = k | (1 << kb);
                     const int r = rbase | (k << w);
-                    const double2 W = twc[(1 << g) + (cpart << s) + (r >> (LOGS - s))];
+                    const double2 W = twid((1 << g) + (cpart << s) + (r >> (LOGS - s)));
                     double u = x[k];
                     u = u >= two_q ? u - two_q : u;
                     const double v = mm_lazy(x[k2], W.x, W.y, q);
@@ -191,7 +202,7 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
                         x[k2] = mm_lazy(d, N1.x, N1.y, q);
                     } else {
                         const int r = rbase | (k << w);
-                        const double2 W = twc[(1 << g) + (cpart << s) + (r >> (LOGS - s))];
+                        const double2 W = twid((1 << g) + (cpart << s) + (r >> (LOGS - s)));
                         x[k] = sm >= two_q ? sm - two_q : sm;
                         x[k2] = mm_lazy(d, W.x, W.y, q);
                     }
@@ -245,8 +256,9 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
 template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool FUSE>
 __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
     ntt_pass(u64 *__restrict__ base, size_t poly_stride, int limbs, LimbMap map, int logn,
-             const double2 *__restrict__ mq, const double2 *__restrict__ twtab, const double2 *__restrict__ twlast,
-             const NttFuse fz, const u64 *__restrict__ src, size_t src_stride, u32 gal) {
+             const double2 *__restrict__ mq, const double2 *__restrict__ twtab, const double *__restrict__ twqtab,
+             const double2 *__restrict__ twlast, const NttFuse fz, const u64 *__restrict__ src, size_t src_stride,
+             u32 gal) {
     constexpr int S = 1 << LOGS;
     constexpr int SP = S + (S >> 4) + 1;
     __shared__ __align__(16) double lds[((C * SP + 1) & ~1) + (COLPASS ? 2 * S : 0)];
@@ -260,6 +272,7 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
     const u64 *din = (FIRST && src) ? src + (size_t)p * src_stride + (size_t)t * n : data;
     const double q = mq[mod].x, qinv = mq[mod].y;
     const double2 *tw = twtab + (size_t)mod * n;
+    const double *twq = twqtab + (size_t)mod * n;
     constexpr bool PRO = FUSE && COLPASS && !INV;   // prologue: broadcast-reduce one limb
     constexpr bool EPI = FUSE && !COLPASS && !INV;  // epilogue: (x - y) * c (+ add)
     const int c0 = blockIdx.x * C;
@@ -274,7 +287,7 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
             padd2 = fz.add2 + pb * fz.add2_stride + pk * fz.add2_off + (size_t)t * n;
         const double ec = fz.c.v[t], ecq = fz.c.vq[t];
         const u32 ag = fz.add_gal;
-        pass_core<LOGS, LOGE, C, COLPASS, INV, false>(din, c0, logn, mod, q, qinv, tw, twlast, lds,
+        pass_core<LOGS, LOGE, C, COLPASS, INV, false>(din, c0, logn, mod, q, qinv, tw, twq, twlast, lds,
                                                       [&](int, u32 pos, double y) {
             double r = red1(mm_lazy(u2d(px[pos]) - y + q, ec, ecq, q), q);
             if (padd) r = red1(r + u2d(padd[ag > 1 ? gal_src(pos, logn, ag) : pos]), q);
@@ -283,9 +296,10 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
         });
     } else if constexpr (PRO) {
         pass_core<LOGS, LOGE, C, COLPASS, INV, true>(fz.src + (size_t)p * fz.src_stride, c0, logn, mod, q, qinv, tw,
-                                                     twlast, lds, [&](int, u32 pos, double y) { data[pos] = d2u(y); });
+                                                     twq, twlast, lds,
+                                                     [&](int, u32 pos, double y) { data[pos] = d2u(y); });
     } else {
-        pass_core<LOGS, LOGE, C, COLPASS, INV, false>(din, c0, logn, mod, q, qinv, tw, twlast, lds,
+        pass_core<LOGS, LOGE, C, COLPASS, INV, false>(din, c0, logn, mod, q, qinv, tw, twq, twlast, lds,
                                                       [&](int, u32 pos, double y) { data[pos] = d2u(y); }, g);
     }
 }
@@ -302,7 +316,7 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
 // tile's key words from its L2.
 template <int LOGS, int LOGE, int C>
 __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
-    ntt_row_ip(const IPArgs a, int logn, const double2 *__restrict__ mq, const double2 *__restrict__ twtab,
+    ntt_row_ip(const IPArgs a, int logn, const double2 *__restrict__ mq, const double *__restrict__ twqtab,
                const double2 *__restrict__ twlast) {
     constexpr int S = 1 << LOGS, E = 1 << LOGE, NT = C * (S / E);
     constexpr int SP = S + (S >> 4) + 1;
@@ -317,7 +331,7 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
     const int mod = t <= a.level ? t : a.nq + (t - a.level - 1);
     const int kl = t <= a.level ? t : a.lmax_key + 1 + (t - a.level - 1);
     const double q = mq[mod].x, qinv = mq[mod].y;
-    const double2 *tw = twtab + (size_t)mod * n;
+    const double *twq = twqtab + (size_t)mod * n;
     const int own = (t <= a.level) ? t / a.alpha : -1;  // digit holding limb t, if any
     const int tid = threadIdx.x;
     double sb[E], sa[E];
@@ -358,7 +372,7 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
         } else {
             __syncthreads();  // the previous digit's last LDS reads are done
             pass_core<LOGS, LOGE, C, false, false, false>(a.ext + bi * a.sext + ((size_t)j * a.E + t) * n, c0, logn,
-                                                          mod, q, qinv, tw, twlast, lds, acc);
+                                                          mod, q, qinv, nullptr, twq, twlast, lds, acc);
         }
         if ((j & 7) == 7) {
 #pragma unroll
@@ -384,7 +398,7 @@ static void launch_row_ip(const DevTables &T, const IPArgs &a, hipStream_t s) {
     const int groups = a.E * tiles;
     const unsigned blocks = (unsigned)(((groups + 7) / 8) * 8) * (unsigned)a.B;
     hipLaunchKernelGGL((ntt_row_ip<LOGS, LOGE, C>), dim3(blocks), dim3(C * (1 << (LOGS - LOGE))), 0, s, a, T.logn,
-                       T.mq, T.tw_fwd, T.tw_last);
+                       T.mq, T.twq_fwd, T.tw_last);
 }
 
 template <int LOGS, int LOGE, int C, bool COLPASS, bool INV>
@@ -395,12 +409,13 @@ static void launch_pass(const DevTables &T, const LimbBatch &b, hipStream_t s, c
     dim3 grid(blocks, b.limbs * b.polys);
     dim3 block(C * (1 << (LOGS - LOGE)));
     const double2 *tw = INV ? T.tw_inv : T.tw_fwd;
+    const double *twq = INV ? T.twq_inv : T.twq_fwd;
     if (f && !INV && (COLPASS ? f->pro : f->epi))
         hipLaunchKernelGGL((ntt_pass<LOGS, LOGE, C, COLPASS, INV, true>), grid, block, 0, s, b.base, b.poly_stride,
-                           b.limbs, b.map, logn, T.mq, tw, T.tw_last, *f, b.src, b.src_stride, b.gal);
+                           b.limbs, b.map, logn, T.mq, tw, twq, T.tw_last, *f, b.src, b.src_stride, b.gal);
     else
         hipLaunchKernelGGL((ntt_pass<LOGS, LOGE, C, COLPASS, INV, false>), grid, block, 0, s, b.base, b.poly_stride,
-                           b.limbs, b.map, logn, T.mq, tw, T.tw_last, NttFuse{}, b.src, b.src_stride, b.gal);
+                           b.limbs, b.map, logn, T.mq, tw, twq, T.tw_last, NttFuse{}, b.src, b.src_stride, b.gal);
 }
 
 // tile variants: (elements per thread 2^LOGE, columns per workgroup C)

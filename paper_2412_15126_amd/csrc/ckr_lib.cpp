@@ -459,6 +459,7 @@ static void setup_tables(Ctx &C) {
     C.T.logn = P.logn;
     C.T.nmod = nm;
     std::vector<double2> mq(nm), fwd((size_t)nm * n), inv((size_t)nm * n), last(2 * nm);
+    std::vector<double> fwdq((size_t)nm * n), invq((size_t)nm * n);
     std::vector<u64> qi(nm);
     std::vector<u64> pw(n), ipw(n);
     for (int t = 0; t < nm; t++) {
@@ -476,6 +477,8 @@ static void setup_tables(Ctx &C) {
             const u64 w = pw[brev(i, P.logn)], wi = ipw[brev(i, P.logn)];
             fwd[(size_t)t * n + i] = make_double2((double)w, (double)w / dq);
             inv[(size_t)t * n + i] = make_double2((double)wi, (double)wi / dq);
+            fwdq[(size_t)t * n + i] = fwd[(size_t)t * n + i].y;
+            invq[(size_t)t * n + i] = inv[(size_t)t * n + i].y;
         }
         const u64 ninv = hinv(n % q, q);
         const u64 w1 = hmul(ipw[n / 2], ninv, q);
@@ -492,6 +495,10 @@ static void setup_tables(Ctx &C) {
     HIPCHK(hipMemcpy(C.T.tw_fwd, fwd.data(), fwd.size() * sizeof(double2), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(C.T.tw_inv, inv.data(), inv.size() * sizeof(double2), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(C.T.tw_last, last.data(), last.size() * sizeof(double2), hipMemcpyHostToDevice));
+    C.T.twq_fwd = (double *)C.table_alloc(fwdq.size() * sizeof(double));
+    C.T.twq_inv = (double *)C.table_alloc(invq.size() * sizeof(double));
+    HIPCHK(hipMemcpy(C.T.twq_fwd, fwdq.data(), fwdq.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(C.T.twq_inv, invq.data(), invq.size() * sizeof(double), hipMemcpyHostToDevice));
 }
 
 // fast base conversion table from moduli src[] to moduli tgt[] (output slots given)

@@ -67,3 +67,28 @@ def test_sampler_matches_oracle(ora):
     key = bytes(range(1, 33))
     for purpose, oid, kind, q in [(1, 0, 0, 0), (3, 0, 1, 0), (2, 5, 2, (1 << 44) + 7), (4, (97 << 32) | 3, 2, 12289)]:
         assert np.array_equal(ckr.sample(key, purpose, oid, kind, q, 5000), ora.sample(key, purpose, oid, kind, q, 5000))
+
+
+def _rn(x):
+    """round a Fraction to the nearest IEEE double (ties to even), as a Fraction"""
+    from fractions import Fraction
+    f = float(x)                     # Python's int/Fraction -> float conversion rounds to nearest even
+    return Fraction(f)
+
+
+def test_twiddle_recovered_from_its_quotient():
+    """The row passes keep only wq = RN(w/q) per twiddle and recover
+    w = RN(wq * q + 2^52) - 2^52 (one FMA, one subtraction).  For primes below
+    2^50 this is exact: |wq q - w| <= w 2^-53 < 1/8.  Checked with exact
+    rational arithmetic on the extreme and random cases."""
+    from fractions import Fraction
+    rng = np.random.default_rng(5)
+    cases = []
+    for q in (2**50 - 27, 2**49 + 9, 2**44 + 7, 1125899906826241, 65537):
+        cases += [(w, q) for w in (1, 2, q - 1, q - 2, q // 2, q // 3)]
+        cases += [(int(w), q) for w in rng.integers(1, q, 200)]
+    for w, q in cases:
+        wq = _rn(Fraction(w, q))
+        assert wq == Fraction(float(w) / float(q))            # the table's value: IEEE division, correctly rounded
+        rec = _rn(wq * q + 2**52) - 2**52                      # the FMA rounds the exact sum once
+        assert rec == w, (w, q)
