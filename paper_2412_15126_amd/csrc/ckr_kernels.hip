@@ -68,7 +68,7 @@ __device__ __forceinline__ u32 gal_src(u32 i, int logn, u32 g) {
 // negacyclic NTT: one pass of a two-pass decomposition n = n1 * n2
 // ------------------------------------------------------------------------
 // Forward transform (Cooley-Tukey, merged psi twiddles): stage g pairs indices
-// j, j + n/2^{g+1} with twiddle tw[2^g + (j >> (logn - g))].  The first logn1
+// j, j + n/2^{g+1} with twiddle w[2^g + (j >> (logn - g))].  The first logn1
 // stages act on columns {c + n2 r}, the rest on contiguous rows of n2.  The
 // inverse runs the Gentleman-Sande butterflies in the opposite stage order,
 // rows first, and folds n^{-1} into its final stage.
@@ -85,8 +85,8 @@ __device__ __forceinline__ u32 gal_src(u32 i, int logn, u32 g) {
 // from the same thread).
 template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool PRO, class Emit>
 __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, int logn, int mod, double q,
-                                          double qinv, const double2 *__restrict__ tw,
-                                          const double *__restrict__ twq, const double2 *__restrict__ twlast,
+                                          double qinv, const double *__restrict__ twq,
+                                          const double2 *__restrict__ twlast,
                                           double *lds, Emit &&emit, u32 gal = 0) {
     constexpr int S = 1 << LOGS, E = 1 << LOGE, TPC = S / E, NT = C * TPC;
     constexpr int NR = (LOGS + LOGE - 1) / LOGE;
@@ -104,22 +104,25 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
     auto gaddr = [&](int r) -> u32 { return COLPASS ? (u32)(r * ncol + c) : (u32)(c * S + r); };
     auto lidx = [&](int cc, int r) -> int { return cc * SP + r + (r >> 4); };
 
-    // A column pass uses only the first S twiddles of its limb's table, the
-    // same for every column: they are staged in LDS once per workgroup (after
-    // the C*SP data words), so the butterflies read them there.
-    const double2 *twc = tw;
+    // Twiddles come from the w/q table alone (8 bytes each instead of 16);
+    // w = rint(w/q * q) is recovered exactly: |(w/q) q - w| <= w 2^-53 < 1/8
+    // for w < 2^50, and the FMA rounds the exact product once.  A row pass
+    // recovers w at each use.  A column pass uses only the first S entries of
+    // its limb's table, the same for every column: they are staged in LDS as
+    // {w, w/q} pairs once per workgroup (after the C*SP data words), so its
+    // butterflies read them there with no recovery.
+    double2 *twl = nullptr;
     if constexpr (COLPASS) {
-        double2 *twl = reinterpret_cast<double2 *>(lds + ((C * SP + 1) & ~1));
-        for (int i = tid; i < S; i += NT) twl[i] = tw[i];
+        twl = reinterpret_cast<double2 *>(lds + ((C * SP + 1) & ~1));
+        for (int i = tid; i < S; i += NT) {
+            const double wq = twq[i];
+            twl[i] = make_double2(__fma_rn(wq, q, C52) - C52, wq);
+        }
         __syncthreads();
-        twc = twl;
     }
-    // A row pass reads its twiddles from the w/q table alone (8 bytes each
-    // instead of 16) and recovers w = rint(w/q * q) exactly: |(w/q) q - w| <=
-    // w 2^-53 < 1/8 for w < 2^50, and the FMA rounds the exact product once.
     auto twid = [&](int idx) -> double2 {
         if constexpr (COLPASS) {
-            return twc[idx];
+            return twl[idx];
         } else {
             const double wq = twq[idx];
             return make_double2(__fma_rn(wq, q, C52) - C52, wq);
@@ -243,7 +246,7 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
 }
 
 // Forward transform (Cooley-Tukey, merged psi twiddles): stage g pairs indices
-// j, j + n/2^{g+1} with twiddle tw[2^g + (j >> (logn - g))].  The first logn1
+// j, j + n/2^{g+1} with twiddle w[2^g + (j >> (logn - g))].  The first logn1
 // stages act on columns {c + n2 r}, the rest on contiguous rows of n2.  The
 // inverse runs the Gentleman-Sande butterflies in the opposite stage order,
 // rows first, and folds n^{-1} into its final stage.
@@ -256,7 +259,7 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
 template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool FUSE>
 __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
     ntt_pass(u64 *__restrict__ base, size_t poly_stride, int limbs, LimbMap map, int logn,
-             const double2 *__restrict__ mq, const double2 *__restrict__ twtab, const double *__restrict__ twqtab,
+             const double2 *__restrict__ mq, const double *__restrict__ twqtab,
              const double2 *__restrict__ twlast, const NttFuse fz, const u64 *__restrict__ src, size_t src_stride,
              u32 gal) {
     constexpr int S = 1 << LOGS;
@@ -271,7 +274,6 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
     constexpr bool FIRST = (COLPASS != INV);  // the pass that runs first reads the input
     const u64 *din = (FIRST && src) ? src + (size_t)p * src_stride + (size_t)t * n : data;
     const double q = mq[mod].x, qinv = mq[mod].y;
-    const double2 *tw = twtab + (size_t)mod * n;
     const double *twq = twqtab + (size_t)mod * n;
     constexpr bool PRO = FUSE && COLPASS && !INV;   // prologue: broadcast-reduce one limb
     constexpr bool EPI = FUSE && !COLPASS && !INV;  // epilogue: (x - y) * c (+ add)
@@ -287,7 +289,7 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
             padd2 = fz.add2 + pb * fz.add2_stride + pk * fz.add2_off + (size_t)t * n;
         const double ec = fz.c.v[t], ecq = fz.c.vq[t];
         const u32 ag = fz.add_gal;
-        pass_core<LOGS, LOGE, C, COLPASS, INV, false>(din, c0, logn, mod, q, qinv, tw, twq, twlast, lds,
+        pass_core<LOGS, LOGE, C, COLPASS, INV, false>(din, c0, logn, mod, q, qinv, twq, twlast, lds,
                                                       [&](int, u32 pos, double y) {
             double r = red1(mm_lazy(u2d(px[pos]) - y + q, ec, ecq, q), q);
             if (padd) r = red1(r + u2d(padd[ag > 1 ? gal_src(pos, logn, ag) : pos]), q);
@@ -295,11 +297,11 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
             pout[pos] = d2u(r);
         });
     } else if constexpr (PRO) {
-        pass_core<LOGS, LOGE, C, COLPASS, INV, true>(fz.src + (size_t)p * fz.src_stride, c0, logn, mod, q, qinv, tw,
+        pass_core<LOGS, LOGE, C, COLPASS, INV, true>(fz.src + (size_t)p * fz.src_stride, c0, logn, mod, q, qinv,
                                                      twq, twlast, lds,
                                                      [&](int, u32 pos, double y) { data[pos] = d2u(y); });
     } else {
-        pass_core<LOGS, LOGE, C, COLPASS, INV, false>(din, c0, logn, mod, q, qinv, tw, twq, twlast, lds,
+        pass_core<LOGS, LOGE, C, COLPASS, INV, false>(din, c0, logn, mod, q, qinv, twq, twlast, lds,
                                                       [&](int, u32 pos, double y) { data[pos] = d2u(y); }, g);
     }
 }
@@ -372,7 +374,7 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
         } else {
             __syncthreads();  // the previous digit's last LDS reads are done
             pass_core<LOGS, LOGE, C, false, false, false>(a.ext + bi * a.sext + ((size_t)j * a.E + t) * n, c0, logn,
-                                                          mod, q, qinv, nullptr, twq, twlast, lds, acc);
+                                                          mod, q, qinv, twq, twlast, lds, acc);
         }
         if ((j & 7) == 7) {
 #pragma unroll
@@ -408,14 +410,13 @@ static void launch_pass(const DevTables &T, const LimbBatch &b, hipStream_t s, c
     const int blocks = (1 << (logn - LOGS)) / C;
     dim3 grid(blocks, b.limbs * b.polys);
     dim3 block(C * (1 << (LOGS - LOGE)));
-    const double2 *tw = INV ? T.tw_inv : T.tw_fwd;
     const double *twq = INV ? T.twq_inv : T.twq_fwd;
     if (f && !INV && (COLPASS ? f->pro : f->epi))
         hipLaunchKernelGGL((ntt_pass<LOGS, LOGE, C, COLPASS, INV, true>), grid, block, 0, s, b.base, b.poly_stride,
-                           b.limbs, b.map, logn, T.mq, tw, twq, T.tw_last, *f, b.src, b.src_stride, b.gal);
+                           b.limbs, b.map, logn, T.mq, twq, T.tw_last, *f, b.src, b.src_stride, b.gal);
     else
         hipLaunchKernelGGL((ntt_pass<LOGS, LOGE, C, COLPASS, INV, false>), grid, block, 0, s, b.base, b.poly_stride,
-                           b.limbs, b.map, logn, T.mq, tw, twq, T.tw_last, NttFuse{}, b.src, b.src_stride, b.gal);
+                           b.limbs, b.map, logn, T.mq, twq, T.tw_last, NttFuse{}, b.src, b.src_stride, b.gal);
 }
 
 // tile variants: (elements per thread 2^LOGE, columns per workgroup C)

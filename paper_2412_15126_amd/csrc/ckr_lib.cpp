@@ -458,8 +458,8 @@ static void setup_tables(Ctx &C) {
     const u64 n = P.n;
     C.T.logn = P.logn;
     C.T.nmod = nm;
-    std::vector<double2> mq(nm), fwd((size_t)nm * n), inv((size_t)nm * n), last(2 * nm);
-    std::vector<double> fwdq((size_t)nm * n), invq((size_t)nm * n);
+    std::vector<double2> mq(nm), last(2 * nm);
+    std::vector<double> fwdq((size_t)nm * n), invq((size_t)nm * n);  // w/q (IEEE division)
     std::vector<u64> qi(nm);
     std::vector<u64> pw(n), ipw(n);
     for (int t = 0; t < nm; t++) {
@@ -475,10 +475,8 @@ static void setup_tables(Ctx &C) {
         }
         for (u64 i = 0; i < n; i++) {
             const u64 w = pw[brev(i, P.logn)], wi = ipw[brev(i, P.logn)];
-            fwd[(size_t)t * n + i] = make_double2((double)w, (double)w / dq);
-            inv[(size_t)t * n + i] = make_double2((double)wi, (double)wi / dq);
-            fwdq[(size_t)t * n + i] = fwd[(size_t)t * n + i].y;
-            invq[(size_t)t * n + i] = inv[(size_t)t * n + i].y;
+            fwdq[(size_t)t * n + i] = (double)w / dq;
+            invq[(size_t)t * n + i] = (double)wi / dq;
         }
         const u64 ninv = hinv(n % q, q);
         const u64 w1 = hmul(ipw[n / 2], ninv, q);
@@ -487,13 +485,9 @@ static void setup_tables(Ctx &C) {
     }
     C.T.mq = (double2 *)C.table_alloc(nm * sizeof(double2));
     C.T.qi = (u64 *)C.table_alloc(nm * sizeof(u64));
-    C.T.tw_fwd = (double2 *)C.table_alloc(fwd.size() * sizeof(double2));
-    C.T.tw_inv = (double2 *)C.table_alloc(inv.size() * sizeof(double2));
     C.T.tw_last = (double2 *)C.table_alloc(last.size() * sizeof(double2));
     HIPCHK(hipMemcpy(C.T.mq, mq.data(), nm * sizeof(double2), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(C.T.qi, qi.data(), nm * sizeof(u64), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(C.T.tw_fwd, fwd.data(), fwd.size() * sizeof(double2), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(C.T.tw_inv, inv.data(), inv.size() * sizeof(double2), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(C.T.tw_last, last.data(), last.size() * sizeof(double2), hipMemcpyHostToDevice));
     C.T.twq_fwd = (double *)C.table_alloc(fwdq.size() * sizeof(double));
     C.T.twq_inv = (double *)C.table_alloc(invq.size() * sizeof(double));

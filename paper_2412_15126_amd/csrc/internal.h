@@ -34,11 +34,9 @@ struct DevTables {
     int nmod;
     double2 *mq;      // [nmod] {q, 1/q}
     u64 *qi;          // [nmod] q as integers
-    double2 *tw_fwd;  // [nmod][n] {w, w/q}, w = psi^{brev(i)}
-    double2 *tw_inv;  // [nmod][n] {w, w/q}, w = psi^{-brev(i)}
     double2 *tw_last; // [nmod][2]: {n^-1, n^-1/q}, {psi^{-brev(1)} n^-1, ./q}
-    double *twq_fwd;  // [nmod][n] w/q of tw_fwd alone (row passes recover w = rint(w/q * q))
-    double *twq_inv;  // [nmod][n] w/q of tw_inv alone
+    double *twq_fwd;  // [nmod][n] w/q, w = psi^{brev(i)} (the passes recover w = rint(w/q * q))
+    double *twq_inv;  // [nmod][n] w/q, w = psi^{-brev(i)}
     int ntt_variant[2][2] = {{0, 0}, {0, 0}};  // [inverse][pass]: tile variant chosen by the autotuner
     int row_ip_variant = 2;                      // tile of the fused row pass + inner product
 };
