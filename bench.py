@@ -14,6 +14,7 @@ kernel sources), per-category kernel rates and the oracle timed on the host.
 Other workloads: --workload, --mixed, --serve.
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -441,6 +442,89 @@ def circuit_bench(args):
     print(json.dumps(res), flush=True)
 
 
+def cheb_sweep(args):
+    """Rank of N=128 with the Chebyshev comparator at depths 6..14 (degree
+    2^(D-1) - 1): the setting of the appendix figure on the approximation
+    degree (values uniform in [0, 1) with no gap; ring n=2^15 up to depth 11,
+    n=2^16 above).  Per depth: batched throughput (graph replays of 32
+    queries), one-query latency (graph replays of one query), and the mean and
+    maximum rank error over the batch, next to the figure's values."""
+    import paper_2412_15126_amd as ckr
+    from paper_2412_15126_amd import hip
+    from paper_2412_15126_amd import workloads as W
+
+    fig = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                                      "paper_rank_degree.json")))
+    N = 128
+    rows = []
+
+    def run_depth(i, D, B):
+        pname = "P15" if fig["ring_logn"][i] == 15 else "P16"
+        ps = W.PSETS[pname]
+        cmp = (0, 0, D)
+        level = ckr.rank_depth(cmp)
+        ctx = ckr.Context(ps)
+        try:
+            stream = hip.Stream()
+            ctx.set_stream(stream.h.value)
+            keys = ctx.keygen(bytes(range(7, 39)), level, [N], what=1)
+            ctx.autotune(2 * 4 * (level + 1), 2)
+            ctx.autotune_row_ip(4, 2)
+            rng = np.random.default_rng(900 + D)
+            vals = [W.min_gap_uniform(N, 0.0, rng) for _ in range(B)]
+            cts = [ctx.encrypt(keys, v, level, bytes([q]) + bytes(range(1, 32))) for q, v in enumerate(vals)]
+
+            def timed(batch, reps):
+                for _ in range(2):
+                    outs = ctx.run_batch(keys, "rank", batch, N, cmp)
+                ctx.synchronize()
+                ev = [hip.Event() for _ in range(reps + 1)]
+                ev[0].record(stream)
+                for r in range(reps):
+                    ctx.run_batch(keys, "rank", batch, N, cmp)
+                    ev[r + 1].record(stream)
+                ctx.synchronize()
+                return outs, [ev[r].elapsed_ms(ev[r + 1]) for r in range(reps)]
+
+            outs, step_ms = timed(cts, args.steps)
+            one_ms = timed(cts[:1], 10)[1]
+            err = np.concatenate([np.abs(ctx.decrypt(keys, o, N) - (np.argsort(np.argsort(v)) + 1))
+                                  for o, v in zip(outs, vals)])
+            return {"depth": D, "degree": 2 ** (D - 1) - 1, "ring": f"2^{ps['logn']}", "level": level, "batch": B,
+                    "queries_per_s": round(B * 1e3 / float(np.mean(step_ms)), 2),
+                    "ms_per_query_alone": round(float(np.median(one_ms)), 3),
+                    "avg_error": round(float(err.mean()), 4), "max_error": round(float(err.max()), 4),
+                    "paper_s_per_query": fig["runtime_s"][i], "paper_avg_error": fig["avg_error"][i],
+                    "paper_max_error": fig["max_error"][i]}
+        finally:
+            outs = cts = keys = timed = None
+            gc.collect()
+            ctx.close()   # release this ring's device memory before the next run
+
+    for i, D in enumerate(fig["depth"]):
+        B = 32
+        while True:
+            try:
+                rows.append(run_depth(i, D, B))
+                break
+            except ckr.CkrError as e:
+                # a captured batch keeps every intermediate of the circuit: the
+                # deepest comparators need a smaller batch to fit
+                if e.status != -4 or B == 1:
+                    raise
+                log(f"[cheb-sweep] depth {D}: batch {B} does not fit ({e}); halving")
+                B //= 2
+        log(f"[cheb-sweep] {rows[-1]}")
+    res = {"metric": "rank-128 queries/s and rank error against the Chebyshev comparison depth",
+           "value": rows[-1]["queries_per_s"], "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
+           "data": "synthetic", "dtype": "u64",
+           "config": {"workload": f"rank N=128, values uniform in [0, 1) without gap, batch 32 (less where it "
+                                  f"does not fit), depths "
+                                  f"{fig['depth'][0]}..{fig['depth'][-1]} (value: the deepest)"},
+           "sweep": rows}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -455,6 +539,8 @@ def main():
                     choices=["rank128", "argmin128", "argmax128", "sort128", "rank512", "sort512", "rank128cheb",
                              "argmin128cheb", "sort128col", "kth64div", "median128"],
                     help="circuit to time (rank128: the headline metric)")
+    ap.add_argument("--cheb-sweep", action="store_true",
+                    help="rank-128 runtime and error against the Chebyshev comparison depth 6..14")
     ap.add_argument("--rate", type=float, default=4.0)
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--max-batch", type=int, default=8)
@@ -467,6 +553,8 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
     if args.serve:
         return serve(args)
+    if args.cheb_sweep:
+        return cheb_sweep(args)
     if args.mixed:
         return mixed(args)
     if args.workload != "rank128":

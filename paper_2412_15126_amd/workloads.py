@@ -23,6 +23,9 @@ import numpy as np
 PSETS = {
     # toy ring for the N=8 rank (not secure)
     "P12": dict(logn=12, L=11, q0_bits=44, log_scale=36, K=4, p_bits=40, dnum=3),
+    # rank on N = 128 at n = 2^15 with the Chebyshev comparator up to 11 levels
+    # (13 levels, log QP ~ 820 bits)
+    "P15": dict(logn=15, L=13, q0_bits=50, log_scale=40, K=5, p_bits=50, dnum=3),
     # rank on N <= 128 at n = 2^16 (log QP ~ 1320 bits)
     "P16": dict(logn=16, L=23, q0_bits=50, log_scale=40, K=7, p_bits=50, dnum=3),
     # tie-corrected argmin and sort on N <= 128 at n = 2^17 (40 levels, log QP ~ 2150 bits)
