@@ -83,7 +83,7 @@ __device__ __forceinline__ u32 gal_src(u32 i, int logn, u32 g) {
 // stages and hands every final value to emit(k, pos, y), k in [0, E) being
 // the thread's ordinal of that element (the same position for every call
 // from the same thread).
-template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool PRO, class Emit>
+template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool PRO, bool IN_LOOP = false, class Emit>
 __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, int logn, int mod, double q,
                                           double qinv, const double *__restrict__ twq,
                                           const double2 *__restrict__ twlast,
@@ -94,7 +94,13 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
     constexpr bool FINAL = (INV == COLPASS);
     const double two_q = 2.0 * q;
     const int ncol = 1 << (logn - LOGS);
-    const int tid = threadIdx.x;
+    int tid = threadIdx.x;
+    // Called in a loop (the fused key-switch kernel runs one pass per digit),
+    // the compiler would compute every thread-dependent address once, before
+    // the loop, and keep them all live across it: 2 waves per SIMD instead of
+    // 3 (5 for 4 elements per thread).  An opaque copy of the thread index
+    // makes it recompute them in each pass.
+    if constexpr (IN_LOOP) asm volatile("" : "+v"(tid));
     const int cl = COLPASS ? (tid % C) : (tid / TPC);
     const int tau = COLPASS ? (tid / C) : (tid % TPC);
     const int c = c0 + cl;
@@ -340,24 +346,16 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
 #pragma unroll
     for (int k = 0; k < E; k++) sb[k] = sa[k] = 0.0;
     for (int j = 0; j < a.beta; j++) {
-        // this digit's key words, loaded before the butterflies so that their
-        // latency hides behind the pass (loaded at the point of use, each one
-        // would be a separate round trip)
+        // this digit's key words, read where the pass hands over its outputs
+        // (held across the pass they would cost 4E registers)
         const u64 *kb = a.key + (((size_t)j * 2 + 0) * a.Ek + kl) * n;
         const u64 *ka = a.key + (((size_t)j * 2 + 1) * a.Ek + kl) * n;
-        u64 kbw[E], kaw[E];
-#pragma unroll
-        for (int k = 0; k < E; k++) {
-            const u32 pos = (u32)(c0 * S + tid + k * NT);
-            kbw[k] = kb[pos];
-            kaw[k] = ka[pos];
-        }
         // products in (-0.75q, 0.75q) accumulate unreduced: exact while the
         // sums stay below 2^53 in magnitude (the library allows at most 8
         // digits; a reduction every 8 keeps any count safe)
-        auto acc = [&](int k, u32, double x) {
-            sb[k] += mm_signed(x, u2d(kbw[k]), q, qinv);
-            sa[k] += mm_signed(x, u2d(kaw[k]), q, qinv);
+        auto acc = [&](int k, u32 pos, double x) {
+            sb[k] += mm_signed(x, u2d(kb[pos]), q, qinv);
+            sa[k] += mm_signed(x, u2d(ka[pos]), q, qinv);
         };
         if (j == own) {
             const u64 *xs = a.d + bi * a.sd + (size_t)t * n;
@@ -370,10 +368,11 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
                 for (int k = 0; k < E; k++) xv[k] = u2d(xs[(u32)(c0 * S + tid + k * NT)]);
             }
 #pragma unroll
-            for (int k = 0; k < E; k++) acc(k, 0, xv[k]);
+            for (int k = 0; k < E; k++) acc(k, (u32)(c0 * S + tid + k * NT), xv[k]);
         } else {
             __syncthreads();  // the previous digit's last LDS reads are done
-            pass_core<LOGS, LOGE, C, false, false, false>(a.ext + bi * a.sext + ((size_t)j * a.E + t) * n, c0, logn,
+            pass_core<LOGS, LOGE, C, false, false, false, true>(a.ext + bi * a.sext + ((size_t)j * a.E + t) * n, c0,
+                                                                logn,
                                                           mod, q, qinv, twq, twlast, lds, acc);
         }
         if ((j & 7) == 7) {
