@@ -644,40 +644,49 @@ __global__ void __launch_bounds__(256)
     ew_bconv(u64 *out, const u64 *__restrict__ src, BConvTab tab, const double2 *__restrict__ hmod,
              const double2 *__restrict__ hinv, int logn, size_t so, size_t si, const double2 *__restrict__ mq,
              int tpg) {
+    // two adjacent coefficients per thread: 16-byte loads and stores, and
+    // every (source, target) constant serves two products
     const size_t n = (size_t)1 << logn;
     const int j0 = blockIdx.z * tpg, j1 = min(j0 + tpg, tab.nt);
-    const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t c = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 2;
     if (c >= n) return;
     const u64 *sb = src + blockIdx.y * si;
     u64 *ob = out + blockIdx.y * so;
-    double y[NS];
+    double y0[NS], y1[NS];
 #pragma unroll
     for (int i = 0; i < NS; i++) {
         const double q = mq[tab.src_mod[i]].x;
         const double2 h = hinv[i];
-        y[i] = red1(mm_lazy(u2d(sb[(size_t)i * n + c]), h.x, h.y, q), q);
+        const ulonglong2 v = *(const ulonglong2 *)(sb + (size_t)i * n + c);
+        y0[i] = red1(mm_lazy(u2d(v.x), h.x, h.y, q), q);
+        y1[i] = red1(mm_lazy(u2d(v.y), h.x, h.y, q), q);
     }
     for (int j = j0; j < j1; j++) {
         const double2 Q = mq[tab.tgt_mod[j]];
         const double tq = Q.x, two_t = 2.0 * tq;
-        double acc = 0.0;
+        double a0 = 0.0, a1 = 0.0;
         if (tq * (2 * NS) < C52) {
 #pragma unroll
             for (int i = 0; i < NS; i++) {
                 const double2 h = hmod[i * tab.nt + j];
-                acc += mm_lazy(y[i], h.x, h.y, tq);
+                a0 += mm_lazy(y0[i], h.x, h.y, tq);
+                a1 += mm_lazy(y1[i], h.x, h.y, tq);
             }
-            acc = red_any(acc, tq, Q.y);
+            a0 = red_any(a0, tq, Q.y);
+            a1 = red_any(a1, tq, Q.y);
         } else {
 #pragma unroll
             for (int i = 0; i < NS; i++) {
                 const double2 h = hmod[i * tab.nt + j];
-                acc += mm_lazy(y[i], h.x, h.y, tq);
-                acc = acc >= two_t ? acc - two_t : acc;
+                a0 += mm_lazy(y0[i], h.x, h.y, tq);
+                a0 = a0 >= two_t ? a0 - two_t : a0;
+                a1 += mm_lazy(y1[i], h.x, h.y, tq);
+                a1 = a1 >= two_t ? a1 - two_t : a1;
             }
-            acc = red1(acc, tq);
+            a0 = red1(a0, tq);
+            a1 = red1(a1, tq);
         }
-        ob[(size_t)tab.tgt_slot[j] * n + c] = d2u(acc);
+        *(ulonglong2 *)(ob + (size_t)tab.tgt_slot[j] * n + c) = make_ulonglong2(d2u(a0), d2u(a1));
     }
 }
 
@@ -765,12 +774,14 @@ void k_automorph(const DevTables &T, u64 *out, const u64 *in, int limbs, int pol
 }
 void k_bconv(const DevTables &T, u64 *out, const u64 *src, const BConvTab &tab, int batch, size_t so, size_t si,
              hipStream_t s) {
-    // split the targets into groups so small batches still fill the chip
-    const int blocks = (int)(((1u << T.logn) + 255) / 256) * batch;
+    // two coefficients per thread; split the targets into groups so small
+    // batches still fill the chip
+    const unsigned bx = ((1u << T.logn) / 2 + 255) / 256;
+    const int blocks = (int)bx * batch;
     int groups = std::max(1, std::min(tab.nt, 2048 / std::max(blocks, 1)));
     const int tpg = (tab.nt + groups - 1) / groups;
     groups = (tab.nt + tpg - 1) / tpg;
-    dim3 grid((unsigned)(((1u << T.logn) + 255) / 256), (unsigned)batch, (unsigned)groups);
+    dim3 grid(bx, (unsigned)batch, (unsigned)groups);
 #define BCONV_CASE(K)                                                                                       \
     case K:                                                                                                 \
         hipLaunchKernelGGL(ew_bconv<K>, grid, dim3(256), 0, s, out, src, tab, tab.hmod, tab.hinv, T.logn, so, si, \
