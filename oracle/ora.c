@@ -624,6 +624,23 @@ void ora_bconv(const u64 *x, const u64 *src, int ns, u64 t, u64 n, u64 *out) {
 }
 
 /* key switch of d (coefficient domain, limbs 0..level) with key w -> (kb, ka), coefficient domain */
+/* ModDown rounds: floor((X + (P - 1)/2) / P) - u (u < K from the fast base
+ * conversion) instead of floor(X / P) - u.  This adds (P - 1)/2 to every
+ * coefficient of x (coefficient domain), given on q_0..q_level then
+ * p_0..p_{K-1}; P is odd, so (P - 1)/2 mod m = (P mod m - 1) / 2 mod m. */
+static void add_half_P(const ora_params *P, u64 *x, int level) {
+    const u64 n = P->n;
+    const int K = P->K;
+    for (int i = 0; i <= level + K; i++) {
+        const u64 m = i <= level ? P->mod[i] : P->mod[P->nq + (i - level - 1)];
+        u64 pm = 1 % m;
+        for (int k = 0; k < K; k++) pm = mulm(pm, P->mod[P->nq + k] % m, m);
+        const u64 h = mulm(subm(pm, 1 % m, m), invm(2 % m, m), m);
+        u64 *xl = LIMB(x, i, n);
+        for (u64 c = 0; c < n; c++) xl[c] = addm(xl[c], h, m);
+    }
+}
+
 static void keyswitch(const ora_keys *Kp, const ora_swk *w, const u64 *d, int level, u64 *kb, u64 *ka) {
     const ora_params *P = Kp->P;
     u64 n = P->n; int lmax = Kp->lmax, K = P->K;
@@ -663,6 +680,7 @@ static void keyswitch(const ora_keys *Kp, const ora_swk *w, const u64 *d, int le
     for (int k = 0; k < K; k++) psrc[k] = P->mod[P->nq + k];
     for (int pol = 0; pol < 2; pol++) {
         u64 *acc = pol == 0 ? accb : acca, *out = pol == 0 ? kb : ka;
+        add_half_P(P, acc, level);
         const u64 *ptr[ORA_MAXMOD];
         for (int k = 0; k < K; k++) ptr[k] = LIMB(acc, level + 1 + k, n);
         #pragma omp parallel for schedule(dynamic)
@@ -680,8 +698,11 @@ static void keyswitch(const ora_keys *Kp, const ora_swk *w, const u64 *d, int le
 }
 
 /* pin helper: ModDown of one polynomial given on (q_0..q_level, p_0..p_{K-1}) */
-void ora_moddown(const ora_params *P, int level, const u64 *x, u64 *out) {
+void ora_moddown(const ora_params *P, int level, const u64 *x_in, u64 *out) {
     u64 n = P->n; int K = P->K;
+    u64 *x = (u64 *)malloc((size_t)(level + 1 + K) * n * 8);
+    memcpy(x, x_in, (size_t)(level + 1 + K) * n * 8);
+    add_half_P(P, x, level);
     u64 psrc[ORA_MAXMOD]; const u64 *ptr[ORA_MAXMOD];
     for (int k = 0; k < K; k++) { psrc[k] = P->mod[P->nq + k]; ptr[k] = LIMB(x, level + 1 + k, n); }
     for (int i = 0; i <= level; i++) {
@@ -693,16 +714,25 @@ void ora_moddown(const ora_params *P, int level, const u64 *x, u64 *out) {
         for (u64 c = 0; c < n; c++) LIMB(out, i, n)[c] = mulm(subm(LIMB(x, i, n)[c], conv[c], q), pinv, q);
         free(conv);
     }
+    free(x);
 }
 
-/* floor-form rescale of one polynomial (limbs 0..level) -> limbs 0..level-1 */
+/* rounding rescale of one polynomial (limbs 0..level) -> limbs 0..level-1:
+ * floor((X + (q_l - 1)/2) / q_l), i.e. (X - v) / q_l with v the residue of X
+ * mod q_l taken in (-q_l/2, q_l/2).  A floor would leave every coefficient
+ * about 1/2 low, and such a constant coefficient bias b shows in slot k as
+ * 2b / (1 - zeta_k), largest in slot 0. */
 static void rescale_poly(const ora_params *P, const u64 *x, int level, u64 *out) {
     u64 n = P->n, ql = P->mod[level];
     const u64 *xl = LIMB(x, level, n);
     #pragma omp parallel for schedule(dynamic)
     for (int i = 0; i < level; i++) {
-        u64 q = P->mod[i], inv = invm(ql % q, q);
-        for (u64 c = 0; c < n; c++) LIMB(out, i, n)[c] = mulm(subm(LIMB(x, i, n)[c], xl[c] % q, q), inv, q);
+        u64 q = P->mod[i], inv = invm(ql % q, q), qlq = ql % q;
+        for (u64 c = 0; c < n; c++) {
+            u64 v = xl[c] % q;
+            if (xl[c] > ql / 2) v = subm(v, qlq, q);   /* the residue minus q_l */
+            LIMB(out, i, n)[c] = mulm(subm(LIMB(x, i, n)[c], v, q), inv, q);
+        }
     }
 }
 void ora_rescale_poly(const ora_params *P, const u64 *x, int level, u64 *out) { rescale_poly(P, x, level, out); }

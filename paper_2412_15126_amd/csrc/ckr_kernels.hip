@@ -87,7 +87,7 @@ template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool PRO, bool IN_L
 __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, int logn, int mod, double q,
                                           double qinv, const double *__restrict__ twq,
                                           const double2 *__restrict__ twlast,
-                                          double *lds, Emit &&emit, u32 gal = 0) {
+                                          double *lds, Emit &&emit, u32 gal = 0, double cq = 0.0) {
     constexpr int S = 1 << LOGS, E = 1 << LOGE, TPC = S / E, NT = C * TPC;
     constexpr int NR = (LOGS + LOGE - 1) / LOGE;
     constexpr int SP = S + (S >> 4) + 1;
@@ -145,8 +145,13 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
         // ---- load
         if (rho == 0) {
             if (PRO) {
+                // the input limb's residues mod cq, taken in (-cq/2, cq/2) when cq > 0
 #pragma unroll
-                for (int k = 0; k < E; k++) x[k] = red_any(u2d(din[gaddr(rbase | (k << w))]), q, qinv);
+                for (int k = 0; k < E; k++) {
+                    double v = u2d(din[gaddr(rbase | (k << w))]);
+                    if (v > 0.5 * cq) v -= cq;
+                    x[k] = red_any(v, q, qinv);
+                }
             } else if (direct) {
                 if (gal > 1) {
 #pragma unroll
@@ -305,7 +310,8 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
     } else if constexpr (PRO) {
         pass_core<LOGS, LOGE, C, COLPASS, INV, true>(fz.src + (size_t)p * fz.src_stride, c0, logn, mod, q, qinv,
                                                      twq, twlast, lds,
-                                                     [&](int, u32 pos, double y) { data[pos] = d2u(y); });
+                                                     [&](int, u32 pos, double y) { data[pos] = d2u(y); }, 0,
+                                                     fz.pro_q);
     } else {
         pass_core<LOGS, LOGE, C, COLPASS, INV, false>(din, c0, logn, mod, q, qinv, twq, twlast, lds,
                                                       [&](int, u32 pos, double y) { data[pos] = d2u(y); }, g);
@@ -660,6 +666,11 @@ __global__ void __launch_bounds__(256)
         const ulonglong2 v = *(const ulonglong2 *)(sb + (size_t)i * n + c);
         y0[i] = red1(mm_lazy(u2d(v.x), h.x, h.y, q), q);
         y1[i] = red1(mm_lazy(u2d(v.y), h.x, h.y, q), q);
+        if (tab.pre) {
+            const double a = tab.pre[i];
+            y0[i] = red1(y0[i] + a, q);
+            y1[i] = red1(y1[i] + a, q);
+        }
     }
     for (int j = j0; j < j1; j++) {
         const double2 Q = mq[tab.tgt_mod[j]];
@@ -685,6 +696,11 @@ __global__ void __launch_bounds__(256)
             }
             a0 = red1(a0, tq);
             a1 = red1(a1, tq);
+        }
+        if (tab.post) {
+            const double b = tab.post[j];
+            a0 = pos1(a0 - b, tq);
+            a1 = pos1(a1 - b, tq);
         }
         *(ulonglong2 *)(ob + (size_t)tab.tgt_slot[j] * n + c) = make_ulonglong2(d2u(a0), d2u(a1));
     }

@@ -497,7 +497,7 @@ static void setup_tables(Ctx &C) {
 
 // fast base conversion table from moduli src[] to moduli tgt[] (output slots given)
 static BConvTab make_bconv(Ctx &C, const std::vector<int> &src, const std::vector<int> &tgt,
-                           const std::vector<int> &slot) {
+                           const std::vector<int> &slot, bool round = false) {
     if ((int)src.size() > kMaxBConvSrc || (int)tgt.size() > kMaxLimbArgs) throw Error{CKR_E_INVALID, "bconv size"};
     BConvTab tab{};
     tab.ns = (int)src.size();
@@ -527,6 +527,25 @@ static BConvTab make_bconv(Ctx &C, const std::vector<int> &src, const std::vecto
     tab.hmod = (double2 *)C.table_alloc(hm.size() * sizeof(double2));
     HIPCHK(hipMemcpy(tab.hinv, hi.data(), hi.size() * sizeof(double2), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(tab.hmod, hm.data(), hm.size() * sizeof(double2), hipMemcpyHostToDevice));
+    tab.pre = tab.post = nullptr;
+    if (round) {
+        // h = (D - 1)/2 for the (odd) source product D: h mod m = (D mod m - 1) / 2 mod m
+        auto half_mod = [&](u64 m) {
+            u64 d = 1 % m;
+            for (int k = 0; k < tab.ns; k++) d = hmul(d, C.P.mod[src[k]] % m, m);
+            return hmul((d + m - 1 % m) % m, hinv(2 % m, m), m);
+        };
+        std::vector<double> pre(tab.ns), post(tab.nt);
+        for (int i = 0; i < tab.ns; i++) {
+            const u64 qi = C.P.mod[src[i]];
+            pre[i] = (double)hmul(half_mod(qi), (u64)hi[i].x, qi);
+        }
+        for (int j = 0; j < tab.nt; j++) post[j] = (double)half_mod(C.P.mod[tgt[j]]);
+        tab.pre = (double *)C.table_alloc(pre.size() * sizeof(double));
+        tab.post = (double *)C.table_alloc(post.size() * sizeof(double));
+        HIPCHK(hipMemcpy(tab.pre, pre.data(), pre.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(tab.post, post.data(), post.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     return tab;
 }
 
@@ -556,7 +575,7 @@ static const BConvTab &moddown_tab(Ctx &C, int level) {
     std::vector<int> src, tgt, slot;
     for (int k = 0; k < C.P.K; k++) src.push_back(C.P.nq + k);
     for (int i = 0; i <= level; i++) tgt.push_back(i), slot.push_back(i);
-    return C.moddown.emplace(level, make_bconv(C, src, tgt, slot)).first->second;
+    return C.moddown.emplace(level, make_bconv(C, src, tgt, slot, true)).first->second;
 }
 
 // ------------------------------------------------------------------------
@@ -640,10 +659,12 @@ static DCt gather(Ctx &C, const DCt &a, const std::vector<int> &idx) {
     return o;
 }
 
-// floor-form rescale: c_i <- (c_i - [c_l]_{q_i}) * q_l^{-1} mod q_i.  The
-// last limb is brought to the coefficient domain, then one fused forward
-// transform reduces it modulo every q_i (prologue) and writes the combined
-// result (epilogue).
+// rounding rescale: c_i <- (c_i - [v]_{q_i}) * q_l^{-1} mod q_i, v the last
+// limb's residue taken in (-q_l/2, q_l/2), i.e. floor((X + (q_l - 1)/2) / q_l)
+// (a floor would leave every coefficient about 1/2 low: a constant bias that
+// slot 0 amplifies the most).  The last limb is brought to the coefficient
+// domain, then one fused forward transform reduces it modulo every q_i
+// (prologue) and writes the combined result (epilogue).
 static DCt ev_rescale(Ctx &C, const DCt &a) {
     const int l = a.level;
     if (l < 1) throw Error{CKR_E_DEPTH, "rescale at level 0"};
@@ -656,6 +677,7 @@ static DCt ev_rescale(Ctx &C, const DCt &a) {
     for (int i = 0; i < l; i++) inv[i] = hinv(C.P.mod[l] % C.P.mod[i], C.P.mod[i]);
     NttFuse f;
     f.pro = true;
+    f.pro_q = (double)C.P.mod[l];
     f.src = last.get();
     f.src_stride = n;
     f.epi = true;
@@ -743,7 +765,8 @@ static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_
     ia.gal = gal;
     // per target limb: beta inputs and 2 outputs per batch entry, 2*beta key limbs once
     timed(C, kNttRowIP, 8.0 * n * E * ((beta + 2.0) * B + 2.0 * beta), [&] { k_ntt_row_ip(C.T, ia, C.stream); });
-    // ModDown: (x_Q - BConv_{P->Q}(x_P)) * P^{-1}, the combine fused into the last NTT pass
+    // ModDown, rounding: (x_Q + h - BConv_{P->Q}(x_P + h)) * P^{-1}, h = (P - 1)/2 (both h's
+    // folded into the base conversion), the combine fused into the last NTT pass
     ntt(C, acc.get() + (size_t)(l + 1) * n, P.K, 2 * B, (size_t)E * n, plain_map(P.nq), true);
     Buf conv(&C, (size_t)2 * B * (l + 1) * n);
     const BConvTab &mdt = moddown_tab(C, l);

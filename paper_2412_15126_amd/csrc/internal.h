@@ -85,6 +85,7 @@ struct NttFuse {
     size_t add2_stride = 0, add2_off = 0;
     int add2_mask = 0;
     LimbScalars c;
+    double pro_q = 0.0;  // prologue: when > 0, the input limb's residues mod pro_q are taken in (-pro_q/2, pro_q/2)
 };
 void k_ntt_fused(const DevTables &T, const LimbBatch &b, const NttFuse &f, int pass, hipStream_t s);
 
@@ -132,6 +133,11 @@ struct BConvTab {
     int tgt_slot[kMaxLimbArgs];  // output limb index of target j
     double2 *hinv;  // [ns]
     double2 *hmod;  // [ns][nt]
+    // rounding ModDown (null otherwise): pre[i] = [h p-hat_i^{-1}]_{p_i} is added
+    // to source i's scaled residue and post[j] = h mod t_j subtracted from
+    // target j, h = (P - 1)/2: the conversion of X + h, minus h
+    double *pre;    // [ns]
+    double *post;   // [nt]
 };
 void k_bconv(const DevTables &T, u64 *out, const u64 *src, const BConvTab &tab, int batch, size_t stride_o,
              size_t stride_i, hipStream_t s);

@@ -170,7 +170,9 @@ def test_bconv_is_exact_up_to_multiple_of_source_product(ora, t10):
         assert ok, c
 
 
-def test_rescale_poly_is_floor_division(ora, t10):
+def test_rescale_poly_is_rounding_division(ora, t10):
+    """rescale = floor((X + (q_l - 1)/2) / q_l) on the CRT lift X: division by
+    q_l rounded to nearest, without the -1/2 bias of a floor"""
     level = 4
     mods = t10.q[:level + 1]
     rng = np.random.default_rng(12)
@@ -178,11 +180,13 @@ def test_rescale_poly_is_floor_division(ora, t10):
     got = ora.rescale_poly(t10, x, level)
     for c in range(0, t10.n, 7):
         X, _ = _crt(x[:, c], mods)
-        y = X // mods[level]
+        y = (X + (mods[level] - 1) // 2) // mods[level]
         assert [int(got[i, c]) for i in range(level)] == [y % m for m in mods[:level]]
 
 
-def test_moddown_is_floor_division_by_P_minus_small(ora, t10):
+def test_moddown_is_rounding_division_by_P_minus_small(ora, t10):
+    """ModDown = floor((X + (P - 1)/2) / P) - u, 0 <= u < K (the fast base
+    conversion's overshoot), on the CRT lift X"""
     level = 3
     qs = t10.q[:level + 1]
     mods = qs + t10.p
@@ -194,7 +198,7 @@ def test_moddown_is_floor_division_by_P_minus_small(ora, t10):
         Pp *= p
     for c in range(0, t10.n, 5):
         X, _ = _crt(x[:, c], mods)
-        base = X // Pp
+        base = (X + (Pp - 1) // 2) // Pp
         found = [u for u in range(len(t10.p)) if all(int(got[i, c]) == (base - u) % qs[i] for i in range(level + 1))]
         assert found, c
 
