@@ -664,19 +664,17 @@ __global__ void __launch_bounds__(256)
         const double q = mq[tab.src_mod[i]].x;
         const double2 h = hinv[i];
         const ulonglong2 v = *(const ulonglong2 *)(sb + (size_t)i * n + c);
-        y0[i] = red1(mm_lazy(u2d(v.x), h.x, h.y, q), q);
-        y1[i] = red1(mm_lazy(u2d(v.y), h.x, h.y, q), q);
-        if (tab.pre) {
-            const double a = tab.pre[i];
-            y0[i] = red1(y0[i] + a, q);
-            y1[i] = red1(y1[i] + a, q);
-        }
+        const double a = tab.pre ? tab.pre[i] : 0.0;  // added before the product: x + a < 2q
+        y0[i] = red1(mm_lazy(u2d(v.x) + a, h.x, h.y, q), q);
+        y1[i] = red1(mm_lazy(u2d(v.y) + a, h.x, h.y, q), q);
     }
     for (int j = j0; j < j1; j++) {
         const double2 Q = mq[tab.tgt_mod[j]];
         const double tq = Q.x, two_t = 2.0 * tq;
-        double a0 = 0.0, a1 = 0.0;
+        const double b = tab.post ? tab.post[j] : 0.0;
+        double a0, a1;
         if (tq * (2 * NS) < C52) {
+            a0 = a1 = -b;  // in (-tq, 0]: the sum stays in (-tq, 2 NS tq), which red_any takes
 #pragma unroll
             for (int i = 0; i < NS; i++) {
                 const double2 h = hmod[i * tab.nt + j];
@@ -686,6 +684,7 @@ __global__ void __launch_bounds__(256)
             a0 = red_any(a0, tq, Q.y);
             a1 = red_any(a1, tq, Q.y);
         } else {
+            a0 = a1 = 0.0;
 #pragma unroll
             for (int i = 0; i < NS; i++) {
                 const double2 h = hmod[i * tab.nt + j];
@@ -694,13 +693,8 @@ __global__ void __launch_bounds__(256)
                 a1 += mm_lazy(y1[i], h.x, h.y, tq);
                 a1 = a1 >= two_t ? a1 - two_t : a1;
             }
-            a0 = red1(a0, tq);
-            a1 = red1(a1, tq);
-        }
-        if (tab.post) {
-            const double b = tab.post[j];
-            a0 = pos1(a0 - b, tq);
-            a1 = pos1(a1 - b, tq);
+            a0 = pos1(red1(a0, tq) - b, tq);
+            a1 = pos1(red1(a1, tq) - b, tq);
         }
         *(ulonglong2 *)(ob + (size_t)tab.tgt_slot[j] * n + c) = make_ulonglong2(d2u(a0), d2u(a1));
     }

@@ -536,10 +536,7 @@ static BConvTab make_bconv(Ctx &C, const std::vector<int> &src, const std::vecto
             return hmul((d + m - 1 % m) % m, hinv(2 % m, m), m);
         };
         std::vector<double> pre(tab.ns), post(tab.nt);
-        for (int i = 0; i < tab.ns; i++) {
-            const u64 qi = C.P.mod[src[i]];
-            pre[i] = (double)hmul(half_mod(qi), (u64)hi[i].x, qi);
-        }
+        for (int i = 0; i < tab.ns; i++) pre[i] = (double)half_mod(C.P.mod[src[i]]);
         for (int j = 0; j < tab.nt; j++) post[j] = (double)half_mod(C.P.mod[tgt[j]]);
         tab.pre = (double *)C.table_alloc(pre.size() * sizeof(double));
         tab.post = (double *)C.table_alloc(post.size() * sizeof(double));

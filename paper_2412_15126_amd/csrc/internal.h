@@ -133,9 +133,9 @@ struct BConvTab {
     int tgt_slot[kMaxLimbArgs];  // output limb index of target j
     double2 *hinv;  // [ns]
     double2 *hmod;  // [ns][nt]
-    // rounding ModDown (null otherwise): pre[i] = [h p-hat_i^{-1}]_{p_i} is added
-    // to source i's scaled residue and post[j] = h mod t_j subtracted from
-    // target j, h = (P - 1)/2: the conversion of X + h, minus h
+    // rounding ModDown (null otherwise): pre[i] = h mod p_i is added to source
+    // i's residue and post[j] = h mod t_j subtracted from target j,
+    // h = (P - 1)/2: the conversion of X + h, minus h
     double *pre;    // [ns]
     double *post;   // [nt]
 };
