@@ -30,8 +30,10 @@
  *               m_j = round_half_away((2*D/n) * Re DFT_2n(w)[j]) with w the
  *               slot vector scattered to positions 5^k mod 2n; evaluated in
  *               binary128 so the rounding is that of the exact value.
- *   - key switching: fast base conversion without correction; rescale is
- *               the floor form (c_i - [c_l]_{q_i}) * q_l^{-1}.
+ *   - key switching: fast base conversion without correction; ModDown and
+ *               rescale round (X + (m - 1)/2 before the floor division by m,
+ *               m = P or q_l): rescale is (c_i - [v]_{q_i}) * q_l^{-1} with v
+ *               the last limb's residue in (-q_l/2, q_l/2).
  */
 #include <stdint.h>
 #include <stdlib.h>
