@@ -329,7 +329,7 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
 // entries of one (limb, tile) run back to back on one XCD and read that
 // tile's key words from its L2.
 template <int LOGS, int LOGE, int C>
-__global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
+__global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)), (LOGE == 2 ? 6 : 1))  // 4 elements: 78 VGPRs, no spill
     ntt_row_ip(const IPArgs a, int logn, const double2 *__restrict__ mq, const double *__restrict__ twqtab,
                const double2 *__restrict__ twlast) {
     constexpr int S = 1 << LOGS, E = 1 << LOGE, NT = C * (S / E);
