@@ -63,10 +63,23 @@ def measured_traffic(category):
     return rows[category]
 
 
+def host_cores():
+    """CPUs this process may run on (its affinity mask), and the thread count
+    the oracle uses: all of them, at most 16 (a GPU machine's CPU share)"""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return avail, max(1, min(16, avail))
+
+
 def cpu_baseline(pset, N, cmp, level, threads):
-    """The oracle, as it stands, timed on this host: one rank-128 query."""
+    """The oracle, as it stands, timed on this host: one rank-128 query with
+    its limb loops on `threads` OpenMP threads, and the same query on one
+    thread (the paper's MT / ST reporting, section 6.1)."""
     from oracle import oracle as O
     from paper_2412_15126_amd import workloads as W
+    avail, _ = host_cores()
     O.set_threads(threads)
     P = O.Params(**pset)
     v, kseed, eseed = W.rank_workload(N, 2.0 ** -10, 0)
@@ -74,15 +87,25 @@ def cpu_baseline(pset, N, cmp, level, threads):
     K = O.Keys(P, kseed, level, P.rank_galois(N))
     tk = time.time() - t
     ct = O.encrypt(K, v, level, eseed)
-    t = time.time()
-    R = O.rank(K, ct, N, *cmp)
-    tr = time.time() - t
-    exact = np.array_equal(np.round(O.decrypt(K, R, N)), np.argsort(np.argsort(v)) + 1)
+    runs = {}
+    for th in (threads, 1):
+        O.set_threads(th)
+        t = time.time()
+        R = O.rank(K, ct, N, *cmp)
+        runs[th] = (time.time() - t, np.array_equal(np.round(O.decrypt(K, R, N)), np.argsort(np.argsort(v)) + 1))
+        log(f"[bench] oracle rank-{N} on {th} thread(s): {runs[th][0]:.1f}s")
+    O.set_threads(threads)
+    tr, exact = runs[threads]
+    t1, exact1 = runs[1]
     return {"value": 1.0 / tr, "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": f"1 rank-{N} query at n=2^16 (keygen {tk:.1f}s excluded), {tr:.1f}s wall, ranks exact={exact}"}
+            "host_cpus_available": avail,
+            "sample": f"1 rank-{N} query at n=2^16 (keygen {tk:.1f}s excluded), {tr:.1f}s wall on {threads} threads, "
+                      f"ranks exact={exact}",
+            "single_thread": {"value": 1.0 / t1, "unit": "queries/s", "cores": 1,
+                              "sample": f"the same query on 1 thread: {t1:.1f}s wall, ranks exact={exact1}"}}
 
 
-def serve(args):
+def serve(args, quiet=False):
     """Served mix: Poisson arrivals, rank N=128 at n=2^16, argmin N=64 and sort
     N in {32,64,128} at n=2^17, continuous batching with an HBM budget."""
     import paper_2412_15126_amd as ckr
@@ -176,7 +199,10 @@ def serve(args):
         "hbm_high_GiB": round((a.memory()[1] + b.memory()[1]) / 2 ** 30, 2),
         "same_alone_as_in_mix": bool(same),
     }
-    print(json.dumps(res), flush=True)
+    srv.close()
+    if not quiet:
+        print(json.dumps(res), flush=True)
+    return res
 
 
 def mixed(args):
@@ -263,10 +289,11 @@ def circuit_bench(args):
 
     name = args.workload
     spec = {
-        "argmin128": dict(pset="P17", N=128, q=dict(kind="order", k=1, tie=True), ci=W.ARGMIN_CMP[128], what=2,
+        "argmin128": dict(pset="P17O", N=128, q=dict(kind="order", k=1, tie=True), ci=W.ARGMIN_CMP[128], what=2,
+                          level="depth",
                           desc="tie-corrected argmin of N=128 (96 distinct values + 32 duplicates, gap 2^-10) at "
-                               "n=2^17 (41 + 10 primes, dnum=4), encrypted at level 40, comparator g^4 f^2, "
-                               "indicator g^3 f^2"),
+                               "n=2^17 (45 + 11 primes, dnum=4), encrypted at level 43 (the circuit's depth), "
+                               "comparator and indicator g^4 f^2"),
         "argmax128": dict(pset="P17O", N=128, q=dict(kind="order", k=128, tie=True), ci=W.ORDER_TIE_CMP[128], what=2,
                           desc="tie-corrected argmax of N=128 (96 distinct values + 32 duplicates, gap 2^-10) at "
                                "n=2^17 (45 + 11 primes, dnum=4), encrypted at level 44, comparator and indicator "
@@ -284,7 +311,7 @@ def circuit_bench(args):
                                  "comparator of degree 2^11 - 1 (12 levels, the paper's setting for rank), encrypted "
                                  "at level 14"),
         "argmin128cheb": dict(pset="P17", N=128, q=dict(kind="order", k=1, tie=True),
-                              ci=(W.CHEB_CMP[128], W.CHEB_CMP[128]), what=2, level="depth", bound=0.02,
+                              ci=(W.CHEB_CMP[128], W.CHEB_CMP[128]), what=2, level="depth", bound=0.05,
                               desc="tie-corrected argmin of N=128 (96 distinct values + 32 duplicates, gap 2^-10) "
                                    "at n=2^17 (41 + 10 primes, dnum=4) with the Chebyshev comparator and indicator "
                                    "of degree 2^11 - 1 (12 levels each, the paper's setting for the minimum), "
@@ -398,7 +425,8 @@ def circuit_bench(args):
                 if not np.array_equal(oh, np.eye(N)[j]):
                     return False, float("inf")
                 worst = max(worst, abs(float(ctx.decrypt(keys, o[1], 1)[0]) - float(np.sort(v)[k - 1])))
-        bound = 0.5 if (multi and not msort) or spec.get("q", {}).get("kind") == "rank" else spec.get("bound", 5e-3)
+        # ranks: within 1/2 of the integers; values: within half the workload's 2^-10 gap
+        bound = 0.5 if (multi and not msort) or spec.get("q", {}).get("kind") == "rank" else spec.get("bound", 2.0 ** -11)
         return worst < bound, worst
 
     for _ in range(2 + args.warmup):
@@ -542,7 +570,8 @@ def main():
     ap.add_argument("--cheb-sweep", action="store_true",
                     help="rank-128 runtime and error against the Chebyshev comparison depth 6..14")
     ap.add_argument("--rate", type=float, default=4.0)
-    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--no-serve", action="store_true", help="skip the served segment of the default run")
     ap.add_argument("--max-batch", type=int, default=8)
     ap.add_argument("--hbm-budget", type=int, default=64, help="GiB of circuit working set in flight")
     args = ap.parse_args()
@@ -615,6 +644,15 @@ def main():
     calib2 = hip.DeviceArray(np.zeros(COPY_BYTES // 8, np.uint64))
     hip.rt().hipMemcpy(calib2.ptr, calib.ptr, COPY_BYTES, 3)
     hip.synchronize()
+    # the same copy timed: a STREAM-style measured HBM rate (read + write bytes)
+    ce = [hip.Event() for _ in range(2)]
+    ce[0].record()
+    for _ in range(10):
+        hip.rt().hipMemcpy(calib2.ptr, calib.ptr, COPY_BYTES, 3)
+    ce[1].record()
+    ce[1].synchronize()
+    copy_GBps = 2 * COPY_BYTES * 10 / (ce[0].elapsed_ms(ce[1]) * 1e-3) / 1e9
+    log(f"[bench] device copy of {COPY_BYTES >> 20} MiB: {copy_GBps:.0f} GB/s (read + write)")
     del calib, calib2
 
     def timed_steps(fn, steps):
@@ -699,7 +737,7 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
                      "launches": int(launches), "avg_launch_us": round(ms * 1e3 / max(launches, 1), 2),
                      "algorithmic_bytes_per_launch": int(nbytes / max(launches, 1)),
-                     "profiled_steps": psteps},
+                     "profiled_steps": psteps, "measured_copy_GBps": round(copy_GBps, 1)},
         "kernels": breakdown,
         "rank_error": {"max": round(float(max(errs)), 4), "queries_exact": int(sum(e < 0.5 for e in errs)),
                        "queries": len(vals)},
@@ -708,9 +746,16 @@ def main():
     if tr:
         res["roofline"]["traffic"] = tr["read"] + tr["write"]
         res["roofline"]["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    if rank == 0 and not args.no_serve:
+        del out
+        log(f"[bench] served segment: Poisson {args.rate}/s for {args.serve_seconds:.0f}s")
+        sv = serve(args, quiet=True)
+        res["served"] = {k: sv[k] for k in ("value", "unit", "latency_ms", "by_kind", "batches", "mean_batch",
+                                              "same_alone_as_in_mix", "hbm_high_GiB")}
+        res["served"]["workload"] = sv["config"]["workload"]
     if rank == 0 and not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        log(f"[bench] cpu baseline with {threads} threads")
+        _, threads = host_cores()
+        log(f"[bench] cpu baseline with {threads} threads and with 1")
         res["cpu_baseline"] = cpu_baseline(pset, N, cmp, level, threads)
     if rank == 0:
         print(json.dumps(res), flush=True)

@@ -278,7 +278,8 @@ typedef struct {
 } ckr_query;
 
 /* Run `count` independent queries of any kinds, sizes and levels as one unit
- * (the batched execution of section 6's many-query setting): queries with the
+ * (batched execution across queries; the paper's own parallelism, sections 5
+ * and 6.1, runs one query's independent comparisons on CPU threads): queries with the
  * same circuit and level form a group whose kernel launches cover all of its
  * members.  With graphs enabled (the default) the first call for a given mix
  * runs eagerly, the second captures every group into one hipGraph owned by

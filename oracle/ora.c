@@ -30,10 +30,13 @@
  *               m_j = round_half_away((2*D/n) * Re DFT_2n(w)[j]) with w the
  *               slot vector scattered to positions 5^k mod 2n; evaluated in
  *               binary128 so the rounding is that of the exact value.
- *   - key switching: fast base conversion without correction; ModDown and
- *               rescale round (X + (m - 1)/2 before the floor division by m,
- *               m = P or q_l): rescale is (c_i - [v]_{q_i}) * q_l^{-1} with v
- *               the last limb's residue in (-q_l/2, q_l/2).
+ *   - key switching: fast base conversion without correction in ModUp;
+ *               ModDown and rescale round (X + (m - 1)/2 before the floor
+ *               division by m, m = P or q_l): rescale is (c_i - [v]_{q_i}) *
+ *               q_l^{-1} with v the last limb's residue in (-q_l/2, q_l/2);
+ *               ModDown's conversion removes its overflow u = floor(sum_i
+ *               y_i / p_i) (evaluated in IEEE double, in source order), so
+ *               ModDown is round(X / P).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -62,7 +65,9 @@ typedef unsigned __int128 u128;
 /* comparator: the f/g composite of section 2.2, g applied d_g times then f
  * applied d_f times (cheb = 0), or the Chebyshev interpolant of Eq. (1) with
  * cheb = D levels (d_g = d_f = 0) */
-typedef struct { int dg, df, cheb; } ora_cmp;
+/* comparator: the f/g composite g^dg then f^df, the Chebyshev interpolant of
+ * cheb levels, or the first mm stages of the minimax composite */
+typedef struct { int dg, df, cheb, mm; } ora_cmp;
 
 /* ------------------------------------------------------------------ */
 /* modular arithmetic on canonical residues                            */
@@ -618,6 +623,42 @@ static void bconv(const u64 *const *x, const u64 *src, int ns, u64 t, u64 *out, 
     }
 }
 
+/* ModDown's base conversion from P = p_0 ... p_{K-1} to t with the overflow
+ * removed.  With y_i = [x_i (P/p_i)^{-1}]_{p_i}, the sum S = sum_i y_i (P/p_i)
+ * equals (X mod P) + u P for the integer u = floor(sum_i y_i / p_i) in
+ * [0, K): the fast conversion's excess.  Uncorrected, u has mean about
+ * (K - 1)/2 in every coefficient of both key-switch outputs; the c1 part's
+ * bias, times the secret, puts a systematic error of about
+ * (K/2) |s(zeta_0)| (2n/pi) / D into slot 0 (the slot whose root lies
+ * closest to 1) after every key switch.  u is computed as the floor of the
+ * IEEE double sum of y_i * (1/p_i), i = 0 .. K-1 in order, no fused
+ * operations (the result can differ from the exact floor only when
+ * X mod P lies within about K^2 2^-52 P of a multiple of P), and u P is
+ * subtracted: the conversion then returns X mod P itself. */
+static void bconv_exact(const u64 *const *x, const u64 *src, int ns, u64 t, u64 *out, u64 n) {
+    u64 hinv[ORA_MAXMOD], hmod[ORA_MAXMOD], pmod = 1 % t;
+    double rinv[ORA_MAXMOD];
+    for (int i = 0; i < ns; i++) {
+        u64 si = src[i], a = 1 % si, b = 1 % t;
+        for (int k = 0; k < ns; k++) if (k != i) { a = mulm(a, src[k] % si, si); b = mulm(b, src[k] % t, t); }
+        hinv[i] = invm(a, si); hmod[i] = b;
+        rinv[i] = 1.0 / (double)si;
+        pmod = mulm(pmod, si % t, t);
+    }
+    for (u64 c = 0; c < n; c++) {
+        u64 acc = 0;
+        double v = 0.0;
+        for (int i = 0; i < ns; i++) {
+            const u64 y = mulm(x[i][c], hinv[i], src[i]);
+            const double f = (double)y * rinv[i];
+            v = v + f;
+            acc = addm(acc, mulm(y % t, hmod[i], t), t);
+        }
+        const u64 u = (u64)floor(v);
+        out[c] = subm(acc, mulm(u % t, pmod, t), t);
+    }
+}
+
 /* pin helper: x given as ns limbs of n residues */
 void ora_bconv(const u64 *x, const u64 *src, int ns, u64 t, u64 n, u64 *out) {
     const u64 *ptr[ORA_MAXMOD];
@@ -626,8 +667,8 @@ void ora_bconv(const u64 *x, const u64 *src, int ns, u64 t, u64 n, u64 *out) {
 }
 
 /* key switch of d (coefficient domain, limbs 0..level) with key w -> (kb, ka), coefficient domain */
-/* ModDown rounds: floor((X + (P - 1)/2) / P) - u (u < K from the fast base
- * conversion) instead of floor(X / P) - u.  This adds (P - 1)/2 to every
+/* ModDown rounds: floor((X + (P - 1)/2) / P) = round(X / P), the base
+ * conversion's overflow removed (bconv_exact).  This adds (P - 1)/2 to every
  * coefficient of x (coefficient domain), given on q_0..q_level then
  * p_0..p_{K-1}; P is odd, so (P - 1)/2 mod m = (P mod m - 1) / 2 mod m. */
 static void add_half_P(const ora_params *P, u64 *x, int level) {
@@ -677,7 +718,7 @@ static void keyswitch(const ora_keys *Kp, const ora_swk *w, const u64 *d, int le
         ntt_inv(LIMB(acca, li, n), n, q, P->psi[mt]);
         free(y);
     }
-    /* ModDown: (x_Q - BConv_{P->q_i}(x_P)) * P^{-1} mod q_i */
+    /* ModDown: (x_Q - [X mod P]_{q_i}) * P^{-1} mod q_i, X mod P from the exact conversion */
     u64 psrc[ORA_MAXMOD];
     for (int k = 0; k < K; k++) psrc[k] = P->mod[P->nq + k];
     for (int pol = 0; pol < 2; pol++) {
@@ -691,7 +732,7 @@ static void keyswitch(const ora_keys *Kp, const ora_swk *w, const u64 *d, int le
             for (int k = 0; k < K; k++) pinv = mulm(pinv, psrc[k] % q, q);
             pinv = invm(pinv, q);
             u64 *conv = (u64 *)malloc(n * 8);
-            bconv(ptr, psrc, K, q, conv, n);
+            bconv_exact(ptr, psrc, K, q, conv, n);
             for (u64 c = 0; c < n; c++) LIMB(out, i, n)[c] = mulm(subm(LIMB(acc, i, n)[c], conv[c], q), pinv, q);
             free(conv);
         }
@@ -712,7 +753,7 @@ void ora_moddown(const ora_params *P, int level, const u64 *x_in, u64 *out) {
         for (int k = 0; k < K; k++) pinv = mulm(pinv, psrc[k] % q, q);
         pinv = invm(pinv, q);
         u64 *conv = (u64 *)malloc(n * 8);
-        bconv(ptr, psrc, K, q, conv, n);
+        bconv_exact(ptr, psrc, K, q, conv, n);
         for (u64 c = 0; c < n; c++) LIMB(out, i, n)[c] = mulm(subm(LIMB(x, i, n)[c], conv[c], q), pinv, q);
         free(conv);
     }
@@ -1020,6 +1061,20 @@ ora_ct *ora_repl_c(const ora_keys *Kp, const ora_ct *V, u32 N, int *st) {
 /* ------------------------------------------------------------------ */
 static const double F_COEF[4] = {35.0 / 16, -35.0 / 16, 21.0 / 16, -5.0 / 16};
 static const double G_COEF[4] = {4589.0 / 1024, -16577.0 / 1024, 25614.0 / 1024, -12860.0 / 1024};
+/* The minimax composite (section 2.2 names composite minimax approximations
+ * of the sign function as the alternative to f and g): stage 0 is the odd
+ * degree-7 polynomial closest to 1 in the maximum norm on [2^-8.5, 1], stage
+ * s the one closest to 1 on the interval stage s-1 maps that onto.  Each
+ * equioscillates on its interval at 5 points; the errors are 0.968, 0.827,
+ * 0.362, 9.8e-3 and 5.1e-9.  Coefficients of x, x^3, x^5, x^7. */
+#define MM_STAGES 5
+static const double MM_COEF[MM_STAGES][4] = {
+    {11.626630381861787, -68.36534054680979, 126.44790262989271, -69.67707957286088},
+    {5.38484717173034, -7.907363201737443, 3.7393070660732937, -0.5295271268765817},
+    {3.8547436306459173, -5.358791130620638, 2.7473565274453287, -0.4363096838044091},
+    {2.363269725894833, -2.5537068630909263, 1.5095093062451124, -0.32798232661912397},
+    {2.1876161909909757, -2.187742945230383, 1.3126373118789916, -0.3125105627390891},
+};
 
 /* a1 x + a3 x^3 + a5 x^5 + a7 x^7 (a7 != 0) at depth 3 with four products:
  *   y = x*x, t = (a7 x)*y = a7 x^3, y2 = y*y, h = y2*(t + a5 x) = a7 x^7 + a5 x^5,
@@ -1186,10 +1241,11 @@ ora_ct *ora_cheb_eval(const ora_keys *Kp, const ora_ct *x, const double *c, u32 
 /* ------------------------------------------------------------------ */
 /* levels the comparator takes: 3 per degree-7 polynomial of the f/g
  * composite, D for the Chebyshev interpolant */
-static int cmp_levels(ora_cmp c) { return c.cheb > 0 ? c.cheb : 3 * (c.dg + c.df); }
+static int cmp_levels(ora_cmp c) { return c.cheb > 0 ? c.cheb : 3 * (c.dg + c.df + c.mm); }
 
 static int cmp_valid(ora_cmp c) {
-    if (c.cheb != 0) return c.dg == 0 && c.df == 0 && c.cheb >= 2 && c.cheb <= 16;
+    if (c.cheb != 0) return c.dg == 0 && c.df == 0 && c.mm == 0 && c.cheb >= 2 && c.cheb <= 16;
+    if (c.mm != 0) return c.dg == 0 && c.df == 0 && c.mm >= 1 && c.mm <= MM_STAGES;
     return c.dg >= 0 && c.df >= 0 && c.dg + c.df >= 1;
 }
 
@@ -1209,9 +1265,9 @@ static ora_ct *cmp_sign_scaled(const ora_keys *Kp, const ora_ct *D, ora_cmp cm, 
         return r;
     }
     ora_ct *X = ct_copy(D);
-    int total = cm.dg + cm.df;
+    int total = cm.mm > 0 ? cm.mm : cm.dg + cm.df;
     for (int r = 0; r < total; r++) {
-        const double *c = r < cm.dg ? G_COEF : F_COEF;
+        const double *c = cm.mm > 0 ? MM_COEF[r] : (r < cm.dg ? G_COEF : F_COEF);
         double cc[4];
         for (int i = 0; i < 4; i++) cc[i] = (r == total - 1) ? c[i] * (a * 0.5) : c[i];
         replace(&X, ora_poly7(Kp, X, cc, st));

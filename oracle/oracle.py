@@ -38,14 +38,15 @@ _lib = None
 
 
 class OraCmp(C.Structure):
-    """comparator: (d_g, d_f) of the f/g composite, or cheb = D levels of the Chebyshev interpolant"""
-    _fields_ = [("dg", C.c_int), ("df", C.c_int), ("cheb", C.c_int)]
+    """comparator: (d_g, d_f) of the f/g composite, cheb = D levels of the
+    Chebyshev interpolant, or mm stages of the minimax composite"""
+    _fields_ = [("dg", C.c_int), ("df", C.c_int), ("cheb", C.c_int), ("mm", C.c_int)]
 
 
 def _cmp(spec):
-    """(d_g, d_f) or (0, 0, D) -> OraCmp"""
-    spec = tuple(int(x) for x in spec)
-    return OraCmp(spec[0], spec[1], spec[2] if len(spec) > 2 else 0)
+    """(d_g, d_f), (0, 0, D) or (0, 0, 0, k) -> OraCmp"""
+    spec = tuple(int(x) for x in spec) + (0, 0)
+    return OraCmp(spec[0], spec[1], spec[2], spec[3])
 
 
 def lib():
@@ -360,25 +361,25 @@ def poly7(keys, a, coeffs):
 # A comparator is given as (d_g, d_f) for the f/g composite or (0, 0, D) for
 # the Chebyshev interpolant taking D levels; the functions taking "dg, df"
 # accept the Chebyshev depth as a third argument.
-def cmp_sign(keys, a, dg, df, cheb=0):
-    return _ct(lib().ora_cmp_sign, a.params, keys.ptr, a.ptr, _cmp((dg, df, cheb)), what="cmp_sign")
+def cmp_sign(keys, a, dg, df, cheb=0, mm=0):
+    return _ct(lib().ora_cmp_sign, a.params, keys.ptr, a.ptr, _cmp((dg, df, cheb, mm)), what="cmp_sign")
 
 
-def cmp_matrix(keys, a, N, dg, df, cheb=0):
-    return _ct(lib().ora_cmp_matrix, a.params, keys.ptr, a.ptr, N, _cmp((dg, df, cheb)), what="cmp_matrix")
+def cmp_matrix(keys, a, N, dg, df, cheb=0, mm=0):
+    return _ct(lib().ora_cmp_matrix, a.params, keys.ptr, a.ptr, N, _cmp((dg, df, cheb, mm)), what="cmp_matrix")
 
 
-def rank(keys, a, N, dg, df, cheb=0):
+def rank(keys, a, N, dg, df, cheb=0, mm=0):
     keys.need(N, 1)
-    return _ct(lib().ora_rank, a.params, keys.ptr, a.ptr, N, _cmp((dg, df, cheb)), what="rank")
+    return _ct(lib().ora_rank, a.params, keys.ptr, a.ptr, N, _cmp((dg, df, cheb, mm)), what="rank")
 
 
-def rank_depth(dg, df, cheb=0):
-    return lib().ora_rank_depth(_cmp((dg, df, cheb)))
+def rank_depth(dg, df, cheb=0, mm=0):
+    return lib().ora_rank_depth(_cmp((dg, df, cheb, mm)))
 
 
-def rank_multi_depth(dg, df, cheb=0):
-    return lib().ora_rank_multi_depth(_cmp((dg, df, cheb)))
+def rank_multi_depth(dg, df, cheb=0, mm=0):
+    return lib().ora_rank_multi_depth(_cmp((dg, df, cheb, mm)))
 
 
 def cheb_step_coeffs(D):
@@ -398,13 +399,13 @@ def cheb_eval(keys, a, coeffs):
     return _ct(lib().ora_cheb_eval, a.params, keys.ptr, a.ptr, _p(c, dblp), len(c), what="cheb_eval")
 
 
-def rank_multi(keys, blocks, b, dg, df, cheb=0):
+def rank_multi(keys, blocks, b, dg, df, cheb=0, mm=0):
     """Multi-ciphertext ranking of len(blocks) blocks of b values; returns the L rank blocks."""
     keys.need(b, 4)
     L = len(blocks)
     arr = (C.c_void_p * L)(*[x.ptr for x in blocks])
     out = (C.c_void_p * L)()
-    st = lib().ora_rank_multi(keys.ptr, arr, L, b, _cmp((dg, df, cheb)), out)
+    st = lib().ora_rank_multi(keys.ptr, arr, L, b, _cmp((dg, df, cheb, mm)), out)
     if st != 0:
         raise OracleError(f"rank_multi: status {STATUS.get(st, st)}")
     return [Ct(out[i], blocks[0].params) for i in range(L)]
@@ -426,10 +427,10 @@ def sort_multi(keys, blocks, b, cmp, ind):
     return [Ct(out[i], blocks[0].params) for i in range(L)]
 
 
-def rank_tie(keys, a, N, dg, df, cheb=0):
+def rank_tie(keys, a, N, dg, df, cheb=0, mm=0):
     """tie-corrected rank (rank plus the tie-correction offset): a permutation of 1..N"""
     keys.need(N, 1)
-    return _ct(lib().ora_rank_tie, a.params, keys.ptr, a.ptr, N, _cmp((dg, df, cheb)), what="rank_tie")
+    return _ct(lib().ora_rank_tie, a.params, keys.ptr, a.ptr, N, _cmp((dg, df, cheb, mm)), what="rank_tie")
 
 
 # ---- primitive pins -------------------------------------------------------

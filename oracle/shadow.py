@@ -21,6 +21,18 @@ from numpy.polynomial import chebyshev as _cheb
 
 F_COEF = (35 / 16, -35 / 16, 21 / 16, -5 / 16)
 G_COEF = (4589 / 1024, -16577 / 1024, 25614 / 1024, -12860 / 1024)
+# minimax composite (section 2.2's pointer to composite minimax approximations
+# of the sign function): stage s is the odd degree-7 minimax approximation of
+# 1 on the interval stage s-1 maps [2^-8.5, 1] onto, stage 0 on [2^-8.5, 1]
+# itself; coefficients of x, x^3, x^5, x^7
+MM_COEF = (
+    (11.626630381861787, -68.36534054680979, 126.44790262989271, -69.67707957286088),
+    (5.38484717173034, -7.907363201737443, 3.7393070660732937, -0.5295271268765817),
+    (3.8547436306459173, -5.358791130620638, 2.7473565274453287, -0.4363096838044091),
+    (2.363269725894833, -2.5537068630909263, 1.5095093062451124, -0.32798232661912397),
+    (2.1876161909909757, -2.187742945230383, 1.3126373118789916, -0.3125105627390891),
+)
+MM_DESIGN_LO = 2.0 ** -8.5
 
 
 def rot_left(x, k):
@@ -119,15 +131,29 @@ def cheb_step_coeffs(D):
 
 
 def is_cheb(cmp):
-    return len(cmp) == 3 and cmp[2] > 0
+    return len(cmp) >= 3 and cmp[2] > 0
+
+
+def is_minimax(cmp):
+    return len(cmp) == 4 and cmp[3] > 0
+
+
+def sign_minimax(d, k):
+    """the first k stages of the minimax composite on d"""
+    for a in MM_COEF[:k]:
+        d = poly7(d, a)
+    return d
 
 
 def cmp_of(d, cmp):
-    """Cmp on the difference d under the spec cmp (ideal, composite or Chebyshev)."""
+    """Cmp on the difference d under the spec cmp: ideal, f/g composite
+    (d_g, d_f), Chebyshev (0, 0, D) or minimax composite (0, 0, 0, k)."""
     if isinstance(cmp, str):
         return cmp_ideal(d, 0.0)
     if is_cheb(cmp):
         return _cheb.chebval(d, cheb_step_coeffs(cmp[2]))
+    if is_minimax(cmp):
+        return (sign_minimax(d, cmp[3]) + 1.0) / 2.0
     return (sign_composite(d, cmp[0], cmp[1]) + 1.0) / 2.0
 
 

@@ -246,6 +246,17 @@ class Context:
     def set_stream(self, stream_ptr):
         _ok(lib().ckr_context_set_stream(self.h, vp(stream_ptr)))
 
+    def set_allocator(self, alloc, free):
+        """Route the context's device allocations through alloc(nbytes) -> device
+        pointer (int; 0 or None fails the allocation) and free(ptr); must come
+        before any key or ciphertext exists.  The callbacks stay referenced by
+        the context."""
+        AF = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+        FF = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+        cbs = (AF(lambda nbytes, user: alloc(nbytes) or None), FF(lambda ptr, user: free(ptr)))
+        _ok(lib().ckr_context_set_allocator(self.h, C.cast(cbs[0], vp), C.cast(cbs[1], vp), None))
+        self._allocator = cbs
+
     def memory(self):
         a, b = C.c_size_t(), C.c_size_t()
         _ok(lib().ckr_context_memory(self.h, C.byref(a), C.byref(b)))
@@ -507,6 +518,8 @@ class Server:
     def add_route(self, kind, N, ctx, keys, cmp, ind=(0, 0)):
         _ok(lib().ckr_server_add_route(self.h, KINDS[kind], N, ctx.h, keys.h, sign(cmp), sign(ind)))
         self.ctx_of[(kind, N)] = ctx
+        self._routes = getattr(self, "_routes", [])
+        self._routes.append((ctx, keys))     # the route's context and keys outlive the server
 
     def submit(self, kind, N, ct):
         t = C.c_uint64()

@@ -659,6 +659,9 @@ __global__ void __launch_bounds__(256)
     const u64 *sb = src + blockIdx.y * si;
     u64 *ob = out + blockIdx.y * so;
     double y0[NS], y1[NS];
+    // exact conversion (rounding ModDown): overflow counts u = floor(sum_i y_i / p_i)
+    const bool exact = tab.rinv != nullptr;
+    double v0 = 0.0, v1 = 0.0;
 #pragma unroll
     for (int i = 0; i < NS; i++) {
         const double q = mq[tab.src_mod[i]].x;
@@ -667,14 +670,27 @@ __global__ void __launch_bounds__(256)
         const double a = tab.pre ? tab.pre[i] : 0.0;  // added before the product: x + a < 2q
         y0[i] = red1(mm_lazy(u2d(v.x) + a, h.x, h.y, q), q);
         y1[i] = red1(mm_lazy(u2d(v.y) + a, h.x, h.y, q), q);
+        if (exact) {
+            const double r = tab.rinv[i];
+            v0 = __dadd_rn(v0, __dmul_rn(y0[i], r));
+            v1 = __dadd_rn(v1, __dmul_rn(y1[i], r));
+        }
     }
+    const double u0 = floor(v0), u1 = floor(v1);  // 0 unless exact
     for (int j = j0; j < j1; j++) {
         const double2 Q = mq[tab.tgt_mod[j]];
         const double tq = Q.x, two_t = 2.0 * tq;
-        const double b = tab.post ? tab.post[j] : 0.0;
+        double b0 = tab.post ? tab.post[j] : 0.0, b1 = b0;
+        if (exact) {
+            // subtract u P: b + [u P]_t in [0, 2t), reduced once
+            const double2 pm = tab.pmod[j];
+            b0 = red1(b0 + red1(mm_lazy(u0, pm.x, pm.y, tq), tq), tq);
+            b1 = red1(b1 + red1(mm_lazy(u1, pm.x, pm.y, tq), tq), tq);
+        }
         double a0, a1;
         if (tq * (2 * NS) < C52) {
-            a0 = a1 = -b;  // in (-tq, 0]: the sum stays in (-tq, 2 NS tq), which red_any takes
+            a0 = -b0;  // in (-tq, 0]: the sum stays in (-tq, 2 NS tq), which red_any takes
+            a1 = -b1;
 #pragma unroll
             for (int i = 0; i < NS; i++) {
                 const double2 h = hmod[i * tab.nt + j];
@@ -693,8 +709,8 @@ __global__ void __launch_bounds__(256)
                 a1 += mm_lazy(y1[i], h.x, h.y, tq);
                 a1 = a1 >= two_t ? a1 - two_t : a1;
             }
-            a0 = pos1(red1(a0, tq) - b, tq);
-            a1 = pos1(red1(a1, tq) - b, tq);
+            a0 = pos1(red1(a0, tq) - b0, tq);
+            a1 = pos1(red1(a1, tq) - b1, tq);
         }
         *(ulonglong2 *)(ob + (size_t)tab.tgt_slot[j] * n + c) = make_ulonglong2(d2u(a0), d2u(a1));
     }

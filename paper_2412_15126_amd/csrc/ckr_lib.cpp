@@ -74,8 +74,42 @@ class Pool {
         for (auto &b : owned) cache_[b.second].push_back(b.first);
     }
 
+    // While branches of one circuit run on several streams (fork()..join()),
+    // a freed block goes to a free list of the stream that freed it and is
+    // reused only by later allocations on that same stream (stream order
+    // makes that safe); blocks freed before the fork serve every stream.  At
+    // the join, whose wait orders every branch before later work on the
+    // joining stream, the lists return to the common cache.  `cur` names the
+    // stream work is being issued on.
+    void fork(const void *const *cur) {
+        std::lock_guard<std::recursive_mutex> g(pmu_);
+        if (forked_++ == 0) cur_ = cur;
+    }
+    void join() {
+        std::lock_guard<std::recursive_mutex> g(pmu_);
+        if (--forked_ > 0) return;
+        cur_ = nullptr;
+        for (auto &st : sfree_)
+            for (auto &kv : st.second)
+                for (void *p : kv.second) release_locked(p, kv.first);
+        sfree_.clear();
+    }
+
     void *get(size_t bytes) {
         std::lock_guard<std::recursive_mutex> g(pmu_);
+        if (forked_) {
+            auto st = sfree_.find(*cur_);
+            if (st != sfree_.end()) {
+                auto it = st->second.find(round(bytes));
+                if (it != st->second.end() && !it->second.empty()) {
+                    void *p = it->second.back();
+                    it->second.pop_back();
+                    in_use += round(bytes);
+                    high = std::max(high, in_use);
+                    return p;
+                }
+            }
+        }
         bytes = round(bytes);
         if (capturing_) {
             auto cf = cap_free_.find(bytes);
@@ -126,8 +160,11 @@ class Pool {
         std::lock_guard<std::recursive_mutex> g(pmu_);
         bytes = round(bytes);
         in_use -= bytes;
-        if (capturing_ && cap_set_.count(p)) cap_free_[bytes].push_back(p);
-        else cache_[bytes].push_back(p);
+        if (forked_) {
+            sfree_[*cur_][bytes].push_back(p);
+            return;
+        }
+        release_locked(p, bytes);
     }
     // return cached blocks to the allocator (stream-ordered frees are safe
     // because the caller synchronises first)
@@ -145,7 +182,14 @@ class Pool {
     ~Pool() { trim(); }
 
   private:
+    void release_locked(void *p, size_t bytes) {
+        if (capturing_ && cap_set_.count(p)) cap_free_[bytes].push_back(p);
+        else cache_[bytes].push_back(p);
+    }
     std::recursive_mutex pmu_;
+    int forked_ = 0;
+    const void *const *cur_ = nullptr;
+    std::map<const void *, std::unordered_map<size_t, std::vector<void *>>> sfree_;
     std::unordered_map<size_t, std::vector<void *>> cache_;
     bool capturing_ = false;
     std::unordered_set<void *> cap_set_;
@@ -221,6 +265,9 @@ struct Ctx {
     bool graphs = true;           // capture batched circuits into hipGraphs
     int ntt_chunk = 0;            // limbs per two-pass chunk (0: whole dispatch), keeps pass-1 output in cache
     hipStream_t own_stream = nullptr;
+    static constexpr int kSide = 4;
+    hipStream_t side[kSide] = {};  // streams of concurrent circuit branches (default priority)
+    int forks = 0;                 // open Branches (at most one: they do not nest)
     Params P;
     DevTables T{};
     hipStream_t stream = nullptr;
@@ -252,6 +299,8 @@ struct Ctx {
         pool.trim();
         for (void *p : table_mem) (void)hipFree(p);
         if (own_stream) (void)hipStreamDestroy(own_stream);
+        for (hipStream_t st : side)
+            if (st) (void)hipStreamDestroy(st);
     }
 };
 
@@ -320,6 +369,84 @@ static DCt ct_new(Ctx &C, int level, int B) {
     c.buf = Buf(&C, (size_t)B * 2 * (level + 1) * C.n());
     return c;
 }
+
+// Concurrent branches of one circuit.  Each run() issues its work on one of
+// the context's side streams, ordered after everything issued on the current
+// stream before the Branches object was made; join() orders everything issued
+// afterwards on the current stream after every branch.  Under graph capture
+// the branches become parallel paths of the graph, forked from and joined back
+// to the capturing stream.  Branches never nest: inside an open fork, run()
+// issues its work inline on the current stream.  Blocks freed inside a branch
+// are reused only within that branch until the join (Pool::fork).
+class Branches {
+  public:
+    explicit Branches(Ctx &C) : C_(C), main_(C.stream), nested_(C.forks > 0) {
+        if (nested_) return;
+        C_.forks++;
+        HIPCHK(hipEventCreateWithFlags(&fork_, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(fork_, main_));
+        C_.pool.fork((const void *const *)&C_.stream);
+    }
+    Branches(const Branches &) = delete;
+    Branches &operator=(const Branches &) = delete;
+    template <class F>
+    void run(F &&f) {
+        if (nested_) {
+            f();
+            return;
+        }
+        hipStream_t st = C_.side[next_++ % Ctx::kSide];
+        HIPCHK(hipStreamWaitEvent(st, fork_, 0));
+        C_.stream = st;
+        struct Back {
+            Ctx &C;
+            hipStream_t m;
+            ~Back() { C.stream = m; }
+        } back{C_, main_};
+        f();
+        hipEvent_t e = nullptr;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ends_.push_back(e);
+        HIPCHK(hipEventRecord(e, st));
+    }
+    void join() {
+        if (joined_ || nested_) return;
+        joined_ = true;
+        hipError_t err = hipSuccess;
+        for (hipEvent_t e : ends_) {
+            const hipError_t r = hipStreamWaitEvent(main_, e, 0);
+            if (err == hipSuccess) err = r;
+        }
+        C_.pool.join();
+        C_.forks--;
+        release();
+        if (err != hipSuccess) throw Error{CKR_E_DEVICE, std::string("branch join: ") + hipGetErrorString(err)};
+    }
+    ~Branches() {
+        if (!joined_ && !nested_) {
+            joined_ = true;
+            for (hipEvent_t e : ends_) (void)hipStreamWaitEvent(main_, e, 0);
+            C_.pool.join();
+            C_.forks--;
+            release();
+        }
+    }
+
+  private:
+    void release() {
+        for (hipEvent_t e : ends_) (void)hipEventDestroy(e);
+        ends_.clear();
+        if (fork_) (void)hipEventDestroy(fork_);
+        fork_ = nullptr;
+    }
+    Ctx &C_;
+    hipStream_t main_;
+    hipEvent_t fork_ = nullptr;
+    std::vector<hipEvent_t> ends_;
+    bool nested_;
+    int next_ = 0;
+    bool joined_ = false;
+};
 
 static hipEvent_t prof_event(Ctx &C) {
     if (!C.prof.spare.empty()) {
@@ -527,7 +654,8 @@ static BConvTab make_bconv(Ctx &C, const std::vector<int> &src, const std::vecto
     tab.hmod = (double2 *)C.table_alloc(hm.size() * sizeof(double2));
     HIPCHK(hipMemcpy(tab.hinv, hi.data(), hi.size() * sizeof(double2), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(tab.hmod, hm.data(), hm.size() * sizeof(double2), hipMemcpyHostToDevice));
-    tab.pre = tab.post = nullptr;
+    tab.pre = tab.post = tab.rinv = nullptr;
+    tab.pmod = nullptr;
     if (round) {
         // h = (D - 1)/2 for the (odd) source product D: h mod m = (D mod m - 1) / 2 mod m
         auto half_mod = [&](u64 m) {
@@ -542,6 +670,20 @@ static BConvTab make_bconv(Ctx &C, const std::vector<int> &src, const std::vecto
         tab.post = (double *)C.table_alloc(post.size() * sizeof(double));
         HIPCHK(hipMemcpy(tab.pre, pre.data(), pre.size() * sizeof(double), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(tab.post, post.data(), post.size() * sizeof(double), hipMemcpyHostToDevice));
+        // exact conversion: 1/p_i for the overflow count, P mod t_j for its removal
+        std::vector<double> rinv(tab.ns);
+        std::vector<double2> pm(tab.nt);
+        for (int i = 0; i < tab.ns; i++) rinv[i] = 1.0 / (double)C.P.mod[src[i]];
+        for (int j = 0; j < tab.nt; j++) {
+            const u64 t = C.P.mod[tgt[j]];
+            u64 d = 1 % t;
+            for (int k = 0; k < tab.ns; k++) d = hmul(d, C.P.mod[src[k]] % t, t);
+            pm[j] = make_double2((double)d, (double)d / (double)t);
+        }
+        tab.rinv = (double *)C.table_alloc(rinv.size() * sizeof(double));
+        tab.pmod = (double2 *)C.table_alloc(pm.size() * sizeof(double2));
+        HIPCHK(hipMemcpy(tab.rinv, rinv.data(), rinv.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(tab.pmod, pm.data(), pm.size() * sizeof(double2), hipMemcpyHostToDevice));
     }
     return tab;
 }
@@ -762,8 +904,8 @@ static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_
     ia.gal = gal;
     // per target limb: beta inputs and 2 outputs per batch entry, 2*beta key limbs once
     timed(C, kNttRowIP, 8.0 * n * E * ((beta + 2.0) * B + 2.0 * beta), [&] { k_ntt_row_ip(C.T, ia, C.stream); });
-    // ModDown, rounding: (x_Q + h - BConv_{P->Q}(x_P + h)) * P^{-1}, h = (P - 1)/2 (both h's
-    // folded into the base conversion), the combine fused into the last NTT pass
+    // ModDown, rounding: (x_Q + h - [(X + h) mod P]_Q) * P^{-1} = round(X / P), h = (P - 1)/2
+    // (both h's folded into the exact base conversion), the combine fused into the last NTT pass
     ntt(C, acc.get() + (size_t)(l + 1) * n, P.K, 2 * B, (size_t)E * n, plain_map(P.nq), true);
     Buf conv(&C, (size_t)2 * B * (l + 1) * n);
     const BConvTab &mdt = moddown_tab(C, l);
@@ -1304,9 +1446,17 @@ uint32_t sort_depth(ckr_sign c, ckr_sign i) { return rank_depth(c, 0) + 5 + cmp_
 // C = Cmp(V_R, V_C): C[i][j] = Cmp(v_j, v_i)
 static DCt cmp_matrix(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, DCt *VR_out = nullptr,
                       double a = 1.0) {
-    DCt VR = repl_r(C, K, V, N);
-    DCt T = trans_r(C, K, V, N);
-    DCt VC = repl_c(C, K, T, N);
+    // ReplR runs concurrently with TransR -> ReplC (section 3.1's cost
+    // paragraph: the replications run in parallel, so the critical path
+    // holds 3 log N rotations instead of 4 log N); the bits are unchanged
+    DCt VR, VC;
+    {
+        Branches br(C);
+        br.run([&] { VR = repl_r(C, K, V, N); });
+        DCt T = trans_r(C, K, V, N);
+        VC = repl_c(C, K, T, N);
+        br.join();
+    }
     DCt VRa = ev_cmul_to(C, VR, 1.0, VC.level);
     DCt D = ev_add(C, VRa, VC, true);
     if (VR_out) *VR_out = std::move(VR);
@@ -1858,6 +2008,17 @@ class Server {
         }
         for (auto &t : workers_) t.join();
         workers_.clear();
+        // requests that never ran complete with an error, so no wait blocks forever
+        std::lock_guard<std::mutex> g(mu_);
+        for (u64 t : pending_) {
+            Request *r = reqs_[t].get();
+            r->status = CKR_E_INVALID;
+            r->err = "server stopped before the request ran";
+            r->t_done = now_ms();
+            r->done = true;
+        }
+        pending_.clear();
+        cv_.notify_all();
     }
 
   private:
@@ -2065,6 +2226,7 @@ ckr_status ckr_context_create(const ckr_params *p, int dev, size_t budget, ckr_c
         // a stream of the context's own (default priority): graph capture needs a non-null stream
         HIPCHK(hipStreamCreate(&C.own_stream));
         C.stream = C.own_stream;
+        for (hipStream_t &st : C.side) HIPCHK(hipStreamCreate(&st));
         *out = ctx.release();
     });
 }

@@ -135,12 +135,18 @@ struct BConvTab {
     double2 *hmod;  // [ns][nt]
     // rounding ModDown (null otherwise): pre[i] = h mod p_i is added to source
     // i's residue and post[j] = h mod t_j subtracted from target j,
-    // h = (P - 1)/2: the conversion of X + h, minus h
+    // h = (P - 1)/2: the conversion of X + h, minus h.  The conversion is
+    // then exact: its overflow u = floor(sum_i y_i * rinv[i]) (IEEE double,
+    // in source order, no fused operations) times pmod[j] = P mod t_j is
+    // subtracted as well, so target j receives [(X + h) mod P - h]_{t_j}.
     double *pre;    // [ns]
     double *post;   // [nt]
+    double *rinv;   // [ns] 1/p_i
+    double2 *pmod;  // [nt] {P mod t_j, (P mod t_j) / t_j}
 };
 void k_bconv(const DevTables &T, u64 *out, const u64 *src, const BConvTab &tab, int batch, size_t stride_o,
              size_t stride_i, hipStream_t s);
+
 
 // key-switch inner product over E limbs (eval domain):
 //   accb[t] = sum_j X_j[t] * kb_j[t], acca[t] = sum_j X_j[t] * ka_j[t]

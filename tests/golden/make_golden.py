@@ -31,20 +31,21 @@ def rank128_p16():
             "exact": [int(x) for x in np.argsort(np.argsort(v)) + 1]}
 
 
-def argmin128_p17():
+def argmin128_p17o():
     N = 128
     cmp, ind = W.ARGMIN_CMP[N]
     O.set_threads(min(16, os.cpu_count() or 1))
-    P = O.Params(**W.PSETS["P17"])
-    level = P.L
+    P = O.Params(**W.PSETS["P17O"])
+    level = O.argmin_depth(cmp, ind)
     v, kseed, eseed = W.tied_workload(N, 0)
     K = O.Keys(P, kseed, level, P.circuit_galois(N, 2))
     ct = O.encrypt(K, v, level, eseed)
     oh, val = O.argmin(K, ct, N, cmp, ind)
     a, b = oh.export(), val.export()
-    return {"_what": "oracle tie-corrected argmin of N=128 at n=2^17 (P17), tied workload seed 0 (96 distinct values "
-                     "+ 32 duplicates), encryption level 40, comparator g^4 f^2, indicator g^3 f^2: sha256 of the "
-                     "exported one-hot and value ciphertexts and their decoded slots",
+    return {"_what": "oracle tie-corrected argmin of N=128 at n=2^17 (P17O), tied workload seed 0 (96 distinct "
+                     "values + 32 duplicates), encryption level 43 (the circuit's depth), comparator g^4 f^2, "
+                     "indicator g^4 f^2: sha256 of the exported one-hot and value ciphertexts and their decoded slots",
+            "level": level,
             "sha256_onehot": hashlib.sha256(a.tobytes()).hexdigest(),
             "sha256_value": hashlib.sha256(b.tobytes()).hexdigest(),
             "onehot": [float(x) for x in O.decrypt(K, oh, N)],
@@ -290,7 +291,7 @@ def median101_p17s():
 
 
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["rank128_p16", "argmin128_p17", "sort128_p17", "mixed_p16d", "argmax128_p17o",
+    which = sys.argv[1:] or ["rank128_p16", "argmin128_p17o", "sort128_p17", "mixed_p16d", "argmax128_p17o",
                              "rank512_p16_multi", "sort512_p17s_multi", "rank128_p16_cheb",
                              "argmin128_p17_cheb", "sort128_p17_col", "kth64_p17s_div", "median128_p17o",
                              "median101_p17s"]

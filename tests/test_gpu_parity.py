@@ -183,6 +183,27 @@ def test_rank8_batch_equals_single(p12):
         assert np.array_equal(s, b.export())
 
 
+def test_rank8_hundred_seeds_batched_bit_exact(ora, p12):
+    """Configuration 1 over its seeds 0..99: one batch of 100 rank-8 queries
+    (one graph-captured circuit after the eager first call) against the
+    oracle's rank of each query alone, bit for bit, and exact ranks."""
+    N, cmp = 8, W.RANK_CMP[8]
+    vals, gcts, want = [], [], []
+    for seed in range(100):
+        v, _, eseed = W.rank_workload(N, 0.01, seed)
+        vals.append(v)
+        o, g = p12.enc(v, p12.P.L, eseed)
+        gcts.append(g)
+        want.append(ora.rank(p12.okeys, o, N, *cmp).export())
+    say("[gpu] rank-8 batch of 100 (eager, captured)")
+    for rep in range(2):
+        outs = p12.ctx.rank_batch(p12.gkeys, gcts, N, cmp)
+        for i, (o, w) in enumerate(zip(outs, want)):
+            assert np.array_equal(o.export(), w), (rep, i)
+    for o, v in zip(outs, vals):
+        assert np.array_equal(np.round(p12.ctx.decrypt(p12.gkeys, o, N)), np.argsort(np.argsort(v)) + 1)
+
+
 def test_rank8_graph_replays_equal_eager(p12):
     """Batched rank through hipGraph capture: call 1 runs eagerly, call 2 captures
     and replays, calls 3-4 replay; eager single calls run in between.  Every

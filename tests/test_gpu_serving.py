@@ -100,3 +100,67 @@ def test_budget_rejects_oversized_request(rings):
         srv.wait(srv.submit("rank", 8, ct), 60000)
     assert e.value.status == -4
     srv.close()
+
+
+def test_served_mix_full_size_matches_oracle_digests():
+    """The served configuration at full size: rank-128 at n = 2^16 and sort /
+    argmin at n = 2^17 arriving interleaved (Poisson gaps) through the server,
+    batched as they come.  The rank-128 and sort-128 queries of the stored
+    oracle digests (tests/golden/rank128_p16.json, sort128_p17.json: workload
+    seed 0, the same key seed) must reproduce those digests in the mix; every
+    other request must equal the same query run alone, bit for bit."""
+    import hashlib
+    import json
+    import os
+    import paper_2412_15126_amd as ckr
+    gold_dir = os.path.join(os.path.dirname(__file__), "golden")
+    g_rank = json.load(open(os.path.join(gold_dir, "rank128_p16.json")))
+    g_sort = json.load(open(os.path.join(gold_dir, "sort128_p17.json")))
+    p16, p17 = W.PSETS["P16"], W.PSETS["P17"]
+    v0, kseed, e0 = W.rank_workload(128, 2.0 ** -10, 0)
+    say("[gpu] served full size: keys")
+    a = ckr.Context(p16)
+    ka = a.keygen(kseed, 17, [128])
+    b = ckr.Context(p17)
+    kb = b.keygen(kseed, p17["L"], [64, 128], what=6)
+    jobs = [("rank", 128, a, ka, a.encrypt(ka, v0, 17, e0), "gold"),
+            ("sort", 128, b, kb, b.encrypt(kb, v0, p17["L"], e0), "gold")]
+    for s in range(4):
+        v, _, e = W.rank_workload(128, 2.0 ** -10, 700 + s)
+        jobs.append(("rank", 128, a, ka, a.encrypt(ka, v, 17, e), None))
+    for s in range(2):
+        v, _, e = W.tied_workload(64, 710 + s)
+        jobs.append(("argmin", 64, b, kb, b.encrypt(kb, v, p17["L"], e), None))
+        v, _, e = W.rank_workload(64, 2.0 ** -10, 720 + s)
+        jobs.append(("sort", 64, b, kb, b.encrypt(kb, v, p17["L"], e), None))
+    order = np.random.default_rng(5).permutation(len(jobs))
+    jobs = [jobs[i] for i in order]
+    srv = ckr.Server(hbm_budget=64 << 30, max_batch=4)
+    srv.add_route("rank", 128, a, ka, W.RANK_CMP[128])
+    srv.add_route("argmin", 64, b, kb, *W.ARGMIN_CMP[64])
+    srv.add_route("sort", 64, b, kb, *W.SORT_CMP[64])
+    srv.add_route("sort", 128, b, kb, *W.SORT_CMP[128])
+    rng = np.random.default_rng(9)
+    say("[gpu] served full size: submitting")
+    tickets = []
+    for j in jobs:
+        tickets.append(srv.submit(j[0], j[1], j[4]))
+        time.sleep(float(rng.exponential(0.05)))
+    outs = []
+    for t in tickets:
+        o, _ = srv.wait(t, 300000)
+        outs.append(o)
+    say(f"[gpu] served full size: {srv.stats()}")
+    srv.close()
+    for (kind, N, ctx, keys, ct, tag), o in zip(jobs, outs):
+        if tag == "gold":
+            want = g_rank["sha256"] if kind == "rank" else g_sort["sha256"]
+            assert hashlib.sha256(o[0].export().tobytes()).hexdigest() == want, kind
+            continue
+        if kind == "rank":
+            alone = [ctx.rank(keys, ct, N, W.RANK_CMP[N])]
+        elif kind == "argmin":
+            alone = list(ctx.argmin(keys, ct, N, *W.ARGMIN_CMP[N]))
+        else:
+            alone = [ctx.sort(keys, ct, N, *W.SORT_CMP[N])]
+        assert all(np.array_equal(x.export(), y.export()) for x, y in zip(alone, o)), kind
