@@ -344,6 +344,25 @@ void ckr_ct_free(ckr_ct *ct);
 /* Homomorphic operations on single ciphertexts (the building blocks the
  * circuits use; exposed for testing and custom circuits). */
 ckr_status ckr_op_rotate(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, int64_t k, ckr_ct **out);
+/* Allocation-free rotation, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Computes ckr_op_rotate(a, k) bit for bit into `out`, an existing
+ * single ciphertext at a's level (caller-owned, e.g. from ckr_ct_import or a
+ * previous call; it must not be a).  The key switch's temporaries live in a
+ * file-scope device array of 128 MiB that every GPU the library runs on holds
+ * until the process ends; no device memory is allocated or freed and nothing
+ * is drawn from the context pool (ckr_context_memory does not move).  The
+ * base-conversion tables of every level up to the keys' max_level are made by
+ * ckr_keygen.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (other threads, other contexts or streams of the same
+ * device) race; calls on one context are serialised by its lock and its
+ * stream.  Errors: CKR_E_NOMEM when one key switch at a's ring and level
+ * needs more than 128 MiB ((l+1) + beta E + 2E + 2(l+1) limbs of 8n bytes,
+ * E = l + 1 + n_p; e.g. n = 2^16 up to level 21 with 7 special primes and
+ * dnum = 3), CKR_E_INVALID (out not at a's level, out == a, handles of
+ * another context, missing rotation key), CKR_E_DEPTH (a above the keys'
+ * level). */
+ckr_status ckr_op_rotate_into(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, int64_t k, ckr_ct *out);
 ckr_status ckr_op_mul(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, const ckr_ct *b, ckr_ct **out);
 /* sum_{i < deg1} coeffs[i] T_i(a) for a Chebyshev series of deg1 = 2^B terms
  * (1 <= B <= 15), the evaluation behind the Chebyshev comparator (section

@@ -92,6 +92,7 @@ _SIGS = {
     "ckr_ct_import": (C.c_int, [vp, u64p, C.c_size_t, C.c_uint32, C.POINTER(vp)]),
     "ckr_ct_free": (None, [vp]),
     "ckr_op_rotate": (C.c_int, [vp, vp, vp, C.c_int64, C.POINTER(vp)]),
+    "ckr_op_rotate_into": (C.c_int, [vp, vp, vp, C.c_int64, vp]),
     "ckr_op_mul": (C.c_int, [vp, vp, vp, vp, C.POINTER(vp)]),
     "ckr_op_cheb_eval": (C.c_int, [vp, vp, vp, dblp, C.c_uint32, C.POINTER(vp)]),
     "ckr_op_add": (C.c_int, [vp, vp, vp, C.POINTER(vp)]),
@@ -411,6 +412,12 @@ class Context:
 
     def rotate(self, keys, a, k):
         return self._unary(lib().ckr_op_rotate, keys.h, a.h, int(k))
+
+    def rotate_into(self, keys, a, k, out):
+        """the rotation of ckr_op_rotate written into the existing ciphertext
+        `out` (a's level), allocating no device memory"""
+        _ok(lib().ckr_op_rotate_into(self.h, keys.h, a.h, int(k), out.h))
+        return out
 
     def mul(self, keys, a, b):
         return self._unary(lib().ckr_op_mul, keys.h, a.h, b.h)

@@ -4,7 +4,7 @@
 // Every homomorphic step runs in the HIP kernels of ckr_kernels.hip on the
 // context stream; the host only derives parameters, samples randomness,
 // encodes plaintexts and sequences launches.
-#include <hip/hip_runtime_api.h>
+#include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
@@ -52,6 +52,22 @@ class Pool {
 
     static size_t round(size_t b) { return (b + 65535) & ~size_t(65535); }
 
+    // While an arena is set (the allocation-free entry point), every block
+    // comes from it by bumping an offset: nothing is taken from the cache or
+    // the allocator, nothing is returned to them, and the byte counts do not
+    // move.  Blocks are released all at once by clear_arena().
+    void set_arena(void *base, size_t bytes) {
+        std::lock_guard<std::recursive_mutex> g(pmu_);
+        arena_ = (char *)base;
+        arena_size_ = bytes;
+        arena_off_ = 0;
+    }
+    void clear_arena() {
+        std::lock_guard<std::recursive_mutex> g(pmu_);
+        arena_ = nullptr;
+        arena_size_ = arena_off_ = 0;
+    }
+
     // While a graph is being captured, every block the capture obtains is
     // tracked; blocks freed during the capture are reused only by the capture
     // and then handed to the graph (its replays write them).
@@ -97,7 +113,7 @@ class Pool {
 
     void *get(size_t bytes) {
         std::lock_guard<std::recursive_mutex> g(pmu_);
-        if (forked_) {
+        if (forked_ && !arena_) {
             auto st = sfree_.find(*cur_);
             if (st != sfree_.end()) {
                 auto it = st->second.find(round(bytes));
@@ -109,6 +125,12 @@ class Pool {
                     return p;
                 }
             }
+        }
+        if (arena_) {
+            const size_t off = (arena_off_ + 255) & ~size_t(255);
+            if (off + bytes > arena_size_) throw Error{CKR_E_NOMEM, "scratch exhausted"};
+            arena_off_ = off + bytes;
+            return arena_ + off;
         }
         bytes = round(bytes);
         if (capturing_) {
@@ -158,6 +180,7 @@ class Pool {
     void put(void *p, size_t bytes) {
         if (!p) return;
         std::lock_guard<std::recursive_mutex> g(pmu_);
+        if (arena_ && (char *)p >= arena_ && (char *)p < arena_ + arena_size_) return;
         bytes = round(bytes);
         in_use -= bytes;
         if (forked_) {
@@ -194,6 +217,8 @@ class Pool {
     bool capturing_ = false;
     std::unordered_set<void *> cap_set_;
     std::unordered_map<size_t, std::vector<void *>> cap_free_;
+    char *arena_ = nullptr;
+    size_t arena_size_ = 0, arena_off_ = 0;
 };
 
 struct Ctx;
@@ -272,6 +297,7 @@ struct Ctx {
     DevTables T{};
     hipStream_t stream = nullptr;
     int device = 0;
+    u64 *scratch = nullptr;  // this device's copy of the allocation-free entry point's scratch array
     Pool pool;
     std::vector<void *> table_mem;  // owned by the context (tables)
     std::map<std::pair<int, int>, BConvTab> modup;  // (level, digit)
@@ -2175,6 +2201,38 @@ struct ckr_ct {
     DCt ct;
 };
 
+// ------------------------------------------------------------------------
+// scratch memory of the allocation-free rotation (ckr_op_rotate_into)
+// ------------------------------------------------------------------------
+// A file-scope device array: every GPU the library runs on holds its own copy
+// at its own address until the process ends.  In host code `scratch` names a
+// host-side stand-in, so its device address is looked up once per device
+// (with that device current) and only that address is ever handed to kernels.
+constexpr size_t kScratchWords = size_t(16) << 20;  // 128 MiB
+static __device__ __align__(256) u64 scratch[kScratchWords];
+static std::mutex g_scratch_mu;
+static std::map<int, u64 *> g_scratch_dev;
+
+static u64 *scratch_ptr(int dev) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_dev.find(dev);
+    if (it != g_scratch_dev.end()) return it->second;
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Error{CKR_E_DEVICE, "no device address for the scratch array"};
+    g_scratch_dev[dev] = (u64 *)p;
+    return (u64 *)p;
+}
+
+// words of scratch one key switch of a single ciphertext at level l takes:
+// the coefficient-domain input, the extended digits, the two accumulators
+// and the ModDown conversion (each block 256-byte aligned)
+static size_t keyswitch_scratch_words(const Ctx &C, int l) {
+    const size_t n = C.n(), E = (size_t)(l + 1 + C.P.K), beta = (size_t)C.P.beta(l);
+    auto al = [](size_t w) { return (w + 31) & ~size_t(31); };
+    return al((size_t)(l + 1) * n) + al(beta * E * n) + al(2 * E * n) + al((size_t)2 * (l + 1) * n);
+}
+
 template <class F>
 static ckr_status guard(F &&f) {
     try {
@@ -2223,6 +2281,7 @@ ckr_status ckr_context_create(const ckr_params *p, int dev, size_t budget, ckr_c
         if (C.P.nmod() > kMaxLimbArgs) throw Error{CKR_E_INVALID, "too many primes"};
         C.pool.budget = budget;
         setup_tables(C);
+        C.scratch = scratch_ptr(dev);
         // a stream of the context's own (default priority): graph capture needs a non-null stream
         HIPCHK(hipStreamCreate(&C.own_stream));
         C.stream = C.own_stream;
@@ -2476,6 +2535,12 @@ ckr_status ckr_keygen(ckr_context *ctx, const uint8_t seed[32], uint32_t max_lev
         add_rotation_keys(C, *K, shifts, seed);
         // conjugation: the real part of a Chebyshev indicator's argument
         if (nN && (what & 6)) add_galois_keys(C, *K, {(u32)(2 * C.n() - 1)}, seed);
+        // base-conversion tables of every level the keys serve, so that no key
+        // switch (the allocation-free rotation in particular) allocates them later
+        for (int l = 0; l <= K->lmax; l++) {
+            for (int j = 0; j < P.beta(l); j++) (void)modup_tab(C, l, j);
+            (void)moddown_tab(C, l);
+        }
         {
             std::lock_guard<std::mutex> g(g_key_seed_mu);
             g_key_seed[K.get()] = std::vector<uint8_t>(seed, seed + 32);
@@ -2970,6 +3035,47 @@ ckr_status ckr_op_rotate(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a
         NEED(ctx && keys && a && out);
         std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         *out = wrap(*ctx->C, ev_rotate(*ctx->C, *keys->K, a->ct, k));
+    });
+}
+ckr_status ckr_op_rotate_into(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, int64_t k, ckr_ct *out) {
+    return guard([&] {
+        NEED(ctx && keys && a && out);
+        Ctx &C = *ctx->C;
+        std::lock_guard<std::recursive_mutex> lk_(C.mu_run);
+        const DCt &x = a->ct;
+        const DCt &y = out->ct;
+        if (a->C != &C || out->C != &C || keys->K->C != &C) throw Error{CKR_E_INVALID, "handles of another context"};
+        if (x.B != 1 || y.B != 1 || x.level != y.level)
+            throw Error{CKR_E_INVALID, "out must be a single ciphertext at the input's level"};
+        if (x.d() == y.d()) throw Error{CKR_E_INVALID, "out must not be the input"};
+        const int l = x.level;
+        if (l > keys->K->lmax) throw Error{CKR_E_DEPTH, "ciphertext above key level"};
+        const size_t n = C.n(), L = (size_t)(l + 1) * n;
+        const u32 g = galois_left(C, k);
+        if (g == 1) {  // a rotation by a multiple of n/2 slots: the identity
+            HIPCHK(hipMemcpyAsync(y.d(), x.d(), 2 * L * 8, hipMemcpyDeviceToDevice, C.stream));
+            return;
+        }
+        const size_t need = keyswitch_scratch_words(C, l);
+        if (need > kScratchWords)
+            throw Error{CKR_E_NOMEM, "the allocation-free rotation needs " + std::to_string(need * 8 >> 20) +
+                                         " MiB of scratch at this ring and level; it has " +
+                                         std::to_string(kScratchWords * 8 >> 20) + " MiB"};
+        const Buf &key = find_key(*keys->K, g);
+        {
+            std::lock_guard<std::mutex> tg(C.mu);
+            bool have = C.moddown.count(l) != 0;
+            for (int j = 0; j < C.P.beta(l); j++) have = have && C.modup.count(std::make_pair(l, j));
+            if (!have) throw Error{CKR_E_INVALID, "base-conversion tables of this level are missing"};
+        }
+        if (!C.scratch) throw Error{CKR_E_DEVICE, "scratch array unavailable"};
+        struct Arena {
+            Pool &p;
+            ~Arena() { p.clear_arena(); }
+        } arena{C.pool};
+        C.pool.set_arena(C.scratch, kScratchWords * 8);
+        keyswitch(C, *keys->K, key, x.d() + L, 2 * L, l, 1, y.d(), 2 * L, L, x.d(), 2 * L, L, 1, nullptr, 0, 0, 0,
+                  g);
     });
 }
 ckr_status ckr_op_mul(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, const ckr_ct *b, ckr_ct **out) {
