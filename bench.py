@@ -114,7 +114,8 @@ def serve(args, quiet=False):
     p16, p17 = W.PSETS["P16"], W.PSETS["P17"]
     t = time.time()
     a = ckr.Context(p16)
-    ka = a.keygen(bytes(range(32)), 17, [128])
+    lr = ckr.rank_depth(W.RANK128_MM)
+    ka = a.keygen(bytes(range(32)), lr, [128])
     b = ckr.Context(p17)
     kb = b.keygen(bytes(range(3, 35)), p17["L"], [32, 64, 128], what=6)
     a.autotune(2 * 8 * 18, 2)
@@ -123,7 +124,7 @@ def serve(args, quiet=False):
     b.autotune_row_ip(4, 2)
     log(f"[serve] keys ready in {time.time() - t:.1f}s")
     srv = ckr.Server(hbm_budget=args.hbm_budget << 30, max_batch=args.max_batch)
-    srv.add_route("rank", 128, a, ka, W.RANK_CMP[128])
+    srv.add_route("rank", 128, a, ka, W.RANK128_MM)
     srv.add_route("argmin", 64, b, kb, *W.ARGMIN_CMP[64])
     for N in (32, 64, 128):
         srv.add_route("sort", N, b, kb, *W.SORT_CMP[N])
@@ -139,7 +140,7 @@ def serve(args, quiet=False):
     for i, ta in enumerate(arrivals):
         kind = ["rank", "argmin", "sort"][int(rng.integers(0, 3))]
         if kind == "rank":
-            N, ctx, keys, lvl = 128, a, ka, 17
+            N, ctx, keys, lvl = 128, a, ka, lr
             v, _, e = W.rank_workload(N, 2.0 ** -10, 5000 + i)
         elif kind == "argmin":
             N, ctx, keys, lvl = 64, b, kb, p17["L"]
@@ -151,7 +152,7 @@ def serve(args, quiet=False):
         jobs.append(dict(t=ta, kind=kind, N=N, ctx=ctx, keys=keys, ct=ctx.encrypt(keys, v, lvl, e), v=v))
     log(f"[serve] {len(jobs)} requests encrypted")
     # warm each route once (its first batch runs alone and measures its working set)
-    for kind, N, ctx, keys, lvl in [("rank", 128, a, ka, 17), ("argmin", 64, b, kb, p17["L"])] + \
+    for kind, N, ctx, keys, lvl in [("rank", 128, a, ka, lr), ("argmin", 64, b, kb, p17["L"])] + \
             [("sort", N, b, kb, p17["L"]) for N in (32, 64, 128)]:
         v, _, e = W.rank_workload(N, 2.0 ** -10, 99)
         srv.wait(srv.submit(kind, N, ctx.encrypt(keys, v, lvl, e)))
@@ -171,7 +172,7 @@ def serve(args, quiet=False):
     same = True
     for kind in ("rank", "argmin", "sort"):
         for j in [j for j in jobs if j["kind"] == kind][:2]:
-            cmp, ind = {"rank": (W.RANK_CMP[128], (0, 0)), "argmin": W.ARGMIN_CMP[64], "sort": W.SORT_CMP[j["N"]]}[kind]
+            cmp, ind = {"rank": (W.RANK128_MM, (0, 0)), "argmin": W.ARGMIN_CMP[64], "sort": W.SORT_CMP[j["N"]]}[kind]
             if kind == "rank":
                 alone = [j["ctx"].rank(j["keys"], j["ct"], j["N"], cmp)]
             elif kind == "argmin":
@@ -310,6 +311,10 @@ def circuit_bench(args):
                             desc="rank of N=128 (gap 2^-10) at n=2^16 (24 + 7 primes, dnum=3) with the Chebyshev "
                                  "comparator of degree 2^11 - 1 (12 levels, the paper's setting for rank), encrypted "
                                  "at level 14"),
+        "rank128mm": dict(pset="P16", N=128, q=dict(kind="rank"), ci=((0, 0, 0, 4), None), what=1,
+                          level="depth", B=32,
+                          desc="rank of N=128 (gap 2^-10) at n=2^16 (24 + 7 primes, dnum=3) with four stages of the "
+                               "minimax composite comparator (12 levels), encrypted at level 14"),
         "argmin128cheb": dict(pset="P17", N=128, q=dict(kind="order", k=1, tie=True),
                               ci=(W.CHEB_CMP[128], W.CHEB_CMP[128]), what=2, level="depth", bound=0.05,
                               desc="tie-corrected argmin of N=128 (96 distinct values + 32 duplicates, gap 2^-10) "
@@ -565,13 +570,14 @@ def main():
     ap.add_argument("--mixed", action="store_true", help="64 mixed rank/argmin queries in one launch instead")
     ap.add_argument("--workload", default="rank128",
                     choices=["rank128", "argmin128", "argmax128", "sort128", "rank512", "sort512", "rank128cheb",
-                             "argmin128cheb", "sort128col", "kth64div", "median128"],
+                             "argmin128cheb", "sort128col", "kth64div", "median128", "rank128mm"],
                     help="circuit to time (rank128: the headline metric)")
     ap.add_argument("--cheb-sweep", action="store_true",
                     help="rank-128 runtime and error against the Chebyshev comparison depth 6..14")
     ap.add_argument("--rate", type=float, default=4.0)
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--no-serve", action="store_true", help="skip the served segment of the default run")
+    ap.add_argument("--no-fg", action="store_true", help="skip the g^4 f comparison of the default run")
     ap.add_argument("--max-batch", type=int, default=8)
     ap.add_argument("--hbm-budget", type=int, default=64, help="GiB of circuit working set in flight")
     args = ap.parse_args()
@@ -594,7 +600,8 @@ def main():
     from paper_2412_15126_amd import workloads as W
 
     pset = W.PSETS["P16"]
-    N, cmp, level = 128, W.RANK_CMP[128], 17
+    N, cmp = 128, W.RANK128_MM
+    level = ckr.rank_depth(cmp)
     B = max(1, args.batch)
     ctx = ckr.Context(pset)
     stream = hip.Stream()
@@ -725,8 +732,10 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "rank N=128 at n=2^16 (q0 50-bit + 23 rescale primes near 2^40, 7 special 50-bit "
-                               "primes, dnum=3, scale 2^40), encrypted at level 17, comparator g^4 then f",
+        "config": {"workload": f"rank N=128 at n=2^16 (q0 50-bit + 23 rescale primes near 2^40, 7 special 50-bit "
+                               f"primes, dnum=3, scale 2^40), encrypted at level {level} (the circuit's depth), "
+                               "comparator: the degree-7 polynomial composed 4 times (four stages of the minimax "
+                               "composite)",
                    "batch": B, "ranks_exact": bool(exact), "graphs": True,
                    "ntt_variants": {"fwd": chosen[0], "inv": chosen[1]}, "row_ip_variant": ip_var, "ntt_chunk_limbs": chunk},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
@@ -742,6 +751,21 @@ def main():
         "rank_error": {"max": round(float(max(errs)), 4), "queries_exact": int(sum(e < 0.5 for e in errs)),
                        "queries": len(vals)},
     }
+    # the same batch with the f/g comparator g^4 f (five compositions, level 17)
+    if not args.no_fg:
+        lfg = ckr.rank_depth(W.RANK_CMP[N])
+        kfg = ctx.keygen(kseed, lfg, [N])
+        cfg = [ctx.encrypt(kfg, v, lfg, W.rank_workload(N, 2.0 ** -10, 1000 + q)[2]) for q, v in enumerate(vals)]
+        for _ in range(2):
+            ofg = ctx.run_batch(kfg, "rank", cfg, N, W.RANK_CMP[N])
+        ctx.synchronize()
+        efg = max(np.max(np.abs(ctx.decrypt(kfg, o, N) - (np.argsort(np.argsort(v)) + 1))) for o, v in zip(ofg, vals))
+        wfg, _, tfg = timed_steps(lambda: ctx.run_batch(kfg, "rank", cfg, N, W.RANK_CMP[N]), max(3, args.steps // 2))
+        res["g4f"] = {"queries_per_s": round(B * max(3, args.steps // 2) / max(wfg, tfg * 1e-3), 3),
+                      "comparator": "g^4 then f (five compositions)", "level": lfg,
+                      "max_rank_error": round(float(efg), 4)}
+        log(f"[bench] same batch with g^4 f: {res['g4f']}")
+        del ofg, cfg, kfg
     tr = measured_traffic(dom) if B == 32 else None
     if tr:
         res["roofline"]["traffic"] = tr["read"] + tr["write"]

@@ -68,17 +68,25 @@ typedef struct {
 
 /* Comparator (section 2.2), one of:
  *  - the f/g composite: g applied d_g times, then f applied d_f times
- *    (cheb = 0, d_g + d_f >= 1); each application consumes 3 levels;
+ *    (cheb = minimax = 0, d_g + d_f >= 1); each application consumes 3 levels;
  *  - the Chebyshev interpolant of the comparison function of Eq. (1) on
  *    [-1, 1] at the 2^(cheb-1) Chebyshev nodes (degree 2^(cheb-1) - 1),
  *    evaluated by Paterson-Stockmeyer in the Chebyshev basis in cheb levels
- *    (d_g = d_f = 0, 2 <= cheb <= 16).  The paper's experiments use this
- *    form for rank and minimum at N <= 256, up to degree 2^11 (cheb = 12).
+ *    (d_g = d_f = minimax = 0, 2 <= cheb <= 16).  The paper's experiments use
+ *    this form for rank and minimum at N <= 256, up to degree 2^11 (cheb = 12);
+ *  - the first `minimax` stages (1..5) of the minimax composite that section
+ *    2.2 names as the alternative to f and g (d_g = d_f = cheb = 0): stage 0
+ *    is the odd degree-7 polynomial closest to sign(x) in the maximum norm on
+ *    [2^-8.5, 1], each later stage the one closest to 1 on the interval the
+ *    previous stage maps that onto; 3 levels per stage.  Four stages rank
+ *    N = 128 values at a 2^-10 gap exactly, where the four-fold f/g split
+ *    g^3 f does not.
  * Any other combination is rejected with CKR_E_INVALID. */
 typedef struct {
     uint8_t d_g;
     uint8_t d_f;
     uint8_t cheb;
+    uint8_t minimax;
 } ckr_sign;
 
 /* Create a context on HIP device `hip_device`.  hbm_budget bounds the bytes
@@ -374,6 +382,11 @@ ckr_status ckr_op_mul(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, c
  * length that is not a power of two is CKR_E_INVALID. */
 ckr_status ckr_op_cheb_eval(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, const double *coeffs,
                             uint32_t deg1, ckr_ct **out);
+/* Cmp(d) of section 2.2 on a ciphertext of differences d = x - y (slots in
+ * [-1, 1]): the comparator `cmp` alone, (p(d) + 1)/2 for the f/g or minimax
+ * composite p, or the Chebyshev interpolant.  Consumes the comparator's levels
+ * (CKR_E_DEPTH if a has fewer); CKR_E_INVALID for an invalid comparator. */
+ckr_status ckr_op_cmp_sign(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, ckr_sign cmp, ckr_ct **out);
 ckr_status ckr_op_add(ckr_context *ctx, const ckr_ct *a, const ckr_ct *b, ckr_ct **out);
 ckr_status ckr_op_sub(ckr_context *ctx, const ckr_ct *a, const ckr_ct *b, ckr_ct **out);
 ckr_status ckr_op_rescale(ckr_context *ctx, const ckr_ct *a, ckr_ct **out);

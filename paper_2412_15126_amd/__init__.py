@@ -32,7 +32,7 @@ class Params(C.Structure):
 
 
 class Sign(C.Structure):
-    _fields_ = [("d_g", C.c_uint8), ("d_f", C.c_uint8), ("cheb", C.c_uint8)]
+    _fields_ = [("d_g", C.c_uint8), ("d_f", C.c_uint8), ("cheb", C.c_uint8), ("minimax", C.c_uint8)]
 
 
 class Query(C.Structure):
@@ -95,6 +95,7 @@ _SIGS = {
     "ckr_op_rotate_into": (C.c_int, [vp, vp, vp, C.c_int64, vp]),
     "ckr_op_mul": (C.c_int, [vp, vp, vp, vp, C.POINTER(vp)]),
     "ckr_op_cheb_eval": (C.c_int, [vp, vp, vp, dblp, C.c_uint32, C.POINTER(vp)]),
+    "ckr_op_cmp_sign": (C.c_int, [vp, vp, vp, Sign, C.POINTER(vp)]),
     "ckr_op_add": (C.c_int, [vp, vp, vp, C.POINTER(vp)]),
     "ckr_op_sub": (C.c_int, [vp, vp, vp, C.POINTER(vp)]),
     "ckr_op_rescale": (C.c_int, [vp, vp, C.POINTER(vp)]),
@@ -150,8 +151,10 @@ def _p(a, t):
 
 
 def sign(cmp):
-    """(d_g, d_f) for the f/g composite, (0, 0, D) for the Chebyshev comparator of D levels"""
-    return Sign(int(cmp[0]), int(cmp[1]), int(cmp[2]) if len(cmp) > 2 else 0)
+    """(d_g, d_f) for the f/g composite, (0, 0, D) for the Chebyshev comparator
+    of D levels, (0, 0, 0, k) for k stages of the minimax composite"""
+    c = tuple(int(x) for x in cmp) + (0, 0)
+    return Sign(c[0], c[1], c[2], c[3])
 
 
 # ---- host-only helpers ------------------------------------------------------
@@ -418,6 +421,10 @@ class Context:
         `out` (a's level), allocating no device memory"""
         _ok(lib().ckr_op_rotate_into(self.h, keys.h, a.h, int(k), out.h))
         return out
+
+    def cmp_sign(self, keys, a, cmp):
+        """Cmp on a ciphertext of differences (section 2.2) under the comparator spec cmp"""
+        return self._unary(lib().ckr_op_cmp_sign, keys.h, a.h, sign(cmp))
 
     def mul(self, keys, a, b):
         return self._unary(lib().ckr_op_mul, keys.h, a.h, b.h)

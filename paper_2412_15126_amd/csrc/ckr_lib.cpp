@@ -359,7 +359,8 @@ struct Spec {
     int kind = 0, N = 0, k = 0, k_hi = 0, tie = 0;  // order statistics: the rank window [k, k_hi]
     ckr_sign cmp{0, 0, 0}, ind{0, 0, 0};
     auto tup() const {
-        return std::make_tuple(kind, N, k, k_hi, tie, cmp.d_g, cmp.d_f, cmp.cheb, ind.d_g, ind.d_f, ind.cheb);
+        return std::make_tuple(kind, N, k, k_hi, tie, cmp.d_g, cmp.d_f, cmp.cheb, cmp.minimax, ind.d_g, ind.d_f,
+                               ind.cheb, ind.minimax);
     }
 };
 // a group of B inputs of one level running one circuit
@@ -406,7 +407,9 @@ static DCt ct_new(Ctx &C, int level, int B) {
 // are reused only within that branch until the join (Pool::fork).
 class Branches {
   public:
-    explicit Branches(Ctx &C) : C_(C), main_(C.stream), nested_(C.forks > 0) {
+    // While kernel timing is on, branches run inline too: concurrent kernels
+    // would stretch each other's event-bracketed durations.
+    explicit Branches(Ctx &C) : C_(C), main_(C.stream), nested_(C.forks > 0 || C.prof.on) {
         if (nested_) return;
         C_.forks++;
         HIPCHK(hipEventCreateWithFlags(&fork_, hipEventDisableTiming));
@@ -1162,6 +1165,19 @@ static DCt repl_c(Ctx &C, const Keys &K, const DCt &V, int N) {
 // ------------------------------------------------------------------------
 static const double kF[4] = {35.0 / 16, -35.0 / 16, 21.0 / 16, -5.0 / 16};
 static const double kG[4] = {4589.0 / 1024, -16577.0 / 1024, 25614.0 / 1024, -12860.0 / 1024};
+// Minimax composite (section 2.2's alternative to f and g: composite minimax
+// approximations of the sign function): stage 0 is the odd degree-7
+// polynomial closest to 1 in the maximum norm on [2^-8.5, 1], stage s the one
+// closest to 1 on the interval stage s-1 maps that onto (errors 0.968, 0.827,
+// 0.362, 9.8e-3, 5.1e-9).  Coefficients of x, x^3, x^5, x^7.
+constexpr int kMinimaxStages = 5;
+static const double kMM[kMinimaxStages][4] = {
+    {11.626630381861787, -68.36534054680979, 126.44790262989271, -69.67707957286088},
+    {5.38484717173034, -7.907363201737443, 3.7393070660732937, -0.5295271268765817},
+    {3.8547436306459173, -5.358791130620638, 2.7473565274453287, -0.4363096838044091},
+    {2.363269725894833, -2.5537068630909263, 1.5095093062451124, -0.32798232661912397},
+    {2.1876161909909757, -2.187742945230383, 1.3126373118789916, -0.3125105627390891},
+};
 
 // a1 x + a3 x^3 + a5 x^5 + a7 x^7 (a7 != 0) in three levels and four products:
 //   y = x^2, t = (a7 x) y = a7 x^3, y2 = y^2, h = y2 (t + a5 x) = a7 x^7 + a5 x^5,
@@ -1204,7 +1220,7 @@ static DCt poly7(Ctx &C, const Keys &K, const DCt &x, const double a[4]) {
 constexpr int kChebMaxDepth = 16;
 constexpr int kChebChunk = 256;  // batch entries per product launch in the Chebyshev evaluation
 
-static int cmp_levels(ckr_sign c) { return c.cheb ? c.cheb : 3 * (c.d_g + c.d_f); }
+static int cmp_levels(ckr_sign c) { return c.cheb ? c.cheb : 3 * (c.d_g + c.d_f + c.minimax); }
 
 static void cheb_split(const std::vector<double> &c, int k, int r, int m, int idx,
                        std::vector<std::vector<double>> &leaves) {
@@ -1410,12 +1426,13 @@ static DCt cmp_sign(Ctx &C, const Keys &K, const DCt &D, ckr_sign cmp, double a 
         for (double &v : c) v = v * a;
         return cheb_eval(C, K, D, c);
     }
-    const int total = cmp.d_g + cmp.d_f;
+    const int total = cmp.minimax ? cmp.minimax : cmp.d_g + cmp.d_f;
     if (total < 1) throw Error{CKR_E_INVALID, "empty comparator"};
+    if (cmp.minimax > kMinimaxStages) throw Error{CKR_E_INVALID, "minimax composite has 5 stages"};
     DCt X;
     const DCt *cur = &D;
     for (int r = 0; r < total; r++) {
-        const double *c = r < cmp.d_g ? kG : kF;
+        const double *c = cmp.minimax ? kMM[r] : (r < cmp.d_g ? kG : kF);
         double cc[4];
         for (int i = 0; i < 4; i++) cc[i] = (r == total - 1) ? c[i] * (a * 0.5) : c[i];
         X = poly7(C, K, *cur, cc);
@@ -1429,11 +1446,13 @@ static DCt cmp_sign(Ctx &C, const Keys &K, const DCt &D, ckr_sign cmp, double a 
 // tie-correction offset), Sorting
 // ------------------------------------------------------------------------
 static bool sign_valid(ckr_sign c) {
-    if (c.cheb) return c.d_g == 0 && c.d_f == 0 && c.cheb >= 2 && c.cheb <= kChebMaxDepth;
+    if (c.cheb) return c.d_g == 0 && c.d_f == 0 && c.minimax == 0 && c.cheb >= 2 && c.cheb <= kChebMaxDepth;
+    if (c.minimax) return c.d_g == 0 && c.d_f == 0 && c.minimax <= kMinimaxStages;
     return c.d_g + c.d_f >= 1;
 }
 static void check_sign(ckr_sign c) {
-    if (!sign_valid(c)) throw Error{CKR_E_INVALID, "empty comparator composition or bad Chebyshev depth"};
+    if (!sign_valid(c))
+        throw Error{CKR_E_INVALID, "empty comparator composition, bad Chebyshev depth or minimax stage count"};
 }
 
 static void check_N(const Ctx &C, u32 N) {
@@ -3091,6 +3110,14 @@ ckr_status ckr_op_cheb_eval(ckr_context *ctx, const ckr_keys *keys, const ckr_ct
         NEED(ctx && keys && a && coeffs && out);
         std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         *out = wrap(*ctx->C, cheb_eval(*ctx->C, *keys->K, a->ct, std::vector<double>(coeffs, coeffs + deg1)));
+    });
+}
+ckr_status ckr_op_cmp_sign(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *a, ckr_sign cmp, ckr_ct **out) {
+    return guard([&] {
+        NEED(ctx && keys && a && out);
+        check_sign(cmp);
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
+        *out = wrap(*ctx->C, cmp_sign(*ctx->C, *keys->K, a->ct, cmp));
     });
 }
 ckr_status ckr_op_add(ckr_context *ctx, const ckr_ct *a, const ckr_ct *b, ckr_ct **out) {

@@ -47,6 +47,10 @@ PSETS = {
 
 # Comparator compositions (d_g, d_f) per workload: g applied d_g times, then f d_f times.
 RANK_CMP = {8: (2, 1), 16: (3, 1), 32: (3, 1), 64: (4, 1), 128: (4, 1)}
+# rank of N = 128 at the 2^-10 gap with the degree-7 polynomial composed 4
+# times: four stages of the minimax composite (0, 0, 0, 4) rank exactly, where
+# every four-fold f/g split fails (g^4 f above takes five)
+RANK128_MM = (0, 0, 0, 4)
 # tie-corrected argmin: (comparator, one-sided indicator).  At N = 128 the
 # indicator g^3 f^2 leaks up to 4.6e-2 of the second-smallest value into the
 # minimum's value (its output at rank distance 1/2 over N); g^4 f^2 bounds the

@@ -31,6 +31,26 @@ def rank128_p16():
             "exact": [int(x) for x in np.argsort(np.argsort(v)) + 1]}
 
 
+def rank128_p16_mm():
+    """rank of N = 128 at n = 2^16 with four stages of the minimax composite
+    (12 levels), encrypted at the circuit's depth"""
+    N, cmp = 128, (0, 0, 0, 4)
+    O.set_threads(min(16, os.cpu_count() or 1))
+    P = O.Params(**W.PSETS["P16"])
+    level = O.rank_depth(*cmp)
+    v, kseed, eseed = W.rank_workload(N, 2.0 ** -10, 0)
+    K = O.Keys(P, kseed, level, P.rank_galois(N))
+    R = O.rank(K, O.encrypt(K, v, level, eseed), N, *cmp)
+    dec = O.decrypt(K, R, N)
+    return {"_what": "oracle rank of N=128 at n=2^16 (P16), workload seed 0 (gap 2^-10), encryption level 14, "
+                     "comparator: four stages of the minimax composite: sha256 of the exported output and its "
+                     "decoded ranks",
+            "level": level,
+            "sha256": hashlib.sha256(R.export().tobytes()).hexdigest(),
+            "decoded": [float(x) for x in dec],
+            "exact": [int(x) for x in np.argsort(np.argsort(v)) + 1]}
+
+
 def argmin128_p17o():
     N = 128
     cmp, ind = W.ARGMIN_CMP[N]
@@ -294,7 +314,7 @@ if __name__ == "__main__":
     which = sys.argv[1:] or ["rank128_p16", "argmin128_p17o", "sort128_p17", "mixed_p16d", "argmax128_p17o",
                              "rank512_p16_multi", "sort512_p17s_multi", "rank128_p16_cheb",
                              "argmin128_p17_cheb", "sort128_p17_col", "kth64_p17s_div", "median128_p17o",
-                             "median101_p17s"]
+                             "median101_p17s", "rank128_p16_mm"]
     for name in which:
         json.dump(globals()[name](), open(os.path.join(HERE, name + ".json"), "w"), indent=1)
         print("wrote", name + ".json", flush=True)

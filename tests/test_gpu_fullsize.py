@@ -119,6 +119,37 @@ def test_rank128_chebyshev_full_size_matches_golden(full):
         assert np.array_equal(np.round(ctx.decrypt(gk, o, N)), np.argsort(np.argsort(v)) + 1)
 
 
+def test_rank128_minimax_four_stages_full_size(ora, full):
+    """Four stages of the minimax composite (12 levels; section 2.2's
+    alternative to f and g) rank N = 128 at the 2^-10 gap: one query against
+    the oracle run here and its stored digest, then a captured batch of 32 in
+    which every query ranks exactly and query 0 equals the digest."""
+    gold = json.load(open(os.path.join(os.path.dirname(GOLD), "rank128_p16_mm.json")))
+    cmp = (0, 0, 0, 4)
+    ctx = full["ctx"]
+    level = gold["level"]
+    assert level == ctx_rank_depth(cmp) == ora.rank_depth(*cmp) == 14
+    kseed = W.rank_workload(N, 2.0 ** -10, 0)[1]
+    say("[gpu] P16 keys at level 14 (device and oracle)")
+    gk = ctx.keygen(kseed, level, [N])
+    ok = ora.Keys(full["P"], kseed, level, full["P"].rank_galois(N))
+    g = ctx.encrypt(gk, full["v"], level, full["eseed"])
+    rg = ctx.rank(gk, g, N, cmp).export()
+    say("[gpu] P16 rank-128 minimax oracle")
+    ro = ora.rank(ok, ora.encrypt(ok, full["v"], level, full["eseed"]), N, *cmp).export()
+    assert np.array_equal(ro, rg)
+    assert hashlib.sha256(rg.tobytes()).hexdigest() == gold["sha256"]
+    qs = [(full["v"], full["eseed"])] + [W.rank_workload(N, 2.0 ** -10, 400 + i)[::2] for i in range(31)]
+    cts = [ctx.encrypt(gk, v, level, e) for v, e in qs]
+    for rep in range(2):     # eager, then captured
+        say(f"[gpu] P16 rank-128 minimax batch of 32, pass {rep}")
+        outs = ctx.run_batch(gk, "rank", cts, N, cmp)
+        assert hashlib.sha256(outs[0].export().tobytes()).hexdigest() == gold["sha256"]
+    errs = [np.max(np.abs(ctx.decrypt(gk, o, N) - (np.argsort(np.argsort(v)) + 1))) for (v, _), o in zip(qs, outs)]
+    say(f"[gpu] rank-128 minimax: max error {max(errs):.3f}")
+    assert max(errs) < 0.45
+
+
 def ctx_rank_depth(cmp):
     import paper_2412_15126_amd as ckr
     return ckr.rank_depth(cmp)

@@ -316,3 +316,21 @@ def test_rank8_ntt_chunking_bit_identical(p12):
     finally:
         p12.ctx.set_ntt_chunk(0)
         p12.ctx.set_graphs(True)
+
+
+@pytest.mark.parametrize("k", [1, 3, 5])
+def test_minimax_comparator_bit_exact(ora, ckr, k):
+    """k stages of the minimax composite on ciphertexts (the constants of
+    stage 0 reach 126) against the oracle, bit for bit, at n = 2^12, and rank
+    of 8 values with four stages."""
+    ps = W.PSETS["T12D"]
+    say(f"[gpu] minimax comparator, {k} stages")
+    pr = Pair(ora, ckr, ps, 16, Ns=(8,))
+    v = np.random.default_rng(30 + k).uniform(-1, 1, pr.n // 2)
+    o, g = pr.enc(v, 16, bytes([k] * 32))
+    same(ora.cmp_sign(pr.okeys, o, 0, 0, 0, k), pr.ctx.cmp_sign(pr.gkeys, g, (0, 0, 0, k)), f"minimax {k}")
+    if k == 3:
+        w, _, eseed = W.rank_workload(8, 0.01, 77)
+        o, g = pr.enc(w, 14, eseed)
+        same(ora.rank(pr.okeys, o, 8, 0, 0, 0, 4), pr.ctx.rank(pr.gkeys, g, 8, (0, 0, 0, 4)), "rank-8 minimax")
+
