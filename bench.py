@@ -196,6 +196,7 @@ def serve(args, quiet=False):
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2)},
         "by_kind": by_kind,
         "batches": st["batches"], "mean_batch": round(float(np.mean([j["batch"] for j in jobs])), 2),
+        "overlap_high": st["overlap_high"],
         "inflight_high_GiB": round(st["inflight_high_bytes"] / 2 ** 30, 2),
         "hbm_high_GiB": round((a.memory()[1] + b.memory()[1]) / 2 ** 30, 2),
         "same_alone_as_in_mix": bool(same),
@@ -775,7 +776,7 @@ def main():
         log(f"[bench] served segment: Poisson {args.rate}/s for {args.serve_seconds:.0f}s")
         sv = serve(args, quiet=True)
         res["served"] = {k: sv[k] for k in ("value", "unit", "latency_ms", "by_kind", "batches", "mean_batch",
-                                              "same_alone_as_in_mix", "hbm_high_GiB")}
+                                              "overlap_high", "same_alone_as_in_mix", "hbm_high_GiB")}
         res["served"]["workload"] = sv["config"]["workload"]
     if rank == 0 and not args.no_cpu_baseline:
         _, threads = host_cores()

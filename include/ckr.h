@@ -313,19 +313,23 @@ ckr_status ckr_rank_batch(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *
 /* Enable (default) or disable hipGraph capture of batched circuits. */
 ckr_status ckr_context_set_graphs(ckr_context *ctx, int enable);
 
-/* Serving.  A server owns one worker thread per context it routes to; each
- * worker repeatedly takes the oldest pending request of its context plus up
- * to max_batch pending requests of the same circuit, N and level, admits them
- * against hbm_budget (bytes of circuit working set in flight; 0 = unbounded;
- * each route's per-query working set is measured on its first batch, which
- * runs alone), runs them as one batched circuit (graph-captured after the
- * first call of a shape) and completes their tickets.  Requests arriving
- * while a batch runs join the next batch; routes on different contexts run
- * on different streams and overlap on the device.  A request whose working
- * set alone exceeds the budget fails with CKR_E_NOMEM.  Results are the same
- * bits as single calls.  The ciphertext passed to submit must stay alive
- * until its ticket completes.  API calls on a context are serialised with
- * its worker by a per-context lock. */
+/* Serving (continuous batching).  A server runs two worker slots per context
+ * it routes to, each issuing work on a stream of its own.  A free slot takes
+ * the oldest pending request of its context plus up to max_batch pending
+ * requests of the same circuit, N and level, admits them against hbm_budget
+ * (bytes of circuit working set in flight; 0 = unbounded; each route's
+ * per-query working set is measured on its first batch, which runs alone on
+ * its context), runs them as one batched circuit (graph-captured per slot
+ * after the first call of a shape) and completes their tickets.  A request
+ * that arrives while a batch of its context runs starts in the other slot as
+ * soon as admission allows, so batches of one context, and of different
+ * contexts, overlap on the device.  While a server runs, a block freed on one
+ * stream of a context is reused on that stream only, until the host has
+ * waited for it.  A request whose working set alone exceeds the budget fails
+ * with CKR_E_NOMEM.  Results are the same bits as single calls.  The
+ * ciphertext passed to submit must stay alive until its ticket completes.
+ * API calls on a context are serialised with its workers' launches by a
+ * per-context lock; waits run outside it. */
 typedef struct ckr_server ckr_server;
 ckr_status ckr_server_create(size_t hbm_budget, uint32_t max_batch, ckr_server **out);
 /* kind 1 rank, 2 argmin, 3 sort; all routes are added before the first submit */
@@ -337,7 +341,8 @@ ckr_status ckr_server_submit(ckr_server *srv, int kind, uint32_t N, const ckr_ct
  * submit-to-done, submit-to-start, batch size. */
 ckr_status ckr_server_wait(ckr_server *srv, uint64_t ticket, int timeout_ms, ckr_ct **outs, size_t n_outs,
                            double *latency_ms);
-/* stats: completed requests, batches run, high-water bytes in flight, pending requests */
+/* stats (5 values): completed requests, batches run, high-water bytes in
+ * flight, pending requests, most batches of one context in flight at once */
 ckr_status ckr_server_stats(ckr_server *srv, double *stats);
 void ckr_server_free(ckr_server *srv);
 

@@ -559,10 +559,10 @@ class Server:
         return [Ct(ctx, vp(o)) for o in outs], (lat[0], lat[1], int(lat[2]))
 
     def stats(self):
-        st = (C.c_double * 4)()
+        st = (C.c_double * 5)()
         _ok(lib().ckr_server_stats(self.h, st))
         return {"completed": int(st[0]), "batches": int(st[1]), "inflight_high_bytes": int(st[2]),
-                "pending": int(st[3])}
+                "pending": int(st[3]), "overlap_high": int(st[4])}
 
     def close(self):
         if getattr(self, "h", None):

@@ -90,42 +90,57 @@ class Pool {
         for (auto &b : owned) cache_[b.second].push_back(b.first);
     }
 
-    // While branches of one circuit run on several streams (fork()..join()),
-    // a freed block goes to a free list of the stream that freed it and is
-    // reused only by later allocations on that same stream (stream order
-    // makes that safe); blocks freed before the fork serve every stream.  At
-    // the join, whose wait orders every branch before later work on the
-    // joining stream, the lists return to the common cache.  `cur` names the
-    // stream work is being issued on.
-    void fork(const void *const *cur) {
+    // Stream-local reuse.  While branches of one circuit run on several streams
+    // (fork()..join()), or while a server issues batches on several slot
+    // streams of this context (set_local), a freed block goes to a free list of
+    // the stream that freed it and is reused only by later allocations on that
+    // same stream (stream order makes that safe); blocks freed before serve
+    // every stream.  A join moves the branches' lists to the joining stream,
+    // whose wait orders every branch before its later work (or, with no server,
+    // returns every list to the common cache); flush(stream), called once the
+    // host has waited for that stream, returns its list to the common cache.
+    // Blocks a graph capture uses stay the capture's (cap_free_) either way.
+    // `cur` names the stream work is being issued on.
+    void set_cur(const void *const *cur) { cur_ = cur; }
+    void set_local(bool on) {
         std::lock_guard<std::recursive_mutex> g(pmu_);
-        if (forked_++ == 0) cur_ = cur;
+        local_ += on ? 1 : -1;
+        if (local_ == 0 && forked_ == 0) release_all_locked();
     }
-    void join() {
+    void fork() {
         std::lock_guard<std::recursive_mutex> g(pmu_);
-        if (--forked_ > 0) return;
-        cur_ = nullptr;
-        for (auto &st : sfree_)
-            for (auto &kv : st.second)
-                for (void *p : kv.second) release_locked(p, kv.first);
-        sfree_.clear();
+        forked_++;
+    }
+    void join(const void *main, const void *const *sides, int nsides) {
+        std::lock_guard<std::recursive_mutex> g(pmu_);
+        --forked_;
+        if (local_ == 0 && forked_ == 0) {
+            release_all_locked();
+            return;
+        }
+        for (int i = 0; i < nsides; i++) {
+            if (sides[i] == main) continue;
+            auto st = sfree_.find(sides[i]);
+            if (st == sfree_.end()) continue;
+            for (auto &kv : st->second)
+                for (void *p : kv.second) {
+                    if (capturing_ && cap_set_.count(p)) cap_free_[kv.first].push_back(p);
+                    else sfree_[main][kv.first].push_back(p);
+                }
+            sfree_.erase(sides[i]);
+        }
+    }
+    void flush(const void *stream) {
+        std::lock_guard<std::recursive_mutex> g(pmu_);
+        auto st = sfree_.find(stream);
+        if (st == sfree_.end()) return;
+        for (auto &kv : st->second)
+            for (void *p : kv.second) release_locked(p, kv.first);
+        sfree_.erase(st);
     }
 
     void *get(size_t bytes) {
         std::lock_guard<std::recursive_mutex> g(pmu_);
-        if (forked_ && !arena_) {
-            auto st = sfree_.find(*cur_);
-            if (st != sfree_.end()) {
-                auto it = st->second.find(round(bytes));
-                if (it != st->second.end() && !it->second.empty()) {
-                    void *p = it->second.back();
-                    it->second.pop_back();
-                    in_use += round(bytes);
-                    high = std::max(high, in_use);
-                    return p;
-                }
-            }
-        }
         if (arena_) {
             const size_t off = (arena_off_ + 255) & ~size_t(255);
             if (off + bytes > arena_size_) throw Error{CKR_E_NOMEM, "scratch exhausted"};
@@ -143,7 +158,20 @@ class Pool {
                 return p;
             }
         }
-        void *p = get_uncaptured(bytes);
+        void *p = nullptr;
+        if (forked_ || local_) {
+            auto st = sfree_.find(*cur_);
+            if (st != sfree_.end()) {
+                auto it = st->second.find(bytes);
+                if (it != st->second.end() && !it->second.empty()) {
+                    p = it->second.back();
+                    it->second.pop_back();
+                    in_use += bytes;
+                    high = std::max(high, in_use);
+                }
+            }
+        }
+        if (!p) p = get_uncaptured(bytes);
         if (capturing_) cap_set_.insert(p);
         return p;
     }
@@ -183,7 +211,7 @@ class Pool {
         if (arena_ && (char *)p >= arena_ && (char *)p < arena_ + arena_size_) return;
         bytes = round(bytes);
         in_use -= bytes;
-        if (forked_) {
+        if (forked_ || (local_ && !(capturing_ && cap_set_.count(p)))) {
             sfree_[*cur_][bytes].push_back(p);
             return;
         }
@@ -202,15 +230,24 @@ class Pool {
             kv.second.clear();
         }
     }
-    ~Pool() { trim(); }
+    ~Pool() {
+        release_all_locked();
+        trim();
+    }
 
   private:
     void release_locked(void *p, size_t bytes) {
         if (capturing_ && cap_set_.count(p)) cap_free_[bytes].push_back(p);
         else cache_[bytes].push_back(p);
     }
+    void release_all_locked() {
+        for (auto &st : sfree_)
+            for (auto &kv : st.second)
+                for (void *p : kv.second) release_locked(p, kv.first);
+        sfree_.clear();
+    }
     std::recursive_mutex pmu_;
-    int forked_ = 0;
+    int forked_ = 0, local_ = 0;
     const void *const *cur_ = nullptr;
     std::map<const void *, std::unordered_map<size_t, std::vector<void *>>> sfree_;
     std::unordered_map<size_t, std::vector<void *>> cache_;
@@ -291,8 +328,21 @@ struct Ctx {
     int ntt_chunk = 0;            // limbs per two-pass chunk (0: whole dispatch), keeps pass-1 output in cache
     hipStream_t own_stream = nullptr;
     static constexpr int kSide = 4;
-    hipStream_t side[kSide] = {};  // streams of concurrent circuit branches (default priority)
-    int forks = 0;                 // open Branches (at most one: they do not nest)
+    static constexpr int kSlots = 2;  // server slots: batches of one context in flight at once
+    // slot 0: the API calls (stream = own_stream or the caller's); slots 1..kSlots: server batches
+    int slot = 0;
+    hipStream_t slot_stream[kSlots + 1] = {};
+    hipStream_t side[kSlots + 1][kSide] = {};  // streams of concurrent circuit branches, per slot
+    int forks = 0;                             // open Branches (at most one: they do not nest)
+    // streams of server slot s (made on first use, default priority)
+    void ensure_slot(int s) {
+        if (slot_stream[s]) return;
+        hipStream_t st = nullptr;
+        if (hipStreamCreate(&st) != hipSuccess) throw Error{CKR_E_DEVICE, "slot stream"};
+        slot_stream[s] = st;
+        for (hipStream_t &x : side[s])
+            if (!x && hipStreamCreate(&x) != hipSuccess) throw Error{CKR_E_DEVICE, "slot side stream"};
+    }
     Params P;
     DevTables T{};
     hipStream_t stream = nullptr;
@@ -316,7 +366,7 @@ struct Ctx {
     }
     ~Ctx() {
         plain.clear();
-        if (stream) (void)hipStreamSynchronize(stream);
+        (void)hipDeviceSynchronize();  // every stream of the context (slots and branches) is done
         for (auto &r : prof.pending) {
             (void)hipEventDestroy(r.a);
             (void)hipEventDestroy(r.b);
@@ -325,8 +375,11 @@ struct Ctx {
         pool.trim();
         for (void *p : table_mem) (void)hipFree(p);
         if (own_stream) (void)hipStreamDestroy(own_stream);
-        for (hipStream_t st : side)
-            if (st) (void)hipStreamDestroy(st);
+        for (auto &row : side)
+            for (hipStream_t st : row)
+                if (st) (void)hipStreamDestroy(st);
+        for (int i = 1; i <= kSlots; i++)
+            if (slot_stream[i]) (void)hipStreamDestroy(slot_stream[i]);
     }
 };
 
@@ -340,13 +393,14 @@ void Buf::release() {
 // plan-owned input batch and writes plan-owned outputs
 struct GraphPlan {
     Ctx *C = nullptr;
+    hipStream_t stream = nullptr;  // the stream its replays run on
     std::vector<DCt> in;  // one input batch per query group
     std::vector<DCt> outs;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<std::pair<void *, size_t>> owned;  // temporaries the replays write
     ~GraphPlan() {
-        if (C && C->stream) (void)hipStreamSynchronize(C->stream);
+        if (stream) (void)hipStreamSynchronize(stream);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (C) C->pool.release_owned(owned);
@@ -380,7 +434,9 @@ struct Keys {
     Buf pk;                           // [2][lmax+1][n] eval domain
     std::map<u32, Buf> swk;           // galois element (0 = relinearisation) -> [beta][2][Ek][n]
     std::set<PlanKey> warm;           // circuits run once eagerly (caches filled)
-    std::map<PlanKey, std::unique_ptr<GraphPlan>> plans;  // destroyed before the keys they read
+    // captured plans per (slot, circuit): each slot replays its own copy, so
+    // batches of several server slots never share a plan's buffers
+    std::map<std::pair<int, PlanKey>, std::unique_ptr<GraphPlan>> plans;  // destroyed before the keys they read
     int Ek() const { return lmax + 1 + C->P.K; }
 };
 
@@ -414,7 +470,7 @@ class Branches {
         C_.forks++;
         HIPCHK(hipEventCreateWithFlags(&fork_, hipEventDisableTiming));
         HIPCHK(hipEventRecord(fork_, main_));
-        C_.pool.fork((const void *const *)&C_.stream);
+        C_.pool.fork();
     }
     Branches(const Branches &) = delete;
     Branches &operator=(const Branches &) = delete;
@@ -424,7 +480,8 @@ class Branches {
             f();
             return;
         }
-        hipStream_t st = C_.side[next_++ % Ctx::kSide];
+        hipStream_t st = C_.side[C_.slot][next_++ % Ctx::kSide];
+        used_[std::min(next_, Ctx::kSide) - 1] = st;
         HIPCHK(hipStreamWaitEvent(st, fork_, 0));
         C_.stream = st;
         struct Back {
@@ -446,7 +503,7 @@ class Branches {
             const hipError_t r = hipStreamWaitEvent(main_, e, 0);
             if (err == hipSuccess) err = r;
         }
-        C_.pool.join();
+        pool_join();
         C_.forks--;
         release();
         if (err != hipSuccess) throw Error{CKR_E_DEVICE, std::string("branch join: ") + hipGetErrorString(err)};
@@ -455,13 +512,19 @@ class Branches {
         if (!joined_ && !nested_) {
             joined_ = true;
             for (hipEvent_t e : ends_) (void)hipStreamWaitEvent(main_, e, 0);
-            C_.pool.join();
+            pool_join();
             C_.forks--;
             release();
         }
     }
 
   private:
+    void pool_join() {
+        const void *sides[Ctx::kSide];
+        const int ns = std::min(next_, Ctx::kSide);
+        for (int i = 0; i < ns; i++) sides[i] = used_[i];
+        C_.pool.join(main_, sides, ns);
+    }
     void release() {
         for (hipEvent_t e : ends_) (void)hipEventDestroy(e);
         ends_.clear();
@@ -474,6 +537,7 @@ class Branches {
     std::vector<hipEvent_t> ends_;
     bool nested_;
     int next_ = 0;
+    hipStream_t used_[Ctx::kSide] = {};
     bool joined_ = false;
 };
 
@@ -486,6 +550,13 @@ static hipEvent_t prof_event(Ctx &C) {
     hipEvent_t e;
     HIPCHK(hipEventCreate(&e));
     return e;
+}
+
+// wait for the context stream; every block freed on it is then free for
+// every stream
+static void sync(Ctx &C) {
+    HIPCHK(hipStreamSynchronize(C.stream));
+    C.pool.flush(C.stream);
 }
 
 // run `launch` on the context stream; when profiling, bracket it with events
@@ -504,7 +575,7 @@ static void timed(Ctx &C, int cat, double bytes, F &&launch) {
 
 static void prof_resolve(Ctx &C) {
     if (C.prof.pending.empty()) return;
-    HIPCHK(hipStreamSynchronize(C.stream));
+    sync(C);
     for (auto &r : C.prof.pending) {
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
@@ -1046,7 +1117,7 @@ static Buf encode_plain(Ctx &C, const std::vector<double> &z, int level) {
     Buf b(&C, res.size());
     HIPCHK(hipMemcpyAsync(b.get(), res.data(), res.size() * 8, hipMemcpyHostToDevice, C.stream));
     ntt(C, b.get(), level + 1, 1, (size_t)(level + 1) * n, plain_map(), false);
-    HIPCHK(hipStreamSynchronize(C.stream));  // res goes out of scope
+    sync(C);  // res goes out of scope
     return b;
 }
 
@@ -1270,7 +1341,7 @@ static const Buf &lincomb_table(Ctx &C, const std::vector<std::vector<double>> &
         }
     Buf b(&C, tab.size() * 2);
     HIPCHK(hipMemcpyAsync(b.get(), tab.data(), tab.size() * sizeof(double2), hipMemcpyHostToDevice, C.stream));
-    HIPCHK(hipStreamSynchronize(C.stream));  // tab goes out of scope
+    sync(C);  // tab goes out of scope
     std::lock_guard<std::mutex> g(C.mu);
     return C.lincomb.emplace(std::move(key), std::move(b)).first->second;
 }
@@ -1879,7 +1950,7 @@ static std::vector<DCt> run_circuit(Ctx &C, Keys &K, const PlanKey &key,
         return X;
     };
     const bool use_graph = C.graphs && !C.prof.on;
-    auto it = K.plans.find(key);
+    auto it = K.plans.find({C.slot, key});
     if (!use_graph || (it == K.plans.end() && !K.warm.count(key))) {
         std::vector<DCt> X = inputs();
         fill(X);
@@ -1890,8 +1961,9 @@ static std::vector<DCt> run_circuit(Ctx &C, Keys &K, const PlanKey &key,
     if (it == K.plans.end()) {
         auto plan = std::make_unique<GraphPlan>();
         plan->C = &C;
+        plan->stream = C.stream;
         plan->in = inputs();
-        HIPCHK(hipStreamSynchronize(C.stream));
+        sync(C);
         HIPCHK(hipStreamBeginCapture(C.stream, hipStreamCaptureModeRelaxed));
         C.pool.begin_capture();
         try {
@@ -1906,7 +1978,7 @@ static std::vector<DCt> run_circuit(Ctx &C, Keys &K, const PlanKey &key,
         plan->owned = C.pool.end_capture();
         HIPCHK(hipStreamEndCapture(C.stream, &plan->graph));
         HIPCHK(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
-        it = K.plans.emplace(key, std::move(plan)).first;
+        it = K.plans.emplace(std::make_pair(C.slot, key), std::move(plan)).first;
     }
     GraphPlan &pl = *it->second;
     fill(pl.in);
@@ -2043,6 +2115,7 @@ class Server {
         out[1] = (double)batches_;
         out[2] = (double)inflight_high_;
         out[3] = (double)pending_.size();
+        out[4] = (double)overlap_high_;
     }
 
     void stop() {
@@ -2053,6 +2126,8 @@ class Server {
         }
         for (auto &t : workers_) t.join();
         workers_.clear();
+        for (Ctx *c : ctxs_) c->pool.set_local(false);
+        ctxs_.clear();
         // requests that never ran complete with an error, so no wait blocks forever
         std::lock_guard<std::mutex> g(mu_);
         for (u64 t : pending_) {
@@ -2069,18 +2144,26 @@ class Server {
   private:
     static std::recursive_mutex &ctx_mu(Ctx *C) { return C->mu_run; }
 
+    // Each context gets Ctx::kSlots workers, each issuing its batches on a
+    // stream of its own: a request that arrives while a batch of its context
+    // runs starts in the next free slot (admission permitting), so batches of
+    // one context overlap on the device.  The pool then reuses a freed block
+    // only on the stream that freed it until the host has waited for it.
     void start_locked() {
         if (started_) return;
         started_ = true;
-        std::vector<Ctx *> ctxs;
         for (auto &r : routes_)
-            if (std::find(ctxs.begin(), ctxs.end(), r.C) == ctxs.end()) ctxs.push_back(r.C);
-        for (Ctx *c : ctxs) workers_.emplace_back([this, c] { work(c); });
+            if (std::find(ctxs_.begin(), ctxs_.end(), r.C) == ctxs_.end()) ctxs_.push_back(r.C);
+        for (Ctx *c : ctxs_) {
+            c->pool.set_local(true);
+            for (int s = 1; s <= Ctx::kSlots; s++) workers_.emplace_back([this, c, s] { work(c, s); });
+        }
     }
 
     // oldest pending request of this context, then up to max_batch of the same route and level
     bool pick(Ctx *C, std::vector<Request *> &batch, size_t &bytes) {
         batch.clear();
+        if (exclusive_[C]) return false;  // a route's measuring batch runs alone on its context
         Request *first = nullptr;
         for (u64 t : pending_) {
             Request *r = reqs_[t].get();
@@ -2091,6 +2174,7 @@ class Server {
         }
         if (!first) return false;
         const Route &rt = routes_[first->route];
+        if (!rt.bytes_per_query && active_[C] > 0) return false;  // measure alone
         int cap = rt.bytes_per_query ? max_batch_ : 1;  // first batch of a route measures its working set
         for (u64 t : pending_) {
             Request *r = reqs_[t].get();
@@ -2115,7 +2199,7 @@ class Server {
         return true;
     }
 
-    void work(Ctx *C) {
+    void work(Ctx *C, int slot) {
         HIPCHK_NOTHROW(hipSetDevice(C->device));
         hipEvent_t done_ev = nullptr;
         HIPCHK_NOTHROW(hipEventCreateWithFlags(&done_ev, hipEventDisableTiming));
@@ -2130,19 +2214,34 @@ class Server {
             inflight_high_ = std::max(inflight_high_, inflight_);
             const Route rt = routes_[batch[0]->route];
             const bool measure = rt.bytes_per_query == 0;
+            if (measure) exclusive_[C] = true;
+            overlap_high_ = std::max(overlap_high_, ++active_[C]);
             lk.unlock();
             const double t0 = now_ms();
             std::vector<std::vector<DCt>> per(batch.size());
             int st = CKR_OK;
             std::string err;
             size_t measured = 0;
+            hipStream_t sst = nullptr;
             try {
                 {
-                    // enqueue under the context lock, wait outside it
+                    // enqueue under the context lock on this slot's stream, wait outside it
                     std::lock_guard<std::recursive_mutex> cg(ctx_mu(C));
-                    if (measure) HIPCHK(hipStreamSynchronize(C->stream));
+                    C->ensure_slot(slot);
+                    sst = C->slot_stream[slot];
+                    struct Use {
+                        Ctx *C;
+                        hipStream_t s0;
+                        int k0;
+                        ~Use() {
+                            C->stream = s0;
+                            C->slot = k0;
+                        }
+                    } use{C, C->stream, C->slot};
+                    C->stream = sst;
+                    C->slot = slot;
                     const size_t base = C->pool.in_use;
-                    C->pool.high = base;
+                    if (measure) C->pool.high = base;
                     std::vector<const DCt *> in;
                     for (Request *r : batch) in.push_back(r->in);
                     // the measuring batch runs eagerly so the pool sees its whole working set
@@ -2158,10 +2257,12 @@ class Server {
                     C->graphs = graphs;
                     for (size_t i = 0; i < batch.size(); i++)
                         for (auto &o : outs) per[i].push_back(slice(*C, o, (int)i, 1));
-                    measured = (C->pool.high - base) / batch.size();
-                    HIPCHK(hipEventRecord(done_ev, C->stream));
+                    outs.clear();  // freed on this slot's stream
+                    if (measure) measured = (C->pool.high - base) / batch.size();
+                    HIPCHK(hipEventRecord(done_ev, sst));
                 }
                 HIPCHK(hipEventSynchronize(done_ev));
+                C->pool.flush(sst);
             } catch (const Error &e) {
                 st = e.status;
                 err = e.msg;
@@ -2169,9 +2270,16 @@ class Server {
                 st = CKR_E_INVALID;
                 err = e.what();
             }
+            if (st != CKR_OK && sst) {
+                // the batch's work may still be queued: wait before its blocks serve other streams
+                (void)hipStreamSynchronize(sst);
+                C->pool.flush(sst);
+            }
             const double t1 = now_ms();
             lk.lock();
             if (measure && measured) routes_[batch[0]->route].bytes_per_query = measured;
+            if (measure) exclusive_[C] = false;
+            active_[C]--;
             inflight_ -= bytes;
             for (size_t i = 0; i < batch.size(); i++) {
                 Request *r = batch[i];
@@ -2197,6 +2305,10 @@ class Server {
     std::unordered_map<u64, std::unique_ptr<Request>> reqs_;
     std::vector<std::thread> workers_;
     size_t budget_, inflight_ = 0, inflight_high_ = 0;
+    std::vector<Ctx *> ctxs_;
+    std::map<Ctx *, int> active_;      // batches of each context in flight
+    std::map<Ctx *, bool> exclusive_;  // a measuring batch runs on the context
+    int overlap_high_ = 0;             // most batches of one context in flight at once
     int max_batch_;
     u64 next_ticket_ = 0, completed_ = 0, batches_ = 0;
     bool stop_ = false, started_ = false;
@@ -2304,7 +2416,8 @@ ckr_status ckr_context_create(const ckr_params *p, int dev, size_t budget, ckr_c
         // a stream of the context's own (default priority): graph capture needs a non-null stream
         HIPCHK(hipStreamCreate(&C.own_stream));
         C.stream = C.own_stream;
-        for (hipStream_t &st : C.side) HIPCHK(hipStreamCreate(&st));
+        for (hipStream_t &st : C.side[0]) HIPCHK(hipStreamCreate(&st));
+        C.pool.set_cur((const void *const *)&C.stream);
         *out = ctx.release();
     });
 }
@@ -2457,7 +2570,7 @@ static void gen_switch_key(Ctx &C, Keys &K, u32 g, const Buf &s_eval, const Buf 
         k_add(C.T, kb + (size_t)lo * n, kb + (size_t)lo * n, tmp.get(), hi - lo + 1, 1, 0, 0, 0, plain_map(lo), false,
               C.stream);
         HIPCHK(hipMemcpyAsync(ka, ea.get(), (size_t)Ek * n * 8, hipMemcpyDeviceToDevice, C.stream));
-        HIPCHK(hipStreamSynchronize(C.stream));  // host staging reused next digit
+        sync(C);  // host staging reused next digit
     }
     K.swk[g] = std::move(key);
 }
@@ -2479,7 +2592,7 @@ static void add_galois_keys(Ctx &C, Keys &K, const std::vector<u32> &gals, const
         k_automorph(C.T, sp.get(), s_eval.get(), Ek, 1, 0, 0, g, C.stream);
         gen_switch_key(C, K, g, s_eval, sp, seed);
     }
-    HIPCHK(hipStreamSynchronize(C.stream));
+    sync(C);
 }
 
 static void add_rotation_keys(Ctx &C, Keys &K, const std::vector<i64> &shifts, const uint8_t *seed) {
@@ -2541,7 +2654,7 @@ ckr_status ckr_keygen(ckr_context *ctx, const uint8_t seed[32], uint32_t max_lev
             ntt(C, ee.get(), L1, 1, 0, plain_map(), false);
             k_mul_pt(C.T, tmp.get(), p1, s_eval.get(), L1, 1, 0, 0, plain_map(), false, C.stream);
             k_add(C.T, p0, ee.get(), tmp.get(), L1, 1, 0, 0, 0, plain_map(), true, C.stream);
-            HIPCHK(hipStreamSynchronize(C.stream));
+            sync(C);
         }
         // relinearisation key: s' = s^2
         {
@@ -2644,7 +2757,7 @@ ckr_status ckr_encrypt(ckr_context *ctx, const ckr_keys *keys, const double *v, 
         k_mul_pt(C.T, c.d(), pk0, dh.get(), L1, 1, 0, 0, plain_map(), false, C.stream);
         k_mul_pt(C.T, c.d() + L, pk1, dh.get(), L1, 1, 0, 0, plain_map(), false, C.stream);
         k_add(C.T, c.d(), c.d(), dh.get() + L, L1, 2, L, L, L, plain_map(), false, C.stream);
-        HIPCHK(hipStreamSynchronize(C.stream));
+        sync(C);
         *out = wrap(C, std::move(c));
     });
 }
@@ -2656,7 +2769,7 @@ static std::vector<u64> download_coeffs(Ctx &C, const DCt &c) {
     ntt(C, t.d(), c.level + 1, 2 * c.B, L, plain_map(), true);
     std::vector<u64> h((size_t)c.B * 2 * L);
     HIPCHK(hipMemcpyAsync(h.data(), t.d(), h.size() * 8, hipMemcpyDeviceToHost, C.stream));
-    HIPCHK(hipStreamSynchronize(C.stream));
+    sync(C);
     return h;
 }
 
@@ -2681,7 +2794,7 @@ ckr_status ckr_decrypt(ckr_context *ctx, const ckr_keys *keys, const ckr_ct *ct,
         ntt(C, x.get(), 1, 1, 0, plain_map(), true);
         std::vector<u64> h(n);
         HIPCHK(hipMemcpyAsync(h.data(), x.get(), n * 8, hipMemcpyDeviceToHost, C.stream));
-        HIPCHK(hipStreamSynchronize(C.stream));
+        sync(C);
         std::vector<i64> m(n);
         for (size_t i = 0; i < n; i++) m[i] = h[i] > q / 2 ? -(i64)(q - h[i]) : (i64)h[i];
         decode_slots(C.P.logn, m.data(), C.P.scale[ct->ct.level], count, out);
@@ -2723,7 +2836,7 @@ ckr_status ckr_ct_import(ckr_context *ctx, const uint64_t *data, size_t words, u
         DCt c = ct_new(C, (int)level, 1);
         HIPCHK(hipMemcpyAsync(c.d(), data, 2 * L * 8, hipMemcpyHostToDevice, C.stream));
         ntt(C, c.d(), (int)level + 1, 2, L, plain_map(), false);
-        HIPCHK(hipStreamSynchronize(C.stream));
+        sync(C);
         *out = wrap(C, std::move(c));
     });
 }
@@ -3349,7 +3462,7 @@ ckr_status ckr_synchronize(ckr_context *ctx) {
     return guard([&] {
         NEED(ctx);
         std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
-        HIPCHK(hipStreamSynchronize(ctx->C->stream));
+        sync(*ctx->C);
     });
 }
 

@@ -82,6 +82,7 @@ def test_served_results_equal_alone(rings):
     say(f"[gpu] served {st}; p50 {np.percentile(lats, 50):.2f} ms p99 {np.percentile(lats, 99):.2f} ms")
     assert st["completed"] == len(qs)
     assert st["batches"] < len(qs) and max(batches) > 1     # requests were batched
+    assert st["overlap_high"] >= 2                           # batches of one context overlapped
     assert min(lats) > 0
     srv.close()
 
