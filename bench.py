@@ -332,6 +332,15 @@ def circuit_bench(args):
         "rank512": dict(pset="P16", N=512, b=128, ci=(W.MULTI_RANK_CMP[512], None), what=4,
                         desc="multi-ciphertext rank of N=512 (gap 2^-10) in 4 blocks of 128 at n=2^16 (24 + 7 "
                              "primes, dnum=3), blocks encrypted at level 21, comparator g^4 f^2"),
+        "rank2048": dict(pset="P16D", N=2048, b=128, ci=(W.MULTI_RANK_CMP[2048], None), what=4,
+                         desc="multi-ciphertext rank of N=2048 (gap 2^-12) in 16 blocks of 128 at n=2^16 (37 + 5 "
+                              "primes, dnum=8), blocks encrypted at level 24, comparator g^5 f^2"),
+        "rank16384": dict(pset="P16D", N=16384, b=128, ci=(W.MULTI_RANK_CMP[16384], None), what=4,
+                          desc="multi-ciphertext rank of N=16384 (gap 2^-15) in 128 blocks of 128 at n=2^16 (37 + 5 "
+                               "primes, dnum=8; 8256 block pairs), blocks encrypted at level 27, comparator g^6 f^2"),
+        "sort1024": dict(pset="P17S", N=1024, b=256, ci=W.MULTI_SORT_CMP[1024], what=4, sort=True,
+                         desc="multi-ciphertext sort of N=1024 (gap 2^-11) in 4 blocks of 256 at n=2^17 (48 + 12 "
+                              "primes, dnum=4), blocks encrypted at level 47, comparator g^4 f^2, indicator g^5 f^2"),
         "sort512": dict(pset="P17S", N=512, b=256, ci=W.MULTI_SORT_CMP[512], what=4, sort=True,
                         desc="multi-ciphertext sort of N=512 (gap 2^-10) in 2 blocks of 256 at n=2^17 (48 + 12 "
                              "primes, dnum=4), blocks encrypted at level 47, comparator g^4 f^2, indicator g^5 f^2"),
@@ -368,7 +377,8 @@ def circuit_bench(args):
         if spec.get("q", {}).get("kind") == "div":
             v, _, eseed = W.tripled_workload(N, 2000 + i, triples=4)
         else:
-            v, _, eseed = W.tied_workload(N, 2000 + i) if tie else W.rank_workload(N, 2.0 ** -10, 2000 + i)
+            gap = W.MULTI_GAP.get(N, 2.0 ** -10) if multi else 2.0 ** -10
+            v, _, eseed = W.tied_workload(N, 2000 + i) if tie else W.rank_workload(N, gap, 2000 + i)
         vals.append(v)
         if multi:
             queries.append([ctx.encrypt(keys, v[j * b:(j + 1) * b], level, bytes([j]) + eseed[1:])
@@ -435,35 +445,45 @@ def circuit_bench(args):
         bound = 0.5 if (multi and not msort) or spec.get("q", {}).get("kind") == "rank" else spec.get("bound", 2.0 ** -11)
         return worst < bound, worst
 
-    for _ in range(2 + args.warmup):
+    # single-ciphertext circuits: the first call runs eagerly, the second
+    # captures the graph; multi-ciphertext circuits run eagerly every time
+    outs = None
+    for _ in range(args.warmup if multi else 2 + args.warmup):
         outs = step()
     ctx.synchronize()
-    ok, worst = check(outs)
-    log(f"[{name}] warmup done, results correct: {ok} (worst error {worst:.3g})")
+    ok, worst = check(outs) if outs is not None else (None, None)
+    if ok is not None:
+        log(f"[{name}] warmup done, results correct: {ok} (worst error {worst:.3g})")
     ev = [hip.Event() for _ in range(args.steps + 1)]
     ctx.synchronize()
     t0 = time.perf_counter()
     ev[0].record(stream)
     for s_ in range(args.steps):
-        step()
+        outs = step()
         ev[s_ + 1].record(stream)
     ctx.synchronize()
     wall = time.perf_counter() - t0
     step_ms = [ev[s_].elapsed_ms(ev[s_ + 1]) for s_ in range(args.steps)]
-    ctx.set_profiling(True)
-    ctx.profile_reset()
-    step()
-    ctx.synchronize()
-    ctx.set_profiling(False)
-    prof = ctx.profile()
-    dom = max(prof, key=lambda k: prof[k][1])
-    launches, ms, nbytes = prof[dom]
+    if ok is None:   # no warm run: check the timed run's outputs
+        ok, worst = check(outs)
+        log(f"[{name}] results correct: {ok} (worst error {worst:.3g})")
+    prof = {}
+    if not args.no_profile:
+        ctx.set_profiling(True)
+        ctx.profile_reset()
+        step()
+        ctx.synchronize()
+        ctx.set_profiling(False)
+        prof = ctx.profile()
+    dom = max(prof, key=lambda k: prof[k][1]) if prof else None
+    launches, ms, nbytes = prof[dom] if prof else (0, 0.0, 0.0)
     achieved = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     res = {
         "metric": f"{name} queries/s", "value": round(B * args.steps / wall, 3), "unit": "queries/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3),
         "higher_is_better": True, "data": "synthetic", "dtype": "u64",
-        "config": {"workload": spec["desc"], "batch": B, "correct": ok, "worst_error": worst},
+        "config": {"workload": spec["desc"], "batch": B, "correct": ok, "worst_error": worst,
+                   "device_high_water_GiB": round(ctx.memory()[1] / 2 ** 30, 2)},
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
                        "p99": round(float(np.percentile(step_ms, 99)), 3), "per": f"step of {B} queries"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
@@ -571,7 +591,8 @@ def main():
     ap.add_argument("--mixed", action="store_true", help="64 mixed rank/argmin queries in one launch instead")
     ap.add_argument("--workload", default="rank128",
                     choices=["rank128", "argmin128", "argmax128", "sort128", "rank512", "sort512", "rank128cheb",
-                             "argmin128cheb", "sort128col", "kth64div", "median128", "rank128mm"],
+                             "argmin128cheb", "sort128col", "kth64div", "median128", "rank128mm", "rank2048",
+                             "rank16384", "sort1024"],
                     help="circuit to time (rank128: the headline metric)")
     ap.add_argument("--cheb-sweep", action="store_true",
                     help="rank-128 runtime and error against the Chebyshev comparison depth 6..14")
@@ -579,6 +600,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--no-serve", action="store_true", help="skip the served segment of the default run")
     ap.add_argument("--no-fg", action="store_true", help="skip the g^4 f comparison of the default run")
+    ap.add_argument("--no-profile", action="store_true", help="circuit workloads: skip the event-timed kernel pass")
     ap.add_argument("--max-batch", type=int, default=8)
     ap.add_argument("--hbm-budget", type=int, default=64, help="GiB of circuit working set in flight")
     args = ap.parse_args()

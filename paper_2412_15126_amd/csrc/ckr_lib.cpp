@@ -50,7 +50,14 @@ class Pool {
     void *user = nullptr;
     size_t budget = 0, in_use = 0, held = 0, high = 0;
 
-    static size_t round(size_t b) { return (b + 65535) & ~size_t(65535); }
+    // size classes: 64 KiB granules up to 1 MiB, then 8 classes per power of
+    // two (at most 12.5% over), so blocks of nearby sizes serve each other
+    static size_t round(size_t b) {
+        if (b <= (size_t(1) << 20)) return (b + 65535) & ~size_t(65535);
+        int e = 63 - __builtin_clzll((unsigned long long)(b - 1));
+        const size_t g = size_t(1) << (e - 3);
+        return (b + g - 1) & ~(g - 1);
+    }
 
     // While an arena is set (the allocation-free entry point), every block
     // comes from it by bumping an offset: nothing is taken from the cache or
@@ -192,12 +199,11 @@ class Pool {
             p = ualloc(bytes, user);
         } else if (hipMalloc(&p, bytes) != hipSuccess) {
             (void)hipGetLastError();
-            if (!capturing_) trim();
             p = nullptr;
-            if (hipMalloc(&p, bytes) != hipSuccess) {
-                (void)hipGetLastError();
-                p = nullptr;
-            }
+            // out of device memory: return cached blocks to the device, the
+            // largest first, only until the allocation fits (freeing the whole
+            // cache would make every later block a fresh allocation)
+            if (!capturing_) p = evict_for(bytes);
         }
         if (!p) throw Error{CKR_E_NOMEM, "device allocation failed"};
         held += bytes;
@@ -216,6 +222,32 @@ class Pool {
             return;
         }
         release_locked(p, bytes);
+    }
+    void *evict_for(size_t bytes) {
+        std::vector<size_t> sizes;
+        for (auto &kv : cache_)
+            if (!kv.second.empty()) sizes.push_back(kv.first);
+        std::sort(sizes.rbegin(), sizes.rend());
+        size_t freed = 0;
+        for (size_t sz : sizes) {
+            auto &v = cache_[sz];
+            while (!v.empty()) {
+                (void)hipFree(v.back());
+                v.pop_back();
+                held -= sz;
+                freed += sz;
+                if (freed >= bytes) {
+                    void *p = nullptr;
+                    if (hipMalloc(&p, bytes) == hipSuccess) return p;
+                    (void)hipGetLastError();
+                    freed = 0;
+                }
+            }
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) == hipSuccess) return p;
+        (void)hipGetLastError();
+        return nullptr;
     }
     // return cached blocks to the allocator (stream-ordered frees are safe
     // because the caller synchronises first)
@@ -1676,26 +1708,31 @@ static DCt sort_multi(Ctx &C, const Keys &K, const DCt &Bk, int b, ckr_sign cmp,
     DCt R = rank_multi(C, K, Bk, b, cmp);
     DCt RR = repl_r(C, K, R, b);
     DCt VR = repl_r(C, K, Bk, b);
-    std::vector<DCt> Xi;  // entry i*L + j: ReplR(R_j) - steps of output block i
-    for (int i = 0; i < L; i++) Xi.push_back(ev_add_plain(C, RR, get_plain(C, kStepsBlock, b, RR.level, i)));
-    std::vector<const DCt *> xp;
-    for (const DCt &x : Xi) xp.push_back(&x);
-    DCt Xs = ev_cmul_to(C, stack(C, xp), ind.cheb ? 0.5 / dN : 1.0 / dN, RR.level - 1);
-    if (ind.cheb) Xs = ev_plus_conj(C, K, Xs);
-    DCt d1 = ev_add_const(C, Xs, 0.5 / dN), d2 = ev_add_const(C, Xs, -0.5 / dN);
-    const int P = L * L;
-    DCt cc = cmp_sign(C, K, stack(C, {&d1, &d2}), ind);
-    DCt c1 = slice(C, cc, 0, P), c2 = slice(C, cc, P, P);
-    DCt M = ev_mul(C, K, c1, ev_add_const(C, ev_mul_int(C, c2, -1), 1.0));
-    std::vector<int> jj;
-    for (int i = 0; i < L; i++)
-        for (int j = 0; j < L; j++) jj.push_back(j);
-    DCt Pm = ev_mul(C, K, M, ev_cmul_to(C, gather(C, VR, jj), 1.0, M.level));
+    // the L^2 (output block, source block) indicators in batched comparator
+    // passes of at most kPairChunk ciphertexts: g output blocks at a time
+    const int g = std::max(1, kPairChunk / (2 * L));
     std::vector<DCt> Si;
-    for (int i = 0; i < L; i++) {
-        DCt acc = slice(C, Pm, i * L, 1);
-        for (int j = 1; j < L; j++) acc = ev_add(C, acc, slice(C, Pm, i * L + j, 1), false);
-        Si.push_back(std::move(acc));
+    for (int i0 = 0; i0 < L; i0 += g) {
+        const int ng = std::min(g, L - i0), P = ng * L;
+        std::vector<DCt> Xi;  // entry (i - i0) * L + j: ReplR(R_j) - steps of output block i
+        for (int i = i0; i < i0 + ng; i++) Xi.push_back(ev_add_plain(C, RR, get_plain(C, kStepsBlock, b, RR.level, i)));
+        std::vector<const DCt *> xp;
+        for (const DCt &x : Xi) xp.push_back(&x);
+        DCt Xs = ev_cmul_to(C, stack(C, xp), ind.cheb ? 0.5 / dN : 1.0 / dN, RR.level - 1);
+        if (ind.cheb) Xs = ev_plus_conj(C, K, Xs);
+        DCt d1 = ev_add_const(C, Xs, 0.5 / dN), d2 = ev_add_const(C, Xs, -0.5 / dN);
+        DCt cc = cmp_sign(C, K, stack(C, {&d1, &d2}), ind);
+        DCt c1 = slice(C, cc, 0, P), c2 = slice(C, cc, P, P);
+        DCt M = ev_mul(C, K, c1, ev_add_const(C, ev_mul_int(C, c2, -1), 1.0));
+        std::vector<int> jj;
+        for (int i = 0; i < ng; i++)
+            for (int j = 0; j < L; j++) jj.push_back(j);
+        DCt Pm = ev_mul(C, K, M, ev_cmul_to(C, gather(C, VR, jj), 1.0, M.level));
+        for (int i = 0; i < ng; i++) {
+            DCt acc = slice(C, Pm, i * L, 1);
+            for (int j = 1; j < L; j++) acc = ev_add(C, acc, slice(C, Pm, i * L + j, 1), false);
+            Si.push_back(std::move(acc));
+        }
     }
     std::vector<const DCt *> sp;
     for (const DCt &x : Si) sp.push_back(&x);

@@ -69,9 +69,13 @@ ORDER_TIE_CMP = {8: ((3, 1), (2, 2)), 128: ((4, 2), (4, 2))}
 # round exactly at the workload's minimum gap
 CHEB_CMP = {8: (0, 0, 8), 128: (0, 0, 12)}
 # multi-ciphertext rank (blocks of b values, N = L b): comparator per total N
-MULTI_RANK_CMP = {64: (4, 1), 128: (4, 1), 256: (4, 2), 512: (4, 2), 1024: (4, 2)}
+MULTI_RANK_CMP = {64: (4, 1), 128: (4, 1), 256: (4, 2), 512: (4, 2), 1024: (4, 2), 2048: (5, 2), 4096: (5, 2),
+                  8192: (6, 2), 16384: (6, 2)}
+# the gap of the min-gap workload per total N: (N - 1) gap < 1
+MULTI_GAP = {64: 2.0 ** -10, 128: 2.0 ** -10, 256: 2.0 ** -10, 512: 2.0 ** -10, 1024: 2.0 ** -11,
+             2048: 2.0 ** -12, 4096: 2.0 ** -13, 8192: 2.0 ** -14, 16384: 2.0 ** -15}
 # multi-ciphertext sort: (comparator, two-sided indicator) per total N
-MULTI_SORT_CMP = {64: ((4, 2), (4, 2)), 128: ((4, 2), (4, 2)), 512: ((4, 2), (5, 2))}
+MULTI_SORT_CMP = {64: ((4, 2), (4, 2)), 128: ((4, 2), (4, 2)), 512: ((4, 2), (5, 2)), 1024: ((4, 2), (5, 2))}
 # sort: (comparator, two-sided indicator)
 SORT_CMP = {8: ((3, 1), (3, 2)), 16: ((4, 1), (3, 2)), 32: ((4, 1), (3, 2)), 64: ((4, 1), (4, 2)),
             128: ((4, 1), (4, 2))}
