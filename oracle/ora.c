@@ -62,11 +62,9 @@ typedef unsigned __int128 u128;
 #define ORA_E_RANGE (-2)
 #define ORA_E_DEPTH (-3)
 
-/* comparator: the f/g composite of section 2.2, g applied d_g times then f
- * applied d_f times (cheb = 0), or the Chebyshev interpolant of Eq. (1) with
- * cheb = D levels (d_g = d_f = 0) */
-/* comparator: the f/g composite g^dg then f^df, the Chebyshev interpolant of
- * cheb levels, or the first mm stages of the minimax composite */
+/* comparator: the f/g composite of section 2.2, g applied dg times then f
+ * applied df times; or the Chebyshev interpolant of Eq. (1) with cheb levels;
+ * or the first mm stages of the minimax composite (the other fields 0) */
 typedef struct { int dg, df, cheb, mm; } ora_cmp;
 
 /* ------------------------------------------------------------------ */
