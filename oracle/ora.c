@@ -549,6 +549,18 @@ static const ora_swk *find_swk(const ora_keys *Kp, u32 g) {
     return NULL;
 }
 
+int ora_circuit_galois(const ora_params *P, u32 Nr, int what, u32 *out);
+
+/* ORA_OK when the keys hold every rotation key that the circuits `what` (the
+ * bits of ora_circuit_galois) need on N values; the circuits assume them */
+static int need_keys(const ora_keys *Kp, u32 N, int what) {
+    u32 g[256];
+    int c = ora_circuit_galois(Kp->P, N, what, g);
+    for (int i = 0; i < c; i++)
+        if (!find_swk(Kp, g[i])) return ORA_E_INVALID;
+    return ORA_OK;
+}
+
 /* ---------------- encryption / decryption ---------------- */
 ora_ct *ora_encrypt(const ora_keys *Kp, const double *z, u32 count, int level, const u8 seed[32], int *status) {
     const ora_params *P = Kp->P;
@@ -1346,6 +1358,7 @@ ora_ct *ora_cmp_matrix(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, i
 ora_ct *ora_rank(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, int *status) {
     int st = check_N_padded(Kp->P, N);
     if (st != ORA_OK) { *status = st; return NULL; }
+    if ((st = need_keys(Kp, N, 1)) != ORA_OK) { *status = st; return NULL; }
     if (V->level < ora_rank_depth_n(N, cm, 0)) { *status = ORA_E_DEPTH; return NULL; }
     const u32 Np = pow2_ceil(N);
     ora_ct *C = ora_cmp_matrix(Kp, V, Np, cm, &st);
@@ -1373,6 +1386,7 @@ int ora_rank_multi_depth(ora_cmp cm) { return 3 + cmp_levels(cm); }
 int ora_rank_multi(const ora_keys *Kp, ora_ct *const *Bk, u32 L, u32 b, ora_cmp cm, ora_ct **R) {
     int st = check_N(Kp->P, b);
     if (st != ORA_OK) return st;
+    if ((st = need_keys(Kp, b, 4)) != ORA_OK) return st;
     if (L < 1) return ORA_E_INVALID;
     for (u32 i = 0; i < L; i++)
         if (Bk[i]->level != Bk[0]->level) return ORA_E_INVALID;
@@ -1436,6 +1450,7 @@ int ora_sort_multi(const ora_keys *Kp, ora_ct *const *Bk, u32 L, u32 b, ora_cmp 
                    ora_ct **S) {
     int st = check_N(Kp->P, b);
     if (st != ORA_OK) return st;
+    if ((st = need_keys(Kp, b, 4)) != ORA_OK) return st;
     if (L < 1) return ORA_E_INVALID;
     for (u32 i = 0; i < L; i++)
         if (Bk[i]->level != Bk[0]->level) return ORA_E_INVALID;
@@ -1575,6 +1590,7 @@ static ora_ct *tie_rank(const ora_keys *Kp, const ora_ct *V, u32 Nr, ora_cmp cm,
 ora_ct *ora_rank_tie(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, int *status) {
     int st = check_N_padded(Kp->P, N);
     if (st != ORA_OK) { *status = st; return NULL; }
+    if ((st = need_keys(Kp, N, 1)) != ORA_OK) { *status = st; return NULL; }
     if (V->level < ora_rank_depth_n(N, cm, 1)) { *status = ORA_E_DEPTH; return NULL; }
     ora_ct *kv = tie_rank(Kp, V, N, cm, &st);
     *status = st;
@@ -1646,6 +1662,7 @@ int ora_order_stat(const ora_keys *Kp, const ora_ct *V, u32 N, u32 k, ora_cmp cm
                    ora_ct **onehot, ora_ct **value) {
     int st = check_N(Kp->P, N);
     if (st != ORA_OK) return st;
+    if ((st = need_keys(Kp, N, 2)) != ORA_OK) return st;
     if (k < 1 || k > N) return ORA_E_INVALID;
     return order_range(Kp, V, N, k, k, cm, ci, tie, onehot, value);
 }
@@ -1656,6 +1673,7 @@ int ora_order_range(const ora_keys *Kp, const ora_ct *V, u32 N, u32 a, u32 b, or
                     ora_ct **onehot, ora_ct **value) {
     int st = check_N_padded(Kp->P, N);
     if (st != ORA_OK) return st;
+    if ((st = need_keys(Kp, N, 2)) != ORA_OK) return st;
     return order_range(Kp, V, N, a, b, cm, ci, tie, onehot, value);
 }
 
@@ -1723,6 +1741,7 @@ int ora_sort_depth(ora_cmp cm, ora_cmp ci) { return ora_rank_depth(cm) + 5 + cmp
 ora_ct *ora_sort(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, ora_cmp ci, int *status) {
     int st = check_N(Kp->P, N);
     if (st != ORA_OK) { *status = st; return NULL; }
+    if ((st = need_keys(Kp, N, 4)) != ORA_OK) { *status = st; return NULL; }
     if (V->level < ora_sort_depth(cm, ci)) { *status = ORA_E_DEPTH; return NULL; }
     ora_ct *R = ora_rank(Kp, V, N, cm, &st);
     ora_ct *RR = ora_repl_r(Kp, R, N, &st);
@@ -1767,6 +1786,7 @@ int ora_sort_col_depth(ora_cmp cm, ora_cmp ci) { return ora_rank_depth(cm) + 4 +
 ora_ct *ora_sort_col(const ora_keys *Kp, const ora_ct *V, u32 N, ora_cmp cm, ora_cmp ci, int *status) {
     int st = check_N(Kp->P, N);
     if (st != ORA_OK) { *status = st; return NULL; }
+    if ((st = need_keys(Kp, N, 2)) != ORA_OK) { *status = st; return NULL; }
     if (!cmp_valid(cm) || !cmp_valid(ci)) { *status = ORA_E_INVALID; return NULL; }
     if (V->level < ora_sort_col_depth(cm, ci)) { *status = ORA_E_DEPTH; return NULL; }
     const double dN = (double)N;
