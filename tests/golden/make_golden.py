@@ -169,6 +169,27 @@ def rank512_p16_multi():
             "exact": [int(x) for x in np.argsort(np.argsort(v)) + 1]}
 
 
+def rank2048_p16d_multi():
+    """multi-ciphertext ranking of N = 2048 values in 16 blocks of 128 at n = 2^16 (136 block pairs)"""
+    N, b = 2048, 128
+    cmp = W.MULTI_RANK_CMP[N]
+    O.set_threads(min(16, os.cpu_count() or 1))
+    P = O.Params(**W.PSETS["P16D"])
+    level = O.rank_multi_depth(*cmp)
+    v, kseed, eseed = W.rank_workload(N, W.MULTI_GAP[N], 0)
+    K = O.Keys(P, kseed, level, P.circuit_galois(b, 4))
+    blocks = [O.encrypt(K, v[i * b:(i + 1) * b], level, bytes([i]) + eseed[1:]) for i in range(N // b)]
+    R = O.rank_multi(K, blocks, b, *cmp)
+    dec = np.concatenate([O.decrypt(K, r, b) for r in R])
+    return {"_what": "oracle multi-ciphertext ranking (section 5) of N=2048 values (workload seed 0, gap 2^-12) in 16 "
+                     "blocks of 128 at n=2^16 (P16D), blocks encrypted at level 24 with seeds (i, eseed[1:]), "
+                     "comparator g^5 f^2: sha256 of each exported rank block and the decoded ranks",
+            "level": level,
+            "sha256": [hashlib.sha256(r.export().tobytes()).hexdigest() for r in R],
+            "decoded": [float(x) for x in dec],
+            "exact": [int(x) for x in np.argsort(np.argsort(v)) + 1]}
+
+
 def sort512_p17s_multi():
     """multi-ciphertext sorting of N = 512 values in 2 blocks of 256 at n = 2^17"""
     N, b = 512, 256
@@ -182,6 +203,28 @@ def sort512_p17s_multi():
     out = O.sort_multi(K, blocks, b, cmp, ind)
     dec = np.concatenate([O.decrypt(K, o, b) for o in out])
     return {"_what": "oracle multi-ciphertext sorting (section 5) of N=512 values (workload seed 0, gap 2^-10) in 2 "
+                     "blocks of 256 at n=2^17 (P17S), blocks encrypted at level 47 with seeds (i, eseed[1:]), "
+                     "comparator g^4 f^2, indicator g^5 f^2: sha256 of each exported sorted block and the decoded "
+                     "values",
+            "level": level,
+            "sha256": [hashlib.sha256(o.export().tobytes()).hexdigest() for o in out],
+            "decoded": [float(x) for x in dec],
+            "sorted": [float(x) for x in np.sort(v)]}
+
+
+def sort1024_p17s_multi():
+    """multi-ciphertext sorting of N = 1024 values in 4 blocks of 256 at n = 2^17"""
+    N, b = 1024, 256
+    cmp, ind = W.MULTI_SORT_CMP[N]
+    O.set_threads(min(16, os.cpu_count() or 1))
+    P = O.Params(**W.PSETS["P17S"])
+    level = O.sort_multi_depth(cmp, ind)
+    v, kseed, eseed = W.rank_workload(N, W.MULTI_GAP[N], 0)
+    K = O.Keys(P, kseed, level, P.circuit_galois(b, 4))
+    blocks = [O.encrypt(K, v[i * b:(i + 1) * b], level, bytes([i]) + eseed[1:]) for i in range(N // b)]
+    out = O.sort_multi(K, blocks, b, cmp, ind)
+    dec = np.concatenate([O.decrypt(K, o, b) for o in out])
+    return {"_what": "oracle multi-ciphertext sorting (section 5) of N=1024 values (workload seed 0, gap 2^-11) in 4 "
                      "blocks of 256 at n=2^17 (P17S), blocks encrypted at level 47 with seeds (i, eseed[1:]), "
                      "comparator g^4 f^2, indicator g^5 f^2: sha256 of each exported sorted block and the decoded "
                      "values",
@@ -314,7 +357,8 @@ if __name__ == "__main__":
     which = sys.argv[1:] or ["rank128_p16", "argmin128_p17o", "sort128_p17", "mixed_p16d", "argmax128_p17o",
                              "rank512_p16_multi", "sort512_p17s_multi", "rank128_p16_cheb",
                              "argmin128_p17_cheb", "sort128_p17_col", "kth64_p17s_div", "median128_p17o",
-                             "median101_p17s", "rank128_p16_mm"]
+                             "median101_p17s", "rank128_p16_mm", "rank2048_p16d_multi",
+                             "sort1024_p17s_multi"]
     for name in which:
         json.dump(globals()[name](), open(os.path.join(HERE, name + ".json"), "w"), indent=1)
         print("wrote", name + ".json", flush=True)

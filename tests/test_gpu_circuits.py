@@ -752,3 +752,50 @@ def test_median101_padded_full_size_matches_golden():
     tol = VB.tolerance(v, 51, 51, cmp, ind, True, 17)
     assert tol < 2.0 ** -11
     assert abs(ctx.decrypt(keys, val, 1)[0] - np.median(v)) <= tol
+
+
+def test_multi_ciphertext_rank2048_full_size_matches_golden():
+    """N = 2048 values (gap 2^-12) in 16 blocks of 128 at n = 2^16 (136 block
+    pairs in batched comparator passes of 32) against oracle digests; every
+    rank exact; the device high-water mark is reported."""
+    import paper_2412_15126_amd as ckr
+    gold = json.load(open(os.path.join(GOLD, "rank2048_p16d_multi.json")))
+    ps = W.PSETS["P16D"]
+    N, b = 2048, 128
+    cmp = W.MULTI_RANK_CMP[N]
+    level = ckr.rank_multi_depth(cmp)
+    assert level == gold["level"] == 24
+    v, kseed, eseed = W.rank_workload(N, W.MULTI_GAP[N], 0)
+    ctx = ckr.Context(ps)
+    say("[gpu] P16D multi-ciphertext keys")
+    keys = ctx.keygen(kseed, level, [b], what=4)
+    blocks = [ctx.encrypt(keys, v[i * b:(i + 1) * b], level, bytes([i]) + eseed[1:]) for i in range(N // b)]
+    say("[gpu] P16D multi-ciphertext rank of 2048")
+    R = ctx.rank_multi(keys, blocks, b, cmp)
+    assert [hashlib.sha256(r.export().tobytes()).hexdigest() for r in R] == gold["sha256"]
+    got = np.concatenate([ctx.decrypt(keys, r, b) for r in R])
+    assert np.array_equal(np.round(got), np.argsort(np.argsort(v)) + 1)
+    say(f"[gpu] rank-2048: max error {np.max(np.abs(got - (np.argsort(np.argsort(v)) + 1))):.3f}, "
+        f"device high-water {ctx.memory()[1] / 2 ** 30:.1f} GiB")
+
+
+def test_multi_ciphertext_sort1024_full_size_matches_golden():
+    """N = 1024 values (gap 2^-11) in 4 blocks of 256 at n = 2^17 against
+    oracle digests (the L^2 indicators in batched passes of 32)."""
+    import paper_2412_15126_amd as ckr
+    gold = json.load(open(os.path.join(GOLD, "sort1024_p17s_multi.json")))
+    ps = W.PSETS["P17S"]
+    N, b = 1024, 256
+    cmp, ind = W.MULTI_SORT_CMP[N]
+    level = ckr.sort_multi_depth(cmp, ind)
+    assert level == gold["level"] == 47
+    v, kseed, eseed = W.rank_workload(N, W.MULTI_GAP[N], 0)
+    ctx = ckr.Context(ps)
+    say("[gpu] P17S multi-ciphertext keys (1024)")
+    keys = ctx.keygen(kseed, level, [b], what=4)
+    blocks = [ctx.encrypt(keys, v[i * b:(i + 1) * b], level, bytes([i]) + eseed[1:]) for i in range(N // b)]
+    say("[gpu] P17S multi-ciphertext sort of 1024")
+    S = ctx.sort_multi(keys, blocks, b, cmp, ind)
+    assert [hashlib.sha256(s.export().tobytes()).hexdigest() for s in S] == gold["sha256"]
+    got = np.concatenate([ctx.decrypt(keys, s, b) for s in S])
+    assert np.max(np.abs(got - np.sort(v))) < W.MULTI_GAP[N] / 2
