@@ -8,6 +8,9 @@ import pytest
 
 from paper_2412_15126_amd import workloads as W
 
+import value_bound as VB
+
+
 pytestmark = pytest.mark.gpu
 
 
@@ -133,4 +136,4 @@ def test_sort8_chebyshev_rank_bit_exact(ora, small):
     o = ora.sort(small["okeys"], ora.encrypt(small["okeys"], v, level, eseed), N, cmp, ind)
     g = ctx.sort(small["gkeys"], ctx.encrypt(small["gkeys"], v, level, eseed), N, cmp, ind)
     assert np.array_equal(o.export(), g.export())
-    assert np.max(np.abs(ctx.decrypt(small["gkeys"], g, N) - np.sort(v))) < 0.01
+    assert np.max(np.abs(ctx.decrypt(small["gkeys"], g, N) - np.sort(v))) <= VB.sort_tolerance(v, cmp, ind)
