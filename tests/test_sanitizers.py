@@ -1,9 +1,10 @@
 """The CPU oracle and the library's host code under AddressSanitizer (with
 LeakSanitizer) and UndefinedBehaviorSanitizer.
 
-Each driver under tests/sanitize/ is built with gcc/g++ and
--fsanitize=address,undefined (no GPU code is involved) and run; the run must
-pass its own functional checks and print no sanitizer report.  The oracle's
+Each driver under tests/sanitize/ is built with gcc/g++,
+-fsanitize=address,undefined and -Wall -Werror (no GPU code is involved) and
+run; the run must pass its own functional checks and print no sanitizer
+report.  The oracle's
 driver runs rank with the f/g, minimax and Chebyshev comparators, a
 tie-corrected order statistic, sort, multi-ciphertext rank and the error
 paths (too few levels, bad N, missing rotation keys) on a ring of 2^10; the
@@ -16,7 +17,8 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SAN = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
+SAN = ["-Wall", "-Werror", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+       "-fno-sanitize-recover=undefined"]
 REPORTS = ("ERROR: AddressSanitizer", "ERROR: LeakSanitizer", "runtime error:")
 
 
