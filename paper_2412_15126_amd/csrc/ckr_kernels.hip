@@ -87,7 +87,8 @@ template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool PRO, bool IN_L
 __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, int logn, int mod, double q,
                                           double qinv, const double *__restrict__ twq,
                                           const double2 *__restrict__ twlast,
-                                          double *lds, Emit &&emit, u32 gal = 0, double cq = 0.0) {
+                                          double *lds, Emit &&emit, u32 gal = 0, double cq = 0.0,
+                                          const double2 *twrow = nullptr) {
     constexpr int S = 1 << LOGS, E = 1 << LOGE, TPC = S / E, NT = C * TPC;
     constexpr int NR = (LOGS + LOGE - 1) / LOGE;
     constexpr int SP = S + (S >> 4) + 1;
@@ -132,6 +133,17 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
         } else {
             const double wq = twq[idx];
             return make_double2(__fma_rn(wq, q, C52) - C52, wq);
+        }
+    };
+    // twiddle of stage s (global stage g) for local position r.  A row pass run
+    // in a loop (the fused key switch: one pass per digit over the same rows)
+    // reads them from twrow, the rows' {w, w/q} pairs staged in LDS once by the
+    // caller at local index (1 << s) + (r >> (LOGS - s)).
+    auto twid_at = [&](int s, int g, int r) -> double2 {
+        if constexpr (IN_LOOP && !COLPASS) {
+            return twrow[cl * S + (1 << s) + (r >> (LOGS - s))];
+        } else {
+            return twid((1 << g) + (cpart << s) + (r >> (LOGS - s)));
         }
     };
     double x[E];
@@ -189,7 +201,7 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
                     if (k & (1 << kb)) continue;
                     const int k2 = k | (1 << kb);
                     const int r = rbase | (k << w);
-                    const double2 W = twid((1 << g) + (cpart << s) + (r >> (LOGS - s)));
+                    const double2 W = twid_at(s, g, r);
                     double u = x[k];
                     u = u >= two_q ? u - two_q : u;
                     const double v = mm_lazy(x[k2], W.x, W.y, q);
@@ -216,7 +228,7 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
                         x[k2] = mm_lazy(d, N1.x, N1.y, q);
                     } else {
                         const int r = rbase | (k << w);
-                        const double2 W = twid((1 << g) + (cpart << s) + (r >> (LOGS - s)));
+                        const double2 W = twid_at(s, g, r);
                         x[k] = sm >= two_q ? sm - two_q : sm;
                         x[k2] = mm_lazy(d, W.x, W.y, q);
                     }
@@ -335,6 +347,7 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)), (LOGE == 2 ? 6 : 1))
     constexpr int S = 1 << LOGS, E = 1 << LOGE, NT = C * (S / E);
     constexpr int SP = S + (S >> 4) + 1;
     __shared__ double lds[C * SP];
+    __shared__ double2 twr[C * S];  // the rows' forward twiddles {w, w/q}, shared by the digits' passes
     const size_t n = (size_t)1 << logn;
     const int tiles = (int)(n >> LOGS) / C;
     const int wg = blockIdx.x, xcd = wg & 7, seq = wg >> 3;
@@ -348,6 +361,20 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)), (LOGE == 2 ? 6 : 1))
     const double *twq = twqtab + (size_t)mod * n;
     const int own = (t <= a.level) ? t / a.alpha : -1;  // digit holding limb t, if any
     const int tid = threadIdx.x;
+    if (a.beta > (own >= 0 ? 1 : 0)) {
+        // row c0 + cl, stage s (global stage logn - LOGS + s) uses table entry
+        // 2^(logn - LOGS + s) + ((c0 + cl) << s) + (r >> (LOGS - s)); staged at
+        // cl S + 2^s + (r >> (LOGS - s)), entry 0 of each row unused
+        const int g0 = logn - LOGS;
+        for (int i = tid; i < C * S; i += NT) {
+            const int cl = i / S, li = i % S;
+            if (li == 0) continue;
+            const int st = 31 - __clz(li);
+            const double wq = twq[(1 << (g0 + st)) + ((c0 + cl) << st) + (li - (1 << st))];
+            twr[i] = make_double2(__fma_rn(wq, q, C52) - C52, wq);
+        }
+        __syncthreads();
+    }
     double sb[E], sa[E];
 #pragma unroll
     for (int k = 0; k < E; k++) sb[k] = sa[k] = 0.0;
@@ -378,8 +405,7 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)), (LOGE == 2 ? 6 : 1))
         } else {
             __syncthreads();  // the previous digit's last LDS reads are done
             pass_core<LOGS, LOGE, C, false, false, false, true>(a.ext + bi * a.sext + ((size_t)j * a.E + t) * n, c0,
-                                                                logn,
-                                                          mod, q, qinv, twq, twlast, lds, acc);
+                                                                logn, mod, q, qinv, twq, twlast, lds, acc, 0, 0.0, twr);
         }
         if ((j & 7) == 7) {
 #pragma unroll
