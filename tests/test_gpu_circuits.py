@@ -760,8 +760,6 @@ def test_multi_ciphertext_rank2048_full_size_matches_golden():
     pairs in batched comparator passes of 32) against oracle digests; every
     rank exact; the device high-water mark is reported."""
     import paper_2412_15126_amd as ckr
-    if not os.path.exists(os.path.join(GOLD, "rank2048_p16d_multi.json")):
-        pytest.skip("oracle digest not written yet (tests/golden/make_golden.py rank2048_p16d_multi)")
     gold = json.load(open(os.path.join(GOLD, "rank2048_p16d_multi.json")))
     ps = W.PSETS["P16D"]
     N, b = 2048, 128
@@ -786,8 +784,6 @@ def test_multi_ciphertext_sort1024_full_size_matches_golden():
     """N = 1024 values (gap 2^-11) in 4 blocks of 256 at n = 2^17 against
     oracle digests (the L^2 indicators in batched passes of 32)."""
     import paper_2412_15126_amd as ckr
-    if not os.path.exists(os.path.join(GOLD, "sort1024_p17s_multi.json")):
-        pytest.skip("oracle digest not written yet (tests/golden/make_golden.py sort1024_p17s_multi)")
     gold = json.load(open(os.path.join(GOLD, "sort1024_p17s_multi.json")))
     ps = W.PSETS["P17S"]
     N, b = 1024, 256
