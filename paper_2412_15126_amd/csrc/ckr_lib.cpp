@@ -431,6 +431,7 @@ struct GraphPlan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<std::pair<void *, size_t>> owned;  // temporaries the replays write
+    unsigned long long last_use = 0;               // Keys::plan_clock at its latest replay
     ~GraphPlan() {
         if (stream) (void)hipStreamSynchronize(stream);
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -469,6 +470,7 @@ struct Keys {
     // captured plans per (slot, circuit): each slot replays its own copy, so
     // batches of several server slots never share a plan's buffers
     std::map<std::pair<int, PlanKey>, std::unique_ptr<GraphPlan>> plans;  // destroyed before the keys they read
+    unsigned long long plan_clock = 0;
     int Ek() const { return lmax + 1 + C->P.K; }
 };
 
@@ -1972,6 +1974,8 @@ static std::vector<DCt> eval_spec(Ctx &C, const Keys &K, const Spec &s, const DC
 // launches the same kernels in the same order: outputs are bit-identical.
 using Circuit = std::function<std::vector<DCt>(const std::vector<DCt> &)>;
 
+constexpr int kPlansPerSlot = 16;
+
 static std::vector<DCt> run_circuit(Ctx &C, Keys &K, const PlanKey &key,
                                     const std::vector<std::vector<const DCt *>> &in, const Circuit &circuit) {
     auto fill = [&](std::vector<DCt> &X) {
@@ -1996,6 +2000,18 @@ static std::vector<DCt> run_circuit(Ctx &C, Keys &K, const PlanKey &key,
         return outs;
     }
     if (it == K.plans.end()) {
+        // at most kPlansPerSlot captured plans per slot: each holds its
+        // temporaries until destroyed, so a new batch size or level past the
+        // cap evicts the slot's least recently replayed plan (this slot's
+        // plans only run on this thread; the destructor waits for the stream)
+        int mine = 0;
+        auto lru = K.plans.end();
+        for (auto p = K.plans.begin(); p != K.plans.end(); ++p)
+            if (p->first.first == C.slot) {
+                mine++;
+                if (lru == K.plans.end() || p->second->last_use < lru->second->last_use) lru = p;
+            }
+        if (mine >= kPlansPerSlot) K.plans.erase(lru);
         auto plan = std::make_unique<GraphPlan>();
         plan->C = &C;
         plan->stream = C.stream;
@@ -2018,6 +2034,7 @@ static std::vector<DCt> run_circuit(Ctx &C, Keys &K, const PlanKey &key,
         it = K.plans.emplace(std::make_pair(C.slot, key), std::move(plan)).first;
     }
     GraphPlan &pl = *it->second;
+    pl.last_use = ++K.plan_clock;
     fill(pl.in);
     HIPCHK(hipGraphLaunch(pl.exec, C.stream));
     std::vector<DCt> outs;

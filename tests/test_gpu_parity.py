@@ -223,6 +223,27 @@ def test_rank8_graph_replays_equal_eager(p12):
         p12.ctx.rank(p12.gkeys, cts[rep], N, cmp)
 
 
+def test_graph_plan_cache_evicts_and_stays_exact(p12):
+    """Captured plans are cached per (slot, circuit, batch size) and each keeps
+    its temporaries; past 16 plans on a slot the least recently replayed one
+    is destroyed.  Batches of 1..20 queries, three passes (eager, captured with
+    evictions from the 17th size on, then re-captured after eviction): every
+    result equals the same query ranked alone."""
+    N, cmp = 8, W.RANK_CMP[8]
+    cts, singles = [], []
+    for seed in range(20):
+        v, _, eseed = W.rank_workload(N, 0.01, 600 + seed)
+        g = p12.ctx.encrypt(p12.gkeys, v, p12.P.L, eseed)
+        cts.append(g)
+        singles.append(p12.ctx.rank(p12.gkeys, g, N, cmp).export())
+    for rep in range(3):
+        say(f"[gpu] rank-8 batches of 1..20, pass {rep}")
+        for B in range(1, 21):
+            outs = p12.ctx.run_batch(p12.gkeys, "rank", cts[:B], N, cmp)
+            for i, o in enumerate(outs):
+                assert np.array_equal(o.export(), singles[i]), (rep, B, i)
+
+
 @pytest.mark.parametrize("name", ["T10", "P12", "P16", "P17"])
 def test_ntt_tile_variants_bit_identical(ckr, name):
     """Every NTT tile variant the autotuner may pick computes the same transform."""
