@@ -19,13 +19,10 @@ def _powers(x, m):
 def _extrema(err, xs):
     """indices of the largest |err| on each maximal run of constant sign"""
     s = np.sign(err)
-    idx, start = [], 0
-    for j in range(1, len(xs) + 1):
-        if j == len(xs) or s[j] != s[start]:
-            seg = np.arange(start, j)
-            idx.append(seg[np.argmax(np.abs(err[seg]))])
-            start = j
-    return np.array(idx)
+    cuts = np.flatnonzero(s[1:] != s[:-1]) + 1
+    starts = np.concatenate([[0], cuts])
+    ends = np.concatenate([cuts, [len(xs)]])
+    return np.array([a + int(np.argmax(np.abs(err[a:b]))) for a, b in zip(starts, ends)])
 
 
 def minimax_odd_sign(a, b, deg=7, grid=400001, iters=100):
