@@ -55,6 +55,33 @@ __device__ __forceinline__ double red_any(double x, double q, double qinv) {
     return r >= q ? r - q : r;
 }
 
+// one 64-bit value through a DPP quad permutation (CTRL: the quad_perm selector)
+template <int CTRL>
+__device__ __forceinline__ double qperm(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// 4 x 4 transpose inside each quad of lanes (lane l's x[j] <- lane j's x[l]):
+// swap the off-diagonal 2 x 2 blocks across lanes l ^ 2, then the
+// off-diagonal entries of each block across lanes l ^ 1
+__device__ __forceinline__ void quad_transpose(double *x) {
+    const int l = threadIdx.x & 3;
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+        const double recv = qperm<0x4E>((l & 2) ? x[j] : x[j + 2]);  // quad_perm [2,3,0,1]
+        if (l & 2) x[j] = recv;
+        else x[j + 2] = recv;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j += 2) {
+        const double recv = qperm<0xB1>((l & 1) ? x[j] : x[j + 1]);  // quad_perm [1,0,3,2]
+        if (l & 1) x[j] = recv;
+        else x[j + 1] = recv;
+    }
+}
+
 // Evaluation-domain automorphism sigma_g: position i holds a(psi^{2 brev(i) + 1}),
 // and sigma_g(a) at i is a at the position of exponent (2 brev(i) + 1) g.  The
 // map keeps aligned blocks of 2^k positions together (for every k), so
@@ -147,6 +174,11 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
         }
     };
     double x[E];
+    // A forward row pass of 256 points, 4 per thread, one row per wave, ends
+    // its third round holding 16 h + 4 k + l in lane 4 h + l, register k, and
+    // starts its fourth holding it in lane 4 h + k, register l: a transpose
+    // inside each quad of lanes, done with DPP moves instead of LDS.
+    constexpr bool QUADX = !COLPASS && !INV && LOGS == 8 && LOGE == 2 && TPC % 64 == 0;
 
 #pragma unroll
     for (int rho = 0; rho < NR; rho++) {
@@ -185,7 +217,7 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
 #pragma unroll
                 for (int k = 0; k < E; k++) x[k] = lds[lidx(cl, rbase | (k << w))];
             }
-        } else {
+        } else if (!(QUADX && rho == NR - 1)) {
 #pragma unroll
             for (int k = 0; k < E; k++) x[k] = lds[lidx(cl, rbase | (k << w))];
         }
@@ -259,6 +291,8 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
                     emit(k, (u32)(c0 * S + i), lds[lidx(i / S, i % S)]);
                 }
             }
+        } else if (QUADX && rho == NR - 2) {
+            quad_transpose(x);
         } else {
             __syncthreads();
 #pragma unroll
