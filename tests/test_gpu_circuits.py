@@ -131,6 +131,31 @@ def test_argmin128_full_size_matches_golden(p17o):
     assert abs(ctx.decrypt(keys, val, 1)[0] - v.min()) <= tol
 
 
+def test_argmin128_hundred_seeds_one_hot_and_value_within_bound(p17o):
+    """Configuration 3 over its seeds 0..99 (tied workloads, one key), in
+    batches of 4: every one-hot rounds to the first minimum, and every value
+    lies within its derived bound (reading of Algorithm Order Statistic's
+    value, tests/value_bound.py)."""
+    ctx, ps = p17o
+    N = 128
+    cmp, ind = W.ARGMIN_CMP[N]
+    import paper_2412_15126_amd as ckr
+    level = ckr.argmin_depth(cmp, ind)
+    keys = ctx.keygen(W.tied_workload(N, 0)[1], level, [N], what=2)
+    qs = [W.tied_workload(N, s) for s in range(100)]
+    worst = 0.0
+    for b0 in range(0, 100, 4):
+        part = qs[b0:b0 + 4]
+        say(f"[gpu] P17O argmin-128 seeds {b0}..{b0 + 3}")
+        outs = ctx.run_batch(keys, "argmin", [ctx.encrypt(keys, v, level, e) for v, _, e in part], N, cmp, ind)
+        for (v, _, _), (oh, val) in zip(part, outs):
+            assert np.array_equal(np.round(ctx.decrypt(keys, oh, N)), np.eye(N)[np.argmin(v)])
+            err = abs(ctx.decrypt(keys, val, 1)[0] - v.min())
+            assert err <= VB.tolerance(v, 1, 1, cmp, ind, True, 17), (b0, err)
+            worst = max(worst, err)
+    say(f"[gpu] argmin-128, 100 seeds: max |value - min| {worst:.2e}")
+
+
 def test_argmin128_chebyshev_full_size_matches_golden(p17):
     """The paper's setting for the minimum: Chebyshev comparator and
     indicator of degree 2^11 - 1 (12 levels each), tie-corrected, N = 128."""

@@ -148,6 +148,16 @@ def test_rank128_minimax_four_stages_full_size(ora, full):
     errs = [np.max(np.abs(ctx.decrypt(gk, o, N) - (np.argsort(np.argsort(v)) + 1))) for (v, _), o in zip(qs, outs)]
     say(f"[gpu] rank-128 minimax: max error {max(errs):.3f}")
     assert max(errs) < 0.45
+    # three more queries of the batch against the oracle, bit for bit
+    for i in (1, 2, 3):
+        say(f"[gpu] P16 rank-128 minimax oracle, query {i}")
+        ro = ora.rank(ok, ora.encrypt(ok, qs[i][0], level, qs[i][1]), N, *cmp).export()
+        assert np.array_equal(ro, outs[i].export()), i
+    # the CKKS error: decoded ranks against the noiseless slot-level shadow
+    from oracle import shadow as S
+    ckks = max(np.max(np.abs(ctx.decrypt(gk, o, N) - S.rank(v, N, 1 << 15, cmp)[0][:N])) for (v, _), o in zip(qs, outs))
+    say(f"[gpu] rank-128 minimax: max |decoded - shadow| over 32 queries {ckks:.2e}")
+    assert ckks < 0.01    # well inside the 0.5 an exact rank allows
 
 
 def ctx_rank_depth(cmp):
@@ -175,3 +185,29 @@ def test_rank100_padded_full_size_bit_exact(ora):
     ro = ora.rank(ok, ora.encrypt(ok, v, level, eseed), N, *cmp)
     assert np.array_equal(ro.export(), rg.export())
     assert np.array_equal(np.round(ctx.decrypt(gk, rg, N)), np.argsort(np.argsort(v)) + 1)
+
+
+@pytest.mark.parametrize("cmp,level", [((4, 1), 17), ((0, 0, 0, 4), 14)])
+def test_rank128_hundred_seeds_exact_with_ckks_error(full, cmp, level):
+    """Configuration 2 over its seeds 0..99 (one key, each seed's values and
+    encryption seed), in captured batches of 32: every rank exact, and the
+    CKKS error, max |decoded - noiseless slot-level shadow|, reported and well
+    inside the half rank an exact rank allows.  g^4 f (the configuration's
+    comparator) at level 17 and the four minimax stages at level 14."""
+    from oracle import shadow as S
+    ctx = full["ctx"]
+    kseed = W.rank_workload(N, 2.0 ** -10, 0)[1]
+    gk = full["gkeys"] if level == LEVEL else ctx.keygen(kseed, level, [N])
+    qs = [W.rank_workload(N, 2.0 ** -10, s) for s in range(100)]
+    worst_rank, worst_ckks = 0.0, 0.0
+    for b0 in range(0, 100, 32):
+        part = qs[b0:b0 + 32]
+        say(f"[gpu] P16 rank-128 {cmp} seeds {b0}..{b0 + len(part) - 1}")
+        outs = ctx.run_batch(gk, "rank", [ctx.encrypt(gk, v, level, e) for v, _, e in part], N, cmp)
+        for (v, _, _), o in zip(part, outs):
+            d = ctx.decrypt(gk, o, N)
+            worst_rank = max(worst_rank, float(np.max(np.abs(d - (np.argsort(np.argsort(v)) + 1)))))
+            worst_ckks = max(worst_ckks, float(np.max(np.abs(d - S.rank(v, N, 1 << 15, cmp)[0][:N]))))
+    say(f"[gpu] rank-128 {cmp}, 100 seeds: max rank error {worst_rank:.3f}, max |decoded - shadow| {worst_ckks:.2e}")
+    assert worst_rank < 0.5
+    assert worst_ckks < 0.01
