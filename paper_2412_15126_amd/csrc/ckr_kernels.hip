@@ -115,7 +115,8 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
                                           double qinv, const double *__restrict__ twq,
                                           const double2 *__restrict__ twlast,
                                           double *lds, Emit &&emit, u32 gal = 0, double cq = 0.0,
-                                          const double2 *twrow = nullptr) {
+                                          const double2 *twrow = nullptr, const u64 *din2 = nullptr,
+                                          double2 c2 = double2{0.0, 0.0}) {
     constexpr int S = 1 << LOGS, E = 1 << LOGE, TPC = S / E, NT = C * TPC;
     constexpr int NR = (LOGS + LOGE - 1) / LOGE;
     constexpr int SP = S + (S >> 4) + 1;
@@ -189,12 +190,15 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
         // ---- load
         if (rho == 0) {
             if (PRO) {
-                // the input limb's residues mod cq, taken in (-cq/2, cq/2) when cq > 0
+                // the input limb's residues mod cq, taken in (-cq/2, cq/2) when cq > 0,
+                // plus din2 * c2 when din2 is set
 #pragma unroll
                 for (int k = 0; k < E; k++) {
                     double v = u2d(din[gaddr(rbase | (k << w))]);
                     if (v > 0.5 * cq) v -= cq;
                     x[k] = red_any(v, q, qinv);
+                    if (din2)
+                        x[k] = red1(x[k] + red1(mm_lazy(u2d(din2[gaddr(rbase | (k << w))]), c2.x, c2.y, q), q), q);
                 }
             } else if (direct) {
                 if (gal > 1) {
@@ -345,19 +349,31 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
         if (fz.add2 && (fz.add2_mask >> pk & 1))
             padd2 = fz.add2 + pb * fz.add2_stride + pk * fz.add2_off + (size_t)t * n;
         const double ec = fz.c.v[t], ecq = fz.c.vq[t];
+        const double pc = fz.c2.v[t], pcq = fz.c2.vq[t];
+        const bool pre = fz.pre;
         const u32 ag = fz.add_gal;
         pass_core<LOGS, LOGE, C, COLPASS, INV, false>(din, c0, logn, mod, q, qinv, twq, twlast, lds,
                                                       [&](int, u32 pos, double y) {
-            double r = red1(mm_lazy(u2d(px[pos]) - y + q, ec, ecq, q), q);
-            if (padd) r = red1(r + u2d(padd[ag > 1 ? gal_src(pos, logn, ag) : pos]), q);
+            double r;
+            if (pre) {
+                // (x * c2 + add - y) * c
+                double xv = red1(mm_lazy(u2d(px[pos]), pc, pcq, q), q);
+                if (padd) xv = red1(xv + u2d(padd[ag > 1 ? gal_src(pos, logn, ag) : pos]), q);
+                r = red1(mm_lazy(xv - y + q, ec, ecq, q), q);
+            } else {
+                r = red1(mm_lazy(u2d(px[pos]) - y + q, ec, ecq, q), q);
+                if (padd) r = red1(r + u2d(padd[ag > 1 ? gal_src(pos, logn, ag) : pos]), q);
+            }
             if (padd2) r = red1(r + u2d(padd2[pos]), q);
             pout[pos] = d2u(r);
         });
     } else if constexpr (PRO) {
+        const u64 *src2 = fz.src2 ? fz.src2 + (size_t)p * fz.src2_stride + (size_t)t * n : nullptr;
         pass_core<LOGS, LOGE, C, COLPASS, INV, true>(fz.src + (size_t)p * fz.src_stride, c0, logn, mod, q, qinv,
                                                      twq, twlast, lds,
                                                      [&](int, u32 pos, double y) { data[pos] = d2u(y); }, 0,
-                                                     fz.pro_q);
+                                                     fz.pro_q, nullptr, src2,
+                                                     make_double2(fz.c2.v[t], fz.c2.vq[t]));
     } else {
         pass_core<LOGS, LOGE, C, COLPASS, INV, false>(din, c0, logn, mod, q, qinv, twq, twlast, lds,
                                                       [&](int, u32 pos, double y) { data[pos] = d2u(y); }, g);

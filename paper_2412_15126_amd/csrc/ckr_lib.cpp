@@ -665,6 +665,7 @@ static void ntt_fused(Ctx &C, u64 *base, int limbs, int polys, size_t stride, Li
         NttFuse g = f;
         const size_t b0 = (size_t)(p0 >> 1);  // first batch entry of the chunk
         if (g.pro) g.src = f.src + (size_t)p0 * f.src_stride;
+        if (g.src2) g.src2 = f.src2 + (size_t)p0 * f.src2_stride;
         if (g.epi) {
             g.out = f.out + b0 * f.out_stride;
             g.x = f.x + b0 * f.x_stride;
@@ -672,7 +673,7 @@ static void ntt_fused(Ctx &C, u64 *base, int limbs, int polys, size_t stride, Li
             if (g.add2) g.add2 = f.add2 + b0 * f.add2_stride;
         }
         const double all = limb * limbs * np;
-        const double b0b = g.pro ? limb * np + all : 2 * all;
+        const double b0b = g.pro ? limb * np + all + (g.src2 ? all : 0) : 2 * all;
         const double b1b = g.epi ? 3 * all + (g.add ? all * __builtin_popcount(g.add_mask) / 2 : 0) +
                                        (g.add2 ? all * __builtin_popcount(g.add2_mask) / 2 : 0)
                                  : 2 * all;
@@ -968,20 +969,111 @@ static DCt ev_rescale(Ctx &C, const DCt &a) {
 
 // c * a brought to level `target`: drop to target+1 limbs, multiply by
 // round(c * D_target * q_{target+1} / D_level), rescale by q_{target+1}
+// The product by K rides in the rescale: limb l2 of K a is formed alone and
+// brought to the coefficient domain, and the rescale's fused transform of
+// limbs 0..l2-1 takes (x K - y) q_{l2}^{-1} in its epilogue, the same residues
+// as rescaling the full product.
 static DCt ev_cmul_to(Ctx &C, const DCt &a, double c, int target) {
     if (target < 0 || target >= a.level) throw Error{CKR_E_DEPTH, "cmul_to target"};
     const double v = ((c * C.P.scale[target]) * (double)C.P.mod[target + 1]) / C.P.scale[a.level];
     const i64 K = std::llround(v);
     const int l2 = target + 1;
-    DCt m = ct_new(C, l2, a.B);
-    LimbScalars s;
-    scalars_of(C, K, l2 + 1, plain_map(), s);
-    const size_t n = C.n();
-    timed(C, kElem, 16.0 * n * (l2 + 1) * 2 * a.B, [&] {
-        k_mul_scalar(C.T, m.d(), a.d(), l2 + 1, 2 * a.B, (size_t)(l2 + 1) * n, (size_t)(a.level + 1) * n, plain_map(),
-                     s, C.stream);
+    const size_t n = C.n(), La = (size_t)(a.level + 1) * n;
+    const int P2 = 2 * a.B;
+    // K times limb l2, then its coefficients
+    Buf ml(&C, (size_t)P2 * n);
+    LimbScalars sl;
+    scalars_of(C, K, 1, plain_map(l2), sl);
+    timed(C, kElem, 16.0 * n * P2, [&] {
+        k_mul_scalar(C.T, ml.get(), a.d() + (size_t)l2 * n, 1, P2, n, La, plain_map(l2), sl, C.stream);
     });
-    return ev_rescale(C, m);
+    Buf last(&C, (size_t)P2 * n);
+    ntt(C, last.get(), 1, P2, n, plain_map(l2), true, ml.get(), n);
+    DCt o = ct_new(C, target, a.B);
+    std::vector<u64> inv(l2);
+    for (int i = 0; i < l2; i++) inv[i] = hinv(C.P.mod[l2] % C.P.mod[i], C.P.mod[i]);
+    NttFuse f;
+    f.pro = true;
+    f.pro_q = (double)C.P.mod[l2];
+    f.src = last.get();
+    f.src_stride = n;
+    f.epi = true;
+    f.pre = true;
+    f.out = o.d();
+    f.out_stride = (size_t)2 * l2 * n;
+    f.out_off = (size_t)l2 * n;
+    f.x = a.d();
+    f.x_stride = 2 * La;
+    f.x_off = La;
+    scalars_of_vals(C, inv, f.c);
+    scalars_of(C, K, l2, plain_map(), f.c2);
+    Buf y(&C, (size_t)P2 * l2 * n);
+    ntt_fused(C, y.get(), l2, P2, (size_t)l2 * n, plain_map(), f);
+    return o;
+}
+
+// The relinearisation's ModDown and the rescale after it, in one pass over
+// limbs 0..l-1 (multiplication's tail).  With x the key inner product (eval
+// domain), b = conv the ModDown base conversion (coefficient domain) and d the
+// tensor's (d0, d1), the switched ciphertext is r = (x - NTT(b)) P^{-1} + d,
+// and the rescale gives o_i = (r_i - NTT([v]_{q_i})) q_l^{-1}, v = INTT(r_l)
+// taken in (-q_l/2, q_l/2).  NTT is linear, so
+//   o_i = (x_i P^{-1} + d_i - NTT(b_i P^{-1} + [v]_{q_i})) q_l^{-1}:
+// limb l of r is formed first (the ModDown epilogue on that limb alone) and
+// brought to the coefficient domain; then one fused forward transform of
+// limbs 0..l-1 adds [v]_{q_i} and b_i P^{-1} in its prologue and combines in
+// its epilogue.  Every operation is modular, so o is the same residues as the
+// ModDown followed by the rescale, and the switched ciphertext at level l
+// never reaches HBM.
+static void moddown_rescale(Ctx &C, u64 *conv, const u64 *acc, size_t sacc, int E, int l, int B,
+                            const std::vector<u64> &pinv, const u64 *d, size_t sd, size_t d_off, DCt &o) {
+    const size_t n = C.n();
+    const int P2 = 2 * B;
+    // r_l = (x_l - NTT(b_l)) P^{-1} + d_l, then its coefficients
+    Buf rl(&C, (size_t)P2 * n);
+    NttFuse f1;
+    f1.epi = true;
+    f1.out = rl.get();
+    f1.out_stride = 2 * n;
+    f1.out_off = n;
+    f1.x = acc + (size_t)l * n;
+    f1.x_stride = sacc;
+    f1.x_off = (size_t)E * n;
+    f1.add = d + (size_t)l * n;
+    f1.add_stride = sd;
+    f1.add_off = d_off;
+    f1.add_mask = 3;
+    f1.c.v[0] = (double)pinv[l];  // limb 0 of this one-limb transform is modulus l
+    f1.c.vq[0] = (double)pinv[l] / (double)C.P.mod[l];
+    ntt_fused(C, conv + (size_t)l * n, 1, P2, (size_t)(l + 1) * n, plain_map(l), f1);
+    Buf last(&C, (size_t)P2 * n);
+    ntt(C, last.get(), 1, P2, n, plain_map(l), true, rl.get(), n);
+    // limbs 0..l-1
+    std::vector<u64> qlinv(l), pv(pinv.begin(), pinv.begin() + l);
+    for (int i = 0; i < l; i++) qlinv[i] = hinv(C.P.mod[l] % C.P.mod[i], C.P.mod[i]);
+    NttFuse f;
+    f.pro = true;
+    f.pro_q = (double)C.P.mod[l];
+    f.src = last.get();
+    f.src_stride = n;
+    f.src2 = conv;
+    f.src2_stride = (size_t)(l + 1) * n;
+    f.epi = true;
+    f.pre = true;
+    f.out = o.d();
+    f.out_stride = (size_t)2 * l * n;
+    f.out_off = (size_t)l * n;
+    f.x = acc;
+    f.x_stride = sacc;
+    f.x_off = (size_t)E * n;
+    f.add = d;
+    f.add_stride = sd;
+    f.add_off = d_off;
+    f.add_mask = 3;
+    scalars_of_vals(C, qlinv, f.c);
+    scalars_of_vals(C, pv, f.c2);
+    Buf y(&C, (size_t)P2 * l * n);
+    ntt_fused(C, y.get(), l, P2, (size_t)l * n, plain_map(), f);
 }
 
 // hybrid key switch of d (B polys, eval domain, limbs 0..l, batch stride sd):
@@ -993,7 +1085,7 @@ static DCt ev_cmul_to(Ctx &C, const DCt &a, double c, int target) {
 static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_t sd, int l, int B, u64 *out,
                       size_t so, size_t out_off, const u64 *add, size_t sadd, size_t add_off, int add_mask,
                       const u64 *add2 = nullptr, size_t sadd2 = 0, size_t add2_off = 0, int add2_mask = 0,
-                      u32 gal = 0) {
+                      u32 gal = 0, DCt *rescaled = nullptr) {
     const Params &P = C.P;
     if (l > K.lmax) throw Error{CKR_E_DEPTH, "ciphertext above key level"};
     const size_t n = C.n();
@@ -1054,6 +1146,10 @@ static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_
         for (int k = 0; k < P.K; k++) pp = hmul(pp, P.mod[P.nq + k] % q, q);
         pinv[i] = hinv(pp, q);
     }
+    if (rescaled) {
+        moddown_rescale(C, conv.get(), acc.get(), sacc, E, l, B, pinv, add, sadd, add_off, *rescaled);
+        return;
+    }
     NttFuse f;
     f.epi = true;
     f.out = out;
@@ -1089,10 +1185,11 @@ static DCt ev_mul(Ctx &C, const Keys &K, const DCt &a, const DCt &b) {
     const size_t n = C.n(), L = (size_t)(l + 1) * n;
     Buf d(&C, (size_t)a.B * 3 * L);
     timed(C, kTensor, 56.0 * L * a.B, [&] { k_tensor(C.T, d.get(), a.d(), b.d(), l + 1, a.B, 3 * L, 2 * L, 2 * L, C.stream); });
-    DCt r = ct_new(C, l, a.B);
-    // (d0 + KS_b(d2), d1 + KS_a(d2))
-    keyswitch(C, K, find_key(K, 0), d.get() + 2 * L, 3 * L, l, a.B, r.d(), 2 * L, L, d.get(), 3 * L, L, 3);
-    return ev_rescale(C, r);
+    // (d0 + KS_b(d2), d1 + KS_a(d2)) rescaled, the ModDown and the rescale in one pass
+    DCt o = ct_new(C, l - 1, a.B);
+    keyswitch(C, K, find_key(K, 0), d.get() + 2 * L, 3 * L, l, a.B, nullptr, 0, 0, d.get(), 3 * L, L, 3, nullptr, 0,
+              0, 0, 0, &o);
+    return o;
 }
 
 static u32 galois_left(const Ctx &C, i64 k) {

@@ -86,6 +86,13 @@ struct NttFuse {
     int add2_mask = 0;
     LimbScalars c;
     double pro_q = 0.0;  // prologue: when > 0, the input limb's residues mod pro_q are taken in (-pro_q/2, pro_q/2)
+    // fused ModDown + rescale: the prologue adds limb t of src2 (poly p at
+    // src2 + p*src2_stride) times c2[t] to the broadcast limb, and the
+    // epilogue (pre) takes (x*c2[t] + add - y) * c[t] instead of (x - y) * c[t] + add
+    const u64 *src2 = nullptr;
+    size_t src2_stride = 0;
+    bool pre = false;
+    LimbScalars c2;
 };
 void k_ntt_fused(const DevTables &T, const LimbBatch &b, const NttFuse &f, int pass, hipStream_t s);
 
