@@ -973,8 +973,9 @@ static DCt ev_rescale(Ctx &C, const DCt &a) {
 // brought to the coefficient domain, and the rescale's fused transform of
 // limbs 0..l2-1 takes (x K - y) q_{l2}^{-1} in its epilogue, the same residues
 // as rescaling the full product.
-static DCt ev_cmul_to(Ctx &C, const DCt &a, double c, int target) {
+static DCt ev_cmul_to(Ctx &C, const DCt &a, double c, int target, const DCt *plus = nullptr) {
     if (target < 0 || target >= a.level) throw Error{CKR_E_DEPTH, "cmul_to target"};
+    if (plus && (plus->level != target || plus->B != a.B)) throw Error{CKR_E_INVALID, "cmul_to addend"};
     const double v = ((c * C.P.scale[target]) * (double)C.P.mod[target + 1]) / C.P.scale[a.level];
     const i64 K = std::llround(v);
     const int l2 = target + 1;
@@ -1005,6 +1006,12 @@ static DCt ev_cmul_to(Ctx &C, const DCt &a, double c, int target) {
     f.x = a.d();
     f.x_stride = 2 * La;
     f.x_off = La;
+    if (plus) {  // + plus, after the rescale
+        f.add2 = plus->d();
+        f.add2_stride = (size_t)2 * l2 * n;
+        f.add2_off = (size_t)l2 * n;
+        f.add2_mask = 3;
+    }
     scalars_of_vals(C, inv, f.c);
     scalars_of(C, K, l2, plain_map(), f.c2);
     Buf y(&C, (size_t)P2 * l2 * n);
@@ -1392,10 +1399,10 @@ static DCt poly7(Ctx &C, const Keys &K, const DCt &x, const double a[4]) {
     DCt y = ev_mul(C, K, x, x);
     DCt t = ev_mul(C, K, ev_cmul_to(C, x, a[3], l - 1), y);
     DCt y2 = ev_mul(C, K, y, y);
-    DCt w = ev_add(C, t, ev_cmul_to(C, x, a[2], l - 2), false);
+    DCt w = ev_cmul_to(C, x, a[2], l - 2, &t);              // t + a5 x
     DCt h = ev_mul(C, K, y2, w);
-    DCt s1 = ev_add(C, h, ev_cmul_to(C, t, a[1] / a[3], l - 3), false);
-    return ev_add(C, s1, ev_cmul_to(C, x, a[0], l - 3), false);
+    DCt s1 = ev_cmul_to(C, t, a[1] / a[3], l - 3, &h);      // h + (a3/a7) t
+    return ev_cmul_to(C, x, a[0], l - 3, &s1);              // + a1 x
 }
 
 // ------------------------------------------------------------------------
