@@ -2162,9 +2162,20 @@ static std::vector<std::vector<DCt>> run_groups(Ctx &C, Keys &K, const std::vect
         key.push_back(GroupKey{specs[g], level, (int)in[g].size()});
     }
     Circuit f = [&](const std::vector<DCt> &X) {
+        // the groups are independent circuits: each runs as a branch on a side
+        // stream (their own replication branches then run inline: branches do
+        // not nest), joined before the outputs are used
+        std::vector<std::vector<DCt>> per(specs.size());
+        if (specs.size() > 1) {
+            Branches br(C);
+            for (size_t g = 0; g < specs.size(); g++) br.run([&, g] { per[g] = eval_spec(C, K, specs[g], X[g]); });
+            br.join();
+        } else {
+            per[0] = eval_spec(C, K, specs[0], X[0]);
+        }
         std::vector<DCt> outs;
-        for (size_t g = 0; g < specs.size(); g++)
-            for (DCt &o : eval_spec(C, K, specs[g], X[g])) outs.push_back(std::move(o));
+        for (auto &v : per)
+            for (DCt &o : v) outs.push_back(std::move(o));
         return outs;
     };
     std::vector<DCt> flat = run_circuit(C, K, key, in, f);
