@@ -84,6 +84,12 @@ class Pool {
         cap_free_.clear();
     }
     std::vector<std::pair<void *, size_t>> end_capture() {
+        std::lock_guard<std::recursive_mutex> g(pmu_);
+        // every block the capture handed out and got back is the plan's,
+        // whichever free list it sits on
+        std::vector<const void *> streams;
+        for (auto &st : sfree_) streams.push_back(st.first);
+        for (const void *st : streams) take_captured_locked(st);
         capturing_ = false;
         std::vector<std::pair<void *, size_t>> owned;
         for (auto &kv : cap_free_)
@@ -135,6 +141,29 @@ class Pool {
                     else sfree_[main][kv.first].push_back(p);
                 }
             sfree_.erase(sides[i]);
+        }
+        // Blocks of a capture freed on the joining stream while the branches
+        // were open belong to the capture as well: everything captured after
+        // the join is ordered after it, so they go back to the capture's free
+        // list.  Left in the stream's list they would outlive end_capture()
+        // and be handed to other work while the graph's replays still use them.
+        if (capturing_) take_captured_locked(main);
+    }
+    // capture-owned blocks of `stream`'s free list -> cap_free_
+    void take_captured_locked(const void *stream) {
+        auto st = sfree_.find(stream);
+        if (st == sfree_.end()) return;
+        for (auto &kv : st->second) {
+            auto &v = kv.second;
+            for (size_t i = 0; i < v.size();) {
+                if (cap_set_.count(v[i])) {
+                    cap_free_[kv.first].push_back(v[i]);
+                    v[i] = v.back();
+                    v.pop_back();
+                } else {
+                    i++;
+                }
+            }
         }
     }
     void flush(const void *stream) {
@@ -1396,9 +1425,20 @@ static DCt poly7(Ctx &C, const Keys &K, const DCt &x, const double a[4]) {
     const int l = x.level;
     if (l < 3) throw Error{CKR_E_DEPTH, "poly7 needs three levels"};
     if (a[3] == 0.0) throw Error{CKR_E_INVALID, "poly7 needs a degree-7 term"};
-    DCt y = ev_mul(C, K, x, x);
-    DCt t = ev_mul(C, K, ev_cmul_to(C, x, a[3], l - 1), y);
-    DCt y2 = ev_mul(C, K, y, y);
+    // x^2 runs beside a7 x, then y^2 beside (a7 x) y: two branches each
+    DCt y, c3, t, y2;
+    {
+        Branches br(C);
+        br.run([&] { c3 = ev_cmul_to(C, x, a[3], l - 1); });
+        y = ev_mul(C, K, x, x);
+        br.join();
+    }
+    {
+        Branches br(C);
+        br.run([&] { y2 = ev_mul(C, K, y, y); });
+        t = ev_mul(C, K, c3, y);
+        br.join();
+    }
     DCt w = ev_cmul_to(C, x, a[2], l - 2, &t);              // t + a5 x
     DCt h = ev_mul(C, K, y2, w);
     DCt s1 = ev_cmul_to(C, t, a[1] / a[3], l - 3, &h);      // h + (a3/a7) t
