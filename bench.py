@@ -312,6 +312,11 @@ def circuit_bench(args):
                             desc="rank of N=128 (gap 2^-10) at n=2^16 (24 + 7 primes, dnum=3) with the Chebyshev "
                                  "comparator of degree 2^11 - 1 (12 levels, the paper's setting for rank), encrypted "
                                  "at level 14"),
+        "rank8": dict(pset="P12", N=8, q=dict(kind="rank"), ci=(W.RANK_CMP[8], None), what=1, level="depth",
+                      B=100, gap=0.01, seed0=0,
+                      desc="rank of N=8 (gap 0.01, seeds 0..99 as one batch) at n=2^12 (toy ring: q0 44-bit + 11 "
+                           "primes near 2^36, scale 2^36), comparator g^2 f (the degree-7 polynomial composed 3 "
+                           "times), encrypted at level 11"),
         "rank128mm": dict(pset="P16", N=128, q=dict(kind="rank"), ci=((0, 0, 0, 4), None), what=1,
                           level="depth", B=32,
                           desc="rank of N=128 (gap 2^-10) at n=2^16 (24 + 7 primes, dnum=3) with four stages of the "
@@ -377,8 +382,9 @@ def circuit_bench(args):
         if spec.get("q", {}).get("kind") == "div":
             v, _, eseed = W.tripled_workload(N, 2000 + i, triples=4)
         else:
-            gap = W.MULTI_GAP.get(N, 2.0 ** -10) if multi else 2.0 ** -10
-            v, _, eseed = W.tied_workload(N, 2000 + i) if tie else W.rank_workload(N, gap, 2000 + i)
+            gap = W.MULTI_GAP.get(N, 2.0 ** -10) if multi else spec.get("gap", 2.0 ** -10)
+            seed = spec.get("seed0", 2000) + i
+            v, _, eseed = W.tied_workload(N, seed) if tie else W.rank_workload(N, gap, seed)
         vals.append(v)
         if multi:
             queries.append([ctx.encrypt(keys, v[j * b:(j + 1) * b], level, bytes([j]) + eseed[1:])
@@ -590,9 +596,9 @@ def main():
     ap.add_argument("--serve", action="store_true", help="served mix with Poisson arrivals instead of the batch run")
     ap.add_argument("--mixed", action="store_true", help="64 mixed rank/argmin queries in one launch instead")
     ap.add_argument("--workload", default="rank128",
-                    choices=["rank128", "argmin128", "argmax128", "sort128", "rank512", "sort512", "rank128cheb",
-                             "argmin128cheb", "sort128col", "kth64div", "median128", "rank128mm", "rank2048",
-                             "rank16384", "sort1024"],
+                    choices=["rank128", "rank8", "argmin128", "argmax128", "sort128", "rank512", "sort512",
+                             "rank128cheb", "argmin128cheb", "sort128col", "kth64div", "median128", "rank128mm",
+                             "rank2048", "rank16384", "sort1024"],
                     help="circuit to time (rank128: the headline metric)")
     ap.add_argument("--cheb-sweep", action="store_true",
                     help="rank-128 runtime and error against the Chebyshev comparison depth 6..14")
