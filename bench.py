@@ -716,7 +716,8 @@ def main():
         out = step()
     ctx.synchronize()
     # correctness of what is timed: decrypted ranks are exact
-    errs = [np.max(np.abs(ctx.decrypt(keys, o, N) - (np.argsort(np.argsort(v)) + 1))) for o, v in zip(out, vals)]
+    decs = [ctx.decrypt(keys, o, N) for o in out]
+    errs = [np.max(np.abs(d - (np.argsort(np.argsort(v)) + 1))) for d, v in zip(decs, vals)]
     exact = bool(max(errs) < 0.5)
     log(f"[bench] warmup done, ranks exact: {exact}")
 
@@ -810,6 +811,14 @@ def main():
         _, threads = host_cores()
         log(f"[bench] cpu baseline with {threads} threads and with 1")
         res["cpu_baseline"] = cpu_baseline(pset, N, cmp, level, threads)
+        # the timed batch's decoded ranks against the noiseless slot-level
+        # shadow of the same circuit: the CKKS error, as a number
+        from oracle import shadow as S
+        slots = 1 << (pset["logn"] - 1)
+        ck = max(float(np.max(np.abs(d - S.rank(v, N, slots, cmp)[0][:N]))) for d, v in zip(decs, vals))
+        res["cpu_baseline"]["ckks_error_of_timed_batch"] = {
+            "max_abs_decoded_minus_shadow": round(ck, 6), "queries": len(vals),
+            "what": "decoded GPU ranks of the timed batch against the oracle's noiseless slot-level shadow"}
     if rank == 0:
         print(json.dumps(res), flush=True)
 
