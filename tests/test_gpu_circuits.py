@@ -132,7 +132,7 @@ def test_argmin128_full_size_matches_golden(p17o):
 
 
 def test_argmin128_hundred_seeds_one_hot_and_value_within_bound(p17o):
-    """Configuration 3 over its seeds 0..99 (tied workloads, one key), in
+    """Tie-corrected argmin of N = 128 over seeds 0..99 (tied workloads, one key), in
     batches of 4: every one-hot rounds to the first minimum, and every value
     lies within its derived bound (reading of Algorithm Order Statistic's
     value, tests/value_bound.py)."""

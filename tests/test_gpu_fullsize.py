@@ -189,11 +189,11 @@ def test_rank100_padded_full_size_bit_exact(ora):
 
 @pytest.mark.parametrize("cmp,level", [((4, 1), 17), ((0, 0, 0, 4), 14)])
 def test_rank128_hundred_seeds_exact_with_ckks_error(full, cmp, level):
-    """Configuration 2 over its seeds 0..99 (one key, each seed's values and
+    """Rank of N = 128 (gap 2^-10) over seeds 0..99 (one key, each seed's values and
     encryption seed), in captured batches of 32: every rank exact, and the
     CKKS error, max |decoded - noiseless slot-level shadow|, reported and well
-    inside the half rank an exact rank allows.  g^4 f (the configuration's
-    comparator) at level 17 and the four minimax stages at level 14."""
+    inside the half rank an exact rank allows.  g^4 f (five compositions) at
+    level 17 and the four minimax stages at level 14."""
     from oracle import shadow as S
     ctx = full["ctx"]
     kseed = W.rank_workload(N, 2.0 ** -10, 0)[1]

@@ -184,7 +184,7 @@ def test_rank8_batch_equals_single(p12):
 
 
 def test_rank8_hundred_seeds_batched_bit_exact(ora, p12):
-    """Configuration 1 over its seeds 0..99: one batch of 100 rank-8 queries
+    """Rank of N = 8 (gap 0.01) over seeds 0..99: one batch of 100 rank-8 queries
     (one graph-captured circuit after the eager first call) against the
     oracle's rank of each query alone, bit for bit, and exact ranks."""
     N, cmp = 8, W.RANK_CMP[8]
