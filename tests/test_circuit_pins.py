@@ -567,7 +567,7 @@ def test_shadow_order_range_reduces_to_order_statistic(N):
 
 @pytest.mark.parametrize("N", [8, 128])
 def test_shadow_median_with_composites(N):
-    """Median of an even N (section 4) with the configured composites: the
+    """Median of an even N (section 4) with the tabled composites: the
     window [N/2, N/2 + 1] selects both middle elements, the value is their
     mean, distinct and tied inputs."""
     gap = 0.01 if N == 8 else 2.0 ** -10

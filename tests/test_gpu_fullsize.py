@@ -78,9 +78,10 @@ def test_rank128_batch_equals_single_full_size(full):
 
 
 def test_rank128_four_compositions_is_not_enough(full):
-    """The configs' "composed 4 times": the best 4-fold split g^3 f does not
-    rank N = 128 values with gap 2^-10 exactly on the decrypted CKKS output,
-    while the 5-fold g^4 f used by the benchmark does (32 queries each)."""
+    """The degree-7 polynomial composed 4 times as an f/g split: the best one,
+    g^3 f, does not rank N = 128 values with gap 2^-10 exactly on the
+    decrypted CKKS output, while the 5-fold g^4 f does (32 queries each); four
+    minimax stages do (test_rank128_minimax_four_stages_full_size)."""
     ctx, keys = full["ctx"], full["gkeys"]
     vals = [W.rank_workload(N, 2.0 ** -10, 1000 + q)[0] for q in range(32)]
     seeds = [W.rank_workload(N, 2.0 ** -10, 1000 + q)[2] for q in range(32)]
