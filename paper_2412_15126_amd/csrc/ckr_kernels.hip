@@ -350,7 +350,8 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
             padd2 = fz.add2 + pb * fz.add2_stride + pk * fz.add2_off + (size_t)t * n;
         const double ec = fz.c.v[t], ecq = fz.c.vq[t];
         const double pc = fz.c2.v[t], pcq = fz.c2.vq[t];
-        const bool pre = fz.pre;
+        const bool pre = fz.pre, sub2 = fz.add2_sub;
+        const u64 *pxm = fz.xmul ? fz.xmul + (size_t)t * n : nullptr;
         const u32 ag = fz.add_gal;
         pass_core<LOGS, LOGE, C, COLPASS, INV, false>(din, c0, logn, mod, q, qinv, twq, twlast, lds,
                                                       [&](int, u32 pos, double y) {
@@ -361,10 +362,12 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
                 if (padd) xv = red1(xv + u2d(padd[ag > 1 ? gal_src(pos, logn, ag) : pos]), q);
                 r = red1(mm_lazy(xv - y + q, ec, ecq, q), q);
             } else {
-                r = red1(mm_lazy(u2d(px[pos]) - y + q, ec, ecq, q), q);
+                double xv = u2d(px[pos]);
+                if (pxm) xv = pos1(mm_signed(xv, u2d(pxm[pos]), q, qinv), q);  // slot-wise plaintext product
+                r = red1(mm_lazy(xv - y + q, ec, ecq, q), q);
                 if (padd) r = red1(r + u2d(padd[ag > 1 ? gal_src(pos, logn, ag) : pos]), q);
             }
-            if (padd2) r = red1(r + u2d(padd2[pos]), q);
+            if (padd2) r = sub2 ? pos1(r - u2d(padd2[pos]), q) : red1(r + u2d(padd2[pos]), q);
             pout[pos] = d2u(r);
         });
     } else if constexpr (PRO) {

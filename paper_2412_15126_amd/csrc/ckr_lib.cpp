@@ -1002,7 +1002,7 @@ static DCt ev_rescale(Ctx &C, const DCt &a) {
 // brought to the coefficient domain, and the rescale's fused transform of
 // limbs 0..l2-1 takes (x K - y) q_{l2}^{-1} in its epilogue, the same residues
 // as rescaling the full product.
-static DCt ev_cmul_to(Ctx &C, const DCt &a, double c, int target, const DCt *plus = nullptr) {
+static DCt ev_cmul_to(Ctx &C, const DCt &a, double c, int target, const DCt *plus = nullptr, bool minus = false) {
     if (target < 0 || target >= a.level) throw Error{CKR_E_DEPTH, "cmul_to target"};
     if (plus && (plus->level != target || plus->B != a.B)) throw Error{CKR_E_INVALID, "cmul_to addend"};
     const double v = ((c * C.P.scale[target]) * (double)C.P.mod[target + 1]) / C.P.scale[a.level];
@@ -1035,11 +1035,12 @@ static DCt ev_cmul_to(Ctx &C, const DCt &a, double c, int target, const DCt *plu
     f.x = a.d();
     f.x_stride = 2 * La;
     f.x_off = La;
-    if (plus) {  // + plus, after the rescale
+    if (plus) {  // + plus (- plus when minus), after the rescale
         f.add2 = plus->d();
         f.add2_stride = (size_t)2 * l2 * n;
         f.add2_off = (size_t)l2 * n;
         f.add2_mask = 3;
+        f.add2_sub = minus;
     }
     scalars_of_vals(C, inv, f.c);
     scalars_of(C, K, l2, plain_map(), f.c2);
@@ -1335,14 +1336,43 @@ static const Buf &get_plain(Ctx &C, int kind, int N, int level, int arg = 0) {
     return C.plain.emplace(key, std::move(b)).first->second;
 }
 
-// slot-wise product with a plaintext (eval domain), then rescale
+// slot-wise product with a plaintext (eval domain), then rescale.  As for a
+// constant product, only the dropped limb's product is formed ahead (and
+// brought to the coefficient domain); the rescale's fused transform takes
+// (x pt - y) q_l^{-1} in its epilogue: the same residues as rescaling the
+// full product, which is never written.
 static DCt ev_mul_plain(Ctx &C, const DCt &a, const Buf &pt) {
-    const size_t L = (size_t)(a.level + 1) * C.n();
-    DCt m = ct_new(C, a.level, a.B);
-    timed(C, kElem, 8.0 * L * (4 * a.B + 1), [&] {
-        k_mul_pt(C.T, m.d(), a.d(), pt.get(), a.level + 1, 2 * a.B, L, L, plain_map(), false, C.stream);
+    const int l = a.level;
+    if (l < 1) throw Error{CKR_E_DEPTH, "rescale at level 0"};
+    const size_t n = C.n(), L = (size_t)(l + 1) * n;
+    const int P2 = 2 * a.B;
+    Buf ml(&C, (size_t)P2 * n);
+    timed(C, kElem, 8.0 * n * (4 * a.B + 1), [&] {
+        k_mul_pt(C.T, ml.get(), a.d() + (size_t)l * n, pt.get() + (size_t)l * n, 1, P2, n, L, plain_map(l), false,
+                 C.stream);
     });
-    return ev_rescale(C, m);
+    Buf last(&C, (size_t)P2 * n);
+    ntt(C, last.get(), 1, P2, n, plain_map(l), true, ml.get(), n);
+    DCt o = ct_new(C, l - 1, a.B);
+    std::vector<u64> inv(l);
+    for (int i = 0; i < l; i++) inv[i] = hinv(C.P.mod[l] % C.P.mod[i], C.P.mod[i]);
+    NttFuse f;
+    f.pro = true;
+    f.pro_q = (double)C.P.mod[l];
+    f.src = last.get();
+    f.src_stride = n;
+    f.epi = true;
+    f.xmul = pt.get();
+    f.out = o.d();
+    f.out_stride = (size_t)2 * l * n;
+    f.out_off = (size_t)l * n;
+    f.x = a.d();
+    f.x_stride = 2 * L;
+    f.x_off = L;
+    scalars_of_vals(C, inv, f.c);
+    Buf y(&C, (size_t)P2 * l * n);
+    ntt_fused(C, y.get(), l, P2, (size_t)l * n, plain_map(), f);
+    return o;
 }
 
 static DCt ev_add_plain(Ctx &C, const DCt &a, const Buf &pt) {
@@ -1751,8 +1781,7 @@ static DCt cmp_matrix(Ctx &C, const Keys &K, const DCt &V, int N, ckr_sign cmp, 
         VC = repl_c(C, K, T, N);
         br.join();
     }
-    DCt VRa = ev_cmul_to(C, VR, 1.0, VC.level);
-    DCt D = ev_add(C, VRa, VC, true);
+    DCt D = ev_cmul_to(C, VR, 1.0, VC.level, &VC, true);  // VR brought to VC's level, minus VC
     if (VR_out) *VR_out = std::move(VR);
     return cmp_sign(C, K, D, cmp, a);
 }

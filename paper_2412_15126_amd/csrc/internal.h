@@ -93,6 +93,10 @@ struct NttFuse {
     size_t src2_stride = 0;
     bool pre = false;
     LimbScalars c2;
+    // epilogue: x taken slot-wise times the plaintext limb xmul + t*n (the
+    // same for every poly) before the combine; add2 subtracted, not added
+    const u64 *xmul = nullptr;
+    bool add2_sub = false;
 };
 void k_ntt_fused(const DevTables &T, const LimbBatch &b, const NttFuse &f, int pass, hipStream_t s);
 
