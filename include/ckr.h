@@ -433,7 +433,7 @@ ckr_status ckr_autotune(ckr_context *ctx, uint32_t limbs, uint32_t iters, float 
  * ciphertexts sharing the key (all-zero operands; device memory of about
  * batch * (dnum + 2) * (L + 1 + K) limbs is taken from the context pool for
  * the run), `iters` repetitions, and keeps the fastest.  ms, if not NULL,
- * receives 7 average milliseconds [variant].  Every variant computes the same
+ * receives 8 average milliseconds [variant].  Every variant computes the same
  * result bit for bit.  Errors: CKR_E_INVALID for batch 0 or above 4096. */
 ckr_status ckr_autotune_row_ip(ckr_context *ctx, uint32_t batch, uint32_t iters, float *ms);
 /* Run transforms of more than `limbs` limbs in chunks of whole polynomials
@@ -442,7 +442,7 @@ ckr_status ckr_autotune_row_ip(ckr_context *ctx, uint32_t batch, uint32_t iters,
 ckr_status ckr_set_ntt_chunk(ckr_context *ctx, uint32_t limbs);
 /* Force one tile variant (0..3) for a (direction, pass). */
 ckr_status ckr_ntt_variant(ckr_context *ctx, int inverse, int pass, int variant);
-/* Force one tile variant (0..6) of the key switch's fused forward row pass +
+/* Force one tile variant (0..7) of the key switch's fused forward row pass +
  * inner product (rows of 2^8 points; other ring sizes have one tile). */
 ckr_status ckr_row_ip_variant(ckr_context *ctx, int variant);
 

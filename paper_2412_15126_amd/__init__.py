@@ -359,7 +359,7 @@ class Context:
 
     def autotune_row_ip(self, batch, iters=3):
         """Pick the fastest tile of the fused row pass + key-switch inner product; returns ms per variant."""
-        ms = (C.c_float * 7)()
+        ms = (C.c_float * 8)()
         _ok(lib().ckr_autotune_row_ip(self.h, int(batch), int(iters), ms))
         return np.array(ms[:], dtype=np.float64)
 

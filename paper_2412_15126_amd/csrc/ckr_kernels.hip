@@ -16,6 +16,7 @@
 namespace ckr {
 
 #define C52 4503599627370496.0  // 2^52
+#define C53 9007199254740992.0  // 2^53
 
 // ------------------------------------------------------------------------
 // exact modular arithmetic in FP64
@@ -47,12 +48,12 @@ __device__ __forceinline__ double mm_signed(double x, double y, double q, double
 }
 __device__ __forceinline__ double red1(double x, double q) { return x >= q ? x - q : x; }  // [0,2q) -> [0,q)
 __device__ __forceinline__ double pos1(double x, double q) { return x < 0 ? x + q : x; }   // (-q,q) -> [0,q)
-// integer-valued x in (-2^53, 2^53) -> x mod q in [0, q)
+// integer-valued x in (-2^53, 2^53) -> x mod q in [0, q), qinv = fl(1/q).
+// k = rint(x qinv) is within 1/2 + 2/q of x/q, so x - k q is an integer in
+// (-q, q): the FMA forms it exactly and one correction makes it canonical.
 __device__ __forceinline__ double red_any(double x, double q, double qinv) {
-    double k = floor(x * qinv);
-    double r = __fma_rn(-k, q, x);
-    r = r < 0 ? r + q : r;
-    return r >= q ? r - q : r;
+    const double r = __fma_rn(-rint(x * qinv), q, x);
+    return r < 0 ? r + q : r;
 }
 
 // one 64-bit value through a DPP quad permutation (CTRL: the quad_perm selector)
@@ -110,7 +111,8 @@ __device__ __forceinline__ u32 gal_src(u32 i, int logn, u32 g) {
 // stages and hands every final value to emit(k, pos, y), k in [0, E) being
 // the thread's ordinal of that element (the same position for every call
 // from the same thread).
-template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool PRO, bool IN_LOOP = false, class Emit>
+template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool PRO, bool IN_LOOP = false, int NB = 1,
+          class Emit>
 __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, int logn, int mod, double q,
                                           double qinv, const double *__restrict__ twq,
                                           const double2 *__restrict__ twlast,
@@ -123,7 +125,9 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
     constexpr bool FINAL = (INV == COLPASS);
     const double two_q = 2.0 * q;
     const int ncol = 1 << (logn - LOGS);
-    int tid = threadIdx.x;
+    // NB > 1: the workgroup holds NB groups of NT threads, each running this
+    // pass on its own polynomial over the same rows, with its own LDS region
+    int tid = NB > 1 ? (int)(threadIdx.x % NT) : (int)threadIdx.x;
     // Called in a loop (the fused key-switch kernel runs one pass per digit),
     // the compiler would compute every thread-dependent address once, before
     // the loop, and keep them all live across it: 2 waves per SIMD instead of
@@ -138,6 +142,19 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
     // positions within one limb fit 32 bits (n <= 2^17): offsets from a uniform base
     auto gaddr = [&](int r) -> u32 { return COLPASS ? (u32)(r * ncol + c) : (u32)(c * S + r); };
     auto lidx = [&](int cc, int r) -> int { return cc * SP + r + (r >> 4); };
+    // A row pass of one wave per LDS region exchanges data within the wave
+    // only: a wave's LDS operations complete in issue order, so ordering the
+    // compiler's memory accesses is enough (no s_barrier)
+    constexpr bool WAVE_SYNC = IN_LOOP && !COLPASS && NT == 64;
+    auto sync = [] {
+        if constexpr (WAVE_SYNC) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            __syncthreads();
+        }
+    };
 
     // Twiddles come from the w/q table alone (8 bytes each instead of 16);
     // w = rint(w/q * q) is recovered exactly: |(w/q) q - w| <= w 2^-53 < 1/8
@@ -217,7 +234,7 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
                 } else {
                     for (int i = tid; i < C * S; i += NT) lds[lidx(i / S, i % S)] = u2d(tile[i]);
                 }
-                __syncthreads();
+                sync();
 #pragma unroll
                 for (int k = 0; k < E; k++) x[k] = lds[lidx(cl, rbase | (k << w))];
             }
@@ -285,10 +302,10 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
 #pragma unroll
                 for (int k = 0; k < E; k++) emit(k, gaddr(rbase | (k << w)), x[k]);
             } else {
-                __syncthreads();
+                sync();
 #pragma unroll
                 for (int k = 0; k < E; k++) lds[lidx(cl, rbase | (k << w))] = x[k];
-                __syncthreads();
+                sync();
 #pragma unroll
                 for (int k = 0; k < E; k++) {
                     const int i = tid + k * NT;
@@ -298,10 +315,10 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
         } else if (QUADX && rho == NR - 2) {
             quad_transpose(x);
         } else {
-            __syncthreads();
+            sync();
 #pragma unroll
             for (int k = 0; k < E; k++) lds[lidx(cl, rbase | (k << w))] = x[k];
-            __syncthreads();
+            sync();
         }
     }
 }
@@ -387,39 +404,51 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
 // t fused with the inner product against the switching key,
 //   accb[t] = sum_j X_j[t] kb_j[t],  acca[t] = sum_j X_j[t] ka_j[t],
 // X_j[t] = d[t] for the digit that holds limb t, else the row-pass output of
-// ext[j][t] (which has had its column pass).  One workgroup per (batch entry,
-// limb, tile of C rows); the extended limbs never go back to HBM in the
-// evaluation domain.  Workgroups are dealt to the 8 XCDs round-robin, so the
-// workgroup index is decoded as (xcd, then per-XCD sequence): the B batch
-// entries of one (limb, tile) run back to back on one XCD and read that
-// tile's key words from its L2.
-template <int LOGS, int LOGE, int C>
-__global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)), (LOGE == 2 ? 6 : 1))  // 4 elements: 78 VGPRs, no spill
+// ext[j][t] (which has had its column pass).  One workgroup per (slot of NB
+// batch entries, limb, tile of C rows); the extended limbs never go back to
+// HBM in the evaluation domain.  Workgroups are dealt to the 8 XCDs
+// round-robin, so the workgroup index is decoded as (xcd, then per-XCD
+// sequence): the batch slots of one (limb, tile) run back to back on one XCD
+// and read that tile's key words from its L2.  With NB > 1 (one row), the NB
+// waves of a workgroup run NB batch entries over the same row: the row's
+// twiddles and each digit's key words are staged in LDS once for all of them.
+template <int LOGS, int LOGE, int C, int NB>
+__global__ void __launch_bounds__(NB * C * (1 << (LOGS - LOGE)), (LOGE == 2 ? 6 : 1))  // 4 elements: 78 VGPRs
     ntt_row_ip(const IPArgs a, int logn, const double2 *__restrict__ mq, const double *__restrict__ twqtab,
                const double2 *__restrict__ twlast) {
-    constexpr int S = 1 << LOGS, E = 1 << LOGE, NT = C * (S / E);
+    constexpr int S = 1 << LOGS, E = 1 << LOGE, NT = C * (S / E), NALL = NB * NT;
     constexpr int SP = S + (S >> 4) + 1;
-    __shared__ double lds[C * SP];
+    static_assert(NB == 1 || (C == 1 && NT == 64 && LOGS - LOGE >= 3),
+                  "batch-shared workgroups: one row per wave, first round read directly");
+    __shared__ double lds[NB * C * SP];
     __shared__ double2 twr[C * S];  // the rows' forward twiddles {w, w/q}, shared by the digits' passes
+    __shared__ double keyl[NB > 1 ? 2 * C * S : 2];  // NB > 1: the digit's key words kb, ka of the rows
     const size_t n = (size_t)1 << logn;
     const int tiles = (int)(n >> LOGS) / C;
+    const int slots = (a.B + NB - 1) / NB;
     const int wg = blockIdx.x, xcd = wg & 7, seq = wg >> 3;
-    const int gl = seq / a.B, bi = seq - gl * a.B;
+    const int gl = seq / slots, slot = seq - gl * slots;
     const int g = gl * 8 + xcd;
     if (g >= a.E * tiles) return;
+    // wave wv of the workgroup takes batch entry slot * NB + wv; a wave past
+    // the batch end repeats the last entry (every wave must reach the
+    // workgroup barriers) and stores nothing
+    const int wv = NB > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x / NT)) : 0;
+    const bool live = slot * NB + wv < a.B;
+    const int bi = live ? slot * NB + wv : a.B - 1;
     const int t = g / tiles, c0 = (g - t * tiles) * C;
     const int mod = t <= a.level ? t : a.nq + (t - a.level - 1);
     const int kl = t <= a.level ? t : a.lmax_key + 1 + (t - a.level - 1);
     const double q = mq[mod].x, qinv = mq[mod].y;
     const double *twq = twqtab + (size_t)mod * n;
     const int own = (t <= a.level) ? t / a.alpha : -1;  // digit holding limb t, if any
-    const int tid = threadIdx.x;
+    const int tall = threadIdx.x, tid = NB > 1 ? (int)(threadIdx.x % NT) : (int)threadIdx.x;
     if (a.beta > (own >= 0 ? 1 : 0)) {
         // row c0 + cl, stage s (global stage logn - LOGS + s) uses table entry
         // 2^(logn - LOGS + s) + ((c0 + cl) << s) + (r >> (LOGS - s)); staged at
         // cl S + 2^s + (r >> (LOGS - s)), entry 0 of each row unused
         const int g0 = logn - LOGS;
-        for (int i = tid; i < C * S; i += NT) {
+        for (int i = tall; i < C * S; i += NALL) {
             const int cl = i / S, li = i % S;
             if (li == 0) continue;
             const int st = 31 - __clz(li);
@@ -432,16 +461,30 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)), (LOGE == 2 ? 6 : 1))
 #pragma unroll
     for (int k = 0; k < E; k++) sb[k] = sa[k] = 0.0;
     for (int j = 0; j < a.beta; j++) {
-        // this digit's key words, read where the pass hands over its outputs
-        // (held across the pass they would cost 4E registers)
         const u64 *kb = a.key + (((size_t)j * 2 + 0) * a.Ek + kl) * n;
         const u64 *ka = a.key + (((size_t)j * 2 + 1) * a.Ek + kl) * n;
-        // products in (-0.75q, 0.75q) accumulate unreduced: exact while the
+        if constexpr (NB > 1) {
+            __syncthreads();  // every wave is done with the previous digit's key words and row data
+            for (int i = tall; i < C * S; i += NALL) {
+                keyl[i] = u2d(kb[(u32)(c0 * S + i)]);
+                keyl[C * S + i] = u2d(ka[(u32)(c0 * S + i)]);
+            }
+            __syncthreads();
+        }
+        // NB == 1: this digit's key words, read where the pass hands over its
+        // outputs (held across the pass they would cost 4E registers).
+        // Products in (-0.75q, 0.75q) accumulate unreduced: exact while the
         // sums stay below 2^53 in magnitude (the library allows at most 8
         // digits; a reduction every 8 keeps any count safe)
         auto acc = [&](int k, u32 pos, double x) {
-            sb[k] += mm_signed(x, u2d(kb[pos]), q, qinv);
-            sa[k] += mm_signed(x, u2d(ka[pos]), q, qinv);
+            if constexpr (NB > 1) {
+                const int r = (int)(pos - (u32)(c0 * S));
+                sb[k] += mm_signed(x, keyl[r], q, qinv);
+                sa[k] += mm_signed(x, keyl[C * S + r], q, qinv);
+            } else {
+                sb[k] += mm_signed(x, u2d(kb[pos]), q, qinv);
+                sa[k] += mm_signed(x, u2d(ka[pos]), q, qinv);
+            }
         };
         if (j == own) {
             const u64 *xs = a.d + bi * a.sd + (size_t)t * n;
@@ -456,9 +499,10 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)), (LOGE == 2 ? 6 : 1))
 #pragma unroll
             for (int k = 0; k < E; k++) acc(k, (u32)(c0 * S + tid + k * NT), xv[k]);
         } else {
-            __syncthreads();  // the previous digit's last LDS reads are done
-            pass_core<LOGS, LOGE, C, false, false, false, true>(a.ext + bi * a.sext + ((size_t)j * a.E + t) * n, c0,
-                                                                logn, mod, q, qinv, twq, twlast, lds, acc, 0, 0.0, twr);
+            if constexpr (NB == 1) __syncthreads();  // the previous digit's last LDS reads are done
+            pass_core<LOGS, LOGE, C, false, false, false, true, NB>(
+                a.ext + bi * a.sext + ((size_t)j * a.E + t) * n, c0, logn, mod, q, qinv, twq, twlast,
+                lds + wv * (C * SP), acc, 0, 0.0, twr);
         }
         if ((j & 7) == 7) {
 #pragma unroll
@@ -468,6 +512,7 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)), (LOGE == 2 ? 6 : 1))
             }
         }
     }
+    if (!live) return;
     u64 *ob = a.accb + bi * a.sacc + (size_t)t * n, *oa = a.acca + bi * a.sacc + (size_t)t * n;
 #pragma unroll
     for (int k = 0; k < E; k++) {
@@ -477,14 +522,22 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)), (LOGE == 2 ? 6 : 1))
     }
 }
 
-template <int LOGS, int LOGE, int C>
+template <int LOGS, int LOGE, int C, int NB = 1>
 static void launch_row_ip(const DevTables &T, const IPArgs &a, hipStream_t s) {
-    static_assert(C * (1 << (LOGS - LOGE)) <= 1024, "workgroup larger than 1024 threads");
+    static_assert(NB * C * (1 << (LOGS - LOGE)) <= 1024, "workgroup larger than 1024 threads");
     const int tiles = (1 << (T.logn - LOGS)) / C;
     const int groups = a.E * tiles;
-    const unsigned blocks = (unsigned)(((groups + 7) / 8) * 8) * (unsigned)a.B;
-    hipLaunchKernelGGL((ntt_row_ip<LOGS, LOGE, C>), dim3(blocks), dim3(C * (1 << (LOGS - LOGE))), 0, s, a, T.logn,
-                       T.mq, T.twq_fwd, T.tw_last);
+    const unsigned blocks = (unsigned)(((groups + 7) / 8) * 8) * (unsigned)((a.B + NB - 1) / NB);
+    hipLaunchKernelGGL((ntt_row_ip<LOGS, LOGE, C, NB>), dim3(blocks), dim3(NB * C * (1 << (LOGS - LOGE))), 0, s, a,
+                       T.logn, T.mq, T.twq_fwd, T.tw_last);
+}
+
+// batch entries per workgroup of the batch-shared tile: 4 or 2, the larger
+// that leaves at most B/8 idle waves (a ragged last slot), else 1
+static int row_ip_share(int B) {
+    for (int nb = 4; nb > 1; nb >>= 1)
+        if (B >= nb && ((B + nb - 1) / nb * nb - B) * 8 <= B) return nb;
+    return 1;
 }
 
 template <int LOGS, int LOGE, int C, bool COLPASS, bool INV>
@@ -556,7 +609,9 @@ static void run_pass(const DevTables &T, const LimbBatch &b, bool inv, int pass,
 
 // tiles of the fused row pass + inner product, (elements per thread, rows per
 // workgroup) for passes of 2^8 points: 0 (8, 16), 1 (8, 8), 2 (8, 4), 3 (8, 2),
-// 4 (4, 4), 5 (4, 2), 6 (4, 1); smaller passes: one fixed tile
+// 4 (4, 4), 5 (4, 2), 6 (4, 1), 7 (4, 1) with up to 4 batch entries per
+// workgroup sharing the staged twiddles and key words; smaller passes: one
+// fixed tile
 template <int LOGS>
 static void row_ip_variant(const DevTables &T, const IPArgs &a, hipStream_t s, int v) {
     if constexpr (LOGS == 8) {
@@ -567,6 +622,12 @@ static void row_ip_variant(const DevTables &T, const IPArgs &a, hipStream_t s, i
         case 4: launch_row_ip<8, 2, 4>(T, a, s); return;
         case 5: launch_row_ip<8, 2, 2>(T, a, s); return;
         case 6: launch_row_ip<8, 2, 1>(T, a, s); return;
+        case 7:
+            switch (row_ip_share(a.B)) {
+            case 4: launch_row_ip<8, 2, 1, 4>(T, a, s); return;
+            case 2: launch_row_ip<8, 2, 1, 2>(T, a, s); return;
+            default: launch_row_ip<8, 2, 1>(T, a, s); return;
+            }
         default: launch_row_ip<8, 3, 16>(T, a, s); return;
         }
     } else if constexpr (LOGS == 7) {
@@ -689,14 +750,14 @@ __global__ void ew_tensor(u64 *d, const u64 *a, const u64 *bb, int limbs, size_t
     {
         const double x0 = u2d(A0.x), x1 = u2d(A1.x), y0 = u2d(B0.x), y1 = u2d(B1.x);
         r0.x = d2u(pos1(mm_signed(x0, y0, Q.x, Q.y), Q.x));
-        const double m = mm_signed(x0, y1, Q.x, Q.y) + mm_signed(x1, y0, Q.x, Q.y) + 2.0 * Q.x;  // (0.5q, 3.5q)
+        const double m = mm_signed(x0, y1, Q.x, Q.y) + mm_signed(x1, y0, Q.x, Q.y);  // (-1.5q, 1.5q)
         r1.x = d2u(red_any(m, Q.x, Q.y));
         r2.x = d2u(pos1(mm_signed(x1, y1, Q.x, Q.y), Q.x));
     }
     {
         const double x0 = u2d(A0.y), x1 = u2d(A1.y), y0 = u2d(B0.y), y1 = u2d(B1.y);
         r0.y = d2u(pos1(mm_signed(x0, y0, Q.x, Q.y), Q.x));
-        const double m = mm_signed(x0, y1, Q.x, Q.y) + mm_signed(x1, y0, Q.x, Q.y) + 2.0 * Q.x;
+        const double m = mm_signed(x0, y1, Q.x, Q.y) + mm_signed(x1, y0, Q.x, Q.y);
         r1.y = d2u(red_any(m, Q.x, Q.y));
         r2.y = d2u(pos1(mm_signed(x1, y1, Q.x, Q.y), Q.x));
     }
@@ -719,8 +780,8 @@ __global__ void ew_automorph(u64 *out, const u64 *in, int limbs, size_t so, size
 // fast base conversion; grid.x over coefficients, grid.y over the batch,
 // grid.z over groups of `tpg` targets.  y_i = [x_i * hinv_i]_{q_i} once per
 // source, then for each target t: sum_i y_i * hmod[i][t] mod t.  Lazy products
-// are < 2t, so for t < 2^47 the NS-term sum stays exact below 2^52 and is
-// reduced once; larger targets reduce after every term.
+// are < 2t and the sum is reduced only when more terms could leave the exact
+// range of doubles: once at the end for small targets, every 3 terms near 2^50.
 // The conversion constants are the same for every thread of a workgroup: they
 // are read through restrict pointers, which the compiler serves from the
 // scalar cache (no LDS staging, no barrier).
@@ -758,7 +819,7 @@ __global__ void __launch_bounds__(256)
     const double u0 = floor(v0), u1 = floor(v1);  // 0 unless exact
     for (int j = j0; j < j1; j++) {
         const double2 Q = mq[tab.tgt_mod[j]];
-        const double tq = Q.x, two_t = 2.0 * tq;
+        const double tq = Q.x;
         double b0 = tab.post ? tab.post[j] : 0.0, b1 = b0;
         if (exact) {
             // subtract u P: b + [u P]_t in [0, 2t), reduced once
@@ -766,31 +827,32 @@ __global__ void __launch_bounds__(256)
             b0 = red1(b0 + red1(mm_lazy(u0, pm.x, pm.y, tq), tq), tq);
             b1 = red1(b1 + red1(mm_lazy(u1, pm.x, pm.y, tq), tq), tq);
         }
-        double a0, a1;
-        if (tq * (2 * NS) < C52) {
-            a0 = -b0;  // in (-tq, 0]: the sum stays in (-tq, 2 NS tq), which red_any takes
-            a1 = -b1;
+        // the sum starts at -b in (-tq, 0] and gains terms in (0, 2 tq).  From a
+        // start in (-tq, tq), m terms keep it below (2m + 1) tq, exact while
+        // that is at most 2^53: all NS terms for small targets, else 3 at a
+        // time (every modulus is below 2^50 < 2^53 / 7), reduced in between
+        double a0 = -b0, a1 = -b1;
+        if (tq * (2 * NS + 1) <= C53) {
 #pragma unroll
             for (int i = 0; i < NS; i++) {
                 const double2 h = hmod[i * tab.nt + j];
                 a0 += mm_lazy(y0[i], h.x, h.y, tq);
                 a1 += mm_lazy(y1[i], h.x, h.y, tq);
             }
-            a0 = red_any(a0, tq, Q.y);
-            a1 = red_any(a1, tq, Q.y);
         } else {
-            a0 = a1 = 0.0;
 #pragma unroll
             for (int i = 0; i < NS; i++) {
                 const double2 h = hmod[i * tab.nt + j];
                 a0 += mm_lazy(y0[i], h.x, h.y, tq);
-                a0 = a0 >= two_t ? a0 - two_t : a0;
                 a1 += mm_lazy(y1[i], h.x, h.y, tq);
-                a1 = a1 >= two_t ? a1 - two_t : a1;
+                if (i % 3 == 2 && i + 1 < NS) {
+                    a0 = red_any(a0, tq, Q.y);
+                    a1 = red_any(a1, tq, Q.y);
+                }
             }
-            a0 = pos1(red1(a0, tq) - b0, tq);
-            a1 = pos1(red1(a1, tq) - b1, tq);
         }
+        a0 = red_any(a0, tq, Q.y);
+        a1 = red_any(a1, tq, Q.y);
         *(ulonglong2 *)(ob + (size_t)tab.tgt_slot[j] * n + c) = make_ulonglong2(d2u(a0), d2u(a1));
     }
 }

@@ -38,10 +38,10 @@ struct DevTables {
     double *twq_fwd;  // [nmod][n] w/q, w = psi^{brev(i)} (the passes recover w = rint(w/q * q))
     double *twq_inv;  // [nmod][n] w/q, w = psi^{-brev(i)}
     int ntt_variant[2][2] = {{0, 0}, {0, 0}};  // [inverse][pass]: tile variant chosen by the autotuner
-    int row_ip_variant = 2;                      // tile of the fused row pass + inner product
+    int row_ip_variant = 7;                      // tile of the fused row pass + inner product
 };
 constexpr int kNttVariants = 4;
-constexpr int kRowIpVariants = 7;
+constexpr int kRowIpVariants = 8;
 
 // description of a batch of limbs: `polys` groups of `limbs` limbs, group p
 // starting at base + p * poly_stride, limbs n words apart

@@ -77,6 +77,30 @@ def test_rank128_batch_equals_single_full_size(full):
         assert np.array_equal(s, b.export())
 
 
+def test_rank128_batch_shared_row_ip_tiles(full):
+    """The fused key-switch tile that runs up to 4 batch entries per
+    workgroup (sharing the row's twiddles and key words; 2 entries at B = 2
+    and B = 9, 4 at B = 30 and 32, B = 9 and 30 with a ragged last slot)
+    gives the batched rank bit for bit as the tile with one entry per
+    workgroup."""
+    ctx, keys = full["ctx"], full["gkeys"]
+    qs = [W.rank_workload(N, 2.0 ** -10, 400 + i) for i in range(32)]
+    cts = [ctx.encrypt(keys, v, LEVEL, e) for v, _, e in qs]
+    ctx.set_graphs(False)
+    try:
+        for B in (2, 9, 30, 32):
+            outs = {}
+            for var in (6, 7):
+                say(f"[gpu] P16 rank-128 batch of {B}, fused key-switch tile {var}")
+                ctx.row_ip_variant(var)
+                outs[var] = [o.export() for o in ctx.rank_batch(keys, cts[:B], N, W.RANK_CMP[N])]
+            for var in (7,):
+                assert all(np.array_equal(a, b) for a, b in zip(outs[6], outs[var])), (B, var)
+    finally:
+        ctx.row_ip_variant(7)  # the library's default
+        ctx.set_graphs(True)
+
+
 def test_rank128_four_compositions_is_not_enough(full):
     """The degree-7 polynomial composed 4 times as an f/g split: the best one,
     g^3 f, does not rank N = 128 values with gap 2^-10 exactly on the

@@ -312,7 +312,7 @@ def test_row_ip_tile_variants_bit_identical(ckr):
     v = np.random.default_rng(5).uniform(0, 1, 1 << 15)
     cts = [ctx.encrypt(keys, v, lv, bytes([lv] * 32)) for lv in (9, 4)]
     ref = None
-    for var in range(7):
+    for var in range(8):
         say(f"[gpu] row_ip variant {var}")
         ctx.row_ip_variant(var)
         got = [ctx.mul(keys, c, c).export() for c in cts]
@@ -320,7 +320,7 @@ def test_row_ip_tile_variants_bit_identical(ckr):
             ref = got
         assert all(np.array_equal(a, b) for a, b in zip(ref, got)), f"variant {var}"
     ms = ctx.autotune_row_ip(4, 2)
-    assert ms.shape == (7,) and np.all(ms > 0)
+    assert ms.shape == (8,) and np.all(ms > 0)
 
 
 def test_rank8_ntt_chunking_bit_identical(p12):
