@@ -425,7 +425,7 @@ const char *ckr_profile_name(int category);
  * columns per workgroup) of every (direction, pass) on `limbs` limbs (one launch
  * over polynomials of the whole q chain, then the rest), `iters`
  * repetitions, and keeps the fastest for this context.  ms, if not NULL,
- * receives the 2 x 2 x 4 average milliseconds [inverse][pass][variant].
+ * receives the 2 x 2 x 5 average milliseconds [inverse][pass][variant].
  * Every variant computes the same transform bit for bit. */
 ckr_status ckr_autotune(ckr_context *ctx, uint32_t limbs, uint32_t iters, float *ms);
 /* Autotuner of the key switch's fused forward row pass + inner product: times
@@ -440,7 +440,7 @@ ckr_status ckr_autotune_row_ip(ckr_context *ctx, uint32_t batch, uint32_t iters,
  * (0 = never), so each chunk's second pass reads data still in the
  * last-level cache.  Results do not depend on the chunking. */
 ckr_status ckr_set_ntt_chunk(ckr_context *ctx, uint32_t limbs);
-/* Force one tile variant (0..3) for a (direction, pass). */
+/* Force one tile variant (0..4) for a (direction, pass). */
 ckr_status ckr_ntt_variant(ckr_context *ctx, int inverse, int pass, int variant);
 /* Force one tile variant (0..7) of the key switch's fused forward row pass +
  * inner product (rows of 2^8 points; other ring sizes have one tile). */

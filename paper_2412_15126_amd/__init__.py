@@ -353,9 +353,9 @@ class Context:
 
     def autotune(self, limbs, iters=5):
         """Pick the fastest NTT tile per (direction, pass); returns the timing table [inv][pass][variant] in ms."""
-        ms = (C.c_float * 16)()
+        ms = (C.c_float * 20)()
         _ok(lib().ckr_autotune(self.h, limbs, iters, ms))
-        return np.array(ms[:], dtype=np.float64).reshape(2, 2, 4)
+        return np.array(ms[:], dtype=np.float64).reshape(2, 2, 5)
 
     def autotune_row_ip(self, batch, iters=3):
         """Pick the fastest tile of the fused row pass + key-switch inner product; returns ms per variant."""

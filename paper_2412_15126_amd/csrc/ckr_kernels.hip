@@ -145,7 +145,8 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
     // A row pass of one wave per LDS region exchanges data within the wave
     // only: a wave's LDS operations complete in issue order, so ordering the
     // compiler's memory accesses is enough (no s_barrier)
-    constexpr bool WAVE_SYNC = IN_LOOP && !COLPASS && NT == 64;
+    constexpr bool STAGED = (IN_LOOP || NB > 1) && !COLPASS;  // row twiddles staged in LDS (twrow)
+    constexpr bool WAVE_SYNC = STAGED && NT == 64;
     auto sync = [] {
         if constexpr (WAVE_SYNC) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -181,11 +182,12 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
         }
     };
     // twiddle of stage s (global stage g) for local position r.  A row pass run
-    // in a loop (the fused key switch: one pass per digit over the same rows)
-    // reads them from twrow, the rows' {w, w/q} pairs staged in LDS once by the
-    // caller at local index (1 << s) + (r >> (LOGS - s)).
+    // several times over the same rows (the fused key switch: one pass per
+    // digit; NB > 1: one pass per polynomial of the workgroup) reads them from
+    // twrow, the rows' {w, w/q} pairs staged in LDS once by the caller at
+    // local index (1 << s) + (r >> (LOGS - s)).
     auto twid_at = [&](int s, int g, int r) -> double2 {
-        if constexpr (IN_LOOP && !COLPASS) {
+        if constexpr (STAGED) {
             return twrow[cl * S + (1 << s) + (r >> (LOGS - s))];
         } else {
             return twid((1 << g) + (cpart << s) + (r >> (LOGS - s)));
@@ -334,18 +336,29 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
 // LDS exchanges; a round's LOGE-bit window of the local index selects which
 // elements a thread holds.  Values stay lazily reduced: [0, 4q) in the
 // forward direction, [0, 2q) in the inverse, canonical at the end.
-template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool FUSE>
-__global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
-    ntt_pass(u64 *__restrict__ base, size_t poly_stride, int limbs, LimbMap map, int logn,
+//
+// NB > 1 (row passes, C rows per wave): the workgroup's NB waves take NB
+// polynomials of the same limb over the same rows, and the rows' twiddles
+// are staged in LDS once for all of them; a wave past the last polynomial
+// repeats it and stores nothing.
+template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool FUSE, int NB = 1>
+__global__ void __launch_bounds__(NB * C * (1 << (LOGS - LOGE)))
+    ntt_pass(u64 *__restrict__ base, size_t poly_stride, int limbs, int polys, LimbMap map, int logn,
              const double2 *__restrict__ mq, const double *__restrict__ twqtab,
              const double2 *__restrict__ twlast, const NttFuse fz, const u64 *__restrict__ src, size_t src_stride,
              u32 gal) {
-    constexpr int S = 1 << LOGS;
+    constexpr int S = 1 << LOGS, NT = C * (S >> LOGE);
     constexpr int SP = S + (S >> 4) + 1;
-    __shared__ __align__(16) double lds[((C * SP + 1) & ~1) + (COLPASS ? 2 * S : 0)];
+    constexpr int REGION = ((C * SP + 1) & ~1);
+    static_assert(NB == 1 || (!COLPASS && NT == 64), "shared-twiddle row passes: one wave per polynomial");
+    __shared__ __align__(16) double lds[NB * REGION + (COLPASS ? 2 * S : 0)];
+    __shared__ double2 twr[NB > 1 ? C * S : 1];
 
     const int job = blockIdx.y;
-    const int p = job / limbs, t = job - p * limbs;
+    const int slot = job / limbs, t = job - slot * limbs;
+    const int wv = NB > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x / NT)) : 0;
+    const bool live = slot * NB + wv < polys;
+    const int p = live ? slot * NB + wv : polys - 1;
     const int mod = map(t);
     const size_t n = (size_t)1 << logn;
     u64 *data = base + (size_t)p * poly_stride + (size_t)t * n;
@@ -353,6 +366,20 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
     const u64 *din = (FIRST && src) ? src + (size_t)p * src_stride + (size_t)t * n : data;
     const double q = mq[mod].x, qinv = mq[mod].y;
     const double *twq = twqtab + (size_t)mod * n;
+    if constexpr (NB > 1) {
+        // row c0 + cl, stage s: table entry 2^(logn - LOGS + s) + ((c0 + cl) << s) + j,
+        // staged at cl S + 2^s + j (entry 0 of each row unused)
+        const int g0 = logn - LOGS;
+        for (int i = threadIdx.x; i < C * S; i += NB * NT) {
+            const int cl = i / S, li = i % S;
+            if (li == 0) continue;
+            const int st = 31 - __clz(li);
+            const double wq = twq[(1 << (g0 + st)) + (((int)blockIdx.x * C + cl) << st) + (li - (1 << st))];
+            twr[i] = make_double2(__fma_rn(wq, q, C52) - C52, wq);
+        }
+        __syncthreads();
+    }
+    double *ldsw = lds + wv * REGION;
     constexpr bool PRO = FUSE && COLPASS && !INV;   // prologue: broadcast-reduce one limb
     constexpr bool EPI = FUSE && !COLPASS && !INV;  // epilogue: (x - y) * c (+ add)
     const int c0 = blockIdx.x * C;
@@ -370,8 +397,9 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
         const bool pre = fz.pre, sub2 = fz.add2_sub;
         const u64 *pxm = fz.xmul ? fz.xmul + (size_t)t * n : nullptr;
         const u32 ag = fz.add_gal;
-        pass_core<LOGS, LOGE, C, COLPASS, INV, false>(din, c0, logn, mod, q, qinv, twq, twlast, lds,
-                                                      [&](int, u32 pos, double y) {
+        pass_core<LOGS, LOGE, C, COLPASS, INV, false, false, NB>(din, c0, logn, mod, q, qinv, twq, twlast, ldsw,
+                                                                 [&](int, u32 pos, double y) {
+            if (!live) return;
             double r;
             if (pre) {
                 // (x * c2 + add - y) * c
@@ -386,17 +414,21 @@ __global__ void __launch_bounds__(C * (1 << (LOGS - LOGE)))
             }
             if (padd2) r = sub2 ? pos1(r - u2d(padd2[pos]), q) : red1(r + u2d(padd2[pos]), q);
             pout[pos] = d2u(r);
-        });
+        }, 0, 0.0, twr);
     } else if constexpr (PRO) {
         const u64 *src2 = fz.src2 ? fz.src2 + (size_t)p * fz.src2_stride + (size_t)t * n : nullptr;
         pass_core<LOGS, LOGE, C, COLPASS, INV, true>(fz.src + (size_t)p * fz.src_stride, c0, logn, mod, q, qinv,
-                                                     twq, twlast, lds,
+                                                     twq, twlast, ldsw,
                                                      [&](int, u32 pos, double y) { data[pos] = d2u(y); }, 0,
                                                      fz.pro_q, nullptr, src2,
                                                      make_double2(fz.c2.v[t], fz.c2.vq[t]));
     } else {
-        pass_core<LOGS, LOGE, C, COLPASS, INV, false>(din, c0, logn, mod, q, qinv, twq, twlast, lds,
-                                                      [&](int, u32 pos, double y) { data[pos] = d2u(y); }, g);
+        pass_core<LOGS, LOGE, C, COLPASS, INV, false, false, NB>(
+            din, c0, logn, mod, q, qinv, twq, twlast, ldsw,
+            [&](int, u32 pos, double y) {
+                if (live) data[pos] = d2u(y);
+            },
+            g, 0.0, twr);
     }
 }
 
@@ -532,32 +564,39 @@ static void launch_row_ip(const DevTables &T, const IPArgs &a, hipStream_t s) {
                        T.logn, T.mq, T.twq_fwd, T.tw_last);
 }
 
-// batch entries per workgroup of the batch-shared tile: 4 or 2, the larger
-// that leaves at most B/8 idle waves (a ragged last slot), else 1
-static int row_ip_share(int B) {
+
+template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, int NB = 1>
+static void launch_pass(const DevTables &T, const LimbBatch &b, hipStream_t s, const NttFuse *f = nullptr) {
+    static_assert(NB * C * (1 << (LOGS - LOGE)) <= 1024, "workgroup larger than 1024 threads");
+    const int logn = T.logn;
+    const int blocks = (1 << (logn - LOGS)) / C;
+    dim3 grid(blocks, b.limbs * ((b.polys + NB - 1) / NB));
+    dim3 block(NB * C * (1 << (LOGS - LOGE)));
+    const double *twq = INV ? T.twq_inv : T.twq_fwd;
+    if (f && !INV && (COLPASS ? f->pro : f->epi))
+        hipLaunchKernelGGL((ntt_pass<LOGS, LOGE, C, COLPASS, INV, true, NB>), grid, block, 0, s, b.base,
+                           b.poly_stride, b.limbs, b.polys, b.map, logn, T.mq, twq, T.tw_last, *f, b.src,
+                           b.src_stride, b.gal);
+    else
+        hipLaunchKernelGGL((ntt_pass<LOGS, LOGE, C, COLPASS, INV, false, NB>), grid, block, 0, s, b.base,
+                           b.poly_stride, b.limbs, b.polys, b.map, logn, T.mq, twq, T.tw_last, NttFuse{}, b.src,
+                           b.src_stride, b.gal);
+}
+
+// entries per workgroup of the shared tiles (row passes: polynomials, fused
+// key switch: batch entries): 4 or 2, the larger that leaves at most B/8
+// idle waves (a ragged last slot), else 1
+static int share_of(int B) {
     for (int nb = 4; nb > 1; nb >>= 1)
         if (B >= nb && ((B + nb - 1) / nb * nb - B) * 8 <= B) return nb;
     return 1;
 }
 
-template <int LOGS, int LOGE, int C, bool COLPASS, bool INV>
-static void launch_pass(const DevTables &T, const LimbBatch &b, hipStream_t s, const NttFuse *f = nullptr) {
-    static_assert(C * (1 << (LOGS - LOGE)) <= 1024, "workgroup larger than 1024 threads");
-    const int logn = T.logn;
-    const int blocks = (1 << (logn - LOGS)) / C;
-    dim3 grid(blocks, b.limbs * b.polys);
-    dim3 block(C * (1 << (LOGS - LOGE)));
-    const double *twq = INV ? T.twq_inv : T.twq_fwd;
-    if (f && !INV && (COLPASS ? f->pro : f->epi))
-        hipLaunchKernelGGL((ntt_pass<LOGS, LOGE, C, COLPASS, INV, true>), grid, block, 0, s, b.base, b.poly_stride,
-                           b.limbs, b.map, logn, T.mq, twq, T.tw_last, *f, b.src, b.src_stride, b.gal);
-    else
-        hipLaunchKernelGGL((ntt_pass<LOGS, LOGE, C, COLPASS, INV, false>), grid, block, 0, s, b.base, b.poly_stride,
-                           b.limbs, b.map, logn, T.mq, twq, T.tw_last, NttFuse{}, b.src, b.src_stride, b.gal);
-}
-
 // tile variants: (elements per thread 2^LOGE, columns per workgroup C)
-//   passes of 2^8 and 2^9 points: 0 (16, 16), 1 (8, 32) / (16, 32), 2 (8, 16), 3 (8, 8)
+//   passes of 2^8 and 2^9 points: 0 (16, 16), 1 (8, 32) / (16, 32), 2 (8, 16), 3 (8, 8),
+//   4: row passes of 2^8 points, (4, 1) forward and (8, 2) inverse per wave,
+//   with up to 4 polynomials per workgroup sharing the rows' staged
+//   twiddles; column passes as 3
 //   smaller passes: one fixed tile
 template <int LOGS, bool COLPASS, bool INV>
 static void pass_variant(const DevTables &T, const LimbBatch &b, hipStream_t s, const NttFuse *f, int v) {
@@ -566,6 +605,20 @@ static void pass_variant(const DevTables &T, const LimbBatch &b, hipStream_t s, 
         case 1: launch_pass<LOGS, (LOGS == 8 ? 3 : 4), 32, COLPASS, INV>(T, b, s, f); return;
         case 2: launch_pass<LOGS, 3, 16, COLPASS, INV>(T, b, s, f); return;
         case 3: launch_pass<LOGS, 3, 8, COLPASS, INV>(T, b, s, f); return;
+        case 4:
+            if constexpr (LOGS == 8 && !COLPASS) {
+                // forward: one row of 4 per lane (its last exchange in DPP);
+                // inverse: two rows of 8 per lane
+                constexpr int E2 = INV ? 3 : 2, CR = INV ? 2 : 1;
+                switch (share_of(b.polys)) {
+                case 4: launch_pass<8, E2, CR, false, INV, 4>(T, b, s, f); return;
+                case 2: launch_pass<8, E2, CR, false, INV, 2>(T, b, s, f); return;
+                default: launch_pass<8, E2, CR, false, INV>(T, b, s, f); return;
+                }
+            } else {
+                launch_pass<LOGS, 3, 8, COLPASS, INV>(T, b, s, f);
+                return;
+            }
         default: launch_pass<LOGS, 4, 16, COLPASS, INV>(T, b, s, f); return;
         }
     } else if constexpr (LOGS == 7) {
@@ -623,7 +676,7 @@ static void row_ip_variant(const DevTables &T, const IPArgs &a, hipStream_t s, i
         case 5: launch_row_ip<8, 2, 2>(T, a, s); return;
         case 6: launch_row_ip<8, 2, 1>(T, a, s); return;
         case 7:
-            switch (row_ip_share(a.B)) {
+            switch (share_of(a.B)) {
             case 4: launch_row_ip<8, 2, 1, 4>(T, a, s); return;
             case 2: launch_row_ip<8, 2, 1, 2>(T, a, s); return;
             default: launch_row_ip<8, 2, 1>(T, a, s); return;

@@ -40,7 +40,7 @@ struct DevTables {
     int ntt_variant[2][2] = {{0, 0}, {0, 0}};  // [inverse][pass]: tile variant chosen by the autotuner
     int row_ip_variant = 7;                      // tile of the fused row pass + inner product
 };
-constexpr int kNttVariants = 4;
+constexpr int kNttVariants = 5;
 constexpr int kRowIpVariants = 8;
 
 // description of a batch of limbs: `polys` groups of `limbs` limbs, group p

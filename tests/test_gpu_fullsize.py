@@ -77,27 +77,34 @@ def test_rank128_batch_equals_single_full_size(full):
         assert np.array_equal(s, b.export())
 
 
-def test_rank128_batch_shared_row_ip_tiles(full):
-    """The fused key-switch tile that runs up to 4 batch entries per
-    workgroup (sharing the row's twiddles and key words; 2 entries at B = 2
-    and B = 9, 4 at B = 30 and 32, B = 9 and 30 with a ragged last slot)
-    gives the batched rank bit for bit as the tile with one entry per
-    workgroup."""
+def test_rank128_shared_tiles_bit_identical(full):
+    """The tiles that run several batch entries (or polynomials) per
+    workgroup over the same rows give the batched rank bit for bit as the
+    tiles with one per workgroup: the fused key-switch tile 7 (up to 4 batch
+    entries sharing the row's twiddles and key words) and the row-pass tile 4
+    of both transforms (up to 4 polynomials sharing the row's twiddles).
+    B = 9 and B = 30 leave a ragged last slot."""
     ctx, keys = full["ctx"], full["gkeys"]
     qs = [W.rank_workload(N, 2.0 ** -10, 400 + i) for i in range(32)]
     cts = [ctx.encrypt(keys, v, LEVEL, e) for v, _, e in qs]
+
+    def tiles(row_ip, rows):
+        ctx.row_ip_variant(row_ip)
+        for inv in (0, 1):
+            ctx.ntt_variant(inv, 1 - inv, rows)   # the row pass: forward pass 1, inverse pass 0
+
     ctx.set_graphs(False)
     try:
         for B in (2, 9, 30, 32):
             outs = {}
-            for var in (6, 7):
-                say(f"[gpu] P16 rank-128 batch of {B}, fused key-switch tile {var}")
-                ctx.row_ip_variant(var)
-                outs[var] = [o.export() for o in ctx.rank_batch(keys, cts[:B], N, W.RANK_CMP[N])]
-            for var in (7,):
-                assert all(np.array_equal(a, b) for a, b in zip(outs[6], outs[var])), (B, var)
+            for name, row_ip, rows in (("per-entry", 6, 0), ("shared key switch", 7, 0), ("shared rows", 7, 4)):
+                say(f"[gpu] P16 rank-128 batch of {B}, tiles: {name}")
+                tiles(row_ip, rows)
+                outs[name] = [o.export() for o in ctx.rank_batch(keys, cts[:B], N, W.RANK_CMP[N])]
+            for name in ("shared key switch", "shared rows"):
+                assert all(np.array_equal(a, b) for a, b in zip(outs["per-entry"], outs[name])), (B, name)
     finally:
-        ctx.row_ip_variant(7)  # the library's default
+        tiles(7, 0)  # the library's defaults
         ctx.set_graphs(True)
 
 

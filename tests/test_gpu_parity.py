@@ -255,7 +255,7 @@ def test_ntt_tile_variants_bit_identical(ckr, name):
     rng = np.random.default_rng(1)
     host = np.stack([rng.integers(0, int(q), n, dtype=np.uint64) for q in ctx.moduli[:limbs]])
     ref = None
-    for v in range(4):
+    for v in range(5):
         for inv in (0, 1):
             for ps_ in (0, 1):
                 ctx.ntt_variant(inv, ps_, v)
@@ -270,7 +270,7 @@ def test_ntt_tile_variants_bit_identical(ckr, name):
             ref = fwd
         assert np.array_equal(fwd, ref), f"variant {v} forward differs"
     table = ctx.autotune(limbs * 4, 2)
-    assert table.shape == (2, 2, 4) and np.all(table > 0)
+    assert table.shape == (2, 2, 5) and np.all(table > 0)
 
 
 @pytest.mark.parametrize("logn", [11, 13, 14, 15])
