@@ -651,10 +651,10 @@ def main():
 
     # NTT tile autotuning on a dispatch of the size the circuit issues
     tune_limbs = min(2 * B * (level + 1), 1152)
-    table = ctx.autotune(tune_limbs, 3)
+    table = ctx.autotune(tune_limbs, 10)
     chosen = [[int(np.argmin(table[i][p])) for p in range(2)] for i in range(2)]
     log(f"[bench] autotune ({tune_limbs} limbs): variants fwd {chosen[0]} inv {chosen[1]}; ms {np.round(table, 3).tolist()}")
-    ip_ms = ctx.autotune_row_ip(B, 3)
+    ip_ms = ctx.autotune_row_ip(B, 10)
     ip_var = int(np.argmin(ip_ms))
     log(f"[bench] fused row pass + inner product tile: variant {ip_var} ({np.round(ip_ms, 3).tolist()} ms)")
     chunk = args.ntt_chunk
