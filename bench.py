@@ -649,6 +649,19 @@ def main():
     def step():
         return ctx.run_batch(keys, "rank", cts, N, cmp)
 
+    def step_ms(reps=3):
+        # every tile or chunk change makes the next batched run capture its
+        # graph again: run twice (eager the very first time, then capture),
+        # then time replays
+        step()
+        step()
+        ctx.synchronize()
+        t_ = time.perf_counter()
+        for _ in range(reps):
+            step()
+        ctx.synchronize()
+        return (time.perf_counter() - t_) / reps * 1e3
+
     # NTT tile autotuning on a dispatch of the size the circuit issues
     tune_limbs = min(2 * B * (level + 1), 1152)
     table = ctx.autotune(tune_limbs, 10)
@@ -657,19 +670,31 @@ def main():
     ip_ms = ctx.autotune_row_ip(B, 10)
     ip_var = int(np.argmin(ip_ms))
     log(f"[bench] fused row pass + inner product tile: variant {ip_var} ({np.round(ip_ms, 3).tolist()} ms)")
+    # the autotuner's launch is not the circuit's mix of launches (fused
+    # prologues and epilogues, other sizes): where tiles come within 8% of the
+    # best one there, whole batched steps decide
+    for inv in (0, 1):
+        for p_ in (0, 1):
+            row = table[inv][p_]
+            cands = [v for v in range(len(row)) if row[v] <= 1.08 * row.min()]
+            if len(cands) < 2:
+                continue
+            per = {}
+            for v in cands:
+                ctx.ntt_variant(inv, p_, v)
+                per[v] = step_ms()
+            chosen[inv][p_] = min(per, key=per.get)
+            ctx.ntt_variant(inv, p_, chosen[inv][p_])
+            log(f"[bench] {'inverse' if inv else 'forward'} pass {p_}: ms/step by tile "
+                f"{ {v: round(t, 2) for v, t in per.items()} } -> {chosen[inv][p_]}")
     chunk = args.ntt_chunk
     if chunk < 0:
-        # pick the cache chunk by timing one batched step per candidate
+        # pick the cache chunk by timing batched steps per candidate
         best = None
         for cand in (0, 96, 192, 384):
             ctx.set_ntt_chunk(cand)
-            step()
-            ctx.synchronize()
-            t_ = time.perf_counter()
-            step()
-            ctx.synchronize()
-            dt = time.perf_counter() - t_
-            log(f"[bench] ntt chunk {cand}: {dt * 1e3:.1f} ms/step (eager)")
+            dt = step_ms()
+            log(f"[bench] ntt chunk {cand}: {dt:.1f} ms/step")
             if best is None or dt < best[0]:
                 best = (dt, cand)
         chunk = best[1]

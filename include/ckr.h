@@ -445,6 +445,9 @@ ckr_status ckr_ntt_variant(ckr_context *ctx, int inverse, int pass, int variant)
 /* Force one tile variant (0..7) of the key switch's fused forward row pass +
  * inner product (rows of 2^8 points; other ring sizes have one tile). */
 ckr_status ckr_row_ip_variant(ckr_context *ctx, int variant);
+/* The five calls above change the kernels later work runs.  A batched
+ * circuit captured into a hipGraph before such a change is captured again on
+ * its next run, so replays always use the current tiles and chunking. */
 
 /* Wait for all work issued on the context stream. */
 ckr_status ckr_synchronize(ckr_context *ctx);

@@ -121,6 +121,7 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
                                           double2 c2 = double2{0.0, 0.0}) {
     constexpr int S = 1 << LOGS, E = 1 << LOGE, TPC = S / E, NT = C * TPC;
     constexpr int NR = (LOGS + LOGE - 1) / LOGE;
+    static_assert(!PRO || (COLPASS && !INV), "the prologue feeds the first pass of the forward transform");
     constexpr int SP = S + (S >> 4) + 1;
     constexpr bool FINAL = (INV == COLPASS);
     const double two_q = 2.0 * q;
@@ -210,14 +211,14 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
         if (rho == 0) {
             if (PRO) {
                 // the input limb's residues mod cq, taken in (-cq/2, cq/2) when cq > 0,
-                // plus din2 * c2 when din2 is set
+                // plus din2 * c2 when din2 is set: [0, q) + (0, 2q), below 4q, which
+                // the forward butterflies take as it is
 #pragma unroll
                 for (int k = 0; k < E; k++) {
                     double v = u2d(din[gaddr(rbase | (k << w))]);
                     if (v > 0.5 * cq) v -= cq;
                     x[k] = red_any(v, q, qinv);
-                    if (din2)
-                        x[k] = red1(x[k] + red1(mm_lazy(u2d(din2[gaddr(rbase | (k << w))]), c2.x, c2.y, q), q), q);
+                    if (din2) x[k] += mm_lazy(u2d(din2[gaddr(rbase | (k << w))]), c2.x, c2.y, q);
                 }
             } else if (direct) {
                 if (gal > 1) {

@@ -387,6 +387,7 @@ struct Ctx {
     Prof prof;
     bool graphs = true;           // capture batched circuits into hipGraphs
     int ntt_chunk = 0;            // limbs per two-pass chunk (0: whole dispatch), keeps pass-1 output in cache
+    unsigned tune_epoch = 0;      // bumped by every tile or chunk change: older captured plans are re-captured
     hipStream_t own_stream = nullptr;
     static constexpr int kSide = 4;
     static constexpr int kSlots = 2;  // server slots: batches of one context in flight at once
@@ -461,6 +462,7 @@ struct GraphPlan {
     hipGraphExec_t exec = nullptr;
     std::vector<std::pair<void *, size_t>> owned;  // temporaries the replays write
     unsigned long long last_use = 0;               // Keys::plan_clock at its latest replay
+    unsigned epoch = 0;                            // Ctx::tune_epoch at capture
     ~GraphPlan() {
         if (stream) (void)hipStreamSynchronize(stream);
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -2165,6 +2167,12 @@ static std::vector<DCt> run_circuit(Ctx &C, Keys &K, const PlanKey &key,
     };
     const bool use_graph = C.graphs && !C.prof.on;
     auto it = K.plans.find({C.slot, key});
+    if (it != K.plans.end() && it->second->epoch != C.tune_epoch) {
+        // captured with other tiles or chunking: capture again, so that a
+        // replay always runs the kernels the context is set to
+        K.plans.erase(it);
+        it = K.plans.end();
+    }
     if (!use_graph || (it == K.plans.end() && !K.warm.count(key))) {
         std::vector<DCt> X = inputs();
         fill(X);
@@ -2188,6 +2196,7 @@ static std::vector<DCt> run_circuit(Ctx &C, Keys &K, const PlanKey &key,
         auto plan = std::make_unique<GraphPlan>();
         plan->C = &C;
         plan->stream = C.stream;
+        plan->epoch = C.tune_epoch;
         plan->in = inputs();
         sync(C);
         HIPCHK(hipStreamBeginCapture(C.stream, hipStreamCaptureModeRelaxed));
@@ -3611,6 +3620,7 @@ ckr_status ckr_autotune(ckr_context *ctx, uint32_t limbs, uint32_t iters, float 
                 }
                 C.T.ntt_variant[inv][pass] = bestv;
             }
+        C.tune_epoch++;
         for (auto &e : ev) (void)hipEventDestroy(e);
     });
 }
@@ -3666,6 +3676,7 @@ ckr_status ckr_autotune_row_ip(ckr_context *ctx, uint32_t batch, uint32_t iters,
             if (t < best) best = t, bestv = v;
         }
         C.T.row_ip_variant = bestv;
+        C.tune_epoch++;
         for (auto &e : ev) (void)hipEventDestroy(e);
     });
 }
@@ -3675,6 +3686,7 @@ ckr_status ckr_set_ntt_chunk(ckr_context *ctx, uint32_t limbs) {
         NEED(ctx);
         std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         ctx->C->ntt_chunk = (int)limbs;
+        ctx->C->tune_epoch++;
     });
 }
 
@@ -3683,7 +3695,9 @@ ckr_status ckr_ntt_variant(ckr_context *ctx, int inverse, int pass, int variant)
         NEED(ctx);
         if (inverse < 0 || inverse > 1 || pass < 0 || pass > 1 || variant < 0 || variant >= kNttVariants)
             throw Error{CKR_E_INVALID, "variant"};
+        std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         ctx->C->T.ntt_variant[inverse][pass] = variant;
+        ctx->C->tune_epoch++;
     });
 }
 
@@ -3693,6 +3707,7 @@ ckr_status ckr_row_ip_variant(ckr_context *ctx, int variant) {
         if (variant < 0 || variant >= kRowIpVariants) throw Error{CKR_E_INVALID, "variant"};
         std::lock_guard<std::recursive_mutex> lk_(ctx->C->mu_run);
         ctx->C->T.row_ip_variant = variant;
+        ctx->C->tune_epoch++;
     });
 }
 

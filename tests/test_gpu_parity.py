@@ -339,6 +339,33 @@ def test_rank8_ntt_chunking_bit_identical(p12):
         p12.ctx.set_graphs(True)
 
 
+def test_rank8_tuning_changes_between_replays(p12):
+    """A captured batch replayed, then run again after each tile or chunk
+    change (each makes the next run capture its graph again): every run
+    gives the eager result bit for bit."""
+    N, cmp = 8, W.RANK_CMP[8]
+    ctx = p12.ctx
+    cts = [ctx.encrypt(p12.gkeys, W.rank_workload(N, 0.01, 80 + s)[0], p12.P.L, bytes([s + 7] * 32)) for s in range(4)]
+    run = lambda: [o.export() for o in ctx.run_batch(p12.gkeys, "rank", cts, N, cmp)]
+    ref = run()            # eager
+    changes = [lambda: ctx.ntt_variant(1, 0, 4), lambda: ctx.ntt_variant(0, 1, 3), lambda: ctx.set_ntt_chunk(5),
+               lambda: ctx.row_ip_variant(6), lambda: ctx.autotune(8, 1)]
+    try:
+        for i, change in enumerate([None] + changes):
+            if change:
+                say(f"[gpu] tuning change {i}")
+                change()
+            for _ in range(2):     # capture (or re-capture), then replay
+                got = run()
+                assert all(np.array_equal(a, b) for a, b in zip(ref, got)), i
+    finally:
+        for inv in (0, 1):
+            for ps_ in (0, 1):
+                ctx.ntt_variant(inv, ps_, 0)
+        ctx.set_ntt_chunk(0)
+        ctx.row_ip_variant(7)
+
+
 @pytest.mark.parametrize("k", [1, 3, 5])
 def test_minimax_comparator_bit_exact(ora, ckr, k):
     """k stages of the minimax composite on ciphertexts (the constants of
