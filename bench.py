@@ -65,7 +65,7 @@ def measured_traffic(category):
 
 def host_cores():
     """CPUs this process may run on (its affinity mask), and the thread count
-    the oracle uses: all of them, at most 16 (a GPU machine's CPU share)"""
+    the oracle uses: all of them, at most 16"""
     try:
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
