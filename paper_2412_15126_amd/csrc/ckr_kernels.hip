@@ -112,7 +112,7 @@ __device__ __forceinline__ u32 gal_src(u32 i, int logn, u32 g) {
 // the thread's ordinal of that element (the same position for every call
 // from the same thread).
 template <int LOGS, int LOGE, int C, bool COLPASS, bool INV, bool PRO, bool IN_LOOP = false, int NB = 1,
-          class Emit>
+          bool LDS_IN = false, class Emit>
 __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, int logn, int mod, double q,
                                           double qinv, const double *__restrict__ twq,
                                           const double2 *__restrict__ twlast,
@@ -122,6 +122,7 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
     constexpr int S = 1 << LOGS, E = 1 << LOGE, TPC = S / E, NT = C * TPC;
     constexpr int NR = (LOGS + LOGE - 1) / LOGE;
     static_assert(!PRO || (COLPASS && !INV), "the prologue feeds the first pass of the forward transform");
+    static_assert(!LDS_IN || (!COLPASS && INV), "an LDS-resident tile feeds the first pass of the inverse");
     constexpr int SP = S + (S >> 4) + 1;
     constexpr bool FINAL = (INV == COLPASS);
     const double two_q = 2.0 * q;
@@ -229,13 +230,16 @@ __device__ __forceinline__ void pass_core(const u64 *__restrict__ din, int c0, i
                     for (int k = 0; k < E; k++) x[k] = u2d(din[gaddr(rbase | (k << w))]);
                 }
             } else {
-                // rows are contiguous: the tile is C*S consecutive words
-                const u64 *tile = din + (u32)(c0 * S);
-                if (gal > 1) {
-                    for (int i = tid; i < C * S; i += NT)
-                        lds[lidx(i / S, i % S)] = u2d(din[gal_src((u32)(c0 * S + i), logn, gal)]);
-                } else {
-                    for (int i = tid; i < C * S; i += NT) lds[lidx(i / S, i % S)] = u2d(tile[i]);
+                // rows are contiguous: the tile is C*S consecutive words (LDS_IN:
+                // the caller has put the tile in LDS already)
+                if constexpr (!LDS_IN) {
+                    const u64 *tile = din + (u32)(c0 * S);
+                    if (gal > 1) {
+                        for (int i = tid; i < C * S; i += NT)
+                            lds[lidx(i / S, i % S)] = u2d(din[gal_src((u32)(c0 * S + i), logn, gal)]);
+                    } else {
+                        for (int i = tid; i < C * S; i += NT) lds[lidx(i / S, i % S)] = u2d(tile[i]);
+                    }
                 }
                 sync();
 #pragma unroll
@@ -445,10 +449,13 @@ __global__ void __launch_bounds__(NB * C * (1 << (LOGS - LOGE)))
 // and read that tile's key words from its L2.  With NB > 1 (one row), the NB
 // waves of a workgroup run NB batch entries over the same row: the row's
 // twiddles and each digit's key words are staged in LDS once for all of them.
+// With a.inv_p, the outputs of the special-prime limbs (t > level) also get
+// the inverse transform's row pass, ModDown's first step, before they are
+// stored: the same lazily reduced values that pass writes on its own.
 template <int LOGS, int LOGE, int C, int NB>
 __global__ void __launch_bounds__(NB * C * (1 << (LOGS - LOGE)), (LOGE == 2 ? 6 : 1))  // 4 elements: 78 VGPRs
     ntt_row_ip(const IPArgs a, int logn, const double2 *__restrict__ mq, const double *__restrict__ twqtab,
-               const double2 *__restrict__ twlast) {
+               const double *__restrict__ twqinv, const double2 *__restrict__ twlast) {
     constexpr int S = 1 << LOGS, E = 1 << LOGE, NT = C * (S / E), NALL = NB * NT;
     constexpr int SP = S + (S >> 4) + 1;
     static_assert(NB == 1 || (C == 1 && NT == 64 && LOGS - LOGE >= 3),
@@ -456,6 +463,7 @@ __global__ void __launch_bounds__(NB * C * (1 << (LOGS - LOGE)), (LOGE == 2 ? 6 
     __shared__ double lds[NB * C * SP];
     __shared__ double2 twr[C * S];  // the rows' forward twiddles {w, w/q}, shared by the digits' passes
     __shared__ double keyl[NB > 1 ? 2 * C * S : 2];  // NB > 1: the digit's key words kb, ka of the rows
+    __shared__ double2 twi[NB > 1 ? C * S : 1];      // NB > 1 and a.inv_p: the rows' inverse twiddles
     const size_t n = (size_t)1 << logn;
     const int tiles = (int)(n >> LOGS) / C;
     const int slots = (a.B + NB - 1) / NB;
@@ -476,20 +484,26 @@ __global__ void __launch_bounds__(NB * C * (1 << (LOGS - LOGE)), (LOGE == 2 ? 6 
     const double *twq = twqtab + (size_t)mod * n;
     const int own = (t <= a.level) ? t / a.alpha : -1;  // digit holding limb t, if any
     const int tall = threadIdx.x, tid = NB > 1 ? (int)(threadIdx.x % NT) : (int)threadIdx.x;
-    if (a.beta > (own >= 0 ? 1 : 0)) {
-        // row c0 + cl, stage s (global stage logn - LOGS + s) uses table entry
-        // 2^(logn - LOGS + s) + ((c0 + cl) << s) + (r >> (LOGS - s)); staged at
-        // cl S + 2^s + (r >> (LOGS - s)), entry 0 of each row unused
+    const bool invp = a.inv_p && t > a.level;
+    const double *twqi = twqinv + (size_t)mod * n;
+    // row c0 + cl, stage s (global stage logn - LOGS + s) uses table entry
+    // 2^(logn - LOGS + s) + ((c0 + cl) << s) + (r >> (LOGS - s)); staged at
+    // cl S + 2^s + (r >> (LOGS - s)), entry 0 of each row unused
+    auto stage = [&](double2 *dst, const double *tab) {
         const int g0 = logn - LOGS;
         for (int i = tall; i < C * S; i += NALL) {
             const int cl = i / S, li = i % S;
             if (li == 0) continue;
             const int st = 31 - __clz(li);
-            const double wq = twq[(1 << (g0 + st)) + ((c0 + cl) << st) + (li - (1 << st))];
-            twr[i] = make_double2(__fma_rn(wq, q, C52) - C52, wq);
+            const double wq = tab[(1 << (g0 + st)) + ((c0 + cl) << st) + (li - (1 << st))];
+            dst[i] = make_double2(__fma_rn(wq, q, C52) - C52, wq);
         }
-        __syncthreads();
-    }
+    };
+    const bool fwd_staged = a.beta > (own >= 0 ? 1 : 0);
+    if (fwd_staged) stage(twr, twq);
+    if constexpr (NB > 1)
+        if (invp) stage(twi, twqi);
+    if (fwd_staged || (NB > 1 && invp)) __syncthreads();
     double sb[E], sa[E];
 #pragma unroll
     for (int k = 0; k < E; k++) sb[k] = sa[k] = 0.0;
@@ -545,8 +559,36 @@ __global__ void __launch_bounds__(NB * C * (1 << (LOGS - LOGE)), (LOGE == 2 ? 6 
             }
         }
     }
-    if (!live) return;
+    if (!live) return;  // NB > 1: only wave-level synchronisation follows
     u64 *ob = a.accb + bi * a.sacc + (size_t)t * n, *oa = a.acca + bi * a.sacc + (size_t)t * n;
+    if (invp) {
+        // each output row through the inverse row pass: the reduced sums go
+        // into this wave's LDS tile, where that pass's first round reads them
+        double *ldsw = lds + wv * (C * SP);
+        auto region_sync = [] {
+            if constexpr (NB > 1) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            } else {
+                __syncthreads();
+            }
+        };
+        auto inv_store = [&](const double(&sv)[E], u64 *o) {
+            region_sync();  // earlier readers of the tile are done
+#pragma unroll
+            for (int k = 0; k < E; k++) {
+                const int i = tid + k * NT;
+                ldsw[(i / S) * SP + i % S + ((i % S) >> 4)] = red_any(sv[k], q, qinv);
+            }
+            pass_core<LOGS, LOGE, C, false, true, false, false, NB, true>(
+                nullptr, c0, logn, mod, q, qinv, twqi, twlast, ldsw, [&](int, u32 pos, double y) { o[pos] = d2u(y); },
+                0, 0.0, twi);
+        };
+        inv_store(sb, ob);
+        inv_store(sa, oa);
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < E; k++) {
         const u32 pos = (u32)(c0 * S + tid + k * NT);
@@ -562,7 +604,7 @@ static void launch_row_ip(const DevTables &T, const IPArgs &a, hipStream_t s) {
     const int groups = a.E * tiles;
     const unsigned blocks = (unsigned)(((groups + 7) / 8) * 8) * (unsigned)((a.B + NB - 1) / NB);
     hipLaunchKernelGGL((ntt_row_ip<LOGS, LOGE, C, NB>), dim3(blocks), dim3(NB * C * (1 << (LOGS - LOGE))), 0, s, a,
-                       T.logn, T.mq, T.twq_fwd, T.tw_last);
+                       T.logn, T.mq, T.twq_fwd, T.twq_inv, T.tw_last);
 }
 
 

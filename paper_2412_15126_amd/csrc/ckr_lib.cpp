@@ -684,6 +684,13 @@ static void ntt_first(Ctx &C, u64 *base, int limbs, int polys, size_t stride, Li
     timed(C, kNttFwdCol, 16.0 * C.P.n * limbs * polys, [&] { k_ntt_pass(C.T, b, false, 0, C.stream); });
 }
 
+// the second (column) pass of the inverse transform only, on data that has had
+// the row pass
+static void intt_second(Ctx &C, u64 *base, int limbs, int polys, size_t stride, LimbMap map) {
+    LimbBatch b{base, limbs, polys, stride, map};
+    timed(C, kNttInvCol, 16.0 * C.P.n * limbs * polys, [&] { k_ntt_pass(C.T, b, true, 1, C.stream); });
+}
+
 // forward transform with the fused prologue / epilogue of NttFuse.  The
 // epilogue addresses poly p = 2b + k, so chunks hold whole (b) pairs.
 static void ntt_fused(Ctx &C, u64 *base, int limbs, int polys, size_t stride, LimbMap map, const NttFuse &f) {
@@ -1167,11 +1174,13 @@ static void keyswitch(Ctx &C, const Keys &K, const Buf &key, const u64 *d, size_
     ia.sext = sext;
     ia.sacc = sacc;
     ia.gal = gal;
+    ia.inv_p = true;  // the special-prime limbs leave after ModDown's first inverse pass
     // per target limb: beta inputs and 2 outputs per batch entry, 2*beta key limbs once
     timed(C, kNttRowIP, 8.0 * n * E * ((beta + 2.0) * B + 2.0 * beta), [&] { k_ntt_row_ip(C.T, ia, C.stream); });
     // ModDown, rounding: (x_Q + h - [(X + h) mod P]_Q) * P^{-1} = round(X / P), h = (P - 1)/2
-    // (both h's folded into the exact base conversion), the combine fused into the last NTT pass
-    ntt(C, acc.get() + (size_t)(l + 1) * n, P.K, 2 * B, (size_t)E * n, plain_map(P.nq), true);
+    // (both h's folded into the exact base conversion), the combine fused into the last NTT pass.
+    // The inverse transform of the special-prime limbs: its row pass ran in the kernel above.
+    intt_second(C, acc.get() + (size_t)(l + 1) * n, P.K, 2 * B, (size_t)E * n, plain_map(P.nq));
     Buf conv(&C, (size_t)2 * B * (l + 1) * n);
     const BConvTab &mdt = moddown_tab(C, l);
     timed(C, kBConv, 8.0 * n * (mdt.ns + mdt.nt) * 2 * B, [&] {
@@ -3657,6 +3666,7 @@ ckr_status ckr_autotune_row_ip(ckr_context *ctx, uint32_t batch, uint32_t iters,
         ia.sd = (size_t)(l + 1) * n;
         ia.sext = (size_t)beta * E * n;
         ia.sacc = (size_t)2 * E * n;
+        ia.inv_p = true;  // as in the key switch
         hipEvent_t ev[2];
         for (auto &e : ev) HIPCHK(hipEventCreate(&e));
         const int keep = C.T.row_ip_variant;

@@ -171,6 +171,8 @@ struct IPArgs {
     int B;                       // batch of inputs sharing the key
     size_t sd, sext, sacc;       // batch strides of d, ext, accb/acca
     u32 gal = 0;                 // when > 1, d is read through the automorphism sigma_gal
+    bool inv_p = false;          // limbs t > level (special primes): store them after the inverse
+                                 // transform's row pass (ModDown's first pass), lazily reduced
 };
 // computed with the forward row pass of ext fused in front: ext holds the
 // extended limbs after their column pass only
