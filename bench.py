@@ -63,6 +63,28 @@ def measured_traffic(category):
     return rows[category]
 
 
+def settle_tiles(ctx, table, step_ms, chosen, tol=1.08):
+    """The autotuner's launch is not a circuit's mix of launches (fused
+    prologues and epilogues, other sizes): where NTT tiles come within `tol`
+    of the best one there, whole batched steps (step_ms() -> ms) decide.
+    Returns the chosen [inverse][pass] tiles, which the context keeps."""
+    for inv in (0, 1):
+        for p_ in (0, 1):
+            row = table[inv][p_]
+            cands = [v for v in range(len(row)) if row[v] <= tol * row.min()]
+            if len(cands) < 2:
+                continue
+            per = {}
+            for v in cands:
+                ctx.ntt_variant(inv, p_, v)
+                per[v] = step_ms()
+            chosen[inv][p_] = min(per, key=per.get)
+            ctx.ntt_variant(inv, p_, chosen[inv][p_])
+            log(f"[bench] {'inverse' if inv else 'forward'} pass {p_}: ms/step by tile "
+                f"{ {v: round(t, 2) for v, t in per.items()} } -> {chosen[inv][p_]}")
+    return chosen
+
+
 def host_cores():
     """CPUs this process may run on (its affinity mask), and the thread count
     the oracle uses: all of them, at most 16"""
@@ -374,8 +396,8 @@ def circuit_bench(args):
     t = time.time()
     keys = ctx.keygen(bytes(range(11, 43)), level, [b], what=spec["what"])
     log(f"[{name}] keygen {time.time() - t:.1f}s")
-    ctx.autotune(2 * 4 * (level + 1), 2)
-    ctx.autotune_row_ip(4, 2)
+    table = ctx.autotune(2 * 4 * (level + 1), 10)
+    ctx.autotune_row_ip(4, 10)
     queries, vals = [], []
     for i in range(B):
         tie = spec.get("q", {}).get("tie", False)
@@ -450,6 +472,19 @@ def circuit_bench(args):
         # ranks: within 1/2 of the integers; values: within half the workload's 2^-10 gap
         bound = 0.5 if (multi and not msort) or spec.get("q", {}).get("kind") == "rank" else spec.get("bound", 2.0 ** -11)
         return worst < bound, worst
+
+    if not multi:
+        def step_ms(reps=2):
+            step()
+            step()
+            ctx.synchronize()
+            t_ = time.perf_counter()
+            for _ in range(reps):
+                step()
+            ctx.synchronize()
+            return (time.perf_counter() - t_) / reps * 1e3
+
+        settle_tiles(ctx, table, step_ms, [[int(np.argmin(table[i][p_])) for p_ in range(2)] for i in range(2)])
 
     # single-ciphertext circuits: the first call runs eagerly, the second
     # captures the graph; multi-ciphertext circuits run eagerly every time
@@ -670,23 +705,7 @@ def main():
     ip_ms = ctx.autotune_row_ip(B, 10)
     ip_var = int(np.argmin(ip_ms))
     log(f"[bench] fused row pass + inner product tile: variant {ip_var} ({np.round(ip_ms, 3).tolist()} ms)")
-    # the autotuner's launch is not the circuit's mix of launches (fused
-    # prologues and epilogues, other sizes): where tiles come within 8% of the
-    # best one there, whole batched steps decide
-    for inv in (0, 1):
-        for p_ in (0, 1):
-            row = table[inv][p_]
-            cands = [v for v in range(len(row)) if row[v] <= 1.08 * row.min()]
-            if len(cands) < 2:
-                continue
-            per = {}
-            for v in cands:
-                ctx.ntt_variant(inv, p_, v)
-                per[v] = step_ms()
-            chosen[inv][p_] = min(per, key=per.get)
-            ctx.ntt_variant(inv, p_, chosen[inv][p_])
-            log(f"[bench] {'inverse' if inv else 'forward'} pass {p_}: ms/step by tile "
-                f"{ {v: round(t, 2) for v, t in per.items()} } -> {chosen[inv][p_]}")
+    chosen = settle_tiles(ctx, table, step_ms, chosen)
     chunk = args.ntt_chunk
     if chunk < 0:
         # pick the cache chunk by timing batched steps per candidate
