@@ -140,10 +140,10 @@ def serve(args, quiet=False):
     ka = a.keygen(bytes(range(32)), lr, [128])
     b = ckr.Context(p17)
     kb = b.keygen(bytes(range(3, 35)), p17["L"], [32, 64, 128], what=6)
-    a.autotune(2 * 8 * 18, 2)
-    b.autotune(2 * 4 * 41, 2)
-    a.autotune_row_ip(8, 2)
-    b.autotune_row_ip(4, 2)
+    a.autotune(2 * 8 * 18, 10)
+    b.autotune(2 * 4 * 41, 10)
+    a.autotune_row_ip(8, 10)
+    b.autotune_row_ip(4, 10)
     log(f"[serve] keys ready in {time.time() - t:.1f}s")
     srv = ckr.Server(hbm_budget=args.hbm_budget << 30, max_batch=args.max_batch)
     srv.add_route("rank", 128, a, ka, W.RANK128_MM)
@@ -243,8 +243,8 @@ def mixed(args):
     t = time.time()
     keys = ctx.keygen(kseed, ps["L"], [16, 32, 64, 128], what=2)
     log(f"[mixed] keys ready in {time.time() - t:.1f}s")
-    ctx.autotune(2 * 8 * 37, 2)
-    ctx.autotune_row_ip(8, 2)
+    ctx.autotune(2 * 8 * 37, 10)
+    ctx.autotune_row_ip(8, 10)
     queries = []
     for q in qs:
         N = q["N"]
@@ -563,8 +563,8 @@ def cheb_sweep(args):
             stream = hip.Stream()
             ctx.set_stream(stream.h.value)
             keys = ctx.keygen(bytes(range(7, 39)), level, [N], what=1)
-            ctx.autotune(2 * 4 * (level + 1), 2)
-            ctx.autotune_row_ip(4, 2)
+            ctx.autotune(2 * 4 * (level + 1), 10)
+            ctx.autotune_row_ip(4, 10)
             rng = np.random.default_rng(900 + D)
             vals = [W.min_gap_uniform(N, 0.0, rng) for _ in range(B)]
             cts = [ctx.encrypt(keys, v, level, bytes([q]) + bytes(range(1, 32))) for q, v in enumerate(vals)]
